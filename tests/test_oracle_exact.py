@@ -1,0 +1,110 @@
+"""Pins for the oracle's exact entropy (eqn. (1)), Jacobi eigensolver, random
+projection (Algorithm 3) and the FP64 MLP."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def shannon(p):
+    p = p[p > 0]
+    return float(-np.sum(p * np.log(p)))
+
+
+def test_jacobi_against_known_spectrum_and_numpy(orc):
+    n = 80
+    p = W.spectrum_exp(n, 20.0)
+    R = W.dense_density(p, 21)
+    e, V, sweeps = orc.jacobi_eigen(R, vectors=True)
+    assert np.max(np.abs(np.sort(e)[::-1] - p)) < 1e-15
+    assert np.max(np.abs(np.sort(e) - np.linalg.eigvalsh(R))) < 1e-15
+    assert np.max(np.abs(R @ V - V * e[None, :])) < 1e-13 * np.abs(R).max()
+    assert np.max(np.abs(V.T @ V - np.eye(n))) < 1e-13
+    assert sweeps < 20
+
+
+def test_exact_entropy_invariants(orc):
+    n = 40
+    assert abs(orc.exact_entropy(W.pure_state(n, 1))) < 1e-12
+    assert orc.exact_entropy(W.maximally_mixed(n)) == pytest.approx(math.log(n), rel=1e-14)
+    p = W.spectrum_inverse(n)
+    assert orc.exact_entropy(np.diag(p)) == pytest.approx(shannon(p), rel=1e-14)
+    R = W.dense_density(p, 3)
+    assert orc.exact_entropy(R) == pytest.approx(shannon(p), rel=1e-12)
+    # rank-deficient: zero eigenvalues contribute nothing
+    q = np.zeros(n)
+    q[:7] = W.spectrum_inverse(7)
+    assert orc.exact_entropy(W.dense_density(q, 4)) == pytest.approx(shannon(q), rel=1e-12)
+
+
+def test_poisson_spectrum_closed_form(orc):
+    # tridiagonal experiment (Section 5): lambda_i = (4/2n) sin^2(i pi/(2n+2))
+    n = 150
+    csr = W.poisson_csr(n)
+    lam = W.poisson_eigenvalues(n)
+    assert abs(lam.sum() - 1.0) < 1e-14
+    e = orc.jacobi_eigen(W.csr_to_dense(csr))
+    assert np.max(np.abs(np.sort(e) - np.sort(lam))) < 1e-13 * lam.max()
+    assert orc.exact_entropy(csr) == pytest.approx(shannon(lam), rel=1e-13)
+    fast = W.poisson_csr_fast(n)
+    for a, b in zip(fast[:3], csr[:3]):
+        assert np.array_equal(a, b)
+
+
+def test_poisson_entropy_values():
+    # closed-form entropies of the normalised tridiagonal matrix at the paper's sizes
+    for n, want in ((5000, 8.210417630846004), (100000, 11.206076508473785)):
+        assert shannon(W.poisson_eigenvalues(n)) == pytest.approx(want, rel=1e-12)
+
+
+def test_rp_with_orthonormal_sketch_recovers_spectrum(orc):
+    # Algorithm 3: if Pi has orthonormal columns spanning the range of R, the
+    # singular values of R Pi are exactly the nonzero p_i
+    n, k = 60, 6
+    p = np.zeros(n)
+    p[:k] = W.spectrum_inverse(k)
+    rng = np.random.default_rng(5)
+    U = W.random_orthogonal(n, rng)
+    R = (U * p) @ U.T
+    R = 0.5 * (R + R.T)
+    h, sig = orc.rp_entropy_with_pi(R, U[:, :10], k)
+    assert np.allclose(sig, p[:k], rtol=1e-12, atol=1e-15)
+    assert h == pytest.approx(shannon(p), rel=1e-12)
+    Q = W.random_orthogonal(n, rng)   # any orthogonal n x n sketch
+    h2, _ = orc.rp_entropy_with_pi(R, Q, k)
+    assert h2 == pytest.approx(shannon(p), rel=1e-11)
+
+
+def test_rp_gaussian_sketch_theorem3_sanity(orc):
+    n, k = 200, 5
+    p = np.zeros(n)
+    p[:k] = W.spectrum_exp(k, 2.0)
+    R = W.dense_density(p, 6)
+    h, sig = orc.rp_entropy(R, s=150, k=k, seed=3)
+    H = shannon(p)
+    # Theorem 3 with a generous eps; a sanity check, not a gate on the bound
+    eps = 0.5
+    assert abs(h - H) <= math.sqrt(eps) * H + math.sqrt(1.5) * eps
+    assert np.all(np.abs(sig ** 2 - p[:k] ** 2) <= eps * p[:k] ** 2)
+
+
+def test_mlp_gradient_finite_differences(orc):
+    rng = np.random.default_rng(0)
+    npar = orc.mlp_nparams()
+    assert npar == 64 * 16 + 64 + 64 * 64 + 64 + 2 * 64 + 2
+    P = rng.standard_normal(npar) * 0.3
+    X = rng.standard_normal((7, 16))
+    T = rng.standard_normal((7, 2))
+    loss, g = orc.mlp_loss_grad(P, X, T)
+    Y = orc.mlp_forward(P, X)
+    assert loss == pytest.approx(np.mean(np.sum((Y - T) ** 2, axis=1)), rel=1e-14)
+    idx = rng.choice(npar, 60, replace=False)
+    hstep = 1e-6
+    for i in idx:
+        Pp, Pm = P.copy(), P.copy()
+        Pp[i] += hstep
+        Pm[i] -= hstep
+        fd = (orc.mlp_loss_grad(Pp, X, T)[0] - orc.mlp_loss_grad(Pm, X, T)[0]) / (2 * hstep)
+        assert fd == pytest.approx(g[i], rel=1e-6, abs=2e-8)  # FD rounding ~ eps*loss/h
