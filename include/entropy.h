@@ -1,0 +1,225 @@
+/*
+ * entropy.h -- C ABI of libentropy, an MI355X (gfx950) library for the
+ * randomized von Neumann entropy estimators of Kontopoulou, Dexter,
+ * Szpankowski, Grama and Drineas (arXiv:1801.01072).
+ *
+ * Problem (Section 1.1, eqns. (1)-(4)): R is a real symmetric positive
+ * semidefinite n x n matrix with unit trace; H(R) = -sum_i p_i ln p_i =
+ * -tr(R ln R), p_i the eigenvalues of R, with 0 ln 0 = 0.
+ *
+ * Conventions for every entry point
+ *  - Nothing throws across this boundary.  Every call returns an ent_status;
+ *    on failure the status is negative, ent_last_error() describes it, and
+ *    the output structures are left untouched.
+ *  - Matrices are passed by descriptor (ent_matrix).  Their arrays live in
+ *    device memory of the current HIP device; the caller owns them and the
+ *    library never retains a pointer past the call.
+ *  - Scalar results are returned in host structures / host arrays owned by
+ *    the caller.
+ *  - Work is enqueued on opt->stream (a hipStream_t; NULL = the legacy
+ *    default stream).  Estimating calls synchronise that stream before they
+ *    return.  Distinct threads may call concurrently on distinct streams.
+ *  - Workspace (probe blocks, recurrence buffers, partial sums) is owned by
+ *    the library, cached per device between calls and released by
+ *    ent_release_workspace().  ent_set_workspace_limit() caps it; a call
+ *    that would exceed the cap returns ENT_ENOMEM.
+ */
+#ifndef ENTROPY_H
+#define ENTROPY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ENT_OK = 0,
+  ENT_EINVAL = -1,       /* null pointer, size < 1, unknown enum, bad layout  */
+  ENT_ENOTDENSITY = -2,  /* |tr R - 1| above tolerance (see ent_options)      */
+  ENT_ENOMEM = -3,       /* device allocation failed or workspace cap reached */
+  ENT_EDEVICE = -4,      /* a HIP runtime call failed                          */
+  ENT_ENUMERIC = -5,     /* p~1 <= 0, or a non-finite estimate                 */
+  ENT_EUNSUPPORTED = -6  /* valid request this build does not implement       */
+} ent_status;
+
+/* Estimator (Algorithm 1 = Taylor, Section 2; Algorithm 2 = Chebyshev,
+ * Section 3; Algorithm 3 = random projection, Section 4). */
+typedef enum {
+  ENT_TAYLOR = 0,
+  ENT_CHEBYSHEV = 1,
+  ENT_RANDPROJ = 2
+} ent_method;
+
+/* Arithmetic of the recurrence products R.V.  The power method, the
+ * coefficients and every reduction are always FP64. */
+typedef enum {
+  ENT_F64 = 0,    /* FP64 MFMA                                              */
+  ENT_F32 = 1,    /* FP32 MFMA                                              */
+  ENT_BF16X3 = 2  /* three BF16 MFMA products (hi.hi + hi.lo + lo.hi) with
+                     FP32 accumulation; dense only                          */
+} ent_precision;
+
+typedef enum { ENT_DENSE = 0, ENT_CSR = 1 } ent_layout;
+
+/* Storage type of a matrix (independent of the compute precision). */
+typedef enum { ENT_STORE_F64 = 0, ENT_STORE_F32 = 1 } ent_dtype;
+
+/* Probe vectors g_1..g_s: the paper draws standard Gaussians (Lemma 1);
+ * Rademacher signs are the other unbiased choice. */
+typedef enum { ENT_RADEMACHER = 0, ENT_GAUSSIAN = 1 } ent_probe_dist;
+
+enum {
+  ENT_FLAG_SKIP_TRACE_CHECK = 1  /* do not verify tr R = 1                    */
+};
+
+/*
+ * A density matrix on the device.
+ *  layout ENT_DENSE: values -> n x n row-major, leading dimension ld >= n
+ *                    elements; row_ptr/col_idx/nnz ignored.
+ *  layout ENT_CSR:   row_ptr -> int64[n+1] (row_ptr[0] = 0, non-decreasing,
+ *                    row_ptr[n] = nnz), col_idx -> int32[nnz] in [0, n),
+ *                    values -> nnz entries; ld ignored.
+ *  dtype: ENT_STORE_F64 (double) or ENT_STORE_F32 (float) values.
+ * R must be symmetric; symmetry is not checked (an asymmetric R is used as
+ * given in the products R.v).
+ */
+typedef struct {
+  int64_t n;
+  int32_t layout;
+  int32_t dtype;
+  int64_t ld;
+  int64_t nnz;
+  const void *values;
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+} ent_matrix;
+
+typedef struct {
+  int32_t power_iters;   /* t of Algorithm 4 (default 20)                      */
+  int32_t power_trials;  /* q of Algorithm 4 (default 1)                       */
+  double u_factor;       /* c in u = min{1, c p~1} (Algorithms 1-2: c = 6)     */
+  double u_fixed;        /* > 0: use this u and skip the power method          */
+  double cutoff;         /* lower end lo of the Chebyshev interval [lo, u];
+                            0 = the paper's [0, u] with the Lemma 3 closed
+                            form; > 0 = interpolant of x ln x on [lo, u]       */
+  int32_t precision;     /* ent_precision (default ENT_F64)                    */
+  int32_t probe_dist;    /* ent_probe_dist (default ENT_RADEMACHER)            */
+  int32_t rank_k;        /* Algorithm 3: number of singular values kept        */
+  int32_t sketch_width;  /* Algorithm 3: columns s of the Gaussian sketch      */
+  int32_t flags;         /* ENT_FLAG_* bits                                    */
+  int32_t reserved;
+  double trace_tol;      /* |tr R - 1| tolerance; 0 = 1e-10 (F64 storage) or
+                            1e-4 (F32 storage)                                 */
+  void *stream;          /* hipStream_t                                        */
+} ent_options;
+
+typedef struct {
+  double entropy;   /* H^: mean of the per-probe values h_j                   */
+  double std_err;   /* standard error of that mean over the probes           */
+  double p1_est;    /* p~1 from the power method (0 if u_fixed was given)    */
+  double u;         /* upper end of the approximation interval               */
+  double lo;        /* lower end of the approximation interval               */
+  int32_t degree;   /* m actually used                                       */
+  int32_t probes;   /* s actually used                                       */
+  int32_t method;   /* ent_method actually run                               */
+  int32_t precision;
+} ent_result;
+
+/* Fill *opt with the defaults listed above. */
+void ent_options_default(ent_options *opt);
+
+/*
+ * One estimate of H(R) (Algorithms 1 and 2, with Algorithm 4 for p~1).
+ *   method  ENT_TAYLOR:    h_j = ln(1/u) + sum_{k=1}^{m} g_j^T R (I - R/u)^k g_j / k
+ *           ENT_CHEBYSHEV: h_j = -g_j^T f_m(R) g_j, f_m = sum_w alpha_w T_w
+ *                          on [lo, u] (Lemma 3 coefficients when lo = 0)
+ *           ENT_RANDPROJ:  Algorithm 3 with a Gaussian sketch of
+ *                          opt->sketch_width columns, top opt->rank_k
+ *                          singular values (degree and probes ignored)
+ *   degree  m >= 1; probes s >= 1; seed keys the Philox4x32-10 stream of
+ *   probes (stream 0), power-method start vectors (stream 1) and sketch
+ *   entries (stream 2).
+ * opt may be NULL (defaults).  Returns ENT_EINVAL for bad arguments,
+ * ENT_ENOTDENSITY if the trace check fails, ENT_ENUMERIC if p~1 <= 0 or the
+ * estimate is not finite.
+ */
+ent_status ent_entropy_estimate(const ent_matrix *R, int32_t method, int32_t degree,
+                                int32_t probes, uint64_t seed, const ent_options *opt,
+                                ent_result *out);
+
+/*
+ * Same as ent_entropy_estimate, and also copies per-probe detail to host
+ * arrays the caller owns (either may be NULL):
+ *   per_probe[j]            = h_j, j < probes
+ *   moments[k * probes + j] = Chebyshev: d_{k,j} = g_j^T T_k(X) g_j, k = 0..m,
+ *                             X = (2R - (u+lo)I)/(u-lo);
+ *                             Taylor: e_{k,j} = g_j^T (R/u)(I - R/u)^k g_j,
+ *                             k = 0..m.
+ * Used for per-probe parity checks.  RANDPROJ: per_probe[i] = the i-th kept
+ * singular value (rank_k entries); moments unused.
+ */
+ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int32_t degree,
+                                       int32_t probes, uint64_t seed, const ent_options *opt,
+                                       ent_result *out, double *per_probe, double *moments);
+
+/*
+ * Algorithm 4 (Appendix A): q trials of t power iterations from random sign
+ * vectors, each iterate divided by its 2-norm, Rayleigh quotient of the last
+ * iterate, maximum over trials.  *p1 (host) receives p~1.
+ */
+ent_status ent_power_method(const ent_matrix *R, int32_t t, int32_t q, uint64_t seed,
+                            void *stream, double *p1);
+
+/*
+ * Chebyshev coefficients alpha_0..alpha_m of x ln x on [lo, u], computed in
+ * FP64 on the device and copied to alpha (host, m+1 entries).  lo = 0: the
+ * closed form of Lemma 3; lo > 0: the interpolant at the m+1 Chebyshev points
+ * of [lo, u].  Requires 0 <= lo < u, m >= 1.
+ */
+ent_status ent_chebyshev_coeffs(double lo, double u, int32_t m, double *alpha);
+
+/* Parameter rules of the paper (host helpers, no device work). */
+int32_t ent_probes_for(double eps, double delta);              /* ceil(20 ln(2/delta)/eps^2), Lemma 1     */
+int32_t ent_degree_taylor(double u, double ell, double eps);   /* ceil((u/ell) ln(1/eps)), Theorem 1      */
+int32_t ent_degree_chebyshev(double u, double ell, double eps);/* ceil(sqrt(u/(2 eps ell ln(1/(1-ell))))), Theorem 2 */
+int32_t ent_power_trials_for(double delta);                    /* ceil(4.82 ln(1/delta)), Lemma 5         */
+int32_t ent_power_iters_for(int64_t n);                        /* ceil(ln sqrt(4n)), Lemma 5              */
+
+/*
+ * Phase timing of the last estimate made on the calling thread, from HIP
+ * events recorded on the estimate's stream between launches (only while
+ * enabled on that thread; off by default).  For profiling: the events add a
+ * few microseconds per launch.
+ */
+typedef struct {
+  double total_ms;       /* first to last enqueued operation                  */
+  double power_ms;       /* power method, all trials                          */
+  double steps_ms;       /* the recurrence products R.V, summed               */
+  double step_max_ms;    /* longest single product launch                     */
+  double other_ms;       /* probes, trace check, setup and reductions         */
+  int32_t step_launches;
+  int32_t power_launches;
+} ent_timing;
+
+ent_status ent_timing_enable(int32_t on);
+ent_status ent_last_timing(ent_timing *out);
+
+/* Workspace control (device memory cached between calls, per device). */
+ent_status ent_set_workspace_limit(size_t bytes);  /* 0 = no limit */
+ent_status ent_release_workspace(void);
+size_t ent_workspace_bytes(void);
+
+/* Thread-local description of the last failure on this thread ("" if none).
+ * Valid until the next call on this thread. */
+const char *ent_last_error(void);
+
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int32_t ent_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENTROPY_H */

@@ -1,0 +1,294 @@
+"""Python binding of libentropy: randomized von Neumann entropy estimators
+(Kontopoulou et al., arXiv:1801.01072) on MI355X.
+
+Argument marshalling only.  Every step of every estimate runs in the gfx950
+kernels of ``libentropy.so``; there is no CPU or PyTorch fallback, and
+importing this package fails loudly if the library has not been built.
+PyTorch supplies device memory (tensors) and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libentropy.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- enums (mirror include/entropy.h) ---------------------------------------
+OK, EINVAL, ENOTDENSITY, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+TAYLOR, CHEBYSHEV, RANDPROJ = 0, 1, 2
+F64, F32, BF16X3 = 0, 1, 2
+DENSE, CSR = 0, 1
+STORE_F64, STORE_F32 = 0, 1
+RADEMACHER, GAUSSIAN = 0, 1
+FLAG_SKIP_TRACE_CHECK = 1
+
+_METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ}
+_PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
+_DISTS = {"rademacher": RADEMACHER, "gaussian": GAUSSIAN}
+
+
+class EntMatrix(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("layout", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("ld", ctypes.c_int64), ("nnz", ctypes.c_int64), ("values", ctypes.c_void_p),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class EntOptions(ctypes.Structure):
+    _fields_ = [("power_iters", ctypes.c_int32), ("power_trials", ctypes.c_int32),
+                ("u_factor", ctypes.c_double), ("u_fixed", ctypes.c_double),
+                ("cutoff", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("probe_dist", ctypes.c_int32), ("rank_k", ctypes.c_int32),
+                ("sketch_width", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("trace_tol", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class EntResult(ctypes.Structure):
+    _fields_ = [("entropy", ctypes.c_double), ("std_err", ctypes.c_double),
+                ("p1_est", ctypes.c_double), ("u", ctypes.c_double), ("lo", ctypes.c_double),
+                ("degree", ctypes.c_int32), ("probes", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class EntTiming(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double), ("power_ms", ctypes.c_double),
+                ("steps_ms", ctypes.c_double), ("step_max_ms", ctypes.c_double),
+                ("other_ms", ctypes.c_double), ("step_launches", ctypes.c_int32),
+                ("power_launches", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "ent_options_default": (None, [ctypes.POINTER(EntOptions)]),
+    "ent_entropy_estimate": (ctypes.c_int, [ctypes.POINTER(EntMatrix), ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_uint64,
+                                            ctypes.POINTER(EntOptions), ctypes.POINTER(EntResult)]),
+    "ent_entropy_estimate_detail": (ctypes.c_int, [ctypes.POINTER(EntMatrix), ctypes.c_int32,
+                                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                                   ctypes.POINTER(EntOptions),
+                                                   ctypes.POINTER(EntResult), _P, _P]),
+    "ent_power_method": (ctypes.c_int, [ctypes.POINTER(EntMatrix), ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_uint64, _P, ctypes.POINTER(ctypes.c_double)]),
+    "ent_chebyshev_coeffs": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P]),
+    "ent_probes_for": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double]),
+    "ent_degree_taylor": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "ent_degree_chebyshev": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "ent_power_trials_for": (ctypes.c_int32, [ctypes.c_double]),
+    "ent_power_iters_for": (ctypes.c_int32, [ctypes.c_int64]),
+    "ent_timing_enable": (ctypes.c_int, [ctypes.c_int32]),
+    "ent_last_timing": (ctypes.c_int, [ctypes.POINTER(EntTiming)]),
+    "ent_set_workspace_limit": (ctypes.c_int, [ctypes.c_size_t]),
+    "ent_release_workspace": (ctypes.c_int, []),
+    "ent_workspace_bytes": (ctypes.c_size_t, []),
+    "ent_last_error": (ctypes.c_char_p, []),
+    "ent_version": (ctypes.c_int32, []),
+}
+for _name, (_res, _args) in _SIGNATURES.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class EntropyError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+        self.message = message
+
+
+def last_error() -> str:
+    return _lib.ent_last_error().decode()
+
+
+def _check(status: int):
+    if status != OK:
+        raise EntropyError(status, last_error())
+
+
+@dataclass
+class Result:
+    entropy: float
+    std_err: float
+    p1_est: float
+    u: float
+    lo: float
+    degree: int
+    probes: int
+    method: int
+    precision: int
+
+
+def _result(r: EntResult) -> Result:
+    return Result(r.entropy, r.std_err, r.p1_est, r.u, r.lo, r.degree, r.probes, r.method,
+                  r.precision)
+
+
+# ---- matrices -----------------------------------------------------------------
+def _store_dtype(t) -> int:
+    import torch
+
+    if t.dtype == torch.float64:
+        return STORE_F64
+    if t.dtype == torch.float32:
+        return STORE_F32
+    raise TypeError(f"unsupported value dtype {t.dtype}")
+
+
+def dense_matrix(R) -> EntMatrix:
+    """Descriptor of a dense 2-D device tensor with unit column stride."""
+    if R.dim() != 2 or R.shape[0] != R.shape[1]:
+        raise ValueError("R must be a square 2-D tensor")
+    if R.stride(1) != 1:
+        raise ValueError("R must have unit column stride (row-major)")
+    return EntMatrix(R.shape[0], DENSE, _store_dtype(R), R.stride(0), 0, R.data_ptr(), None, None)
+
+
+def csr_matrix(row_ptr, col_idx, values, n: int) -> EntMatrix:
+    """Descriptor of a CSR matrix held in device tensors (int64, int32, values)."""
+    import torch
+
+    if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32:
+        raise TypeError("row_ptr must be int64 and col_idx int32")
+    return EntMatrix(n, CSR, _store_dtype(values), 0, values.numel(), values.data_ptr(),
+                     row_ptr.data_ptr(), col_idx.data_ptr())
+
+
+def as_matrix(R) -> EntMatrix:
+    if isinstance(R, EntMatrix):
+        return R
+    if isinstance(R, tuple):
+        rp, ci, val, n = R
+        return csr_matrix(rp, ci, val, n)
+    return dense_matrix(R)
+
+
+def _stream_handle(stream):
+    if stream is not None:
+        return int(getattr(stream, "cuda_stream", stream))
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:  # pragma: no cover - torch without a device
+        pass
+    return None
+
+
+def options(precision="f64", probe_dist="rademacher", power_iters=20, power_trials=1,
+            u_factor=6.0, u_fixed=0.0, cutoff=0.0, rank_k=0, sketch_width=0, flags=0,
+            trace_tol=0.0, stream=None) -> EntOptions:
+    o = EntOptions()
+    _lib.ent_options_default(ctypes.byref(o))
+    o.precision = _PRECISIONS.get(precision, precision)
+    o.probe_dist = _DISTS.get(probe_dist, probe_dist)
+    o.power_iters = power_iters
+    o.power_trials = power_trials
+    o.u_factor = u_factor
+    o.u_fixed = u_fixed
+    o.cutoff = cutoff
+    o.rank_k = rank_k
+    o.sketch_width = sketch_width
+    o.flags = flags
+    o.trace_tol = trace_tol
+    o.stream = _stream_handle(stream)
+    return o
+
+
+# ---- entry points ----------------------------------------------------------------
+def entropy_estimate(R, method="chebyshev", degree=30, probes=50, seed=0, **opts) -> Result:
+    """One estimate of H(R) (Algorithms 1-3); see ent_entropy_estimate."""
+    M = as_matrix(R)
+    o = options(**opts)
+    res = EntResult()
+    _check(_lib.ent_entropy_estimate(ctypes.byref(M), _METHODS.get(method, method), degree, probes,
+                                     seed, ctypes.byref(o), ctypes.byref(res)))
+    return _result(res)
+
+
+def entropy_estimate_detail(R, method="chebyshev", degree=30, probes=50, seed=0, **opts):
+    """Estimate plus per-probe values h_j and the moment table (degree+1, probes)."""
+    M = as_matrix(R)
+    o = options(**opts)
+    res = EntResult()
+    meth = _METHODS.get(method, method)
+    nper = opts.get("rank_k", 0) if meth == RANDPROJ else probes
+    per = np.zeros(max(nper, 1), dtype=np.float64)
+    mom = np.zeros((degree + 1) * probes if meth != RANDPROJ else 1, dtype=np.float64)
+    _check(_lib.ent_entropy_estimate_detail(ctypes.byref(M), meth, degree, probes, seed,
+                                            ctypes.byref(o), ctypes.byref(res),
+                                            per.ctypes.data_as(_P), mom.ctypes.data_as(_P)))
+    if meth == RANDPROJ:
+        return _result(res), per[:nper], None
+    return _result(res), per, mom.reshape(degree + 1, probes)
+
+
+def power_method(R, t=20, q=1, seed=0, stream=None) -> float:
+    """Algorithm 4 with per-iteration normalisation; returns p~1."""
+    M = as_matrix(R)
+    v = ctypes.c_double()
+    _check(_lib.ent_power_method(ctypes.byref(M), t, q, seed, _stream_handle(stream), ctypes.byref(v)))
+    return v.value
+
+
+def chebyshev_coeffs(lo: float, u: float, m: int) -> np.ndarray:
+    a = np.zeros(m + 1, dtype=np.float64)
+    _check(_lib.ent_chebyshev_coeffs(lo, u, m, a.ctypes.data_as(_P)))
+    return a
+
+
+def probes_for(eps: float, delta: float) -> int:
+    return _lib.ent_probes_for(eps, delta)
+
+
+def degree_taylor(u: float, ell: float, eps: float) -> int:
+    return _lib.ent_degree_taylor(u, ell, eps)
+
+
+def degree_chebyshev(u: float, ell: float, eps: float) -> int:
+    return _lib.ent_degree_chebyshev(u, ell, eps)
+
+
+def power_trials_for(delta: float) -> int:
+    return _lib.ent_power_trials_for(delta)
+
+
+def power_iters_for(n: int) -> int:
+    return _lib.ent_power_iters_for(n)
+
+
+def timing_enable(on: bool = True):
+    """Record HIP events between launches of later estimates on this thread."""
+    _check(_lib.ent_timing_enable(1 if on else 0))
+
+
+def last_timing() -> dict:
+    t = EntTiming()
+    _check(_lib.ent_last_timing(ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in EntTiming._fields_}
+
+
+def set_workspace_limit(nbytes: int):
+    _check(_lib.ent_set_workspace_limit(nbytes))
+
+
+def release_workspace():
+    _check(_lib.ent_release_workspace())
+
+
+def workspace_bytes() -> int:
+    return _lib.ent_workspace_bytes()
+
+
+def version() -> int:
+    return _lib.ent_version()

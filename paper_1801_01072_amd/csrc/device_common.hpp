@@ -1,0 +1,129 @@
+// device_common.hpp -- device-side helpers shared by the gfx950 kernels of
+// libentropy: the Philox4x32-10 counter generator and the probe mapping,
+// wave64 reductions and MFMA wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ent {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten S-box rounds over a
+// 128-bit counter; the 64-bit key is advanced by the two Weyl constants
+// between rounds.
+// ---------------------------------------------------------------------------
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+    U4 n;
+    n.x = hi1 ^ c.y ^ k0;
+    n.y = lo1;
+    n.z = hi0 ^ c.w ^ k1;
+    n.w = lo0;
+    c = n;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Counter layout: (row mod 2^32, block, stream, row >> 32); key = seed.
+__device__ __forceinline__ U4 philox_block(uint64_t seed, uint32_t stream, int64_t row,
+                                           uint32_t block) {
+  U4 c;
+  c.x = (uint32_t)((uint64_t)row & 0xffffffffu);
+  c.y = block;
+  c.z = stream;
+  c.w = (uint32_t)((uint64_t)row >> 32);
+  return philox10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+}
+
+// 32 Rademacher signs of probes [32*word, 32*word+32) of one row, as a bit
+// mask: bit b set means probe 32*word+b is -1.  One Philox block serves 128
+// probes: block = probe >> 7, word index (probe >> 5) & 3.
+__device__ __forceinline__ uint32_t rademacher_word(uint64_t seed, uint32_t stream, int64_t row,
+                                                    int32_t word) {
+  const U4 o = philox_block(seed, stream, row, (uint32_t)word >> 2);
+  switch (word & 3) {
+    case 0: return o.x;
+    case 1: return o.y;
+    case 2: return o.z;
+    default: return o.w;
+  }
+}
+
+__device__ __forceinline__ double rademacher(uint64_t seed, uint32_t stream, int64_t row,
+                                             int64_t probe) {
+  const uint32_t w = rademacher_word(seed, stream, row, (int32_t)(probe >> 5));
+  return ((w >> (probe & 31)) & 1u) ? -1.0 : 1.0;
+}
+
+// Standard Gaussian by Box-Muller on two 53-bit uniforms of one Philox block
+// (block = probe >> 1); even probes take the cosine branch, odd the sine.
+__device__ __forceinline__ double gaussian(uint64_t seed, uint32_t stream, int64_t row,
+                                           int64_t probe) {
+  const U4 o = philox_block(seed, stream, row, (uint32_t)((uint64_t)probe >> 1));
+  const uint64_t a = ((((uint64_t)o.y) << 32) | o.x) >> 11;
+  const uint64_t b = ((((uint64_t)o.w) << 32) | o.z) >> 11;
+  const double u1 = ((double)a + 1.0) * 0x1.0p-53;
+  const double u2 = (double)b * 0x1.0p-53;
+  const double r = sqrt(-2.0 * log(u1));
+  const double th = 6.283185307179586476925286766559 * u2;
+  return (probe & 1) ? r * sin(th) : r * cos(th);
+}
+
+// ---------------------------------------------------------------------------
+// wave64 reductions (fixed butterfly order: deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// MFMA 16x16x4 for FP64 and FP32.  Operand layout (per lane l of the wave):
+//   A: row l%16, k-slot l/16      B: k-slot l/16, column l%16
+//   D register r (r = 0..3), column l%16, row:
+//     FP32: 4*(l/16) + r      FP64: (l/16) + 4*r
+// (measured on gfx950 with a one-wave layout probe against a host product).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Mfma16;
+
+template <>
+struct Mfma16<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int drow(int q, int r) { return q + 4 * r; }
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma16<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int drow(int q, int r) { return 4 * q + r; }
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// XCD-aware remap of a linear workgroup id: the hardware deals consecutive
+// ids round-robin over the 8 XCDs; this gives each XCD a contiguous range of
+// logical tiles so that tiles sharing operands share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  if ((nb & 7) != 0) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+}  // namespace ent

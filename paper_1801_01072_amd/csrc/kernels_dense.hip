@@ -1,0 +1,177 @@
+// kernels_dense.hip -- one step of the polynomial recurrence for dense R on
+// gfx950 matrix cores (FP64 / FP32 MFMA 16x16x4), with the recurrence update
+// and the per-probe dot products fused into the epilogue.
+//
+//   Y = a * (R V_k)                                  (MFMA, K = n)
+//   Z = c1*Y + c2*b*V_k + cw*V_{k-1}  -> V_{k+1}      (epilogue)
+//   part[slot][tile][j] = sum_{rows of tile} g_ij * (dot_y ? Y : Z)_ij
+//
+// Chebyshev (Algorithm 2 via the forward three-term recurrence of T_w,
+// Section 3 / Appendix B): a = 2/(u-lo), b = (u+lo)/(u-lo); step 0 has
+// (c1,c2,cw) = (1,-1,0), later steps (2,-2,-1); dots with Z give
+// d_{k+1,j} = g_j^T T_{k+1}(X) g_j.  Taylor (Algorithm 1): a = 1/u, b = 1,
+// (c1,c2,cw) = (-1,1,0) so Z = (I - R/u) V_k, dots with Y give
+// e_{k,j} = g_j^T (R/u)(I - R/u)^k g_j.
+//
+// Tiling: a workgroup of 4 waves owns 64 rows x BN probe columns.  Each wave
+// owns 16 rows and streams its own slab of R straight from HBM into
+// registers: lane (m = l%16, q = l/16) loads 8 consecutive elements
+// R[row m][kc + 8q .. kc + 8q + 7] and feeds them to 8 successive MFMAs, so
+// MFMA k-slot q of call t is column kc + 8q + t (the k order inside a chunk
+// is permuted consistently for A and B).  The V_k chunk (32 x BN) is shared
+// by the 4 waves through LDS.  Row/column padding of the V buffers is zero,
+// so only the loads of R need bounds checks.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace ent {
+
+template <typename T, int BN>
+__global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
+  using M = Mfma16<T>;
+  using v4 = typename M::v4;
+  constexpr int BM = 64, BK = 32, PAD = 2, LDL = BN + PAD;
+  constexpr int NSUB = BN / 16;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  constexpr int VPR = BN / VEC;
+  constexpr int NV = BK * VPR / 256;
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
+
+  __shared__ __attribute__((aligned(16))) T Vs[BK * LDL];
+  __shared__ double red[2][4][BN];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ntn = (int)(a.ldv / BN);
+  const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int tm = b / ntn, tn = b % ntn;
+  const int64_t n = a.n, ldv = a.ldv;
+  const T *__restrict__ R = (const T *)a.R;
+  const T *__restrict__ Vk = (const T *)a.Vk;
+  const int64_t col0 = (int64_t)tn * BN;
+  const int m16 = lane & 15, kq = lane >> 4;
+  const int64_t arow = (int64_t)tm * BM + 16 * w + m16;
+  const bool arow_ok = arow < n;
+  const T *Arow = R + (arow_ok ? arow : 0) * a.ldr;
+
+  v4 acc[NSUB];
+#pragma unroll
+  for (int c = 0; c < NSUB; ++c) acc[c] = v4{0, 0, 0, 0};
+
+  vec_t vreg[NV];
+  T areg[8];
+
+  auto load_v = [&](int64_t kc) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int idx = tid + i * 256;
+      const int r = idx / VPR, cv = idx % VPR;
+      vreg[i] = *(const vec_t *)(Vk + (kc + r) * ldv + col0 + cv * VEC);
+    }
+  };
+  auto load_a = [&](int64_t kc) {
+    const int64_t k0 = kc + 8 * kq;
+    if (arow_ok && k0 + 8 <= n) {
+#pragma unroll
+      for (int h = 0; h < 8 / VEC; ++h) {
+        const vec_t v = *(const vec_t *)(Arow + k0 + h * VEC);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) areg[h * VEC + e] = v[e];
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) areg[t] = (arow_ok && k0 + t < n) ? Arow[k0 + t] : T(0);
+    }
+  };
+  auto store_v = [&]() {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int idx = tid + i * 256;
+      const int r = idx / VPR, cv = idx % VPR;
+      T *dst = Vs + r * LDL + cv * VEC;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) dst[e] = vreg[i][e];
+    }
+  };
+
+  load_v(0);
+  load_a(0);
+  for (int64_t kc = 0; kc < n; kc += BK) {
+    store_v();
+    T acur[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acur[t] = areg[t];
+    __syncthreads();
+    if (kc + BK < n) {
+      load_v(kc + BK);
+      load_a(kc + BK);
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const T *brow = Vs + (8 * kq + t) * LDL + m16;
+#pragma unroll
+      for (int c = 0; c < NSUB; ++c) acc[c] = M::mma(acur[t], brow[16 * c], acc[c]);
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue ----
+  const T ta = (T)a.scal[S_A];
+  const T tb = (T)(a.c2 * a.scal[S_B]);
+  const T tc1 = (T)a.c1, tcw = (T)a.cw;
+  const T *Vkm1 = (const T *)a.Vkm1;
+  const T *__restrict__ G = (const T *)a.G;
+  T *Vkp1 = (T *)a.Vkp1;
+  const bool use_m1 = (a.cw != 0.0) && Vkm1;
+  const bool want_gg = a.slot_gg >= 0;
+  const int64_t rbase = (int64_t)tm * BM + 16 * w;
+#pragma unroll
+  for (int c = 0; c < NSUB; ++c) {
+    const int64_t col = col0 + 16 * c + m16;
+    double ds = 0.0, gs = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t off = (rbase + M::drow(kq, r)) * ldv + col;
+      const T y = ta * acc[c][r];
+      T z = tc1 * y + tb * Vk[off];
+      if (use_m1) z += tcw * Vkm1[off];
+      if (Vkp1) Vkp1[off] = z;
+      const T g = G[off];
+      ds += (double)g * (double)(a.dot_y ? y : z);
+      if (want_gg) gs += (double)g * (double)g;
+    }
+    ds += __shfl_xor(ds, 16, 64);
+    ds += __shfl_xor(ds, 32, 64);
+    gs += __shfl_xor(gs, 16, 64);
+    gs += __shfl_xor(gs, 32, 64);
+    if (kq == 0) {
+      red[0][w][16 * c + m16] = ds;
+      red[1][w][16 * c + m16] = gs;
+    }
+  }
+  __syncthreads();
+  for (int col = tid; col < BN; col += 256) {
+    const double s = red[0][0][col] + red[0][1][col] + red[0][2][col] + red[0][3][col];
+    a.part[((int64_t)a.slot * a.ntile + tm) * ldv + col0 + col] = s;
+    if (want_gg) {
+      const double g2 = red[1][0][col] + red[1][1][col] + red[1][2][col] + red[1][3][col];
+      a.part[((int64_t)a.slot_gg * a.ntile + tm) * ldv + col0 + col] = g2;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st) {
+  const int ntn = (int)(a.ldv / a.bn);
+  const unsigned grid = (unsigned)(a.ntile * ntn);
+  switch (a.bn) {
+    case 64: dense_step_kernel<T, 64><<<grid, 256, 0, st>>>(a); break;
+    case 128: dense_step_kernel<T, 128><<<grid, 256, 0, st>>>(a); break;
+    case 256: dense_step_kernel<T, 256><<<grid, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_dense_step<double>(const DenseStepArgs &, hipStream_t);
+template hipError_t launch_dense_step<float>(const DenseStepArgs &, hipStream_t);
+
+}  // namespace ent
