@@ -71,7 +71,9 @@ typedef enum { ENT_STORE_F64 = 0, ENT_STORE_F32 = 1 } ent_dtype;
 typedef enum { ENT_RADEMACHER = 0, ENT_GAUSSIAN = 1 } ent_probe_dist;
 
 enum {
-  ENT_FLAG_SKIP_TRACE_CHECK = 1  /* do not verify tr R = 1                    */
+  ENT_FLAG_SKIP_TRACE_CHECK = 1, /* do not verify tr R = 1                    */
+  ENT_FLAG_AUTOTUNE = 2          /* batches: time the candidate tile shapes on
+                                    the batch if no cached choice exists      */
 };
 
 /*
@@ -196,15 +198,52 @@ int32_t ent_power_iters_for(int64_t n);                        /* ceil(ln sqrt(4
 typedef struct {
   double total_ms;       /* first to last enqueued operation                  */
   double power_ms;       /* power method, all trials                          */
-  double steps_ms;       /* the recurrence products R.V, summed               */
+  double steps_ms;       /* the recurrence product kernels R.V, summed        */
   double step_max_ms;    /* longest single product launch                     */
+  double epilogue_ms;    /* separate epilogue kernels (BF16x3 path), summed   */
   double other_ms;       /* probes, trace check, setup and reductions         */
   int32_t step_launches;
   int32_t power_launches;
+  int32_t epilogue_launches;
+  int32_t reserved;
 } ent_timing;
 
 ent_status ent_timing_enable(int32_t on);
 ent_status ent_last_timing(ent_timing *out);
+
+/*
+ * Batches of dense density matrices (uneven n): every phase of the estimate
+ * runs as one grouped launch over all matrices.  Matrix b uses probe seed
+ * seed + b.  Precision ENT_F32 or ENT_F64 (compute); storage of all matrices
+ * must be the same type.  Each matrix is copied into an aligned compute-type
+ * buffer at the start of every run (so later changes of the caller's values
+ * are seen by the next launch; the caller's pointers must stay valid while a
+ * graph exists).
+ *
+ * ent_entropy_estimate_batched: one synchronous run; outs[count].
+ * ent_graph_create: plans the batch (workspace, descriptor and tile tables,
+ *   tile shape -- from the autotune cache, or timed on the batch when
+ *   ENT_FLAG_AUTOTUNE is set; the cache persists as JSON in the file named by
+ *   the environment variable ENT_AUTOTUNE_CACHE), then captures the whole
+ *   launch sequence into a hipGraph on a private stream.
+ * ent_graph_launch: replays the graph, synchronises, fills outs[count].
+ * ent_graph_per_probe: h_j of the last launch, per_probe[count * probes].
+ * ent_graph_time_eager: runs the same sequence without the graph, recording
+ *   phase events (for profiling), fills outs and *timing.
+ * ent_graph_destroy: releases the graph, its workspace and stream.
+ */
+typedef struct ent_graph_s *ent_graph;
+ent_status ent_entropy_estimate_batched(const ent_matrix *Rs, int32_t count, int32_t method,
+                                        int32_t degree, int32_t probes, uint64_t seed,
+                                        const ent_options *opt, ent_result *outs);
+ent_status ent_graph_create(const ent_matrix *Rs, int32_t count, int32_t method, int32_t degree,
+                            int32_t probes, uint64_t seed, const ent_options *opt, ent_graph *graph);
+ent_status ent_graph_launch(ent_graph graph, ent_result *outs);
+ent_status ent_graph_per_probe(ent_graph graph, double *per_probe);
+ent_status ent_graph_time_eager(ent_graph graph, ent_result *outs, ent_timing *timing);
+int32_t ent_graph_tile_rows(ent_graph graph);       /* 64 or 128 (chosen tile shape) */
+size_t ent_graph_workspace_bytes(ent_graph graph);
+ent_status ent_graph_destroy(ent_graph graph);
 
 /* Workspace control (device memory cached between calls, per device). */
 ent_status ent_set_workspace_limit(size_t bytes);  /* 0 = no limit */

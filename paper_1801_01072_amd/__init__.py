@@ -31,6 +31,7 @@ DENSE, CSR = 0, 1
 STORE_F64, STORE_F32 = 0, 1
 RADEMACHER, GAUSSIAN = 0, 1
 FLAG_SKIP_TRACE_CHECK = 1
+FLAG_AUTOTUNE = 2
 
 _METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ}
 _PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
@@ -63,8 +64,9 @@ class EntResult(ctypes.Structure):
 class EntTiming(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_double), ("power_ms", ctypes.c_double),
                 ("steps_ms", ctypes.c_double), ("step_max_ms", ctypes.c_double),
-                ("other_ms", ctypes.c_double), ("step_launches", ctypes.c_int32),
-                ("power_launches", ctypes.c_int32)]
+                ("epilogue_ms", ctypes.c_double), ("other_ms", ctypes.c_double),
+                ("step_launches", ctypes.c_int32), ("power_launches", ctypes.c_int32),
+                ("epilogue_launches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -85,6 +87,19 @@ _SIGNATURES = {
     "ent_degree_chebyshev": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "ent_power_trials_for": (ctypes.c_int32, [ctypes.c_double]),
     "ent_power_iters_for": (ctypes.c_int32, [ctypes.c_int64]),
+    "ent_entropy_estimate_batched": (ctypes.c_int, [ctypes.POINTER(EntMatrix), ctypes.c_int32,
+                                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.c_uint64, ctypes.POINTER(EntOptions),
+                                                    ctypes.POINTER(EntResult)]),
+    "ent_graph_create": (ctypes.c_int, [ctypes.POINTER(EntMatrix), ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                        ctypes.POINTER(EntOptions), ctypes.POINTER(_P)]),
+    "ent_graph_launch": (ctypes.c_int, [_P, ctypes.POINTER(EntResult)]),
+    "ent_graph_per_probe": (ctypes.c_int, [_P, _P]),
+    "ent_graph_time_eager": (ctypes.c_int, [_P, ctypes.POINTER(EntResult), ctypes.POINTER(EntTiming)]),
+    "ent_graph_tile_rows": (ctypes.c_int32, [_P]),
+    "ent_graph_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "ent_graph_destroy": (ctypes.c_int, [_P]),
     "ent_timing_enable": (ctypes.c_int, [ctypes.c_int32]),
     "ent_last_timing": (ctypes.c_int, [ctypes.POINTER(EntTiming)]),
     "ent_set_workspace_limit": (ctypes.c_int, [ctypes.c_size_t]),
@@ -276,6 +291,74 @@ def last_timing() -> dict:
     t = EntTiming()
     _check(_lib.ent_last_timing(ctypes.byref(t)))
     return {f: getattr(t, f) for f, _ in EntTiming._fields_}
+
+
+# ---- batches ----------------------------------------------------------------------
+def _mat_array(mats):
+    arr = (EntMatrix * len(mats))()
+    for i, R in enumerate(mats):
+        arr[i] = as_matrix(R)
+    return arr
+
+
+def entropy_estimate_batched(mats, method="chebyshev", degree=40, probes=64, seed=0, **opts):
+    """One synchronous run over a batch of dense matrices; matrix b uses seed + b."""
+    arr = _mat_array(mats)
+    o = options(**opts)
+    outs = (EntResult * len(mats))()
+    _check(_lib.ent_entropy_estimate_batched(arr, len(mats), _METHODS.get(method, method), degree,
+                                             probes, seed, ctypes.byref(o), outs))
+    return [_result(r) for r in outs]
+
+
+class Graph:
+    """A planned batch captured into a hipGraph (see ent_graph_create)."""
+
+    def __init__(self, mats, method="chebyshev", degree=40, probes=64, seed=0, **opts):
+        self._mats = list(mats)  # keep the tensors alive while the graph exists
+        self._arr = _mat_array(self._mats)
+        self.count = len(self._mats)
+        self.probes = probes
+        o = options(**opts)
+        h = _P()
+        _check(_lib.ent_graph_create(self._arr, self.count, _METHODS.get(method, method), degree,
+                                     probes, seed, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        outs = (EntResult * self.count)()
+        _check(_lib.ent_graph_launch(self._h, outs))
+        return [_result(r) for r in outs]
+
+    def per_probe(self) -> np.ndarray:
+        a = np.zeros(self.count * self.probes, dtype=np.float64)
+        _check(_lib.ent_graph_per_probe(self._h, a.ctypes.data_as(_P)))
+        return a.reshape(self.count, self.probes)
+
+    def time_eager(self):
+        outs = (EntResult * self.count)()
+        t = EntTiming()
+        _check(_lib.ent_graph_time_eager(self._h, outs, ctypes.byref(t)))
+        return [_result(r) for r in outs], {f: getattr(t, f) for f, _ in EntTiming._fields_}
+
+    @property
+    def tile_rows(self) -> int:
+        return _lib.ent_graph_tile_rows(self._h)
+
+    @property
+    def workspace_bytes(self) -> int:
+        return _lib.ent_graph_workspace_bytes(self._h)
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.ent_graph_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:  # pragma: no cover - interpreter shutdown
+            pass
 
 
 def set_workspace_limit(nbytes: int):

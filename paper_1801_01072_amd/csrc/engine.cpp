@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -30,6 +31,9 @@ struct PhaseEvents {
   std::vector<hipEvent_t> ev;
   int power_begin = -1, power_end = -1, steps_begin = -1, steps_end = -1;
   int32_t power_launches = 0;
+  // split steps (product kernel + separate epilogue kernel): event index
+  // pairs of the product launches and of the epilogue launches
+  std::vector<std::pair<int, int>> main_spans, epi_spans;
   ~PhaseEvents() {
     for (auto e : ev) (void)hipEventDestroy(e);
   }
@@ -55,13 +59,24 @@ struct PhaseEvents {
     ent_timing t{};
     t.total_ms = between(0, (int)ev.size() - 1);
     t.power_ms = between(power_begin, power_end);
-    t.step_launches = steps_end - steps_begin;
-    for (int i = steps_begin; i >= 0 && i < steps_end; ++i) {
-      const double d = between(i, i + 1);
-      t.steps_ms += d;
-      if (d > t.step_max_ms) t.step_max_ms = d;
+    if (main_spans.empty()) {
+      t.step_launches = steps_end - steps_begin;
+      for (int i = steps_begin; i >= 0 && i < steps_end; ++i) {
+        const double d = between(i, i + 1);
+        t.steps_ms += d;
+        if (d > t.step_max_ms) t.step_max_ms = d;
+      }
+    } else {
+      t.step_launches = (int32_t)main_spans.size();
+      for (auto &sp : main_spans) {
+        const double d = between(sp.first, sp.second);
+        t.steps_ms += d;
+        if (d > t.step_max_ms) t.step_max_ms = d;
+      }
+      for (auto &sp : epi_spans) t.epilogue_ms += between(sp.first, sp.second);
+      t.epilogue_launches = (int32_t)epi_spans.size();
     }
-    t.other_ms = t.total_ms - t.power_ms - t.steps_ms;
+    t.other_ms = t.total_ms - t.power_ms - t.steps_ms - t.epilogue_ms;
     t.power_launches = power_launches;
     g_last_timing = t;
   }
@@ -207,25 +222,25 @@ ent_status validate_options(const ent_options &o) {
 // ---------------------------------------------------------------------------
 template <typename T>
 ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t t, int32_t q,
-                         uint64_t seed, double *x0, double *x1, double *p0, double *p1,
+                         uint64_t seed, double *x0, double *x1, double *part3, double *norm,
                          double *scal, hipStream_t st) {
   const int64_t n = R->n;
   for (int32_t trial = 0; trial < q; ++trial) {
     HIP_TRY(ent::launch_power_start(x0, n, seed, trial, st));
-    double *xin = x0, *xout = x1, *pin = nullptr, *pout = p1;
-    int32_t in_cnt = 0, nblk = 0;
+    double *xin = x0, *xout = x1;
+    const double *in_norm = nullptr;
     for (int32_t it = 0; it <= t; ++it) {  // t iterations + the Rayleigh product
+      int32_t nblk = 0;
       if (R->layout == ENT_DENSE)
-        HIP_TRY(ent::launch_power_gemv<T>(Rc, ldr, n, xin, pin, in_cnt, xout, pout, &nblk, st));
+        HIP_TRY(ent::launch_power_gemv<T>(Rc, ldr, n, xin, in_norm, xout, part3, &nblk, st));
       else
         HIP_TRY(ent::launch_power_spmv<T>(R->row_ptr, R->col_idx, (const T *)R->values, n, xin,
-                                          pin, in_cnt, xout, pout, &nblk, st));
+                                          in_norm, xout, part3, &nblk, st));
+      HIP_TRY(ent::launch_power_reduce(part3, nblk, norm, st));
       std::swap(xin, xout);
-      pin = pout;
-      pout = (pout == p1) ? p0 : p1;
-      in_cnt = nblk;
+      in_norm = norm;
     }
-    HIP_TRY(ent::launch_power_rq(scal, pin, nblk, trial, st));
+    HIP_TRY(ent::launch_power_rq(scal, norm, trial, st));
   }
   return ENT_OK;
 }
@@ -246,7 +261,7 @@ ent_status check_csr(const ent_matrix *R, void *scratch, hipStream_t st) {
 }
 
 int64_t power_blocks(const ent_matrix *R) {
-  return R->layout == ENT_DENSE ? (R->n + 15) / 16 : (R->n + 31) / 32;
+  return R->layout == ENT_DENSE ? ent::power_blocks_dense(R->n) : ent::power_blocks_csr(R->n);
 }
 
 // ---------------------------------------------------------------------------
@@ -291,7 +306,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     cv.add(&x0, n_pad);
     cv.add(&x1, n_pad);
     cv.add(&p0, 3 * (size_t)pblk);
-    cv.add(&p1, 3 * (size_t)pblk);
+    cv.add(&p1, 4);
   }
   const int64_t ldc = round_up(n, vec_elems);
   if (need_copy) cv.add(&Rc, (size_t)n * ldc);
@@ -438,6 +453,784 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   return ENT_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// BF16x3 dense estimate: A = a R split into bf16 hi/lo once, each step is a
+// split-K BF16 MFMA product plus an elementwise FP32 epilogue.
+// ---------------------------------------------------------------------------
+ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s, uint64_t seed,
+                      const Opts &op, ent_result *out, double *per_probe, double *moments) {
+  const ent_options &o = op.o;
+  hipStream_t st = op.st;
+  if (R->layout != ENT_DENSE) return fail(ENT_EUNSUPPORTED, "BF16x3 is implemented for dense R only");
+  const int64_t n = R->n;
+  const bool f64 = R->dtype == ENT_STORE_F64;
+  const int ve = f64 ? 2 : 4;
+  const bool copy = (R->ld % ve) != 0 || ((uintptr_t)R->values % 16) != 0;
+  const int64_t n_pad = round_up(n, 128);
+  const int bn = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
+  const int64_t ldv = round_up(s, bn);
+  const int64_t tiles = (n_pad / 128) * (ldv / bn);
+  int32_t splits = 1;
+  while (tiles * splits < 256 && splits < 16 && (n_pad / (2 * splits)) % 32 == 0) splits *= 2;
+  const int64_t kps = n_pad / splits;
+  const int32_t nblk = ent::bf16x3_epilogue_blocks(n_pad);
+  const int32_t nslot = m + 1;
+  const bool use_power = !(o.u_fixed > 0);
+  const int32_t pblk = (int32_t)power_blocks(R);
+  const int64_t ldc = round_up(n, ve);
+
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DeviceWorkspace *ws = workspace_for(dev);
+  std::lock_guard<std::mutex> lk(ws->mu);
+  double *scal = nullptr, *x0 = nullptr, *x1 = nullptr, *p0 = nullptr, *p1 = nullptr;
+  double *part = nullptr, *d = nullptr, *h = nullptr;
+  uint16_t *Ahi = nullptr, *Alo = nullptr, *Vhi = nullptr, *Vlo = nullptr;
+  float *G = nullptr, *VA = nullptr, *VB = nullptr, *party = nullptr;
+  char *Rc = nullptr;
+  Carve cv;
+  cv.add(&scal, kScalarDoubles);
+  if (use_power) {
+    cv.add(&x0, n_pad);
+    cv.add(&x1, n_pad);
+    cv.add(&p0, 3 * (size_t)pblk);
+    cv.add(&p1, 4);
+  }
+  if (copy) cv.add(&Rc, (size_t)n * ldc * (f64 ? 8 : 4));
+  cv.add(&Ahi, (size_t)n_pad * n_pad);
+  cv.add(&Alo, (size_t)n_pad * n_pad);
+  cv.add(&G, (size_t)ldv * n_pad);
+  cv.add(&VA, (size_t)ldv * n_pad);
+  cv.add(&VB, (size_t)ldv * n_pad);
+  cv.add(&Vhi, (size_t)ldv * n_pad);
+  cv.add(&Vlo, (size_t)ldv * n_pad);
+  cv.add(&party, (size_t)splits * ldv * n_pad);
+  cv.add(&part, (size_t)nslot * nblk * ldv);
+  cv.add(&d, (size_t)nslot * s);
+  cv.add(&h, (size_t)s);
+  ent_status rc = ensure_workspace(ws, cv.total());
+  if (rc != ENT_OK) return rc;
+  cv.assign(ws->ptr);
+
+  PhaseEvents pe;
+  pe.on = g_timing_on;
+  pe.st = st;
+  pe.mark();
+  HIP_TRY(hipMemsetAsync(scal, 0, sizeof(double) * 64, st));
+  const bool check_trace = !(o.flags & ENT_FLAG_SKIP_TRACE_CHECK);
+  const void *Rv = R->values;
+  int64_t ldr = R->ld;
+  if (copy) {
+    if (f64)
+      HIP_TRY((ent::launch_convert<double, double>((const double *)Rv, R->ld, (double *)Rc, ldc, n, n, st)));
+    else
+      HIP_TRY((ent::launch_convert<float, float>((const float *)Rv, R->ld, (float *)Rc, ldc, n, n, st)));
+    Rv = Rc;
+    ldr = ldc;
+  }
+  if (check_trace) {
+    if (f64)
+      HIP_TRY(ent::launch_trace_dense<double>((const double *)Rv, ldr, n, scal, st));
+    else
+      HIP_TRY(ent::launch_trace_dense<float>((const float *)Rv, ldr, n, scal, st));
+  }
+  HIP_TRY(ent::launch_probe_gen_t(G, Vhi, Vlo, n, n_pad, s, ldv, seed, o.probe_dist, st));
+  if (use_power) {
+    pe.power_begin = pe.mark();
+    if (f64)
+      rc = enqueue_power<double>(R, (const double *)Rv, ldr, o.power_iters, o.power_trials, seed, x0,
+                                 x1, p0, p1, scal, st);
+    else
+      rc = enqueue_power<float>(R, (const float *)Rv, ldr, o.power_iters, o.power_trials, seed, x0,
+                                x1, p0, p1, scal, st);
+    if (rc != ENT_OK) return rc;
+    pe.power_end = pe.mark();
+    pe.power_launches = o.power_trials * (o.power_iters + 1);
+  }
+  HIP_TRY(ent::launch_setup_interval(scal, method, m, o.u_factor, o.u_fixed, o.cutoff, st));
+  if (f64)
+    HIP_TRY(ent::launch_split_matrix<double>((const double *)Rv, ldr, n, n_pad, scal, Ahi, Alo, st));
+  else
+    HIP_TRY(ent::launch_split_matrix<float>((const float *)Rv, ldr, n, n_pad, scal, Ahi, Alo, st));
+
+  const int32_t nsteps = (method == ENT_CHEBYSHEV) ? m : m + 1;
+  const float *Vk = G, *Vkm1 = nullptr;
+  float *bufs[2] = {VA, VB};
+  pe.steps_begin = pe.mark();
+  for (int32_t k = 0; k < nsteps; ++k) {
+    float *Vout = bufs[k & 1];
+    double c1, c2, cw;
+    int32_t dot_y, slot, slot_gg = -1;
+    bool write = true;
+    if (method == ENT_CHEBYSHEV) {
+      if (k == 0) {
+        c1 = 1.0; c2 = -1.0; cw = 0.0;
+        slot_gg = 0;
+      } else {
+        c1 = 2.0; c2 = -2.0; cw = -1.0;
+      }
+      dot_y = 0;
+      slot = k + 1;
+    } else {
+      c1 = -1.0; c2 = 1.0; cw = 0.0;
+      dot_y = 1;
+      slot = k;
+      write = k < nsteps - 1;
+    }
+    ent::Bf16GemmArgs ga{};
+    ga.A_hi = Ahi; ga.A_lo = Alo; ga.V_hi = Vhi; ga.V_lo = Vlo; ga.part_y = party;
+    ga.n_pad = n_pad; ga.ldv = ldv; ga.k_per_split = kps; ga.splits = splits; ga.bn = bn;
+    const int e0 = pe.mark();
+    HIP_TRY(ent::launch_bf16x3_gemm(ga, st));
+    const int e1 = pe.mark();
+    ent::Bf16EpiArgs ea{};
+    ea.part_y = party; ea.splits = splits; ea.Vk = Vk; ea.Vkm1 = Vkm1;
+    ea.Vkp1 = write ? Vout : nullptr; ea.V_hi = Vhi; ea.V_lo = Vlo; ea.G = G; ea.scal = scal;
+    ea.c1 = c1; ea.c2 = c2; ea.cw = cw; ea.dot_y = dot_y; ea.slot = slot; ea.slot_gg = slot_gg;
+    ea.part = part; ea.nblk = nblk; ea.n_pad = n_pad; ea.ldv = ldv;
+    HIP_TRY(ent::launch_bf16x3_epilogue(ea, st));
+    const int e2 = pe.mark();
+    if (pe.on) {
+      pe.main_spans.push_back({e0, e1});
+      pe.epi_spans.push_back({e1, e2});
+    }
+    if (method == ENT_CHEBYSHEV) Vkm1 = Vk;
+    Vk = Vout;
+  }
+  pe.steps_end = pe.mark();
+  HIP_TRY(ent::launch_reduce_moments(part, nslot, nblk, ldv, s, d, st));
+  HIP_TRY(ent::launch_final(d, scal, method, m, s, h, st));
+  double hs[16];
+  HIP_TRY(hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, st));
+  if (per_probe) HIP_TRY(hipMemcpyAsync(per_probe, h, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+  if (moments)
+    HIP_TRY(hipMemcpyAsync(moments, d, sizeof(double) * nslot * s, hipMemcpyDeviceToHost, st));
+  pe.mark();
+  HIP_TRY(hipStreamSynchronize(st));
+  pe.finish();
+  if (check_trace) {
+    double tol = o.trace_tol > 0 ? o.trace_tol : (f64 ? 1e-10 : 1e-4);
+    if (!(std::fabs(hs[ent::S_TRACE] - 1.0) <= tol))
+      return fail(ENT_ENOTDENSITY, "trace of R is %.17g, not 1 within %.3g", hs[ent::S_TRACE], tol);
+  }
+  if (hs[ent::S_FLAG] != 0.0)
+    return fail(ENT_ENUMERIC, "numeric failure: p1~ = %.17g, u = %.17g, estimate = %.17g",
+                hs[ent::S_P1], hs[ent::S_U], hs[ent::S_ENT]);
+  out->entropy = hs[ent::S_ENT];
+  out->std_err = hs[ent::S_SE];
+  out->p1_est = use_power ? hs[ent::S_P1] : 0.0;
+  out->u = hs[ent::S_U];
+  out->lo = hs[ent::S_LO];
+  out->degree = m;
+  out->probes = s;
+  out->method = method;
+  out->precision = ENT_BF16X3;
+  return ENT_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Random projection (Algorithm 3): R~ = R Pi on the MFMA product kernels,
+// Gram matrix and its Jacobi eigenvalues in FP64, top-k singular values.
+// ---------------------------------------------------------------------------
+ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_result *out,
+                        double *sigma_out) {
+  const ent_options &o = op.o;
+  hipStream_t st = op.st;
+  const int32_t s = o.sketch_width, k = o.rank_k;
+  if (R->layout != ENT_DENSE) return fail(ENT_EUNSUPPORTED, "random projection needs dense R");
+  if (s < 1 || s > 256) return fail(ENT_EINVAL, "sketch_width = %d out of range [1, 256]", s);
+  if (k < 1 || k > s) return fail(ENT_EINVAL, "rank_k = %d out of range [1, sketch_width]", k);
+  const int64_t n = R->n;
+  const bool f64 = R->dtype == ENT_STORE_F64;
+  const int prec = o.precision;
+  const int32_t N = (s + 1) / 2 * 2;
+  const int32_t nsplit = 64;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DeviceWorkspace *ws = workspace_for(dev);
+  std::lock_guard<std::mutex> lk(ws->mu);
+  double *scal = nullptr, *gp = nullptr, *G = nullptr, *work = nullptr, *eig = nullptr, *sig = nullptr;
+  Carve cv;
+  cv.add(&scal, kScalarDoubles);
+  cv.add(&gp, (size_t)nsplit * s * s);
+  cv.add(&G, (size_t)s * s);
+  cv.add(&work, (size_t)N * N);
+  cv.add(&eig, (size_t)N);
+  cv.add(&sig, (size_t)k);
+  const bool check_trace = !(o.flags & ENT_FLAG_SKIP_TRACE_CHECK);
+  PhaseEvents pe;
+  pe.on = g_timing_on;
+  pe.st = st;
+  if (prec == ENT_BF16X3) {
+    const int64_t n_pad = round_up(n, 128);
+    const int bn = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
+    const int64_t ldv = round_up(s, bn);
+    const int64_t tiles = (n_pad / 128) * (ldv / bn);
+    int32_t splits = 1;
+    while (tiles * splits < 256 && splits < 16 && (n_pad / (2 * splits)) % 32 == 0) splits *= 2;
+    uint16_t *Ahi = nullptr, *Alo = nullptr, *Phi = nullptr, *Plo = nullptr;
+    float *P = nullptr, *X = nullptr, *party = nullptr;
+    cv.add(&Ahi, (size_t)n_pad * n_pad);
+    cv.add(&Alo, (size_t)n_pad * n_pad);
+    cv.add(&P, (size_t)ldv * n_pad);
+    cv.add(&X, (size_t)ldv * n_pad);
+    cv.add(&Phi, (size_t)ldv * n_pad);
+    cv.add(&Plo, (size_t)ldv * n_pad);
+    cv.add(&party, (size_t)splits * ldv * n_pad);
+    ent_status rc = ensure_workspace(ws, cv.total());
+    if (rc != ENT_OK) return rc;
+    cv.assign(ws->ptr);
+    pe.mark();
+    HIP_TRY(ent::launch_fill(scal, 64, 0.0, st));
+    HIP_TRY(ent::launch_fill(scal + ent::S_A, 1, 1.0, st));
+    if (check_trace) {
+      if (f64)
+        HIP_TRY(ent::launch_trace_dense<double>((const double *)R->values, R->ld, n, scal, st));
+      else
+        HIP_TRY(ent::launch_trace_dense<float>((const float *)R->values, R->ld, n, scal, st));
+    }
+    HIP_TRY(ent::launch_probe_gen_t(P, Phi, Plo, n, n_pad, s, ldv, seed, ENT_GAUSSIAN, st, 2u,
+                                    1.0 / std::sqrt((double)s)));
+    if (f64)
+      HIP_TRY(ent::launch_split_matrix<double>((const double *)R->values, R->ld, n, n_pad, scal, Ahi, Alo, st));
+    else
+      HIP_TRY(ent::launch_split_matrix<float>((const float *)R->values, R->ld, n, n_pad, scal, Ahi, Alo, st));
+    pe.steps_begin = pe.mark();
+    ent::Bf16GemmArgs ga{};
+    ga.A_hi = Ahi; ga.A_lo = Alo; ga.V_hi = Phi; ga.V_lo = Plo; ga.part_y = party;
+    ga.n_pad = n_pad; ga.ldv = ldv; ga.k_per_split = n_pad / splits; ga.splits = splits; ga.bn = bn;
+    HIP_TRY(ent::launch_bf16x3_gemm(ga, st));
+    const int e1 = pe.mark();
+    ent::Bf16EpiArgs ea{};
+    ea.part_y = party; ea.splits = splits; ea.Vk = P; ea.Vkp1 = X; ea.V_hi = Phi; ea.V_lo = Plo;
+    ea.G = P; ea.scal = scal; ea.c1 = 1.0; ea.c2 = 0.0; ea.cw = 0.0; ea.slot = -1; ea.slot_gg = -1;
+    ea.nblk = ent::bf16x3_epilogue_blocks(n_pad); ea.n_pad = n_pad; ea.ldv = ldv;
+    HIP_TRY(ent::launch_bf16x3_epilogue(ea, st));
+    const int e2 = pe.mark();
+    if (pe.on) {
+      pe.main_spans.push_back({pe.steps_begin, e1});
+      pe.epi_spans.push_back({e1, e2});
+    }
+    pe.steps_end = e2;
+    HIP_TRY(ent::launch_gram<float>(X, 1, n_pad, n, s, gp, nsplit, G, st));
+  } else {
+    const bool d64 = prec == ENT_F64;
+    const size_t esz = d64 ? 8 : 4;
+    const int ve = d64 ? 2 : 4;
+    const bool stored_T = f64 == d64;
+    const bool copy = !stored_T || (R->ld % ve) != 0 || ((uintptr_t)R->values % 16) != 0;
+    const int64_t n_pad = round_up(n, 64);
+    const int bn = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
+    const int64_t ldv = round_up(s, bn);
+    const int64_t ldc = round_up(n, ve);
+    char *Rc = nullptr, *P = nullptr, *X = nullptr;
+    if (copy) cv.add(&Rc, (size_t)n * ldc * esz);
+    cv.add(&P, (size_t)n_pad * ldv * esz);
+    cv.add(&X, (size_t)n_pad * ldv * esz);
+    ent_status rc = ensure_workspace(ws, cv.total());
+    if (rc != ENT_OK) return rc;
+    cv.assign(ws->ptr);
+    pe.mark();
+    HIP_TRY(ent::launch_fill(scal, 64, 0.0, st));
+    HIP_TRY(ent::launch_fill(scal + ent::S_A, 1, 1.0, st));
+    if (check_trace) {
+      if (f64)
+        HIP_TRY(ent::launch_trace_dense<double>((const double *)R->values, R->ld, n, scal, st));
+      else
+        HIP_TRY(ent::launch_trace_dense<float>((const float *)R->values, R->ld, n, scal, st));
+    }
+    const void *Rt = R->values;
+    int64_t ldr = R->ld;
+    if (copy) {
+      if (f64 && d64) HIP_TRY((ent::launch_convert<double, double>((const double *)Rt, R->ld, (double *)Rc, ldc, n, n, st)));
+      if (f64 && !d64) HIP_TRY((ent::launch_convert<double, float>((const double *)Rt, R->ld, (float *)Rc, ldc, n, n, st)));
+      if (!f64 && d64) HIP_TRY((ent::launch_convert<float, double>((const float *)Rt, R->ld, (double *)Rc, ldc, n, n, st)));
+      if (!f64 && !d64) HIP_TRY((ent::launch_convert<float, float>((const float *)Rt, R->ld, (float *)Rc, ldc, n, n, st)));
+      Rt = Rc;
+      ldr = ldc;
+    }
+    if (d64)
+      HIP_TRY(ent::launch_sketch_gen<double>((double *)P, n, n_pad, s, ldv, seed, st));
+    else
+      HIP_TRY(ent::launch_sketch_gen<float>((float *)P, n, n_pad, s, ldv, seed, st));
+    ent::DenseStepArgs a{};
+    a.R = Rt; a.ldr = ldr; a.n = n; a.ldv = ldv; a.Vk = P; a.Vkm1 = nullptr; a.Vkp1 = X; a.G = nullptr;
+    a.scal = scal; a.c1 = 1.0; a.c2 = 0.0; a.cw = 0.0; a.dot_y = 0; a.slot = -1; a.slot_gg = -1;
+    a.part = nullptr; a.ntile = (int32_t)(n_pad / 64); a.bn = bn;
+    pe.steps_begin = pe.mark();
+    if (d64)
+      HIP_TRY(ent::launch_dense_step<double>(a, st));
+    else
+      HIP_TRY(ent::launch_dense_step<float>(a, st));
+    pe.steps_end = pe.mark();
+    if (d64)
+      HIP_TRY(ent::launch_gram<double>((const double *)X, ldv, 1, n, s, gp, nsplit, G, st));
+    else
+      HIP_TRY(ent::launch_gram<float>((const float *)X, ldv, 1, n, s, gp, nsplit, G, st));
+  }
+  HIP_TRY(ent::launch_rp_spectrum(G, s, k, work, eig, sig, scal, st));
+  double hs[16];
+  HIP_TRY(hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, st));
+  if (sigma_out) HIP_TRY(hipMemcpyAsync(sigma_out, sig, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+  pe.mark();
+  HIP_TRY(hipStreamSynchronize(st));
+  pe.finish();
+  if (check_trace) {
+    const double tol = o.trace_tol > 0 ? o.trace_tol : (f64 ? 1e-10 : 1e-4);
+    if (!(std::fabs(hs[ent::S_TRACE] - 1.0) <= tol))
+      return fail(ENT_ENOTDENSITY, "trace of R is %.17g, not 1 within %.3g", hs[ent::S_TRACE], tol);
+  }
+  if (hs[ent::S_FLAG] != 0.0) return fail(ENT_ENUMERIC, "non-finite random-projection estimate");
+  out->entropy = hs[ent::S_ENT];
+  out->std_err = 0.0;
+  out->p1_est = 0.0;
+  out->u = 0.0;
+  out->lo = 0.0;
+  out->degree = k;
+  out->probes = s;
+  out->method = ENT_RANDPROJ;
+  out->precision = prec;
+  return ENT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of dense matrices: one launch per phase over every matrix (grouped
+// kernels driven by device descriptor and tile tables), captured once into a
+// hipGraph.  The step tile shape (64- or 128-row tiles) is chosen by timing
+// both on the batch itself.
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;  // autotune cache: key -> rows-per-wave factor
+bool g_tune_loaded = false;
+
+std::string tune_cache_path() {
+  const char *p = std::getenv("ENT_AUTOTUNE_CACHE");
+  return p ? std::string(p) : std::string();
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE *f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    char key[400];
+    int v = 0;
+    if (std::sscanf(line, " \"%399[^\"]\" : %d", key, &v) == 2) g_tune[key] = v;
+  }
+  std::fclose(f);
+}
+
+void tune_store_locked() {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE *f = std::fopen(path.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (auto &kv : g_tune)
+    std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < g_tune.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+}
+
+}  // namespace
+
+struct ent_graph_s {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  int32_t count = 0, method = 0, m = 0, s = 0, nslot = 0;
+  ent_options o{};
+  bool src_f64 = false, comp_f64 = false;
+  int64_t ldv = 0, sb = 0, max_n = 0, max_npad = 0, max_elems = 0;
+  int32_t wr = 1, ntiles1 = 0, ntiles2 = 0, nptiles = 0;
+  std::vector<ent::BatchMat> mats;
+  std::vector<int2> tiles1, tiles2, ptiles;
+  ent::BatchMat *mats_d = nullptr;
+  int2 *tiles1_d = nullptr, *tiles2_d = nullptr, *ptiles_d = nullptr;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  char *Rc = nullptr, *G = nullptr, *VA = nullptr, *VB = nullptr;
+  double *x0 = nullptr, *x1 = nullptr, *p0 = nullptr, *norm = nullptr;
+  double *part = nullptr, *d = nullptr, *h = nullptr, *scal = nullptr;
+  double *host_scal = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool launched = false;
+};
+
+namespace {
+
+template <typename T>
+ent_status enqueue_batch(ent_graph_s *g, hipStream_t st, PhaseEvents *pe) {
+  const ent_options &o = g->o;
+  const int32_t count = g->count;
+  HIP_TRY(ent::launch_fill(g->scal, (int64_t)count * g->sb, 0.0, st));
+  if (g->src_f64)
+    HIP_TRY((ent::launch_batch_convert<double, T>(g->mats_d, count, g->max_elems, st)));
+  else
+    HIP_TRY((ent::launch_batch_convert<float, T>(g->mats_d, count, g->max_elems, st)));
+  if (!(o.flags & ENT_FLAG_SKIP_TRACE_CHECK)) HIP_TRY(ent::launch_batch_trace<T>(g->mats_d, count, st));
+  HIP_TRY(ent::launch_batch_probes<T>(g->mats_d, count, g->max_npad, (T *)g->G, g->s, g->ldv,
+                                      o.probe_dist, st));
+  if (!(o.u_fixed > 0)) {
+    if (pe) pe->power_begin = pe->mark();
+    for (int32_t trial = 0; trial < o.power_trials; ++trial) {
+      HIP_TRY(ent::launch_batch_power_start(g->mats_d, count, g->max_n, g->x0, trial, st));
+      double *xin = g->x0, *xout = g->x1;
+      const double *in_norm = nullptr;
+      for (int32_t it = 0; it <= o.power_iters; ++it) {
+        HIP_TRY(ent::launch_batch_power_gemv<T>(g->mats_d, g->ptiles_d, g->nptiles, xin, in_norm,
+                                                xout, g->p0, st));
+        HIP_TRY(ent::launch_batch_power_reduce(g->mats_d, count, g->p0, g->norm, st));
+        std::swap(xin, xout);
+        in_norm = g->norm;
+      }
+      HIP_TRY(ent::launch_batch_power_rq(g->mats_d, count, g->norm, trial, st));
+    }
+    if (pe) {
+      pe->power_end = pe->mark();
+      pe->power_launches = o.power_trials * (o.power_iters + 1);
+    }
+  }
+  HIP_TRY(ent::launch_batch_setup(g->mats_d, count, g->method, g->m, o.u_factor, o.u_fixed,
+                                  o.cutoff, st));
+  const int32_t nsteps = (g->method == ENT_CHEBYSHEV) ? g->m : g->m + 1;
+  const T *Vk = (const T *)g->G, *Vkm1 = nullptr;
+  T *bufs[2] = {(T *)g->VA, (T *)g->VB};
+  if (pe) pe->steps_begin = pe->mark();
+  for (int32_t k = 0; k < nsteps; ++k) {
+    T *Vout = bufs[k & 1];
+    ent::BatchStepArgs ba{};
+    ent::DenseStepArgs &a = ba.base;
+    a.ldv = g->ldv;
+    a.Vk = Vk;
+    a.G = g->G;
+    a.part = g->part;
+    a.bn = 64;
+    if (g->method == ENT_CHEBYSHEV) {
+      a.dot_y = 0;
+      a.slot = k + 1;
+      if (k == 0) {
+        a.c1 = 1.0; a.c2 = -1.0; a.cw = 0.0;
+        a.slot_gg = 0;
+      } else {
+        a.c1 = 2.0; a.c2 = -2.0; a.cw = -1.0;
+        a.slot_gg = -1;
+      }
+      a.Vkm1 = Vkm1;
+      a.Vkp1 = Vout;
+    } else {
+      a.c1 = -1.0; a.c2 = 1.0; a.cw = 0.0;
+      a.dot_y = 1;
+      a.slot = k;
+      a.slot_gg = -1;
+      a.Vkp1 = (k < nsteps - 1) ? Vout : nullptr;
+    }
+    ba.mats = g->mats_d;
+    ba.tiles = g->wr == 2 ? g->tiles2_d : g->tiles1_d;
+    HIP_TRY(ent::launch_batch_dense_step<T>(ba, g->wr == 2 ? g->ntiles2 : g->ntiles1, g->wr, st));
+    if (g->method == ENT_CHEBYSHEV) Vkm1 = Vk;
+    Vk = Vout;
+    if (pe) {
+      const int e = pe->mark();
+      if (k == nsteps - 1) pe->steps_end = e;
+    }
+  }
+  HIP_TRY(ent::launch_batch_reduce(g->mats_d, count, g->part, g->nslot, g->ldv, g->s, g->d, st));
+  HIP_TRY(ent::launch_batch_final(g->mats_d, count, g->d, g->method, g->m, g->s, g->h, st));
+  return ENT_OK;
+}
+
+ent_status batch_enqueue(ent_graph_s *g, hipStream_t st, PhaseEvents *pe) {
+  return g->comp_f64 ? enqueue_batch<double>(g, st, pe) : enqueue_batch<float>(g, st, pe);
+}
+
+// Upload descriptors with the row-tile count of the chosen tile shape.
+ent_status batch_upload(ent_graph_s *g, int wr) {
+  for (auto &M : g->mats) M.ntile = (int32_t)(M.n_pad / (64 * wr));
+  HIP_TRY(hipMemcpyAsync(g->mats_d, g->mats.data(), sizeof(ent::BatchMat) * g->mats.size(),
+                         hipMemcpyHostToDevice, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  g->wr = wr;
+  return ENT_OK;
+}
+
+// Time one product step of each tile shape on the batch's own buffers.
+ent_status batch_autotune(ent_graph_s *g) {
+  ent_status rc = batch_upload(g, 1);
+  if (rc != ENT_OK) return rc;
+  rc = batch_enqueue(g, g->stream, nullptr);  // fills every buffer with real data
+  if (rc != ENT_OK) return rc;
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  float best = 1e30f;
+  int best_wr = 1;
+  for (int wr = 1; wr <= 2; ++wr) {
+    rc = batch_upload(g, wr);
+    if (rc != ENT_OK) return rc;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    ent::BatchStepArgs ba{};
+    ent::DenseStepArgs &a = ba.base;
+    a.ldv = g->ldv;
+    a.Vk = g->VA;
+    a.Vkm1 = g->G;
+    a.Vkp1 = g->VB;
+    a.G = g->G;
+    a.part = g->part;
+    a.bn = 64;
+    a.c1 = 2.0; a.c2 = -2.0; a.cw = -1.0;
+    a.slot = 1;
+    a.slot_gg = -1;
+    ba.mats = g->mats_d;
+    ba.tiles = wr == 2 ? g->tiles2_d : g->tiles1_d;
+    const int32_t nt = wr == 2 ? g->ntiles2 : g->ntiles1;
+    hipError_t e = hipSuccess;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)  // warm
+      e = g->comp_f64 ? ent::launch_batch_dense_step<double>(ba, nt, wr, g->stream)
+                      : ent::launch_batch_dense_step<float>(ba, nt, wr, g->stream);
+    (void)hipEventRecord(e0, g->stream);
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+      e = g->comp_f64 ? ent::launch_batch_dense_step<double>(ba, nt, wr, g->stream)
+                      : ent::launch_batch_dense_step<float>(ba, nt, wr, g->stream);
+    (void)hipEventRecord(e1, g->stream);
+    HIP_TRY(e);
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ms < best) {
+      best = ms;
+      best_wr = wr;
+    }
+  }
+  return batch_upload(g, best_wr);
+}
+
+std::string batch_tune_key(const ent_graph_s *g) {
+  int64_t sum2 = 0;
+  for (auto &M : g->mats) sum2 += M.n * M.n;
+  int bucket = 0;
+  while ((int64_t(1) << (bucket + 1)) <= sum2) ++bucket;
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "gfx950|%s|batch|count=%d|log2sum_n2=%d|s=%d|maxn=%lld",
+                g->comp_f64 ? "f64" : "f32", g->count, bucket, g->s, (long long)g->max_n);
+  return buf;
+}
+
+void batch_free(ent_graph_s *g) {
+  if (!g) return;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->ws) (void)hipFree(g->ws);
+  if (g->host_scal) (void)hipHostFree(g->host_scal);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+  delete g;
+}
+
+ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int32_t m, int32_t s,
+                        uint64_t seed, const ent_options *opt, bool capture, ent_graph_s **out) {
+  if (!Rs) return fail(ENT_EINVAL, "Rs is NULL");
+  if (count < 1) return fail(ENT_EINVAL, "count = %d < 1", count);
+  if (method != ENT_TAYLOR && method != ENT_CHEBYSHEV)
+    return fail(ENT_EINVAL, "batches support the Taylor and Chebyshev methods");
+  if (m < 1 || m > 4000) return fail(ENT_EINVAL, "degree = %d out of range [1, 4000]", m);
+  if (s < 1) return fail(ENT_EINVAL, "probes = %d < 1", s);
+  Opts op = resolve_options(opt);
+  ent_status rc = validate_options(op.o);
+  if (rc != ENT_OK) return rc;
+  if (method == ENT_TAYLOR && op.o.cutoff > 0)
+    return fail(ENT_EINVAL, "cutoff applies to the Chebyshev method only");
+  if (op.o.precision == ENT_BF16X3)
+    return fail(ENT_EUNSUPPORTED, "batches run in F32 or F64 in this build");
+  for (int32_t b = 0; b < count; ++b) {
+    rc = validate_matrix(&Rs[b]);
+    if (rc != ENT_OK) return fail(rc, "matrix %d: %s", b, g_last_error.c_str());
+    if (Rs[b].layout != ENT_DENSE) return fail(ENT_EUNSUPPORTED, "matrix %d: batches are dense only", b);
+    if (Rs[b].dtype != Rs[0].dtype) return fail(ENT_EINVAL, "matrix %d: mixed storage types", b);
+  }
+  auto *g = new ent_graph_s();
+  g->count = count;
+  g->method = method;
+  g->m = m;
+  g->s = s;
+  g->nslot = m + 1;
+  g->o = op.o;
+  g->src_f64 = Rs[0].dtype == ENT_STORE_F64;
+  g->comp_f64 = op.o.precision == ENT_F64;
+  const size_t esz = g->comp_f64 ? 8 : 4;
+  g->ldv = round_up(s, 64);
+  g->sb = round_up(ent::S_ALPHA + m + 1 + 8, 32);
+  auto fail_free = [&](ent_status st) {
+    batch_free(g);
+    return st;
+  };
+  if (hipGetDevice(&g->dev) != hipSuccess) return fail_free(fail(ENT_EDEVICE, "hipGetDevice failed"));
+  if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess)
+    return fail_free(fail(ENT_EDEVICE, "hipStreamCreate failed"));
+  // layout of every per-matrix region
+  int64_t roff = 0, voff = 0, poff = 0, xoff = 0, pboff = 0;
+  g->mats.resize(count);
+  for (int32_t b = 0; b < count; ++b) {
+    ent::BatchMat &M = g->mats[b];
+    const int64_t n = Rs[b].n;
+    M.src = Rs[b].values;
+    M.ldsrc = Rs[b].ld;
+    M.ldr = round_up(n, 8);
+    M.n = n;
+    M.n_pad = round_up(n, 128);
+    M.ntile = (int32_t)(M.n_pad / 64);
+    M.pblk = ent::power_blocks_dense(n);
+    M.seed = seed + (uint64_t)b;
+    M.R = (const void *)(intptr_t)roff;  // offsets for now; rebased below
+    M.voff = voff;
+    M.poff = poff;
+    M.xoff = xoff;
+    M.pboff = pboff;
+    M.doff = (int64_t)b * g->nslot * s;
+    M.hoff = (int64_t)b * s;
+    roff += n * M.ldr;
+    voff += M.n_pad * g->ldv;
+    poff += (int64_t)g->nslot * M.ntile * g->ldv;
+    xoff += M.n_pad;
+    pboff += 3 * (int64_t)M.pblk;
+    g->max_n = std::max(g->max_n, n);
+    g->max_npad = std::max(g->max_npad, M.n_pad);
+    g->max_elems = std::max(g->max_elems, n * M.ldr);
+  }
+  // tile tables, largest matrices first (their tiles are the longest)
+  std::vector<int32_t> order(count);
+  for (int32_t b = 0; b < count; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return g->mats[a].n > g->mats[b].n; });
+  for (int32_t b : order) {
+    const ent::BatchMat &M = g->mats[b];
+    for (int32_t t = 0; t < (int32_t)(M.n_pad / 64); ++t) g->tiles1.push_back(make_int2(b, t));
+    for (int32_t t = 0; t < (int32_t)(M.n_pad / 128); ++t) g->tiles2.push_back(make_int2(b, t));
+    for (int32_t t = 0; t < M.pblk; ++t) g->ptiles.push_back(make_int2(b, t));
+  }
+  g->ntiles1 = (int32_t)g->tiles1.size();
+  g->ntiles2 = (int32_t)g->tiles2.size();
+  g->nptiles = (int32_t)g->ptiles.size();
+  Carve cv;
+  cv.add(&g->mats_d, (size_t)count);
+  cv.add(&g->tiles1_d, g->tiles1.size());
+  cv.add(&g->tiles2_d, g->tiles2.size());
+  cv.add(&g->ptiles_d, g->ptiles.size());
+  cv.add(&g->scal, (size_t)count * g->sb);
+  cv.add(&g->Rc, (size_t)roff * esz);
+  cv.add(&g->G, (size_t)voff * esz);
+  cv.add(&g->VA, (size_t)voff * esz);
+  cv.add(&g->VB, (size_t)voff * esz);
+  cv.add(&g->x0, (size_t)xoff);
+  cv.add(&g->x1, (size_t)xoff);
+  cv.add(&g->p0, (size_t)pboff);
+  cv.add(&g->norm, (size_t)4 * count);
+  cv.add(&g->part, (size_t)poff);
+  cv.add(&g->d, (size_t)count * g->nslot * s);
+  cv.add(&g->h, (size_t)count * s);
+  g->ws_bytes = cv.total();
+  if (g_ws_limit && g->ws_bytes > g_ws_limit)
+    return fail_free(fail(ENT_ENOMEM, "batch workspace of %zu bytes exceeds the limit", g->ws_bytes));
+  if (hipMalloc(&g->ws, g->ws_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    g->ws = nullptr;
+    return fail_free(fail(ENT_ENOMEM, "hipMalloc(%zu) for the batch failed", g->ws_bytes));
+  }
+  cv.assign(g->ws);
+  if (hipHostMalloc((void **)&g->host_scal, sizeof(double) * count * g->sb, hipHostMallocDefault) !=
+      hipSuccess)
+    return fail_free(fail(ENT_ENOMEM, "pinned host buffer allocation failed"));
+  for (int32_t b = 0; b < count; ++b) {
+    ent::BatchMat &M = g->mats[b];
+    M.R = g->Rc + (intptr_t)M.R * esz;
+    M.scal = g->scal + (int64_t)b * g->sb;
+  }
+  if (hipMemcpy(g->tiles1_d, g->tiles1.data(), sizeof(int2) * g->tiles1.size(), hipMemcpyHostToDevice) ||
+      hipMemcpy(g->tiles2_d, g->tiles2.data(), sizeof(int2) * g->tiles2.size(), hipMemcpyHostToDevice) ||
+      hipMemcpy(g->ptiles_d, g->ptiles.data(), sizeof(int2) * g->ptiles.size(), hipMemcpyHostToDevice))
+    return fail_free(fail(ENT_EDEVICE, "descriptor upload failed"));
+  // tile shape: cached choice, else timed on this batch when asked, else 64-row tiles
+  const std::string key = batch_tune_key(g);
+  int wr = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) wr = it->second;
+  }
+  if (wr != 1 && wr != 2) {
+    if (op.o.flags & ENT_FLAG_AUTOTUNE) {
+      rc = batch_autotune(g);
+      if (rc != ENT_OK) return fail_free(rc);
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key] = g->wr;
+      tune_store_locked();
+      wr = g->wr;
+    } else {
+      wr = 1;
+    }
+  }
+  rc = batch_upload(g, wr);
+  if (rc != ENT_OK) return fail_free(rc);
+  if (capture) {
+    if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail_free(fail(ENT_EDEVICE, "hipStreamBeginCapture failed"));
+    rc = batch_enqueue(g, g->stream, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(g->stream, &graph);
+    if (rc != ENT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail_free(rc);
+    }
+    if (ce != hipSuccess) return fail_free(fail(ENT_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ce)));
+    g->graph = graph;
+    if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+      return fail_free(fail(ENT_EDEVICE, "hipGraphInstantiate failed"));
+  }
+  *out = g;
+  return ENT_OK;
+}
+
+// Copy the scalar blocks back and fill the results (after the work ran).
+ent_status batch_collect(ent_graph_s *g, ent_result *outs) {
+  HIP_TRY(hipMemcpyAsync(g->host_scal, g->scal, sizeof(double) * g->count * g->sb,
+                         hipMemcpyDeviceToHost, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  g->launched = true;
+  const bool check = !(g->o.flags & ENT_FLAG_SKIP_TRACE_CHECK);
+  const double tol = g->o.trace_tol > 0 ? g->o.trace_tol : ((g->src_f64 && g->comp_f64) ? 1e-10 : 1e-4);
+  for (int32_t b = 0; b < g->count; ++b) {
+    const double *hs = g->host_scal + (int64_t)b * g->sb;
+    if (check && !(std::fabs(hs[ent::S_TRACE] - 1.0) <= tol))
+      return fail(ENT_ENOTDENSITY, "matrix %d: trace %.17g is not 1 within %.3g", b, hs[ent::S_TRACE], tol);
+    if (hs[ent::S_FLAG] != 0.0)
+      return fail(ENT_ENUMERIC, "matrix %d: numeric failure (p1~ = %.17g)", b, hs[ent::S_P1]);
+  }
+  for (int32_t b = 0; b < g->count; ++b) {
+    const double *hs = g->host_scal + (int64_t)b * g->sb;
+    ent_result &r = outs[b];
+    r.entropy = hs[ent::S_ENT];
+    r.std_err = hs[ent::S_SE];
+    r.p1_est = (g->o.u_fixed > 0) ? 0.0 : hs[ent::S_P1];
+    r.u = hs[ent::S_U];
+    r.lo = hs[ent::S_LO];
+    r.degree = g->m;
+    r.probes = g->s;
+    r.method = g->method;
+    r.precision = g->o.precision;
+  }
+  return ENT_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -465,7 +1258,12 @@ ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int3
   Opts op = resolve_options(opt);
   rc = validate_options(op.o);
   if (rc != ENT_OK) return rc;
-  if (method == ENT_RANDPROJ) return fail(ENT_EUNSUPPORTED, "random projection is not built yet");
+  if (method == ENT_RANDPROJ) {
+    ent_result tmp{};
+    rc = run_randproj(R, seed, op, &tmp, per_probe);
+    if (rc == ENT_OK) *out = tmp;
+    return rc;
+  }
   if (method != ENT_TAYLOR && method != ENT_CHEBYSHEV)
     return fail(ENT_EINVAL, "unknown method %d", method);
   if (degree < 1) return fail(ENT_EINVAL, "degree = %d < 1", degree);
@@ -477,7 +1275,7 @@ ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int3
   switch (op.o.precision) {
     case ENT_F64: rc = run_poly<double>(R, method, degree, probes, seed, op, &tmp, per_probe, moments); break;
     case ENT_F32: rc = run_poly<float>(R, method, degree, probes, seed, op, &tmp, per_probe, moments); break;
-    default: return fail(ENT_EUNSUPPORTED, "precision %d is not built yet", op.o.precision);
+    default: rc = run_bf16x3(R, method, degree, probes, seed, op, &tmp, per_probe, moments); break;
   }
   if (rc == ENT_OK) *out = tmp;
   return rc;
@@ -513,7 +1311,7 @@ ent_status ent_power_method(const ent_matrix *R, int32_t t, int32_t q, uint64_t 
   cv.add(&x0, n_pad);
   cv.add(&x1, n_pad);
   cv.add(&p0, 3 * (size_t)pblk);
-  cv.add(&pp1, 3 * (size_t)pblk);
+  cv.add(&pp1, 4);
   if (copy) cv.add((char **)&Rc, (size_t)n * ldc * (f64 ? 8 : 4));
   rc = ensure_workspace(ws, cv.total());
   if (rc != ENT_OK) return rc;
@@ -587,6 +1385,75 @@ int32_t ent_power_trials_for(double delta) {
 int32_t ent_power_iters_for(int64_t n) {
   if (n < 1) return -1;
   return (int32_t)std::ceil(std::log(std::sqrt(4.0 * (double)n)));
+}
+
+ent_status ent_graph_create(const ent_matrix *Rs, int32_t count, int32_t method, int32_t degree,
+                            int32_t probes, uint64_t seed, const ent_options *opt, ent_graph *graph) {
+  g_last_error.clear();
+  if (!graph) return fail(ENT_EINVAL, "graph is NULL");
+  ent_graph_s *g = nullptr;
+  ent_status rc = batch_create(Rs, count, method, degree, probes, seed, opt, true, &g);
+  if (rc != ENT_OK) return rc;
+  *graph = g;
+  return ENT_OK;
+}
+
+ent_status ent_graph_launch(ent_graph graph, ent_result *outs) {
+  g_last_error.clear();
+  if (!graph || !outs) return fail(ENT_EINVAL, "graph or outs is NULL");
+  HIP_TRY(hipGraphLaunch(graph->exec, graph->stream));
+  return batch_collect(graph, outs);
+}
+
+ent_status ent_graph_per_probe(ent_graph graph, double *per_probe) {
+  g_last_error.clear();
+  if (!graph || !per_probe) return fail(ENT_EINVAL, "graph or per_probe is NULL");
+  if (!graph->launched) return fail(ENT_EINVAL, "the graph has not been launched");
+  HIP_TRY(hipMemcpyAsync(per_probe, graph->h, sizeof(double) * graph->count * graph->s,
+                         hipMemcpyDeviceToHost, graph->stream));
+  HIP_TRY(hipStreamSynchronize(graph->stream));
+  return ENT_OK;
+}
+
+ent_status ent_graph_time_eager(ent_graph graph, ent_result *outs, ent_timing *timing) {
+  g_last_error.clear();
+  if (!graph || !outs || !timing) return fail(ENT_EINVAL, "NULL argument");
+  PhaseEvents pe;
+  pe.on = true;
+  pe.st = graph->stream;
+  pe.mark();
+  ent_status rc = batch_enqueue(graph, graph->stream, &pe);
+  if (rc != ENT_OK) return rc;
+  pe.mark();
+  rc = batch_collect(graph, outs);
+  if (rc != ENT_OK) return rc;
+  pe.finish();
+  *timing = g_last_timing;
+  return ENT_OK;
+}
+
+int32_t ent_graph_tile_rows(ent_graph graph) { return graph ? 64 * graph->wr : -1; }
+
+size_t ent_graph_workspace_bytes(ent_graph graph) { return graph ? graph->ws_bytes : 0; }
+
+ent_status ent_graph_destroy(ent_graph graph) {
+  g_last_error.clear();
+  batch_free(graph);
+  return ENT_OK;
+}
+
+ent_status ent_entropy_estimate_batched(const ent_matrix *Rs, int32_t count, int32_t method,
+                                        int32_t degree, int32_t probes, uint64_t seed,
+                                        const ent_options *opt, ent_result *outs) {
+  g_last_error.clear();
+  if (!outs) return fail(ENT_EINVAL, "outs is NULL");
+  ent_graph_s *g = nullptr;
+  ent_status rc = batch_create(Rs, count, method, degree, probes, seed, opt, false, &g);
+  if (rc != ENT_OK) return rc;
+  rc = batch_enqueue(g, g->stream, nullptr);
+  if (rc == ENT_OK) rc = batch_collect(g, outs);
+  batch_free(g);
+  return rc;
 }
 
 ent_status ent_timing_enable(int32_t on) {

@@ -61,6 +61,33 @@ struct CsrStepArgs {
   int32_t nblk;         // persistent grid size (partial stride)
 };
 
+// Per-matrix descriptor of a batch (device resident).  Offsets are in
+// elements of the batch-wide buffers they index.
+struct BatchMat {
+  const void *src; // caller's matrix (storage type), ld = ldsrc
+  int64_t ldsrc;
+  const void *R;   // matrix in the compute type, row-major, ld = ldr
+  int64_t ldr;
+  int64_t n;
+  int64_t n_pad;   // rows of this matrix's V blocks
+  int64_t voff;    // V / G blocks (n_pad x ldv, row-major)
+  int64_t poff;    // step partials [slot][ntile][ldv]
+  int64_t xoff;    // power-method vectors
+  int64_t pboff;   // power-method partials (3 per block)
+  int64_t doff;    // moments [slot][s]
+  int64_t hoff;    // per-probe values [s]
+  double *scal;    // scalar block
+  uint64_t seed;   // probe seed of this matrix
+  int32_t ntile;   // row tiles of the step kernel
+  int32_t pblk;    // power-method blocks
+};
+
+struct BatchStepArgs {
+  DenseStepArgs base;  // V/G/part are batch base pointers; R, n, ntile, scal per matrix
+  const BatchMat *mats;
+  const int2 *tiles;   // (matrix, row tile) per workgroup
+};
+
 // ---- probes ----------------------------------------------------------------
 // G[i][j] (row-major, ld = ldv) for i < n_pad, j < ldv; zero outside n x s.
 // Rademacher also writes the sign words signs[i][w] (w < ldv/32) if non-null.
@@ -72,21 +99,24 @@ hipError_t launch_sign_gen(uint32_t *signs, int64_t n, int32_t s, int64_t ldv, u
 
 // ---- power method (Algorithm 4) ------------------------------------------
 hipError_t launch_power_start(double *x, int64_t n, uint64_t seed, int32_t trial, hipStream_t st);
-// y = (R x) / ||x_prev||, with ||x_prev||^2 = sum(in_part[0..in_cnt)) (in_part
-// null: scale 1).  part3[3*b + {0,1,2}] = per-block sums of y^2, xs.y, xs^2
-// with xs = x/||x_prev||.  Returns the number of blocks in *nblk.
+// y = (R x) / ||x_prev||, ||x_prev||^2 = in_norm[0] (in_norm null: scale 1);
+// part3[3*b + {0,1,2}] = per-block sums of y^2, xs.y, xs^2, xs = x/||x_prev||.
+// *nblk receives the number of blocks.
+int32_t power_blocks_dense(int64_t n);
+int32_t power_blocks_csr(int64_t n);
 template <typename T>
 hipError_t launch_power_gemv(const T *R, int64_t ldr, int64_t n, const double *x,
-                             const double *in_part, int32_t in_cnt, double *y, double *part3,
-                             int32_t *nblk, hipStream_t st);
+                             const double *in_norm, double *y, double *part3, int32_t *nblk,
+                             hipStream_t st);
 template <typename T>
 hipError_t launch_power_spmv(const int64_t *rp, const int32_t *ci, const T *val, int64_t n,
-                             const double *x, const double *in_part, int32_t in_cnt, double *y,
-                             double *part3, int32_t *nblk, hipStream_t st);
-// p~ of trial = sum(xs.y)/sum(xs^2) from part3 of the final product; keeps
-// the maximum over trials in scal[S_P1] (trial 0 overwrites).
-hipError_t launch_power_rq(double *scal, const double *part3, int32_t nblk, int32_t trial,
-                           hipStream_t st);
+                             const double *x, const double *in_norm, double *y, double *part3,
+                             int32_t *nblk, hipStream_t st);
+// norm3[0..2] = fixed-order sums of the nblk block triples.
+hipError_t launch_power_reduce(const double *part3, int32_t nblk, double *norm3, hipStream_t st);
+// p~ of trial = norm3[1]/norm3[2] of its final product; scal[S_P1] keeps the
+// maximum over trials (trial 0 overwrites).
+hipError_t launch_power_rq(double *scal, const double *norm3, int32_t trial, hipStream_t st);
 // u = u_fixed > 0 ? u_fixed : min(1, c p~1); interval scalars and, for
 // Chebyshev, alpha_0..alpha_m (closed form of Lemma 3 when lo = 0,
 // interpolant at m+1 Chebyshev points otherwise).
@@ -115,6 +145,90 @@ hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st);
 template <typename T>
 hipError_t launch_csr_step(const CsrStepArgs &a, hipStream_t st);
 int32_t csr_step_blocks(int64_t n);
+
+// ---- BF16x3 dense path (probe-major blocks, leading dimension n_pad) ----------
+struct Bf16GemmArgs {
+  const uint16_t *A_hi, *A_lo;  // n_pad x n_pad, row-major, bf16 bits
+  const uint16_t *V_hi, *V_lo;  // ldv x n_pad, probe-major
+  float *part_y;                // splits x ldv x n_pad
+  int64_t n_pad;                // multiple of 128
+  int64_t ldv;                  // multiple of bn
+  int64_t k_per_split;          // multiple of 32, splits * k_per_split = n_pad
+  int32_t splits;
+  int32_t bn;                   // 64, 128 or 256
+};
+struct Bf16EpiArgs {
+  const float *part_y;
+  int32_t splits;
+  const float *Vk, *Vkm1;       // FP32 probe-major (Vkm1 may be null)
+  float *Vkp1;                  // null: no write (last Taylor step)
+  uint16_t *V_hi, *V_lo;        // split of V_{k+1}, written in place
+  const float *G;
+  const double *scal;
+  double c1, c2, cw;
+  int32_t dot_y, slot, slot_gg;
+  double *part;                 // [slot][nblk][ldv]
+  int32_t nblk;
+  int64_t n_pad, ldv;
+};
+template <typename Tin>
+hipError_t launch_split_matrix(const Tin *R, int64_t ldr, int64_t n, int64_t n_pad,
+                               const double *scal, uint16_t *hi, uint16_t *lo, hipStream_t st);
+// Probe-major block G[j][i] = scale * (probe of the given stream) and its
+// bf16 split.
+hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, int64_t n_pad,
+                              int32_t s, int64_t ldv, uint64_t seed, int32_t dist, hipStream_t st,
+                              uint32_t stream = 0, double scale = 1.0);
+hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st);
+hipError_t launch_bf16x3_epilogue(const Bf16EpiArgs &a, hipStream_t st);
+int32_t bf16x3_epilogue_blocks(int64_t n_pad);
+
+// ---- batches of dense matrices (one launch per phase over all matrices) ------
+template <typename T>
+hipError_t launch_batch_dense_step(const BatchStepArgs &ba, int32_t ntiles, int32_t wr,
+                                   hipStream_t st);
+hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t st);
+// R (compute copy, ld = ldr, zero columns n..ldr) <- src for every matrix.
+template <typename Tin, typename Tout>
+hipError_t launch_batch_convert(const BatchMat *mats, int32_t count, int64_t max_elems,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_batch_trace(const BatchMat *mats, int32_t count, hipStream_t st);
+template <typename T>
+hipError_t launch_batch_probes(const BatchMat *mats, int32_t count, int64_t max_n_pad, T *G,
+                               int32_t s, int64_t ldv, int32_t dist, hipStream_t st);
+hipError_t launch_batch_power_start(const BatchMat *mats, int32_t count, int64_t max_n, double *x,
+                                    int32_t trial, hipStream_t st);
+// norm holds 4 doubles per matrix (reduced triple of the previous product).
+template <typename T>
+hipError_t launch_batch_power_gemv(const BatchMat *mats, const int2 *ptiles, int32_t nptiles,
+                                   const double *x, const double *norm, double *y, double *pout,
+                                   hipStream_t st);
+hipError_t launch_batch_power_reduce(const BatchMat *mats, int32_t count, const double *p,
+                                     double *norm, hipStream_t st);
+hipError_t launch_batch_power_rq(const BatchMat *mats, int32_t count, const double *norm,
+                                 int32_t trial, hipStream_t st);
+hipError_t launch_batch_setup(const BatchMat *mats, int32_t count, int32_t method, int32_t m,
+                              double c, double u_fixed, double lo, hipStream_t st);
+hipError_t launch_batch_reduce(const BatchMat *mats, int32_t count, const double *part,
+                               int32_t nslot, int64_t ldv, int32_t s, double *d, hipStream_t st);
+hipError_t launch_batch_final(const BatchMat *mats, int32_t count, const double *d, int32_t method,
+                              int32_t m, int32_t s, double *h, hipStream_t st);
+
+// ---- random projection (Algorithm 3) -----------------------------------------
+template <typename T>
+hipError_t launch_sketch_gen(T *P, int64_t n, int64_t n_pad, int32_t s, int64_t ldv, uint64_t seed,
+                             hipStream_t st);
+// G = X^T X (s x s, FP64) with X(i, a) at X[i*si + a*sa]; scratch holds
+// nsplit * s * s doubles.
+template <typename T>
+hipError_t launch_gram(const T *X, int64_t si, int64_t sa, int64_t n, int32_t s, double *scratch,
+                       int32_t nsplit, double *G, hipStream_t st);
+// Eigenvalues of G by parallel Jacobi, sigma = sqrt, top k -> sigma[0..k),
+// scal[S_ENT] = sum sigma ln(1/sigma).  work: N*N doubles, eig: N (N = s
+// rounded up to even, at most 256).
+hipError_t launch_rp_spectrum(const double *G, int32_t s, int32_t k, double *work, double *eig,
+                              double *sigma, double *scal, hipStream_t st);
 
 // ---- reductions ---------------------------------------------------------------
 // d[k][j] = sum_t part[k][t][j] (fixed order), k < nslot, j < s.

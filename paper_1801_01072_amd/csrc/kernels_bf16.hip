@@ -1,0 +1,314 @@
+// kernels_bf16.hip -- BF16x3 split-precision recurrence step for dense R.
+//
+// A = a*R is split once per estimate into bf16 hi = RNE(A), lo = RNE(A - hi)
+// (zero padded to n_pad x n_pad).  Each step forms
+//     Y = A_hi V_hi + A_hi V_lo + A_lo V_hi          (FP32 accumulation)
+// on the gfx950 BF16 matrix cores (v_mfma_f32_32x32x16_bf16), then an
+// elementwise epilogue applies the recurrence in FP32, re-splits V_{k+1}
+// into hi/lo for the next product and accumulates the per-probe dots in FP64.
+//
+// All n x s blocks of this path are stored probe-major ([probe][row], leading
+// dimension n_pad): the MFMA B operand needs 8 consecutive k of one probe
+// (16 contiguous bytes), and the epilogue touches 8 consecutive rows of one
+// probe per thread.
+//
+// MFMA 32x32x16 bf16 layout (lane l, measured on gfx950): A row l%32, k-slots
+// 8(l/32)..8(l/32)+7; B column l%32, same k-slots; D register r holds row
+// 8(r/4) + 4(l/32) + r%4, column l%32.
+//
+// GEMM tiling: a workgroup (4 waves) owns 128 rows x BN probes over one
+// K-split; wave w owns rows 32w..32w+31 and all BN probes, so A is streamed
+// from HBM once per step (each lane loads 16 B of hi and of lo per k-step
+// straight into registers) while the V^T chunk (BN x 32, hi and lo) is
+// shared through LDS.  Split-K partials go to part_y[split][probe][row]; the
+// epilogue sums them in split order (deterministic).
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace ent {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// Round-to-nearest-even FP32 -> BF16 bits (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------------------------
+// A = a * R -> hi/lo (row-major, ld = n_pad, zero outside n x n)
+// ---------------------------------------------------------------------------
+template <typename Tin>
+__global__ void split_matrix_kernel(const Tin *__restrict__ R, int64_t ldr, int64_t n, int64_t n_pad,
+                                    const double *__restrict__ scal, uint16_t *__restrict__ hi,
+                                    uint16_t *__restrict__ lo) {
+  const int64_t row = blockIdx.y;
+  const double a = scal[S_A];
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_pad;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    float v = 0.f;
+    if (row < n && c < n) v = (float)(a * (double)R[row * ldr + c]);
+    const uint16_t h = bf16_rne(v);
+    const uint16_t l = bf16_rne(v - bf16_to_f32(h));
+    hi[row * n_pad + c] = h;
+    lo[row * n_pad + c] = l;
+  }
+}
+
+template <typename Tin>
+hipError_t launch_split_matrix(const Tin *R, int64_t ldr, int64_t n, int64_t n_pad,
+                               const double *scal, uint16_t *hi, uint16_t *lo, hipStream_t st) {
+  dim3 grid((unsigned)((n_pad + 255) / 256 < 32 ? (n_pad + 255) / 256 : 32), (unsigned)n_pad);
+  split_matrix_kernel<Tin><<<grid, 256, 0, st>>>(R, ldr, n, n_pad, scal, hi, lo);
+  return hipGetLastError();
+}
+template hipError_t launch_split_matrix<double>(const double *, int64_t, int64_t, int64_t,
+                                                const double *, uint16_t *, uint16_t *, hipStream_t);
+template hipError_t launch_split_matrix<float>(const float *, int64_t, int64_t, int64_t,
+                                               const double *, uint16_t *, uint16_t *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Probe block, probe-major: G[j][i] (FP32) plus its hi/lo split.
+// ---------------------------------------------------------------------------
+__global__ void probe_gen_t_kernel(float *__restrict__ G, uint16_t *__restrict__ hi,
+                                   uint16_t *__restrict__ lo, int64_t n, int64_t n_pad, int32_t s,
+                                   int64_t ldv, uint64_t seed, int32_t dist, uint32_t stream,
+                                   double scale) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ldv * n_pad) return;
+  const int64_t j = t / n_pad, i = t % n_pad;
+  float v = 0.f;
+  if (i < n && j < s)
+    v = (float)(scale * (dist == 0 ? rademacher(seed, stream, i, j) : gaussian(seed, stream, i, j)));
+  G[t] = v;
+  const uint16_t h = bf16_rne(v);
+  hi[t] = h;
+  lo[t] = bf16_rne(v - bf16_to_f32(h));
+}
+
+hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, int64_t n_pad,
+                              int32_t s, int64_t ldv, uint64_t seed, int32_t dist, hipStream_t st,
+                              uint32_t stream, double scale) {
+  const int64_t tot = ldv * n_pad;
+  probe_gen_t_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(G, hi, lo, n, n_pad, s, ldv, seed,
+                                                                   dist, stream, scale);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: part_y[ks][j][i] = sum_{k in split ks} (A_hi V_hi + A_hi V_lo + A_lo V_hi)[i][j]
+// ---------------------------------------------------------------------------
+template <int BN>
+__global__ __launch_bounds__(256) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
+  constexpr int BK = 32;              // two MFMA k-steps per chunk
+  constexpr int LDK = BK + 8;         // padded LDS row (bf16 elements): 80 bytes
+  constexpr int NSUB = BN / 32;
+  constexpr int PIECES = BN * BK * 2 / 8 / 256;  // 8-element (16 B) pieces per thread (hi+lo)
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDK];  // [hi/lo][col][k]
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nrt = (int)(a.n_pad / 128);
+  const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  // tile order: row tile fastest, then K-split, then column tile, so the
+  // workgroups of one XCD share the V^T slice of their split in L2
+  const int rt = b % nrt;
+  const int ks = (b / nrt) % a.splits;
+  const int ct = b / (nrt * a.splits);
+  const int64_t npad = a.n_pad;
+  const int64_t kbeg = (int64_t)ks * a.k_per_split;
+  const int64_t kend = kbeg + a.k_per_split;
+  const int64_t col0 = (int64_t)ct * BN;
+  const int m32 = lane & 31, kh = lane >> 5;
+  const int64_t arow = (int64_t)rt * 128 + 32 * w + m32;
+  const uint16_t *__restrict__ Ahi = a.A_hi + arow * npad;
+  const uint16_t *__restrict__ Alo = a.A_lo + arow * npad;
+
+  f32x16 acc[NSUB];
+#pragma unroll
+  for (int c = 0; c < NSUB; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
+
+  u16x8 vreg[PIECES];
+  u16x8 ahi[2], alo[2];
+  auto load_b = [&](int64_t kc) {
+#pragma unroll
+    for (int p = 0; p < PIECES; ++p) {
+      const int idx = tid + p * 256;          // over [hl][col][k/8]
+      const int hl = idx / (BN * 4);
+      const int rem = idx % (BN * 4);
+      const int col = rem / 4, kq = rem % 4;
+      const uint16_t *src = (hl ? a.V_lo : a.V_hi) + (col0 + col) * npad + kc + kq * 8;
+      vreg[p] = *(const u16x8 *)src;
+    }
+  };
+  auto store_b = [&]() {
+#pragma unroll
+    for (int p = 0; p < PIECES; ++p) {
+      const int idx = tid + p * 256;
+      const int hl = idx / (BN * 4);
+      const int rem = idx % (BN * 4);
+      const int col = rem / 4, kq = rem % 4;
+      *(u16x8 *)(&Bs[hl][col * LDK + kq * 8]) = vreg[p];
+    }
+  };
+  auto load_a = [&](int64_t kc) {
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      ahi[s2] = *(const u16x8 *)(Ahi + kc + 16 * s2 + 8 * kh);
+      alo[s2] = *(const u16x8 *)(Alo + kc + 16 * s2 + 8 * kh);
+    }
+  };
+
+  load_b(kbeg);
+  load_a(kbeg);
+  for (int64_t kc = kbeg; kc < kend; kc += BK) {
+    store_b();
+    u16x8 ch[2] = {ahi[0], ahi[1]}, cl[2] = {alo[0], alo[1]};
+    __syncthreads();
+    if (kc + BK < kend) {
+      load_b(kc + BK);
+      load_a(kc + BK);
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const bf16x8 a_h = __builtin_bit_cast(bf16x8, ch[s2]);
+      const bf16x8 a_l = __builtin_bit_cast(bf16x8, cl[s2]);
+      bf16x8 b_h[NSUB], b_l[NSUB];
+#pragma unroll
+      for (int c = 0; c < NSUB; ++c) {
+        const int off = (32 * c + m32) * LDK + 16 * s2 + 8 * kh;
+        b_h[c] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(&Bs[0][off]));
+        b_l[c] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(&Bs[1][off]));
+      }
+#pragma unroll
+      for (int c = 0; c < NSUB; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h[c], acc[c], 0, 0, 0);
+#pragma unroll
+      for (int c = 0; c < NSUB; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l[c], acc[c], 0, 0, 0);
+#pragma unroll
+      for (int c = 0; c < NSUB; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h[c], acc[c], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // partial tile -> part_y[ks][col][row], 4 consecutive rows per store
+  float *__restrict__ out = a.part_y + (int64_t)ks * a.ldv * npad;
+  const int64_t rbase = (int64_t)rt * 128 + 32 * w + 4 * kh;
+#pragma unroll
+  for (int c = 0; c < NSUB; ++c) {
+    const int64_t col = col0 + 32 * c + m32;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      f32x4 v = {acc[c][4 * g], acc[c][4 * g + 1], acc[c][4 * g + 2], acc[c][4 * g + 3]};
+      *(f32x4 *)(out + col * npad + rbase + 8 * g) = v;
+    }
+  }
+}
+
+hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st) {
+  const int nrt = (int)(a.n_pad / 128), nct = (int)(a.ldv / a.bn);
+  const unsigned grid = (unsigned)(nrt * nct * a.splits);
+  switch (a.bn) {
+    case 64: bf16x3_gemm_kernel<64><<<grid, 256, 0, st>>>(a); break;
+    case 128: bf16x3_gemm_kernel<128><<<grid, 256, 0, st>>>(a); break;
+    case 256: bf16x3_gemm_kernel<256><<<grid, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue: y = sum_ks part_y[ks]; z = c1*y + c2*b*V_k + cw*V_{k-1};
+// V_{k+1} = z (FP32) and its hi/lo split; per-probe dots with g.
+// Thread = (probe j, 8 consecutive rows); block = 256 threads of one probe.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void bf16x3_epilogue_kernel(Bf16EpiArgs a) {
+  __shared__ double red[2][4];
+  const int64_t j = blockIdx.y;
+  const int64_t npad = a.n_pad;
+  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
+  const float c1 = (float)a.c1, c2b = (float)(a.c2 * a.scal[S_B]), cw = (float)a.cw;
+  double ds = 0.0, gs = 0.0;
+  if (i0 < npad) {
+    const int64_t off = j * npad + i0;
+    float y[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) y[e] = 0.f;
+    for (int ks = 0; ks < a.splits; ++ks) {
+      const f32x4 *p = (const f32x4 *)(a.part_y + (int64_t)ks * a.ldv * npad + off);
+      const f32x4 p0 = p[0], p1 = p[1];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        y[e] += p0[e];
+        y[4 + e] += p1[e];
+      }
+    }
+    const f32x4 *vk = (const f32x4 *)(a.Vk + off);
+    const f32x4 vk0 = vk[0], vk1 = vk[1];
+    f32x4 vm0 = {0, 0, 0, 0}, vm1 = {0, 0, 0, 0};
+    if (a.Vkm1 && a.cw != 0.0) {
+      const f32x4 *vm = (const f32x4 *)(a.Vkm1 + off);
+      vm0 = vm[0];
+      vm1 = vm[1];
+    }
+    const f32x4 *gp = (const f32x4 *)(a.G + off);
+    const f32x4 g0 = gp[0], g1 = gp[1];
+    float z[8];
+    u16x8 zh, zl;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float vke = e < 4 ? vk0[e] : vk1[e - 4];
+      const float vme = e < 4 ? vm0[e] : vm1[e - 4];
+      const float ge = e < 4 ? g0[e] : g1[e - 4];
+      z[e] = c1 * y[e] + c2b * vke + cw * vme;
+      const uint16_t h = bf16_rne(z[e]);
+      zh[e] = h;
+      zl[e] = bf16_rne(z[e] - bf16_to_f32(h));
+      if (a.slot >= 0) {
+        ds += (double)ge * (double)(a.dot_y ? y[e] : z[e]);
+        gs += (double)ge * (double)ge;
+      }
+    }
+    if (a.Vkp1) {
+      f32x4 *o = (f32x4 *)(a.Vkp1 + off);
+      o[0] = f32x4{z[0], z[1], z[2], z[3]};
+      o[1] = f32x4{z[4], z[5], z[6], z[7]};
+      *(u16x8 *)(a.V_hi + off) = zh;
+      *(u16x8 *)(a.V_lo + off) = zl;
+    }
+  }
+  if (a.slot < 0) return;
+  ds = wave_sum(ds);
+  gs = wave_sum(gs);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = ds;
+    red[1][w] = gs;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t idx = ((int64_t)a.slot * a.nblk + blockIdx.x) * a.ldv + j;
+    a.part[idx] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    if (a.slot_gg >= 0)
+      a.part[((int64_t)a.slot_gg * a.nblk + blockIdx.x) * a.ldv + j] =
+          red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+int32_t bf16x3_epilogue_blocks(int64_t n_pad) { return (int32_t)((n_pad / 8 + 255) / 256); }
+
+hipError_t launch_bf16x3_epilogue(const Bf16EpiArgs &a, hipStream_t st) {
+  dim3 grid((unsigned)a.nblk, (unsigned)a.ldv);
+  bf16x3_epilogue_kernel<<<grid, 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace ent

@@ -13,8 +13,8 @@
 // (c1,c2,cw) = (-1,1,0) so Z = (I - R/u) V_k, dots with Y give
 // e_{k,j} = g_j^T (R/u)(I - R/u)^k g_j.
 //
-// Tiling: a workgroup of 4 waves owns 64 rows x BN probe columns.  Each wave
-// owns 16 rows and streams its own slab of R straight from HBM into
+// Tiling: a workgroup of 4 waves owns 64*WR rows x BN probe columns.  Each
+// wave owns WR slabs of 16 rows and streams them straight from HBM into
 // registers: lane (m = l%16, q = l/16) loads 8 consecutive elements
 // R[row m][kc + 8q .. kc + 8q + 7] and feeds them to 8 successive MFMAs, so
 // MFMA k-slot q of call t is column kc + 8q + t (the k order inside a chunk
@@ -26,11 +26,14 @@
 
 namespace ent {
 
-template <typename T, int BN>
-__global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
+// Body of one tile: rows [64*WR*tm, +64*WR) (wave w owns WR 16-row slabs),
+// probe columns [BN*tn, +BN).  Shared by the single-matrix kernel and the
+// grouped (batched) kernel.
+template <typename T, int BN, int WR>
+__device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, int tn) {
   using M = Mfma16<T>;
   using v4 = typename M::v4;
-  constexpr int BM = 64, BK = 32, PAD = 2, LDL = BN + PAD;
+  constexpr int BM = 64 * WR, BK = 32, PAD = 2, LDL = BN + PAD;
   constexpr int NSUB = BN / 16;
   constexpr int VEC = 16 / (int)sizeof(T);
   constexpr int VPR = BN / VEC;
@@ -41,24 +44,29 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
   __shared__ double red[2][4][BN];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int ntn = (int)(a.ldv / BN);
-  const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-  const int tm = b / ntn, tn = b % ntn;
   const int64_t n = a.n, ldv = a.ldv;
   const T *__restrict__ R = (const T *)a.R;
   const T *__restrict__ Vk = (const T *)a.Vk;
   const int64_t col0 = (int64_t)tn * BN;
   const int m16 = lane & 15, kq = lane >> 4;
-  const int64_t arow = (int64_t)tm * BM + 16 * w + m16;
-  const bool arow_ok = arow < n;
-  const T *Arow = R + (arow_ok ? arow : 0) * a.ldr;
-
-  v4 acc[NSUB];
+  const int64_t wrow0 = (int64_t)tm * BM + 16 * WR * w;  // first row of this wave
+  bool arow_ok[WR];
+  const T *Arow[WR];
 #pragma unroll
-  for (int c = 0; c < NSUB; ++c) acc[c] = v4{0, 0, 0, 0};
+  for (int f = 0; f < WR; ++f) {
+    const int64_t arow = wrow0 + 16 * f + m16;
+    arow_ok[f] = arow < n;
+    Arow[f] = R + (arow_ok[f] ? arow : 0) * a.ldr;
+  }
+
+  v4 acc[WR][NSUB];
+#pragma unroll
+  for (int f = 0; f < WR; ++f)
+#pragma unroll
+    for (int c = 0; c < NSUB; ++c) acc[f][c] = v4{0, 0, 0, 0};
 
   vec_t vreg[NV];
-  T areg[8];
+  T areg[WR][8];
 
   auto load_v = [&](int64_t kc) {
 #pragma unroll
@@ -70,16 +78,19 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
   };
   auto load_a = [&](int64_t kc) {
     const int64_t k0 = kc + 8 * kq;
-    if (arow_ok && k0 + 8 <= n) {
 #pragma unroll
-      for (int h = 0; h < 8 / VEC; ++h) {
-        const vec_t v = *(const vec_t *)(Arow + k0 + h * VEC);
+    for (int f = 0; f < WR; ++f) {
+      if (arow_ok[f] && k0 + 8 <= n) {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) areg[h * VEC + e] = v[e];
+        for (int h = 0; h < 8 / VEC; ++h) {
+          const vec_t v = *(const vec_t *)(Arow[f] + k0 + h * VEC);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) areg[f][h * VEC + e] = v[e];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) areg[f][t] = (arow_ok[f] && k0 + t < n) ? Arow[f][k0 + t] : T(0);
       }
-    } else {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) areg[t] = (arow_ok && k0 + t < n) ? Arow[k0 + t] : T(0);
     }
   };
   auto store_v = [&]() {
@@ -97,9 +108,11 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
   load_a(0);
   for (int64_t kc = 0; kc < n; kc += BK) {
     store_v();
-    T acur[8];
+    T acur[WR][8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) acur[t] = areg[t];
+    for (int f = 0; f < WR; ++f)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acur[f][t] = areg[f][t];
     __syncthreads();
     if (kc + BK < n) {
       load_v(kc + BK);
@@ -109,7 +122,11 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
     for (int t = 0; t < 8; ++t) {
       const T *brow = Vs + (8 * kq + t) * LDL + m16;
 #pragma unroll
-      for (int c = 0; c < NSUB; ++c) acc[c] = M::mma(acur[t], brow[16 * c], acc[c]);
+      for (int c = 0; c < NSUB; ++c) {
+        const T bv = brow[16 * c];
+#pragma unroll
+        for (int f = 0; f < WR; ++f) acc[f][c] = M::mma(acur[f][t], bv, acc[f][c]);
+      }
     }
     __syncthreads();
   }
@@ -122,22 +139,26 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
   const T *__restrict__ G = (const T *)a.G;
   T *Vkp1 = (T *)a.Vkp1;
   const bool use_m1 = (a.cw != 0.0) && Vkm1;
+  const bool want_dot = a.slot >= 0;
   const bool want_gg = a.slot_gg >= 0;
-  const int64_t rbase = (int64_t)tm * BM + 16 * w;
 #pragma unroll
   for (int c = 0; c < NSUB; ++c) {
     const int64_t col = col0 + 16 * c + m16;
     double ds = 0.0, gs = 0.0;
 #pragma unroll
+    for (int f = 0; f < WR; ++f)
+#pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t off = (rbase + M::drow(kq, r)) * ldv + col;
-      const T y = ta * acc[c][r];
+      const int64_t off = (wrow0 + 16 * f + M::drow(kq, r)) * ldv + col;
+      const T y = ta * acc[f][c][r];
       T z = tc1 * y + tb * Vk[off];
       if (use_m1) z += tcw * Vkm1[off];
       if (Vkp1) Vkp1[off] = z;
-      const T g = G[off];
-      ds += (double)g * (double)(a.dot_y ? y : z);
-      if (want_gg) gs += (double)g * (double)g;
+      if (want_dot) {
+        const T g = G[off];
+        ds += (double)g * (double)(a.dot_y ? y : z);
+        if (want_gg) gs += (double)g * (double)g;
+      }
     }
     ds += __shfl_xor(ds, 16, 64);
     ds += __shfl_xor(ds, 32, 64);
@@ -148,6 +169,7 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
       red[1][w][16 * c + m16] = gs;
     }
   }
+  if (!want_dot) return;
   __syncthreads();
   for (int col = tid; col < BN; col += 256) {
     const double s = red[0][0][col] + red[0][1][col] + red[0][2][col] + red[0][3][col];
@@ -159,18 +181,60 @@ __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
   }
 }
 
+template <typename T, int BN, int WR>
+__global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
+  const int ntn = (int)(a.ldv / BN);
+  const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  dense_step_tile<T, BN, WR>(a, b / ntn, b % ntn);
+}
+
+// Grouped step over a batch: block -> (matrix, row tile) from the tile table;
+// the batch base pointers are offset by the matrix's region.
+template <typename T, int BN, int WR>
+__global__ __launch_bounds__(256) void batch_dense_step_kernel(BatchStepArgs ba) {
+  const int2 tl = ba.tiles[blockIdx.x];
+  const BatchMat &M = ba.mats[tl.x];
+  DenseStepArgs a = ba.base;
+  a.R = M.R;
+  a.ldr = M.ldr;
+  a.n = M.n;
+  a.Vk = (const T *)ba.base.Vk + M.voff;
+  if (ba.base.Vkm1) a.Vkm1 = (const T *)ba.base.Vkm1 + M.voff;
+  if (ba.base.Vkp1) a.Vkp1 = (T *)ba.base.Vkp1 + M.voff;
+  a.G = (const T *)ba.base.G + M.voff;
+  a.part = ba.base.part + M.poff;
+  a.ntile = M.ntile;
+  a.scal = M.scal;
+  dense_step_tile<T, BN, WR>(a, tl.y, 0);
+}
+
 template <typename T>
 hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st) {
   const int ntn = (int)(a.ldv / a.bn);
   const unsigned grid = (unsigned)(a.ntile * ntn);
   switch (a.bn) {
-    case 64: dense_step_kernel<T, 64><<<grid, 256, 0, st>>>(a); break;
-    case 128: dense_step_kernel<T, 128><<<grid, 256, 0, st>>>(a); break;
-    case 256: dense_step_kernel<T, 256><<<grid, 256, 0, st>>>(a); break;
+    case 64: dense_step_kernel<T, 64, 1><<<grid, 256, 0, st>>>(a); break;
+    case 128: dense_step_kernel<T, 128, 1><<<grid, 256, 0, st>>>(a); break;
+    case 256: dense_step_kernel<T, 256, 1><<<grid, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_batch_dense_step(const BatchStepArgs &ba, int32_t ntiles, int32_t wr,
+                                   hipStream_t st) {
+  if (ba.base.bn != 64) return hipErrorInvalidValue;
+  if (wr == 1)
+    batch_dense_step_kernel<T, 64, 1><<<(unsigned)ntiles, 256, 0, st>>>(ba);
+  else if (wr == 2)
+    batch_dense_step_kernel<T, 64, 2><<<(unsigned)ntiles, 256, 0, st>>>(ba);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+template hipError_t launch_batch_dense_step<double>(const BatchStepArgs &, int32_t, int32_t, hipStream_t);
+template hipError_t launch_batch_dense_step<float>(const BatchStepArgs &, int32_t, int32_t, hipStream_t);
 template hipError_t launch_dense_step<double>(const DenseStepArgs &, hipStream_t);
 template hipError_t launch_dense_step<float>(const DenseStepArgs &, hipStream_t);
 

@@ -82,24 +82,9 @@ hipError_t launch_power_start(double *x, int64_t n, uint64_t seed, int32_t trial
   return hipGetLastError();
 }
 
-// Scale 1/||x_prev|| from the yy entries of the previous product's partials.
-__device__ __forceinline__ double block_input_scale(const double *in_part, int32_t in_cnt,
-                                                    double *s_scale) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (w == 0) {
-    double acc = 0.0;
-    if (in_part)
-      for (int i = lane; i < in_cnt; i += 64) acc += in_part[3 * i];
-    acc = wave_sum(acc);
-    if (lane == 0) *s_scale = in_part ? 1.0 / sqrt(acc) : 1.0;
-  }
-  __syncthreads();
-  return *s_scale;
-}
-
-// Block sums of y^2, xs.y, xs^2 over the rows a block produced.
+// Block sums of y^2, xs.y, xs^2 over the rows a block produced (fixed order).
 __device__ __forceinline__ void block_power_partials(double yy, double xy, double xx,
-                                                     double *part3) {
+                                                     double *part3, int64_t blk) {
   __shared__ double red[3][16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   yy = wave_sum(yy);
@@ -119,157 +104,231 @@ __device__ __forceinline__ void block_power_partials(double yy, double xy, doubl
       b += red[1][i];
       c += red[2][i];
     }
-    part3[3 * blockIdx.x + 0] = a;
-    part3[3 * blockIdx.x + 1] = b;
-    part3[3 * blockIdx.x + 2] = c;
+    part3[3 * blk + 0] = a;
+    part3[3 * blk + 1] = b;
+    part3[3 * blk + 2] = c;
   }
 }
 
-// Dense: each wave owns 4 consecutive rows; lanes stride over 16-byte
-// vectors of those rows (FP64 accumulation).
+// Dense y = (R x)/||x_prev|| (||x_prev||^2 = in_norm[0]; null: no scaling).
+// Each wave owns 2 consecutive rows; lanes stride over 16-byte vectors of
+// both rows, two vectors in flight per row (FP64 accumulation).
 template <typename T>
-__global__ __launch_bounds__(256) void power_gemv_kernel(const T *__restrict__ R, int64_t ldr,
-                                                         int64_t n, const double *__restrict__ x,
-                                                         const double *__restrict__ in_part,
-                                                         int32_t in_cnt, double *__restrict__ y,
-                                                         double *__restrict__ part3) {
-  __shared__ double s_scale;
-  const double sc = block_input_scale(in_part, in_cnt, &s_scale);
+__device__ __forceinline__ void power_gemv_body(const T *__restrict__ R, int64_t ldr, int64_t n,
+                                                const double *__restrict__ x,
+                                                const double *__restrict__ in_norm,
+                                                double *__restrict__ y, double *__restrict__ part3,
+                                                int64_t blk) {
+  const double sc = in_norm ? 1.0 / sqrt(in_norm[0]) : 1.0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int VEC = 16 / sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(VEC)));
-  const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 4;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t r0 = (blk * 4 + w) * 2;
+  const bool ok0 = r0 < n, ok1 = r0 + 1 < n;
+  const T *R0 = R + (ok0 ? r0 : 0) * ldr;
+  const T *R1 = R + (ok1 ? r0 + 1 : 0) * ldr;
+  double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
   const int64_t nvec = n / VEC;
-  for (int64_t v = lane; v < nvec; v += 64) {
+  int64_t v = lane;
+  for (; v + 64 < nvec; v += 128) {
+    const int64_t k = v * VEC, k2 = (v + 64) * VEC;
+    vec_t p0 = {}, p1 = {}, q0 = {}, q1 = {};
+    if (ok0) {
+      p0 = *(const vec_t *)(R0 + k);
+      q0 = *(const vec_t *)(R0 + k2);
+    }
+    if (ok1) {
+      p1 = *(const vec_t *)(R1 + k);
+      q1 = *(const vec_t *)(R1 + k2);
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const double xe = x[k + e], xf = x[k2 + e];
+      a0 += (double)p0[e] * xe;
+      a1 += (double)p1[e] * xe;
+      b0 += (double)q0[e] * xf;
+      b1 += (double)q1[e] * xf;
+    }
+  }
+  for (; v < nvec; v += 64) {
     const int64_t k = v * VEC;
-    double xv[VEC];
+    vec_t p0 = {}, p1 = {};
+    if (ok0) p0 = *(const vec_t *)(R0 + k);
+    if (ok1) p1 = *(const vec_t *)(R1 + k);
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) xv[e] = x[k + e];
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      if (r0 + rr < n) {
-        const vec_t rv = *(const vec_t *)(R + (r0 + rr) * ldr + k);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[rr] += (double)rv[e] * xv[e];
-      }
+    for (int e = 0; e < VEC; ++e) {
+      a0 += (double)p0[e] * x[k + e];
+      a1 += (double)p1[e] * x[k + e];
     }
   }
   for (int64_t k = nvec * VEC + lane; k < n; k += 64) {
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
-      if (r0 + rr < n) acc[rr] += (double)R[(r0 + rr) * ldr + k] * x[k];
+    if (ok0) a0 += (double)R0[k] * x[k];
+    if (ok1) a1 += (double)R1[k] * x[k];
   }
+  const double s0 = wave_sum(a0 + b0), s1 = wave_sum(a1 + b1);
   double yy = 0.0, xy = 0.0, xx = 0.0;
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const double s = wave_sum(acc[rr]);
-    if (r0 + rr < n) {
-      const double yv = sc * s;
-      const double xs = sc * x[r0 + rr];
-      if (lane == 0) {
-        y[r0 + rr] = yv;
-        yy += yv * yv;
-        xy += xs * yv;
-        xx += xs * xs;
-      }
+  if (lane == 0) {
+    if (ok0) {
+      const double yv = sc * s0, xs = sc * x[r0];
+      y[r0] = yv;
+      yy += yv * yv;
+      xy += xs * yv;
+      xx += xs * xs;
+    }
+    if (ok1) {
+      const double yv = sc * s1, xs = sc * x[r0 + 1];
+      y[r0 + 1] = yv;
+      yy += yv * yv;
+      xy += xs * yv;
+      xx += xs * xs;
     }
   }
-  block_power_partials(yy, xy, xx, part3);
+  block_power_partials(yy, xy, xx, part3, blk);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void power_gemv_kernel(const T *__restrict__ R, int64_t ldr,
+                                                         int64_t n, const double *__restrict__ x,
+                                                         const double *__restrict__ in_norm,
+                                                         double *__restrict__ y,
+                                                         double *__restrict__ part3) {
+  power_gemv_body<T>(R, ldr, n, x, in_norm, y, part3, blockIdx.x);
+}
+
+int32_t power_blocks_dense(int64_t n) { return (int32_t)((n + 7) / 8); }
+int32_t power_blocks_csr(int64_t n) {
+  const int64_t b = (n + 31) / 32;
+  return (int32_t)(b < 4096 ? b : 4096);
 }
 
 template <typename T>
 hipError_t launch_power_gemv(const T *R, int64_t ldr, int64_t n, const double *x,
-                             const double *in_part, int32_t in_cnt, double *y, double *part3,
-                             int32_t *nblk, hipStream_t st) {
-  const int64_t blocks = (n + 15) / 16;
-  *nblk = (int32_t)blocks;
-  power_gemv_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(R, ldr, n, x, in_part, in_cnt, y, part3);
+                             const double *in_norm, double *y, double *part3, int32_t *nblk,
+                             hipStream_t st) {
+  const int32_t blocks = power_blocks_dense(n);
+  *nblk = blocks;
+  power_gemv_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(R, ldr, n, x, in_norm, y, part3);
   return hipGetLastError();
 }
 template hipError_t launch_power_gemv<double>(const double *, int64_t, int64_t, const double *,
-                                              const double *, int32_t, double *, double *,
-                                              int32_t *, hipStream_t);
+                                              const double *, double *, double *, int32_t *,
+                                              hipStream_t);
 template hipError_t launch_power_gemv<float>(const float *, int64_t, int64_t, const double *,
-                                             const double *, int32_t, double *, double *, int32_t *,
+                                             const double *, double *, double *, int32_t *,
                                              hipStream_t);
 
-// CSR: 8 lanes per row, 8 rows per wave, 32 rows per block.
+// CSR: 8 lanes per row, 32 rows per block per pass, persistent grid-stride
+// over row groups (one partial triple per block).
 template <typename T>
 __global__ __launch_bounds__(256) void power_spmv_kernel(const int64_t *__restrict__ rp,
                                                          const int32_t *__restrict__ ci,
                                                          const T *__restrict__ val, int64_t n,
                                                          const double *__restrict__ x,
-                                                         const double *__restrict__ in_part,
-                                                         int32_t in_cnt, double *__restrict__ y,
+                                                         const double *__restrict__ in_norm,
+                                                         double *__restrict__ y,
                                                          double *__restrict__ part3) {
-  __shared__ double s_scale;
-  const double sc = block_input_scale(in_part, in_cnt, &s_scale);
-  const int lane = threadIdx.x & 63;
-  const int sub = lane & 7;
-  const int64_t row = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
-  double acc = 0.0;
-  if (row < n) {
-    const int64_t e1 = rp[row + 1];
-    for (int64_t e = rp[row] + sub; e < e1; e += 8) acc += (double)val[e] * x[ci[e]];
-  }
-#pragma unroll
-  for (int off = 4; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  const double sc = in_norm ? 1.0 / sqrt(in_norm[0]) : 1.0;
+  const int sub = threadIdx.x & 7;
   double yy = 0.0, xy = 0.0, xx = 0.0;
-  if (row < n && sub == 0) {
-    const double yv = sc * acc;
-    const double xs = sc * x[row];
-    y[row] = yv;
-    yy = yv * yv;
-    xy = xs * yv;
-    xx = xs * xs;
+  for (int64_t base = (int64_t)blockIdx.x * 32; base < n; base += (int64_t)gridDim.x * 32) {
+    const int64_t row = base + (threadIdx.x >> 3);
+    double acc = 0.0;
+    if (row < n) {
+      const int64_t e1 = rp[row + 1];
+      for (int64_t e = rp[row] + sub; e < e1; e += 8) acc += (double)val[e] * x[ci[e]];
+    }
+#pragma unroll
+    for (int off = 4; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (row < n && sub == 0) {
+      const double yv = sc * acc;
+      const double xs = sc * x[row];
+      y[row] = yv;
+      yy += yv * yv;
+      xy += xs * yv;
+      xx += xs * xs;
+    }
   }
-  block_power_partials(yy, xy, xx, part3);
+  block_power_partials(yy, xy, xx, part3, blockIdx.x);
 }
 
 template <typename T>
 hipError_t launch_power_spmv(const int64_t *rp, const int32_t *ci, const T *val, int64_t n,
-                             const double *x, const double *in_part, int32_t in_cnt, double *y,
-                             double *part3, int32_t *nblk, hipStream_t st) {
-  const int64_t blocks = (n + 31) / 32;
-  *nblk = (int32_t)blocks;
-  power_spmv_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(rp, ci, val, n, x, in_part, in_cnt, y, part3);
+                             const double *x, const double *in_norm, double *y, double *part3,
+                             int32_t *nblk, hipStream_t st) {
+  const int32_t blocks = power_blocks_csr(n);
+  *nblk = blocks;
+  power_spmv_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(rp, ci, val, n, x, in_norm, y, part3);
   return hipGetLastError();
 }
 template hipError_t launch_power_spmv<double>(const int64_t *, const int32_t *, const double *,
-                                              int64_t, const double *, const double *, int32_t,
-                                              double *, double *, int32_t *, hipStream_t);
+                                              int64_t, const double *, const double *, double *,
+                                              double *, int32_t *, hipStream_t);
 template hipError_t launch_power_spmv<float>(const int64_t *, const int32_t *, const float *,
-                                             int64_t, const double *, const double *, int32_t,
-                                             double *, double *, int32_t *, hipStream_t);
+                                             int64_t, const double *, const double *, double *,
+                                             double *, int32_t *, hipStream_t);
 
-__global__ void power_rq_kernel(double *__restrict__ scal, const double *__restrict__ part3,
-                                int32_t nblk, int32_t trial) {
-  const int lane = threadIdx.x;
-  double xy = 0.0, xx = 0.0;
-  for (int i = lane; i < nblk; i += 64) {
-    xy += part3[3 * i + 1];
-    xx += part3[3 * i + 2];
+// Fixed-order sum of the block triples of one product into norm3[0..2].
+__device__ __forceinline__ void power_reduce_body(const double *__restrict__ part3, int32_t nblk,
+                                                  double *__restrict__ norm3) {
+  __shared__ double red[3][4];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+    a += part3[3 * i];
+    b += part3[3 * i + 1];
+    c += part3[3 * i + 2];
   }
-  xy = wave_sum(xy);
-  xx = wave_sum(xx);
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) {
-    const double rq = xy / xx;
+    red[0][w] = a;
+    red[1][w] = b;
+    red[2][w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    norm3[0] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    norm3[1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    norm3[2] = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+  }
+}
+
+__global__ __launch_bounds__(256) void power_reduce_kernel(const double *__restrict__ part3,
+                                                           int32_t nblk, double *__restrict__ norm3) {
+  power_reduce_body(part3, nblk, norm3);
+}
+
+hipError_t launch_power_reduce(const double *part3, int32_t nblk, double *norm3, hipStream_t st) {
+  power_reduce_kernel<<<1, 256, 0, st>>>(part3, nblk, norm3);
+  return hipGetLastError();
+}
+
+// Rayleigh quotient of a trial from the reduced triple of its final product;
+// scal[S_P1] keeps the maximum over trials (trial 0 overwrites).
+__device__ __forceinline__ void power_rq_body(double *__restrict__ scal,
+                                              const double *__restrict__ norm3, int32_t trial) {
+  if (threadIdx.x == 0) {
+    const double rq = norm3[1] / norm3[2];
     if (trial == 0 || rq > scal[S_P1]) scal[S_P1] = rq;
   }
 }
 
-hipError_t launch_power_rq(double *scal, const double *part3, int32_t nblk, int32_t trial,
-                           hipStream_t st) {
-  power_rq_kernel<<<1, 64, 0, st>>>(scal, part3, nblk, trial);
+__global__ void power_rq_kernel(double *__restrict__ scal, const double *__restrict__ norm3,
+                                int32_t trial) {
+  power_rq_body(scal, norm3, trial);
+}
+
+hipError_t launch_power_rq(double *scal, const double *norm3, int32_t trial, hipStream_t st) {
+  power_rq_kernel<<<1, 64, 0, st>>>(scal, norm3, trial);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Interval [lo, u] and Chebyshev coefficients
 // ---------------------------------------------------------------------------
-__global__ void setup_interval_kernel(double *__restrict__ scal, int32_t method, int32_t m,
-                                      double c, double u_fixed, double lo) {
+__device__ __forceinline__ void setup_interval_body(double *__restrict__ scal, int32_t method,
+                                                    int32_t m, double c, double u_fixed, double lo) {
   __shared__ double su;
   if (threadIdx.x == 0) {
     double u;
@@ -326,6 +385,11 @@ __global__ void setup_interval_kernel(double *__restrict__ scal, int32_t method,
   }
 }
 
+__global__ void setup_interval_kernel(double *__restrict__ scal, int32_t method, int32_t m,
+                                      double c, double u_fixed, double lo) {
+  setup_interval_body(scal, method, m, c, u_fixed, lo);
+}
+
 hipError_t launch_setup_interval(double *scal, int32_t method, int32_t m, double c, double u_fixed,
                                  double lo, hipStream_t st) {
   setup_interval_kernel<<<1, 256, 0, st>>>(scal, method, m, c, u_fixed, lo);
@@ -336,8 +400,8 @@ hipError_t launch_setup_interval(double *scal, int32_t method, int32_t m, double
 // Trace of R (input contract: unit trace)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void trace_dense_kernel(const T *__restrict__ R, int64_t ldr, int64_t n,
-                                   double *__restrict__ scal) {
+__device__ __forceinline__ void trace_dense_body(const T *__restrict__ R, int64_t ldr, int64_t n,
+                                                 double *__restrict__ scal) {
   __shared__ double red[4];
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += (double)R[i * ldr + i];
@@ -345,6 +409,12 @@ __global__ void trace_dense_kernel(const T *__restrict__ R, int64_t ldr, int64_t
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) scal[S_TRACE] = red[0] + red[1] + red[2] + red[3];
+}
+
+template <typename T>
+__global__ void trace_dense_kernel(const T *__restrict__ R, int64_t ldr, int64_t n,
+                                   double *__restrict__ scal) {
+  trace_dense_body<T>(R, ldr, n, scal);
 }
 
 template <typename T>
@@ -455,16 +525,21 @@ template hipError_t launch_convert<float, float>(const float *, int64_t, float *
 // ---------------------------------------------------------------------------
 // Reductions
 // ---------------------------------------------------------------------------
-__global__ void reduce_moments_kernel(const double *__restrict__ part, int32_t nslot,
-                                      int32_t ntile, int64_t ldv, int32_t s,
-                                      double *__restrict__ d) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void reduce_moments_body(const double *__restrict__ part, int32_t nslot,
+                                                    int32_t ntile, int64_t ldv, int32_t s,
+                                                    double *__restrict__ d, int64_t t) {
   if (t >= (int64_t)nslot * s) return;
   const int32_t k = (int32_t)(t / s), j = (int32_t)(t % s);
   const double *p = part + (int64_t)k * ntile * ldv + j;
   double acc = 0.0;
   for (int32_t i = 0; i < ntile; ++i) acc += p[(int64_t)i * ldv];
   d[(int64_t)k * s + j] = acc;
+}
+
+__global__ void reduce_moments_kernel(const double *__restrict__ part, int32_t nslot,
+                                      int32_t ntile, int64_t ldv, int32_t s,
+                                      double *__restrict__ d) {
+  reduce_moments_body(part, nslot, ntile, ldv, s, d, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 hipError_t launch_reduce_moments(const double *part, int32_t nslot, int32_t ntile, int64_t ldv,
@@ -476,8 +551,9 @@ hipError_t launch_reduce_moments(const double *part, int32_t nslot, int32_t ntil
 
 // h_j and the mean/standard error.  Chebyshev: h_j = -sum_{k=0}^m alpha_k d_kj.
 // Taylor: h_j = ln(1/u) + u sum_{k=1}^m e_kj / k  (e_kj = g^T (R/u) C^k g).
-__global__ void final_kernel(const double *__restrict__ d, double *__restrict__ scal, int32_t method,
-                             int32_t m, int32_t s, double *__restrict__ h) {
+__device__ __forceinline__ void final_body(const double *__restrict__ d, double *__restrict__ scal,
+                                           int32_t method, int32_t m, int32_t s,
+                                           double *__restrict__ h) {
   __shared__ double red[4];
   __shared__ double smean;
   const double u = scal[S_U];
@@ -515,9 +591,204 @@ __global__ void final_kernel(const double *__restrict__ d, double *__restrict__ 
   }
 }
 
+__global__ void final_kernel(const double *__restrict__ d, double *__restrict__ scal, int32_t method,
+                             int32_t m, int32_t s, double *__restrict__ h) {
+  final_body(d, scal, method, m, s, h);
+}
+
 hipError_t launch_final(const double *d, double *scal, int32_t method, int32_t m, int32_t s,
                         double *h, hipStream_t st) {
   final_kernel<<<1, 256, 0, st>>>(d, scal, method, m, s, h);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batches: the same phases over many matrices in one launch each.  Blocks map
+// to matrices through the descriptor array (grid.y) or a tile table.
+// ---------------------------------------------------------------------------
+__global__ void fill_kernel(double *__restrict__ p, int64_t count, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t st) {
+  const int64_t blocks = (count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024;
+  fill_kernel<<<(unsigned)(blocks > 0 ? blocks : 1), 256, 0, st>>>(p, count, v);
+  return hipGetLastError();
+}
+
+template <typename Tin, typename Tout>
+__global__ void batch_convert_kernel(const BatchMat *__restrict__ mats) {
+  const BatchMat &M = mats[blockIdx.y];
+  const Tin *src = (const Tin *)M.src;
+  Tout *dst = (Tout *)M.R;
+  const int64_t tot = M.n * M.ldr;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / M.ldr, c = t % M.ldr;
+    dst[t] = c < M.n ? (Tout)src[r * M.ldsrc + c] : Tout(0);
+  }
+}
+
+template <typename Tin, typename Tout>
+hipError_t launch_batch_convert(const BatchMat *mats, int32_t count, int64_t max_elems,
+                                hipStream_t st) {
+  const int64_t per = (max_elems + 255) / 256;
+  dim3 grid((unsigned)(per < 512 ? per : 512), (unsigned)count);
+  batch_convert_kernel<Tin, Tout><<<grid, 256, 0, st>>>(mats);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_convert<double, double>(const BatchMat *, int32_t, int64_t, hipStream_t);
+template hipError_t launch_batch_convert<float, float>(const BatchMat *, int32_t, int64_t, hipStream_t);
+template hipError_t launch_batch_convert<double, float>(const BatchMat *, int32_t, int64_t, hipStream_t);
+template hipError_t launch_batch_convert<float, double>(const BatchMat *, int32_t, int64_t, hipStream_t);
+
+template <typename T>
+__global__ void batch_trace_kernel(const BatchMat *__restrict__ mats) {
+  const BatchMat &M = mats[blockIdx.x];
+  trace_dense_body<T>((const T *)M.R, M.ldr, M.n, M.scal);
+}
+
+template <typename T>
+hipError_t launch_batch_trace(const BatchMat *mats, int32_t count, hipStream_t st) {
+  batch_trace_kernel<T><<<(unsigned)count, 256, 0, st>>>(mats);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_trace<double>(const BatchMat *, int32_t, hipStream_t);
+template hipError_t launch_batch_trace<float>(const BatchMat *, int32_t, hipStream_t);
+
+// G of matrix b = its n_pad x ldv region; probes from the matrix's own seed.
+template <typename T>
+__global__ void batch_probe_kernel(const BatchMat *__restrict__ mats, T *__restrict__ G, int32_t s,
+                                   int64_t ldv, int32_t dist) {
+  const BatchMat &M = mats[blockIdx.y];
+  T *Gb = G + M.voff;
+  const int64_t tot = M.n_pad * ldv;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = t / ldv, j = t % ldv;
+    T v = T(0);
+    if (row < M.n && j < s)
+      v = (T)(dist == 0 ? rademacher(M.seed, 0u, row, j) : gaussian(M.seed, 0u, row, j));
+    Gb[t] = v;
+  }
+}
+
+template <typename T>
+hipError_t launch_batch_probes(const BatchMat *mats, int32_t count, int64_t max_n_pad, T *G,
+                               int32_t s, int64_t ldv, int32_t dist, hipStream_t st) {
+  const int64_t per = (max_n_pad * ldv + 255) / 256;
+  dim3 grid((unsigned)(per < 256 ? per : 256), (unsigned)count);
+  batch_probe_kernel<T><<<grid, 256, 0, st>>>(mats, G, s, ldv, dist);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_probes<double>(const BatchMat *, int32_t, int64_t, double *, int32_t,
+                                                int64_t, int32_t, hipStream_t);
+template hipError_t launch_batch_probes<float>(const BatchMat *, int32_t, int64_t, float *, int32_t,
+                                               int64_t, int32_t, hipStream_t);
+
+__global__ void batch_power_start_kernel(const BatchMat *__restrict__ mats, double *__restrict__ x,
+                                         int32_t trial) {
+  const BatchMat &M = mats[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M.n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[M.xoff + i] = rademacher(M.seed, 1u, i, trial);
+}
+
+hipError_t launch_batch_power_start(const BatchMat *mats, int32_t count, int64_t max_n, double *x,
+                                    int32_t trial, hipStream_t st) {
+  const int64_t per = (max_n + 255) / 256;
+  dim3 grid((unsigned)(per < 64 ? per : 64), (unsigned)count);
+  batch_power_start_kernel<<<grid, 256, 0, st>>>(mats, x, trial);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void batch_power_gemv_kernel(const BatchMat *__restrict__ mats,
+                                                               const int2 *__restrict__ ptiles,
+                                                               const double *x, const double *norm,
+                                                               double *y, double *pout) {
+  const int2 t = ptiles[blockIdx.x];
+  const BatchMat &M = mats[t.x];
+  power_gemv_body<T>((const T *)M.R, M.ldr, M.n, x + M.xoff, norm ? norm + 4 * t.x : nullptr,
+                     y + M.xoff, pout + M.pboff, t.y);
+}
+
+template <typename T>
+hipError_t launch_batch_power_gemv(const BatchMat *mats, const int2 *ptiles, int32_t nptiles,
+                                   const double *x, const double *norm, double *y, double *pout,
+                                   hipStream_t st) {
+  batch_power_gemv_kernel<T><<<(unsigned)nptiles, 256, 0, st>>>(mats, ptiles, x, norm, y, pout);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_power_gemv<double>(const BatchMat *, const int2 *, int32_t,
+                                                    const double *, const double *, double *,
+                                                    double *, hipStream_t);
+template hipError_t launch_batch_power_gemv<float>(const BatchMat *, const int2 *, int32_t,
+                                                   const double *, const double *, double *, double *,
+                                                   hipStream_t);
+
+// One block per matrix: reduce its block triples into norm[4*b .. 4*b+2].
+__global__ __launch_bounds__(256) void batch_power_reduce_kernel(const BatchMat *__restrict__ mats,
+                                                                 const double *p, double *norm) {
+  const BatchMat &M = mats[blockIdx.x];
+  power_reduce_body(p + M.pboff, M.pblk, norm + 4 * blockIdx.x);
+}
+
+hipError_t launch_batch_power_reduce(const BatchMat *mats, int32_t count, const double *p,
+                                     double *norm, hipStream_t st) {
+  batch_power_reduce_kernel<<<(unsigned)count, 256, 0, st>>>(mats, p, norm);
+  return hipGetLastError();
+}
+
+__global__ void batch_power_rq_kernel(const BatchMat *__restrict__ mats, const double *norm,
+                                      int32_t trial) {
+  power_rq_body(mats[blockIdx.x].scal, norm + 4 * blockIdx.x, trial);
+}
+
+hipError_t launch_batch_power_rq(const BatchMat *mats, int32_t count, const double *norm,
+                                 int32_t trial, hipStream_t st) {
+  batch_power_rq_kernel<<<(unsigned)count, 64, 0, st>>>(mats, norm, trial);
+  return hipGetLastError();
+}
+
+__global__ void batch_setup_kernel(const BatchMat *__restrict__ mats, int32_t method, int32_t m,
+                                   double c, double u_fixed, double lo) {
+  setup_interval_body(mats[blockIdx.x].scal, method, m, c, u_fixed, lo);
+}
+
+hipError_t launch_batch_setup(const BatchMat *mats, int32_t count, int32_t method, int32_t m,
+                              double c, double u_fixed, double lo, hipStream_t st) {
+  batch_setup_kernel<<<(unsigned)count, 256, 0, st>>>(mats, method, m, c, u_fixed, lo);
+  return hipGetLastError();
+}
+
+__global__ void batch_reduce_kernel(const BatchMat *__restrict__ mats, const double *part,
+                                    int32_t nslot, int64_t ldv, int32_t s, double *d) {
+  const BatchMat &M = mats[blockIdx.y];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)nslot * s;
+       t += (int64_t)gridDim.x * blockDim.x)
+    reduce_moments_body(part + M.poff, nslot, M.ntile, ldv, s, d + M.doff, t);
+}
+
+hipError_t launch_batch_reduce(const BatchMat *mats, int32_t count, const double *part,
+                               int32_t nslot, int64_t ldv, int32_t s, double *d, hipStream_t st) {
+  const int64_t per = ((int64_t)nslot * s + 255) / 256;
+  dim3 grid((unsigned)(per < 64 ? per : 64), (unsigned)count);
+  batch_reduce_kernel<<<grid, 256, 0, st>>>(mats, part, nslot, ldv, s, d);
+  return hipGetLastError();
+}
+
+__global__ void batch_final_kernel(const BatchMat *__restrict__ mats, const double *d,
+                                   int32_t method, int32_t m, int32_t s, double *h) {
+  const BatchMat &M = mats[blockIdx.x];
+  final_body(d + M.doff, M.scal, method, m, s, h + M.hoff);
+}
+
+hipError_t launch_batch_final(const BatchMat *mats, int32_t count, const double *d, int32_t method,
+                              int32_t m, int32_t s, double *h, hipStream_t st) {
+  batch_final_kernel<<<(unsigned)count, 256, 0, st>>>(mats, d, method, m, s, h);
   return hipGetLastError();
 }
 

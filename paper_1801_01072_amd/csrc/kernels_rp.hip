@@ -1,0 +1,244 @@
+// kernels_rp.hip -- random-projection estimator (Algorithm 3, Section 4):
+// sketch R~ = R Pi (product on the existing MFMA kernels), Gram matrix
+// R~^T R~ in FP64, its eigenvalues by a parallel cyclic Jacobi method in one
+// workgroup, singular values sigma = sqrt(lambda), the k largest kept and
+// H^ = sum sigma ln(1/sigma).
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace ent {
+
+// ---------------------------------------------------------------------------
+// Sketch Pi, entries N(0, 1/s) (Gaussian stream 2), row-major n_pad x ldv.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void sketch_gen_kernel(T *__restrict__ P, int64_t n, int64_t n_pad, int32_t s, int64_t ldv,
+                                  uint64_t seed, double scale) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_pad * ldv) return;
+  const int64_t i = t / ldv, j = t % ldv;
+  P[t] = (i < n && j < s) ? (T)(scale * gaussian(seed, 2u, i, j)) : T(0);
+}
+
+template <typename T>
+hipError_t launch_sketch_gen(T *P, int64_t n, int64_t n_pad, int32_t s, int64_t ldv, uint64_t seed,
+                             hipStream_t st) {
+  const int64_t tot = n_pad * ldv;
+  sketch_gen_kernel<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(P, n, n_pad, s, ldv, seed,
+                                                                      1.0 / sqrt((double)s));
+  return hipGetLastError();
+}
+template hipError_t launch_sketch_gen<double>(double *, int64_t, int64_t, int32_t, int64_t, uint64_t,
+                                              hipStream_t);
+template hipError_t launch_sketch_gen<float>(float *, int64_t, int64_t, int32_t, int64_t, uint64_t,
+                                             hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Gram matrix G = R~^T R~ (s x s, FP64).  R~(i, a) is at X[i*si + a*sa].
+// Workgroup = 16 x 16 block of G over one K range; partials per K range are
+// summed in range order by gram_sum_kernel.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void gram_partial_kernel(const T *__restrict__ X, int64_t si,
+                                                           int64_t sa, int64_t n, int32_t s,
+                                                           int64_t rows_per, double *__restrict__ gp) {
+  __shared__ double xa[64][17], xb[64][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
+  const int64_t r0 = (int64_t)blockIdx.z * rows_per;
+  const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
+  double acc = 0.0;
+  for (int64_t base = r0; base < r1; base += 64) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int rr = e / 16, cc = e % 16;
+      const int64_t i = base + rr;
+      const bool ok = i < r1;
+      xa[rr][cc] = (ok && a0 + cc < s) ? (double)X[i * si + (int64_t)(a0 + cc) * sa] : 0.0;
+      xb[rr][cc] = (ok && b0 + cc < s) ? (double)X[i * si + (int64_t)(b0 + cc) * sa] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < 64; ++rr) acc += xa[rr][ty] * xb[rr][tx];
+    __syncthreads();
+  }
+  const int a = a0 + ty, b = b0 + tx;
+  if (a < s && b < s) gp[((int64_t)blockIdx.z * s + a) * s + b] = acc;
+}
+
+__global__ void gram_sum_kernel(const double *__restrict__ gp, int32_t nsplit, int32_t s,
+                                double *__restrict__ G) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= s * s) return;
+  double acc = 0.0;
+  for (int k = 0; k < nsplit; ++k) acc += gp[(int64_t)k * s * s + t];
+  G[t] = acc;
+}
+
+template <typename T>
+hipError_t launch_gram(const T *X, int64_t si, int64_t sa, int64_t n, int32_t s, double *scratch,
+                       int32_t nsplit, double *G, hipStream_t st) {
+  const int64_t rows_per = ((n + nsplit - 1) / nsplit + 63) / 64 * 64;
+  dim3 grid((unsigned)((s + 15) / 16), (unsigned)((s + 15) / 16), (unsigned)nsplit);
+  gram_partial_kernel<T><<<grid, 256, 0, st>>>(X, si, sa, n, s, rows_per, scratch);
+  gram_sum_kernel<<<(unsigned)((s * s + 255) / 256), 256, 0, st>>>(scratch, nsplit, s, G);
+  return hipGetLastError();
+}
+template hipError_t launch_gram<double>(const double *, int64_t, int64_t, int64_t, int32_t, double *,
+                                        int32_t, double *, hipStream_t);
+template hipError_t launch_gram<float>(const float *, int64_t, int64_t, int64_t, int32_t, double *,
+                                       int32_t, double *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Parallel cyclic Jacobi on a symmetric N x N matrix (N even, in place in
+// global memory), one workgroup.  A sweep is N-1 rounds of the round-robin
+// schedule (index 0 fixed, the others rotate), each round rotating N/2
+// disjoint (p, q) planes at once: rotation parameters from the round's
+// starting matrix, then all row updates, then all column updates.  Stops when
+// the off-diagonal Frobenius norm is below tol * ||A||_F, or after
+// max_sweeps sweeps (every thread reads the same shared decision).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void jacobi_eig_kernel(double *__restrict__ A, int32_t N,
+                                                          double tol, int32_t max_sweeps,
+                                                          double *__restrict__ eig) {
+  __shared__ int sp[128], sq[128];
+  __shared__ double sc[128], ss[128];
+  __shared__ double red[16];
+  __shared__ int done;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int half = N / 2;
+  for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
+    // convergence test
+    double off = 0.0, fro = 0.0;
+    for (int e = tid; e < N * N; e += nt) {
+      const double v = A[e];
+      fro += v * v;
+      if (e / N != e % N) off += v * v;
+    }
+    off = wave_sum(off);
+    fro = wave_sum(fro);
+    if ((tid & 63) == 0) {
+      red[tid >> 6] = off;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double o = 0.0;
+      for (int w = 0; w < nt / 64; ++w) o += red[w];
+      red[15] = o;
+    }
+    __syncthreads();
+    const double off_tot = red[15];
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = fro;
+    __syncthreads();
+    if (tid == 0) {
+      double f = 0.0;
+      for (int w = 0; w < nt / 64; ++w) f += red[w];
+      done = (sqrt(off_tot) <= tol * sqrt(f)) || (f == 0.0) || (sweep == max_sweeps);
+    }
+    __syncthreads();
+    if (done) break;
+    for (int r = 0; r < N - 1; ++r) {
+      if (tid < half) {
+        const int i = tid;
+        int p = (i == 0) ? 0 : ((i - 1 + r) % (N - 1)) + 1;
+        int q = ((N - 1 - i - 1 + r) % (N - 1)) + 1;
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        const double apq = A[p * N + q];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0) {
+          const double theta = (A[q * N + q] - A[p * N + p]) / (2.0 * apq);
+          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+        }
+        sp[i] = p;
+        sq[i] = q;
+        sc[i] = c;
+        ss[i] = s;
+      }
+      __syncthreads();
+      // rows p, q of every pair
+      for (int e = tid; e < half * N; e += nt) {
+        const int i = e / N, k = e % N;
+        const int p = sp[i], q = sq[i];
+        const double c = sc[i], s = ss[i];
+        const double apk = A[p * N + k], aqk = A[q * N + k];
+        A[p * N + k] = c * apk - s * aqk;
+        A[q * N + k] = s * apk + c * aqk;
+      }
+      __syncthreads();
+      // columns p, q of every pair
+      for (int e = tid; e < half * N; e += nt) {
+        const int i = e / N, k = e % N;
+        const int p = sp[i], q = sq[i];
+        const double c = sc[i], s = ss[i];
+        const double akp = A[k * N + p], akq = A[k * N + q];
+        A[k * N + p] = c * akp - s * akq;
+        A[k * N + q] = s * akp + c * akq;
+      }
+      __syncthreads();
+      if (tid < half) {
+        A[sp[tid] * N + sq[tid]] = 0.0;
+        A[sq[tid] * N + sp[tid]] = 0.0;
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < N; i += nt) eig[i] = A[i * N + i];
+}
+
+// Copy the s x s Gram matrix into an N x N (N even) work matrix.
+__global__ void pad_square_kernel(const double *__restrict__ G, int32_t s, double *__restrict__ A,
+                                  int32_t N) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
+    const int i = e / N, j = e % N;
+    A[e] = (i < s && j < s) ? G[i * s + j] : 0.0;
+  }
+}
+
+// sigma = sqrt(max(lambda, 0)) in descending order (rank by comparison,
+// ties by index), the k largest kept, H^ = sum sigma ln(1/sigma).
+__global__ void rp_finish_kernel(const double *__restrict__ eig, int32_t N, int32_t k,
+                                 double *__restrict__ sigma, double *__restrict__ scal) {
+  __shared__ double sv[256];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += blockDim.x) {
+    const double lam = eig[i];
+    const double si = lam > 0.0 ? sqrt(lam) : 0.0;
+    int rank = 0;
+    for (int j = 0; j < N; ++j) {
+      const double lj = eig[j];
+      const double sj = lj > 0.0 ? sqrt(lj) : 0.0;
+      if (sj > si || (sj == si && j < i)) ++rank;
+    }
+    sv[rank] = si;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double h = 0.0;
+    for (int i = 0; i < k && i < N; ++i) {
+      const double sg = sv[i];
+      sigma[i] = sg;
+      if (sg > 0.0) h += sg * log(1.0 / sg);
+    }
+    scal[S_ENT] = h;
+    scal[S_SE] = 0.0;
+    if (!isfinite(h)) scal[S_FLAG] = 1.0;
+  }
+}
+
+hipError_t launch_rp_spectrum(const double *G, int32_t s, int32_t k, double *work, double *eig,
+                              double *sigma, double *scal, hipStream_t st) {
+  const int32_t N = (s + 1) / 2 * 2;
+  if (N > 256) return hipErrorInvalidValue;
+  pad_square_kernel<<<64, 256, 0, st>>>(G, s, work, N);
+  jacobi_eig_kernel<<<1, 1024, 0, st>>>(work, N, 1e-14, 40, eig);
+  rp_finish_kernel<<<1, 256, 0, st>>>(eig, N, k, sigma, scal);
+  return hipGetLastError();
+}
+
+}  // namespace ent

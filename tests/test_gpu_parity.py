@@ -211,3 +211,49 @@ def test_csr_poisson_closed_form():
     print(f"[poisson 1e5] H exact={H:.10f} gpu={gpu.entropy:.10f} rel={rel:.2e} se={gpu.std_err:.2e}", flush=True)
     # truncation (NTE) + sampling; the paper reports < 0.5% for m = 5, s = 50 at n = 5000
     assert rel < 5e-3
+
+
+# --------------------------------------------------------------- BF16x3 ------
+@pytest.mark.parametrize("method", ["chebyshev", "taylor"])
+@pytest.mark.parametrize("dist", ["rademacher", "gaussian"])
+def test_dense_bf16x3_small_config(orc, method, dist):
+    n, m, s, seed = 512, 30, 50, W.PROBE_SEED + 1
+    R = W.dense_density(W.spectrum_inverse(n), W.MATRIX_SEED + 1)
+    d = 0 if dist == "rademacher" else 1
+    gpu, per, mom = ent.entropy_estimate_detail(to_dev(R), method, m, s, seed, probe_dist=dist,
+                                                precision="bf16x3")
+    ref = orc.estimate(R, 0 if method == "taylor" else 1, m, s, seed, dist=d)
+    rel = abs(gpu.entropy - ref.entropy) / abs(ref.entropy)
+    perr = np.max(np.abs(per - ref.per_probe)) / np.mean(np.abs(ref.per_probe))
+    print(f"[bf16x3 512 {method} {dist}] H gpu={gpu.entropy:.12f} oracle={ref.entropy:.12f} "
+          f"rel={rel:.2e} per-probe={perr:.2e}", flush=True)
+    assert gpu.p1_est == pytest.approx(ref.p1_est, rel=1e-12)   # power method stays FP64
+    assert rel <= 1e-3 and perr <= 1e-3
+
+
+@pytest.mark.parametrize("n,s,m", [(1, 1, 1), (100, 5, 3), (200, 37, 7), (300, 300, 6), (700, 129, 12)])
+def test_dense_bf16x3_ragged(orc, n, s, m):
+    R = W.dense_density(W.spectrum_exp(n, max(n / 5.0, 1.0)), 100 + n)
+    seed = 3 + n
+    for method in ("chebyshev", "taylor"):
+        gpu, per, mom = ent.entropy_estimate_detail(to_dev(R), method, m, s, seed, probe_dist="gaussian",
+                                                    precision="bf16x3")
+        ref = orc.estimate(R, 0 if method == "taylor" else 1, m, s, seed, dist=1)
+        scale = max(np.mean(np.abs(ref.per_probe)), 1e-2)
+        perr = np.max(np.abs(per - ref.per_probe)) / scale
+        print(f"[bf16x3 {n}x{s} m={m} {method}] rel per-probe err={perr:.2e}", flush=True)
+        assert perr <= 1e-3
+        if method == "chebyshev":
+            # moments of a matrix with spectrum in [-1, 1] stay within ||g||^2
+            g2 = mom[0]
+            assert np.all(np.abs(mom) <= g2[None, :] * (1 + 1e-3) + 1e-6)
+
+
+def test_bf16x3_fp32_storage_and_determinism(orc):
+    n, m, s, seed = 384, 20, 64, 4
+    R = W.dense_density(W.spectrum_inverse(n), 9).astype(np.float32)
+    a = ent.entropy_estimate_detail(to_dev(R), "chebyshev", m, s, seed, precision="bf16x3")
+    b = ent.entropy_estimate_detail(to_dev(R), "chebyshev", m, s, seed, precision="bf16x3")
+    assert np.array_equal(a[1], b[1])
+    ref = orc.estimate(R, 1, m, s, seed)
+    assert abs(a[0].entropy - ref.entropy) <= 1e-3 * ref.entropy
