@@ -49,7 +49,8 @@ typedef enum {
 typedef enum {
   ENT_TAYLOR = 0,
   ENT_CHEBYSHEV = 1,
-  ENT_RANDPROJ = 2
+  ENT_RANDPROJ = 2,
+  ENT_AUTO = 3      /* learned degree / cutoff selector (see ent_selector_load) */
 } ent_method;
 
 /* Arithmetic of the recurrence products R.V.  The power method, the
@@ -105,7 +106,8 @@ typedef struct {
   double u_fixed;        /* > 0: use this u and skip the power method          */
   double cutoff;         /* lower end lo of the Chebyshev interval [lo, u];
                             0 = the paper's [0, u] with the Lemma 3 closed
-                            form; > 0 = interpolant of x ln x on [lo, u]       */
+                            form; > 0 = Chebyshev projection of x ln x on
+                            [lo, u] (1024-node Gauss-Chebyshev rule)         */
   int32_t precision;     /* ent_precision (default ENT_F64)                    */
   int32_t probe_dist;    /* ent_probe_dist (default ENT_RADEMACHER)            */
   int32_t rank_k;        /* Algorithm 3: number of singular values kept        */
@@ -127,6 +129,9 @@ typedef struct {
   int32_t probes;   /* s actually used                                       */
   int32_t method;   /* ent_method actually run                               */
   int32_t precision;
+  int32_t fell_back; /* ENT_AUTO: 1 if the a-posteriori check failed and the
+                        plain schedule was run                                */
+  int32_t products;  /* R.V products of the recurrence (all passes)          */
 } ent_result;
 
 /* Fill *opt with the defaults listed above. */
@@ -177,10 +182,45 @@ ent_status ent_power_method(const ent_matrix *R, int32_t t, int32_t q, uint64_t 
 /*
  * Chebyshev coefficients alpha_0..alpha_m of x ln x on [lo, u], computed in
  * FP64 on the device and copied to alpha (host, m+1 entries).  lo = 0: the
- * closed form of Lemma 3; lo > 0: the interpolant at the m+1 Chebyshev points
- * of [lo, u].  Requires 0 <= lo < u, m >= 1.
+ * closed form of Lemma 3; lo > 0: the projection by the 1024-node
+ * Gauss-Chebyshev rule (2(m+1) nodes beyond degree 511).  Requires
+ * 0 <= lo < u, m >= 1.
  */
 ent_status ent_chebyshev_coeffs(double lo, double u, int32_t m, double *alpha);
+
+/*
+ * Learned degree / lower-cutoff selector (not in the paper; the extension of
+ * the plain schedule of Theorem 2).  A 16-64-64-2 ReLU MLP in FP32 maps 16
+ * features of a cheap sketch -- the power method and a degree-12 Chebyshev
+ * moment pass with 16 Rademacher probes on [0, u] -- to (ln m, log10(lo/u)).
+ *
+ * ent_selector_load: copies the parameters (host, ent_mlp_nparams() floats,
+ *   layout W1[64][16], b1[64], W2[64][64], b2[64], W3[2][64], b3[2]) to the
+ *   current device.
+ * ent_entropy_estimate with method ENT_AUTO: runs the sketch pass, the
+ *   network, then Chebyshev on [lo, u] with the predicted degree.  The
+ *   a-posteriori check requires every moment |d_kj| <= ||g_j||^2 and
+ *   |H(m) - H(m-4)| <= 2.5e-4 |H(m)|; if it fails, the plain schedule on
+ *   [0, u] with the caller's degree is run instead (result.fell_back = 1).
+ *   result.products counts every product of every pass.
+ * ent_selector_features: the sketch pass alone; features[16] (host) and, if
+ *   outputs is non-NULL, the network's two outputs.
+ * ent_mlp_forward / ent_mlp_grad / ent_mlp_train_epoch: the network's
+ *   inference, gradient of the mean squared error L = (1/B) sum (y - t)^2,
+ *   and minibatch Adam (beta1 0.9, beta2 0.999, eps 1e-8) over samples in
+ *   order; all arrays are device pointers (X: count x 16, T and Y: count x 2),
+ *   *step counts Adam steps and is advanced, *loss / *mean_loss are host.
+ */
+int32_t ent_mlp_nparams(void);
+ent_status ent_mlp_forward(const float *params, const float *X, int32_t count, float *Y, void *stream);
+ent_status ent_mlp_grad(const float *params, const float *X, const float *T, int32_t count,
+                        float *grad, double *loss, void *stream);
+ent_status ent_mlp_train_epoch(float *params, float *adam_m, float *adam_v, int32_t *step,
+                               const float *X, const float *T, int32_t count, int32_t batch,
+                               float lr, void *stream, double *mean_loss);
+ent_status ent_selector_load(const float *params, int32_t nparams);
+ent_status ent_selector_features(const ent_matrix *R, uint64_t seed, const ent_options *opt,
+                                 float *features, float *outputs);
 
 /* Parameter rules of the paper (host helpers, no device work). */
 int32_t ent_probes_for(double eps, double delta);              /* ceil(20 ln(2/delta)/eps^2), Lemma 1     */

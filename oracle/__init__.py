@@ -85,6 +85,7 @@ def _load():
         "orc_mlp_forward": (None, [P, i32, P, P]),
         "orc_mlp_loss_grad": (d, [P, i32, P, P, P]),
         "orc_max_threads": (i32, []),
+        "orc_cutoff_nodes": (i32, [i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -197,6 +198,11 @@ def cheb_interp_coeffs(lo: float, u: float, m: int, npts: int = 0) -> np.ndarray
     a = np.empty(m + 1, dtype=np.float64)
     _load().orc_cheb_interp_coeffs(lo, u, m, npts, _ptr(a))
     return a
+
+
+def cutoff_nodes(m: int) -> int:
+    """Quadrature nodes of the estimator's lower-cutoff coefficients."""
+    return _load().orc_cutoff_nodes(m)
 
 
 def cheb_eval_scalar(alpha, lo: float, u: float, x: float) -> float:

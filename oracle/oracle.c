@@ -229,6 +229,11 @@ void orc_cheb_interp_coeffs(double lo, double u, int32_t m, int32_t npts,
   c[0] *= 0.5;
 }
 
+/* Nodes of the lower-cutoff coefficients used by the estimator: a fixed
+ * 1024-point rule (2(m+1) beyond degree 511), so the coefficients of degree
+ * w do not depend on m and partial sums over the degree are nested. */
+int32_t orc_cutoff_nodes(int32_t m) { return (m + 1) <= 512 ? 1024 : 2 * (m + 1); }
+
 /*
  * Scalar Clenshaw (Appendix B): b_k = alpha_k + 2 t b_{k+1} - b_{k+2}, with
  * t = (2x - (u+lo)) / (u - lo) the map of [lo,u] onto [-1,1] (lo = 0 gives
@@ -348,7 +353,8 @@ double orc_taylor_quadform(const orc_matrix *R, double u, int32_t m,
  * u = min{1, c p~1} with p~1 from the power method (t iterations, q trials).
  * If u_override > 0 it replaces the power-method value (used by tests that
  * need the exact interval, e.g. u = p_1).  lo is the lower end of the
- * approximation interval (0 = the paper); lo > 0 uses the interpolant above.
+ * approximation interval (0 = the paper); lo > 0 uses the Chebyshev
+ * projection above with orc_cutoff_nodes(m) nodes.
  * probe_idx selects which probes to evaluate (NULL = 0..s-1); per_probe
  * receives h_j for the selected probes; out->entropy is their mean.
  * Probes are independent, so they run in parallel; the mean is formed in
@@ -366,7 +372,7 @@ int orc_estimate(const orc_matrix *R, int32_t method, int32_t m, int32_t s,
   double *alpha = (double *)malloc(sizeof(double) * (m + 1));
   if (method == 1) {
     if (lo > 0.0)
-      orc_cheb_interp_coeffs(lo, u, m, 0, alpha);
+      orc_cheb_interp_coeffs(lo, u, m, orc_cutoff_nodes(m), alpha);
     else
       orc_cheb_coeffs(u, m, alpha);
   }

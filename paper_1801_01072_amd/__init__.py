@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- enums (mirror include/entropy.h) ---------------------------------------
 OK, EINVAL, ENOTDENSITY, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-TAYLOR, CHEBYSHEV, RANDPROJ = 0, 1, 2
+TAYLOR, CHEBYSHEV, RANDPROJ, AUTO = 0, 1, 2, 3
 F64, F32, BF16X3 = 0, 1, 2
 DENSE, CSR = 0, 1
 STORE_F64, STORE_F32 = 0, 1
@@ -33,7 +33,7 @@ RADEMACHER, GAUSSIAN = 0, 1
 FLAG_SKIP_TRACE_CHECK = 1
 FLAG_AUTOTUNE = 2
 
-_METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ}
+_METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ, "auto": AUTO}
 _PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
 _DISTS = {"rademacher": RADEMACHER, "gaussian": GAUSSIAN}
 
@@ -58,7 +58,8 @@ class EntResult(ctypes.Structure):
     _fields_ = [("entropy", ctypes.c_double), ("std_err", ctypes.c_double),
                 ("p1_est", ctypes.c_double), ("u", ctypes.c_double), ("lo", ctypes.c_double),
                 ("degree", ctypes.c_int32), ("probes", ctypes.c_int32),
-                ("method", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("fell_back", ctypes.c_int32), ("products", ctypes.c_int32)]
 
 
 class EntTiming(ctypes.Structure):
@@ -100,6 +101,15 @@ _SIGNATURES = {
     "ent_graph_tile_rows": (ctypes.c_int32, [_P]),
     "ent_graph_workspace_bytes": (ctypes.c_size_t, [_P]),
     "ent_graph_destroy": (ctypes.c_int, [_P]),
+    "ent_mlp_nparams": (ctypes.c_int32, []),
+    "ent_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
+    "ent_mlp_grad": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "ent_mlp_train_epoch": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_int32), _P, _P,
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_float, _P,
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "ent_selector_load": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ent_selector_features": (ctypes.c_int, [ctypes.POINTER(EntMatrix), ctypes.c_uint64,
+                                             ctypes.POINTER(EntOptions), _P, _P]),
     "ent_timing_enable": (ctypes.c_int, [ctypes.c_int32]),
     "ent_last_timing": (ctypes.c_int, [ctypes.POINTER(EntTiming)]),
     "ent_set_workspace_limit": (ctypes.c_int, [ctypes.c_size_t]),
@@ -141,11 +151,13 @@ class Result:
     probes: int
     method: int
     precision: int
+    fell_back: int = 0
+    products: int = 0
 
 
 def _result(r: EntResult) -> Result:
     return Result(r.entropy, r.std_err, r.p1_est, r.u, r.lo, r.degree, r.probes, r.method,
-                  r.precision)
+                  r.precision, r.fell_back, r.products)
 
 
 # ---- matrices -----------------------------------------------------------------
@@ -291,6 +303,69 @@ def last_timing() -> dict:
     t = EntTiming()
     _check(_lib.ent_last_timing(ctypes.byref(t)))
     return {f: getattr(t, f) for f, _ in EntTiming._fields_}
+
+
+# ---- learned selector ---------------------------------------------------------------
+def mlp_nparams() -> int:
+    return _lib.ent_mlp_nparams()
+
+
+def mlp_forward(params, X, stream=None):
+    """Inference of the selector network on device tensors (X: count x 16 float32)."""
+    import torch
+
+    Y = torch.empty((X.shape[0], 2), dtype=torch.float32, device=X.device)
+    _check(_lib.ent_mlp_forward(params.data_ptr(), X.data_ptr(), X.shape[0], Y.data_ptr(),
+                                _stream_handle(stream)))
+    return Y
+
+
+def mlp_grad(params, X, T, stream=None):
+    """Gradient (device tensor) and value of the mean squared error."""
+    import torch
+
+    g = torch.empty_like(params)
+    loss = ctypes.c_double()
+    _check(_lib.ent_mlp_grad(params.data_ptr(), X.data_ptr(), T.data_ptr(), X.shape[0], g.data_ptr(),
+                             ctypes.byref(loss), _stream_handle(stream)))
+    return g, loss.value
+
+
+class AdamState:
+    """Device-resident parameters and Adam moments of the selector network."""
+
+    def __init__(self, params):
+        import torch
+
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.step = ctypes.c_int32(0)
+
+    def epoch(self, X, T, batch, lr, stream=None) -> float:
+        loss = ctypes.c_double()
+        _check(_lib.ent_mlp_train_epoch(self.params.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                                        ctypes.byref(self.step), X.data_ptr(), T.data_ptr(), X.shape[0],
+                                        batch, lr, _stream_handle(stream), ctypes.byref(loss)))
+        return loss.value
+
+
+def selector_load(params):
+    """Install selector parameters (host numpy float32 array or tensor) on the current device."""
+    a = np.ascontiguousarray(np.asarray(params.detach().cpu() if hasattr(params, "detach") else params,
+                                        dtype=np.float32))
+    _check(_lib.ent_selector_load(a.ctypes.data_as(_P), a.size))
+
+
+def selector_features(R, seed=0, **opts):
+    """Features of R's sketch pass and the loaded network's outputs (needs selector_load)."""
+    M = as_matrix(R)
+    o = options(**opts)
+    f = np.zeros(16, dtype=np.float32)
+    y = np.zeros(2, dtype=np.float32)
+    _check(_lib.ent_selector_features(ctypes.byref(M), seed, ctypes.byref(o), f.ctypes.data_as(_P),
+                                      y.ctypes.data_as(_P)))
+    return f, y
 
 
 # ---- batches ----------------------------------------------------------------------

@@ -264,12 +264,24 @@ int64_t power_blocks(const ent_matrix *R) {
   return R->layout == ENT_DENSE ? ent::power_blocks_dense(R->n) : ent::power_blocks_csr(R->n);
 }
 
+// Optional work appended to an estimate: selector features and MLP inference
+// on the device (feature pass of the learned selector), and a copy of the
+// polynomial coefficients for the host-side a-posteriori check.
+struct SelHook {
+  float *feat_dev = nullptr;      // 16 features
+  const float *params_dev = nullptr;
+  float *y_dev = nullptr;         // 2 outputs
+  float *y_host = nullptr;
+  double *alpha_host = nullptr;   // m + 1 coefficients
+};
+
 // ---------------------------------------------------------------------------
 // One polynomial estimate (Algorithms 1-2) in compute type T.
 // ---------------------------------------------------------------------------
 template <typename T>
 ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, uint64_t seed,
-                    const Opts &op, ent_result *out, double *per_probe, double *moments) {
+                    const Opts &op, ent_result *out, double *per_probe, double *moments,
+                    const SelHook *hook = nullptr) {
   const ent_options &o = op.o;
   hipStream_t st = op.st;
   const int64_t n = R->n;
@@ -423,6 +435,14 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   }
   HIP_TRY(ent::launch_reduce_moments(part, nslot, ntile, ldv, s, d, st));
   HIP_TRY(ent::launch_final(d, scal, method, m, s, h, st));
+  if (hook && hook->feat_dev) {
+    HIP_TRY(ent::launch_selector_features(scal, d, m, s, n, hook->feat_dev, st));
+    HIP_TRY(ent::launch_mlp_forward(hook->params_dev, hook->feat_dev, 1, hook->y_dev, st));
+    HIP_TRY(hipMemcpyAsync(hook->y_host, hook->y_dev, 2 * sizeof(float), hipMemcpyDeviceToHost, st));
+  }
+  if (hook && hook->alpha_host)
+    HIP_TRY(hipMemcpyAsync(hook->alpha_host, scal + ent::S_ALPHA, sizeof(double) * (m + 1),
+                           hipMemcpyDeviceToHost, st));
 
   double hs[16];
   HIP_TRY(hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, st));
@@ -450,6 +470,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   out->probes = s;
   out->method = method;
   out->precision = o.precision;
+  out->fell_back = 0;
+  out->products = (method == ENT_CHEBYSHEV) ? m : m + 1;
   return ENT_OK;
 }
 
@@ -459,7 +481,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
 // split-K BF16 MFMA product plus an elementwise FP32 epilogue.
 // ---------------------------------------------------------------------------
 ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s, uint64_t seed,
-                      const Opts &op, ent_result *out, double *per_probe, double *moments) {
+                      const Opts &op, ent_result *out, double *per_probe, double *moments,
+                      const SelHook *hook = nullptr) {
   const ent_options &o = op.o;
   hipStream_t st = op.st;
   if (R->layout != ENT_DENSE) return fail(ENT_EUNSUPPORTED, "BF16x3 is implemented for dense R only");
@@ -601,6 +624,9 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   pe.steps_end = pe.mark();
   HIP_TRY(ent::launch_reduce_moments(part, nslot, nblk, ldv, s, d, st));
   HIP_TRY(ent::launch_final(d, scal, method, m, s, h, st));
+  if (hook && hook->alpha_host)
+    HIP_TRY(hipMemcpyAsync(hook->alpha_host, scal + ent::S_ALPHA, sizeof(double) * (m + 1),
+                           hipMemcpyDeviceToHost, st));
   double hs[16];
   HIP_TRY(hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, st));
   if (per_probe) HIP_TRY(hipMemcpyAsync(per_probe, h, sizeof(double) * s, hipMemcpyDeviceToHost, st));
@@ -626,9 +652,127 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   out->probes = s;
   out->method = method;
   out->precision = ENT_BF16X3;
+  out->fell_back = 0;
+  out->products = (method == ENT_CHEBYSHEV) ? m : m + 1;
   return ENT_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Learned degree / cutoff selector (ENT_AUTO)
+// ---------------------------------------------------------------------------
+constexpr int32_t kFeatDegree = 12, kFeatProbes = 16;
+
+struct SelectorState {
+  float *params = nullptr;  // device copy of the MLP parameters
+  float *feat = nullptr;    // 16 features
+  float *y = nullptr;       // 2 outputs
+};
+std::mutex g_sel_mu;
+std::map<int, SelectorState> g_sel;
+
+ent_status poly_dispatch(const ent_matrix *R, int32_t method, int32_t m, int32_t s, uint64_t seed,
+                         const Opts &op, ent_result *out, double *per_probe, double *moments,
+                         const SelHook *hook) {
+  switch (op.o.precision) {
+    case ENT_F64: return run_poly<double>(R, method, m, s, seed, op, out, per_probe, moments, hook);
+    case ENT_F32: return run_poly<float>(R, method, m, s, seed, op, out, per_probe, moments, hook);
+    default: return run_bf16x3(R, method, m, s, seed, op, out, per_probe, moments, hook);
+  }
+}
+
+// Maps the network outputs to (m, lo): y0 = ln m*, y1 = log10(lo*/u) with
+// values below -11 meaning lo = 0.  A 25% degree margin and half a decade of
+// cutoff margin are applied.
+void selector_decode(const float y[2], double u, int32_t *m, double *lo) {
+  double md = std::exp((double)y[0]) * 1.25;
+  if (!(md > 4.0)) md = 4.0;
+  if (md > 400.0) md = 400.0;
+  *m = (int32_t)std::ceil(md);
+  const double z = (double)y[1];
+  *lo = (z < -11.0) ? 0.0 : u * std::pow(10.0, std::min(z, 0.0) - 0.5);
+}
+
+// A-posteriori check: every moment bounded by ||g||^2 (the spectrum stayed in
+// [lo, u]) and the partial sums converged: |H(m) - H(m-4)| <= 2.5e-4 |H(m)|.
+bool selector_check(const std::vector<double> &mom, const std::vector<double> &alpha, int32_t m,
+                    int32_t s) {
+  for (int32_t k = 0; k <= m; ++k)
+    for (int32_t j = 0; j < s; ++j)
+      if (!(std::fabs(mom[(size_t)k * s + j]) <= (1.0 + 1e-6) * mom[j])) return false;
+  auto partial = [&](int32_t mm) {
+    double acc = 0.0;
+    for (int32_t j = 0; j < s; ++j) {
+      double v = 0.0;
+      for (int32_t k = 0; k <= mm; ++k) v -= alpha[k] * mom[(size_t)k * s + j];
+      acc += v;
+    }
+    return acc / s;
+  };
+  const double hm = partial(m), h4 = partial(std::max(m - 4, 0));
+  return std::isfinite(hm) && std::fabs(hm - h4) <= 2.5e-4 * std::fabs(hm);
+}
+
+ent_status run_auto(const ent_matrix *R, int32_t m_plain, int32_t s, uint64_t seed, const Opts &op,
+                    ent_result *out, double *per_probe, double *moments) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  SelectorState st;
+  {
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    auto it = g_sel.find(dev);
+    if (it == g_sel.end() || !it->second.params)
+      return fail(ENT_EINVAL, "ENT_AUTO needs a selector: call ent_selector_load first");
+    st = it->second;
+  }
+  // 1. sketch pass: power method + degree-12 Chebyshev moments with 16 probes, FP32
+  Opts fo = op;
+  fo.o.precision = ENT_F32;
+  fo.o.u_fixed = 0.0;
+  fo.o.cutoff = 0.0;
+  fo.o.probe_dist = ENT_RADEMACHER;
+  float y[2] = {0.f, 0.f};
+  SelHook fh;
+  fh.feat_dev = st.feat;
+  fh.params_dev = st.params;
+  fh.y_dev = st.y;
+  fh.y_host = y;
+  ent_result fr{};
+  ent_status rc = run_poly<float>(R, ENT_CHEBYSHEV, kFeatDegree, kFeatProbes, seed ^ 0x5E1EC7ull,
+                                  fo, &fr, nullptr, nullptr, &fh);
+  if (rc != ENT_OK) return rc;
+  int32_t m_hat = 0;
+  double lo = 0.0;
+  selector_decode(y, fr.u, &m_hat, &lo);
+  // 2. main pass on [lo, u] with the predicted degree (power method reused)
+  Opts mo = op;
+  mo.o.u_fixed = fr.u;
+  mo.o.cutoff = lo;
+  std::vector<double> mom((size_t)(m_hat + 1) * s), alpha(m_hat + 1);
+  SelHook mh;
+  mh.alpha_host = alpha.data();
+  ent_result r{};
+  rc = poly_dispatch(R, ENT_CHEBYSHEV, m_hat, s, seed, mo, &r, per_probe, mom.data(), &mh);
+  bool ok = rc == ENT_OK && selector_check(mom, alpha, m_hat, s);
+  int32_t products = kFeatDegree + m_hat;
+  if (ok) {
+    if (moments) std::memcpy(moments, mom.data(), sizeof(double) * mom.size());
+  } else {
+    // 3. fallback: the plain schedule on [0, u] with the caller's degree
+    Opts po = op;
+    po.o.u_fixed = fr.u;
+    po.o.cutoff = 0.0;
+    rc = poly_dispatch(R, ENT_CHEBYSHEV, m_plain, s, seed, po, &r, per_probe, moments, nullptr);
+    if (rc != ENT_OK) return rc;
+    products += m_plain;
+  }
+  r.p1_est = fr.p1_est;
+  r.method = ENT_AUTO;
+  r.fell_back = ok ? 0 : 1;
+  r.products = products;
+  *out = r;
+  return ENT_OK;
+}
 
 // ---------------------------------------------------------------------------
 // Random projection (Algorithm 3): R~ = R Pi on the MFMA product kernels,
@@ -792,6 +936,8 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
   out->probes = s;
   out->method = ENT_RANDPROJ;
   out->precision = prec;
+  out->fell_back = 0;
+  out->products = 1;
   return ENT_OK;
 }
 
@@ -1227,6 +1373,8 @@ ent_status batch_collect(ent_graph_s *g, ent_result *outs) {
     r.probes = g->s;
     r.method = g->method;
     r.precision = g->o.precision;
+    r.fell_back = 0;
+    r.products = (g->method == ENT_CHEBYSHEV) ? g->m : g->m + 1;
   }
   return ENT_OK;
 }
@@ -1264,7 +1412,7 @@ ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int3
     if (rc == ENT_OK) *out = tmp;
     return rc;
   }
-  if (method != ENT_TAYLOR && method != ENT_CHEBYSHEV)
+  if (method != ENT_TAYLOR && method != ENT_CHEBYSHEV && method != ENT_AUTO)
     return fail(ENT_EINVAL, "unknown method %d", method);
   if (degree < 1) return fail(ENT_EINVAL, "degree = %d < 1", degree);
   if (degree > 4000) return fail(ENT_EINVAL, "degree = %d > 4000", degree);
@@ -1272,11 +1420,10 @@ ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int3
   if (method == ENT_TAYLOR && op.o.cutoff > 0)
     return fail(ENT_EINVAL, "cutoff applies to the Chebyshev method only");
   ent_result tmp{};
-  switch (op.o.precision) {
-    case ENT_F64: rc = run_poly<double>(R, method, degree, probes, seed, op, &tmp, per_probe, moments); break;
-    case ENT_F32: rc = run_poly<float>(R, method, degree, probes, seed, op, &tmp, per_probe, moments); break;
-    default: rc = run_bf16x3(R, method, degree, probes, seed, op, &tmp, per_probe, moments); break;
-  }
+  if (method == ENT_AUTO)
+    rc = run_auto(R, degree, probes, seed, op, &tmp, per_probe, moments);
+  else
+    rc = poly_dispatch(R, method, degree, probes, seed, op, &tmp, per_probe, moments, nullptr);
   if (rc == ENT_OK) *out = tmp;
   return rc;
 }
@@ -1454,6 +1601,150 @@ ent_status ent_entropy_estimate_batched(const ent_matrix *Rs, int32_t count, int
   if (rc == ENT_OK) rc = batch_collect(g, outs);
   batch_free(g);
   return rc;
+}
+
+int32_t ent_mlp_nparams(void) { return ent::mlp_nparams(); }
+
+ent_status ent_mlp_forward(const float *params, const float *X, int32_t count, float *Y, void *stream) {
+  g_last_error.clear();
+  if (!params || !X || !Y) return fail(ENT_EINVAL, "NULL argument");
+  if (count < 1) return fail(ENT_EINVAL, "count < 1");
+  HIP_TRY(ent::launch_mlp_forward(params, X, count, Y, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return ENT_OK;
+}
+
+// Gradient of the mean squared error over count samples (device grad).
+ent_status ent_mlp_grad(const float *params, const float *X, const float *T, int32_t count,
+                        float *grad, double *loss, void *stream) {
+  g_last_error.clear();
+  if (!params || !X || !T || !grad || !loss) return fail(ENT_EINVAL, "NULL argument");
+  if (count < 1) return fail(ENT_EINVAL, "count < 1");
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DeviceWorkspace *ws = workspace_for(dev);
+  std::lock_guard<std::mutex> lk(ws->mu);
+  const int32_t nb = ent::mlp_blocks(count);
+  float *gpart = nullptr;
+  double *lpart = nullptr, *ldev = nullptr;
+  Carve cv;
+  cv.add(&gpart, (size_t)nb * ent::mlp_nparams());
+  cv.add(&lpart, (size_t)nb);
+  cv.add(&ldev, 1);
+  ent_status rc = ensure_workspace(ws, cv.total());
+  if (rc != ENT_OK) return rc;
+  cv.assign(ws->ptr);
+  HIP_TRY(ent::launch_mlp_grad(params, X, T, count, gpart, lpart, grad, ldev, st));
+  HIP_TRY(hipMemcpyAsync(loss, ldev, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return ENT_OK;
+}
+
+// One pass of minibatch Adam over the samples in order (the caller shuffles).
+ent_status ent_mlp_train_epoch(float *params, float *adam_m, float *adam_v, int32_t *step,
+                               const float *X, const float *T, int32_t count, int32_t batch,
+                               float lr, void *stream, double *mean_loss) {
+  g_last_error.clear();
+  if (!params || !adam_m || !adam_v || !step || !X || !T || !mean_loss)
+    return fail(ENT_EINVAL, "NULL argument");
+  if (count < 1 || batch < 1) return fail(ENT_EINVAL, "count and batch must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DeviceWorkspace *ws = workspace_for(dev);
+  std::lock_guard<std::mutex> lk(ws->mu);
+  const int32_t nb = ent::mlp_blocks(batch);
+  const int32_t nsteps = (count + batch - 1) / batch;
+  float *gpart = nullptr, *grad = nullptr;
+  double *lpart = nullptr, *losses = nullptr;
+  Carve cv;
+  cv.add(&gpart, (size_t)nb * ent::mlp_nparams());
+  cv.add(&lpart, (size_t)nb);
+  cv.add(&grad, (size_t)ent::mlp_nparams());
+  cv.add(&losses, (size_t)nsteps);
+  ent_status rc = ensure_workspace(ws, cv.total());
+  if (rc != ENT_OK) return rc;
+  cv.assign(ws->ptr);
+  const int64_t nin = 16, nout = 2;
+  for (int32_t b = 0; b < nsteps; ++b) {
+    const int32_t off = b * batch;
+    const int32_t cnt = std::min(batch, count - off);
+    HIP_TRY(ent::launch_mlp_grad(params, X + (int64_t)off * nin, T + (int64_t)off * nout, cnt, gpart,
+                                 lpart, grad, losses + b, st));
+    ++*step;
+    HIP_TRY(ent::launch_adam(params, grad, adam_m, adam_v, *step, lr, st));
+  }
+  std::vector<double> lh(nsteps);
+  HIP_TRY(hipMemcpyAsync(lh.data(), losses, sizeof(double) * nsteps, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double acc = 0.0;
+  for (double v : lh) acc += v;
+  *mean_loss = acc / nsteps;
+  return ENT_OK;
+}
+
+ent_status ent_selector_load(const float *params, int32_t nparams) {
+  g_last_error.clear();
+  if (!params) return fail(ENT_EINVAL, "params is NULL");
+  if (nparams != ent::mlp_nparams())
+    return fail(ENT_EINVAL, "expected %d parameters, got %d", ent::mlp_nparams(), nparams);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  SelectorState &st = g_sel[dev];
+  if (!st.params) {
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(float) * (nparams + 16 + 2 + 14)) != hipSuccess)
+      return fail(ENT_ENOMEM, "selector allocation failed");
+    st.params = (float *)p;
+    st.feat = st.params + nparams;
+    st.y = st.feat + 16;
+  }
+  HIP_TRY(hipMemcpy(st.params, params, sizeof(float) * nparams, hipMemcpyHostToDevice));
+  return ENT_OK;
+}
+
+ent_status ent_selector_features(const ent_matrix *R, uint64_t seed, const ent_options *opt,
+                                 float *features, float *outputs) {
+  g_last_error.clear();
+  ent_status rc = validate_matrix(R);
+  if (rc != ENT_OK) return rc;
+  if (!features) return fail(ENT_EINVAL, "features is NULL");
+  Opts op = resolve_options(opt);
+  rc = validate_options(op.o);
+  if (rc != ENT_OK) return rc;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  SelectorState st;
+  {
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    auto it = g_sel.find(dev);
+    if (it == g_sel.end() || !it->second.params)
+      return fail(ENT_EINVAL, "call ent_selector_load first (the features pass also runs the network)");
+    st = it->second;
+  }
+  Opts fo = op;
+  fo.o.precision = ENT_F32;
+  fo.o.u_fixed = 0.0;
+  fo.o.cutoff = 0.0;
+  fo.o.probe_dist = ENT_RADEMACHER;
+  float y[2];
+  SelHook fh;
+  fh.feat_dev = st.feat;
+  fh.params_dev = st.params;
+  fh.y_dev = st.y;
+  fh.y_host = y;
+  ent_result fr{};
+  rc = run_poly<float>(R, ENT_CHEBYSHEV, kFeatDegree, kFeatProbes, seed ^ 0x5E1EC7ull, fo, &fr,
+                       nullptr, nullptr, &fh);
+  if (rc != ENT_OK) return rc;
+  HIP_TRY(hipMemcpy(features, st.feat, sizeof(float) * 16, hipMemcpyDeviceToHost));
+  if (outputs) {
+    outputs[0] = y[0];
+    outputs[1] = y[1];
+  }
+  return ENT_OK;
 }
 
 ent_status ent_timing_enable(int32_t on) {

@@ -230,6 +230,19 @@ hipError_t launch_gram(const T *X, int64_t si, int64_t sa, int64_t n, int32_t s,
 hipError_t launch_rp_spectrum(const double *G, int32_t s, int32_t k, double *work, double *eig,
                               double *sigma, double *scal, hipStream_t st);
 
+// ---- learned selector (MLP 16-64-64-2, FP32) ----------------------------------
+int32_t mlp_nparams();
+int32_t mlp_blocks(int32_t B);
+hipError_t launch_mlp_forward(const float *P, const float *X, int32_t B, float *Y, hipStream_t st);
+// grad (device, nparams) and *loss (device) of the mean squared error;
+// gpart holds mlp_blocks(B) * nparams floats, lpart mlp_blocks(B) doubles.
+hipError_t launch_mlp_grad(const float *P, const float *X, const float *T, int32_t B, float *gpart,
+                           double *lpart, float *grad, double *loss, hipStream_t st);
+hipError_t launch_adam(float *P, const float *grad, float *m, float *v, int32_t t, float lr,
+                       hipStream_t st);
+hipError_t launch_selector_features(const double *scal, const double *d, int32_t mf, int32_t sf,
+                                    int64_t n, float *feat, hipStream_t st);
+
 // ---- reductions ---------------------------------------------------------------
 // d[k][j] = sum_t part[k][t][j] (fixed order), k < nslot, j < s.
 hipError_t launch_reduce_moments(const double *part, int32_t nslot, int32_t ntile, int64_t ldv,

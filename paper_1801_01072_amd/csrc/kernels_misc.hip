@@ -369,8 +369,10 @@ __device__ __forceinline__ void setup_interval_body(double *__restrict__ scal, i
         a = ((w & 1) ? -u : u) / (dw * dw * dw - dw);
       }
     } else {
-      // interpolant of x ln x at the m+1 Chebyshev points of [lo, u]
-      const int N = m + 1;
+      // Chebyshev projection of x ln x on [lo, u] by an N-point Gauss-Chebyshev
+      // rule, N = 1024 (2(m+1) beyond degree 511): independent of m, so the
+      // partial sums over the degree are nested
+      const int N = (m + 1) <= 512 ? 1024 : 2 * (m + 1);
       double acc = 0.0;
       for (int i = 0; i < N; ++i) {
         const double th = pi * ((double)i + 0.5) / (double)N;

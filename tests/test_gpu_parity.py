@@ -157,7 +157,7 @@ def test_power_method_and_coefficients(orc):
         assert v <= p[0] * (1 + 1e-12)
     for lo in (0.0, 1e-3):
         a = ent.chebyshev_coeffs(lo, 0.3, 40)
-        b = orc.cheb_interp_coeffs(lo, 0.3, 40) if lo > 0 else orc.cheb_coeffs(0.3, 40)
+        b = orc.cheb_interp_coeffs(lo, 0.3, 40, orc.cutoff_nodes(40)) if lo > 0 else orc.cheb_coeffs(0.3, 40)
         assert np.allclose(a, b, rtol=1e-13, atol=1e-17)
 
 

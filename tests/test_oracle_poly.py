@@ -113,3 +113,19 @@ def test_interp_coefficients(orc):
     # lo = 0 with many nodes reproduces the closed form of Lemma 3
     cc = orc.cheb_interp_coeffs(0.0, u, m, 1 << 15)
     assert np.max(np.abs(cc - orc.cheb_coeffs(u, m))) < 1e-12 * u
+
+
+def test_cutoff_coefficients_are_nested_projection(orc):
+    # the estimator's lower-cutoff coefficients do not depend on the degree
+    lo, u = 2e-3, 0.4
+    a20 = orc.cheb_interp_coeffs(lo, u, 20, orc.cutoff_nodes(20))
+    a50 = orc.cheb_interp_coeffs(lo, u, 50, orc.cutoff_nodes(50))
+    assert np.array_equal(a20, a50[:21])
+    # and converge geometrically (x ln x is analytic on [lo, u] for lo > 0)
+    assert abs(a50[50]) < 1e-6 * abs(a50[1])
+    # truncation error on [lo, u] is bounded by the tail of the series (|T_w| <= 1)
+    a200 = orc.cheb_interp_coeffs(lo, u, 200, orc.cutoff_nodes(200))
+    tail = float(np.sum(np.abs(a200[51:])))
+    xs = np.linspace(lo, u, 500)
+    err = max(abs(orc.cheb_eval_scalar(a50, lo, u, x) - x * math.log(x)) for x in xs)
+    assert err <= 1.01 * tail + 1e-15
