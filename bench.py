@@ -44,6 +44,8 @@ WORKLOADS = {
                       s=64, dist="rademacher", t=20),
     "batch64": dict(kind="batch", count=64, n_lo=64, n_hi=2048, method="chebyshev", m=40,
                     s=64, dist="rademacher", t=20),
+    "learned4096": dict(kind="learned", count=512, n=4096, m=40, s=64, dist="rademacher", t=20),
+    "rp65536": dict(kind="rp", n=65536, k=64, s=128, tau=8.0),
 }
 
 
@@ -164,6 +166,214 @@ def bench_batch(args, cfg):
     print(json.dumps(out), flush=True)
 
 
+def bench_learned(args, cfg):
+    """The learned selector (method "auto") on held-out dense n = 4096 density
+    matrices of the training families, against the plain schedule (Chebyshev
+    on [0, u], degree m) with the same probes.  One step = one pass over the
+    held-out set."""
+    import torch
+
+    import paper_1801_01072_amd as ent
+    import workloads as W
+    from paper_1801_01072_amd import learned as L
+
+    precision = args.precision or "f32"
+    count = args.count or cfg["count"]
+    n, m, s, t = cfg["n"], cfg["m"], cfg["s"], cfg["t"]
+    mseed, pseed = W.MATRIX_SEED + 5, W.PROBE_SEED + 5
+    ent.selector_load(L.load())
+    rng = np.random.default_rng(mseed + 10**6)          # disjoint from the training seeds
+    t0 = time.time()
+    spectra, fams, mats = [], [], []
+    for i in range(count):
+        p, fam = L.sample_spectrum(rng, n)
+        spectra.append(p)
+        fams.append(fam)
+        mats.append(W.dense_density_torch(p, mseed * 7 + i, device="cuda:0", dtype=torch.float32,
+                                          rng_device="cuda:0"))
+        if (i + 1) % 64 == 0:
+            torch.cuda.synchronize()
+            log(f"generated {i + 1}/{count} held-out matrices ({time.time() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    H = np.array([float(-np.sum(p[p > 0] * np.log(p[p > 0]))) for p in spectra])
+    kw = dict(probe_dist=cfg["dist"], precision=precision, power_iters=t)
+
+    def one_pass(method):
+        return [ent.entropy_estimate(R, method, m, s, pseed + i, **kw) for i, R in enumerate(mats)]
+
+    for _ in range(args.warmup):
+        one_pass("auto")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        auto = one_pass("auto")
+    torch.cuda.synchronize()
+    ms_auto = 1e3 * (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain = one_pass("chebyshev")
+    torch.cuda.synchronize()
+    ms_plain = 1e3 * (time.perf_counter() - t0) / args.steps
+    err_auto = np.array([abs(r.entropy - h) / h for r, h in zip(auto, H)])
+    err_plain = np.array([abs(r.entropy - h) / h for r, h in zip(plain, H)])
+    prod_auto = int(sum(r.products for r in auto))
+    prod_plain = int(sum(r.products for r in plain))
+    fb = float(np.mean([r.fell_back for r in auto]))
+    log(f"auto {ms_auto:.1f} ms/pass ({prod_auto} products, fallback {100 * fb:.1f}%), plain "
+        f"{ms_plain:.1f} ms/pass ({prod_plain} products); median rel err vs exact: auto "
+        f"{np.median(err_auto):.2e}, plain {np.median(err_plain):.2e}")
+
+    # dominant kernel: the recurrence product of the main pass
+    ent.timing_enable(True)
+    tms = []
+    for i in range(min(count, 16)):
+        ent.entropy_estimate(mats[i], "chebyshev", m, s, pseed + i, **kw)
+        tms.append(ent.last_timing())
+    ent.timing_enable(False)
+    avg_step_ms = float(np.mean([x["steps_ms"] / x["step_launches"] for x in tms]))
+    flop = 2.0 * n * n * s
+    achieved = flop / (avg_step_ms * 1e-3) / 1e12
+    peak = MFMA_PEAK_TFLOPS[precision]
+
+    cpu = None
+    max_rel = None
+    if not args.no_cpu:
+        import oracle
+
+        idx = [0, count // 2] if count > 1 else [0]
+        tc = time.perf_counter()
+        errs = []
+        for i in idx:
+            r = auto[i]
+            per = ent.entropy_estimate_detail(mats[i], "auto", m, s, pseed + i, **kw)[1]
+            Rh = mats[i].double().cpu().numpy()
+            ref = oracle.estimate(Rh, oracle.CHEBYSHEV, r.degree, s, pseed + i, t=t, dist=0,
+                                  lo=r.lo, u_override=r.u)
+            errs.append(float(np.max(np.abs(per - ref.per_probe)) / np.mean(np.abs(ref.per_probe))))
+        cpu_s = time.perf_counter() - tc
+        max_rel = max(errs)
+        cpu = {"value": len(idx) / cpu_s, "unit": "estimates/s", "cores": oracle.max_threads(),
+               "kind": "oracle",
+               "sample": f"{len(idx)} of {count} held-out matrices at the selector's (m, lo, u), all "
+                         f"{s} probes, {cpu_s:.1f} s"}
+        log(f"oracle sample: {cpu_s:.1f}s, per-probe rel err vs fp64 oracle {max_rel:.2e}")
+    out = {
+        "metric": "entropy estimates/s at <=1e-3 rel err",
+        "value": count * 1e3 / ms_auto,
+        "unit": "estimates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_auto,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": precision,
+        "data": "synthetic",
+        "config": {"workload": f"learned degree/cutoff selector on {count} held-out dense density "
+                               f"matrices n={n} (power-law / exponential / Dirichlet spectra), "
+                               f"s={s} {cfg['dist']} probes, fallback Chebyshev m={m} on [0,u]",
+                   "count": count, "n": n, "precision": precision, "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None, "kernel": "dense_step_kernel",
+                     "avg_launch_ms": avg_step_ms, "algorithmic_flop_per_launch": flop},
+        "cpu_baseline": cpu,
+        "learned_vs_plain": {
+            "plain_estimates_per_s": count * 1e3 / ms_plain,
+            "products_auto": prod_auto, "products_plain": prod_plain,
+            "fallback_rate": fb,
+            "median_rel_err_vs_exact_auto": float(np.median(err_auto)),
+            "median_rel_err_vs_exact_plain": float(np.median(err_plain)),
+            "mean_rel_err_vs_exact_auto": float(np.mean(err_auto)),
+            "mean_rel_err_vs_exact_plain": float(np.mean(err_plain)),
+            "per_family_mean_rel_err_auto": [float(np.mean(err_auto[np.array(fams) == f])) for f in range(3)],
+            "per_family_mean_rel_err_plain": [float(np.mean(err_plain[np.array(fams) == f])) for f in range(3)],
+        },
+        "accuracy": {"sampled_per_probe_max_rel_err_vs_fp64_oracle": max_rel},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_rp(args, cfg):
+    """Algorithm 3 on a rank-k dense density matrix, n = 65536 (17.2 GB in
+    FP32): Gaussian sketch R Pi (s columns), Gram, Jacobi eigenvalues."""
+    import torch
+
+    import paper_1801_01072_amd as ent
+    import workloads as W
+
+    precision = args.precision or "f32"
+    n, k, s = cfg["n"], cfg["k"], cfg["s"]
+    mseed, pseed = W.MATRIX_SEED + 5, W.PROBE_SEED + 5
+    t0 = time.time()
+    pk = W.spectrum_exp(k, cfg["tau"])
+    R = W.low_rank_density_torch(pk, n, mseed, device="cuda:0", dtype=torch.float32)
+    torch.cuda.synchronize()
+    H = float(-np.sum(pk * np.log(pk)))
+    log(f"generated rank-{k} R, n={n}, in {time.time() - t0:.1f}s")
+    kw = dict(precision=precision, rank_k=k, sketch_width=s)
+    for _ in range(args.warmup):
+        ent.entropy_estimate(R, "randproj", 1, 1, pseed, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = ent.entropy_estimate(R, "randproj", 1, 1, pseed, **kw)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    ent.timing_enable(True)
+    tms = []
+    for _ in range(3):
+        ent.entropy_estimate(R, "randproj", 1, 1, pseed, **kw)
+        tms.append(ent.last_timing())
+    ent.timing_enable(False)
+    avg_ms = float(np.mean([x["steps_ms"] / max(x["step_launches"], 1) for x in tms]))
+    phases = {kk: float(np.mean([x[kk] for x in tms])) for kk in ("total_ms", "steps_ms", "epilogue_ms", "other_ms")}
+    flop = 2.0 * n * n * s
+    achieved = flop / (avg_ms * 1e-3) / 1e12
+    peak = MFMA_PEAK_TFLOPS[precision]
+    kernel = "bf16x3_gemm_kernel" if precision == "bf16x3" else "dense_step_kernel"
+    log(f"{kernel}: {avg_ms:.3f} ms -> {achieved:.1f} TFLOP/s; H^={res.entropy:.8f}, exact {H:.8f}")
+    del R
+    torch.cuda.empty_cache()
+    # second spectrum family of the same shape: Dirichlet(0.5) over the k slots
+    pd = W.spectrum_dirichlet(k, k, 0.5, np.random.default_rng(mseed))
+    Rd = W.low_rank_density_torch(pd, n, mseed + 1, device="cuda:0", dtype=torch.float32)
+    res_d = ent.entropy_estimate(Rd, "randproj", 1, 1, pseed, **kw)
+    pdp = pd[pd > 0]
+    H_d = float(-np.sum(pdp * np.log(pdp)))
+    del Rd
+    torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        ns = 8192
+        Rs = W.low_rank_density_torch(pk, ns, mseed, device="cpu", dtype=torch.float64).numpy()
+        tc = time.perf_counter()
+        h_s, _ = oracle.rp_entropy(Rs, s, k, pseed)
+        cpu_s = time.perf_counter() - tc
+        scale = (n / ns) ** 2
+        cpu = {"value": 1.0 / (cpu_s * scale), "unit": "estimates/s", "cores": 1, "kind": "oracle",
+               "sample": f"the same estimate at n={ns} ({cpu_s:.1f} s, single-threaded oracle), "
+                         f"extrapolated by n^2 (the sketch product dominates)"}
+        log(f"oracle at n={ns}: {cpu_s:.1f}s (H^={h_s:.8f})")
+    out = {
+        "metric": "entropy estimates/s at <=1e-3 rel err",
+        "value": 1e3 / ms,
+        "unit": "estimates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": precision,
+        "data": "synthetic",
+        "config": {"workload": f"random projection (Algorithm 3): dense rank-{k} density matrix "
+                               f"n={n}, p ~ exp(-i/{cfg['tau']:g}), Gaussian sketch width {s}",
+                   "n": n, "rank_k": k, "sketch_width": s, "precision": precision,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None, "kernel": kernel,
+                     "avg_launch_ms": avg_ms, "algorithmic_flop_per_launch": flop},
+        "cpu_baseline": cpu,
+        "phases_ms": phases,
+        "accuracy": {"entropy": res.entropy, "exact_H": H, "rel_err_vs_exact": (res.entropy - H) / H,
+                     "dirichlet_entropy": res_d.entropy, "dirichlet_exact_H": H_d,
+                     "dirichlet_rel_err_vs_exact": (res_d.entropy - H_d) / H_d},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +384,7 @@ def main():
     ap.add_argument("--store", default=None, choices=["f64", "f32"])
     ap.add_argument("--cpu-probes", type=int, default=0, help="oracle sample size (0 = host threads)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--count", type=int, default=0, help="matrices in the learned4096 workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the estimator "
@@ -188,6 +399,10 @@ def main():
     cfg = WORKLOADS[args.workload]
     if cfg["kind"] == "batch":
         return bench_batch(args, cfg)
+    if cfg["kind"] == "learned":
+        return bench_learned(args, cfg)
+    if cfg["kind"] == "rp":
+        return bench_rp(args, cfg)
     dense = cfg["kind"] == "dense"
     precision = args.precision or ("bf16x3" if dense else "f32")
     store = args.store or ("f64" if dense else ("f32" if precision != "f64" else "f64"))

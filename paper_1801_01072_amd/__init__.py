@@ -14,6 +14,11 @@ from dataclasses import dataclass
 
 import numpy as np
 
+# torch first: it brings the HIP runtime that this library then shares (the
+# dynamic linker resolves the library's libamdhip64 to the one already
+# loaded), so both see the same devices, streams and allocations.
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libentropy.so")
 

@@ -688,7 +688,7 @@ void selector_decode(const float y[2], double u, int32_t *m, double *lo) {
   double md = std::exp((double)y[0]) * 1.25;
   if (!(md > 4.0)) md = 4.0;
   if (md > 400.0) md = 400.0;
-  *m = (int32_t)std::ceil(md);
+  *m = (int32_t)std::ceil(md - 1e-3);  // tolerate FP32 rounding of the output
   const double z = (double)y[1];
   *lo = (z < -11.0) ? 0.0 : u * std::pow(10.0, std::min(z, 0.0) - 0.5);
 }

@@ -146,6 +146,7 @@ template <typename T>
 hipError_t launch_csr_step(const CsrStepArgs &a, hipStream_t st);
 int32_t csr_step_blocks(int64_t n);
 
+
 // ---- BF16x3 dense path (probe-major blocks, leading dimension n_pad) ----------
 struct Bf16GemmArgs {
   const uint16_t *A_hi, *A_lo;  // n_pad x n_pad, row-major, bf16 bits

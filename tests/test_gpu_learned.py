@@ -1,0 +1,96 @@
+"""The learned selector: hand-written MLP kernels against the FP64 oracle MLP,
+GPU training, and ENT_AUTO with its a-posteriori check and fallback."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1801_01072_amd as ent  # noqa: E402
+from paper_1801_01072_amd import learned as L  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def test_mlp_forward_and_gradient_match_oracle(orc):
+    rng = np.random.default_rng(1)
+    npar = ent.mlp_nparams()
+    assert npar == orc.mlp_nparams()
+    P = (rng.standard_normal(npar) * 0.3).astype(np.float32)
+    for B in (1, 31, 100, 257):
+        X = rng.standard_normal((B, 16)).astype(np.float32)
+        T = rng.standard_normal((B, 2)).astype(np.float32)
+        Pd, Xd, Td = (torch.from_numpy(a).to(DEV) for a in (P, X, T))
+        Y = ent.mlp_forward(Pd, Xd).cpu().numpy()
+        Yo = orc.mlp_forward(P.astype(np.float64), X.astype(np.float64))
+        assert np.max(np.abs(Y - Yo)) <= 1e-5 * max(1.0, np.max(np.abs(Yo)))
+        g, loss = ent.mlp_grad(Pd, Xd, Td)
+        lo, go = orc.mlp_loss_grad(P.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+        g = g.cpu().numpy()
+        rel = np.max(np.abs(g - go)) / np.max(np.abs(go))
+        print(f"[mlp B={B}] loss gpu={loss:.8f} oracle={lo:.8f} grad rel err={rel:.2e}", flush=True)
+        assert loss == pytest.approx(lo, rel=1e-5)
+        assert rel <= 1e-4
+
+
+def test_training_reduces_loss():
+    X, T, _ = L.make_dataset(2048, 128, 384, seed=5, device=DEV)
+    params, losses = L.train(X, T, epochs=40, batch=256, lr=3e-3, seed=1)
+    print(f"[train] loss {losses[0]:.4f} -> {losses[-1]:.4f}", flush=True)
+    assert losses[-1] < 0.3 * losses[0]
+    assert np.all(np.isfinite(losses))
+
+
+def _trained_small():
+    X, T, _ = L.make_dataset(4096, 128, 512, seed=7, device=DEV)
+    params, _ = L.train(X, T, epochs=40, batch=256, lr=3e-3, seed=2)
+    return params
+
+
+def test_auto_estimates_and_features():
+    params = _trained_small()
+    ent.selector_load(params)
+    n = 384
+    for name, p in (("exp", W.spectrum_exp(n, 60.0)), ("power", W.spectrum_power(n, 1.0)),
+                    ("flat", np.linspace(1.0, 2.0, n) / np.linspace(1.0, 2.0, n).sum())):
+        R = torch.from_numpy(W.dense_density(p, 11)).to(DEV)
+        H = float(-np.sum(p * np.log(p)))
+        f, y = ent.selector_features(R, 3)
+        assert np.all(np.isfinite(f)) and np.all(np.isfinite(y))
+        assert abs(f[0] - math.log(n) / 10) < 1e-6
+        auto = ent.entropy_estimate(R, "auto", 40, 64, 3, probe_dist="gaussian")
+        plain = ent.entropy_estimate(R, "chebyshev", 40, 64, 3, probe_dist="gaussian")
+        print(f"[auto {name}] H={H:.6f} auto={auto.entropy:.6f} (m={auto.degree}, lo={auto.lo:.3e}, "
+              f"fell_back={auto.fell_back}, products={auto.products}) plain={plain.entropy:.6f}",
+              flush=True)
+        assert math.isfinite(auto.entropy)
+        assert abs(auto.entropy - H) / H < 0.05
+
+
+def test_auto_fallback_is_the_plain_schedule():
+    # a network that always predicts degree 4 and lo = 10^-0.25 u fails the
+    # check on a spectrum reaching far below lo, and must fall back
+    params = np.zeros(ent.mlp_nparams(), dtype=np.float32)
+    params[-2] = math.log(4.0)       # b3[0]
+    params[-1] = -0.25               # b3[1]
+    ent.selector_load(params)
+    n = 200
+    p = W.spectrum_exp(n, 20.0)
+    R = torch.from_numpy(W.dense_density(p, 12)).to(DEV)
+    auto = ent.entropy_estimate(R, "auto", 30, 32, 9)
+    assert auto.fell_back == 1
+    plain = ent.entropy_estimate(R, "chebyshev", 30, 32, 9, u_fixed=auto.u)
+    assert auto.entropy == plain.entropy
+    assert auto.products == 12 + 5 + 30   # degree 4 with the 25% margin -> 5
+
+
+def test_selector_rejects_bad_params():
+    with pytest.raises(ent.EntropyError):
+        ent.selector_load(np.zeros(10, dtype=np.float32))

@@ -31,7 +31,9 @@ def test_randproj_fp64_parity(orc, n, k, s):
     h_ref, sig_ref = orc.rp_entropy(R, s, k, seed)
     print(f"[rp f64 n={n} k={k} s={s}] H gpu={res.entropy:.14f} oracle={h_ref:.14f}", flush=True)
     assert res.entropy == pytest.approx(h_ref, rel=1e-10)
-    assert np.allclose(sig, sig_ref, rtol=1e-9, atol=1e-14 * sig_ref.max())
+    # sigma = sqrt(lambda): an FP64 eigenvalue error ~ eps * lambda_max gives the
+    # small singular values an absolute error ~ 1e-11 sigma_max
+    assert np.allclose(sig, sig_ref, rtol=1e-9, atol=1e-10 * sig_ref.max())
 
 
 @pytest.mark.parametrize("precision", ["f32", "bf16x3"])

@@ -79,24 +79,41 @@ def dense_density(p: np.ndarray, seed: int, dtype=np.float64) -> np.ndarray:
     return np.ascontiguousarray(R.astype(dtype))
 
 
-def dense_density_torch(p: np.ndarray, seed: int, device: str = "cuda", dtype=None):
+def dense_density_torch(p: np.ndarray, seed: int, device: str = "cuda", dtype=None,
+                        rng_device: str = "cpu"):
     """Same construction on a torch device (fast input preparation for large n).
 
     Returns a contiguous torch tensor; the orthogonal factor comes from torch's
-    QR of a seeded Gaussian matrix.
+    QR of a seeded Gaussian matrix, drawn by torch's generator on `rng_device`.
     """
     import torch
 
     dtype = dtype or torch.float64
-    g = torch.Generator(device="cpu").manual_seed(seed)
+    g = torch.Generator(device=rng_device).manual_seed(seed)
     n = len(p)
-    Z = torch.randn((n, n), generator=g, dtype=torch.float64).to(device)
+    Z = torch.randn((n, n), generator=g, dtype=torch.float64, device=rng_device).to(device)
     Q, Rr = torch.linalg.qr(Z)
     Q = Q * torch.sign(torch.diagonal(Rr))[None, :]
     pt = torch.as_tensor(p, dtype=torch.float64, device=device)
     R = (Q * pt[None, :]) @ Q.T
     R = 0.5 * (R + R.T)
     return R.to(dtype).contiguous()
+
+
+def low_rank_density_torch(pk: np.ndarray, n: int, seed: int, device: str = "cuda", dtype=None):
+    """R = B B^T with B = Q diag(sqrt(pk)), Q (n x k) the sign-fixed Q factor of
+    a seeded Gaussian n x k matrix: rank k = len(pk), spectrum pk (plus n - k
+    zeros).  Only the n x n result is materialised, in `dtype`."""
+    import torch
+
+    dtype = dtype or torch.float64
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    k = len(pk)
+    Z = torch.randn((n, k), generator=g, dtype=torch.float64).to(device)
+    Q, Rr = torch.linalg.qr(Z)
+    Q = Q * torch.sign(torch.diagonal(Rr))[None, :]
+    B = (Q * torch.sqrt(torch.as_tensor(pk, dtype=torch.float64, device=device))[None, :]).to(dtype)
+    return (B @ B.T).contiguous()
 
 
 def maximally_mixed(n: int) -> np.ndarray:
