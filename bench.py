@@ -46,6 +46,9 @@ WORKLOADS = {
                     s=64, dist="rademacher", t=20),
     "learned4096": dict(kind="learned", count=512, n=4096, m=40, s=64, dist="rademacher", t=20),
     "rp65536": dict(kind="rp", n=65536, k=64, s=128, tau=8.0),
+    # plain device-to-device copy of 1 GiB: the achievable HBM rate, and the
+    # reference that scales the hardware byte counters of the other kernels
+    "copy1g": dict(kind="copy", nbytes=1 << 30),
 }
 
 
@@ -374,6 +377,31 @@ def bench_rp(args, cfg):
     print(json.dumps(out), flush=True)
 
 
+def bench_copy(args, cfg):
+    import torch
+
+    nb = cfg["nbytes"]
+    src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    gbs = 2 * nb / (ms * 1e-3) / 1e9
+    print(json.dumps({"metric": "device copy GB/s (read + write)", "value": gbs, "unit": "GB/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"device copy of {nb} bytes", "bytes": nb},
+                      "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+                      "cpu_baseline": None}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,6 +431,8 @@ def main():
         return bench_learned(args, cfg)
     if cfg["kind"] == "rp":
         return bench_rp(args, cfg)
+    if cfg["kind"] == "copy":
+        return bench_copy(args, cfg)
     dense = cfg["kind"] == "dense"
     precision = args.precision or ("bf16x3" if dense else "f32")
     store = args.store or ("f64" if dense else ("f32" if precision != "f64" else "f64"))

@@ -297,7 +297,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   const int bn = dense ? (s <= 64 ? 64 : (s <= 128 ? 128 : 64)) : 64;
   const int64_t ldv = round_up(s, dense ? bn : 64);
   const int64_t n_pad = round_up(n, 64);
-  const int32_t ntile = dense ? (int32_t)(n_pad / 64) : ent::csr_step_blocks(n);
+  const int32_t ntile = dense ? (int32_t)(n_pad / 64) : ent::csr_step_blocks(n, sizeof(T) == 8);
   const int32_t nslot = m + 1;
   const bool rad = o.probe_dist == ENT_RADEMACHER;
   const bool use_power = !(o.u_fixed > 0);
@@ -312,8 +312,11 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   double *part = nullptr, *d = nullptr, *h = nullptr;
   T *Rc = nullptr, *G = nullptr, *VA = nullptr, *VB = nullptr;
   uint32_t *signs = nullptr;
+  int2 *cwin = nullptr;
+  const int32_t ch = ent::csr_chunk_rows(sizeof(T) == 8);
   Carve cv;
   cv.add(&scal, kScalarDoubles);
+  if (!dense) cv.add(&cwin, (size_t)((n + ch - 1) / ch));
   if (use_power) {
     cv.add(&x0, n_pad);
     cv.add(&x1, n_pad);
@@ -368,6 +371,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     Rt = Rc;
     ldr = ldc;
   }
+  if (!dense) HIP_TRY(ent::launch_csr_chunk_window(R->row_ptr, R->col_idx, n, ch, cwin, st));
   // probes
   if (dense || !rad)
     HIP_TRY(ent::launch_probe_gen<T>(G, nullptr, n, n_pad, s, ldv, seed, o.probe_dist, st));
@@ -422,7 +426,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
       a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr;
       a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
       a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
-      a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nblk = ntile;
+      a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nblk = ntile; a.win = cwin;
       HIP_TRY(ent::launch_csr_step<T>(a, st));
     }
     // Chebyshev: V_{k+1} is written over V_{k-1} (same element, same thread),

@@ -59,6 +59,7 @@ struct CsrStepArgs {
   int32_t slot_gg;
   double *part;
   int32_t nblk;         // persistent grid size (partial stride)
+  const int2 *win;      // column window per row chunk (launch_csr_chunk_window)
 };
 
 // Per-matrix descriptor of a batch (device resident).  Offsets are in
@@ -144,7 +145,12 @@ template <typename T>
 hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st);
 template <typename T>
 hipError_t launch_csr_step(const CsrStepArgs &a, hipStream_t st);
-int32_t csr_step_blocks(int64_t n);
+int32_t csr_step_blocks(int64_t n, int32_t fp64);
+// Rows per chunk of the CSR step (FP64 or FP32 compute), and the column
+// window (min, max) of every chunk, computed once per estimate.
+int32_t csr_chunk_rows(int32_t fp64);
+hipError_t launch_csr_chunk_window(const int64_t *rp, const int32_t *ci, int64_t n, int32_t ch,
+                                   int2 *win, hipStream_t st);
 
 
 // ---- BF16x3 dense path (probe-major blocks, leading dimension n_pad) ----------

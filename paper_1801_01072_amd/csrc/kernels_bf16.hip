@@ -102,113 +102,152 @@ hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, i
 
 // ---------------------------------------------------------------------------
 // GEMM: part_y[ks][j][i] = sum_{k in split ks} (A_hi V_hi + A_hi V_lo + A_lo V_hi)[i][j]
+//
+// Workgroup tile: 128 rows x BN probes over one K-split, 4 waves in a 2 x 2
+// grid (64 rows x BN/2 probes each).  Operands reach LDS by direct
+// global-to-LDS loads (no registers) in a 3-stage ring of BK = 32: stage t+2
+// is in flight while stage t is computed.  LDS holds every operand in the
+// MFMA's own fragment order: a fragment (32 rows or probes x 16 k, hi or lo)
+// is 1 KB with lane l's 8 k-values at byte 16 l, so the loads that fill it
+// and the ds_read_b128 that consume it are both contiguous per wave.
 // ---------------------------------------------------------------------------
+namespace {
+constexpr int kBK = 32;              // k per stage
+constexpr int kKS = kBK / 16;        // MFMA k-steps per stage
+constexpr int kStages = 3;
+constexpr int kFragA = 2 * 4 * kKS;  // (hi/lo, row block, k-step) fragments of A per stage
+}  // namespace
+
+template <int BN>
+struct GemmShape {
+  static constexpr int NCB = BN / 32;                  // probe blocks of the tile
+  static constexpr int WCB = NCB / 2;                  // probe blocks per wave
+  static constexpr int FB = 2 * NCB * kKS;             // B fragments per stage
+  static constexpr int FST = kFragA + FB;              // fragments per stage
+  static constexpr int PER_WAVE = FST / 4;             // loads per wave per stage
+  static constexpr int LDS_BYTES = kStages * FST * 1024;
+};
+
+// s_waitcnt vmcnt(N) in the gfx9 encoding, expcnt and lgkmcnt left free.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 16, "vmcnt immediate");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
+
 template <int BN>
 __global__ __launch_bounds__(256) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
-  constexpr int BK = 32;              // two MFMA k-steps per chunk
-  constexpr int LDK = BK + 8;         // padded LDS row (bf16 elements): 80 bytes
-  constexpr int NSUB = BN / 32;
-  constexpr int PIECES = BN * BK * 2 / 8 / 256;  // 8-element (16 B) pieces per thread (hi+lo)
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDK];  // [hi/lo][col][k]
+  typedef GemmShape<BN> S;
+  static_assert(S::FST % 4 == 0, "fragments must split evenly over 4 waves");
+  __shared__ __attribute__((aligned(1024))) uint8_t lds[S::LDS_BYTES];
 
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = w & 1, wc = w >> 1;
   const int nrt = (int)(a.n_pad / 128);
   const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-  // tile order: row tile fastest, then K-split, then column tile, so the
-  // workgroups of one XCD share the V^T slice of their split in L2
+  // tile order: row tile fastest, then K-split, then probe tile
   const int rt = b % nrt;
-  const int ks = (b / nrt) % a.splits;
+  const int ksp = (b / nrt) % a.splits;
   const int ct = b / (nrt * a.splits);
   const int64_t npad = a.n_pad;
-  const int64_t kbeg = (int64_t)ks * a.k_per_split;
-  const int64_t kend = kbeg + a.k_per_split;
-  const int64_t col0 = (int64_t)ct * BN;
+  const int64_t kbeg = (int64_t)ksp * a.k_per_split;
+  const int nst = (int)(a.k_per_split / kBK);
+  const int64_t row0 = (int64_t)rt * 128, col0 = (int64_t)ct * BN;
   const int m32 = lane & 31, kh = lane >> 5;
-  const int64_t arow = (int64_t)rt * 128 + 32 * w + m32;
-  const uint16_t *__restrict__ Ahi = a.A_hi + arow * npad;
-  const uint16_t *__restrict__ Alo = a.A_lo + arow * npad;
 
-  f32x16 acc[NSUB];
+  // per-lane source of each fragment this wave loads (advanced by kBK per stage)
+  const uint16_t *src[S::PER_WAVE];
 #pragma unroll
-  for (int c = 0; c < NSUB; ++c)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[c][r] = 0.f;
-
-  u16x8 vreg[PIECES];
-  u16x8 ahi[2], alo[2];
-  auto load_b = [&](int64_t kc) {
-#pragma unroll
-    for (int p = 0; p < PIECES; ++p) {
-      const int idx = tid + p * 256;          // over [hl][col][k/8]
-      const int hl = idx / (BN * 4);
-      const int rem = idx % (BN * 4);
-      const int col = rem / 4, kq = rem % 4;
-      const uint16_t *src = (hl ? a.V_lo : a.V_hi) + (col0 + col) * npad + kc + kq * 8;
-      vreg[p] = *(const u16x8 *)src;
+  for (int i = 0; i < S::PER_WAVE; ++i) {
+    const int f = w + 4 * i;
+    const uint16_t *p;
+    if (f < kFragA) {
+      const int hl = f / (4 * kKS), rb = (f / kKS) % 4, ks = f % kKS;
+      p = (hl ? a.A_lo : a.A_hi) + (row0 + 32 * rb + m32) * npad + 16 * ks + 8 * kh;
+    } else {
+      const int g = f - kFragA;
+      const int hl = g / (S::NCB * kKS), cb = (g / kKS) % S::NCB, ks = g % kKS;
+      p = (hl ? a.V_lo : a.V_hi) + (col0 + 32 * cb + m32) * npad + 16 * ks + 8 * kh;
     }
-  };
-  auto store_b = [&]() {
+    src[i] = p + kbeg;
+  }
+  auto issue = [&](int t) {
+    uint8_t *base = lds + (t % kStages) * S::FST * 1024;
 #pragma unroll
-    for (int p = 0; p < PIECES; ++p) {
-      const int idx = tid + p * 256;
-      const int hl = idx / (BN * 4);
-      const int rem = idx % (BN * 4);
-      const int col = rem / 4, kq = rem % 4;
-      *(u16x8 *)(&Bs[hl][col * LDK + kq * 8]) = vreg[p];
-    }
-  };
-  auto load_a = [&](int64_t kc) {
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {
-      ahi[s2] = *(const u16x8 *)(Ahi + kc + 16 * s2 + 8 * kh);
-      alo[s2] = *(const u16x8 *)(Alo + kc + 16 * s2 + 8 * kh);
-    }
+    for (int i = 0; i < S::PER_WAVE; ++i)
+      __builtin_amdgcn_global_load_lds((const void *)(src[i] + (int64_t)t * kBK),
+                                       (__attribute__((address_space(3))) void *)(base + (w + 4 * i) * 1024),
+                                       16, 0, 0);
   };
 
-  load_b(kbeg);
-  load_a(kbeg);
-  for (int64_t kc = kbeg; kc < kend; kc += BK) {
-    store_b();
-    u16x8 ch[2] = {ahi[0], ahi[1]}, cl[2] = {alo[0], alo[1]};
-    __syncthreads();
-    if (kc + BK < kend) {
-      load_b(kc + BK);
-      load_a(kc + BK);
-    }
+  f32x16 acc[2][S::WCB];
 #pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const bf16x8 a_h = __builtin_bit_cast(bf16x8, ch[s2]);
-      const bf16x8 a_l = __builtin_bit_cast(bf16x8, cl[s2]);
-      bf16x8 b_h[NSUB], b_l[NSUB];
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int c = 0; c < NSUB; ++c) {
-        const int off = (32 * c + m32) * LDK + 16 * s2 + 8 * kh;
-        b_h[c] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(&Bs[0][off]));
-        b_l[c] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(&Bs[1][off]));
+    for (int c = 0; c < S::WCB; ++c)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[r][c][e] = 0.f;
+
+  issue(0);
+  if (nst > 1) issue(1);
+  for (int t = 0; t < nst; ++t) {
+    // this wave's loads of stage t are done once at most those of stage t+1
+    // remain; the barrier then makes every wave's part visible, and also
+    // guarantees that stage t-1 (whose buffer stage t+2 reuses) is consumed
+    if (t + 1 < nst)
+      wait_vm<S::PER_WAVE>();
+    else
+      wait_vm<0>();
+    __builtin_amdgcn_s_barrier();
+    if (t + 2 < nst) issue(t + 2);
+    const uint8_t *base = lds + (t % kStages) * S::FST * 1024 + 16 * lane;
+#pragma unroll
+    for (int ks = 0; ks < kKS; ++ks) {
+      bf16x8 ah[2], al[2], bh[S::WCB], bl[S::WCB];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int rb = 2 * wr + r;
+        ah[r] = *(const bf16x8 *)(base + ((0 * 4 + rb) * kKS + ks) * 1024);
+        al[r] = *(const bf16x8 *)(base + ((1 * 4 + rb) * kKS + ks) * 1024);
       }
 #pragma unroll
-      for (int c = 0; c < NSUB; ++c)
-        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h[c], acc[c], 0, 0, 0);
+      for (int c = 0; c < S::WCB; ++c) {
+        const int cb = S::WCB * wc + c;
+        bh[c] = *(const bf16x8 *)(base + (kFragA + (0 * S::NCB + cb) * kKS + ks) * 1024);
+        bl[c] = *(const bf16x8 *)(base + (kFragA + (1 * S::NCB + cb) * kKS + ks) * 1024);
+      }
 #pragma unroll
-      for (int c = 0; c < NSUB; ++c)
-        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l[c], acc[c], 0, 0, 0);
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int c = 0; c < NSUB; ++c)
-        acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h[c], acc[c], 0, 0, 0);
+        for (int c = 0; c < S::WCB; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[r], bh[c], acc[r][c], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < S::WCB; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[r], bl[c], acc[r][c], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < S::WCB; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[r], bh[c], acc[r][c], 0, 0, 0);
     }
-    __syncthreads();
   }
 
-  // partial tile -> part_y[ks][col][row], 4 consecutive rows per store
-  float *__restrict__ out = a.part_y + (int64_t)ks * a.ldv * npad;
-  const int64_t rbase = (int64_t)rt * 128 + 32 * w + 4 * kh;
+  // partial tile -> part_y[ksp][col][row], 4 consecutive rows per store
+  float *__restrict__ out = a.part_y + (int64_t)ksp * a.ldv * npad;
 #pragma unroll
-  for (int c = 0; c < NSUB; ++c) {
-    const int64_t col = col0 + 32 * c + m32;
+  for (int r = 0; r < 2; ++r) {
+    const int64_t rbase = row0 + 32 * (2 * wr + r) + 4 * kh;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      f32x4 v = {acc[c][4 * g], acc[c][4 * g + 1], acc[c][4 * g + 2], acc[c][4 * g + 3]};
-      *(f32x4 *)(out + col * npad + rbase + 8 * g) = v;
+    for (int c = 0; c < S::WCB; ++c) {
+      const int64_t col = col0 + 32 * (S::WCB * wc + c) + m32;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        f32x4 v = {acc[r][c][4 * g], acc[r][c][4 * g + 1], acc[r][c][4 * g + 2], acc[r][c][4 * g + 3]};
+        *(f32x4 *)(out + col * npad + rbase + 8 * g) = v;
+      }
     }
   }
 }

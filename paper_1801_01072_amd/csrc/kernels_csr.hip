@@ -2,14 +2,22 @@
 // R, bandwidth bound: Y = a * (R V_k), Z = c1*Y + c2*b*V_k + cw*V_{k-1},
 // per-probe dots with g (same algebra as the dense step).
 //
-// Mapping: lane = probe (64 probes per wave, one 64-probe chunk per grid
-// column), so every V row access is one coalesced 256 B (FP32) or 512 B
-// (FP64) transaction.  A workgroup owns a contiguous range of rows and its
-// waves take interleaved rows of it, so at any time they gather from the same
-// few dozen V_k rows of a banded R, which stay in the CU's vector L1.  The
-// row's column indices and values are wave-uniform and come through the
-// scalar cache, kCsrUnroll at a time, and the V_k gathers of such a group are
-// independent of each other, so a wave keeps that many loads in flight.
+// Mapping: a row is handled by a group of L lanes, each owning P consecutive
+// probes of a 64-probe chunk (P = 8, L = 8 in FP32; P = 4, L = 16 in FP64:
+// 32 bytes per lane), so a wave works on 64 / L rows at once and every V row
+// access is one contiguous 256 B (FP32) or 512 B (FP64) segment per row.
+//
+// A workgroup walks a contiguous range of row chunks (CH = rows per wave x
+// waves).  The V_k rows a chunk's columns span (its window, found once per
+// estimate by csr_chunk_window_kernel) are copied into LDS by direct
+// global-to-LDS loads, double buffered: the next chunk's window is in flight
+// while the current chunk gathers from LDS, which has twice the bandwidth of
+// the vector L1 that per-entry gathers from global memory would saturate.
+// A chunk whose window is wider than the buffer gathers from global memory
+// instead, so any CSR matrix is accepted.  The row's column indices and
+// values are loaded once by the lanes of its group (one entry per lane) and
+// passed to the group by lane shuffles; the results of a chunk are stored
+// after the next chunk's barrier, so that barrier does not wait on them.
 // Per-probe dot partials stay in registers until the end (one partial per
 // block per probe: deterministic, fixed order).
 // Rademacher probes are read as packed sign bits; when V_k or V_{k-1} is the
@@ -19,41 +27,129 @@
 
 namespace ent {
 
-template <typename T>
-__device__ __forceinline__ T sign_of(const uint32_t *__restrict__ signs, int64_t row, int32_t nw,
-                                     int32_t probe) {
-  const uint32_t wd = signs[row * nw + (probe >> 5)];
-  return ((wd >> (probe & 31)) & 1u) ? T(-1) : T(1);
-}
-
-// The CSR arrays are read through the constant address space: nothing
-// writes them while the kernel runs, and their wave-uniform loads (row
-// offsets, a group's columns and values) then go through the scalar cache as
-// wide scalar loads.
-template <typename T>
-using ConstPtr = __attribute__((address_space(4))) const T *;
-
 namespace {
-constexpr int kCsrWaves = 8;        // waves per workgroup
-constexpr int kCsrBlocksPerCU = 2;  // resident workgroups per CU (256 CUs)
-constexpr int kCsrUnroll = 8;       // independent V_k gathers in flight per wave
+constexpr int kCsrWaves = 4;  // waves per workgroup
 }  // namespace
 
-template <typename T, bool VK_SIGNS, bool VM1_SIGNS>
+template <typename T>
+struct CsrLanes {
+  static constexpr int P = 32 / (int)sizeof(T);    // probes per lane (32 bytes)
+  static constexpr int L = 64 / P;                 // lanes per row
+  static constexpr int RPW = 64 / L;               // rows per wave
+  static constexpr int CH = RPW * kCsrWaves;       // rows per chunk
+  static constexpr int ROWB = 64 * (int)sizeof(T); // bytes of one V row chunk
+  static constexpr int WROWS = 64;                 // window capacity in rows
+  static constexpr int WBYTES = WROWS * ROWB;      // one window buffer
+  // resident workgroups per CU (LDS: two window buffers each; 256 CUs)
+  static constexpr int BLOCKS_PER_CU = sizeof(T) == 4 ? 4 : 2;
+};
+
+int32_t csr_chunk_rows(int32_t fp64) { return fp64 ? CsrLanes<double>::CH : CsrLanes<float>::CH; }
+
+// Column window of every chunk of ch rows: win[c] = (min, max) over the
+// chunk's column indices and its own rows.  One wave per chunk.
+__global__ __launch_bounds__(256) void csr_chunk_window_kernel(const int64_t *__restrict__ rp,
+                                                               const int32_t *__restrict__ ci,
+                                                               int64_t n, int32_t ch,
+                                                               int2 *__restrict__ win) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nch = (n + ch - 1) / ch;
+  for (int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < nch; c += (int64_t)gridDim.x * 4) {
+    const int64_t r_lo = c * ch;
+    const int64_t r_hi = r_lo + ch < n ? r_lo + ch : n;
+    int32_t cmin = (int32_t)r_lo, cmax = (int32_t)(r_hi - 1);
+    for (int64_t e = rp[r_lo] + lane; e < rp[r_hi]; e += 64) {
+      const int32_t col = ci[e];
+      cmin = col < cmin ? col : cmin;
+      cmax = col > cmax ? col : cmax;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const int32_t o1 = __shfl_xor(cmin, off, 64), o2 = __shfl_xor(cmax, off, 64);
+      cmin = o1 < cmin ? o1 : cmin;
+      cmax = o2 > cmax ? o2 : cmax;
+    }
+    if (lane == 0) win[c] = make_int2(cmin, cmax);
+  }
+}
+
+hipError_t launch_csr_chunk_window(const int64_t *rp, const int32_t *ci, int64_t n, int32_t ch,
+                                   int2 *win, hipStream_t st) {
+  const int64_t nch = (n + ch - 1) / ch;
+  const int64_t blocks = (nch + 3) / 4 < 4096 ? (nch + 3) / 4 : 4096;
+  csr_chunk_window_kernel<<<(unsigned)blocks, 256, 0, st>>>(rp, ci, n, ch, win);
+  return hipGetLastError();
+}
+
+// P consecutive probes p0..p0+P-1 of row r (p0 a multiple of P).
+template <typename T, bool SIGNS>
+__device__ __forceinline__ void load_row(const T *__restrict__ V, const uint32_t *__restrict__ signs,
+                                         int64_t r, int64_t ldv, int32_t nw, int32_t p0, T *x) {
+  constexpr int P = CsrLanes<T>::P;
+  if (SIGNS) {
+    const uint32_t wd = signs[r * nw + (p0 >> 5)] >> (p0 & 31);
+#pragma unroll
+    for (int e = 0; e < P; ++e) x[e] = ((wd >> e) & 1u) ? T(-1) : T(1);
+  } else {
+    typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int VE = 16 / (int)sizeof(T);
+    const v16 *src = (const v16 *)(V + r * ldv + p0);
+#pragma unroll
+    for (int h = 0; h < P / VE; ++h) {
+      const v16 q = src[h];
+#pragma unroll
+      for (int e = 0; e < VE; ++e) x[h * VE + e] = q[e];
+    }
+  }
+}
+
+// The same P probes from a window row in LDS.
+template <typename T>
+__device__ __forceinline__ void lds_row(const uint8_t *row, T *x) {
+  constexpr int P = CsrLanes<T>::P;
+  typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int VE = 16 / (int)sizeof(T);
+  const v16 *src = (const v16 *)row;
+#pragma unroll
+  for (int h = 0; h < P / VE; ++h) {
+    const v16 q = src[h];
+#pragma unroll
+    for (int e = 0; e < VE; ++e) x[h * VE + e] = q[e];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_t(T v, int src) {
+  return __shfl(v, src, 64);
+}
+
+// VK_SIGNS: V_k is the sign block.  M1: no V_{k-1} term (0), V_{k-1} stored
+// (1) or the sign block (2).  GG: also accumulate g.g (first Chebyshev step).
+template <typename T, bool VK_SIGNS, int M1, bool GG>
 __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a) {
+  typedef CsrLanes<T> C;
+  constexpr int P = C::P, L = C::L, RPW = C::RPW, CH = C::CH, ROWB = C::ROWB;
+  constexpr int U = 4;    // entries per gather round
+  constexpr int JM = 10;  // rounds whose entries are loaded together
+  constexpr bool use_win = !VK_SIGNS;  // a window of the sign block is not needed
+  __shared__ __attribute__((aligned(16))) uint8_t wbuf[use_win ? 2 : 1][use_win ? C::WBYTES : 16];
   __shared__ double red[2][kCsrWaves][64];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane / L;       // row of the wave's group
+  const int o = lane % L;       // probe slot within the row
+  const int gl = g * L;         // first lane of the row's group
   const int64_t n = a.n, ldv = a.ldv;
   const int32_t nw = (int32_t)(ldv >> 5);
-  const int32_t probe = (int32_t)blockIdx.y * 64 + lane;
-  const ConstPtr<int64_t> rp = (ConstPtr<int64_t>)a.row_ptr;
-  const ConstPtr<int32_t> ci = (ConstPtr<int32_t>)a.col_idx;
-  const ConstPtr<T> vals = (ConstPtr<T>)a.values;
-  auto val = [&](int64_t e) -> T { return vals[e]; };
+  const int32_t chunk0 = (int32_t)blockIdx.y * 64;
+  const int32_t p0 = chunk0 + P * o;
+  const int64_t *__restrict__ rp = a.row_ptr;
+  const int32_t *__restrict__ ci = a.col_idx;
+  const T *__restrict__ val = (const T *)a.values;
   const T *__restrict__ Vk = (const T *)a.Vk;
   const T *__restrict__ G = (const T *)a.G;
   const uint32_t *__restrict__ signs = a.signs;
+  const int2 *__restrict__ win = a.win;
   // V_{k+1} is written over V_{k-1} element by element by the thread that
   // read it, so these two may alias each other (and nothing else)
   const T *Vkm1 = (const T *)a.Vkm1;
@@ -61,61 +157,195 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
   const T ta = (T)a.scal[S_A];
   const T tb = (T)(a.c2 * a.scal[S_B]);
   const T tc1 = (T)a.c1, tcw = (T)a.cw;
-  const bool use_m1 = a.cw != 0.0;
-  const bool want_gg = a.slot_gg >= 0;
+  constexpr bool use_m1 = M1 != 0;
 
-  auto xglob = [&](int64_t r) -> T {
-    if (VK_SIGNS) return sign_of<T>(signs, r, nw, probe);
-    return Vk[r * ldv + probe];
+  // contiguous chunk range per block
+  const int64_t nch = (n + CH - 1) / CH;
+  const int64_t cper = (nch + gridDim.x - 1) / gridDim.x;
+  const int64_t c_beg = (int64_t)blockIdx.x * cper;
+  const int64_t c_end = c_beg + cper < nch ? c_beg + cper : nch;
+  const int64_t r_lim = c_end * CH < n ? c_end * CH : n;
+
+  // direct global-to-LDS copy of chunk c's window (if it fits) into buffer b
+  auto stage = [&](int64_t c, int b) {
+    const int2 mw = win[c];
+    const int nrows = mw.y - mw.x + 1;
+    if (nrows > C::WROWS) return;
+    const int ninstr = (nrows * ROWB + 1023) / 1024;
+    for (int i = w; i < ninstr; i += kCsrWaves) {
+      const int byte = i * 1024 + lane * 16;
+      int64_t row = mw.x + byte / ROWB;
+      row = row < mw.y ? row : mw.y;
+      const uint8_t *src = (const uint8_t *)(Vk + row * ldv + chunk0) + byte % ROWB;
+      __builtin_amdgcn_global_load_lds((const void *)src,
+                                       (__attribute__((address_space(3))) void *)(&wbuf[b][0] + i * 1024),
+                                       16, 0, 0);
+    }
   };
 
-  // contiguous row range per block, a multiple of the wave count
-  const int64_t per0 = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t per = (per0 + kCsrWaves - 1) / kCsrWaves * kCsrWaves;
-  const int64_t r_beg = (int64_t)blockIdx.x * per;
-  const int64_t r_end = r_beg + per < n ? r_beg + per : n;
-  double ds = 0.0, gs = 0.0;
-  for (int64_t r = r_beg + w; r < r_end; r += kCsrWaves) {
-    // epilogue operands first: independent of the gathers
-    const T xr = xglob(r);
-    T vm = T(0);
-    if (use_m1) vm = VM1_SIGNS ? sign_of<T>(signs, r, nw, probe) : Vkm1[r * ldv + probe];
-    const T gv = signs ? sign_of<T>(signs, r, nw, probe) : G[r * ldv + probe];
-    const int64_t e0 = rp[r], e1 = rp[r + 1];
-    T acc0 = T(0), acc1 = T(0);
-    // groups of kCsrUnroll entries: one scalar load of their columns and
-    // values, then kCsrUnroll independent V_k gathers
-    int64_t e = e0;
-    for (; e + kCsrUnroll <= e1; e += kCsrUnroll) {
-      T x[kCsrUnroll];
+  double ds[P], gs[GG ? P : 1];
 #pragma unroll
-      for (int q = 0; q < kCsrUnroll; ++q) x[q] = xglob(ci[e + q]);
+  for (int e = 0; e < P; ++e) ds[e] = 0.0;
 #pragma unroll
-      for (int q = 0; q < kCsrUnroll; q += 2) {
-        acc0 += val(e + q) * x[q];
-        acc1 += val(e + q + 1) * x[q + 1];
+  for (int e = 0; e < (GG ? P : 1); ++e) gs[e] = 0.0;
+  // results of the previous chunk, stored after the next barrier
+  T zs[P];
+  int64_t zrow = -1;
+
+  int64_t e0n = 0, e1n = 0;
+  {
+    const int64_t r = c_beg * CH + RPW * w + g;
+    if (c_beg < c_end && r < r_lim) {
+      e0n = rp[r];
+      e1n = rp[r + 1];
+    }
+  }
+  if (use_win && c_beg < c_end) stage(c_beg, 0);
+  __syncthreads();
+  for (int64_t c = c_beg; c < c_end; ++c) {
+    const int buf = (int)((c - c_beg) & 1);
+    if (zrow >= 0 && Vkp1) {
+      typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
+      constexpr int VE = 16 / (int)sizeof(T);
+      v16 *dst = (v16 *)(Vkp1 + zrow * ldv + p0);
+#pragma unroll
+      for (int h = 0; h < P / VE; ++h) {
+        v16 q;
+#pragma unroll
+        for (int e = 0; e < VE; ++e) q[e] = zs[h * VE + e];
+        dst[h] = q;
       }
     }
-    if (e + 4 <= e1) {
-      T x[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = xglob(ci[e + q]);
-      acc0 += val(e) * x[0];
-      acc1 += val(e + 1) * x[1];
-      acc0 += val(e + 2) * x[2];
-      acc1 += val(e + 3) * x[3];
-      e += 4;
+    zrow = -1;
+    if (use_win && c + 1 < c_end) stage(c + 1, buf ^ 1);
+    int2 mw = make_int2(0, 0);
+    bool inlds = false;
+    if (use_win) {
+      mw = win[c];
+      inlds = mw.y - mw.x + 1 <= C::WROWS;
     }
-    for (; e < e1; ++e) acc0 += val(e) * xglob(ci[e]);
-    const T y = ta * (acc0 + acc1);
-    T z = tc1 * y + tb * xr;
-    if (use_m1) z += tcw * vm;
-    if (Vkp1) Vkp1[r * ldv + probe] = z;
-    ds += (double)gv * (double)(a.dot_y ? y : z);
-    if (want_gg) gs += (double)gv * (double)gv;
+    const uint8_t *wb = &wbuf[use_win ? buf : 0][0] + P * (int)sizeof(T) * o;
+
+    const int64_t r = c * CH + RPW * w + g;
+    const bool live = r < r_lim;
+    const int64_t rr = live ? r : c * CH;  // a valid row for the loads of idle lanes
+    const int64_t e0 = e0n, e1 = e1n;
+    const int len = live ? (int)(e1 - e0) : 0;
+    const int64_t rn = r + CH;
+    if (rn < r_lim) {
+      e0n = rp[rn];
+      e1n = rp[rn + 1];
+    }
+    // epilogue operands: independent of the gathers
+    T xr[P], vm[P], gv[P];
+    if (inlds)
+      lds_row<T>(wb + (rr - mw.x) * ROWB, xr);
+    else
+      load_row<T, VK_SIGNS>(Vk, signs, rr, ldv, nw, p0, xr);
+    if (use_m1) {
+      if (M1 == 2)
+        load_row<T, true>(nullptr, signs, rr, ldv, nw, p0, vm);
+      else
+        load_row<T, false>(Vkm1, nullptr, rr, ldv, nw, p0, vm);
+    } else {
+#pragma unroll
+      for (int e = 0; e < P; ++e) vm[e] = T(0);
+    }
+    if (signs)
+      load_row<T, true>(nullptr, signs, rr, ldv, nw, p0, gv);
+    else
+      load_row<T, false>(G, nullptr, rr, ldv, nw, p0, gv);
+    // longest row of the wave: the number of gather rounds
+    int mlen = len;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const int t = __shfl_xor(mlen, off, 64);
+      mlen = t > mlen ? t : mlen;
+    }
+    T acc[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) acc[e] = T(0);
+    for (int jc = 0; jc < mlen; jc += U * JM) {
+      // all entries of up to JM rounds at once: lane o (< U) of the group
+      // holds entry jc + U t + o of its row; entries past the row's end
+      // gather the row itself with weight zero
+      int32_t mc[JM];
+      T mv[JM];
+#pragma unroll
+      for (int t = 0; t < JM; ++t) {
+        const int j = jc + U * t + o;
+        const bool in = o < U && j < len;
+        mc[t] = in ? ci[e0 + j] : (int32_t)rr;
+        mv[t] = in ? val[e0 + j] : T(0);
+      }
+#pragma unroll
+      for (int t = 0; t < JM; ++t) {
+        if (jc + U * t >= mlen) break;
+        T x[U][P];
+        if (inlds) {
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const int32_t col = __shfl(mc[t], gl + q, 64);
+            lds_row<T>(wb + (col - mw.x) * ROWB, x[q]);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const int32_t col = __shfl(mc[t], gl + q, 64);
+            load_row<T, VK_SIGNS>(Vk, signs, col, ldv, nw, p0, x[q]);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          const T v = shfl_t(mv[t], gl + q);
+#pragma unroll
+          for (int e = 0; e < P; ++e) acc[e] += v * x[q][e];
+        }
+      }
+    }
+    if (live) {
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        const T y = ta * acc[e];
+        T z = tc1 * y + tb * xr[e];
+        if (use_m1) z += tcw * vm[e];
+        zs[e] = z;
+        ds[e] += (double)gv[e] * (double)(a.dot_y ? y : z);
+        if (GG) gs[GG ? e : 0] += (double)gv[e] * (double)gv[e];
+      }
+      zrow = r;
+    }
+    // the next window has landed, and every wave is done with this one
+    __syncthreads();
   }
-  red[0][w][lane] = ds;
-  red[1][w][lane] = gs;
+  if (zrow >= 0 && Vkp1) {
+    typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int VE = 16 / (int)sizeof(T);
+    v16 *dst = (v16 *)(Vkp1 + zrow * ldv + p0);
+#pragma unroll
+    for (int h = 0; h < P / VE; ++h) {
+      v16 q;
+#pragma unroll
+      for (int e = 0; e < VE; ++e) q[e] = zs[h * VE + e];
+      dst[h] = q;
+    }
+  }
+  // per probe: sum over the wave's rows (lanes o, o+L, ...), then over waves
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+#pragma unroll
+    for (int off = L; off < 64; off <<= 1) {
+      ds[e] += __shfl_xor(ds[e], off, 64);
+      if (GG) gs[GG ? e : 0] += __shfl_xor(gs[GG ? e : 0], off, 64);
+    }
+  }
+  if (lane < L) {
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      red[0][w][P * lane + e] = ds[e];
+      red[1][w][P * lane + e] = GG ? gs[GG ? e : 0] : 0.0;
+    }
+  }
   __syncthreads();
   if (w == 0) {
     double t0 = 0.0, t1 = 0.0;
@@ -124,16 +354,17 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
       t0 += red[0][q][lane];
       t1 += red[1][q][lane];
     }
-    const int64_t base = (int64_t)blockIdx.x * ldv + probe;
-    a.part[(int64_t)a.slot * a.nblk * ldv + base] = t0;
-    if (want_gg) a.part[(int64_t)a.slot_gg * a.nblk * ldv + base] = t1;
+    const int64_t bidx = (int64_t)blockIdx.x * ldv + chunk0 + lane;
+    a.part[(int64_t)a.slot * a.nblk * ldv + bidx] = t0;
+    if (GG) a.part[(int64_t)a.slot_gg * a.nblk * ldv + bidx] = t1;
   }
 }
 
-// Persistent grid: kCsrBlocksPerCU workgroups per CU, fewer for small n.
-int32_t csr_step_blocks(int64_t n) {
-  const int64_t groups = (n + kCsrWaves - 1) / kCsrWaves;
-  const int64_t cap = 256 * kCsrBlocksPerCU;
+// Persistent grid: the resident workgroups of 256 CUs, fewer for small n.
+int32_t csr_step_blocks(int64_t n, int32_t fp64) {
+  const int64_t ch = fp64 ? CsrLanes<double>::CH : CsrLanes<float>::CH;
+  const int64_t groups = (n + ch - 1) / ch;
+  const int64_t cap = 256 * (fp64 ? CsrLanes<double>::BLOCKS_PER_CU : CsrLanes<float>::BLOCKS_PER_CU);
   return (int32_t)(groups < cap ? groups : cap);
 }
 
@@ -141,14 +372,28 @@ template <typename T>
 hipError_t launch_csr_step(const CsrStepArgs &a, hipStream_t st) {
   dim3 grid((unsigned)a.nblk, (unsigned)(a.ldv / 64));
   const bool vk_signs = a.Vk == nullptr;
-  const bool vm1_signs = a.Vkm1 == nullptr && a.cw != 0.0;
-  if ((vk_signs || vm1_signs) && !a.signs) return hipErrorInvalidValue;
-  if (vk_signs)
-    csr_step_kernel<T, true, false><<<grid, 64 * kCsrWaves, 0, st>>>(a);
-  else if (vm1_signs)
-    csr_step_kernel<T, false, true><<<grid, 64 * kCsrWaves, 0, st>>>(a);
-  else
-    csr_step_kernel<T, false, false><<<grid, 64 * kCsrWaves, 0, st>>>(a);
+  const int m1 = a.cw == 0.0 ? 0 : (a.Vkm1 == nullptr ? 2 : 1);
+  const bool gg = a.slot_gg >= 0;
+  if ((vk_signs || m1 == 2) && !a.signs) return hipErrorInvalidValue;
+  const unsigned nt = 64 * kCsrWaves;
+  if (gg) {
+    if (m1 != 0) return hipErrorInvalidValue;  // g.g is taken on the first step only
+    if (vk_signs)
+      csr_step_kernel<T, true, 0, true><<<grid, nt, 0, st>>>(a);
+    else
+      csr_step_kernel<T, false, 0, true><<<grid, nt, 0, st>>>(a);
+  } else if (m1 == 0) {
+    if (vk_signs)
+      csr_step_kernel<T, true, 0, false><<<grid, nt, 0, st>>>(a);
+    else
+      csr_step_kernel<T, false, 0, false><<<grid, nt, 0, st>>>(a);
+  } else {
+    if (vk_signs) return hipErrorInvalidValue;  // V_k is stored from the second step on
+    if (m1 == 2)
+      csr_step_kernel<T, false, 2, false><<<grid, nt, 0, st>>>(a);
+    else
+      csr_step_kernel<T, false, 1, false><<<grid, nt, 0, st>>>(a);
+  }
   return hipGetLastError();
 }
 template hipError_t launch_csr_step<double>(const CsrStepArgs &, hipStream_t);

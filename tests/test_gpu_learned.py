@@ -91,6 +91,46 @@ def test_auto_fallback_is_the_plain_schedule():
     assert auto.products == 12 + 5 + 30   # degree 4 with the 25% margin -> 5
 
 
+def test_trained_selector_gain(orc):
+    """What the committed network gains over the plain schedule.
+
+    Held-out spectra of the training families (a seed the training never
+    used), n = 1024, as diagonal matrices with sign probes: then
+    g^T f(R) g = sum_i f(p_i) for every probe, so each estimate is the exact
+    polynomial trace and its error vs H is the truncation error alone.  The
+    plain schedule (Chebyshev on [0, u], degree 40) meets a 1e-3 relative
+    error on about a third of them; the learned degree and cutoff must meet
+    it on most, and every result must equal the oracle's polynomial trace at
+    the (degree, cutoff, u) the selector chose."""
+    ent.selector_load(L.load())
+    rng = np.random.default_rng(424242)
+    rows = []
+    for i in range(24):
+        p, fam = L.sample_spectrum(rng, 1024)
+        H = float(-np.sum(p[p > 0] * np.log(p[p > 0])))
+        R = torch.from_numpy(np.diag(p)).to(DEV)
+        auto = ent.entropy_estimate(R, "auto", 40, 8, 100 + i, precision="f64")
+        plain = ent.entropy_estimate(R, "chebyshev", 40, 8, 100 + i, precision="f64")
+        # the oracle's polynomial trace at the selector's choice
+        lo, u, m = auto.lo, auto.u, auto.degree
+        a = orc.cheb_interp_coeffs(lo, u, m, orc.cutoff_nodes(m)) if lo > 0 else orc.cheb_coeffs(u, m)
+        ref = -orc.cheb_quadform(W.diag_csr(p), a, lo, u, np.ones(len(p)))
+        assert auto.entropy == pytest.approx(ref, rel=1e-9, abs=1e-12)
+        rows.append((fam, abs(auto.entropy - H) / H, abs(plain.entropy - H) / H, auto.products,
+                     plain.products, auto.fell_back, m, lo / u))
+    fam, ea, ep, pa, pp, fb, ms, rho = (np.array(c) for c in zip(*rows))
+    for r in rows:
+        print(f"[gain] family {r[0]}: auto err {r[1]:.2e} (m={r[6]}, lo/u={r[7]:.1e}, products "
+              f"{r[3]}, fell_back={r[5]})  plain err {r[2]:.2e} (products {r[4]})", flush=True)
+    ok_a, ok_p = float(np.mean(ea <= 1e-3)), float(np.mean(ep <= 1e-3))
+    print(f"[gain] within 1e-3: auto {ok_a:.2f}, plain {ok_p:.2f}; median error auto "
+          f"{np.median(ea):.2e}, plain {np.median(ep):.2e}; products auto {pa.sum()}, plain "
+          f"{pp.sum()}; fallbacks {int(fb.sum())}", flush=True)
+    assert ok_a >= 0.75
+    assert ok_a >= ok_p + 0.25
+    assert np.median(ea) < 0.25 * np.median(ep)
+
+
 def test_selector_rejects_bad_params():
     with pytest.raises(ent.EntropyError):
         ent.selector_load(np.zeros(10, dtype=np.float32))
