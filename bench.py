@@ -52,6 +52,35 @@ WORKLOADS = {
 }
 
 
+KERNEL_SOURCES = {
+    "bf16x3_gemm_kernel": "kernels_bf16.hip",
+    "dense_step_kernel": "kernels_dense.hip",
+    "batch_dense_step_kernel": "kernels_dense.hip",
+    "csr_step_kernel": "kernels_csr.hip",
+}
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    hardware-counter summary (profiles/<kernel>__<workload>__traffic.md),
+    or None when there is none or the kernel's source changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}__{workload}__traffic.md")
+    src = os.path.join(ROOT, "paper_1801_01072_amd", "csrc", KERNEL_SOURCES.get(kernel, ""))
+    if not os.path.exists(path) or not os.path.isfile(src):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("source_sha256") != digest or "hbm_bytes_per_launch" not in fields:
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -158,7 +187,8 @@ def bench_batch(args, cfg):
                    "count": count, "sum_n2": sum_n2, "precision": precision,
                    "tile_rows": g.tile_rows, "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": "batch_dense_step_kernel",
+                     "frac": achieved / peak, "traffic": measured_traffic("batch_dense_step_kernel", args.workload),
+                     "kernel": "batch_dense_step_kernel",
                      "avg_launch_ms": avg_step_ms, "algorithmic_flop_per_launch": flop},
         "cpu_baseline": cpu,
         "phases_ms": phases,
@@ -485,7 +515,8 @@ def main():
         flop = 2.0 * n * n * s
         achieved = flop / (avg_step_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS[precision],
-                "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS[precision], "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS[precision],
+                "traffic": measured_traffic(kernel, args.workload + ("" if precision == "bf16x3" else "_" + precision)),
                 "kernel": kernel, "avg_launch_ms": avg_step_ms, "algorithmic_flop_per_launch": flop}
         if precision == "bf16x3":
             roof["executed_tflops"] = 3 * achieved
@@ -498,7 +529,9 @@ def main():
         per_launch = tot_bytes / steps
         achieved = per_launch / (avg_step_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "csr_step_kernel",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic("csr_step_kernel", args.workload + ("" if precision == "f32" else "_" + precision)),
+                "kernel": "csr_step_kernel",
                 "avg_launch_ms": avg_step_ms, "algorithmic_bytes_per_launch": per_launch}
         log(f"csr_step_kernel: {avg_step_ms:.4f} ms/launch -> {achieved:.1f} GB/s")
     log(f"phases (ms): {phases}")

@@ -164,6 +164,9 @@ ent_status ent_entropy_estimate(const ent_matrix *R, int32_t method, int32_t deg
  *                             X = (2R - (u+lo)I)/(u-lo);
  *                             Taylor: e_{k,j} = g_j^T (R/u)(I - R/u)^k g_j,
  *                             k = 0..m.
+ * moments holds (degree + 1) * probes doubles.  ENT_AUTO: the moments of the
+ * pass that produced the result (its degree is out->degree), rows k <=
+ * min(out->degree, degree); any later rows are set to zero.
  * Used for per-probe parity checks.  RANDPROJ: per_probe[i] = the i-th kept
  * singular value (rank_k entries); moments unused.
  */

@@ -126,4 +126,32 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// Block sums of y^2, xs.y, xs^2 over the rows a block produced (fixed order).
+__device__ __forceinline__ void block_power_partials(double yy, double xy, double xx,
+                                                     double *part3, int64_t blk) {
+  __shared__ double red[3][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  yy = wave_sum(yy);
+  xy = wave_sum(xy);
+  xx = wave_sum(xx);
+  if (lane == 0) {
+    red[0][w] = yy;
+    red[1][w] = xy;
+    red[2][w] = xx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    double a = 0, b = 0, c = 0;
+    for (int i = 0; i < nw; ++i) {
+      a += red[0][i];
+      b += red[1][i];
+      c += red[2][i];
+    }
+    part3[3 * blk + 0] = a;
+    part3[3 * blk + 1] = b;
+    part3[3 * blk + 2] = c;
+  }
+}
+
 }  // namespace ent

@@ -245,6 +245,26 @@ ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t 
   return ENT_OK;
 }
 
+// The same power method on the bf16 hi/lo split of a dense R.
+ent_status enqueue_power_split(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t n_pad,
+                               int32_t t, int32_t q, uint64_t seed, double *x0, double *x1,
+                               double *part3, double *norm, double *scal, hipStream_t st) {
+  for (int32_t trial = 0; trial < q; ++trial) {
+    HIP_TRY(ent::launch_power_start(x0, n, seed, trial, st));
+    double *xin = x0, *xout = x1;
+    const double *in_norm = nullptr;
+    for (int32_t it = 0; it <= t; ++it) {
+      int32_t nblk = 0;
+      HIP_TRY(ent::launch_power_gemv_split(hi, lo, n_pad, n, xin, in_norm, xout, part3, &nblk, st));
+      HIP_TRY(ent::launch_power_reduce(part3, nblk, norm, st));
+      std::swap(xin, xout);
+      in_norm = norm;
+    }
+    HIP_TRY(ent::launch_power_rq(scal, norm, trial, st));
+  }
+  return ENT_OK;
+}
+
 // Validate a CSR structure on the device before any kernel dereferences its
 // indices (one synchronisation).  Uses the first 256 bytes of the workspace.
 ent_status check_csr(const ent_matrix *R, void *scratch, hipStream_t st) {
@@ -492,8 +512,6 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   if (R->layout != ENT_DENSE) return fail(ENT_EUNSUPPORTED, "BF16x3 is implemented for dense R only");
   const int64_t n = R->n;
   const bool f64 = R->dtype == ENT_STORE_F64;
-  const int ve = f64 ? 2 : 4;
-  const bool copy = (R->ld % ve) != 0 || ((uintptr_t)R->values % 16) != 0;
   const int64_t n_pad = round_up(n, 128);
   const int bn = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
   const int64_t ldv = round_up(s, bn);
@@ -505,7 +523,6 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   const int32_t nslot = m + 1;
   const bool use_power = !(o.u_fixed > 0);
   const int32_t pblk = (int32_t)power_blocks(R);
-  const int64_t ldc = round_up(n, ve);
 
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -515,7 +532,6 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   double *part = nullptr, *d = nullptr, *h = nullptr;
   uint16_t *Ahi = nullptr, *Alo = nullptr, *Vhi = nullptr, *Vlo = nullptr;
   float *G = nullptr, *VA = nullptr, *VB = nullptr, *party = nullptr;
-  char *Rc = nullptr;
   Carve cv;
   cv.add(&scal, kScalarDoubles);
   if (use_power) {
@@ -524,7 +540,6 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
     cv.add(&p0, 3 * (size_t)pblk);
     cv.add(&p1, 4);
   }
-  if (copy) cv.add(&Rc, (size_t)n * ldc * (f64 ? 8 : 4));
   cv.add(&Ahi, (size_t)n_pad * n_pad);
   cv.add(&Alo, (size_t)n_pad * n_pad);
   cv.add(&G, (size_t)ldv * n_pad);
@@ -546,40 +561,28 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   pe.mark();
   HIP_TRY(hipMemsetAsync(scal, 0, sizeof(double) * 64, st));
   const bool check_trace = !(o.flags & ENT_FLAG_SKIP_TRACE_CHECK);
-  const void *Rv = R->values;
-  int64_t ldr = R->ld;
-  if (copy) {
-    if (f64)
-      HIP_TRY((ent::launch_convert<double, double>((const double *)Rv, R->ld, (double *)Rc, ldc, n, n, st)));
-    else
-      HIP_TRY((ent::launch_convert<float, float>((const float *)Rv, R->ld, (float *)Rc, ldc, n, n, st)));
-    Rv = Rc;
-    ldr = ldc;
-  }
   if (check_trace) {
     if (f64)
-      HIP_TRY(ent::launch_trace_dense<double>((const double *)Rv, ldr, n, scal, st));
+      HIP_TRY(ent::launch_trace_dense<double>((const double *)R->values, R->ld, n, scal, st));
     else
-      HIP_TRY(ent::launch_trace_dense<float>((const float *)Rv, ldr, n, scal, st));
+      HIP_TRY(ent::launch_trace_dense<float>((const float *)R->values, R->ld, n, scal, st));
   }
   HIP_TRY(ent::launch_probe_gen_t(G, Vhi, Vlo, n, n_pad, s, ldv, seed, o.probe_dist, st));
+  // split R itself once; the power method reads the split (half the bytes of
+  // an FP32 copy), and the interval scale a is applied to each product
+  if (f64)
+    HIP_TRY(ent::launch_split_matrix<double>((const double *)R->values, R->ld, n, n_pad, nullptr, Ahi, Alo, st));
+  else
+    HIP_TRY(ent::launch_split_matrix<float>((const float *)R->values, R->ld, n, n_pad, nullptr, Ahi, Alo, st));
   if (use_power) {
     pe.power_begin = pe.mark();
-    if (f64)
-      rc = enqueue_power<double>(R, (const double *)Rv, ldr, o.power_iters, o.power_trials, seed, x0,
-                                 x1, p0, p1, scal, st);
-    else
-      rc = enqueue_power<float>(R, (const float *)Rv, ldr, o.power_iters, o.power_trials, seed, x0,
-                                x1, p0, p1, scal, st);
+    rc = enqueue_power_split(Ahi, Alo, n, n_pad, o.power_iters, o.power_trials, seed, x0, x1, p0, p1,
+                             scal, st);
     if (rc != ENT_OK) return rc;
     pe.power_end = pe.mark();
     pe.power_launches = o.power_trials * (o.power_iters + 1);
   }
   HIP_TRY(ent::launch_setup_interval(scal, method, m, o.u_factor, o.u_fixed, o.cutoff, st));
-  if (f64)
-    HIP_TRY(ent::launch_split_matrix<double>((const double *)Rv, ldr, n, n_pad, scal, Ahi, Alo, st));
-  else
-    HIP_TRY(ent::launch_split_matrix<float>((const float *)Rv, ldr, n, n_pad, scal, Ahi, Alo, st));
 
   const int32_t nsteps = (method == ENT_CHEBYSHEV) ? m : m + 1;
   const float *Vk = G, *Vkm1 = nullptr;
@@ -615,6 +618,7 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
     ea.part_y = party; ea.splits = splits; ea.Vk = Vk; ea.Vkm1 = Vkm1;
     ea.Vkp1 = write ? Vout : nullptr; ea.V_hi = Vhi; ea.V_lo = Vlo; ea.G = G; ea.scal = scal;
     ea.c1 = c1; ea.c2 = c2; ea.cw = cw; ea.dot_y = dot_y; ea.slot = slot; ea.slot_gg = slot_gg;
+    ea.scale_y = 1;
     ea.part = part; ea.nblk = nblk; ea.n_pad = n_pad; ea.ldv = ldv;
     HIP_TRY(ent::launch_bf16x3_epilogue(ea, st));
     const int e2 = pe.mark();
@@ -760,7 +764,12 @@ ent_status run_auto(const ent_matrix *R, int32_t m_plain, int32_t s, uint64_t se
   bool ok = rc == ENT_OK && selector_check(mom, alpha, m_hat, s);
   int32_t products = kFeatDegree + m_hat;
   if (ok) {
-    if (moments) std::memcpy(moments, mom.data(), sizeof(double) * mom.size());
+    // the caller's table has (m_plain + 1) rows: copy the rows that fit
+    if (moments) {
+      const int32_t rows = std::min(m_hat, m_plain) + 1;
+      std::memcpy(moments, mom.data(), sizeof(double) * (size_t)rows * s);
+      std::fill(moments + (size_t)rows * s, moments + (size_t)(m_plain + 1) * s, 0.0);
+    }
   } else {
     // 3. fallback: the plain schedule on [0, u] with the caller's degree
     Opts po = op;

@@ -174,6 +174,7 @@ struct Bf16EpiArgs {
   const double *scal;
   double c1, c2, cw;
   int32_t dot_y, slot, slot_gg;
+  int32_t scale_y;              // 1: y *= scal[S_A] (the split is of R itself)
   double *part;                 // [slot][nblk][ldv]
   int32_t nblk;
   int64_t n_pad, ldv;
@@ -187,6 +188,10 @@ hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, i
                               int32_t s, int64_t ldv, uint64_t seed, int32_t dist, hipStream_t st,
                               uint32_t stream = 0, double scale = 1.0);
 hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st);
+// Power-method product on the bf16 hi/lo split of R (ld = n_pad).
+hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64_t ld, int64_t n,
+                                   const double *x, const double *in_norm, double *y, double *part3,
+                                   int32_t *nblk, hipStream_t st);
 hipError_t launch_bf16x3_epilogue(const Bf16EpiArgs &a, hipStream_t st);
 int32_t bf16x3_epilogue_blocks(int64_t n_pad);
 

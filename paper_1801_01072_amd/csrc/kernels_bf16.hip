@@ -41,14 +41,16 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ---------------------------------------------------------------------------
-// A = a * R -> hi/lo (row-major, ld = n_pad, zero outside n x n)
+// A = a * R -> hi/lo (row-major, ld = n_pad, zero outside n x n); a =
+// scal[S_A], or 1 when scal is null (the split is then of R itself and the
+// scale is applied to the product in the epilogue).
 // ---------------------------------------------------------------------------
 template <typename Tin>
 __global__ void split_matrix_kernel(const Tin *__restrict__ R, int64_t ldr, int64_t n, int64_t n_pad,
                                     const double *__restrict__ scal, uint16_t *__restrict__ hi,
                                     uint16_t *__restrict__ lo) {
   const int64_t row = blockIdx.y;
-  const double a = scal[S_A];
+  const double a = scal ? scal[S_A] : 1.0;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_pad;
        c += (int64_t)gridDim.x * blockDim.x) {
     float v = 0.f;
@@ -252,6 +254,71 @@ __global__ __launch_bounds__(256) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Power-method product on the split of R: y = ((hi + lo) x)/||x_prev|| with
+// FP64 accumulation (hi + lo is exact in FP32).  Each wave owns 2 rows;
+// lanes stride over 8-element (16-byte) vectors of hi and lo.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void power_gemv_split_kernel(const uint16_t *__restrict__ hi,
+                                                               const uint16_t *__restrict__ lo,
+                                                               int64_t ld, int64_t n,
+                                                               const double *__restrict__ x,
+                                                               const double *__restrict__ in_norm,
+                                                               double *__restrict__ y,
+                                                               double *__restrict__ part3) {
+  const double sc = in_norm ? 1.0 / sqrt(in_norm[0]) : 1.0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 2;
+  const bool ok0 = r0 < n, ok1 = r0 + 1 < n;
+  const int64_t o0 = (ok0 ? r0 : 0) * ld, o1 = (ok1 ? r0 + 1 : 0) * ld;
+  double a0 = 0.0, a1 = 0.0;
+  const int64_t nvec = n / 8;
+  for (int64_t v = lane; v < nvec; v += 64) {
+    const int64_t k = v * 8;
+    const u16x8 h0 = *(const u16x8 *)(hi + o0 + k), l0 = *(const u16x8 *)(lo + o0 + k);
+    const u16x8 h1 = *(const u16x8 *)(hi + o1 + k), l1 = *(const u16x8 *)(lo + o1 + k);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const double xe = x[k + e];
+      a0 += (double)(bf16_to_f32(h0[e]) + bf16_to_f32(l0[e])) * xe;
+      a1 += (double)(bf16_to_f32(h1[e]) + bf16_to_f32(l1[e])) * xe;
+    }
+  }
+  for (int64_t k = nvec * 8 + lane; k < n; k += 64) {
+    const double xe = x[k];
+    a0 += (double)(bf16_to_f32(hi[o0 + k]) + bf16_to_f32(lo[o0 + k])) * xe;
+    a1 += (double)(bf16_to_f32(hi[o1 + k]) + bf16_to_f32(lo[o1 + k])) * xe;
+  }
+  const double s0 = wave_sum(a0), s1 = wave_sum(a1);
+  double yy = 0.0, xy = 0.0, xx = 0.0;
+  if (lane == 0) {
+    if (ok0) {
+      const double yv = sc * s0, xs = sc * x[r0];
+      y[r0] = yv;
+      yy += yv * yv;
+      xy += xs * yv;
+      xx += xs * xs;
+    }
+    if (ok1) {
+      const double yv = sc * s1, xs = sc * x[r0 + 1];
+      y[r0 + 1] = yv;
+      yy += yv * yv;
+      xy += xs * yv;
+      xx += xs * xs;
+    }
+  }
+  block_power_partials(yy, xy, xx, part3, blockIdx.x);
+}
+
+hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64_t ld, int64_t n,
+                                   const double *x, const double *in_norm, double *y, double *part3,
+                                   int32_t *nblk, hipStream_t st) {
+  const int32_t blocks = power_blocks_dense(n);
+  *nblk = blocks;
+  power_gemv_split_kernel<<<(unsigned)blocks, 256, 0, st>>>(hi, lo, ld, n, x, in_norm, y, part3);
+  return hipGetLastError();
+}
+
 hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st) {
   const int nrt = (int)(a.n_pad / 128), nct = (int)(a.ldv / a.bn);
   const unsigned grid = (unsigned)(nrt * nct * a.splits);
@@ -275,6 +342,7 @@ __global__ __launch_bounds__(256) void bf16x3_epilogue_kernel(Bf16EpiArgs a) {
   const int64_t npad = a.n_pad;
   const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
   const float c1 = (float)a.c1, c2b = (float)(a.c2 * a.scal[S_B]), cw = (float)a.cw;
+  const float ys = a.scale_y ? (float)a.scal[S_A] : 1.f;
   double ds = 0.0, gs = 0.0;
   if (i0 < npad) {
     const int64_t off = j * npad + i0;
@@ -290,6 +358,8 @@ __global__ __launch_bounds__(256) void bf16x3_epilogue_kernel(Bf16EpiArgs a) {
         y[4 + e] += p1[e];
       }
     }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) y[e] *= ys;
     const f32x4 *vk = (const f32x4 *)(a.Vk + off);
     const f32x4 vk0 = vk[0], vk1 = vk[1];
     f32x4 vm0 = {0, 0, 0, 0}, vm1 = {0, 0, 0, 0};

@@ -82,34 +82,6 @@ hipError_t launch_power_start(double *x, int64_t n, uint64_t seed, int32_t trial
   return hipGetLastError();
 }
 
-// Block sums of y^2, xs.y, xs^2 over the rows a block produced (fixed order).
-__device__ __forceinline__ void block_power_partials(double yy, double xy, double xx,
-                                                     double *part3, int64_t blk) {
-  __shared__ double red[3][16];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  yy = wave_sum(yy);
-  xy = wave_sum(xy);
-  xx = wave_sum(xx);
-  if (lane == 0) {
-    red[0][w] = yy;
-    red[1][w] = xy;
-    red[2][w] = xx;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = blockDim.x >> 6;
-    double a = 0, b = 0, c = 0;
-    for (int i = 0; i < nw; ++i) {
-      a += red[0][i];
-      b += red[1][i];
-      c += red[2][i];
-    }
-    part3[3 * blk + 0] = a;
-    part3[3 * blk + 1] = b;
-    part3[3 * blk + 2] = c;
-  }
-}
-
 // Dense y = (R x)/||x_prev|| (||x_prev||^2 = in_norm[0]; null: no scaling).
 // Each wave owns 2 consecutive rows; lanes stride over 16-byte vectors of
 // both rows, two vectors in flight per row (FP64 accumulation).

@@ -95,17 +95,25 @@ template hipError_t launch_gram<float>(const float *, int64_t, int64_t, int64_t,
 // disjoint (p, q) planes at once: rotation parameters from the round's
 // starting matrix, then all row updates, then all column updates.  Stops when
 // the off-diagonal Frobenius norm is below tol * ||A||_F, or after
-// max_sweeps sweeps (every thread reads the same shared decision).
+// max_sweeps sweeps (every thread reads the same shared decision).  For
+// N <= 128 the matrix is moved into LDS (128 KB) for the whole iteration.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void jacobi_eig_kernel(double *__restrict__ A, int32_t N,
+template <bool IN_LDS>
+__global__ __launch_bounds__(1024) void jacobi_eig_kernel(double *__restrict__ Ag, int32_t N,
                                                           double tol, int32_t max_sweeps,
                                                           double *__restrict__ eig) {
+  __shared__ double As[IN_LDS ? 128 * 128 : 1];
   __shared__ int sp[128], sq[128];
   __shared__ double sc[128], ss[128];
   __shared__ double red[16];
   __shared__ int done;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int half = N / 2;
+  double *A = IN_LDS ? As : Ag;
+  if (IN_LDS) {
+    for (int e = tid; e < N * N; e += nt) As[e] = Ag[e];
+    __syncthreads();
+  }
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
     // convergence test
     double off = 0.0, fro = 0.0;
@@ -236,7 +244,10 @@ hipError_t launch_rp_spectrum(const double *G, int32_t s, int32_t k, double *wor
   const int32_t N = (s + 1) / 2 * 2;
   if (N > 256) return hipErrorInvalidValue;
   pad_square_kernel<<<64, 256, 0, st>>>(G, s, work, N);
-  jacobi_eig_kernel<<<1, 1024, 0, st>>>(work, N, 1e-14, 40, eig);
+  if (N <= 128)
+    jacobi_eig_kernel<true><<<1, 1024, 0, st>>>(work, N, 1e-14, 40, eig);
+  else
+    jacobi_eig_kernel<false><<<1, 1024, 0, st>>>(work, N, 1e-14, 40, eig);
   rp_finish_kernel<<<1, 256, 0, st>>>(eig, N, k, sigma, scal);
   return hipGetLastError();
 }

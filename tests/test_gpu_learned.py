@@ -131,6 +131,22 @@ def test_trained_selector_gain(orc):
     assert np.median(ea) < 0.25 * np.median(ep)
 
 
+def test_auto_moments_fit_the_callers_table():
+    # the selector may pick a degree above the caller's; the moment table the
+    # caller passes has (degree + 1) rows and must not be overrun
+    ent.selector_load(L.load())
+    p = W.spectrum_dirichlet(512, 300, 0.5, np.random.default_rng(3))
+    R = torch.from_numpy(np.diag(p)).to(DEV)
+    for deg in (4, 9):
+        res, per, mom = ent.entropy_estimate_detail(R, "auto", deg, 8, 5, precision="f64")
+        assert mom.shape == (deg + 1, 8)
+        rows = min(res.degree, deg) + 1
+        assert np.all(mom[rows:] == 0.0)
+        assert np.all(np.isfinite(mom)) and np.all(np.isfinite(per))
+        print(f"[auto moments] caller degree {deg}: selector degree {res.degree}, "
+              f"fell_back={res.fell_back}", flush=True)
+
+
 def test_selector_rejects_bad_params():
     with pytest.raises(ent.EntropyError):
         ent.selector_load(np.zeros(10, dtype=np.float32))

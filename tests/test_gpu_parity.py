@@ -229,7 +229,9 @@ def test_dense_bf16x3_small_config(orc, method, dist):
     perr = np.max(np.abs(per - ref.per_probe)) / np.mean(np.abs(ref.per_probe))
     print(f"[bf16x3 512 {method} {dist}] H gpu={gpu.entropy:.12f} oracle={ref.entropy:.12f} "
           f"rel={rel:.2e} per-probe={perr:.2e}", flush=True)
-    assert gpu.p1_est == pytest.approx(ref.p1_est, rel=1e-12)   # power method stays FP64
+    # the power method reads the bf16 hi/lo split of R (about 2^-17 relative per
+    # entry) and accumulates in FP64
+    assert gpu.p1_est == pytest.approx(ref.p1_est, rel=1e-6)
     assert rel <= 1e-3 and perr <= 1e-3
 
 
