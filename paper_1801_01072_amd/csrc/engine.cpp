@@ -515,7 +515,7 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   const int64_t n_pad = round_up(n, 128);
   const int bn = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
   const int64_t ldv = round_up(s, bn);
-  const int64_t tiles = (n_pad / 128) * (ldv / bn);
+  const int64_t tiles = (n_pad / ent::bf16x3_tile_rows(n_pad)) * (ldv / bn);
   int32_t splits = 1;
   while (tiles * splits < 256 && splits < 16 && (n_pad / (2 * splits)) % 32 == 0) splits *= 2;
   const int64_t kps = n_pad / splits;
@@ -824,7 +824,7 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
     const int64_t n_pad = round_up(n, 128);
     const int bn = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
     const int64_t ldv = round_up(s, bn);
-    const int64_t tiles = (n_pad / 128) * (ldv / bn);
+    const int64_t tiles = (n_pad / ent::bf16x3_tile_rows(n_pad)) * (ldv / bn);
     int32_t splits = 1;
     while (tiles * splits < 256 && splits < 16 && (n_pad / (2 * splits)) % 32 == 0) splits *= 2;
     uint16_t *Ahi = nullptr, *Alo = nullptr, *Phi = nullptr, *Plo = nullptr;

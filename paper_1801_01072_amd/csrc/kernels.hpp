@@ -187,6 +187,8 @@ hipError_t launch_split_matrix(const Tin *R, int64_t ldr, int64_t n, int64_t n_p
 hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, int64_t n_pad,
                               int32_t s, int64_t ldv, uint64_t seed, int32_t dist, hipStream_t st,
                               uint32_t stream = 0, double scale = 1.0);
+// Rows of the GEMM's workgroup tile for a padded size (256 when it divides).
+int32_t bf16x3_tile_rows(int64_t n_pad);
 hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st);
 // Power-method product on the bf16 hi/lo split of R (ld = n_pad).
 hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64_t ld, int64_t n,

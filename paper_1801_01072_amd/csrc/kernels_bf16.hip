@@ -105,48 +105,53 @@ hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, i
 // ---------------------------------------------------------------------------
 // GEMM: part_y[ks][j][i] = sum_{k in split ks} (A_hi V_hi + A_hi V_lo + A_lo V_hi)[i][j]
 //
-// Workgroup tile: 128 rows x BN probes over one K-split, 4 waves in a 2 x 2
-// grid (64 rows x BN/2 probes each).  Operands reach LDS by direct
-// global-to-LDS loads (no registers) in a 3-stage ring of BK = 32: stage t+2
-// is in flight while stage t is computed.  LDS holds every operand in the
-// MFMA's own fragment order: a fragment (32 rows or probes x 16 k, hi or lo)
-// is 1 KB with lane l's 8 k-values at byte 16 l, so the loads that fill it
-// and the ds_read_b128 that consume it are both contiguous per wave.
+// Workgroup tile: BM = 64 WM rows x BN probes over one K-split, 2 WM waves
+// in a WM x 2 grid (64 rows x BN/2 probes each).  Operands reach LDS by
+// direct global-to-LDS loads (no registers) in a ring of kStages(WM) stages
+// of BK = 32: the next stages are in flight while one is computed.  LDS holds
+// every operand in the MFMA's own fragment order: a fragment (32 rows or
+// probes x 16 k, hi or lo) is 1 KB with lane l's 8 k-values at byte 16 l, so
+// the loads that fill it and the ds_read_b128 that consume it are both
+// contiguous per wave.
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int kBK = 32;              // k per stage
-constexpr int kKS = kBK / 16;        // MFMA k-steps per stage
-constexpr int kStages = 3;
-constexpr int kFragA = 2 * 4 * kKS;  // (hi/lo, row block, k-step) fragments of A per stage
+constexpr int kBK = 32;        // k per stage
+constexpr int kKS = kBK / 16;  // MFMA k-steps per stage
 }  // namespace
 
-template <int BN>
+template <int BN, int WM>
 struct GemmShape {
+  static constexpr int WAVES = 2 * WM;
+  static constexpr int BM = 64 * WM;
+  static constexpr int NRB = BM / 32;                  // row blocks of the tile
   static constexpr int NCB = BN / 32;                  // probe blocks of the tile
   static constexpr int WCB = NCB / 2;                  // probe blocks per wave
+  static constexpr int FA = 2 * NRB * kKS;             // A fragments per stage
   static constexpr int FB = 2 * NCB * kKS;             // B fragments per stage
-  static constexpr int FST = kFragA + FB;              // fragments per stage
-  static constexpr int PER_WAVE = FST / 4;             // loads per wave per stage
-  static constexpr int LDS_BYTES = kStages * FST * 1024;
+  static constexpr int FST = FA + FB;                  // fragments per stage
+  static constexpr int PER_WAVE = FST / WAVES;         // loads per wave per stage
+  static constexpr int STAGES = (160 / FST) > 3 ? 3 : (160 / FST);
+  static constexpr int LDS_BYTES = STAGES * FST * 1024;
 };
 
 // s_waitcnt vmcnt(N) in the gfx9 encoding, expcnt and lgkmcnt left free.
 template <int N>
 __device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 16, "vmcnt immediate");
-  __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+  static_assert(N >= 0 && N < 64, "vmcnt immediate");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
 }
 
-template <int BN>
-__global__ __launch_bounds__(256) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
-  typedef GemmShape<BN> S;
-  static_assert(S::FST % 4 == 0, "fragments must split evenly over 4 waves");
+template <int BN, int WM>
+__global__ __launch_bounds__(128 * WM) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
+  typedef GemmShape<BN, WM> S;
+  static_assert(S::FST % S::WAVES == 0, "fragments must split evenly over the waves");
+  static_assert(S::STAGES >= 2, "at least two stages");
   __shared__ __attribute__((aligned(1024))) uint8_t lds[S::LDS_BYTES];
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = w & 1, wc = w >> 1;
-  const int nrt = (int)(a.n_pad / 128);
+  const int wr = w % WM, wc = w / WM;
+  const int nrt = (int)(a.n_pad / S::BM);
   const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   // tile order: row tile fastest, then K-split, then probe tile
   const int rt = b % nrt;
@@ -155,31 +160,31 @@ __global__ __launch_bounds__(256) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
   const int64_t npad = a.n_pad;
   const int64_t kbeg = (int64_t)ksp * a.k_per_split;
   const int nst = (int)(a.k_per_split / kBK);
-  const int64_t row0 = (int64_t)rt * 128, col0 = (int64_t)ct * BN;
+  const int64_t row0 = (int64_t)rt * S::BM, col0 = (int64_t)ct * BN;
   const int m32 = lane & 31, kh = lane >> 5;
 
   // per-lane source of each fragment this wave loads (advanced by kBK per stage)
   const uint16_t *src[S::PER_WAVE];
 #pragma unroll
   for (int i = 0; i < S::PER_WAVE; ++i) {
-    const int f = w + 4 * i;
+    const int f = w + S::WAVES * i;
     const uint16_t *p;
-    if (f < kFragA) {
-      const int hl = f / (4 * kKS), rb = (f / kKS) % 4, ks = f % kKS;
+    if (f < S::FA) {
+      const int hl = f / (S::NRB * kKS), rb = (f / kKS) % S::NRB, ks = f % kKS;
       p = (hl ? a.A_lo : a.A_hi) + (row0 + 32 * rb + m32) * npad + 16 * ks + 8 * kh;
     } else {
-      const int g = f - kFragA;
+      const int g = f - S::FA;
       const int hl = g / (S::NCB * kKS), cb = (g / kKS) % S::NCB, ks = g % kKS;
       p = (hl ? a.V_lo : a.V_hi) + (col0 + 32 * cb + m32) * npad + 16 * ks + 8 * kh;
     }
     src[i] = p + kbeg;
   }
   auto issue = [&](int t) {
-    uint8_t *base = lds + (t % kStages) * S::FST * 1024;
+    uint8_t *base = lds + (t % S::STAGES) * S::FST * 1024;
 #pragma unroll
     for (int i = 0; i < S::PER_WAVE; ++i)
       __builtin_amdgcn_global_load_lds((const void *)(src[i] + (int64_t)t * kBK),
-                                       (__attribute__((address_space(3))) void *)(base + (w + 4 * i) * 1024),
+                                       (__attribute__((address_space(3))) void *)(base + (w + S::WAVES * i) * 1024),
                                        16, 0, 0);
   };
 
@@ -191,33 +196,37 @@ __global__ __launch_bounds__(256) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[r][c][e] = 0.f;
 
-  issue(0);
-  if (nst > 1) issue(1);
+  // prologue: the first STAGES-1 stages in flight
+#pragma unroll
+  for (int t = 0; t < S::STAGES - 1; ++t)
+    if (t < nst) issue(t);
   for (int t = 0; t < nst; ++t) {
-    // this wave's loads of stage t are done once at most those of stage t+1
-    // remain; the barrier then makes every wave's part visible, and also
-    // guarantees that stage t-1 (whose buffer stage t+2 reuses) is consumed
-    if (t + 1 < nst)
-      wait_vm<S::PER_WAVE>();
+    // this wave's loads of stage t are done once at most those of the later
+    // stages already issued remain; the barrier then makes every wave's part
+    // visible, and also guarantees that the stage whose buffer the next
+    // issue reuses has been consumed
+    if (t + S::STAGES - 2 < nst)
+      wait_vm<S::PER_WAVE * (S::STAGES - 2)>();
     else
       wait_vm<0>();
     __builtin_amdgcn_s_barrier();
-    if (t + 2 < nst) issue(t + 2);
-    const uint8_t *base = lds + (t % kStages) * S::FST * 1024 + 16 * lane;
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + S::STAGES - 1 < nst) issue(t + S::STAGES - 1);
+    const uint8_t *base = lds + (t % S::STAGES) * S::FST * 1024 + 16 * lane;
 #pragma unroll
     for (int ks = 0; ks < kKS; ++ks) {
       bf16x8 ah[2], al[2], bh[S::WCB], bl[S::WCB];
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const int rb = 2 * wr + r;
-        ah[r] = *(const bf16x8 *)(base + ((0 * 4 + rb) * kKS + ks) * 1024);
-        al[r] = *(const bf16x8 *)(base + ((1 * 4 + rb) * kKS + ks) * 1024);
+        ah[r] = *(const bf16x8 *)(base + ((0 * S::NRB + rb) * kKS + ks) * 1024);
+        al[r] = *(const bf16x8 *)(base + ((1 * S::NRB + rb) * kKS + ks) * 1024);
       }
 #pragma unroll
       for (int c = 0; c < S::WCB; ++c) {
         const int cb = S::WCB * wc + c;
-        bh[c] = *(const bf16x8 *)(base + (kFragA + (0 * S::NCB + cb) * kKS + ks) * 1024);
-        bl[c] = *(const bf16x8 *)(base + (kFragA + (1 * S::NCB + cb) * kKS + ks) * 1024);
+        bh[c] = *(const bf16x8 *)(base + (S::FA + (0 * S::NCB + cb) * kKS + ks) * 1024);
+        bl[c] = *(const bf16x8 *)(base + (S::FA + (1 * S::NCB + cb) * kKS + ks) * 1024);
       }
 #pragma unroll
       for (int r = 0; r < 2; ++r)
@@ -319,14 +328,26 @@ hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64
   return hipGetLastError();
 }
 
+int32_t bf16x3_tile_rows(int64_t n_pad) { return n_pad % 256 == 0 ? 256 : 128; }
+
 hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st) {
-  const int nrt = (int)(a.n_pad / 128), nct = (int)(a.ldv / a.bn);
+  const int bm = bf16x3_tile_rows(a.n_pad);
+  const int nrt = (int)(a.n_pad / bm), nct = (int)(a.ldv / a.bn);
   const unsigned grid = (unsigned)(nrt * nct * a.splits);
-  switch (a.bn) {
-    case 64: bf16x3_gemm_kernel<64><<<grid, 256, 0, st>>>(a); break;
-    case 128: bf16x3_gemm_kernel<128><<<grid, 256, 0, st>>>(a); break;
-    case 256: bf16x3_gemm_kernel<256><<<grid, 256, 0, st>>>(a); break;
-    default: return hipErrorInvalidValue;
+  if (bm == 256) {
+    switch (a.bn) {
+      case 64: bf16x3_gemm_kernel<64, 4><<<grid, 512, 0, st>>>(a); break;
+      case 128: bf16x3_gemm_kernel<128, 4><<<grid, 512, 0, st>>>(a); break;
+      case 256: bf16x3_gemm_kernel<256, 4><<<grid, 512, 0, st>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (a.bn) {
+      case 64: bf16x3_gemm_kernel<64, 2><<<grid, 256, 0, st>>>(a); break;
+      case 128: bf16x3_gemm_kernel<128, 2><<<grid, 256, 0, st>>>(a); break;
+      case 256: bf16x3_gemm_kernel<256, 2><<<grid, 256, 0, st>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

@@ -199,6 +199,11 @@ __global__ __launch_bounds__(1024) void jacobi_eig_kernel(double *__restrict__ A
   for (int i = tid; i < N; i += nt) eig[i] = A[i * N + i];
 }
 
+// Stopping tolerance of the Jacobi sweeps, relative to ||A||_F: rotations in
+// FP64 leave off-diagonal residue of order N eps ||A||_F (about 1.4e-14 at
+// N = 128), so a tolerance below that would never be met.
+constexpr double kJacobiTol = 1e-13;
+
 // Copy the s x s Gram matrix into an N x N (N even) work matrix.
 __global__ void pad_square_kernel(const double *__restrict__ G, int32_t s, double *__restrict__ A,
                                   int32_t N) {
@@ -245,9 +250,9 @@ hipError_t launch_rp_spectrum(const double *G, int32_t s, int32_t k, double *wor
   if (N > 256) return hipErrorInvalidValue;
   pad_square_kernel<<<64, 256, 0, st>>>(G, s, work, N);
   if (N <= 128)
-    jacobi_eig_kernel<true><<<1, 1024, 0, st>>>(work, N, 1e-14, 40, eig);
+    jacobi_eig_kernel<true><<<1, 1024, 0, st>>>(work, N, kJacobiTol, 40, eig);
   else
-    jacobi_eig_kernel<false><<<1, 1024, 0, st>>>(work, N, 1e-14, 40, eig);
+    jacobi_eig_kernel<false><<<1, 1024, 0, st>>>(work, N, kJacobiTol, 40, eig);
   rp_finish_kernel<<<1, 256, 0, st>>>(eig, N, k, sigma, scal);
   return hipGetLastError();
 }
