@@ -249,6 +249,9 @@ ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t 
 ent_status enqueue_power_split(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t n_pad,
                                int32_t t, int32_t q, uint64_t seed, double *x0, double *x1,
                                double *part3, double *norm, double *scal, hipStream_t st) {
+  // the split is zero beyond n, and so must be the vectors it multiplies
+  HIP_TRY(ent::launch_fill(x0, n_pad, 0.0, st));
+  HIP_TRY(ent::launch_fill(x1, n_pad, 0.0, st));
   for (int32_t trial = 0; trial < q; ++trial) {
     HIP_TRY(ent::launch_power_start(x0, n, seed, trial, st));
     double *xin = x0, *xout = x1;
@@ -522,7 +525,7 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   const int32_t nblk = ent::bf16x3_epilogue_blocks(n_pad);
   const int32_t nslot = m + 1;
   const bool use_power = !(o.u_fixed > 0);
-  const int32_t pblk = (int32_t)power_blocks(R);
+  const int32_t pblk = ent::power_blocks_split(n_pad);
 
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));

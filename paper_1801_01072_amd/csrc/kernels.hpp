@@ -190,8 +190,10 @@ hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, i
 // Rows of the GEMM's workgroup tile for a padded size (256 when it divides).
 int32_t bf16x3_tile_rows(int64_t n_pad);
 hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st);
-// Power-method product on the bf16 hi/lo split of R (ld = n_pad).
-hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64_t ld, int64_t n,
+// Power-method product on the fragment-major bf16 hi/lo split of R; x must
+// be zero in [n, n_pad).  power_blocks_split: its grid (= partial count).
+int32_t power_blocks_split(int64_t n_pad);
+hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64_t n_pad, int64_t n,
                                    const double *x, const double *in_norm, double *y, double *part3,
                                    int32_t *nblk, hipStream_t st);
 hipError_t launch_bf16x3_epilogue(const Bf16EpiArgs &a, hipStream_t st);

@@ -7,10 +7,17 @@
 // elementwise epilogue applies the recurrence in FP32, re-splits V_{k+1}
 // into hi/lo for the next product and accumulates the per-probe dots in FP64.
 //
-// All n x s blocks of this path are stored probe-major ([probe][row], leading
-// dimension n_pad): the MFMA B operand needs 8 consecutive k of one probe
-// (16 contiguous bytes), and the epilogue touches 8 consecutive rows of one
-// probe per thread.
+// Operand layout ("fragment-major"): the bf16 hi and lo arrays of A and of
+// V^T are stored in the order the MFMA consumes them.  Element (r, k) of an
+// R x K operand (r = matrix row for A, probe for V^T; k = the contraction
+// index) lives in 1 KB block (r / 32, k / 16), blocks ordered by r / 32 then
+// k / 16, at lane (r % 32) + 32 ((k % 16) / 8), element k % 8.  One block is
+// one MFMA operand fragment, so every load of the GEMM reads 1 KB of
+// contiguous memory and a workgroup streams each of its 32-row bands as one
+// contiguous run.  The FP32 blocks (G, V_k, V_{k+1}, split-K partials) stay
+// probe-major ([probe][row], leading dimension n_pad): the epilogue touches
+// 8 consecutive rows of one probe per thread, which are also 8 consecutive
+// elements of one lane in the fragment-major layout.
 //
 // MFMA 32x32x16 bf16 layout (lane l, measured on gfx950): A row l%32, k-slots
 // 8(l/32)..8(l/32)+7; B column l%32, same k-slots; D register r holds row
@@ -40,10 +47,15 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Element offset of (r, k) in the fragment-major layout (nkb = K / 16).
+__device__ __forceinline__ int64_t frag_off(int64_t r, int64_t k, int64_t nkb) {
+  return ((r >> 5) * nkb + (k >> 4)) * 512 + ((r & 31) + 32 * ((k >> 3) & 1)) * 8 + (k & 7);
+}
+
 // ---------------------------------------------------------------------------
-// A = a * R -> hi/lo (row-major, ld = n_pad, zero outside n x n); a =
-// scal[S_A], or 1 when scal is null (the split is then of R itself and the
-// scale is applied to the product in the epilogue).
+// A = a * R -> hi/lo, fragment-major, zero outside n x n; a = scal[S_A], or 1
+// when scal is null (the split is then of R itself and the scale is applied
+// to the product in the epilogue).  Thread = 8 consecutive columns of a row.
 // ---------------------------------------------------------------------------
 template <typename Tin>
 __global__ void split_matrix_kernel(const Tin *__restrict__ R, int64_t ldr, int64_t n, int64_t n_pad,
@@ -51,21 +63,29 @@ __global__ void split_matrix_kernel(const Tin *__restrict__ R, int64_t ldr, int6
                                     uint16_t *__restrict__ lo) {
   const int64_t row = blockIdx.y;
   const double a = scal ? scal[S_A] : 1.0;
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_pad;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    float v = 0.f;
-    if (row < n && c < n) v = (float)(a * (double)R[row * ldr + c]);
-    const uint16_t h = bf16_rne(v);
-    const uint16_t l = bf16_rne(v - bf16_to_f32(h));
-    hi[row * n_pad + c] = h;
-    lo[row * n_pad + c] = l;
+  const int64_t nkb = n_pad / 16;
+  for (int64_t c0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8; c0 < n_pad;
+       c0 += (int64_t)gridDim.x * blockDim.x * 8) {
+    u16x8 h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t c = c0 + e;
+      float v = 0.f;
+      if (row < n && c < n) v = (float)(a * (double)R[row * ldr + c]);
+      h[e] = bf16_rne(v);
+      l[e] = bf16_rne(v - bf16_to_f32(h[e]));
+    }
+    const int64_t off = frag_off(row, c0, nkb);
+    *(u16x8 *)(hi + off) = h;
+    *(u16x8 *)(lo + off) = l;
   }
 }
 
 template <typename Tin>
 hipError_t launch_split_matrix(const Tin *R, int64_t ldr, int64_t n, int64_t n_pad,
                                const double *scal, uint16_t *hi, uint16_t *lo, hipStream_t st) {
-  dim3 grid((unsigned)((n_pad + 255) / 256 < 32 ? (n_pad + 255) / 256 : 32), (unsigned)n_pad);
+  const int64_t groups = n_pad / 8;
+  dim3 grid((unsigned)((groups + 255) / 256 < 16 ? (groups + 255) / 256 : 16), (unsigned)n_pad);
   split_matrix_kernel<Tin><<<grid, 256, 0, st>>>(R, ldr, n, n_pad, scal, hi, lo);
   return hipGetLastError();
 }
@@ -75,28 +95,39 @@ template hipError_t launch_split_matrix<float>(const float *, int64_t, int64_t, 
                                                const double *, uint16_t *, uint16_t *, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Probe block, probe-major: G[j][i] (FP32) plus its hi/lo split.
+// Probe block: G[j][i] (FP32, probe-major) plus its hi/lo split
+// (fragment-major).  Thread = 8 consecutive rows of one probe.
 // ---------------------------------------------------------------------------
 __global__ void probe_gen_t_kernel(float *__restrict__ G, uint16_t *__restrict__ hi,
                                    uint16_t *__restrict__ lo, int64_t n, int64_t n_pad, int32_t s,
                                    int64_t ldv, uint64_t seed, int32_t dist, uint32_t stream,
                                    double scale) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ldv * n_pad) return;
-  const int64_t j = t / n_pad, i = t % n_pad;
-  float v = 0.f;
-  if (i < n && j < s)
-    v = (float)(scale * (dist == 0 ? rademacher(seed, stream, i, j) : gaussian(seed, stream, i, j)));
-  G[t] = v;
-  const uint16_t h = bf16_rne(v);
-  hi[t] = h;
-  lo[t] = bf16_rne(v - bf16_to_f32(h));
+  if (t >= ldv * (n_pad / 8)) return;
+  const int64_t j = t / (n_pad / 8), i0 = (t % (n_pad / 8)) * 8;
+  float v[8];
+  u16x8 h, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t i = i0 + e;
+    v[e] = 0.f;
+    if (i < n && j < s)
+      v[e] = (float)(scale * (dist == 0 ? rademacher(seed, stream, i, j) : gaussian(seed, stream, i, j)));
+    h[e] = bf16_rne(v[e]);
+    l[e] = bf16_rne(v[e] - bf16_to_f32(h[e]));
+  }
+  f32x4 *g = (f32x4 *)(G + j * n_pad + i0);
+  g[0] = f32x4{v[0], v[1], v[2], v[3]};
+  g[1] = f32x4{v[4], v[5], v[6], v[7]};
+  const int64_t off = frag_off(j, i0, n_pad / 16);
+  *(u16x8 *)(hi + off) = h;
+  *(u16x8 *)(lo + off) = l;
 }
 
 hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, int64_t n_pad,
                               int32_t s, int64_t ldv, uint64_t seed, int32_t dist, hipStream_t st,
                               uint32_t stream, double scale) {
-  const int64_t tot = ldv * n_pad;
+  const int64_t tot = ldv * (n_pad / 8);
   probe_gen_t_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(G, hi, lo, n, n_pad, s, ldv, seed,
                                                                    dist, stream, scale);
   return hipGetLastError();
@@ -106,13 +137,12 @@ hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, i
 // GEMM: part_y[ks][j][i] = sum_{k in split ks} (A_hi V_hi + A_hi V_lo + A_lo V_hi)[i][j]
 //
 // Workgroup tile: BM = 64 WM rows x BN probes over one K-split, 2 WM waves
-// in a WM x 2 grid (64 rows x BN/2 probes each).  Operands reach LDS by
-// direct global-to-LDS loads (no registers) in a ring of kStages(WM) stages
-// of BK = 32: the next stages are in flight while one is computed.  LDS holds
-// every operand in the MFMA's own fragment order: a fragment (32 rows or
-// probes x 16 k, hi or lo) is 1 KB with lane l's 8 k-values at byte 16 l, so
-// the loads that fill it and the ds_read_b128 that consume it are both
-// contiguous per wave.
+// in a WM x 2 grid (64 rows x BN/2 probes each).  Operand fragments (1 KB
+// blocks of the fragment-major layout) reach LDS by direct global-to-LDS
+// loads (no registers) in a ring of stages of BK = 32: the next stages are in
+// flight while one is computed.  A fragment keeps its layout in LDS (lane l's
+// 8 k-values at byte 16 l), so both the loads that fill it and the
+// ds_read_b128 that consume it are contiguous per wave.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int kBK = 32;        // k per stage
@@ -163,7 +193,9 @@ __global__ __launch_bounds__(128 * WM) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
   const int64_t row0 = (int64_t)rt * S::BM, col0 = (int64_t)ct * BN;
   const int m32 = lane & 31, kh = lane >> 5;
 
-  // per-lane source of each fragment this wave loads (advanced by kBK per stage)
+  // per-lane source of each fragment this wave loads (a stage advances kKS
+  // blocks of 512 elements)
+  const int64_t nkb = npad / 16;
   const uint16_t *src[S::PER_WAVE];
 #pragma unroll
   for (int i = 0; i < S::PER_WAVE; ++i) {
@@ -171,19 +203,19 @@ __global__ __launch_bounds__(128 * WM) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
     const uint16_t *p;
     if (f < S::FA) {
       const int hl = f / (S::NRB * kKS), rb = (f / kKS) % S::NRB, ks = f % kKS;
-      p = (hl ? a.A_lo : a.A_hi) + (row0 + 32 * rb + m32) * npad + 16 * ks + 8 * kh;
+      p = (hl ? a.A_lo : a.A_hi) + ((row0 / 32 + rb) * nkb + kbeg / 16 + ks) * 512;
     } else {
       const int g = f - S::FA;
       const int hl = g / (S::NCB * kKS), cb = (g / kKS) % S::NCB, ks = g % kKS;
-      p = (hl ? a.V_lo : a.V_hi) + (col0 + 32 * cb + m32) * npad + 16 * ks + 8 * kh;
+      p = (hl ? a.V_lo : a.V_hi) + ((col0 / 32 + cb) * nkb + kbeg / 16 + ks) * 512;
     }
-    src[i] = p + kbeg;
+    src[i] = p + 8 * lane;
   }
   auto issue = [&](int t) {
     uint8_t *base = lds + (t % S::STAGES) * S::FST * 1024;
 #pragma unroll
     for (int i = 0; i < S::PER_WAVE; ++i)
-      __builtin_amdgcn_global_load_lds((const void *)(src[i] + (int64_t)t * kBK),
+      __builtin_amdgcn_global_load_lds((const void *)(src[i] + (int64_t)t * kKS * 512),
                                        (__attribute__((address_space(3))) void *)(base + (w + S::WAVES * i) * 1024),
                                        16, 0, 0);
   };
@@ -265,66 +297,72 @@ __global__ __launch_bounds__(128 * WM) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
 
 // ---------------------------------------------------------------------------
 // Power-method product on the split of R: y = ((hi + lo) x)/||x_prev|| with
-// FP64 accumulation (hi + lo is exact in FP32).  Each wave owns 2 rows;
-// lanes stride over 8-element (16-byte) vectors of hi and lo.
+// FP64 accumulation (hi + lo is exact in FP32), reading the fragment-major
+// split.  Workgroup = one 32-row band; its 16 waves take every 16th 16-column
+// block, each lane 8 columns of one row; x must be zero beyond n.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void power_gemv_split_kernel(const uint16_t *__restrict__ hi,
+__global__ __launch_bounds__(1024) void power_gemv_split_kernel(const uint16_t *__restrict__ hi,
                                                                const uint16_t *__restrict__ lo,
-                                                               int64_t ld, int64_t n,
+                                                               int64_t n_pad, int64_t n,
                                                                const double *__restrict__ x,
                                                                const double *__restrict__ in_norm,
                                                                double *__restrict__ y,
                                                                double *__restrict__ part3) {
+  constexpr int W = 16;
+  __shared__ double red[W][32];
   const double sc = in_norm ? 1.0 / sqrt(in_norm[0]) : 1.0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 2;
-  const bool ok0 = r0 < n, ok1 = r0 + 1 < n;
-  const int64_t o0 = (ok0 ? r0 : 0) * ld, o1 = (ok1 ? r0 + 1 : 0) * ld;
-  double a0 = 0.0, a1 = 0.0;
-  const int64_t nvec = n / 8;
-  for (int64_t v = lane; v < nvec; v += 64) {
-    const int64_t k = v * 8;
-    const u16x8 h0 = *(const u16x8 *)(hi + o0 + k), l0 = *(const u16x8 *)(lo + o0 + k);
-    const u16x8 h1 = *(const u16x8 *)(hi + o1 + k), l1 = *(const u16x8 *)(lo + o1 + k);
+  const int64_t nkb = n_pad / 16;
+  const int64_t band = blockIdx.x;
+  const uint16_t *H = hi + band * nkb * 512 + 8 * lane;
+  const uint16_t *Lo = lo + band * nkb * 512 + 8 * lane;
+  const int64_t kofs = 8 * (lane >> 5);
+  double acc = 0.0, acc2 = 0.0;
+  int64_t kb = w;
+  for (; kb + W < nkb; kb += 2 * W) {
+    const u16x8 h0 = *(const u16x8 *)(H + kb * 512), l0 = *(const u16x8 *)(Lo + kb * 512);
+    const u16x8 h1 = *(const u16x8 *)(H + (kb + W) * 512), l1 = *(const u16x8 *)(Lo + (kb + W) * 512);
+    const double *x0 = x + kb * 16 + kofs, *x1 = x + (kb + W) * 16 + kofs;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const double xe = x[k + e];
-      a0 += (double)(bf16_to_f32(h0[e]) + bf16_to_f32(l0[e])) * xe;
-      a1 += (double)(bf16_to_f32(h1[e]) + bf16_to_f32(l1[e])) * xe;
+      acc += (double)(bf16_to_f32(h0[e]) + bf16_to_f32(l0[e])) * x0[e];
+      acc2 += (double)(bf16_to_f32(h1[e]) + bf16_to_f32(l1[e])) * x1[e];
     }
   }
-  for (int64_t k = nvec * 8 + lane; k < n; k += 64) {
-    const double xe = x[k];
-    a0 += (double)(bf16_to_f32(hi[o0 + k]) + bf16_to_f32(lo[o0 + k])) * xe;
-    a1 += (double)(bf16_to_f32(hi[o1 + k]) + bf16_to_f32(lo[o1 + k])) * xe;
+  for (; kb < nkb; kb += W) {
+    const u16x8 h0 = *(const u16x8 *)(H + kb * 512), l0 = *(const u16x8 *)(Lo + kb * 512);
+    const double *x0 = x + kb * 16 + kofs;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc += (double)(bf16_to_f32(h0[e]) + bf16_to_f32(l0[e])) * x0[e];
   }
-  const double s0 = wave_sum(a0), s1 = wave_sum(a1);
+  acc += acc2;
+  acc += __shfl_xor(acc, 32, 64);  // the two 8-column halves of a row
+  if (lane < 32) red[w][lane] = acc;
+  __syncthreads();
   double yy = 0.0, xy = 0.0, xx = 0.0;
-  if (lane == 0) {
-    if (ok0) {
-      const double yv = sc * s0, xs = sc * x[r0];
-      y[r0] = yv;
-      yy += yv * yv;
-      xy += xs * yv;
-      xx += xs * xs;
-    }
-    if (ok1) {
-      const double yv = sc * s1, xs = sc * x[r0 + 1];
-      y[r0 + 1] = yv;
-      yy += yv * yv;
-      xy += xs * yv;
-      xx += xs * xs;
+  if (w == 0 && lane < 32) {
+    const int64_t r = band * 32 + lane;
+    double s = 0.0;
+    for (int q = 0; q < W; ++q) s += red[q][lane];
+    if (r < n) {
+      const double yv = sc * s, xs = sc * x[r];
+      y[r] = yv;
+      yy = yv * yv;
+      xy = xs * yv;
+      xx = xs * xs;
     }
   }
   block_power_partials(yy, xy, xx, part3, blockIdx.x);
 }
 
-hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64_t ld, int64_t n,
+int32_t power_blocks_split(int64_t n_pad) { return (int32_t)(n_pad / 32); }
+
+hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64_t n_pad, int64_t n,
                                    const double *x, const double *in_norm, double *y, double *part3,
                                    int32_t *nblk, hipStream_t st) {
-  const int32_t blocks = power_blocks_dense(n);
+  const int32_t blocks = power_blocks_split(n_pad);
   *nblk = blocks;
-  power_gemv_split_kernel<<<(unsigned)blocks, 256, 0, st>>>(hi, lo, ld, n, x, in_norm, y, part3);
+  power_gemv_split_kernel<<<(unsigned)blocks, 1024, 0, st>>>(hi, lo, n_pad, n, x, in_norm, y, part3);
   return hipGetLastError();
 }
 
@@ -411,8 +449,9 @@ __global__ __launch_bounds__(256) void bf16x3_epilogue_kernel(Bf16EpiArgs a) {
       f32x4 *o = (f32x4 *)(a.Vkp1 + off);
       o[0] = f32x4{z[0], z[1], z[2], z[3]};
       o[1] = f32x4{z[4], z[5], z[6], z[7]};
-      *(u16x8 *)(a.V_hi + off) = zh;
-      *(u16x8 *)(a.V_lo + off) = zl;
+      const int64_t foff = frag_off(j, i0, npad / 16);
+      *(u16x8 *)(a.V_hi + foff) = zh;
+      *(u16x8 *)(a.V_lo + foff) = zl;
     }
   }
   if (a.slot < 0) return;

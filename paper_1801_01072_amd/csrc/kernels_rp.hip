@@ -102,7 +102,7 @@ template <bool IN_LDS>
 __global__ __launch_bounds__(1024) void jacobi_eig_kernel(double *__restrict__ Ag, int32_t N,
                                                           double tol, int32_t max_sweeps,
                                                           double *__restrict__ eig) {
-  __shared__ double As[IN_LDS ? 128 * 128 : 1];
+  __shared__ double As[IN_LDS ? 128 * 129 : 1];  // row stride N + 1: no bank conflicts down a column
   __shared__ int sp[128], sq[128];
   __shared__ double sc[128], ss[128];
   __shared__ double red[16];
@@ -110,15 +110,16 @@ __global__ __launch_bounds__(1024) void jacobi_eig_kernel(double *__restrict__ A
   const int tid = threadIdx.x, nt = blockDim.x;
   const int half = N / 2;
   double *A = IN_LDS ? As : Ag;
+  const int ld = IN_LDS ? N + 1 : N;
   if (IN_LDS) {
-    for (int e = tid; e < N * N; e += nt) As[e] = Ag[e];
+    for (int e = tid; e < N * N; e += nt) As[(e / N) * ld + e % N] = Ag[e];
     __syncthreads();
   }
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
     // convergence test
     double off = 0.0, fro = 0.0;
     for (int e = tid; e < N * N; e += nt) {
-      const double v = A[e];
+      const double v = A[(e / N) * ld + e % N];
       fro += v * v;
       if (e / N != e % N) off += v * v;
     }
@@ -155,10 +156,10 @@ __global__ __launch_bounds__(1024) void jacobi_eig_kernel(double *__restrict__ A
           p = q;
           q = tmp;
         }
-        const double apq = A[p * N + q];
+        const double apq = A[p * ld + q];
         double c = 1.0, s = 0.0;
         if (apq != 0.0) {
-          const double theta = (A[q * N + q] - A[p * N + p]) / (2.0 * apq);
+          const double theta = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
           const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
           s = t * c;
@@ -174,9 +175,9 @@ __global__ __launch_bounds__(1024) void jacobi_eig_kernel(double *__restrict__ A
         const int i = e / N, k = e % N;
         const int p = sp[i], q = sq[i];
         const double c = sc[i], s = ss[i];
-        const double apk = A[p * N + k], aqk = A[q * N + k];
-        A[p * N + k] = c * apk - s * aqk;
-        A[q * N + k] = s * apk + c * aqk;
+        const double apk = A[p * ld + k], aqk = A[q * ld + k];
+        A[p * ld + k] = c * apk - s * aqk;
+        A[q * ld + k] = s * apk + c * aqk;
       }
       __syncthreads();
       // columns p, q of every pair
@@ -184,19 +185,19 @@ __global__ __launch_bounds__(1024) void jacobi_eig_kernel(double *__restrict__ A
         const int i = e / N, k = e % N;
         const int p = sp[i], q = sq[i];
         const double c = sc[i], s = ss[i];
-        const double akp = A[k * N + p], akq = A[k * N + q];
-        A[k * N + p] = c * akp - s * akq;
-        A[k * N + q] = s * akp + c * akq;
+        const double akp = A[k * ld + p], akq = A[k * ld + q];
+        A[k * ld + p] = c * akp - s * akq;
+        A[k * ld + q] = s * akp + c * akq;
       }
       __syncthreads();
       if (tid < half) {
-        A[sp[tid] * N + sq[tid]] = 0.0;
-        A[sq[tid] * N + sp[tid]] = 0.0;
+        A[sp[tid] * ld + sq[tid]] = 0.0;
+        A[sq[tid] * ld + sp[tid]] = 0.0;
       }
       __syncthreads();
     }
   }
-  for (int i = tid; i < N; i += nt) eig[i] = A[i * N + i];
+  for (int i = tid; i < N; i += nt) eig[i] = A[i * ld + i];
 }
 
 // Stopping tolerance of the Jacobi sweeps, relative to ||A||_F: rotations in
