@@ -54,6 +54,7 @@ WORKLOADS = {
 
 KERNEL_SOURCES = {
     "bf16x3_gemm_kernel": "kernels_bf16.hip",
+    "batch_bf16x3_gemm_kernel": "kernels_bf16.hip",
     "dense_step_kernel": "kernels_dense.hip",
     "batch_dense_step_kernel": "kernels_dense.hip",
     "csr_step_kernel": "kernels_csr.hip",
@@ -145,11 +146,12 @@ def bench_batch(args, cfg):
     log(f"timed {args.steps} batch launches: {ms_per_step:.2f} ms per batch of {count}")
     tms = [g.time_eager()[1] for _ in range(3)]
     avg_step_ms = float(np.mean([x["steps_ms"] / x["step_launches"] for x in tms]))
-    phases = {k: float(np.mean([x[k] for x in tms])) for k in ("total_ms", "power_ms", "steps_ms", "other_ms")}
+    phases = {k: float(np.mean([x[k] for x in tms])) for k in ("total_ms", "power_ms", "steps_ms", "epilogue_ms", "other_ms")}
     flop = 2.0 * sum_n2 * s
     achieved = flop / (avg_step_ms * 1e-3) / 1e12
     peak = MFMA_PEAK_TFLOPS[precision]
-    log(f"batch_dense_step_kernel: {avg_step_ms:.3f} ms/launch -> {achieved:.1f} TFLOP/s; phases {phases}")
+    kernel = "batch_bf16x3_gemm_kernel" if precision == "bf16x3" else "batch_dense_step_kernel"
+    log(f"{kernel}: {avg_step_ms:.3f} ms/launch -> {achieved:.1f} TFLOP/s; phases {phases}")
     cpu = None
     max_rel = None
     H_exact = [float(-np.sum(p[p > 0] * np.log(p[p > 0]))) for p in spectra]
@@ -187,8 +189,9 @@ def bench_batch(args, cfg):
                    "count": count, "sum_n2": sum_n2, "precision": precision,
                    "tile_rows": g.tile_rows, "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic("batch_dense_step_kernel", args.workload),
-                     "kernel": "batch_dense_step_kernel",
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(kernel, args.workload + ("" if precision == "f32" else "_" + precision)),
+                     "kernel": kernel,
                      "avg_launch_ms": avg_step_ms, "algorithmic_flop_per_launch": flop},
         "cpu_baseline": cpu,
         "phases_ms": phases,

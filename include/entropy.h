@@ -257,11 +257,11 @@ ent_status ent_last_timing(ent_timing *out);
 /*
  * Batches of dense density matrices (uneven n): every phase of the estimate
  * runs as one grouped launch over all matrices.  Matrix b uses probe seed
- * seed + b.  Precision ENT_F32 or ENT_F64 (compute); storage of all matrices
- * must be the same type.  Each matrix is copied into an aligned compute-type
- * buffer at the start of every run (so later changes of the caller's values
- * are seen by the next launch; the caller's pointers must stay valid while a
- * graph exists).
+ * seed + b.  Precision ENT_F32, ENT_F64 or ENT_BF16X3 (probes <= 256);
+ * storage of all matrices must be the same type.  Each matrix is copied into
+ * an aligned compute-type buffer (BF16x3: split into bf16 hi/lo) at the start
+ * of every run, so later changes of the caller's values are seen by the next
+ * launch; the caller's pointers must stay valid while a graph exists.
  *
  * ent_entropy_estimate_batched: one synchronous run; outs[count].
  * ent_graph_create: plans the batch (workspace, descriptor and tile tables,
@@ -284,7 +284,7 @@ ent_status ent_graph_create(const ent_matrix *Rs, int32_t count, int32_t method,
 ent_status ent_graph_launch(ent_graph graph, ent_result *outs);
 ent_status ent_graph_per_probe(ent_graph graph, double *per_probe);
 ent_status ent_graph_time_eager(ent_graph graph, ent_result *outs, ent_timing *timing);
-int32_t ent_graph_tile_rows(ent_graph graph);       /* 64 or 128 (chosen tile shape) */
+int32_t ent_graph_tile_rows(ent_graph graph);       /* 64 or 128 (chosen tile shape; BF16x3: 128) */
 size_t ent_graph_workspace_bytes(ent_graph graph);
 ent_status ent_graph_destroy(ent_graph graph);
 

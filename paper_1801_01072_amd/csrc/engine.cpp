@@ -1009,7 +1009,7 @@ struct ent_graph_s {
   int32_t count = 0, method = 0, m = 0, s = 0, nslot = 0;
   ent_options o{};
   bool src_f64 = false, comp_f64 = false;
-  int64_t ldv = 0, sb = 0, max_n = 0, max_npad = 0, max_elems = 0;
+  int64_t ldv = 0, sb = 0, max_n = 0, max_npad = 0, max_elems = 0, xlen = 0;
   int32_t wr = 1, ntiles1 = 0, ntiles2 = 0, nptiles = 0;
   std::vector<ent::BatchMat> mats;
   std::vector<int2> tiles1, tiles2, ptiles;
@@ -1021,6 +1021,13 @@ struct ent_graph_s {
   double *x0 = nullptr, *x1 = nullptr, *p0 = nullptr, *norm = nullptr;
   double *part = nullptr, *d = nullptr, *h = nullptr, *scal = nullptr;
   double *host_scal = nullptr;
+  // BF16x3 batches: split of every R, bf16 probe blocks, FP32 products
+  bool bf16 = false;
+  uint16_t *Ahi = nullptr, *Alo = nullptr, *Vhi = nullptr, *Vlo = nullptr;
+  float *Y = nullptr;
+  std::vector<int2> etiles;
+  int2 *etiles_d = nullptr;
+  int32_t netiles = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool launched = false;
@@ -1109,7 +1116,100 @@ ent_status enqueue_batch(ent_graph_s *g, hipStream_t st, PhaseEvents *pe) {
   return ENT_OK;
 }
 
+// BF16x3 batch: split each R once (unscaled), power method on the split, then
+// per step one grouped GEMM over every (matrix, 128-row tile) and one grouped
+// epilogue (the interval scale a is applied there).
+ent_status enqueue_batch_bf16(ent_graph_s *g, hipStream_t st, PhaseEvents *pe) {
+  const ent_options &o = g->o;
+  const int32_t count = g->count;
+  HIP_TRY(ent::launch_fill(g->scal, (int64_t)count * g->sb, 0.0, st));
+  if (!(o.flags & ENT_FLAG_SKIP_TRACE_CHECK)) {
+    if (g->src_f64)
+      HIP_TRY(ent::launch_batch_trace<double>(g->mats_d, count, st));
+    else
+      HIP_TRY(ent::launch_batch_trace<float>(g->mats_d, count, st));
+  }
+  if (g->src_f64)
+    HIP_TRY(ent::launch_batch_split<double>(g->mats_d, g->tiles2_d, g->ntiles2, g->Ahi, g->Alo, st));
+  else
+    HIP_TRY(ent::launch_batch_split<float>(g->mats_d, g->tiles2_d, g->ntiles2, g->Ahi, g->Alo, st));
+  HIP_TRY(ent::launch_batch_probe_t(g->mats_d, g->tiles2_d, g->ntiles2, (float *)g->G, g->Vhi, g->Vlo,
+                                    g->s, g->ldv, o.probe_dist, st));
+  if (!(o.u_fixed > 0)) {
+    if (pe) pe->power_begin = pe->mark();
+    // the split is zero beyond n, and so must be the vectors it multiplies
+    HIP_TRY(ent::launch_fill(g->x0, g->xlen, 0.0, st));
+    HIP_TRY(ent::launch_fill(g->x1, g->xlen, 0.0, st));
+    for (int32_t trial = 0; trial < o.power_trials; ++trial) {
+      HIP_TRY(ent::launch_batch_power_start(g->mats_d, count, g->max_n, g->x0, trial, st));
+      double *xin = g->x0, *xout = g->x1;
+      const double *in_norm = nullptr;
+      for (int32_t it = 0; it <= o.power_iters; ++it) {
+        HIP_TRY(ent::launch_batch_power_split(g->mats_d, g->ptiles_d, g->nptiles, g->Ahi, g->Alo, xin,
+                                              in_norm, xout, g->p0, st));
+        HIP_TRY(ent::launch_batch_power_reduce(g->mats_d, count, g->p0, g->norm, st));
+        std::swap(xin, xout);
+        in_norm = g->norm;
+      }
+      HIP_TRY(ent::launch_batch_power_rq(g->mats_d, count, g->norm, trial, st));
+    }
+    if (pe) {
+      pe->power_end = pe->mark();
+      pe->power_launches = o.power_trials * (o.power_iters + 1);
+    }
+  }
+  HIP_TRY(ent::launch_batch_setup(g->mats_d, count, g->method, g->m, o.u_factor, o.u_fixed,
+                                  o.cutoff, st));
+  const int32_t nsteps = (g->method == ENT_CHEBYSHEV) ? g->m : g->m + 1;
+  const float *Vk = (const float *)g->G, *Vkm1 = nullptr;
+  float *bufs[2] = {(float *)g->VA, (float *)g->VB};
+  if (pe) pe->steps_begin = pe->mark();
+  for (int32_t k = 0; k < nsteps; ++k) {
+    float *Vout = bufs[k & 1];
+    ent::Bf16EpiArgs ea{};
+    bool write = true;
+    if (g->method == ENT_CHEBYSHEV) {
+      ea.dot_y = 0;
+      ea.slot = k + 1;
+      if (k == 0) {
+        ea.c1 = 1.0; ea.c2 = -1.0; ea.cw = 0.0;
+        ea.slot_gg = 0;
+      } else {
+        ea.c1 = 2.0; ea.c2 = -2.0; ea.cw = -1.0;
+        ea.slot_gg = -1;
+      }
+    } else {
+      ea.c1 = -1.0; ea.c2 = 1.0; ea.cw = 0.0;
+      ea.dot_y = 1;
+      ea.slot = k;
+      ea.slot_gg = -1;
+      write = k < nsteps - 1;
+    }
+    const int e0 = pe ? pe->mark() : -1;
+    HIP_TRY(ent::launch_batch_bf16x3_gemm(g->mats_d, g->tiles2_d, g->ntiles2, g->ldv, g->Ahi, g->Alo,
+                                          g->Vhi, g->Vlo, g->Y, st));
+    const int e1 = pe ? pe->mark() : -1;
+    ea.part_y = g->Y; ea.splits = 1; ea.Vk = Vk;
+    ea.Vkm1 = (g->method == ENT_CHEBYSHEV && k > 0) ? Vkm1 : nullptr;
+    ea.Vkp1 = write ? Vout : nullptr; ea.V_hi = g->Vhi; ea.V_lo = g->Vlo; ea.G = (const float *)g->G;
+    ea.scale_y = 1; ea.part = g->part; ea.ldv = g->ldv;
+    HIP_TRY(ent::launch_batch_bf16x3_epilogue(ea, g->mats_d, g->etiles_d, g->netiles, st));
+    if (pe) {
+      const int e2 = pe->mark();
+      pe->main_spans.push_back({e0, e1});
+      pe->epi_spans.push_back({e1, e2});
+      if (k == nsteps - 1) pe->steps_end = e2;
+    }
+    if (g->method == ENT_CHEBYSHEV) Vkm1 = Vk;
+    Vk = Vout;
+  }
+  HIP_TRY(ent::launch_batch_reduce(g->mats_d, count, g->part, g->nslot, g->ldv, g->s, g->d, st));
+  HIP_TRY(ent::launch_batch_final(g->mats_d, count, g->d, g->method, g->m, g->s, g->h, st));
+  return ENT_OK;
+}
+
 ent_status batch_enqueue(ent_graph_s *g, hipStream_t st, PhaseEvents *pe) {
+  if (g->bf16) return enqueue_batch_bf16(g, st, pe);
   return g->comp_f64 ? enqueue_batch<double>(g, st, pe) : enqueue_batch<float>(g, st, pe);
 }
 
@@ -1211,8 +1311,6 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
   if (rc != ENT_OK) return rc;
   if (method == ENT_TAYLOR && op.o.cutoff > 0)
     return fail(ENT_EINVAL, "cutoff applies to the Chebyshev method only");
-  if (op.o.precision == ENT_BF16X3)
-    return fail(ENT_EUNSUPPORTED, "batches run in F32 or F64 in this build");
   for (int32_t b = 0; b < count; ++b) {
     rc = validate_matrix(&Rs[b]);
     if (rc != ENT_OK) return fail(rc, "matrix %d: %s", b, g_last_error.c_str());
@@ -1228,8 +1326,17 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
   g->o = op.o;
   g->src_f64 = Rs[0].dtype == ENT_STORE_F64;
   g->comp_f64 = op.o.precision == ENT_F64;
+  g->bf16 = op.o.precision == ENT_BF16X3;
   const size_t esz = g->comp_f64 ? 8 : 4;
   g->ldv = round_up(s, 64);
+  if (g->bf16) {
+    // one probe tile per matrix in the grouped GEMM: 64, 128 or 256 probes
+    if (s > 256) {
+      delete g;
+      return fail(ENT_EUNSUPPORTED, "BF16x3 batches take at most 256 probes");
+    }
+    g->ldv = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
+  }
   g->sb = round_up(ent::S_ALPHA + m + 1 + 8, 32);
   auto fail_free = [&](ent_status st) {
     batch_free(g);
@@ -1239,7 +1346,7 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
   if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess)
     return fail_free(fail(ENT_EDEVICE, "hipStreamCreate failed"));
   // layout of every per-matrix region
-  int64_t roff = 0, voff = 0, poff = 0, xoff = 0, pboff = 0;
+  int64_t roff = 0, voff = 0, poff = 0, xoff = 0, pboff = 0, aoff = 0;
   g->mats.resize(count);
   for (int32_t b = 0; b < count; ++b) {
     ent::BatchMat &M = g->mats[b];
@@ -1249,17 +1356,25 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
     M.ldr = round_up(n, 8);
     M.n = n;
     M.n_pad = round_up(n, 128);
-    M.ntile = (int32_t)(M.n_pad / 64);
-    M.pblk = ent::power_blocks_dense(n);
+    M.ntile = g->bf16 ? ent::bf16x3_epilogue_blocks(M.n_pad) : (int32_t)(M.n_pad / 64);
+    M.pblk = g->bf16 ? ent::power_blocks_split(M.n_pad) : ent::power_blocks_dense(n);
     M.seed = seed + (uint64_t)b;
     M.R = (const void *)(intptr_t)roff;  // offsets for now; rebased below
     M.voff = voff;
     M.poff = poff;
     M.xoff = xoff;
     M.pboff = pboff;
+    M.aoff = aoff;
     M.doff = (int64_t)b * g->nslot * s;
     M.hoff = (int64_t)b * s;
-    roff += n * M.ldr;
+    if (g->bf16) {
+      // the split reads the caller's matrix; the trace check reads it too
+      M.R = Rs[b].values;
+      M.ldr = Rs[b].ld;
+      aoff += M.n_pad * M.n_pad;
+    } else {
+      roff += n * M.ldr;
+    }
     voff += M.n_pad * g->ldv;
     poff += (int64_t)g->nslot * M.ntile * g->ldv;
     xoff += M.n_pad;
@@ -1278,17 +1393,29 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
     for (int32_t t = 0; t < (int32_t)(M.n_pad / 64); ++t) g->tiles1.push_back(make_int2(b, t));
     for (int32_t t = 0; t < (int32_t)(M.n_pad / 128); ++t) g->tiles2.push_back(make_int2(b, t));
     for (int32_t t = 0; t < M.pblk; ++t) g->ptiles.push_back(make_int2(b, t));
+    if (g->bf16)
+      for (int32_t t = 0; t < M.ntile; ++t) g->etiles.push_back(make_int2(b, t));
   }
   g->ntiles1 = (int32_t)g->tiles1.size();
   g->ntiles2 = (int32_t)g->tiles2.size();
   g->nptiles = (int32_t)g->ptiles.size();
+  g->netiles = (int32_t)g->etiles.size();
+  g->xlen = xoff;
   Carve cv;
   cv.add(&g->mats_d, (size_t)count);
   cv.add(&g->tiles1_d, g->tiles1.size());
   cv.add(&g->tiles2_d, g->tiles2.size());
   cv.add(&g->ptiles_d, g->ptiles.size());
+  if (g->bf16) {
+    cv.add(&g->etiles_d, g->etiles.size());
+    cv.add(&g->Ahi, (size_t)aoff);
+    cv.add(&g->Alo, (size_t)aoff);
+    cv.add(&g->Vhi, (size_t)voff);
+    cv.add(&g->Vlo, (size_t)voff);
+    cv.add(&g->Y, (size_t)voff);
+  }
   cv.add(&g->scal, (size_t)count * g->sb);
-  cv.add(&g->Rc, (size_t)roff * esz);
+  if (!g->bf16) cv.add(&g->Rc, (size_t)roff * esz);
   cv.add(&g->G, (size_t)voff * esz);
   cv.add(&g->VA, (size_t)voff * esz);
   cv.add(&g->VB, (size_t)voff * esz);
@@ -1313,16 +1440,19 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
     return fail_free(fail(ENT_ENOMEM, "pinned host buffer allocation failed"));
   for (int32_t b = 0; b < count; ++b) {
     ent::BatchMat &M = g->mats[b];
-    M.R = g->Rc + (intptr_t)M.R * esz;
+    if (!g->bf16) M.R = g->Rc + (intptr_t)M.R * esz;
     M.scal = g->scal + (int64_t)b * g->sb;
   }
   if (hipMemcpy(g->tiles1_d, g->tiles1.data(), sizeof(int2) * g->tiles1.size(), hipMemcpyHostToDevice) ||
       hipMemcpy(g->tiles2_d, g->tiles2.data(), sizeof(int2) * g->tiles2.size(), hipMemcpyHostToDevice) ||
-      hipMemcpy(g->ptiles_d, g->ptiles.data(), sizeof(int2) * g->ptiles.size(), hipMemcpyHostToDevice))
+      hipMemcpy(g->ptiles_d, g->ptiles.data(), sizeof(int2) * g->ptiles.size(), hipMemcpyHostToDevice) ||
+      (g->bf16 && hipMemcpy(g->etiles_d, g->etiles.data(), sizeof(int2) * g->etiles.size(),
+                            hipMemcpyHostToDevice)))
     return fail_free(fail(ENT_EDEVICE, "descriptor upload failed"));
-  // tile shape: cached choice, else timed on this batch when asked, else 64-row tiles
+  // tile shape: cached choice, else timed on this batch when asked, else
+  // 64-row tiles (BF16x3 batches have one shape: 128-row GEMM tiles)
   const std::string key = batch_tune_key(g);
-  int wr = 0;
+  int wr = g->bf16 ? 2 : 0;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
@@ -1341,8 +1471,15 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
       wr = 1;
     }
   }
-  rc = batch_upload(g, wr);
-  if (rc != ENT_OK) return fail_free(rc);
+  if (g->bf16) {
+    if (hipMemcpy(g->mats_d, g->mats.data(), sizeof(ent::BatchMat) * g->mats.size(),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return fail_free(fail(ENT_EDEVICE, "descriptor upload failed"));
+    g->wr = 2;
+  } else {
+    rc = batch_upload(g, wr);
+    if (rc != ENT_OK) return fail_free(rc);
+  }
   if (capture) {
     if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return fail_free(fail(ENT_EDEVICE, "hipStreamBeginCapture failed"));
@@ -1595,7 +1732,7 @@ ent_status ent_graph_time_eager(ent_graph graph, ent_result *outs, ent_timing *t
   return ENT_OK;
 }
 
-int32_t ent_graph_tile_rows(ent_graph graph) { return graph ? 64 * graph->wr : -1; }
+int32_t ent_graph_tile_rows(ent_graph graph) { return graph ? 64 * graph->wr : -1; }  // BF16x3: 128
 
 size_t ent_graph_workspace_bytes(ent_graph graph) { return graph ? graph->ws_bytes : 0; }
 

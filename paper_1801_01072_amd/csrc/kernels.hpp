@@ -79,8 +79,9 @@ struct BatchMat {
   int64_t hoff;    // per-probe values [s]
   double *scal;    // scalar block
   uint64_t seed;   // probe seed of this matrix
-  int32_t ntile;   // row tiles of the step kernel
+  int32_t ntile;   // row tiles of the step kernel (BF16x3: epilogue blocks)
   int32_t pblk;    // power-method blocks
+  int64_t aoff;    // BF16x3: bf16 hi/lo split of R (n_pad x n_pad, fragment-major)
 };
 
 struct BatchStepArgs {
@@ -198,6 +199,24 @@ hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64
                                    int32_t *nblk, hipStream_t st);
 hipError_t launch_bf16x3_epilogue(const Bf16EpiArgs &a, hipStream_t st);
 int32_t bf16x3_epilogue_blocks(int64_t n_pad);
+// ---- BF16x3 batches (descriptor-driven; tables of (matrix, tile) pairs) ----
+// tiles: (matrix, 128-row tile); ptiles: (matrix, 32-row band); etiles:
+// (matrix, epilogue block).  G/VA/VB/Y are FP32 probe-major at M.voff; the
+// bf16 V hi/lo at M.voff and A hi/lo at M.aoff are fragment-major.
+template <typename Tin>
+hipError_t launch_batch_split(const BatchMat *mats, const int2 *tiles, int32_t ntiles, uint16_t *Ahi,
+                              uint16_t *Alo, hipStream_t st);
+hipError_t launch_batch_probe_t(const BatchMat *mats, const int2 *tiles, int32_t ntiles, float *G,
+                                uint16_t *Vhi, uint16_t *Vlo, int32_t s, int64_t ldv, int32_t dist,
+                                hipStream_t st);
+hipError_t launch_batch_power_split(const BatchMat *mats, const int2 *ptiles, int32_t nptiles,
+                                    const uint16_t *Ahi, const uint16_t *Alo, const double *x,
+                                    const double *norm, double *y, double *pout, hipStream_t st);
+hipError_t launch_batch_bf16x3_gemm(const BatchMat *mats, const int2 *tiles, int32_t ntiles,
+                                    int64_t ldv, const uint16_t *Ahi, const uint16_t *Alo,
+                                    const uint16_t *Vhi, const uint16_t *Vlo, float *Y, hipStream_t st);
+hipError_t launch_batch_bf16x3_epilogue(const Bf16EpiArgs &base, const BatchMat *mats,
+                                        const int2 *etiles, int32_t netiles, hipStream_t st);
 
 // ---- batches of dense matrices (one launch per phase over all matrices) ------
 template <typename T>

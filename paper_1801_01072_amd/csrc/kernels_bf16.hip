@@ -133,6 +133,80 @@ hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, i
   return hipGetLastError();
 }
 
+// Batch: split of every matrix (unscaled) and its probe block, one
+// workgroup per (matrix, 128-row tile); thread = 8 columns (split) or 8 rows
+// of one probe (probes).
+template <typename Tin>
+__global__ __launch_bounds__(256) void batch_split_kernel(const BatchMat *__restrict__ mats,
+                                                          const int2 *__restrict__ tiles,
+                                                          uint16_t *Ahi, uint16_t *Alo) {
+  const int2 t = tiles[blockIdx.x];
+  const BatchMat &M = mats[t.x];
+  const Tin *R = (const Tin *)M.src;
+  const int64_t n = M.n, n_pad = M.n_pad, nkb = n_pad / 16, cg = n_pad / 8;
+  uint16_t *hi = Ahi + M.aoff, *lo = Alo + M.aoff;
+  for (int64_t e = threadIdx.x; e < 128 * cg; e += blockDim.x) {
+    const int64_t row = (int64_t)t.y * 128 + e / cg, c0 = (e % cg) * 8;
+    u16x8 h, l;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t c = c0 + q;
+      const float v = (row < n && c < n) ? (float)R[row * M.ldsrc + c] : 0.f;
+      h[q] = bf16_rne(v);
+      l[q] = bf16_rne(v - bf16_to_f32(h[q]));
+    }
+    const int64_t off = frag_off(row, c0, nkb);
+    *(u16x8 *)(hi + off) = h;
+    *(u16x8 *)(lo + off) = l;
+  }
+}
+
+template <typename Tin>
+hipError_t launch_batch_split(const BatchMat *mats, const int2 *tiles, int32_t ntiles, uint16_t *Ahi,
+                              uint16_t *Alo, hipStream_t st) {
+  batch_split_kernel<Tin><<<(unsigned)ntiles, 256, 0, st>>>(mats, tiles, Ahi, Alo);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_split<double>(const BatchMat *, const int2 *, int32_t, uint16_t *,
+                                               uint16_t *, hipStream_t);
+template hipError_t launch_batch_split<float>(const BatchMat *, const int2 *, int32_t, uint16_t *,
+                                              uint16_t *, hipStream_t);
+
+__global__ __launch_bounds__(256) void batch_probe_t_kernel(const BatchMat *__restrict__ mats,
+                                                            const int2 *__restrict__ tiles, float *G,
+                                                            uint16_t *Vhi, uint16_t *Vlo, int32_t s,
+                                                            int64_t ldv, int32_t dist) {
+  const int2 t = tiles[blockIdx.x];
+  const BatchMat &M = mats[t.x];
+  const int64_t n_pad = M.n_pad, nkb = n_pad / 16;
+  for (int64_t e = threadIdx.x; e < 16 * ldv; e += blockDim.x) {
+    const int64_t j = e / 16, i0 = (int64_t)t.y * 128 + (e % 16) * 8;
+    float v[8];
+    u16x8 h, l;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t i = i0 + q;
+      v[q] = 0.f;
+      if (i < M.n && j < s) v[q] = (float)(dist == 0 ? rademacher(M.seed, 0u, i, j) : gaussian(M.seed, 0u, i, j));
+      h[q] = bf16_rne(v[q]);
+      l[q] = bf16_rne(v[q] - bf16_to_f32(h[q]));
+    }
+    f32x4 *gp = (f32x4 *)(G + M.voff + j * n_pad + i0);
+    gp[0] = f32x4{v[0], v[1], v[2], v[3]};
+    gp[1] = f32x4{v[4], v[5], v[6], v[7]};
+    const int64_t off = M.voff + frag_off(j, i0, nkb);
+    *(u16x8 *)(Vhi + off) = h;
+    *(u16x8 *)(Vlo + off) = l;
+  }
+}
+
+hipError_t launch_batch_probe_t(const BatchMat *mats, const int2 *tiles, int32_t ntiles, float *G,
+                                uint16_t *Vhi, uint16_t *Vlo, int32_t s, int64_t ldv, int32_t dist,
+                                hipStream_t st) {
+  batch_probe_t_kernel<<<(unsigned)ntiles, 256, 0, st>>>(mats, tiles, G, Vhi, Vlo, s, ldv, dist);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // GEMM: part_y[ks][j][i] = sum_{k in split ks} (A_hi V_hi + A_hi V_lo + A_lo V_hi)[i][j]
 //
@@ -171,8 +245,15 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
 }
 
+// One workgroup tile: out[col][row] (probe-major, ld = npad) for rows
+// row0..row0+BM-1 and probes col0..col0+BN-1, summing k in [kbeg, kbeg + 32 nst).
 template <int BN, int WM>
-__global__ __launch_bounds__(128 * WM) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
+__device__ __forceinline__ void bf16x3_gemm_tile(const uint16_t *__restrict__ A_hi,
+                                                 const uint16_t *__restrict__ A_lo,
+                                                 const uint16_t *__restrict__ V_hi,
+                                                 const uint16_t *__restrict__ V_lo,
+                                                 float *__restrict__ out, int64_t npad,
+                                                 int64_t kbeg, int nst, int64_t row0, int64_t col0) {
   typedef GemmShape<BN, WM> S;
   static_assert(S::FST % S::WAVES == 0, "fragments must split evenly over the waves");
   static_assert(S::STAGES >= 2, "at least two stages");
@@ -181,16 +262,6 @@ __global__ __launch_bounds__(128 * WM) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = w % WM, wc = w / WM;
-  const int nrt = (int)(a.n_pad / S::BM);
-  const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-  // tile order: row tile fastest, then K-split, then probe tile
-  const int rt = b % nrt;
-  const int ksp = (b / nrt) % a.splits;
-  const int ct = b / (nrt * a.splits);
-  const int64_t npad = a.n_pad;
-  const int64_t kbeg = (int64_t)ksp * a.k_per_split;
-  const int nst = (int)(a.k_per_split / kBK);
-  const int64_t row0 = (int64_t)rt * S::BM, col0 = (int64_t)ct * BN;
   const int m32 = lane & 31, kh = lane >> 5;
 
   // per-lane source of each fragment this wave loads (a stage advances kKS
@@ -203,11 +274,11 @@ __global__ __launch_bounds__(128 * WM) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
     const uint16_t *p;
     if (f < S::FA) {
       const int hl = f / (S::NRB * kKS), rb = (f / kKS) % S::NRB, ks = f % kKS;
-      p = (hl ? a.A_lo : a.A_hi) + ((row0 / 32 + rb) * nkb + kbeg / 16 + ks) * 512;
+      p = (hl ? A_lo : A_hi) + ((row0 / 32 + rb) * nkb + kbeg / 16 + ks) * 512;
     } else {
       const int g = f - S::FA;
       const int hl = g / (S::NCB * kKS), cb = (g / kKS) % S::NCB, ks = g % kKS;
-      p = (hl ? a.V_lo : a.V_hi) + ((col0 / 32 + cb) * nkb + kbeg / 16 + ks) * 512;
+      p = (hl ? V_lo : V_hi) + ((col0 / 32 + cb) * nkb + kbeg / 16 + ks) * 512;
     }
     src[i] = p + 8 * lane;
   }
@@ -278,8 +349,7 @@ __global__ __launch_bounds__(128 * WM) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
     }
   }
 
-  // partial tile -> part_y[ksp][col][row], 4 consecutive rows per store
-  float *__restrict__ out = a.part_y + (int64_t)ksp * a.ldv * npad;
+  // tile -> out[col][row], 4 consecutive rows per store
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
     const int64_t rbase = row0 + 32 * (2 * wr + r) + 4 * kh;
@@ -295,25 +365,63 @@ __global__ __launch_bounds__(128 * WM) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
   }
 }
 
+template <int BN, int WM>
+__global__ __launch_bounds__(128 * WM) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
+  typedef GemmShape<BN, WM> S;
+  const int nrt = (int)(a.n_pad / S::BM);
+  const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  // tile order: row tile fastest, then K-split, then probe tile
+  const int rt = b % nrt;
+  const int ksp = (b / nrt) % a.splits;
+  const int ct = b / (nrt * a.splits);
+  bf16x3_gemm_tile<BN, WM>(a.A_hi, a.A_lo, a.V_hi, a.V_lo, a.part_y + (int64_t)ksp * a.ldv * a.n_pad,
+                           a.n_pad, (int64_t)ksp * a.k_per_split, (int)(a.k_per_split / kBK),
+                           (int64_t)rt * S::BM, (int64_t)ct * BN);
+}
+
+// Batch: one workgroup per (matrix, 128-row tile) over the matrix's full K;
+// the matrix's probe block is one tile of BN = ldv probes.
+template <int BN>
+__global__ __launch_bounds__(256) void batch_bf16x3_gemm_kernel(const BatchMat *__restrict__ mats,
+                                                                const int2 *__restrict__ tiles,
+                                                                const uint16_t *Ahi, const uint16_t *Alo,
+                                                                const uint16_t *Vhi, const uint16_t *Vlo,
+                                                                float *Y) {
+  const int2 t = tiles[blockIdx.x];
+  const BatchMat &M = mats[t.x];
+  bf16x3_gemm_tile<BN, 2>(Ahi + M.aoff, Alo + M.aoff, Vhi + M.voff, Vlo + M.voff, Y + M.voff, M.n_pad, 0,
+                          (int)(M.n_pad / kBK), (int64_t)t.y * 128, 0);
+}
+
+hipError_t launch_batch_bf16x3_gemm(const BatchMat *mats, const int2 *tiles, int32_t ntiles,
+                                    int64_t ldv, const uint16_t *Ahi, const uint16_t *Alo,
+                                    const uint16_t *Vhi, const uint16_t *Vlo, float *Y, hipStream_t st) {
+  switch (ldv) {
+    case 64: batch_bf16x3_gemm_kernel<64><<<(unsigned)ntiles, 256, 0, st>>>(mats, tiles, Ahi, Alo, Vhi, Vlo, Y); break;
+    case 128: batch_bf16x3_gemm_kernel<128><<<(unsigned)ntiles, 256, 0, st>>>(mats, tiles, Ahi, Alo, Vhi, Vlo, Y); break;
+    case 256: batch_bf16x3_gemm_kernel<256><<<(unsigned)ntiles, 256, 0, st>>>(mats, tiles, Ahi, Alo, Vhi, Vlo, Y); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Power-method product on the split of R: y = ((hi + lo) x)/||x_prev|| with
 // FP64 accumulation (hi + lo is exact in FP32), reading the fragment-major
 // split.  Workgroup = one 32-row band; its 16 waves take every 16th 16-column
 // block, each lane 8 columns of one row; x must be zero beyond n.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void power_gemv_split_kernel(const uint16_t *__restrict__ hi,
-                                                               const uint16_t *__restrict__ lo,
-                                                               int64_t n_pad, int64_t n,
-                                                               const double *__restrict__ x,
-                                                               const double *__restrict__ in_norm,
-                                                               double *__restrict__ y,
-                                                               double *__restrict__ part3) {
+__device__ __forceinline__ void power_split_band(const uint16_t *__restrict__ hi,
+                                                 const uint16_t *__restrict__ lo, int64_t n_pad,
+                                                 int64_t n, const double *__restrict__ x,
+                                                 const double *__restrict__ in_norm,
+                                                 double *__restrict__ y, double *__restrict__ part3,
+                                                 int64_t band) {
   constexpr int W = 16;
   __shared__ double red[W][32];
   const double sc = in_norm ? 1.0 / sqrt(in_norm[0]) : 1.0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t nkb = n_pad / 16;
-  const int64_t band = blockIdx.x;
   const uint16_t *H = hi + band * nkb * 512 + 8 * lane;
   const uint16_t *Lo = lo + band * nkb * 512 + 8 * lane;
   const int64_t kofs = 8 * (lane >> 5);
@@ -352,7 +460,37 @@ __global__ __launch_bounds__(1024) void power_gemv_split_kernel(const uint16_t *
       xx = xs * xs;
     }
   }
-  block_power_partials(yy, xy, xx, part3, blockIdx.x);
+  block_power_partials(yy, xy, xx, part3, band);
+}
+
+__global__ __launch_bounds__(1024) void power_gemv_split_kernel(const uint16_t *__restrict__ hi,
+                                                               const uint16_t *__restrict__ lo,
+                                                               int64_t n_pad, int64_t n,
+                                                               const double *__restrict__ x,
+                                                               const double *__restrict__ in_norm,
+                                                               double *__restrict__ y,
+                                                               double *__restrict__ part3) {
+  power_split_band(hi, lo, n_pad, n, x, in_norm, y, part3, blockIdx.x);
+}
+
+// Batch: one workgroup per (matrix, 32-row band).
+__global__ __launch_bounds__(1024) void batch_power_split_kernel(const BatchMat *__restrict__ mats,
+                                                                const int2 *__restrict__ ptiles,
+                                                                const uint16_t *Ahi,
+                                                                const uint16_t *Alo, const double *x,
+                                                                const double *norm, double *y,
+                                                                double *pout) {
+  const int2 t = ptiles[blockIdx.x];
+  const BatchMat &M = mats[t.x];
+  power_split_band(Ahi + M.aoff, Alo + M.aoff, M.n_pad, M.n, x + M.xoff, norm ? norm + 4 * t.x : nullptr,
+                   y + M.xoff, pout + M.pboff, t.y);
+}
+
+hipError_t launch_batch_power_split(const BatchMat *mats, const int2 *ptiles, int32_t nptiles,
+                                    const uint16_t *Ahi, const uint16_t *Alo, const double *x,
+                                    const double *norm, double *y, double *pout, hipStream_t st) {
+  batch_power_split_kernel<<<(unsigned)nptiles, 1024, 0, st>>>(mats, ptiles, Ahi, Alo, x, norm, y, pout);
+  return hipGetLastError();
 }
 
 int32_t power_blocks_split(int64_t n_pad) { return (int32_t)(n_pad / 32); }
@@ -395,11 +533,10 @@ hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st) {
 // V_{k+1} = z (FP32) and its hi/lo split; per-probe dots with g.
 // Thread = (probe j, 8 consecutive rows); block = 256 threads of one probe.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void bf16x3_epilogue_kernel(Bf16EpiArgs a) {
+__device__ __forceinline__ void bf16x3_epilogue_body(const Bf16EpiArgs &a, int64_t blk, int64_t j) {
   __shared__ double red[2][4];
-  const int64_t j = blockIdx.y;
   const int64_t npad = a.n_pad;
-  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8;
+  const int64_t i0 = (blk * 256 + threadIdx.x) * 8;
   const float c1 = (float)a.c1, c2b = (float)(a.c2 * a.scal[S_B]), cw = (float)a.cw;
   const float ys = a.scale_y ? (float)a.scal[S_A] : 1.f;
   double ds = 0.0, gs = 0.0;
@@ -464,12 +601,45 @@ __global__ __launch_bounds__(256) void bf16x3_epilogue_kernel(Bf16EpiArgs a) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int64_t idx = ((int64_t)a.slot * a.nblk + blockIdx.x) * a.ldv + j;
+    const int64_t idx = ((int64_t)a.slot * a.nblk + blk) * a.ldv + j;
     a.part[idx] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
     if (a.slot_gg >= 0)
-      a.part[((int64_t)a.slot_gg * a.nblk + blockIdx.x) * a.ldv + j] =
+      a.part[((int64_t)a.slot_gg * a.nblk + blk) * a.ldv + j] =
           red[1][0] + red[1][1] + red[1][2] + red[1][3];
   }
+}
+
+__global__ __launch_bounds__(256) void bf16x3_epilogue_kernel(Bf16EpiArgs a) {
+  bf16x3_epilogue_body(a, blockIdx.x, blockIdx.y);
+}
+
+// Batch: one workgroup per (matrix, epilogue block) and probe; the pointers
+// of the base arguments are batch-wide and offset by the matrix's regions.
+__global__ __launch_bounds__(256) void batch_bf16x3_epilogue_kernel(Bf16EpiArgs base,
+                                                                    const BatchMat *__restrict__ mats,
+                                                                    const int2 *__restrict__ etiles) {
+  const int2 t = etiles[blockIdx.x];
+  const BatchMat &M = mats[t.x];
+  Bf16EpiArgs e = base;
+  e.part_y = base.part_y + M.voff;
+  e.Vk = base.Vk + M.voff;
+  e.Vkm1 = base.Vkm1 ? base.Vkm1 + M.voff : nullptr;
+  e.Vkp1 = base.Vkp1 ? base.Vkp1 + M.voff : nullptr;
+  e.V_hi = base.V_hi + M.voff;
+  e.V_lo = base.V_lo + M.voff;
+  e.G = base.G + M.voff;
+  e.scal = M.scal;
+  e.part = base.part + M.poff;
+  e.nblk = M.ntile;
+  e.n_pad = M.n_pad;
+  bf16x3_epilogue_body(e, t.y, blockIdx.y);
+}
+
+hipError_t launch_batch_bf16x3_epilogue(const Bf16EpiArgs &base, const BatchMat *mats,
+                                        const int2 *etiles, int32_t netiles, hipStream_t st) {
+  dim3 grid((unsigned)netiles, (unsigned)base.ldv);
+  batch_bf16x3_epilogue_kernel<<<grid, 256, 0, st>>>(base, mats, etiles);
+  return hipGetLastError();
 }
 
 int32_t bf16x3_epilogue_blocks(int64_t n_pad) { return (int32_t)((n_pad / 8 + 255) / 256); }

@@ -98,5 +98,33 @@ def test_batch_errors():
     with pytest.raises(ent.EntropyError) as e:
         ent.entropy_estimate_batched(mats + [bad], "chebyshev", 5, 8, 0, precision="f64")
     assert e.value.status == ent.ENOTDENSITY and "matrix 2" in e.value.message
-    with pytest.raises(ent.EntropyError):
-        ent.entropy_estimate_batched(mats, "chebyshev", 5, 8, 0, precision="bf16x3")
+    with pytest.raises(ent.EntropyError) as e:
+        ent.entropy_estimate_batched(mats, "chebyshev", 5, 300, 0, precision="bf16x3")
+    assert e.value.status == ent.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("method,dtype", [("chebyshev", np.float32), ("taylor", np.float64)])
+def test_batch_bf16x3_against_oracle(orc, method, dtype):
+    # grouped split / power / GEMM / epilogue: each matrix and probe against
+    # the FP64 oracle at the reduced-precision bar
+    mats, host = make_batch(NS, 13, dtype=dtype)
+    m, s, seed = 16, 40, 21
+    g = ent.Graph(mats, method, m, s, seed, precision="bf16x3", probe_dist="gaussian")
+    assert g.tile_rows == 128
+    res = g.launch()
+    per = g.per_probe()
+    for b, R in enumerate(host):
+        ref = orc.estimate(R.astype(np.float64), 0 if method == "taylor" else 1, m, s, seed + b, dist=1)
+        scale = max(np.mean(np.abs(ref.per_probe)), 1e-2)
+        err = np.max(np.abs(per[b] - ref.per_probe)) / scale
+        rel = abs(res[b].entropy - ref.entropy) / max(abs(ref.entropy), 1e-2)
+        print(f"[batch bf16x3 {method}] b={b} n={R.shape[0]} rel={rel:.2e} per-probe={err:.2e}", flush=True)
+        assert err <= 1e-3 and rel <= 1e-3
+        assert res[b].p1_est == pytest.approx(ref.p1_est, rel=1e-6)
+    # replays are bitwise identical and equal to the eager sequence
+    again = [r.entropy for r in g.launch()]
+    assert again == [r.entropy for r in res]
+    eager, tm = g.time_eager()
+    assert [r.entropy for r in eager] == again
+    assert tm["step_launches"] == (m if method == "chebyshev" else m + 1)
+    g.destroy()
