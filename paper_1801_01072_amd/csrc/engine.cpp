@@ -1023,11 +1023,7 @@ struct ent_graph_s {
   double *host_scal = nullptr;
   // BF16x3 batches: split of every R, bf16 probe blocks, FP32 products
   bool bf16 = false;
-  uint16_t *Ahi = nullptr, *Alo = nullptr, *Vhi = nullptr, *Vlo = nullptr;
-  float *Y = nullptr;
-  std::vector<int2> etiles;
-  int2 *etiles_d = nullptr;
-  int32_t netiles = 0;
+  uint16_t *Ahi = nullptr, *Alo = nullptr, *Vhi[2] = {nullptr, nullptr}, *Vlo[2] = {nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool launched = false;
@@ -1133,8 +1129,8 @@ ent_status enqueue_batch_bf16(ent_graph_s *g, hipStream_t st, PhaseEvents *pe) {
     HIP_TRY(ent::launch_batch_split<double>(g->mats_d, g->tiles2_d, g->ntiles2, g->Ahi, g->Alo, st));
   else
     HIP_TRY(ent::launch_batch_split<float>(g->mats_d, g->tiles2_d, g->ntiles2, g->Ahi, g->Alo, st));
-  HIP_TRY(ent::launch_batch_probe_t(g->mats_d, g->tiles2_d, g->ntiles2, (float *)g->G, g->Vhi, g->Vlo,
-                                    g->s, g->ldv, o.probe_dist, st));
+  HIP_TRY(ent::launch_batch_probe_t(g->mats_d, g->tiles2_d, g->ntiles2, (float *)g->G, g->Vhi[0],
+                                    g->Vlo[0], g->s, g->ldv, o.probe_dist, st));
   if (!(o.u_fixed > 0)) {
     if (pe) pe->power_begin = pe->mark();
     // the split is zero beyond n, and so must be the vectors it multiplies
@@ -1185,20 +1181,16 @@ ent_status enqueue_batch_bf16(ent_graph_s *g, hipStream_t st, PhaseEvents *pe) {
       ea.slot_gg = -1;
       write = k < nsteps - 1;
     }
-    const int e0 = pe ? pe->mark() : -1;
-    HIP_TRY(ent::launch_batch_bf16x3_gemm(g->mats_d, g->tiles2_d, g->ntiles2, g->ldv, g->Ahi, g->Alo,
-                                          g->Vhi, g->Vlo, g->Y, st));
-    const int e1 = pe ? pe->mark() : -1;
-    ea.part_y = g->Y; ea.splits = 1; ea.Vk = Vk;
+    // fused step: product + epilogue; V_k hi/lo in set k % 2, V_{k+1} hi/lo to the other
+    ea.Vk = Vk;
     ea.Vkm1 = (g->method == ENT_CHEBYSHEV && k > 0) ? Vkm1 : nullptr;
-    ea.Vkp1 = write ? Vout : nullptr; ea.V_hi = g->Vhi; ea.V_lo = g->Vlo; ea.G = (const float *)g->G;
-    ea.scale_y = 1; ea.part = g->part; ea.ldv = g->ldv;
-    HIP_TRY(ent::launch_batch_bf16x3_epilogue(ea, g->mats_d, g->etiles_d, g->netiles, st));
+    ea.Vkp1 = write ? Vout : nullptr; ea.V_hi = g->Vhi[(k + 1) & 1]; ea.V_lo = g->Vlo[(k + 1) & 1];
+    ea.G = (const float *)g->G; ea.scale_y = 1; ea.part = g->part; ea.ldv = g->ldv;
+    HIP_TRY(ent::launch_batch_bf16x3_step(ea, g->mats_d, g->tiles2_d, g->ntiles2, g->Ahi, g->Alo,
+                                          g->Vhi[k & 1], g->Vlo[k & 1], st));
     if (pe) {
-      const int e2 = pe->mark();
-      pe->main_spans.push_back({e0, e1});
-      pe->epi_spans.push_back({e1, e2});
-      if (k == nsteps - 1) pe->steps_end = e2;
+      const int e = pe->mark();
+      if (k == nsteps - 1) pe->steps_end = e;
     }
     if (g->method == ENT_CHEBYSHEV) Vkm1 = Vk;
     Vk = Vout;
@@ -1356,7 +1348,7 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
     M.ldr = round_up(n, 8);
     M.n = n;
     M.n_pad = round_up(n, 128);
-    M.ntile = g->bf16 ? ent::bf16x3_epilogue_blocks(M.n_pad) : (int32_t)(M.n_pad / 64);
+    M.ntile = (int32_t)(M.n_pad / (g->bf16 ? 128 : 64));
     M.pblk = g->bf16 ? ent::power_blocks_split(M.n_pad) : ent::power_blocks_dense(n);
     M.seed = seed + (uint64_t)b;
     M.R = (const void *)(intptr_t)roff;  // offsets for now; rebased below
@@ -1393,13 +1385,10 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
     for (int32_t t = 0; t < (int32_t)(M.n_pad / 64); ++t) g->tiles1.push_back(make_int2(b, t));
     for (int32_t t = 0; t < (int32_t)(M.n_pad / 128); ++t) g->tiles2.push_back(make_int2(b, t));
     for (int32_t t = 0; t < M.pblk; ++t) g->ptiles.push_back(make_int2(b, t));
-    if (g->bf16)
-      for (int32_t t = 0; t < M.ntile; ++t) g->etiles.push_back(make_int2(b, t));
   }
   g->ntiles1 = (int32_t)g->tiles1.size();
   g->ntiles2 = (int32_t)g->tiles2.size();
   g->nptiles = (int32_t)g->ptiles.size();
-  g->netiles = (int32_t)g->etiles.size();
   g->xlen = xoff;
   Carve cv;
   cv.add(&g->mats_d, (size_t)count);
@@ -1407,12 +1396,12 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
   cv.add(&g->tiles2_d, g->tiles2.size());
   cv.add(&g->ptiles_d, g->ptiles.size());
   if (g->bf16) {
-    cv.add(&g->etiles_d, g->etiles.size());
     cv.add(&g->Ahi, (size_t)aoff);
     cv.add(&g->Alo, (size_t)aoff);
-    cv.add(&g->Vhi, (size_t)voff);
-    cv.add(&g->Vlo, (size_t)voff);
-    cv.add(&g->Y, (size_t)voff);
+    for (int q = 0; q < 2; ++q) {
+      cv.add(&g->Vhi[q], (size_t)voff);
+      cv.add(&g->Vlo[q], (size_t)voff);
+    }
   }
   cv.add(&g->scal, (size_t)count * g->sb);
   if (!g->bf16) cv.add(&g->Rc, (size_t)roff * esz);
@@ -1445,9 +1434,7 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
   }
   if (hipMemcpy(g->tiles1_d, g->tiles1.data(), sizeof(int2) * g->tiles1.size(), hipMemcpyHostToDevice) ||
       hipMemcpy(g->tiles2_d, g->tiles2.data(), sizeof(int2) * g->tiles2.size(), hipMemcpyHostToDevice) ||
-      hipMemcpy(g->ptiles_d, g->ptiles.data(), sizeof(int2) * g->ptiles.size(), hipMemcpyHostToDevice) ||
-      (g->bf16 && hipMemcpy(g->etiles_d, g->etiles.data(), sizeof(int2) * g->etiles.size(),
-                            hipMemcpyHostToDevice)))
+      hipMemcpy(g->ptiles_d, g->ptiles.data(), sizeof(int2) * g->ptiles.size(), hipMemcpyHostToDevice))
     return fail_free(fail(ENT_EDEVICE, "descriptor upload failed"));
   // tile shape: cached choice, else timed on this batch when asked, else
   // 64-row tiles (BF16x3 batches have one shape: 128-row GEMM tiles)

@@ -200,9 +200,10 @@ hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64
 hipError_t launch_bf16x3_epilogue(const Bf16EpiArgs &a, hipStream_t st);
 int32_t bf16x3_epilogue_blocks(int64_t n_pad);
 // ---- BF16x3 batches (descriptor-driven; tables of (matrix, tile) pairs) ----
-// tiles: (matrix, 128-row tile); ptiles: (matrix, 32-row band); etiles:
-// (matrix, epilogue block).  G/VA/VB/Y are FP32 probe-major at M.voff; the
-// bf16 V hi/lo at M.voff and A hi/lo at M.aoff are fragment-major.
+// tiles: (matrix, 128-row tile); ptiles: (matrix, 32-row band).  G/V_k are
+// FP32 probe-major at M.voff; the bf16 V hi/lo at M.voff and A hi/lo at
+// M.aoff are fragment-major.  A step reads V_k hi/lo (vin) and writes
+// V_{k+1} hi/lo (base.V_hi/V_lo): they must be different buffers.
 template <typename Tin>
 hipError_t launch_batch_split(const BatchMat *mats, const int2 *tiles, int32_t ntiles, uint16_t *Ahi,
                               uint16_t *Alo, hipStream_t st);
@@ -212,11 +213,9 @@ hipError_t launch_batch_probe_t(const BatchMat *mats, const int2 *tiles, int32_t
 hipError_t launch_batch_power_split(const BatchMat *mats, const int2 *ptiles, int32_t nptiles,
                                     const uint16_t *Ahi, const uint16_t *Alo, const double *x,
                                     const double *norm, double *y, double *pout, hipStream_t st);
-hipError_t launch_batch_bf16x3_gemm(const BatchMat *mats, const int2 *tiles, int32_t ntiles,
-                                    int64_t ldv, const uint16_t *Ahi, const uint16_t *Alo,
-                                    const uint16_t *Vhi, const uint16_t *Vlo, float *Y, hipStream_t st);
-hipError_t launch_batch_bf16x3_epilogue(const Bf16EpiArgs &base, const BatchMat *mats,
-                                        const int2 *etiles, int32_t netiles, hipStream_t st);
+hipError_t launch_batch_bf16x3_step(const Bf16EpiArgs &base, const BatchMat *mats, const int2 *tiles,
+                                    int32_t ntiles, const uint16_t *Ahi, const uint16_t *Alo,
+                                    const uint16_t *vin_hi, const uint16_t *vin_lo, hipStream_t st);
 
 // ---- batches of dense matrices (one launch per phase over all matrices) ------
 template <typename T>

@@ -38,6 +38,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 
 // Round-to-nearest-even FP32 -> BF16 bits (finite inputs).
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
@@ -245,15 +246,21 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
 }
 
-// One workgroup tile: out[col][row] (probe-major, ld = npad) for rows
-// row0..row0+BM-1 and probes col0..col0+BN-1, summing k in [kbeg, kbeg + 32 nst).
-template <int BN, int WM>
+// One workgroup tile over rows row0..row0+BM-1 and probes col0..col0+BN-1,
+// summing k in [kbeg, kbeg + 32 nst).  Without FUSED the tile goes to
+// out[col][row] (probe-major, ld = npad).  With FUSED (the tile covers all of
+// K) the epilogue of `ep` runs on the accumulators: y = a acc, z = c1 y +
+// c2 b V_k + cw V_{k-1}, V_{k+1} = z with its bf16 split (fragment-major), and
+// the tile's per-probe dot partials go to ep->part[(slot * nblk + ptile) * ldv
+// + probe].
+template <int BN, int WM, bool FUSED>
 __device__ __forceinline__ void bf16x3_gemm_tile(const uint16_t *__restrict__ A_hi,
                                                  const uint16_t *__restrict__ A_lo,
                                                  const uint16_t *__restrict__ V_hi,
                                                  const uint16_t *__restrict__ V_lo,
                                                  float *__restrict__ out, int64_t npad,
-                                                 int64_t kbeg, int nst, int64_t row0, int64_t col0) {
+                                                 int64_t kbeg, int nst, int64_t row0, int64_t col0,
+                                                 const Bf16EpiArgs *ep, int64_t ptile) {
   typedef GemmShape<BN, WM> S;
   static_assert(S::FST % S::WAVES == 0, "fragments must split evenly over the waves");
   static_assert(S::STAGES >= 2, "at least two stages");
@@ -349,7 +356,33 @@ __device__ __forceinline__ void bf16x3_gemm_tile(const uint16_t *__restrict__ A_
     }
   }
 
-  // tile -> out[col][row], 4 consecutive rows per store
+  if (!FUSED) {
+    // tile -> out[col][row], 4 consecutive rows per store
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int64_t rbase = row0 + 32 * (2 * wr + r) + 4 * kh;
+#pragma unroll
+      for (int c = 0; c < S::WCB; ++c) {
+        const int64_t col = col0 + 32 * (S::WCB * wc + c) + m32;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          f32x4 v = {acc[r][c][4 * g], acc[r][c][4 * g + 1], acc[r][c][4 * g + 2], acc[r][c][4 * g + 3]};
+          *(f32x4 *)(out + col * npad + rbase + 8 * g) = v;
+        }
+      }
+    }
+    return;
+  }
+  // fused epilogue: lane (m32, kh) holds rows rbase + 8 g + q (q < 4) of
+  // probe col for every (r, c, g)
+  const Bf16EpiArgs &e = *ep;
+  const float ys = (float)e.scal[S_A];
+  const float c1 = (float)e.c1, c2b = (float)(e.c2 * e.scal[S_B]), cw = (float)e.cw;
+  const bool use_m1 = e.Vkm1 && e.cw != 0.0;
+
+  double ds[S::WCB], gs[S::WCB];
+#pragma unroll
+  for (int c = 0; c < S::WCB; ++c) ds[c] = gs[c] = 0.0;
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
     const int64_t rbase = row0 + 32 * (2 * wr + r) + 4 * kh;
@@ -358,10 +391,54 @@ __device__ __forceinline__ void bf16x3_gemm_tile(const uint16_t *__restrict__ A_
       const int64_t col = col0 + 32 * (S::WCB * wc + c) + m32;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        f32x4 v = {acc[r][c][4 * g], acc[r][c][4 * g + 1], acc[r][c][4 * g + 2], acc[r][c][4 * g + 3]};
-        *(f32x4 *)(out + col * npad + rbase + 8 * g) = v;
+        const int64_t off = col * npad + rbase + 8 * g;
+        const f32x4 vk = *(const f32x4 *)(e.Vk + off);
+        const f32x4 gv = *(const f32x4 *)(e.G + off);
+        f32x4 vm = {0.f, 0.f, 0.f, 0.f};
+        if (use_m1) vm = *(const f32x4 *)(e.Vkm1 + off);
+        f32x4 z;
+        u16x4 zh, zl;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float y = ys * acc[r][c][4 * g + q];
+          z[q] = c1 * y + c2b * vk[q] + cw * vm[q];
+          zh[q] = bf16_rne(z[q]);
+          zl[q] = bf16_rne(z[q] - bf16_to_f32(zh[q]));
+          ds[c] += (double)gv[q] * (double)(e.dot_y ? y : z[q]);
+          gs[c] += (double)gv[q] * (double)gv[q];
+        }
+        if (e.Vkp1) {
+          *(f32x4 *)(e.Vkp1 + off) = z;
+          const int64_t foff = frag_off(col, rbase + 8 * g, nkb);
+          *(u16x4 *)(e.V_hi + foff) = zh;
+          *(u16x4 *)(e.V_lo + foff) = zl;
+        }
       }
     }
+  }
+  if (e.slot < 0) return;
+  // per probe: the two lane halves, then the WM waves of a probe column
+  __syncthreads();  // every wave is done with the operand stages
+  double *red = (double *)lds;  // [2][WM][BN]
+#pragma unroll
+  for (int c = 0; c < S::WCB; ++c) {
+    ds[c] += __shfl_xor(ds[c], 32, 64);
+    gs[c] += __shfl_xor(gs[c], 32, 64);
+    if (kh == 0) {
+      const int pc = 32 * (S::WCB * wc + c) + m32;
+      red[(0 * WM + wr) * BN + pc] = ds[c];
+      red[(1 * WM + wr) * BN + pc] = gs[c];
+    }
+  }
+  __syncthreads();
+  for (int pc = threadIdx.x; pc < BN; pc += blockDim.x) {
+    double t0 = 0.0, t1 = 0.0;
+    for (int q = 0; q < WM; ++q) {
+      t0 += red[(0 * WM + q) * BN + pc];
+      t1 += red[(1 * WM + q) * BN + pc];
+    }
+    e.part[((int64_t)e.slot * e.nblk + ptile) * e.ldv + col0 + pc] = t0;
+    if (e.slot_gg >= 0) e.part[((int64_t)e.slot_gg * e.nblk + ptile) * e.ldv + col0 + pc] = t1;
   }
 }
 
@@ -374,32 +451,47 @@ __global__ __launch_bounds__(128 * WM) void bf16x3_gemm_kernel(Bf16GemmArgs a) {
   const int rt = b % nrt;
   const int ksp = (b / nrt) % a.splits;
   const int ct = b / (nrt * a.splits);
-  bf16x3_gemm_tile<BN, WM>(a.A_hi, a.A_lo, a.V_hi, a.V_lo, a.part_y + (int64_t)ksp * a.ldv * a.n_pad,
-                           a.n_pad, (int64_t)ksp * a.k_per_split, (int)(a.k_per_split / kBK),
-                           (int64_t)rt * S::BM, (int64_t)ct * BN);
+  bf16x3_gemm_tile<BN, WM, false>(a.A_hi, a.A_lo, a.V_hi, a.V_lo,
+                                  a.part_y + (int64_t)ksp * a.ldv * a.n_pad, a.n_pad,
+                                  (int64_t)ksp * a.k_per_split, (int)(a.k_per_split / kBK),
+                                  (int64_t)rt * S::BM, (int64_t)ct * BN, nullptr, 0);
 }
 
-// Batch: one workgroup per (matrix, 128-row tile) over the matrix's full K;
-// the matrix's probe block is one tile of BN = ldv probes.
+// Batch step: one workgroup per (matrix, 128-row tile) over the matrix's full
+// K, with the epilogue fused (the matrix's probe block is one tile of BN =
+// ldv probes).  The step reads V_k hi/lo and writes V_{k+1} hi/lo, so the
+// two live in separate buffers (vin / vout, alternating by step).  The
+// pointers of `base` are batch-wide and offset by the matrix's regions.
 template <int BN>
-__global__ __launch_bounds__(256) void batch_bf16x3_gemm_kernel(const BatchMat *__restrict__ mats,
+__global__ __launch_bounds__(256) void batch_bf16x3_step_kernel(Bf16EpiArgs base,
+                                                                const BatchMat *__restrict__ mats,
                                                                 const int2 *__restrict__ tiles,
                                                                 const uint16_t *Ahi, const uint16_t *Alo,
-                                                                const uint16_t *Vhi, const uint16_t *Vlo,
-                                                                float *Y) {
+                                                                const uint16_t *vin_hi,
+                                                                const uint16_t *vin_lo) {
   const int2 t = tiles[blockIdx.x];
   const BatchMat &M = mats[t.x];
-  bf16x3_gemm_tile<BN, 2>(Ahi + M.aoff, Alo + M.aoff, Vhi + M.voff, Vlo + M.voff, Y + M.voff, M.n_pad, 0,
-                          (int)(M.n_pad / kBK), (int64_t)t.y * 128, 0);
+  Bf16EpiArgs e = base;
+  e.Vk = base.Vk + M.voff;
+  e.Vkm1 = base.Vkm1 ? base.Vkm1 + M.voff : nullptr;
+  e.Vkp1 = base.Vkp1 ? base.Vkp1 + M.voff : nullptr;
+  e.V_hi = base.V_hi + M.voff;
+  e.V_lo = base.V_lo + M.voff;
+  e.G = base.G + M.voff;
+  e.scal = M.scal;
+  e.part = base.part + M.poff;
+  e.nblk = M.ntile;
+  bf16x3_gemm_tile<BN, 2, true>(Ahi + M.aoff, Alo + M.aoff, vin_hi + M.voff, vin_lo + M.voff, nullptr,
+                                M.n_pad, 0, (int)(M.n_pad / kBK), (int64_t)t.y * 128, 0, &e, t.y);
 }
 
-hipError_t launch_batch_bf16x3_gemm(const BatchMat *mats, const int2 *tiles, int32_t ntiles,
-                                    int64_t ldv, const uint16_t *Ahi, const uint16_t *Alo,
-                                    const uint16_t *Vhi, const uint16_t *Vlo, float *Y, hipStream_t st) {
-  switch (ldv) {
-    case 64: batch_bf16x3_gemm_kernel<64><<<(unsigned)ntiles, 256, 0, st>>>(mats, tiles, Ahi, Alo, Vhi, Vlo, Y); break;
-    case 128: batch_bf16x3_gemm_kernel<128><<<(unsigned)ntiles, 256, 0, st>>>(mats, tiles, Ahi, Alo, Vhi, Vlo, Y); break;
-    case 256: batch_bf16x3_gemm_kernel<256><<<(unsigned)ntiles, 256, 0, st>>>(mats, tiles, Ahi, Alo, Vhi, Vlo, Y); break;
+hipError_t launch_batch_bf16x3_step(const Bf16EpiArgs &base, const BatchMat *mats, const int2 *tiles,
+                                    int32_t ntiles, const uint16_t *Ahi, const uint16_t *Alo,
+                                    const uint16_t *vin_hi, const uint16_t *vin_lo, hipStream_t st) {
+  switch (base.ldv) {
+    case 64: batch_bf16x3_step_kernel<64><<<(unsigned)ntiles, 256, 0, st>>>(base, mats, tiles, Ahi, Alo, vin_hi, vin_lo); break;
+    case 128: batch_bf16x3_step_kernel<128><<<(unsigned)ntiles, 256, 0, st>>>(base, mats, tiles, Ahi, Alo, vin_hi, vin_lo); break;
+    case 256: batch_bf16x3_step_kernel<256><<<(unsigned)ntiles, 256, 0, st>>>(base, mats, tiles, Ahi, Alo, vin_hi, vin_lo); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -408,16 +500,16 @@ hipError_t launch_batch_bf16x3_gemm(const BatchMat *mats, const int2 *tiles, int
 // ---------------------------------------------------------------------------
 // Power-method product on the split of R: y = ((hi + lo) x)/||x_prev|| with
 // FP64 accumulation (hi + lo is exact in FP32), reading the fragment-major
-// split.  Workgroup = one 32-row band; its 16 waves take every 16th 16-column
+// split.  Workgroup = one 32-row band; its W waves take every W-th 16-column
 // block, each lane 8 columns of one row; x must be zero beyond n.
 // ---------------------------------------------------------------------------
+template <int W>
 __device__ __forceinline__ void power_split_band(const uint16_t *__restrict__ hi,
                                                  const uint16_t *__restrict__ lo, int64_t n_pad,
                                                  int64_t n, const double *__restrict__ x,
                                                  const double *__restrict__ in_norm,
                                                  double *__restrict__ y, double *__restrict__ part3,
                                                  int64_t band) {
-  constexpr int W = 16;
   __shared__ double red[W][32];
   const double sc = in_norm ? 1.0 / sqrt(in_norm[0]) : 1.0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -470,11 +562,12 @@ __global__ __launch_bounds__(1024) void power_gemv_split_kernel(const uint16_t *
                                                                const double *__restrict__ in_norm,
                                                                double *__restrict__ y,
                                                                double *__restrict__ part3) {
-  power_split_band(hi, lo, n_pad, n, x, in_norm, y, part3, blockIdx.x);
+  power_split_band<16>(hi, lo, n_pad, n, x, in_norm, y, part3, blockIdx.x);
 }
 
-// Batch: one workgroup per (matrix, 32-row band).
-__global__ __launch_bounds__(1024) void batch_power_split_kernel(const BatchMat *__restrict__ mats,
+// Batch: one workgroup of 4 waves per (matrix, 32-row band) (the matrices are
+// at most a few thousand columns wide).
+__global__ __launch_bounds__(256) void batch_power_split_kernel(const BatchMat *__restrict__ mats,
                                                                 const int2 *__restrict__ ptiles,
                                                                 const uint16_t *Ahi,
                                                                 const uint16_t *Alo, const double *x,
@@ -482,14 +575,14 @@ __global__ __launch_bounds__(1024) void batch_power_split_kernel(const BatchMat 
                                                                 double *pout) {
   const int2 t = ptiles[blockIdx.x];
   const BatchMat &M = mats[t.x];
-  power_split_band(Ahi + M.aoff, Alo + M.aoff, M.n_pad, M.n, x + M.xoff, norm ? norm + 4 * t.x : nullptr,
-                   y + M.xoff, pout + M.pboff, t.y);
+  power_split_band<4>(Ahi + M.aoff, Alo + M.aoff, M.n_pad, M.n, x + M.xoff, norm ? norm + 4 * t.x : nullptr,
+                      y + M.xoff, pout + M.pboff, t.y);
 }
 
 hipError_t launch_batch_power_split(const BatchMat *mats, const int2 *ptiles, int32_t nptiles,
                                     const uint16_t *Ahi, const uint16_t *Alo, const double *x,
                                     const double *norm, double *y, double *pout, hipStream_t st) {
-  batch_power_split_kernel<<<(unsigned)nptiles, 1024, 0, st>>>(mats, ptiles, Ahi, Alo, x, norm, y, pout);
+  batch_power_split_kernel<<<(unsigned)nptiles, 256, 0, st>>>(mats, ptiles, Ahi, Alo, x, norm, y, pout);
   return hipGetLastError();
 }
 
@@ -536,7 +629,7 @@ hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st) {
 __device__ __forceinline__ void bf16x3_epilogue_body(const Bf16EpiArgs &a, int64_t blk, int64_t j) {
   __shared__ double red[2][4];
   const int64_t npad = a.n_pad;
-  const int64_t i0 = (blk * 256 + threadIdx.x) * 8;
+  const int64_t i0 = (blk * blockDim.x + threadIdx.x) * 8;
   const float c1 = (float)a.c1, c2b = (float)(a.c2 * a.scal[S_B]), cw = (float)a.cw;
   const float ys = a.scale_y ? (float)a.scal[S_A] : 1.f;
   double ds = 0.0, gs = 0.0;
@@ -601,45 +694,19 @@ __device__ __forceinline__ void bf16x3_epilogue_body(const Bf16EpiArgs &a, int64
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int64_t idx = ((int64_t)a.slot * a.nblk + blk) * a.ldv + j;
-    a.part[idx] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    if (a.slot_gg >= 0)
-      a.part[((int64_t)a.slot_gg * a.nblk + blk) * a.ldv + j] =
-          red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const int nwv = blockDim.x >> 6;
+    double t0 = 0.0, t1 = 0.0;
+    for (int q = 0; q < nwv; ++q) {
+      t0 += red[0][q];
+      t1 += red[1][q];
+    }
+    a.part[((int64_t)a.slot * a.nblk + blk) * a.ldv + j] = t0;
+    if (a.slot_gg >= 0) a.part[((int64_t)a.slot_gg * a.nblk + blk) * a.ldv + j] = t1;
   }
 }
 
 __global__ __launch_bounds__(256) void bf16x3_epilogue_kernel(Bf16EpiArgs a) {
   bf16x3_epilogue_body(a, blockIdx.x, blockIdx.y);
-}
-
-// Batch: one workgroup per (matrix, epilogue block) and probe; the pointers
-// of the base arguments are batch-wide and offset by the matrix's regions.
-__global__ __launch_bounds__(256) void batch_bf16x3_epilogue_kernel(Bf16EpiArgs base,
-                                                                    const BatchMat *__restrict__ mats,
-                                                                    const int2 *__restrict__ etiles) {
-  const int2 t = etiles[blockIdx.x];
-  const BatchMat &M = mats[t.x];
-  Bf16EpiArgs e = base;
-  e.part_y = base.part_y + M.voff;
-  e.Vk = base.Vk + M.voff;
-  e.Vkm1 = base.Vkm1 ? base.Vkm1 + M.voff : nullptr;
-  e.Vkp1 = base.Vkp1 ? base.Vkp1 + M.voff : nullptr;
-  e.V_hi = base.V_hi + M.voff;
-  e.V_lo = base.V_lo + M.voff;
-  e.G = base.G + M.voff;
-  e.scal = M.scal;
-  e.part = base.part + M.poff;
-  e.nblk = M.ntile;
-  e.n_pad = M.n_pad;
-  bf16x3_epilogue_body(e, t.y, blockIdx.y);
-}
-
-hipError_t launch_batch_bf16x3_epilogue(const Bf16EpiArgs &base, const BatchMat *mats,
-                                        const int2 *etiles, int32_t netiles, hipStream_t st) {
-  dim3 grid((unsigned)netiles, (unsigned)base.ldv);
-  batch_bf16x3_epilogue_kernel<<<grid, 256, 0, st>>>(base, mats, etiles);
-  return hipGetLastError();
 }
 
 int32_t bf16x3_epilogue_blocks(int64_t n_pad) { return (int32_t)((n_pad / 8 + 255) / 256); }
