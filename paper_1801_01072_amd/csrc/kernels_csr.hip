@@ -2,10 +2,13 @@
 // R, bandwidth bound: Y = a * (R V_k), Z = c1*Y + c2*b*V_k + cw*V_{k-1},
 // per-probe dots with g (same algebra as the dense step).
 //
-// Mapping: a row is handled by a group of L lanes, each owning P consecutive
-// probes of a 64-probe chunk (P = 8, L = 8 in FP32; P = 4, L = 16 in FP64:
-// 32 bytes per lane), so a wave works on 64 / L rows at once and every V row
-// access is one contiguous 256 B (FP32) or 512 B (FP64) segment per row.
+// Mapping: a row is handled by a group of L lanes, each owning P probes of a
+// 64-probe chunk (P = 8, L = 8 in FP32; P = 4, L = 16 in FP64: 32 bytes per
+// lane) as two 16-byte pieces, one in each half of the row's segment: lane o
+// holds bytes [16 o, 16 o + 16) of both halves.  A wave works on 64 / L rows
+// at once, every V row access is one contiguous 256 B (FP32) or 512 B (FP64)
+// segment per row, and each 16-byte access of a group covers one half of its
+// row without gaps, so the group's LDS reads do not collide on banks.
 //
 // A workgroup walks a contiguous range of row chunks (CH = rows per wave x
 // waves).  The V_k rows a chunk's columns span (its window, found once per
@@ -38,10 +41,10 @@ struct CsrLanes {
   static constexpr int RPW = 64 / L;               // rows per wave
   static constexpr int CH = RPW * kCsrWaves;       // rows per chunk
   static constexpr int ROWB = 64 * (int)sizeof(T); // bytes of one V row chunk
+  static constexpr int VE = 16 / (int)sizeof(T);   // elements per 16-byte piece
+  static constexpr int HALF = ROWB / 2;             // bytes of half a row chunk
   static constexpr int WROWS = 64;                 // window capacity in rows
   static constexpr int WBYTES = WROWS * ROWB;      // one window buffer
-  // resident workgroups per CU (LDS: two window buffers each; 256 CUs)
-  static constexpr int BLOCKS_PER_CU = sizeof(T) == 4 ? 4 : 2;
 };
 
 int32_t csr_chunk_rows(int32_t fp64) { return fp64 ? CsrLanes<double>::CH : CsrLanes<float>::CH; }
@@ -81,40 +84,78 @@ hipError_t launch_csr_chunk_window(const int64_t *rp, const int32_t *ci, int64_t
   return hipGetLastError();
 }
 
-// P consecutive probes p0..p0+P-1 of row r (p0 a multiple of P).
+// Probe (within the 64-probe chunk) of element e of lane o's P values.
+template <typename T>
+__device__ __forceinline__ int probe_of(int o, int e) {
+  constexpr int VE = CsrLanes<T>::VE;
+  return 32 * (e / VE) + VE * o + e % VE;
+}
+
+// Lane o's P probes of row r in the chunk starting at probe chunk0 (a
+// multiple of 64): from V, or expanded from the sign bits.
 template <typename T, bool SIGNS>
 __device__ __forceinline__ void load_row(const T *__restrict__ V, const uint32_t *__restrict__ signs,
-                                         int64_t r, int64_t ldv, int32_t nw, int32_t p0, T *x) {
-  constexpr int P = CsrLanes<T>::P;
+                                         int64_t r, int64_t ldv, int32_t nw, int32_t chunk0, int o,
+                                         T *x) {
+  constexpr int VE = CsrLanes<T>::VE;
   if (SIGNS) {
-    const uint32_t wd = signs[r * nw + (p0 >> 5)] >> (p0 & 31);
 #pragma unroll
-    for (int e = 0; e < P; ++e) x[e] = ((wd >> e) & 1u) ? T(-1) : T(1);
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t wd = signs[r * nw + (chunk0 >> 5) + h] >> (VE * o);
+#pragma unroll
+      for (int e = 0; e < VE; ++e) x[h * VE + e] = ((wd >> e) & 1u) ? T(-1) : T(1);
+    }
   } else {
-    typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
-    constexpr int VE = 16 / (int)sizeof(T);
-    const v16 *src = (const v16 *)(V + r * ldv + p0);
+    typedef T v16 __attribute__((ext_vector_type(VE)));
+    const T *src = V + r * ldv + chunk0 + VE * o;
 #pragma unroll
-    for (int h = 0; h < P / VE; ++h) {
-      const v16 q = src[h];
+    for (int h = 0; h < 2; ++h) {
+      const v16 q = *(const v16 *)(src + 32 * h);
 #pragma unroll
       for (int e = 0; e < VE; ++e) x[h * VE + e] = q[e];
     }
   }
 }
 
-// The same P probes from a window row in LDS.
+// The same P probes from a row in LDS; `row` points at byte 16 o of the row.
 template <typename T>
 __device__ __forceinline__ void lds_row(const uint8_t *row, T *x) {
-  constexpr int P = CsrLanes<T>::P;
-  typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
-  constexpr int VE = 16 / (int)sizeof(T);
-  const v16 *src = (const v16 *)row;
+  constexpr int VE = CsrLanes<T>::VE;
+  typedef T v16 __attribute__((ext_vector_type(VE)));
 #pragma unroll
-  for (int h = 0; h < P / VE; ++h) {
-    const v16 q = src[h];
+  for (int h = 0; h < 2; ++h) {
+    const v16 q = *(const v16 *)(row + CsrLanes<T>::HALF * h);
 #pragma unroll
     for (int e = 0; e < VE; ++e) x[h * VE + e] = q[e];
+  }
+}
+
+// Lane o's P values z into row r of V (global memory).
+template <typename T>
+__device__ __forceinline__ void store_row(T *V, int64_t r, int64_t ldv, int32_t chunk0, int o, const T *z) {
+  constexpr int VE = CsrLanes<T>::VE;
+  typedef T v16 __attribute__((ext_vector_type(VE)));
+  T *dst = V + r * ldv + chunk0 + VE * o;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    v16 q;
+#pragma unroll
+    for (int e = 0; e < VE; ++e) q[e] = z[h * VE + e];
+    *(v16 *)(dst + 32 * h) = q;
+  }
+}
+
+// The same into a row in LDS; `row` points at byte 16 o of the row.
+template <typename T>
+__device__ __forceinline__ void lds_store_row(uint8_t *row, const T *z) {
+  constexpr int VE = CsrLanes<T>::VE;
+  typedef T v16 __attribute__((ext_vector_type(VE)));
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    v16 q;
+#pragma unroll
+    for (int e = 0; e < VE; ++e) q[e] = z[h * VE + e];
+    *(v16 *)(row + CsrLanes<T>::HALF * h) = q;
   }
 }
 
@@ -142,7 +183,6 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
   const int64_t n = a.n, ldv = a.ldv;
   const int32_t nw = (int32_t)(ldv >> 5);
   const int32_t chunk0 = (int32_t)blockIdx.y * 64;
-  const int32_t p0 = chunk0 + P * o;
   const int64_t *__restrict__ rp = a.row_ptr;
   const int32_t *__restrict__ ci = a.col_idx;
   const T *__restrict__ val = (const T *)a.values;
@@ -204,18 +244,7 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
   __syncthreads();
   for (int64_t c = c_beg; c < c_end; ++c) {
     const int buf = (int)((c - c_beg) & 1);
-    if (zrow >= 0 && Vkp1) {
-      typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
-      constexpr int VE = 16 / (int)sizeof(T);
-      v16 *dst = (v16 *)(Vkp1 + zrow * ldv + p0);
-#pragma unroll
-      for (int h = 0; h < P / VE; ++h) {
-        v16 q;
-#pragma unroll
-        for (int e = 0; e < VE; ++e) q[e] = zs[h * VE + e];
-        dst[h] = q;
-      }
-    }
+    if (zrow >= 0 && Vkp1) store_row<T>(Vkp1, zrow, ldv, chunk0, o, zs);
     zrow = -1;
     if (use_win && c + 1 < c_end) stage(c + 1, buf ^ 1);
     int2 mw = make_int2(0, 0);
@@ -224,7 +253,7 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
       mw = win[c];
       inlds = mw.y - mw.x + 1 <= C::WROWS;
     }
-    const uint8_t *wb = &wbuf[use_win ? buf : 0][0] + P * (int)sizeof(T) * o;
+    const uint8_t *wb = &wbuf[use_win ? buf : 0][0] + 16 * o;
 
     const int64_t r = c * CH + RPW * w + g;
     const bool live = r < r_lim;
@@ -241,20 +270,20 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
     if (inlds)
       lds_row<T>(wb + (rr - mw.x) * ROWB, xr);
     else
-      load_row<T, VK_SIGNS>(Vk, signs, rr, ldv, nw, p0, xr);
+      load_row<T, VK_SIGNS>(Vk, signs, rr, ldv, nw, chunk0, o, xr);
     if (use_m1) {
       if (M1 == 2)
-        load_row<T, true>(nullptr, signs, rr, ldv, nw, p0, vm);
+        load_row<T, true>(nullptr, signs, rr, ldv, nw, chunk0, o, vm);
       else
-        load_row<T, false>(Vkm1, nullptr, rr, ldv, nw, p0, vm);
+        load_row<T, false>(Vkm1, nullptr, rr, ldv, nw, chunk0, o, vm);
     } else {
 #pragma unroll
       for (int e = 0; e < P; ++e) vm[e] = T(0);
     }
     if (signs)
-      load_row<T, true>(nullptr, signs, rr, ldv, nw, p0, gv);
+      load_row<T, true>(nullptr, signs, rr, ldv, nw, chunk0, o, gv);
     else
-      load_row<T, false>(G, nullptr, rr, ldv, nw, p0, gv);
+      load_row<T, false>(G, nullptr, rr, ldv, nw, chunk0, o, gv);
     // longest row of the wave: the number of gather rounds
     int mlen = len;
 #pragma unroll
@@ -292,7 +321,7 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
 #pragma unroll
           for (int q = 0; q < U; ++q) {
             const int32_t col = __shfl(mc[t], gl + q, 64);
-            load_row<T, VK_SIGNS>(Vk, signs, col, ldv, nw, p0, x[q]);
+            load_row<T, VK_SIGNS>(Vk, signs, col, ldv, nw, chunk0, o, x[q]);
           }
         }
 #pragma unroll
@@ -318,18 +347,7 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
     // the next window has landed, and every wave is done with this one
     __syncthreads();
   }
-  if (zrow >= 0 && Vkp1) {
-    typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
-    constexpr int VE = 16 / (int)sizeof(T);
-    v16 *dst = (v16 *)(Vkp1 + zrow * ldv + p0);
-#pragma unroll
-    for (int h = 0; h < P / VE; ++h) {
-      v16 q;
-#pragma unroll
-      for (int e = 0; e < VE; ++e) q[e] = zs[h * VE + e];
-      dst[h] = q;
-    }
-  }
+  if (zrow >= 0 && Vkp1) store_row<T>(Vkp1, zrow, ldv, chunk0, o, zs);
   // per probe: sum over the wave's rows (lanes o, o+L, ...), then over waves
 #pragma unroll
   for (int e = 0; e < P; ++e) {
@@ -342,8 +360,8 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
   if (lane < L) {
 #pragma unroll
     for (int e = 0; e < P; ++e) {
-      red[0][w][P * lane + e] = ds[e];
-      red[1][w][P * lane + e] = GG ? gs[GG ? e : 0] : 0.0;
+      red[0][w][probe_of<T>(lane, e)] = ds[e];
+      red[1][w][probe_of<T>(lane, e)] = GG ? gs[GG ? e : 0] : 0.0;
     }
   }
   __syncthreads();
@@ -360,11 +378,44 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
   }
 }
 
-// Persistent grid: the resident workgroups of 256 CUs, fewer for small n.
+// Workgroups of the step kernels resident at once on the current device:
+// CUs x the smallest per-CU occupancy over the instances a recurrence
+// launches (registers or LDS bound it).  Every workgroup walks an equal
+// share of the chunks, so a grid larger than this would finish in a second,
+// partial round that takes as long as the first.
+template <typename T>
+static int32_t csr_resident_blocks() {
+  static int32_t cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+  if (dev < 64 && cache[dev] > 0) return cache[dev];
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  const void *kern[] = {(const void *)csr_step_kernel<T, true, 0, true>,
+                        (const void *)csr_step_kernel<T, false, 0, true>,
+                        (const void *)csr_step_kernel<T, true, 0, false>,
+                        (const void *)csr_step_kernel<T, false, 0, false>,
+                        (const void *)csr_step_kernel<T, false, 1, false>,
+                        (const void *)csr_step_kernel<T, false, 2, false>};
+  int per_cu = 1 << 30;
+  for (const void *k : kern) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, 64 * kCsrWaves, 0) == hipSuccess && b > 0 &&
+        b < per_cu)
+      per_cu = b;
+  }
+  if (per_cu == 1 << 30) per_cu = 1;
+  const int32_t r = (int32_t)(cus * per_cu);
+  if (dev < 64) cache[dev] = r;
+  return r;
+}
+
+// Persistent grid: the resident workgroups, fewer for small n.
 int32_t csr_step_blocks(int64_t n, int32_t fp64) {
   const int64_t ch = fp64 ? CsrLanes<double>::CH : CsrLanes<float>::CH;
   const int64_t groups = (n + ch - 1) / ch;
-  const int64_t cap = 256 * (fp64 ? CsrLanes<double>::BLOCKS_PER_CU : CsrLanes<float>::BLOCKS_PER_CU);
+  const int64_t cap = fp64 ? csr_resident_blocks<double>() : csr_resident_blocks<float>();
   return (int32_t)(groups < cap ? groups : cap);
 }
 

@@ -202,6 +202,24 @@ def test_csr_ragged(orc, n, s):
         check_fp64(gpu, per, mom, ref, orc, csr, "chebyshev", m, s, seed, d, label=f"csr {n} {s} {dist}")
 
 
+def test_csr_wide_windows_fall_back(orc):
+    # scattered columns: most chunks' column windows exceed the LDS window
+    # buffer, so the step gathers those chunks' V_k rows from global memory
+    import scipy.sparse as sp
+
+    n, m, s, seed = 3000, 12, 32, 6
+    rng = np.random.default_rng(8)
+    B = sp.random(n, n, density=4.0 / n, random_state=rng, format="csr") + sp.eye(n, format="csr")
+    Rs = (B @ B.T).tocsr()
+    Rs = Rs / Rs.diagonal().sum()
+    Rs.sort_indices()
+    csr = (Rs.indptr.astype(np.int64), Rs.indices.astype(np.int32), Rs.data.astype(np.float64))
+    for method in ("chebyshev", "taylor"):
+        gpu, per, mom = ent.entropy_estimate_detail(csr_to_dev(csr + (n,)), method, m, s, seed)
+        ref = orc.estimate(csr + (n,), 0 if method == "taylor" else 1, m, s, seed)
+        check_fp64(gpu, per, mom, ref, orc, csr + (n,), method, m, s, seed, 0, label=f"csr wide {method}")
+
+
 def test_csr_poisson_closed_form():
     # tridiagonal experiment: exact H from lambda_i = (4/2n) sin^2(i pi/(2n+2))
     n = 100_000
