@@ -222,6 +222,7 @@ hipError_t launch_batch_probe_t(const BatchMat *mats, const int2 *tiles, int32_t
 namespace {
 constexpr int kBK = 32;        // k per stage
 constexpr int kKS = kBK / 16;  // MFMA k-steps per stage
+constexpr int kNonTemporal = 2;  // cache-policy bits of a load: non-temporal
 }  // namespace
 
 template <int BN, int WM>
@@ -262,7 +263,8 @@ __device__ __forceinline__ void bf16x3_gemm_tile(const uint16_t *__restrict__ A_
                                                  int64_t kbeg, int nst, int64_t row0, int64_t col0,
                                                  const Bf16EpiArgs *ep, int64_t ptile) {
   typedef GemmShape<BN, WM> S;
-  static_assert(S::FST % S::WAVES == 0, "fragments must split evenly over the waves");
+  static_assert(S::FST % S::WAVES == 0 && S::FA % S::WAVES == 0,
+                "A and B fragments must split evenly over the waves");
   static_assert(S::STAGES >= 2, "at least two stages");
   __shared__ __attribute__((aligned(1024))) uint8_t lds[S::LDS_BYTES];
 
@@ -289,13 +291,20 @@ __device__ __forceinline__ void bf16x3_gemm_tile(const uint16_t *__restrict__ A_
     }
     src[i] = p + 8 * lane;
   }
+  // A is streamed once per product: its loads carry the non-temporal hint so
+  // they do not displace the probe block (re-read by every row tile of the
+  // same K-split on this XCD) or the partial sums the epilogue reads next
   auto issue = [&](int t) {
     uint8_t *base = lds + (t % S::STAGES) * S::FST * 1024;
 #pragma unroll
-    for (int i = 0; i < S::PER_WAVE; ++i)
-      __builtin_amdgcn_global_load_lds((const void *)(src[i] + (int64_t)t * kKS * 512),
-                                       (__attribute__((address_space(3))) void *)(base + (w + S::WAVES * i) * 1024),
-                                       16, 0, 0);
+    for (int i = 0; i < S::PER_WAVE; ++i) {
+      const void *g = (const void *)(src[i] + (int64_t)t * kKS * 512);
+      auto *l = (__attribute__((address_space(3))) void *)(base + (w + S::WAVES * i) * 1024);
+      if (i < S::FA / S::WAVES)
+        __builtin_amdgcn_global_load_lds(g, l, 16, 0, kNonTemporal);
+      else
+        __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+    }
   };
 
   f32x16 acc[2][S::WCB];
