@@ -1,7 +1,9 @@
 // kernels_bf16.hip -- BF16x3 split-precision recurrence step for dense R.
 //
-// A = a*R is split once per estimate into bf16 hi = RNE(A), lo = RNE(A - hi)
-// (zero padded to n_pad x n_pad).  Each step forms
+// A = R is split once per estimate into bf16 hi = RNE(A), lo = RNE(A - hi)
+// (zero padded to n_pad x n_pad; the interval scale a multiplies the FP32
+// product in the epilogue, so the power method reads the same split).  Each
+// step forms
 //     Y = A_hi V_hi + A_hi V_lo + A_lo V_hi          (FP32 accumulation)
 // on the gfx950 BF16 matrix cores (v_mfma_f32_32x32x16_bf16), then an
 // elementwise epilogue applies the recurrence in FP32, re-splits V_{k+1}
@@ -23,12 +25,13 @@
 // 8(l/32)..8(l/32)+7; B column l%32, same k-slots; D register r holds row
 // 8(r/4) + 4(l/32) + r%4, column l%32.
 //
-// GEMM tiling: a workgroup (4 waves) owns 128 rows x BN probes over one
-// K-split; wave w owns rows 32w..32w+31 and all BN probes, so A is streamed
-// from HBM once per step (each lane loads 16 B of hi and of lo per k-step
-// straight into registers) while the V^T chunk (BN x 32, hi and lo) is
-// shared through LDS.  Split-K partials go to part_y[split][probe][row]; the
-// epilogue sums them in split order (deterministic).
+// GEMM tiling: a workgroup of 2 WM waves owns 64 WM rows (256 when n_pad
+// allows, else 128) x BN probes over one K-split; each wave computes 64 rows
+// x BN/2 probes.  A and V^T fragments reach LDS by direct global-to-LDS
+// loads in a ring of 32-k stages, so A is streamed from HBM once per step.
+// Split-K partials go to part_y[split][probe][row]; the epilogue sums them in
+// split order (deterministic).  Workgroups are remapped so that those on one
+// XCD share a K-split and hence their slice of V^T in that XCD's L2.
 #include "device_common.hpp"
 #include "kernels.hpp"
 
