@@ -45,7 +45,7 @@ typedef enum {
 } ent_status;
 
 /* Estimator (Algorithm 1 = Taylor, Section 2; Algorithm 2 = Chebyshev,
- * Section 3; Algorithm 3 = random projection, Section 4). */
+ * Section 3; Algorithm 3 = random projection, Section 5). */
 typedef enum {
   ENT_TAYLOR = 0,
   ENT_CHEBYSHEV = 1,

@@ -47,6 +47,11 @@ class _Mat(ctypes.Structure):
                 ("col_idx", ctypes.c_void_p)]
 
 
+class _ZMat(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("ld", ctypes.c_int64), ("values", ctypes.c_void_p)]
+
+
 class _Res(ctypes.Structure):
     _fields_ = [("entropy", ctypes.c_double), ("p1_est", ctypes.c_double),
                 ("u", ctypes.c_double), ("std_err", ctypes.c_double)]
@@ -86,6 +91,13 @@ def _load():
         "orc_mlp_loss_grad": (d, [P, i32, P, P, P]),
         "orc_max_threads": (i32, []),
         "orc_cutoff_nodes": (i32, [i32]),
+        "orc_zmatvec": (None, [P, P, P]),
+        "orc_zpower_method": (d, [P, i32, i32, u64]),
+        "orc_zcheb_quadform": (d, [P, P, i32, d, d, P]),
+        "orc_zcheb_moments_forward": (None, [P, d, d, i32, P, P]),
+        "orc_ztaylor_quadform": (d, [P, d, i32, P]),
+        "orc_zestimate": (ctypes.c_int, [P, i32, i32, i32, u64, i32, i32, d, i32,
+                                         d, d, P, i32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -260,6 +272,88 @@ def estimate(R, method: int, m: int, s: int, seed: int, t: int = 20, q: int = 1,
     rc = _load().orc_estimate(M.ref, method, m, s, seed, t, q, c, dist, lo,
                               u_override, _ptr(sel), 0 if sel is None else len(sel),
                               _ptr(pp), ctypes.byref(res))
+    if rc != 0:
+        raise ValueError("oracle estimate rejected its arguments")
+    return Estimate(res.entropy, res.p1_est, res.u, res.std_err, pp)
+
+
+# --------------------------------------------------------------------------
+# Hermitian density matrices (Section 4; Algorithms 1c and 2c)
+# --------------------------------------------------------------------------
+class ZMatrix:
+    """A dense Hermitian matrix (complex128 or complex64 ndarray) for the C side."""
+
+    def __init__(self, A):
+        a = np.asarray(A)
+        if a.dtype not in (np.complex128, np.complex64):
+            a = a.astype(np.complex128)
+        a = np.ascontiguousarray(a)
+        self._keep = a
+        self.n = a.shape[0]
+        self.s = _ZMat(a.shape[0], 0 if a.dtype == np.complex128 else 1, a.shape[1], a.ctypes.data)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def _zmat(R) -> ZMatrix:
+    return R if isinstance(R, ZMatrix) else ZMatrix(R)
+
+
+def zmatvec(R, x) -> np.ndarray:
+    M = _zmat(R)
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    y = np.empty(M.n, dtype=np.complex128)
+    _load().orc_zmatvec(M.ref, _ptr(x), _ptr(y))
+    return y
+
+
+def zpower_method(R, t: int = 20, q: int = 1, seed: int = 0) -> float:
+    """Algorithm 4 with a complex iterate (start s_i + i s_{n+i}, stream 1)."""
+    return _load().orc_zpower_method(_zmat(R).ref, t, q, seed)
+
+
+def zcheb_quadform(R, alpha, lo: float, u: float, g) -> float:
+    """g^T Re[f_m(R)] g by the complex vector Clenshaw recurrence."""
+    M = _zmat(R)
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    return _load().orc_zcheb_quadform(M.ref, _ptr(a), len(a) - 1, lo, u, _ptr(g))
+
+
+def zcheb_moments_forward(R, lo: float, u: float, m: int, g) -> np.ndarray:
+    """d_k = g^T Re[T_k(X)] g, k = 0..m."""
+    M = _zmat(R)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    d = np.empty(m + 1, dtype=np.float64)
+    _load().orc_zcheb_moments_forward(M.ref, lo, u, m, _ptr(g), _ptr(d))
+    return d
+
+
+def ztaylor_quadform(R, u: float, m: int, g) -> float:
+    """sum_{k=1}^m g^T Re[R (I - R/u)^k] g / k (Algorithm 1c at u = 1)."""
+    M = _zmat(R)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    return _load().orc_ztaylor_quadform(M.ref, u, m, _ptr(g))
+
+
+def zestimate(R, method: int, m: int, s: int, seed: int, t: int = 20, q: int = 1,
+              c: float = 6.0, dist: int = GAUSSIAN, lo: float = 0.0,
+              u_override: float = 1.0, probes=None) -> Estimate:
+    """Algorithms 1c (method=0) and 2c (method=1) on Hermitian R.
+
+    u_override = 1 is the paper's choice for Hermitian inputs; 0 runs the
+    complex power method and takes u = min{1, c p~1}.
+    """
+    M = _zmat(R)
+    sel = None if probes is None else np.ascontiguousarray(probes, dtype=np.int32)
+    cnt = s if sel is None else len(sel)
+    pp = np.empty(cnt, dtype=np.float64)
+    res = _Res()
+    rc = _load().orc_zestimate(M.ref, method, m, s, seed, t, q, c, dist, lo, u_override,
+                               _ptr(sel), 0 if sel is None else len(sel), _ptr(pp),
+                               ctypes.byref(res))
     if rc != 0:
         raise ValueError("oracle estimate rejected its arguments")
     return Estimate(res.entropy, res.p1_est, res.u, res.std_err, pp)

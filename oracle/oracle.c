@@ -19,9 +19,10 @@
  * Parity pins (see tests/test_oracle_*.py): Philox known-answer vectors, closed
  * forms for the Chebyshev coefficients (Lemma 3), the tight truncation bound
  * at x = 0, pure / maximally mixed / diagonal states, the Poisson spectrum
- * (Section 5, tridiagonal experiment), exhaustive 2^n sign enumeration for
+ * (Section 6, tridiagonal experiment), exhaustive 2^n sign enumeration for
  * Hutchinson unbiasedness (Lemma 1), finite differences for the MLP.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -405,6 +406,220 @@ int orc_estimate(const orc_matrix *R, int32_t method, int32_t m, int32_t s,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Hermitian density matrices (Section 4).  R = B + iC with B symmetric and  */
+/* C skew-symmetric; tr R = tr B (Theorem of Section 4), so Lemma 1 applies */
+/* to Re[f(R)] with real probes.  Algorithms 1c / 2c are Algorithms 1 / 2   */
+/* with g^T Re[...] g, and with u = 1 in place of the power-method bound.    */
+/* Complex arithmetic is C99 double complex, element by element.            */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t n;
+  int32_t dtype; /* 0 = complex double, 1 = complex float: interleaved (re, im) */
+  int64_t ld;    /* leading dimension in complex elements                     */
+  const void *values;
+} orc_zmatrix;
+
+static double complex orc_zelem(const orc_zmatrix *R, int64_t i, int64_t j) {
+  int64_t o = 2 * (i * R->ld + j);
+  if (R->dtype == 0) {
+    const double *v = (const double *)R->values;
+    return v[o] + I * v[o + 1];
+  }
+  const float *v = (const float *)R->values;
+  return (double)v[o] + I * (double)v[o + 1];
+}
+
+/* y = R x, complex x and y. */
+void orc_zmatvec(const orc_zmatrix *R, const double complex *x, double complex *y) {
+  for (int64_t i = 0; i < R->n; ++i) {
+    double complex acc = 0.0;
+    for (int64_t j = 0; j < R->n; ++j) acc += orc_zelem(R, i, j) * x[j];
+    y[i] = acc;
+  }
+}
+
+static double orc_znorm2(int64_t n, const double complex *x) {
+  double acc = 0.0;
+  for (int64_t i = 0; i < n; ++i) acc += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
+  return acc;
+}
+
+/*
+ * Power method on Hermitian R (Algorithm 4 with a complex iterate): the
+ * start vector of trial q is x_i = s_i + i s_{n+i}, s the Rademacher signs of
+ * stream 1 at indices 0..2n-1; x <- R x / ||R x|| t times; Rayleigh quotient
+ * Re(x^H R x) / x^H x of the last iterate; maximum over trials.  (The paper
+ * uses u = 1 for Hermitian R because no accuracy bound is known for this
+ * iteration; the estimator calls it only when asked.)
+ */
+double orc_zpower_method(const orc_zmatrix *R, int32_t t, int32_t q, uint64_t seed) {
+  int64_t n = R->n;
+  double complex *x = (double complex *)malloc(sizeof(double complex) * n);
+  double complex *y = (double complex *)malloc(sizeof(double complex) * n);
+  double best = -INFINITY;
+  for (int32_t trial = 0; trial < q; ++trial) {
+    for (int64_t i = 0; i < n; ++i)
+      x[i] = orc_probe_value(seed, 0, 1u, i, trial) + I * orc_probe_value(seed, 0, 1u, n + i, trial);
+    for (int32_t it = 0; it < t; ++it) {
+      orc_zmatvec(R, x, y);
+      double nrm = sqrt(orc_znorm2(n, y));
+      for (int64_t i = 0; i < n; ++i) x[i] = y[i] / nrm;
+    }
+    orc_zmatvec(R, x, y);
+    double complex xy = 0.0;
+    for (int64_t i = 0; i < n; ++i) xy += conj(x[i]) * y[i];
+    double rq = creal(xy) / orc_znorm2(n, x);
+    if (rq > best) best = rq;
+  }
+  free(x);
+  free(y);
+  return best;
+}
+
+/*
+ * g^T Re[f_m(R)] g for real g by the vector Clenshaw recurrence (Algorithm 5)
+ * with complex y_k:  y_k = alpha_k g + 2 X y_{k+1} - y_{k+2},
+ * X = (2R - (u+lo) I)/(u - lo); f_m(R) g = (alpha_0 g + y_0 - y_2)/2, and
+ * since g is real, g^T Re[f_m(R)] g = (alpha_0 g^T g + g^T Re(y_0 - y_2))/2.
+ */
+double orc_zcheb_quadform(const orc_zmatrix *R, const double *alpha, int32_t m, double lo,
+                          double u, const double *g) {
+  int64_t n = R->n;
+  double complex *y1 = (double complex *)calloc(n, sizeof(double complex));
+  double complex *y2 = (double complex *)calloc(n, sizeof(double complex));
+  double complex *yk = (double complex *)calloc(n, sizeof(double complex));
+  double complex *ry = (double complex *)calloc(n, sizeof(double complex));
+  double complex *ysave2 = (double complex *)calloc(n, sizeof(double complex));
+  double a = 2.0 / (u - lo);
+  double sh = (u + lo) / (u - lo);
+  for (int32_t k = m; k >= 0; --k) {
+    orc_zmatvec(R, y1, ry);
+    for (int64_t i = 0; i < n; ++i) yk[i] = alpha[k] * g[i] + 2.0 * (a * ry[i] - sh * y1[i]) - y2[i];
+    if (k == 2) memcpy(ysave2, yk, sizeof(double complex) * n);
+    double complex *tmp = y2;
+    y2 = y1;
+    y1 = yk;
+    yk = tmp;
+  }
+  double gg = 0.0, gy0 = 0.0, gy2 = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    gg += g[i] * g[i];
+    gy0 += g[i] * creal(y1[i]);
+    if (m >= 2) gy2 += g[i] * creal(ysave2[i]);
+  }
+  double res = 0.5 * (alpha[0] * gg + gy0 - gy2);
+  free(y1); free(y2); free(yk); free(ry); free(ysave2);
+  return res;
+}
+
+/* d_k = g^T Re[T_k(X)] g, k = 0..m, by the forward three-term recurrence. */
+void orc_zcheb_moments_forward(const orc_zmatrix *R, double lo, double u, int32_t m,
+                               const double *g, double *d) {
+  int64_t n = R->n;
+  double complex *tm1 = (double complex *)malloc(sizeof(double complex) * n);
+  double complex *tk = (double complex *)malloc(sizeof(double complex) * n);
+  double complex *tp1 = (double complex *)malloc(sizeof(double complex) * n);
+  double complex *r = (double complex *)malloc(sizeof(double complex) * n);
+  double a = 2.0 / (u - lo);
+  double sh = (u + lo) / (u - lo);
+  double acc = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    tk[i] = g[i];
+    acc += g[i] * g[i];
+  }
+  d[0] = acc;
+  for (int32_t k = 0; k < m; ++k) {
+    orc_zmatvec(R, tk, r);
+    acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      double complex xt = a * r[i] - sh * tk[i];
+      tp1[i] = (k == 0) ? xt : 2.0 * xt - tm1[i];
+      acc += g[i] * creal(tp1[i]);
+    }
+    d[k + 1] = acc;
+    double complex *tmp = tm1;
+    tm1 = tk;
+    tk = tp1;
+    tp1 = tmp;
+  }
+  free(tm1); free(tk); free(tp1); free(r);
+}
+
+/*
+ * The Taylor form of Algorithm 1c generalised to an interval [0, u]:
+ *   sum_{k=1}^{m} g^T Re[R (I - R/u)^k] g / k      (u = 1: Algorithm 1c)
+ * with v_k = (I - R/u)^k g (complex) and w = R g: R Hermitian means
+ * R^T = conj(R), so g^T R v = (R^T g)^T v = sum_i conj(w_i) v_i for real g.
+ */
+double orc_ztaylor_quadform(const orc_zmatrix *R, double u, int32_t m, const double *g) {
+  int64_t n = R->n;
+  double complex *w = (double complex *)malloc(sizeof(double complex) * n);
+  double complex *v = (double complex *)malloc(sizeof(double complex) * n);
+  double complex *rv = (double complex *)malloc(sizeof(double complex) * n);
+  for (int64_t i = 0; i < n; ++i) v[i] = g[i];
+  orc_zmatvec(R, v, w);
+  double acc = 0.0;
+  for (int32_t k = 1; k <= m; ++k) {
+    orc_zmatvec(R, v, rv);
+    for (int64_t i = 0; i < n; ++i) v[i] = v[i] - rv[i] / u;
+    double complex wv = 0.0;
+    for (int64_t i = 0; i < n; ++i) wv += conj(w[i]) * v[i];
+    acc += creal(wv) / (double)k;
+  }
+  free(w); free(v); free(rv);
+  return acc;
+}
+
+/*
+ * Algorithms 1c (method 0) and 2c (method 1) on Hermitian R: the estimators
+ * of orc_estimate with Re[...] quadratic forms.  u_override > 0 sets u (the
+ * paper's choice for Hermitian R is u = 1); otherwise u = min{1, c p~1} with
+ * p~1 from orc_zpower_method.  probe_idx as in orc_estimate.
+ */
+int orc_zestimate(const orc_zmatrix *R, int32_t method, int32_t m, int32_t s, uint64_t seed,
+                  int32_t t, int32_t q, double c, int32_t dist, double lo, double u_override,
+                  const int32_t *probe_idx, int32_t nsel, double *per_probe, orc_result *out) {
+  if (!R || !out || m < 1 || s < 1 || R->n < 1) return -1;
+  int64_t n = R->n;
+  double p1 = u_override > 0.0 ? u_override : orc_zpower_method(R, t, q, seed);
+  double u = u_override > 0.0 ? u_override : fmin(1.0, c * p1);
+  int32_t cnt = probe_idx ? nsel : s;
+  double *alpha = (double *)malloc(sizeof(double) * (m + 1));
+  if (method == 1) {
+    if (lo > 0.0)
+      orc_cheb_interp_coeffs(lo, u, m, orc_cutoff_nodes(m), alpha);
+    else
+      orc_cheb_coeffs(u, m, alpha);
+  }
+  double *h = (double *)malloc(sizeof(double) * (cnt > 0 ? cnt : 1));
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t p = 0; p < cnt; ++p) {
+    int64_t j = probe_idx ? probe_idx[p] : p;
+    double *g = (double *)malloc(sizeof(double) * n);
+    orc_probe_vector(seed, dist, 0u, n, j, g);
+    if (method == 0)
+      h[p] = log(1.0 / u) + orc_ztaylor_quadform(R, u, m, g);
+    else
+      h[p] = -orc_zcheb_quadform(R, alpha, m, lo, u, g);
+    free(g);
+  }
+  double mean = 0.0;
+  for (int32_t p = 0; p < cnt; ++p) mean += h[p];
+  mean /= (double)cnt;
+  double var = 0.0;
+  for (int32_t p = 0; p < cnt; ++p) var += (h[p] - mean) * (h[p] - mean);
+  out->entropy = mean;
+  out->p1_est = p1;
+  out->u = u;
+  out->std_err = cnt > 1 ? sqrt(var / ((double)cnt * (double)(cnt - 1))) : 0.0;
+  if (per_probe)
+    for (int32_t p = 0; p < cnt; ++p) per_probe[p] = h[p];
+  free(h);
+  free(alpha);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Exact entropy: eigenvalues by the cyclic Jacobi method, then              */
 /* H = -sum p ln p over p above a round-off threshold (eqn. (1): 0 ln 0 = 0) */
 /* ------------------------------------------------------------------------- */
@@ -508,7 +723,7 @@ double orc_exact_entropy(const orc_matrix *R) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Random projection (Algorithm 3, Section 4): R~ = R Pi (n x s), singular   */
+/* Random projection (Algorithm 3, Section 5): R~ = R Pi (n x s), singular   */
 /* values of R~ via the eigenvalues of the s x s Gram matrix R~^T R~ (Jacobi),*/
 /* keep the k largest, H^ = sum sigma ln(1/sigma).                            */
 /* ------------------------------------------------------------------------- */

@@ -1,4 +1,4 @@
-// kernels_rp.hip -- random-projection estimator (Algorithm 3, Section 4):
+// kernels_rp.hip -- random-projection estimator (Algorithm 3, Section 5):
 // sketch R~ = R Pi (product on the existing MFMA kernels), Gram matrix
 // R~^T R~ in FP64, its eigenvalues by a parallel cyclic Jacobi method in one
 // workgroup, singular values sigma = sqrt(lambda), the k largest kept and

@@ -40,7 +40,7 @@ def test_exact_entropy_invariants(orc):
 
 
 def test_poisson_spectrum_closed_form(orc):
-    # tridiagonal experiment (Section 5): lambda_i = (4/2n) sin^2(i pi/(2n+2))
+    # tridiagonal experiment (Section 6): lambda_i = (4/2n) sin^2(i pi/(2n+2))
     n = 150
     csr = W.poisson_csr(n)
     lam = W.poisson_eigenvalues(n)

@@ -3,7 +3,7 @@
 This module builds inputs only.  It holds none of the estimators' arithmetic
 (no traces, polynomials, power iterations or entropies); both the CPU oracle
 and the GPU library are fed from here.  Shapes and value distributions follow
-the paper's workloads (Section 5): dense random density matrices
+the paper's workloads (Section 6): dense random density matrices
 R = U diag(p) U^T with a random orthogonal U, banded/tridiagonal matrices
 normalised to unit trace, and low-rank matrices with decaying spectra.  The
 paper's QETLAB matrices are not available; these seeded generators stand in
@@ -116,6 +116,47 @@ def low_rank_density_torch(pk: np.ndarray, n: int, seed: int, device: str = "cud
     return (B @ B.T).contiguous()
 
 
+def random_unitary(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Q factor of a complex Gaussian matrix with diag(R) made real positive
+    (Haar measure on U(n))."""
+    Z = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+    Q, Rr = np.linalg.qr(Z)
+    d = np.diagonal(Rr)
+    return Q * (d / np.abs(d))[None, :]
+
+
+def hermitian_density(p: np.ndarray, seed: int, dtype=np.complex128) -> np.ndarray:
+    """R = U diag(p) U^H with Haar-random unitary U, made Hermitian entry by
+    entry (R == R^H exactly).  Stand-in for the random complex density
+    matrices of the paper's Hermitian experiment."""
+    rng = np.random.default_rng(seed)
+    n = len(p)
+    U = random_unitary(n, rng)
+    R = (U * p[None, :]) @ U.conj().T
+    R = 0.5 * (R + R.conj().T)
+    return np.ascontiguousarray(R.astype(dtype))
+
+
+def hermitian_density_torch(p: np.ndarray, seed: int, device: str = "cuda", dtype=None,
+                            rng_device: str = "cpu"):
+    """hermitian_density on a torch device (torch's QR of a seeded complex
+    Gaussian matrix drawn on `rng_device`)."""
+    import torch
+
+    dtype = dtype or torch.complex128
+    g = torch.Generator(device=rng_device).manual_seed(seed)
+    n = len(p)
+    Z = torch.complex(torch.randn((n, n), generator=g, dtype=torch.float64, device=rng_device),
+                      torch.randn((n, n), generator=g, dtype=torch.float64, device=rng_device))
+    Q, Rr = torch.linalg.qr(Z.to(device))
+    d = torch.diagonal(Rr)
+    Q = Q * (d / d.abs())[None, :]
+    pt = torch.as_tensor(p, dtype=torch.float64, device=device).to(torch.complex128)
+    R = (Q * pt[None, :]) @ Q.conj().T
+    R = 0.5 * (R + R.conj().T)
+    return R.to(dtype).contiguous()
+
+
 def maximally_mixed(n: int) -> np.ndarray:
     return np.eye(n, dtype=np.float64) / n
 
@@ -203,7 +244,7 @@ def poisson_csr_fast(n: int, dtype=np.float64):
 
 
 def poisson_eigenvalues(n: int) -> np.ndarray:
-    """Eigenvalues of the trace-normalised tridiagonal matrix (eqn. for lambda_i, Section 5):
+    """Eigenvalues of the trace-normalised tridiagonal matrix (eqn. for lambda_i, Section 6):
     lambda_i = (4 / 2n) sin^2(i pi / (2n + 2)), i = 1..n."""
     i = np.arange(1, n + 1, dtype=np.float64)
     return (4.0 / (2.0 * n)) * np.sin(i * math.pi / (2.0 * n + 2.0)) ** 2
