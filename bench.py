@@ -46,6 +46,9 @@ WORKLOADS = {
                     s=64, dist="rademacher", t=20),
     "learned4096": dict(kind="learned", count=512, n=4096, m=40, s=64, dist="rademacher", t=20),
     "rp65536": dict(kind="rp", n=65536, k=64, s=128, tau=8.0),
+    # Hermitian (complex) density matrix of the paper's Hermitian experiment size
+    "herm5000": dict(kind="herm", n=5000, spectrum=("exp", 600.0), method="chebyshev", m=50,
+                     s=256, dist="gaussian", t=20),
     # plain device-to-device copy of 1 GiB: the achievable HBM rate, and the
     # reference that scales the hardware byte counters of the other kernels
     "copy1g": dict(kind="copy", nbytes=1 << 30),
@@ -87,6 +90,11 @@ def log(msg):
 
 
 def describe(cfg, precision, store):
+    if cfg["kind"] == "herm":
+        sp = cfg["spectrum"]
+        return (f"Hermitian (complex) density matrix n={cfg['n']}, p_i ~ exp(-i/{sp[1]:g}), Haar-random "
+                f"unitary U, {store} storage; {cfg['method']} m={cfg['m']}, s={cfg['s']} {cfg['dist']} "
+                f"probes, u = 6 p~1 from t={cfg['t']} power iterations on the real 2n x 2n form, {precision}")
     if cfg["kind"] == "dense":
         sp = cfg["spectrum"]
         spec = "p_i ~ 1/i" if sp[0] == "inverse" else f"p_i ~ exp(-i/{sp[1]:g})"
@@ -466,14 +474,28 @@ def main():
         return bench_rp(args, cfg)
     if cfg["kind"] == "copy":
         return bench_copy(args, cfg)
-    dense = cfg["kind"] == "dense"
+    herm = cfg["kind"] == "herm"
+    dense = cfg["kind"] in ("dense", "herm")
     precision = args.precision or ("bf16x3" if dense else "f32")
-    store = args.store or ("f64" if dense else ("f32" if precision != "f64" else "f64"))
+    if herm:
+        store = "c64" if args.store == "f32" else "c128"
+    else:
+        store = args.store or ("f64" if dense else ("f32" if precision != "f64" else "f64"))
     n, m, s, t = cfg["n"], cfg["m"], cfg["s"], cfg["t"]
     mseed, pseed = W.MATRIX_SEED + 2, W.PROBE_SEED + 2
     t0 = time.time()
     H_exact = None
-    if dense:
+    if herm:
+        p = W.spectrum_exp(n, cfg["spectrum"][1])
+        cdt = torch.complex64 if store == "c64" else torch.complex128
+        try:
+            Rd = W.hermitian_density_torch(p, mseed, device="cuda:0", dtype=cdt)
+        except RuntimeError as e:  # a device QR this torch build lacks: build it on the host
+            log(f"device QR unavailable ({str(e)[:60]}); building R on the host")
+            Rd = torch.from_numpy(W.hermitian_density(p, mseed)).to("cuda:0").to(cdt)
+        H_exact = float(-np.sum(p * np.log(p)))
+        host_R = None
+    elif dense:
         sp = cfg["spectrum"]
         p = W.spectrum_inverse(n) if sp[0] == "inverse" else W.spectrum_exp(n, sp[1])
         R = W.dense_density(p, mseed)
@@ -489,6 +511,8 @@ def main():
     torch.cuda.synchronize()
     log(f"generated R ({args.workload}, {store}) in {time.time() - t0:.1f}s")
     kw = dict(probe_dist=cfg["dist"], precision=precision, power_iters=t)
+    if herm:
+        kw["flags"] = ent.FLAG_COMPLEX_POWER
 
     for _ in range(args.warmup):
         ent.entropy_estimate(Rd, cfg["method"], m, s, pseed, **kw)
@@ -515,7 +539,8 @@ def main():
                                                                "epilogue_ms", "other_ms")}
     if dense:
         kernel = "bf16x3_gemm_kernel" if precision == "bf16x3" else "dense_step_kernel"
-        flop = 2.0 * n * n * s
+        # a complex n x n by n x s product is 8 n^2 s real flops (the real 2n x 2n form)
+        flop = (8.0 if herm else 2.0) * n * n * s
         achieved = flop / (avg_step_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS[precision],
                 "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK_TFLOPS[precision],
@@ -552,12 +577,21 @@ def main():
         probes = [int(x) for x in np.linspace(0, s - 1, nsamp).astype(int)]
         meth = oracle.CHEBYSHEV if cfg["method"] == "chebyshev" else oracle.TAYLOR
         dist = 1 if cfg["dist"] == "gaussian" else 0
-        tc = time.perf_counter()
-        ref = oracle.estimate(host_R, meth, m, s, pseed, t=t, dist=dist, probes=probes)
-        cpu_s = time.perf_counter() - tc
-        tp = time.perf_counter()
-        oracle.power_method(host_R, t, 1, pseed)
-        power_s = time.perf_counter() - tp
+        if herm:
+            host_R = Rd.cpu().numpy()
+            tc = time.perf_counter()
+            ref = oracle.zestimate(host_R, meth, m, s, pseed, t=t, dist=dist, u_override=0.0, probes=probes)
+            cpu_s = time.perf_counter() - tc
+            tp = time.perf_counter()
+            oracle.zpower_method(host_R, t, 1, pseed)
+            power_s = time.perf_counter() - tp
+        else:
+            tc = time.perf_counter()
+            ref = oracle.estimate(host_R, meth, m, s, pseed, t=t, dist=dist, probes=probes)
+            cpu_s = time.perf_counter() - tc
+            tp = time.perf_counter()
+            oracle.power_method(host_R, t, 1, pseed)
+            power_s = time.perf_counter() - tp
         per_round = max(cpu_s - power_s, 1e-9)
         rounds = int(np.ceil(s / nsamp))
         est_s = power_s + rounds * per_round

@@ -64,8 +64,16 @@ typedef enum {
 
 typedef enum { ENT_DENSE = 0, ENT_CSR = 1 } ent_layout;
 
-/* Storage type of a matrix (independent of the compute precision). */
-typedef enum { ENT_STORE_F64 = 0, ENT_STORE_F32 = 1 } ent_dtype;
+/* Storage type of a matrix (independent of the compute precision).  The
+ * complex types hold a Hermitian density matrix (Section 4) as interleaved
+ * (real, imaginary) pairs; they are accepted by ent_entropy_estimate(_detail)
+ * and ent_power_method, dense layout only. */
+typedef enum {
+  ENT_STORE_F64 = 0,
+  ENT_STORE_F32 = 1,
+  ENT_STORE_C128 = 2,  /* complex double */
+  ENT_STORE_C64 = 3    /* complex float  */
+} ent_dtype;
 
 /* Probe vectors g_1..g_s: the paper draws standard Gaussians (Lemma 1);
  * Rademacher signs are the other unbiased choice. */
@@ -73,8 +81,10 @@ typedef enum { ENT_RADEMACHER = 0, ENT_GAUSSIAN = 1 } ent_probe_dist;
 
 enum {
   ENT_FLAG_SKIP_TRACE_CHECK = 1, /* do not verify tr R = 1                    */
-  ENT_FLAG_AUTOTUNE = 2          /* batches: time the candidate tile shapes on
+  ENT_FLAG_AUTOTUNE = 2,         /* batches: time the candidate tile shapes on
                                     the batch if no cached choice exists      */
+  ENT_FLAG_COMPLEX_POWER = 4     /* Hermitian R: u = min{1, c p~1} from the
+                                    power method instead of the paper's u = 1 */
 };
 
 /*
@@ -84,9 +94,11 @@ enum {
  *  layout ENT_CSR:   row_ptr -> int64[n+1] (row_ptr[0] = 0, non-decreasing,
  *                    row_ptr[n] = nnz), col_idx -> int32[nnz] in [0, n),
  *                    values -> nnz entries; ld ignored.
- *  dtype: ENT_STORE_F64 (double) or ENT_STORE_F32 (float) values.
- * R must be symmetric; symmetry is not checked (an asymmetric R is used as
- * given in the products R.v).
+ *  dtype: ENT_STORE_F64 (double) or ENT_STORE_F32 (float) values; or, dense
+ *         only, ENT_STORE_C128 / ENT_STORE_C64: n x n complex entries as
+ *         interleaved (re, im) pairs, ld counted in complex entries.
+ * R must be symmetric (Hermitian for the complex types); this is not checked
+ * (an asymmetric R is used as given in the products R.v).
  */
 typedef struct {
   int64_t n;
@@ -151,6 +163,16 @@ void ent_options_default(ent_options *opt);
  * opt may be NULL (defaults).  Returns ENT_EINVAL for bad arguments,
  * ENT_ENOTDENSITY if the trace check fails, ENT_ENUMERIC if p~1 <= 0 or the
  * estimate is not finite.
+ *
+ * Hermitian R (complex storage; Section 4, Algorithms 1c and 2c): the same
+ * estimators with h_j = ln(1/u) + sum_k g_j^T Re[R (I - R/u)^k] g_j / k and
+ * h_j = -g_j^T Re[f_m(R)] g_j for real probes g_j.  u = 1 as in the paper
+ * (no power method) unless opt->u_fixed > 0 or ENT_FLAG_COMPLEX_POWER is set.
+ * They run on the real 2n x 2n form [[Re R, -Im R], [Im R, Re R]], built in
+ * a library-owned device buffer of 4 n^2 doubles (C128) or floats (C64) that
+ * is kept for later calls and released by ent_release_workspace(), with
+ * probes [g; 0]; every precision applies.  The trace check is on Re tr R.
+ * ENT_RANDPROJ and ENT_AUTO return ENT_EUNSUPPORTED.
  */
 ent_status ent_entropy_estimate(const ent_matrix *R, int32_t method, int32_t degree,
                                 int32_t probes, uint64_t seed, const ent_options *opt,
@@ -177,7 +199,9 @@ ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int3
 /*
  * Algorithm 4 (Appendix A): q trials of t power iterations from random sign
  * vectors, each iterate divided by its 2-norm, Rayleigh quotient of the last
- * iterate, maximum over trials.  *p1 (host) receives p~1.
+ * iterate, maximum over trials.  *p1 (host) receives p~1.  Hermitian R: the
+ * iteration runs on the real form, i.e. on the complex iterate
+ * x_i = s_i + i s_{n+i} (s the 2n signs of stream 1).
  */
 ent_status ent_power_method(const ent_matrix *R, int32_t t, int32_t q, uint64_t seed,
                             void *stream, double *p1);

@@ -33,10 +33,11 @@ OK, EINVAL, ENOTDENSITY, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3
 TAYLOR, CHEBYSHEV, RANDPROJ, AUTO = 0, 1, 2, 3
 F64, F32, BF16X3 = 0, 1, 2
 DENSE, CSR = 0, 1
-STORE_F64, STORE_F32 = 0, 1
+STORE_F64, STORE_F32, STORE_C128, STORE_C64 = 0, 1, 2, 3
 RADEMACHER, GAUSSIAN = 0, 1
 FLAG_SKIP_TRACE_CHECK = 1
 FLAG_AUTOTUNE = 2
+FLAG_COMPLEX_POWER = 4
 
 _METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ, "auto": AUTO}
 _PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
@@ -173,6 +174,10 @@ def _store_dtype(t) -> int:
         return STORE_F64
     if t.dtype == torch.float32:
         return STORE_F32
+    if t.dtype == torch.complex128:
+        return STORE_C128
+    if t.dtype == torch.complex64:
+        return STORE_C64
     raise TypeError(f"unsupported value dtype {t.dtype}")
 
 

@@ -165,17 +165,50 @@ ent_status ensure_workspace(DeviceWorkspace *w, size_t need) {
   return ENT_OK;
 }
 
+// The 2n x 2n real form of a Hermitian R: one grow-only buffer per device,
+// separate from the workspace (the estimate that runs on the real form
+// carves the workspace from its start).
+struct RealFormBuffer {
+  std::mutex mu;
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_rf_mu;
+std::map<int, RealFormBuffer *> g_rf;
+
+RealFormBuffer *real_form_for(int dev) {
+  std::lock_guard<std::mutex> lk(g_rf_mu);
+  auto it = g_rf.find(dev);
+  if (it != g_rf.end()) return it->second;
+  auto *b = new RealFormBuffer();
+  g_rf[dev] = b;
+  return b;
+}
+
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 constexpr int kScalarDoubles = 8192;
 
-ent_status validate_matrix(const ent_matrix *R) {
+bool is_complex(const ent_matrix *R) {
+  return R->dtype == ENT_STORE_C128 || R->dtype == ENT_STORE_C64;
+}
+
+// allow_complex: the entry point accepts Hermitian (complex) storage.
+ent_status validate_matrix(const ent_matrix *R, bool allow_complex = false) {
   if (!R) return fail(ENT_EINVAL, "R is NULL");
   if (R->n < 1) return fail(ENT_EINVAL, "n = %lld < 1", (long long)R->n);
   if (R->n > (int64_t)INT32_MAX - 64)
     return fail(ENT_EINVAL, "n = %lld exceeds the 32-bit column index range", (long long)R->n);
-  if (R->dtype != ENT_STORE_F64 && R->dtype != ENT_STORE_F32)
+  if (is_complex(R)) {
+    if (!allow_complex)
+      return fail(ENT_EUNSUPPORTED,
+                  "complex (Hermitian) storage is accepted by the estimate and power-method calls only");
+    if (R->layout != ENT_DENSE) return fail(ENT_EUNSUPPORTED, "complex (Hermitian) R must be dense");
+    if (R->n > (int64_t)INT32_MAX / 2 - 64)
+      return fail(ENT_EINVAL, "n = %lld too large for the 2n x 2n real form", (long long)R->n);
+  } else if (R->dtype != ENT_STORE_F64 && R->dtype != ENT_STORE_F32) {
     return fail(ENT_EINVAL, "unknown storage dtype %d", R->dtype);
+  }
   if (!R->values) return fail(ENT_EINVAL, "R->values is NULL");
   if (R->layout == ENT_DENSE) {
     if (R->ld < R->n) return fail(ENT_EINVAL, "ld = %lld < n", (long long)R->ld);
@@ -191,6 +224,11 @@ ent_status validate_matrix(const ent_matrix *R) {
 struct Opts {
   ent_options o;
   hipStream_t st;
+  // Rows of the probe block that carry probes (the rest are zero); -1 = all.
+  // The real form of a Hermitian R has 2n rows and probes [g; 0].
+  int64_t probe_rows = -1;
+  // The matrix's trace is this multiple of tr R (2 for the real form).
+  double trace_div = 1.0;
 };
 
 Opts resolve_options(const ent_options *opt) {
@@ -397,7 +435,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   if (!dense) HIP_TRY(ent::launch_csr_chunk_window(R->row_ptr, R->col_idx, n, ch, cwin, st));
   // probes
   if (dense || !rad)
-    HIP_TRY(ent::launch_probe_gen<T>(G, nullptr, n, n_pad, s, ldv, seed, o.probe_dist, st));
+    HIP_TRY(ent::launch_probe_gen<T>(G, nullptr, op.probe_rows > 0 ? op.probe_rows : n, n_pad, s, ldv,
+                                     seed, o.probe_dist, st));
   else
     HIP_TRY(ent::launch_sign_gen(signs, n, s, ldv, seed, st));
   // power method and interval
@@ -482,8 +521,9 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
 
   if (check_trace) {
     double tol = o.trace_tol > 0 ? o.trace_tol : (R->dtype == ENT_STORE_F64 ? 1e-10 : 1e-4);
-    if (!(std::fabs(hs[ent::S_TRACE] - 1.0) <= tol))
-      return fail(ENT_ENOTDENSITY, "trace of R is %.17g, not 1 within %.3g", hs[ent::S_TRACE], tol);
+    if (!(std::fabs(hs[ent::S_TRACE] / op.trace_div - 1.0) <= tol))
+      return fail(ENT_ENOTDENSITY, "trace of R is %.17g, not 1 within %.3g",
+                  hs[ent::S_TRACE] / op.trace_div, tol);
   }
   if (hs[ent::S_FLAG] != 0.0)
     return fail(ENT_ENUMERIC, "numeric failure: p1~ = %.17g, u = %.17g, estimate = %.17g",
@@ -515,7 +555,10 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   if (R->layout != ENT_DENSE) return fail(ENT_EUNSUPPORTED, "BF16x3 is implemented for dense R only");
   const int64_t n = R->n;
   const bool f64 = R->dtype == ENT_STORE_F64;
-  const int64_t n_pad = round_up(n, 128);
+  // 256-row GEMM tiles run ~8% faster than 128-row ones (n_pad = 8192,
+  // 10240): pad to a multiple of 256 when the extra padded area costs less
+  const int64_t p128 = round_up(n, 128), p256 = round_up(n, 256);
+  const int64_t n_pad = ((double)p256 * (double)p256 <= 1.07 * (double)p128 * (double)p128) ? p256 : p128;
   const int bn = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
   const int64_t ldv = round_up(s, bn);
   const int64_t tiles = (n_pad / ent::bf16x3_tile_rows(n_pad)) * (ldv / bn);
@@ -570,7 +613,8 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
     else
       HIP_TRY(ent::launch_trace_dense<float>((const float *)R->values, R->ld, n, scal, st));
   }
-  HIP_TRY(ent::launch_probe_gen_t(G, Vhi, Vlo, n, n_pad, s, ldv, seed, o.probe_dist, st));
+  HIP_TRY(ent::launch_probe_gen_t(G, Vhi, Vlo, op.probe_rows > 0 ? op.probe_rows : n, n_pad, s, ldv, seed,
+                                  o.probe_dist, st));
   // split R itself once; the power method reads the split (half the bytes of
   // an FP32 copy), and the interval scale a is applied to each product
   if (f64)
@@ -648,8 +692,9 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   pe.finish();
   if (check_trace) {
     double tol = o.trace_tol > 0 ? o.trace_tol : (f64 ? 1e-10 : 1e-4);
-    if (!(std::fabs(hs[ent::S_TRACE] - 1.0) <= tol))
-      return fail(ENT_ENOTDENSITY, "trace of R is %.17g, not 1 within %.3g", hs[ent::S_TRACE], tol);
+    if (!(std::fabs(hs[ent::S_TRACE] / op.trace_div - 1.0) <= tol))
+      return fail(ENT_ENOTDENSITY, "trace of R is %.17g, not 1 within %.3g",
+                  hs[ent::S_TRACE] / op.trace_div, tol);
   }
   if (hs[ent::S_FLAG] != 0.0)
     return fail(ENT_ENUMERIC, "numeric failure: p1~ = %.17g, u = %.17g, estimate = %.17g",
@@ -939,8 +984,9 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
   pe.finish();
   if (check_trace) {
     const double tol = o.trace_tol > 0 ? o.trace_tol : (f64 ? 1e-10 : 1e-4);
-    if (!(std::fabs(hs[ent::S_TRACE] - 1.0) <= tol))
-      return fail(ENT_ENOTDENSITY, "trace of R is %.17g, not 1 within %.3g", hs[ent::S_TRACE], tol);
+    if (!(std::fabs(hs[ent::S_TRACE] / op.trace_div - 1.0) <= tol))
+      return fail(ENT_ENOTDENSITY, "trace of R is %.17g, not 1 within %.3g",
+                  hs[ent::S_TRACE] / op.trace_div, tol);
   }
   if (hs[ent::S_FLAG] != 0.0) return fail(ENT_ENUMERIC, "non-finite random-projection estimate");
   out->entropy = hs[ent::S_ENT];
@@ -1519,6 +1565,70 @@ ent_status batch_collect(ent_graph_s *g, ent_result *outs) {
   return ENT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Hermitian R (Section 4, Algorithms 1c / 2c).  R = B + iC is replaced by its
+// real form M = [[B, -C], [C, B]] (2n x 2n); the recurrence on M with probes
+// [g; 0] equals the complex recurrence on R with the real probe g, and its
+// quadratic forms are g^T Re[f(R)] g.  tr M = 2 tr R and lambda_max(M) =
+// lambda_max(R).  The interval is [0, 1] (the paper's u = 1 for Hermitian
+// inputs) unless the caller fixes u or asks for the power method on M.
+// Holds the device's real-form buffer for the duration of `body`.
+// ---------------------------------------------------------------------------
+template <typename F>
+ent_status with_real_form(const ent_matrix *R, hipStream_t st, F body) {
+  const int64_t n = R->n, n2 = 2 * n;
+  const bool c128 = R->dtype == ENT_STORE_C128;
+  const int64_t ldm = round_up(n2, 4);
+  const size_t bytes = (size_t)n2 * (size_t)ldm * (c128 ? 8 : 4);
+  if (g_ws_limit && bytes > g_ws_limit)
+    return fail(ENT_ENOMEM, "real form of %zu bytes exceeds the workspace limit of %zu bytes", bytes,
+                g_ws_limit);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  RealFormBuffer *b = real_form_for(dev);
+  std::lock_guard<std::mutex> lk(b->mu);
+  if (b->bytes < bytes) {
+    if (b->ptr) {
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(b->ptr));
+      b->ptr = nullptr;
+      b->bytes = 0;
+    }
+    if (hipMalloc(&b->ptr, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      b->ptr = nullptr;
+      return fail(ENT_ENOMEM, "could not allocate the %zu-byte real form of R", bytes);
+    }
+    b->bytes = bytes;
+  }
+  if (c128)
+    HIP_TRY((ent::launch_realify<double, double>((const double *)R->values, R->ld, n, (double *)b->ptr,
+                                                 ldm, st)));
+  else
+    HIP_TRY((ent::launch_realify<float, float>((const float *)R->values, R->ld, n, (float *)b->ptr, ldm,
+                                               st)));
+  ent_matrix M{};
+  M.n = n2;
+  M.layout = ENT_DENSE;
+  M.dtype = c128 ? ENT_STORE_F64 : ENT_STORE_F32;
+  M.ld = ldm;
+  M.values = b->ptr;
+  return body(M);
+}
+
+ent_status run_hermitian(const ent_matrix *R, int32_t method, int32_t m, int32_t s, uint64_t seed,
+                         const Opts &op, ent_result *out, double *per_probe, double *moments) {
+  if (method != ENT_TAYLOR && method != ENT_CHEBYSHEV)
+    return fail(ENT_EUNSUPPORTED, "Hermitian R: Taylor and Chebyshev estimators only");
+  Opts mop = op;
+  mop.probe_rows = R->n;
+  mop.trace_div = 2.0;
+  if (!(mop.o.u_fixed > 0) && !(mop.o.flags & ENT_FLAG_COMPLEX_POWER)) mop.o.u_fixed = 1.0;
+  return with_real_form(R, op.st, [&](const ent_matrix &M) {
+    return poly_dispatch(&M, method, m, s, seed, mop, out, per_probe, moments, nullptr);
+  });
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1540,12 +1650,14 @@ ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int3
                                        int32_t probes, uint64_t seed, const ent_options *opt,
                                        ent_result *out, double *per_probe, double *moments) {
   g_last_error.clear();
-  ent_status rc = validate_matrix(R);
+  ent_status rc = validate_matrix(R, true);
   if (rc != ENT_OK) return rc;
   if (!out) return fail(ENT_EINVAL, "out is NULL");
   Opts op = resolve_options(opt);
   rc = validate_options(op.o);
   if (rc != ENT_OK) return rc;
+  if (is_complex(R) && (method == ENT_RANDPROJ || method == ENT_AUTO))
+    return fail(ENT_EUNSUPPORTED, "Hermitian R: Taylor and Chebyshev estimators only");
   if (method == ENT_RANDPROJ) {
     ent_result tmp{};
     rc = run_randproj(R, seed, op, &tmp, per_probe);
@@ -1560,7 +1672,9 @@ ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int3
   if (method == ENT_TAYLOR && op.o.cutoff > 0)
     return fail(ENT_EINVAL, "cutoff applies to the Chebyshev method only");
   ent_result tmp{};
-  if (method == ENT_AUTO)
+  if (is_complex(R))
+    rc = run_hermitian(R, method, degree, probes, seed, op, &tmp, per_probe, moments);
+  else if (method == ENT_AUTO)
     rc = run_auto(R, degree, probes, seed, op, &tmp, per_probe, moments);
   else
     rc = poly_dispatch(R, method, degree, probes, seed, op, &tmp, per_probe, moments, nullptr);
@@ -1576,11 +1690,13 @@ ent_status ent_entropy_estimate(const ent_matrix *R, int32_t method, int32_t deg
 ent_status ent_power_method(const ent_matrix *R, int32_t t, int32_t q, uint64_t seed, void *stream,
                             double *p1) {
   g_last_error.clear();
-  ent_status rc = validate_matrix(R);
+  ent_status rc = validate_matrix(R, true);
   if (rc != ENT_OK) return rc;
   if (!p1) return fail(ENT_EINVAL, "p1 is NULL");
   if (t < 0 || q < 1) return fail(ENT_EINVAL, "need t >= 0 and q >= 1");
   hipStream_t st = (hipStream_t)stream;
+  if (is_complex(R))
+    return with_real_form(R, st, [&](const ent_matrix &M) { return ent_power_method(&M, t, q, seed, stream, p1); });
   const int64_t n = R->n, n_pad = round_up(n, 64);
   const int32_t pblk = (int32_t)power_blocks(R);
   const bool f64 = R->dtype == ENT_STORE_F64;
@@ -1919,6 +2035,19 @@ ent_status ent_release_workspace(void) {
       HIP_TRY(hipFree(kv.second->ptr));
       kv.second->ptr = nullptr;
       kv.second->bytes = 0;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> l3(g_rf_mu);
+    for (auto &kv : g_rf) {
+      std::lock_guard<std::mutex> l4(kv.second->mu);
+      if (kv.second->ptr) {
+        HIP_TRY(hipSetDevice(kv.first));
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(kv.second->ptr));
+        kv.second->ptr = nullptr;
+        kv.second->bytes = 0;
+      }
     }
   }
   HIP_TRY(hipSetDevice(cur));

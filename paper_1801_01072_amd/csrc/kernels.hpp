@@ -141,6 +141,13 @@ template <typename Tin, typename Tout>
 hipError_t launch_convert(const Tin *src, int64_t lds, Tout *dst, int64_t ldd, int64_t rows,
                           int64_t cols, hipStream_t st);
 
+// Real 2n x 2n form [[B, -C], [C, B]] of a Hermitian R = B + iC stored as
+// interleaved (re, im) pairs with leading dimension ldr (complex elements);
+// M row-major with leading dimension ldm >= 2n (padding columns zeroed).
+template <typename Tin, typename Tout>
+hipError_t launch_realify(const Tin *Rc, int64_t ldr, int64_t n, Tout *M, int64_t ldm,
+                          hipStream_t st);
+
 // ---- recurrence steps --------------------------------------------------------
 template <typename T>
 hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st);

@@ -497,6 +497,54 @@ template hipError_t launch_convert<float, float>(const float *, int64_t, float *
                                                  int64_t, hipStream_t);
 
 // ---------------------------------------------------------------------------
+// Hermitian R = B + iC (Section 4): its real form M = [[B, -C], [C, B]]
+// (2n x 2n, row-major, leading dimension ldm; columns 2n..ldm-1 are zeroed).
+// M [x; y] = [Re(R(x+iy)); Im(R(x+iy))], so the recurrence on M with probes
+// [g; 0] is the complex recurrence on R with the real probe g, and
+// [g; 0]^T T(M) [g; 0] = g^T Re[T(R)] g.  Every eigenvalue of R appears twice
+// in M.  One thread per (row i of R, column j < ldm - n), grid-stride.
+// ---------------------------------------------------------------------------
+template <typename Tin, typename Tout>
+__global__ void realify_kernel(const Tin *__restrict__ Rc, int64_t ldr, int64_t n,
+                               Tout *__restrict__ M, int64_t ldm) {
+  const int64_t cols = ldm - n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * cols;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t / cols, j = t % cols;
+    Tout *top = M + i * ldm, *bot = M + (i + n) * ldm;
+    if (j < n) {
+      const Tin re = Rc[2 * (i * ldr + j)], im = Rc[2 * (i * ldr + j) + 1];
+      top[j] = (Tout)re;
+      top[n + j] = (Tout)(-im);
+      bot[j] = (Tout)im;
+      bot[n + j] = (Tout)re;
+    } else {
+      // padding columns 2n..ldm-1 of both rows
+      top[n + j] = Tout(0);
+      bot[n + j] = Tout(0);
+    }
+  }
+}
+
+template <typename Tin, typename Tout>
+hipError_t launch_realify(const Tin *Rc, int64_t ldr, int64_t n, Tout *M, int64_t ldm,
+                          hipStream_t st) {
+  if (ldm < 2 * n || ldr < n) return hipErrorInvalidValue;
+  const int64_t tot = n * (ldm - n);
+  const int64_t blocks = (tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536;
+  realify_kernel<Tin, Tout><<<(unsigned)blocks, 256, 0, st>>>(Rc, ldr, n, M, ldm);
+  return hipGetLastError();
+}
+template hipError_t launch_realify<double, double>(const double *, int64_t, int64_t, double *, int64_t,
+                                                   hipStream_t);
+template hipError_t launch_realify<double, float>(const double *, int64_t, int64_t, float *, int64_t,
+                                                  hipStream_t);
+template hipError_t launch_realify<float, double>(const float *, int64_t, int64_t, double *, int64_t,
+                                                  hipStream_t);
+template hipError_t launch_realify<float, float>(const float *, int64_t, int64_t, float *, int64_t,
+                                                 hipStream_t);
+
+// ---------------------------------------------------------------------------
 // Reductions
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void reduce_moments_body(const double *__restrict__ part, int32_t nslot,

@@ -100,3 +100,20 @@ def test_options_defaults(ent):
     ent._lib.ent_options_default(ctypes.byref(o))
     assert (o.power_iters, o.power_trials, o.u_factor, o.precision, o.probe_dist) == (20, 1, 6.0, ent.F64, ent.RADEMACHER)
     assert ent.version() >= 100
+
+
+def test_complex_storage_rules_without_device(ent):
+    lib = ent._lib
+    res = ent.EntResult()
+    # Hermitian storage: dense only, Taylor / Chebyshev only, estimate and power calls only
+    M = ent.EntMatrix(10, ent.CSR, ent.STORE_C128, 0, 5, 1, 1, 1)
+    assert lib.ent_entropy_estimate(ctypes.byref(M), 1, 10, 10, 0, None, ctypes.byref(res)) == ent.EUNSUPPORTED
+    M = ent.EntMatrix(10, ent.DENSE, ent.STORE_C64, 10, 0, 1, None, None)
+    for method in (ent.RANDPROJ, ent.AUTO):
+        assert lib.ent_entropy_estimate(ctypes.byref(M), method, 10, 10, 0, None,
+                                        ctypes.byref(res)) == ent.EUNSUPPORTED
+    M = ent.EntMatrix(10, ent.DENSE, ent.STORE_C128, 5, 0, 1, None, None)
+    assert lib.ent_entropy_estimate(ctypes.byref(M), 1, 10, 10, 0, None, ctypes.byref(res)) == ent.EINVAL
+    f = (ctypes.c_float * 16)()
+    M = ent.EntMatrix(10, ent.DENSE, ent.STORE_C128, 10, 0, 1, None, None)
+    assert lib.ent_selector_features(ctypes.byref(M), 0, None, f, f) == ent.EUNSUPPORTED
