@@ -86,6 +86,12 @@ def _load():
         "orc_exact_entropy": (d, [P]),
         "orc_rp_entropy_with_pi": (d, [P, P, i32, i32, P]),
         "orc_rp_entropy": (d, [P, i32, i32, u64, P]),
+        "orc_rp_entropy_kind": (d, [P, i32, i32, i32, u64, P]),
+        "orc_sketch_matrix": (None, [i32, u64, i64, i32, P]),
+        "orc_sketch_sign": (d, [u64, i64]),
+        "orc_sketch_bucket": (i32, [u64, i64, i32]),
+        "orc_srht_column": (i64, [u64, i64, i64]),
+        "orc_hadamard_order": (i64, [i64]),
         "orc_mlp_nparams": (i32, []),
         "orc_mlp_forward": (None, [P, i32, P, P]),
         "orc_mlp_loss_grad": (d, [P, i32, P, P, P]),
@@ -388,12 +394,39 @@ def rp_entropy_with_pi(R, Pi, k: int):
     return h, sig
 
 
-def rp_entropy(R, s: int, k: int, seed: int):
-    """Algorithm 3 with a Gaussian sketch of variance 1/s (stream 2)."""
+SKETCH_GAUSSIAN, SKETCH_SRHT, SKETCH_COUNT = 0, 1, 2
+
+
+def rp_entropy(R, s: int, k: int, seed: int, kind: int = SKETCH_GAUSSIAN):
+    """Algorithm 3 with a Gaussian (kind 0), subsampled randomized Hadamard
+    (1) or input-sparsity (2) sketch; see orc_sketch_matrix."""
     M = as_matrix(R)
     sig = np.zeros(k, dtype=np.float64)
-    h = _load().orc_rp_entropy(M.ref, s, k, seed, _ptr(sig))
+    h = _load().orc_rp_entropy_kind(M.ref, kind, s, k, seed, _ptr(sig))
     return h, sig
+
+
+def sketch_matrix(kind: int, seed: int, n: int, s: int) -> np.ndarray:
+    """The n x s sketch Pi of Algorithm 3 for the given construction."""
+    Pi = np.empty((n, s), dtype=np.float64)
+    _load().orc_sketch_matrix(kind, seed, n, s, _ptr(Pi))
+    return Pi
+
+
+def sketch_sign(seed: int, j: int) -> float:
+    return _load().orc_sketch_sign(seed, j)
+
+
+def sketch_bucket(seed: int, j: int, s: int) -> int:
+    return _load().orc_sketch_bucket(seed, j, s)
+
+
+def srht_column(seed: int, t: int, N: int) -> int:
+    return _load().orc_srht_column(seed, t, N)
+
+
+def hadamard_order(n: int) -> int:
+    return _load().orc_hadamard_order(n)
 
 
 def mlp_nparams() -> int:

@@ -763,17 +763,94 @@ double orc_rp_entropy_with_pi(const orc_matrix *R, const double *Pi, int32_t s,
 }
 
 /* Gaussian sketch, zero mean, variance 1/s (so that E[Pi Pi^T] = I). */
-double orc_rp_entropy(const orc_matrix *R, int32_t s, int32_t k, uint64_t seed,
-                      double *sigma_out) {
+/*
+ * Sketch matrices Pi (n x s, row-major) for Algorithm 3:
+ *   kind 0, Gaussian:  Pi_jt = N(0,1)/sqrt(s) (probe generator, stream 2).
+ *   kind 1, subsampled randomized Hadamard transform (Section 5.2):
+ *           Pi = sqrt(N/s) D H S with N = 2^ceil(log2 n) (R padded with
+ *           zeros to N), H the normalized Sylvester-Hadamard matrix,
+ *           H_ji = (-1)^{popcount(j & i)} / sqrt(N), D_jj = +-1 and S
+ *           sampling s columns uniformly with replacement, so
+ *           Pi_jt = D_jj (-1)^{popcount(j & i_t)} / sqrt(s).
+ *           The sqrt(N/s) scale makes E[Pi Pi^T] = I, the normalization
+ *           under which the embedding bound for this construction holds.
+ *   kind 2, input-sparsity transform (Section 5.2): Pi = D S with one
+ *           entry D_jj in column h(j) of row j, h(j) uniform on 0..s-1.
+ * Random draws (Philox4x32-10, counter (row mod 2^32, 0, stream, row >> 32),
+ * key = seed): D_jj = -1 iff bit 0 of output word 0 of stream 3 at row j;
+ * h(j) = floor(w1 s / 2^32) with w1 output word 1 of the same block
+ * (multiply-shift reduction); i_t = output word 0 of stream 4 at row t,
+ * reduced mod N (N a power of two).
+ */
+static void orc_philox_row(uint64_t seed, uint32_t stream, int64_t row, uint32_t out[4]) {
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t ctr[4] = {(uint32_t)((uint64_t)row & 0xffffffffu), 0u, stream,
+                     (uint32_t)((uint64_t)row >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+int64_t orc_hadamard_order(int64_t n) {
+  int64_t N = 1;
+  while (N < n) N *= 2;
+  return N;
+}
+
+double orc_sketch_sign(uint64_t seed, int64_t j) {
+  uint32_t o[4];
+  orc_philox_row(seed, 3u, j, o);
+  return (o[0] & 1u) ? -1.0 : 1.0;
+}
+
+int32_t orc_sketch_bucket(uint64_t seed, int64_t j, int32_t s) {
+  uint32_t o[4];
+  orc_philox_row(seed, 3u, j, o);
+  return (int32_t)(((uint64_t)o[1] * (uint64_t)s) >> 32);
+}
+
+int64_t orc_srht_column(uint64_t seed, int64_t t, int64_t N) {
+  uint32_t o[4];
+  orc_philox_row(seed, 4u, t, o);
+  return (int64_t)((uint64_t)o[0] % (uint64_t)N);
+}
+
+void orc_sketch_matrix(int32_t kind, uint64_t seed, int64_t n, int32_t s, double *Pi) {
+  double scale = 1.0 / sqrt((double)s);
+  if (kind == 0) {
+    for (int64_t i = 0; i < n; ++i)
+      for (int32_t c = 0; c < s; ++c) Pi[i * s + c] = scale * orc_probe_value(seed, 1, 2u, i, c);
+  } else if (kind == 1) {
+    int64_t N = orc_hadamard_order(n);
+    int64_t *col = (int64_t *)malloc(sizeof(int64_t) * s);
+    for (int32_t c = 0; c < s; ++c) col[c] = orc_srht_column(seed, c, N);
+    for (int64_t j = 0; j < n; ++j) {
+      double d = orc_sketch_sign(seed, j);
+      for (int32_t c = 0; c < s; ++c) {
+        int par = __builtin_popcountll((unsigned long long)(j & col[c])) & 1;
+        Pi[j * s + c] = d * (par ? -1.0 : 1.0) * scale;
+      }
+    }
+    free(col);
+  } else {
+    for (int64_t j = 0; j < n; ++j) {
+      for (int32_t c = 0; c < s; ++c) Pi[j * s + c] = 0.0;
+      Pi[j * s + orc_sketch_bucket(seed, j, s)] = orc_sketch_sign(seed, j);
+    }
+  }
+}
+
+double orc_rp_entropy_kind(const orc_matrix *R, int32_t kind, int32_t s, int32_t k,
+                           uint64_t seed, double *sigma_out) {
   int64_t n = R->n;
   double *Pi = (double *)malloc(sizeof(double) * n * s);
-  double scale = 1.0 / sqrt((double)s);
-  for (int64_t i = 0; i < n; ++i)
-    for (int32_t c = 0; c < s; ++c)
-      Pi[i * s + c] = scale * orc_probe_value(seed, 1, 2u, i, c);
+  orc_sketch_matrix(kind, seed, n, s, Pi);
   double h = orc_rp_entropy_with_pi(R, Pi, s, k, sigma_out);
   free(Pi);
   return h;
+}
+
+double orc_rp_entropy(const orc_matrix *R, int32_t s, int32_t k, uint64_t seed,
+                      double *sigma_out) {
+  return orc_rp_entropy_kind(R, 0, s, k, seed, sigma_out);
 }
 
 /* ------------------------------------------------------------------------- */
