@@ -46,6 +46,10 @@ WORKLOADS = {
                     s=64, dist="rademacher", t=20),
     "learned4096": dict(kind="learned", count=512, n=4096, m=40, s=64, dist="rademacher", t=20),
     "rp65536": dict(kind="rp", n=65536, k=64, s=128, tau=8.0),
+    "rp65536_srht": dict(kind="rp", n=65536, k=64, s=128, tau=8.0, sketch="srht"),
+    # the input-sparsity sketch needs s ~ k^2: rank 8, s = 2 k^2 (widths above
+    # 128 run the s x s eigenproblem out of LDS, ~0.2 s at s = 256)
+    "rp65536_count": dict(kind="rp", n=65536, k=8, s=128, tau=2.0, sketch="count"),
     # Hermitian (complex) density matrix of the paper's Hermitian experiment size
     "herm5000": dict(kind="herm", n=5000, spectrum=("exp", 600.0), method="chebyshev", m=50,
                      s=256, dist="gaussian", t=20),
@@ -334,7 +338,8 @@ def bench_learned(args, cfg):
 
 def bench_rp(args, cfg):
     """Algorithm 3 on a rank-k dense density matrix, n = 65536 (17.2 GB in
-    FP32): Gaussian sketch R Pi (s columns), Gram, Jacobi eigenvalues."""
+    FP32): sketch R Pi (s columns; Gaussian, subsampled randomized Hadamard or
+    input-sparsity), Gram, Jacobi eigenvalues."""
     import torch
 
     import paper_1801_01072_amd as ent
@@ -349,7 +354,8 @@ def bench_rp(args, cfg):
     torch.cuda.synchronize()
     H = float(-np.sum(pk * np.log(pk)))
     log(f"generated rank-{k} R, n={n}, in {time.time() - t0:.1f}s")
-    kw = dict(precision=precision, rank_k=k, sketch_width=s)
+    sketch = cfg.get("sketch", "gaussian")
+    kw = dict(precision=precision, rank_k=k, sketch_width=s, sketch=sketch)
     for _ in range(args.warmup):
         ent.entropy_estimate(R, "randproj", 1, 1, pseed, **kw)
     torch.cuda.synchronize()
@@ -366,11 +372,24 @@ def bench_rp(args, cfg):
     ent.timing_enable(False)
     avg_ms = float(np.mean([x["steps_ms"] / max(x["step_launches"], 1) for x in tms]))
     phases = {kk: float(np.mean([x[kk] for x in tms])) for kk in ("total_ms", "steps_ms", "epilogue_ms", "other_ms")}
-    flop = 2.0 * n * n * s
-    achieved = flop / (avg_ms * 1e-3) / 1e12
-    peak = MFMA_PEAK_TFLOPS[precision]
-    kernel = "bf16x3_gemm_kernel" if precision == "bf16x3" else "dense_step_kernel"
-    log(f"{kernel}: {avg_ms:.3f} ms -> {achieved:.1f} TFLOP/s; H^={res.entropy:.8f}, exact {H:.8f}")
+    if sketch == "count":
+        # one pass over R (FP32) plus the s x n FP64 output and the bucket lists
+        nbytes = 4.0 * n * n + 8.0 * s * (-(-n // 64) * 64) + 4.0 * n + 8.0 * (s + 1)
+        achieved = nbytes / (avg_ms * 1e-3) / 1e9
+        kernel = "cs_apply_kernel"
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+                "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": nbytes}
+        log(f"{kernel}: {avg_ms:.3f} ms -> {achieved:.1f} GB/s; H^={res.entropy:.8f}, exact {H:.8f}")
+    else:
+        flop = 2.0 * n * n * s
+        achieved = flop / (avg_ms * 1e-3) / 1e12
+        peak = MFMA_PEAK_TFLOPS[precision]
+        kernel = "bf16x3_gemm_kernel" if precision == "bf16x3" else "dense_step_kernel"
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "kernel": kernel,
+                "avg_launch_ms": avg_ms, "algorithmic_flop_per_launch": flop}
+        log(f"{kernel}: {avg_ms:.3f} ms -> {achieved:.1f} TFLOP/s; H^={res.entropy:.8f}, exact {H:.8f}")
     del R
     torch.cuda.empty_cache()
     # second spectrum family of the same shape: Dirichlet(0.5) over the k slots
@@ -388,7 +407,7 @@ def bench_rp(args, cfg):
         ns = 8192
         Rs = W.low_rank_density_torch(pk, ns, mseed, device="cpu", dtype=torch.float64).numpy()
         tc = time.perf_counter()
-        h_s, _ = oracle.rp_entropy(Rs, s, k, pseed)
+        h_s, _ = oracle.rp_entropy(Rs, s, k, pseed, kind={"gaussian": 0, "srht": 1, "count": 2}[sketch])
         cpu_s = time.perf_counter() - tc
         scale = (n / ns) ** 2
         cpu = {"value": 1.0 / (cpu_s * scale), "unit": "estimates/s", "cores": 1, "kind": "oracle",
@@ -403,12 +422,10 @@ def bench_rp(args, cfg):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": precision,
         "data": "synthetic",
         "config": {"workload": f"random projection (Algorithm 3): dense rank-{k} density matrix "
-                               f"n={n}, p ~ exp(-i/{cfg['tau']:g}), Gaussian sketch width {s}",
-                   "n": n, "rank_k": k, "sketch_width": s, "precision": precision,
+                               f"n={n}, p ~ exp(-i/{cfg['tau']:g}), {sketch} sketch width {s}",
+                   "n": n, "rank_k": k, "sketch_width": s, "sketch": sketch, "precision": precision,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": kernel,
-                     "avg_launch_ms": avg_ms, "algorithmic_flop_per_launch": flop},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "phases_ms": phases,
         "accuracy": {"entropy": res.entropy, "exact_H": H, "rel_err_vs_exact": (res.entropy - H) / H,

@@ -79,6 +79,22 @@ typedef enum {
  * Rademacher signs are the other unbiased choice. */
 typedef enum { ENT_RADEMACHER = 0, ENT_GAUSSIAN = 1 } ent_probe_dist;
 
+/* Sketch Pi (n x s) of Algorithm 3 (Section 5.2).  Random draws are
+ * Philox4x32-10 with counter (row mod 2^32, 0, stream, row >> 32), key =
+ * seed:
+ *  GAUSSIAN: Pi_jt = N(0,1)/sqrt(s), the probe generator's Gaussian of
+ *            stream 2 at (row j, probe t).
+ *  SRHT:     subsampled randomized Hadamard transform sqrt(N/s) D H S,
+ *            N = 2^ceil(log2 n), H the normalized Sylvester-Hadamard
+ *            matrix: Pi_jt = D_jj (-1)^popcount(j & i_t) / sqrt(s).
+ *  COUNT:    input-sparsity transform D S: row j holds D_jj in column h(j)
+ *            only.  R Pi is one signed pass over R (FP64 sums of the stored
+ *            values; the precision option does not apply).
+ * D_jj = -1 iff bit 0 of output word 0 of stream 3 at row j; h(j) =
+ * floor(w1 s / 2^32), w1 output word 1 of that block; i_t = output word 0
+ * of stream 4 at row t, modulo N. */
+typedef enum { ENT_SKETCH_GAUSSIAN = 0, ENT_SKETCH_SRHT = 1, ENT_SKETCH_COUNT = 2 } ent_sketch;
+
 enum {
   ENT_FLAG_SKIP_TRACE_CHECK = 1, /* do not verify tr R = 1                    */
   ENT_FLAG_AUTOTUNE = 2,         /* batches: time the candidate tile shapes on
@@ -125,7 +141,7 @@ typedef struct {
   int32_t rank_k;        /* Algorithm 3: number of singular values kept        */
   int32_t sketch_width;  /* Algorithm 3: columns s of the Gaussian sketch      */
   int32_t flags;         /* ENT_FLAG_* bits                                    */
-  int32_t reserved;
+  int32_t sketch;        /* Algorithm 3: ent_sketch (default ENT_SKETCH_GAUSSIAN) */
   double trace_tol;      /* |tr R - 1| tolerance; 0 = 1e-10 (F64 storage) or
                             1e-4 (F32 storage)                                 */
   void *stream;          /* hipStream_t                                        */
@@ -154,7 +170,7 @@ void ent_options_default(ent_options *opt);
  *   method  ENT_TAYLOR:    h_j = ln(1/u) + sum_{k=1}^{m} g_j^T R (I - R/u)^k g_j / k
  *           ENT_CHEBYSHEV: h_j = -g_j^T f_m(R) g_j, f_m = sum_w alpha_w T_w
  *                          on [lo, u] (Lemma 3 coefficients when lo = 0)
- *           ENT_RANDPROJ:  Algorithm 3 with a Gaussian sketch of
+ *           ENT_RANDPROJ:  Algorithm 3 with the sketch opt->sketch of
  *                          opt->sketch_width columns, top opt->rank_k
  *                          singular values (degree and probes ignored)
  *   degree  m >= 1; probes s >= 1; seed keys the Philox4x32-10 stream of

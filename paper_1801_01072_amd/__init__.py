@@ -42,6 +42,8 @@ FLAG_COMPLEX_POWER = 4
 _METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ, "auto": AUTO}
 _PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
 _DISTS = {"rademacher": RADEMACHER, "gaussian": GAUSSIAN}
+SKETCH_GAUSSIAN, SKETCH_SRHT, SKETCH_COUNT = 0, 1, 2
+_SKETCHES = {"gaussian": SKETCH_GAUSSIAN, "srht": SKETCH_SRHT, "count": SKETCH_COUNT}
 
 
 class EntMatrix(ctypes.Structure):
@@ -56,7 +58,7 @@ class EntOptions(ctypes.Structure):
                 ("cutoff", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("probe_dist", ctypes.c_int32), ("rank_k", ctypes.c_int32),
                 ("sketch_width", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("trace_tol", ctypes.c_double),
+                ("sketch", ctypes.c_int32), ("trace_tol", ctypes.c_double),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -224,7 +226,7 @@ def _stream_handle(stream):
 
 def options(precision="f64", probe_dist="rademacher", power_iters=20, power_trials=1,
             u_factor=6.0, u_fixed=0.0, cutoff=0.0, rank_k=0, sketch_width=0, flags=0,
-            trace_tol=0.0, stream=None) -> EntOptions:
+            trace_tol=0.0, stream=None, sketch="gaussian") -> EntOptions:
     o = EntOptions()
     _lib.ent_options_default(ctypes.byref(o))
     o.precision = _PRECISIONS.get(precision, precision)
@@ -237,6 +239,7 @@ def options(precision="f64", probe_dist="rademacher", power_iters=20, power_tria
     o.rank_k = rank_k
     o.sketch_width = sketch_width
     o.flags = flags
+    o.sketch = _SKETCHES.get(sketch, sketch)
     o.trace_tol = trace_tol
     o.stream = _stream_handle(stream)
     return o

@@ -81,6 +81,28 @@ __device__ __forceinline__ double gaussian(uint64_t seed, uint32_t stream, int64
   return (probe & 1) ? r * sin(th) : r * cos(th);
 }
 
+// Structured sketches of the random projection (Section 5.2).  Row sign
+// D_jj = -1 iff bit 0 of word x of stream 3's block (row j, block 0); the
+// input-sparsity bucket of row j is floor(word y * s / 2^32) of the same
+// block; the t-th sampled Hadamard column is word x of stream 4's block
+// (row t) modulo N, N = 2^ceil(log2 n).
+__device__ __forceinline__ double sketch_sign(uint64_t seed, int64_t j) {
+  return (philox_block(seed, 3u, j, 0u).x & 1u) ? -1.0 : 1.0;
+}
+__device__ __forceinline__ int32_t sketch_bucket(uint64_t seed, int64_t j, int32_t s) {
+  return (int32_t)(((uint64_t)philox_block(seed, 3u, j, 0u).y * (uint64_t)s) >> 32);
+}
+__device__ __forceinline__ int64_t hadamard_order(int64_t n) {
+  int64_t N = 1;
+  while (N < n) N <<= 1;
+  return N;
+}
+// Entry (j, t) of D H S without the 1/sqrt(s) scale: D_jj (-1)^popcount(j & i_t).
+__device__ __forceinline__ double srht_entry(uint64_t seed, int64_t j, int64_t t, int64_t N) {
+  const int64_t col = (int64_t)((uint64_t)philox_block(seed, 4u, t, 0u).x % (uint64_t)N);
+  return (__popcll((unsigned long long)(j & col)) & 1) ? -sketch_sign(seed, j) : sketch_sign(seed, j);
+}
+
 // ---------------------------------------------------------------------------
 // wave64 reductions (fixed butterfly order: deterministic)
 // ---------------------------------------------------------------------------

@@ -846,6 +846,8 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
   const int32_t s = o.sketch_width, k = o.rank_k;
   if (R->layout != ENT_DENSE) return fail(ENT_EUNSUPPORTED, "random projection needs dense R");
   if (s < 1 || s > 256) return fail(ENT_EINVAL, "sketch_width = %d out of range [1, 256]", s);
+  if (o.sketch < ENT_SKETCH_GAUSSIAN || o.sketch > ENT_SKETCH_COUNT)
+    return fail(ENT_EINVAL, "unknown sketch %d", o.sketch);
   if (k < 1 || k > s) return fail(ENT_EINVAL, "rank_k = %d out of range [1, sketch_width]", k);
   const int64_t n = R->n;
   const bool f64 = R->dtype == ENT_STORE_F64;
@@ -868,7 +870,44 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
   PhaseEvents pe;
   pe.on = g_timing_on;
   pe.st = st;
-  if (prec == ENT_BF16X3) {
+  if (o.sketch == ENT_SKETCH_COUNT) {
+    // one signed pass over R into Y = (R Pi)^T, FP64 from the stored values
+    // (the precision option does not apply)
+    const int64_t ldy = round_up(n, 64);
+    int32_t *cnt = nullptr, *rows = nullptr;
+    int64_t *off = nullptr;
+    double *Y = nullptr;
+    cv.add(&cnt, (size_t)s);
+    cv.add(&off, (size_t)s + 1);
+    cv.add(&rows, (size_t)n);
+    cv.add(&Y, (size_t)s * ldy);
+    ent_status rc = ensure_workspace(ws, cv.total());
+    if (rc != ENT_OK) return rc;
+    cv.assign(ws->ptr);
+    pe.mark();
+    HIP_TRY(ent::launch_fill(scal, 64, 0.0, st));
+    if (check_trace) {
+      if (f64)
+        HIP_TRY(ent::launch_trace_dense<double>((const double *)R->values, R->ld, n, scal, st));
+      else
+        HIP_TRY(ent::launch_trace_dense<float>((const float *)R->values, R->ld, n, scal, st));
+    }
+    if (f64)
+      HIP_TRY(ent::launch_count_sketch<double>((const double *)R->values, R->ld, n, s, seed, cnt, off, rows,
+                                               Y, ldy, st, 0));
+    else
+      HIP_TRY(ent::launch_count_sketch<float>((const float *)R->values, R->ld, n, s, seed, cnt, off, rows, Y,
+                                              ldy, st, 0));
+    pe.steps_begin = pe.mark();
+    if (f64)
+      HIP_TRY(ent::launch_count_sketch<double>((const double *)R->values, R->ld, n, s, seed, cnt, off, rows,
+                                               Y, ldy, st, 1));
+    else
+      HIP_TRY(ent::launch_count_sketch<float>((const float *)R->values, R->ld, n, s, seed, cnt, off, rows, Y,
+                                              ldy, st, 1));
+    pe.steps_end = pe.mark();
+    HIP_TRY(ent::launch_gram<double>(Y, 1, ldy, n, s, gp, nsplit, G, st));
+  } else if (prec == ENT_BF16X3) {
     const int64_t n_pad = round_up(n, 128);
     const int bn = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
     const int64_t ldv = round_up(s, bn);
@@ -896,7 +935,8 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
       else
         HIP_TRY(ent::launch_trace_dense<float>((const float *)R->values, R->ld, n, scal, st));
     }
-    HIP_TRY(ent::launch_probe_gen_t(P, Phi, Plo, n, n_pad, s, ldv, seed, ENT_GAUSSIAN, st, 2u,
+    HIP_TRY(ent::launch_probe_gen_t(P, Phi, Plo, n, n_pad, s, ldv, seed,
+                                    o.sketch == ENT_SKETCH_SRHT ? 2 : ENT_GAUSSIAN, st, 2u,
                                     1.0 / std::sqrt((double)s)));
     if (f64)
       HIP_TRY(ent::launch_split_matrix<double>((const double *)R->values, R->ld, n, n_pad, scal, Ahi, Alo, st));
@@ -957,9 +997,9 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
       ldr = ldc;
     }
     if (d64)
-      HIP_TRY(ent::launch_sketch_gen<double>((double *)P, n, n_pad, s, ldv, seed, st));
+      HIP_TRY(ent::launch_sketch_gen<double>((double *)P, n, n_pad, s, ldv, seed, o.sketch, st));
     else
-      HIP_TRY(ent::launch_sketch_gen<float>((float *)P, n, n_pad, s, ldv, seed, st));
+      HIP_TRY(ent::launch_sketch_gen<float>((float *)P, n, n_pad, s, ldv, seed, o.sketch, st));
     ent::DenseStepArgs a{};
     a.R = Rt; a.ldr = ldr; a.n = n; a.ldv = ldv; a.Vk = P; a.Vkm1 = nullptr; a.Vkp1 = X; a.G = nullptr;
     a.scal = scal; a.c1 = 1.0; a.c2 = 0.0; a.cw = 0.0; a.dot_y = 0; a.slot = -1; a.slot_gg = -1;

@@ -259,7 +259,14 @@ hipError_t launch_batch_final(const BatchMat *mats, int32_t count, const double 
 // ---- random projection (Algorithm 3) -----------------------------------------
 template <typename T>
 hipError_t launch_sketch_gen(T *P, int64_t n, int64_t n_pad, int32_t s, int64_t ldv, uint64_t seed,
-                             hipStream_t st);
+                             int32_t kind, hipStream_t st);
+// Input-sparsity sketch for symmetric R.  phase 0: the bucket row lists
+// cnt (s), off (s + 1), rows (n) for (seed, n, s); phase 1: Y (s x ldy,
+// FP64, row c = bucket c) = (R Pi)^T from those lists.
+template <typename T>
+hipError_t launch_count_sketch(const T *R, int64_t ldr, int64_t n, int32_t s, uint64_t seed,
+                               int32_t *cnt, int64_t *off, int32_t *rows, double *Y, int64_t ldy,
+                               hipStream_t st, int phase);
 // G = X^T X (s x s, FP64) with X(i, a) at X[i*si + a*sa]; scratch holds
 // nsplit * s * s doubles.
 template <typename T>

@@ -116,7 +116,9 @@ __global__ void probe_gen_t_kernel(float *__restrict__ G, uint16_t *__restrict__
     const int64_t i = i0 + e;
     v[e] = 0.f;
     if (i < n && j < s)
-      v[e] = (float)(scale * (dist == 0 ? rademacher(seed, stream, i, j) : gaussian(seed, stream, i, j)));
+      v[e] = (float)(scale * (dist == 0   ? rademacher(seed, stream, i, j)
+                              : dist == 2 ? srht_entry(seed, i, j, hadamard_order(n))
+                                          : gaussian(seed, stream, i, j)));
     h[e] = bf16_rne(v[e]);
     l[e] = bf16_rne(v[e] - bf16_to_f32(h[e]));
   }

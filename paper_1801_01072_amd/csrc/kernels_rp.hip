@@ -1,5 +1,6 @@
 // kernels_rp.hip -- random-projection estimator (Algorithm 3, Section 5):
-// sketch R~ = R Pi (product on the existing MFMA kernels), Gram matrix
+// sketch R~ = R Pi (Gaussian and Hadamard sketches: product on the existing
+// MFMA kernels; input-sparsity sketch: one signed pass over R), Gram matrix
 // R~^T R~ in FP64, its eigenvalues by a parallel cyclic Jacobi method in one
 // workgroup, singular values sigma = sqrt(lambda), the k largest kept and
 // H^ = sum sigma ln(1/sigma).
@@ -9,32 +10,163 @@
 namespace ent {
 
 // ---------------------------------------------------------------------------
-// Sketch Pi, entries N(0, 1/s) (Gaussian stream 2), row-major n_pad x ldv.
+// Sketch Pi, row-major n_pad x ldv: kind 0 entries N(0, 1/s) (Gaussian
+// stream 2); kind 1 the subsampled randomized Hadamard transform
+// sqrt(N/s) D H S, entries D_jj (-1)^popcount(j & i_t) / sqrt(s).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void sketch_gen_kernel(T *__restrict__ P, int64_t n, int64_t n_pad, int32_t s, int64_t ldv,
-                                  uint64_t seed, double scale) {
+                                  uint64_t seed, double scale, int32_t kind) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_pad * ldv) return;
   const int64_t i = t / ldv, j = t % ldv;
-  P[t] = (i < n && j < s) ? (T)(scale * gaussian(seed, 2u, i, j)) : T(0);
+  T v = T(0);
+  if (i < n && j < s)
+    v = (T)(scale * (kind == 1 ? srht_entry(seed, i, j, hadamard_order(n)) : gaussian(seed, 2u, i, j)));
+  P[t] = v;
 }
 
 template <typename T>
 hipError_t launch_sketch_gen(T *P, int64_t n, int64_t n_pad, int32_t s, int64_t ldv, uint64_t seed,
-                             hipStream_t st) {
+                             int32_t kind, hipStream_t st) {
   const int64_t tot = n_pad * ldv;
   sketch_gen_kernel<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(P, n, n_pad, s, ldv, seed,
-                                                                      1.0 / sqrt((double)s));
+                                                                      1.0 / sqrt((double)s), kind);
   return hipGetLastError();
 }
 template hipError_t launch_sketch_gen<double>(double *, int64_t, int64_t, int32_t, int64_t, uint64_t,
-                                              hipStream_t);
+                                              int32_t, hipStream_t);
 template hipError_t launch_sketch_gen<float>(float *, int64_t, int64_t, int32_t, int64_t, uint64_t,
-                                             hipStream_t);
+                                             int32_t, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Gram matrix G = R~^T R~ (s x s, FP64).  R~(i, a) is at X[i*si + a*sa].
+// Input-sparsity sketch Pi = D S (one entry D_jj per row, in column h(j)).
+// R is symmetric, so (R Pi)^T = Pi^T R: row c of Y = (R Pi)^T is the signed
+// sum of the rows j of R with h(j) = c.  The rows of each bucket are listed
+// in ascending order (count, offsets, fill: one workgroup per bucket), and
+// every row of R is then read exactly once: a single pass over R, as the
+// construction's input-sparsity running time promises.  Sums are FP64 in
+// ascending row order (deterministic).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void cs_count_kernel(uint64_t seed, int64_t n, int32_t s,
+                                                       int32_t *__restrict__ cnt) {
+  __shared__ int32_t red[4];
+  const int32_t c = blockIdx.x;
+  int32_t k = 0;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) k += sketch_bucket(seed, j, s) == c;
+  for (int off = 32; off >= 1; off >>= 1) k += __shfl_xor(k, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = k;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[c] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void cs_offsets_kernel(const int32_t *__restrict__ cnt, int32_t s, int64_t *__restrict__ off) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t a = 0;
+  for (int32_t c = 0; c < s; ++c) {
+    off[c] = a;
+    a += cnt[c];
+  }
+  off[s] = a;
+}
+
+__global__ __launch_bounds__(256) void cs_fill_kernel(uint64_t seed, int64_t n, int32_t s,
+                                                      const int64_t *__restrict__ off,
+                                                      int32_t *__restrict__ rows) {
+  __shared__ int32_t wcount[4];
+  const int32_t c = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t base = off[c];
+  for (int64_t j0 = 0; j0 < n; j0 += blockDim.x) {
+    const int64_t j = j0 + threadIdx.x;
+    const bool in = j < n && sketch_bucket(seed, j, s) == c;
+    const uint64_t mask = __ballot(in);
+    const int32_t before = (int32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[w] = (int32_t)__popcll(mask);
+    __syncthreads();
+    int32_t wbase = 0;
+    for (int q = 0; q < w; ++q) wbase += wcount[q];
+    if (in) rows[base + wbase + before] = (int32_t)j;
+    base += wcount[0] + wcount[1] + wcount[2] + wcount[3];
+    __syncthreads();
+  }
+}
+
+// Y[c][col] = sum over the rows j of bucket c of D_jj R[j][col]; workgroup
+// (column chunk of 1024, bucket c); thread columns col0 + tid + 256 q.
+template <typename T>
+__global__ __launch_bounds__(256) void cs_apply_kernel(const T *__restrict__ R, int64_t ldr, int64_t n,
+                                                       uint64_t seed, const int64_t *__restrict__ off,
+                                                       const int32_t *__restrict__ rows,
+                                                       double *__restrict__ Y, int64_t ldy) {
+  const int32_t c = blockIdx.y;
+  const int64_t col0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t r0 = off[c], r1 = off[c + 1];
+  int64_t r = r0;
+  // four rows at a time: 16 independent loads per thread in flight
+  for (; r + 4 <= r1; r += 4) {
+    int64_t j[4];
+    double d[4];
+    T v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      j[u] = rows[r + u];
+      d[u] = sketch_sign(seed, j[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t col = col0 + 256 * q;
+        v[u][q] = col < n ? R[j[u] * ldr + col] : T(0);
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += d[u] * (double)v[u][q];
+  }
+  for (; r < r1; ++r) {
+    const int64_t j = rows[r];
+    const double d = sketch_sign(seed, j);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t col = col0 + 256 * q;
+      if (col < n) acc[q] += d * (double)R[j * ldr + col];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t col = col0 + 256 * q;
+    if (col < ldy) Y[(int64_t)c * ldy + col] = col < n ? acc[q] : 0.0;
+  }
+}
+
+template <typename T>
+hipError_t launch_count_sketch(const T *R, int64_t ldr, int64_t n, int32_t s, uint64_t seed,
+                               int32_t *cnt, int64_t *off, int32_t *rows, double *Y, int64_t ldy,
+                               hipStream_t st, int phase) {
+  if (s < 1 || ldy < n || ldr < n) return hipErrorInvalidValue;
+  if (phase == 0) {
+    cs_count_kernel<<<(unsigned)s, 256, 0, st>>>(seed, n, s, cnt);
+    cs_offsets_kernel<<<1, 64, 0, st>>>(cnt, s, off);
+    cs_fill_kernel<<<(unsigned)s, 256, 0, st>>>(seed, n, s, off, rows);
+  } else {
+    dim3 grid((unsigned)((ldy + 1023) / 1024), (unsigned)s);
+    cs_apply_kernel<T><<<grid, 256, 0, st>>>(R, ldr, n, seed, off, rows, Y, ldy);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_count_sketch<double>(const double *, int64_t, int64_t, int32_t, uint64_t,
+                                                int32_t *, int64_t *, int32_t *, double *, int64_t,
+                                                hipStream_t, int);
+template hipError_t launch_count_sketch<float>(const float *, int64_t, int64_t, int32_t, uint64_t,
+                                               int32_t *, int64_t *, int32_t *, double *, int64_t,
+                                               hipStream_t, int);
+
+// ---------------------------------------------------------------------------
+// Gram matrix G = R~^T R~ (s x s, FP64).  R~(i, a) is at X[i*si + a*sa]
+// (row-major R~: sa = 1; probe-major: si = 1).
 // Workgroup = 16 x 16 block of G over one K range; partials per K range are
 // summed in range order by gram_sum_kernel.
 // ---------------------------------------------------------------------------
@@ -50,7 +182,8 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T *__restrict__
   double acc = 0.0;
   for (int64_t base = r0; base < r1; base += 64) {
     for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int rr = e / 16, cc = e % 16;
+      // consecutive threads take consecutive addresses in either layout
+      const int rr = si == 1 ? e % 64 : e / 16, cc = si == 1 ? e / 64 : e % 16;
       const int64_t i = base + rr;
       const bool ok = i < r1;
       xa[rr][cc] = (ok && a0 + cc < s) ? (double)X[i * si + (int64_t)(a0 + cc) * sa] : 0.0;
