@@ -40,6 +40,10 @@ WORKLOADS = {
                    dist="rademacher", t=20),
     "csr1e5": dict(kind="csr", n=100_000, hb=8, method="chebyshev", m=40, s=64,
                    dist="rademacher", t=20),
+    # the paper's largest experiment at full size: the 10^8 x 10^8 tridiagonal
+    # (-1, 2, -1)/2n, m = 10, s = 100, c = 1; exact H from the closed-form spectrum
+    "poisson1e8": dict(kind="csr", matrix="poisson", n=100_000_000, method="chebyshev", m=10, s=100,
+                       dist="rademacher", t=20, c=1.0, cpu_probes=4),
     "batch1024": dict(kind="batch", count=1024, n_lo=64, n_hi=2048, method="chebyshev", m=40,
                       s=64, dist="rademacher", t=20),
     "batch64": dict(kind="batch", count=64, n_lo=64, n_hi=2048, method="chebyshev", m=40,
@@ -104,6 +108,10 @@ def describe(cfg, precision, store):
         spec = "p_i ~ 1/i" if sp[0] == "inverse" else f"p_i ~ exp(-i/{sp[1]:g})"
         return (f"dense density matrix n={cfg['n']}, {spec}, random orthogonal U; {cfg['method']} "
                 f"m={cfg['m']}, s={cfg['s']} {cfg['dist']} probes, t={cfg['t']}, {precision}")
+    if cfg.get("matrix") == "poisson":
+        return (f"tridiagonal CSR density matrix (-1, 2, -1)/2n, n={cfg['n']:.0e}, {store} values; "
+                f"{cfg['method']} m={cfg['m']}, s={cfg['s']} {cfg['dist']} probes, t={cfg['t']}, "
+                f"u = {cfg.get('c', 6.0):g} p~1, {precision}")
     return (f"banded CSR density matrix n={cfg['n']:.0e}, R = B B^T / tr with B half-bandwidth "
             f"{cfg['hb']}, {store} values; {cfg['method']} m={cfg['m']}, s={cfg['s']} "
             f"{cfg['dist']} probes, t={cfg['t']}, {precision}")
@@ -521,13 +529,19 @@ def main():
         H_exact = float(-np.sum(p[p > 0] * np.log(p[p > 0])))
         Rd = torch.from_numpy(R).to("cuda:0")
         host_R = R
+    elif cfg.get("matrix") == "poisson":
+        Rd = W.poisson_csr_torch(n, device="cuda:0", dtype=torch.float64 if store == "f64" else torch.float32)
+        lam = W.poisson_eigenvalues(n)
+        H_exact = float(-np.sum(lam * np.log(lam)))
+        del lam
+        host_R = None
     else:
         csr = W.banded_density_csr(n, cfg["hb"], seed=mseed, dtype=np.float64 if store == "f64" else np.float32)
         Rd = tuple(torch.from_numpy(a).to("cuda:0") for a in csr[:3]) + (n,)
         host_R = csr
     torch.cuda.synchronize()
     log(f"generated R ({args.workload}, {store}) in {time.time() - t0:.1f}s")
-    kw = dict(probe_dist=cfg["dist"], precision=precision, power_iters=t)
+    kw = dict(probe_dist=cfg["dist"], precision=precision, power_iters=t, u_factor=cfg.get("c", 6.0))
     if herm:
         kw["flags"] = ent.FLAG_COMPLEX_POWER
 
@@ -568,7 +582,7 @@ def main():
             roof["epilogue_avg_launch_ms"] = avg_epi_ms
         log(f"{kernel}: {avg_step_ms:.4f} ms/launch over {launches} launches -> {achieved:.2f} TFLOP/s")
     else:
-        nnz = int(host_R[0][-1])
+        nnz = int(Rd[0][-1]) if host_R is None else int(host_R[0][-1])
         vb = 8 if precision == "f64" else 4
         tot_bytes, steps = csr_step_bytes(n, nnz, s, m, vb, cfg["method"])
         per_launch = tot_bytes / steps
@@ -590,7 +604,9 @@ def main():
         import oracle
 
         threads = oracle.max_threads()
-        nsamp = min(args.cpu_probes or threads, s)
+        nsamp = min(args.cpu_probes or cfg.get("cpu_probes") or threads, s)
+        if host_R is None and not herm:
+            host_R = tuple(a.cpu().numpy() for a in Rd[:3]) + (n,)
         probes = [int(x) for x in np.linspace(0, s - 1, nsamp).astype(int)]
         meth = oracle.CHEBYSHEV if cfg["method"] == "chebyshev" else oracle.TAYLOR
         dist = 1 if cfg["dist"] == "gaussian" else 0
@@ -604,7 +620,7 @@ def main():
             power_s = time.perf_counter() - tp
         else:
             tc = time.perf_counter()
-            ref = oracle.estimate(host_R, meth, m, s, pseed, t=t, dist=dist, probes=probes)
+            ref = oracle.estimate(host_R, meth, m, s, pseed, t=t, dist=dist, probes=probes, c=cfg.get("c", 6.0))
             cpu_s = time.perf_counter() - tc
             tp = time.perf_counter()
             oracle.power_method(host_R, t, 1, pseed)
@@ -617,7 +633,7 @@ def main():
         ref_H = ref.entropy
         log(f"oracle: power method + {nsamp} probes in {cpu_s:.2f}s on {threads} threads; "
             f"sampled per-probe rel err {max_rel:.2e}")
-        cpu = {"value": 1.0 / est_s, "unit": "estimates/s", "cores": threads, "kind": "oracle",
+        cpu = {"value": 1.0 / est_s, "unit": "estimates/s", "cores": min(threads, nsamp), "kind": "oracle",
                "sample": f"power method + {nsamp} of {s} probes of the same estimate "
                          f"({cpu_s:.1f} s), extrapolated to {s} probes ({rounds} rounds of {nsamp})"}
 

@@ -272,8 +272,8 @@ ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t 
       if (R->layout == ENT_DENSE)
         HIP_TRY(ent::launch_power_gemv<T>(Rc, ldr, n, xin, in_norm, xout, part3, &nblk, st));
       else
-        HIP_TRY(ent::launch_power_spmv<T>(R->row_ptr, R->col_idx, (const T *)R->values, n, xin,
-                                          in_norm, xout, part3, &nblk, st));
+        HIP_TRY(ent::launch_power_spmv<T>(R->row_ptr, R->col_idx, (const T *)R->values, n, R->nnz,
+                                          xin, in_norm, xout, part3, &nblk, st));
       HIP_TRY(ent::launch_power_reduce(part3, nblk, norm, st));
       std::swap(xin, xout);
       in_norm = norm;

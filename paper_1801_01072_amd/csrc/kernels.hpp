@@ -111,9 +111,10 @@ hipError_t launch_power_gemv(const T *R, int64_t ldr, int64_t n, const double *x
                              const double *in_norm, double *y, double *part3, int32_t *nblk,
                              hipStream_t st);
 template <typename T>
+// (nnz only picks the lanes per row: 1, 2, 4 or 8 by the mean row length)
 hipError_t launch_power_spmv(const int64_t *rp, const int32_t *ci, const T *val, int64_t n,
-                             const double *x, const double *in_norm, double *y, double *part3,
-                             int32_t *nblk, hipStream_t st);
+                             int64_t nnz, const double *x, const double *in_norm, double *y,
+                             double *part3, int32_t *nblk, hipStream_t st);
 // norm3[0..2] = fixed-order sums of the nblk block triples.
 hipError_t launch_power_reduce(const double *part3, int32_t nblk, double *norm3, hipStream_t st);
 // p~ of trial = norm3[1]/norm3[2] of its final product; scal[S_P1] keeps the

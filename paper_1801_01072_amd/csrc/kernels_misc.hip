@@ -189,9 +189,10 @@ template hipError_t launch_power_gemv<float>(const float *, int64_t, int64_t, co
                                              const double *, double *, double *, int32_t *,
                                              hipStream_t);
 
-// CSR: 8 lanes per row, 32 rows per block per pass, persistent grid-stride
-// over row groups (one partial triple per block).
-template <typename T>
+// CSR: L lanes per row (L = 1, 2, 4 or 8 by the mean row length), 256 / L
+// rows per block per pass, persistent grid-stride over row groups (one
+// partial triple per block).
+template <typename T, int L>
 __global__ __launch_bounds__(256) void power_spmv_kernel(const int64_t *__restrict__ rp,
                                                          const int32_t *__restrict__ ci,
                                                          const T *__restrict__ val, int64_t n,
@@ -199,18 +200,19 @@ __global__ __launch_bounds__(256) void power_spmv_kernel(const int64_t *__restri
                                                          const double *__restrict__ in_norm,
                                                          double *__restrict__ y,
                                                          double *__restrict__ part3) {
+  constexpr int RPB = 256 / L;  // rows per block per pass
   const double sc = in_norm ? 1.0 / sqrt(in_norm[0]) : 1.0;
-  const int sub = threadIdx.x & 7;
+  const int sub = threadIdx.x % L;
   double yy = 0.0, xy = 0.0, xx = 0.0;
-  for (int64_t base = (int64_t)blockIdx.x * 32; base < n; base += (int64_t)gridDim.x * 32) {
-    const int64_t row = base + (threadIdx.x >> 3);
+  for (int64_t base = (int64_t)blockIdx.x * RPB; base < n; base += (int64_t)gridDim.x * RPB) {
+    const int64_t row = base + threadIdx.x / L;
     double acc = 0.0;
     if (row < n) {
       const int64_t e1 = rp[row + 1];
-      for (int64_t e = rp[row] + sub; e < e1; e += 8) acc += (double)val[e] * x[ci[e]];
+      for (int64_t e = rp[row] + sub; e < e1; e += L) acc += (double)val[e] * x[ci[e]];
     }
 #pragma unroll
-    for (int off = 4; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    for (int off = L / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (row < n && sub == 0) {
       const double yv = sc * acc;
       const double xs = sc * x[row];
@@ -225,19 +227,27 @@ __global__ __launch_bounds__(256) void power_spmv_kernel(const int64_t *__restri
 
 template <typename T>
 hipError_t launch_power_spmv(const int64_t *rp, const int32_t *ci, const T *val, int64_t n,
-                             const double *x, const double *in_norm, double *y, double *part3,
-                             int32_t *nblk, hipStream_t st) {
+                             int64_t nnz, const double *x, const double *in_norm, double *y,
+                             double *part3, int32_t *nblk, hipStream_t st) {
   const int32_t blocks = power_blocks_csr(n);
   *nblk = blocks;
-  power_spmv_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(rp, ci, val, n, x, in_norm, y, part3);
+  const double avg = n > 0 ? (double)nnz / (double)n : 0.0;
+  if (avg <= 1.5)
+    power_spmv_kernel<T, 1><<<(unsigned)blocks, 256, 0, st>>>(rp, ci, val, n, x, in_norm, y, part3);
+  else if (avg <= 3.0)
+    power_spmv_kernel<T, 2><<<(unsigned)blocks, 256, 0, st>>>(rp, ci, val, n, x, in_norm, y, part3);
+  else if (avg <= 6.0)
+    power_spmv_kernel<T, 4><<<(unsigned)blocks, 256, 0, st>>>(rp, ci, val, n, x, in_norm, y, part3);
+  else
+    power_spmv_kernel<T, 8><<<(unsigned)blocks, 256, 0, st>>>(rp, ci, val, n, x, in_norm, y, part3);
   return hipGetLastError();
 }
 template hipError_t launch_power_spmv<double>(const int64_t *, const int32_t *, const double *,
-                                              int64_t, const double *, const double *, double *,
-                                              double *, int32_t *, hipStream_t);
+                                              int64_t, int64_t, const double *, const double *,
+                                              double *, double *, int32_t *, hipStream_t);
 template hipError_t launch_power_spmv<float>(const int64_t *, const int32_t *, const float *,
-                                             int64_t, const double *, const double *, double *,
-                                             double *, int32_t *, hipStream_t);
+                                             int64_t, int64_t, const double *, const double *,
+                                             double *, double *, int32_t *, hipStream_t);
 
 // Fixed-order sum of the block triples of one product into norm3[0..2].
 __device__ __forceinline__ void power_reduce_body(const double *__restrict__ part3, int32_t nblk,

@@ -233,6 +233,27 @@ def test_csr_poisson_closed_form():
     assert rel < 5e-3
 
 
+def test_poisson_1e7_paper_configuration(orc):
+    # the paper's tridiagonal experiment settings (m = 10, s = 100, c = 1) at n = 10^7,
+    # built on the device; exact H from the closed-form spectrum
+    n, m, s, seed = 10_000_000, 10, 100, 12
+    Rd = W.poisson_csr_torch(n, device=DEV, dtype=torch.float32)
+    lam = W.poisson_eigenvalues(n)
+    H = float(-np.sum(lam * np.log(lam)))
+    res, per, _ = ent.entropy_estimate_detail(Rd, "chebyshev", m, s, seed, precision="f32", u_factor=1.0)
+    rel = abs(res.entropy - H) / H
+    print(f"[poisson 1e7 m=10 s=100] H exact={H:.8f} gpu={res.entropy:.8f} rel={rel:.2e} se={res.std_err:.2e}",
+          flush=True)
+    assert rel < 2e-3
+    # sampled probes against the oracle on the same (host) matrix
+    host = tuple(a.cpu().numpy() for a in Rd[:3]) + (n,)
+    sel = [0, 99]
+    ref = orc.estimate(host, 1, m, s, seed, t=20, dist=0, c=1.0, probes=sel)
+    err = np.max(np.abs(per[sel] - ref.per_probe)) / np.mean(np.abs(ref.per_probe))
+    print(f"[poisson 1e7] sampled per-probe rel err vs oracle {err:.2e}", flush=True)
+    assert err <= 1e-3
+
+
 # --------------------------------------------------------------- BF16x3 ------
 @pytest.mark.parametrize("method", ["chebyshev", "taylor"])
 @pytest.mark.parametrize("dist", ["rademacher", "gaussian"])

@@ -243,6 +243,24 @@ def poisson_csr_fast(n: int, dtype=np.float64):
     return row_ptr, cols[mask].astype(np.int32), vals[mask].astype(dtype), n
 
 
+def poisson_csr_torch(n: int, device: str = "cuda", dtype=None):
+    """poisson_csr_fast built on a torch device (row_ptr int64, col_idx int32,
+    values), for n up to the 10^8 of the paper's largest experiment."""
+    import torch
+
+    dtype = dtype or torch.float32
+    idx = torch.arange(n, dtype=torch.int64, device=device)
+    cols = torch.stack([idx - 1, idx, idx + 1], dim=1)
+    mask = (cols >= 0) & (cols < n)
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    torch.cumsum(mask.sum(dim=1), dim=0, out=row_ptr[1:])
+    v = torch.tensor([-1.0, 2.0, -1.0], dtype=torch.float64, device=device) / (2.0 * n)
+    vals = v.to(dtype).expand(n, 3)[mask].contiguous()
+    col_idx = cols[mask].to(torch.int32).contiguous()
+    del cols, mask, idx
+    return row_ptr, col_idx, vals, n
+
+
 def poisson_eigenvalues(n: int) -> np.ndarray:
     """Eigenvalues of the trace-normalised tridiagonal matrix (eqn. for lambda_i, Section 6):
     lambda_i = (4 / 2n) sin^2(i pi / (2n + 2)), i = 1..n."""
