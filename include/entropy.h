@@ -99,8 +99,12 @@ enum {
   ENT_FLAG_SKIP_TRACE_CHECK = 1, /* do not verify tr R = 1                    */
   ENT_FLAG_AUTOTUNE = 2,         /* batches: time the candidate tile shapes on
                                     the batch if no cached choice exists      */
-  ENT_FLAG_COMPLEX_POWER = 4     /* Hermitian R: u = min{1, c p~1} from the
+  ENT_FLAG_COMPLEX_POWER = 4,    /* Hermitian R: u = min{1, c p~1} from the
                                     power method instead of the paper's u = 1 */
+  ENT_FLAG_CLENSHAW = 8          /* Chebyshev: evaluate g^T f_m(R) g by the
+                                    backward Clenshaw recurrence (Algorithm 5,
+                                    Appendix B) instead of the forward three-
+                                    term recurrence; see ent_entropy_estimate */
 };
 
 /*
@@ -179,6 +183,12 @@ void ent_options_default(ent_options *opt);
  * opt may be NULL (defaults).  Returns ENT_EINVAL for bad arguments,
  * ENT_ENOTDENSITY if the trace check fails, ENT_ENUMERIC if p~1 <= 0 or the
  * estimate is not finite.
+ *
+ * ENT_FLAG_CLENSHAW (Chebyshev, single estimates): y_{m+1} = y_{m+2} = 0,
+ * y_k = alpha_k g + 2 X y_{k+1} - y_{k+2} for k = m..0 (m + 1 products, the
+ * first on y_{m+1} = 0), and g^T f_m(R) g = (alpha_0 g^T g + g^T y_0 -
+ * g^T y_2) / 2.  The same estimate as the forward recurrence up to rounding;
+ * the moment table then holds g_j^T y_k (k = 0..m) instead of d_{k,j}.
  *
  * Hermitian R (complex storage; Section 4, Algorithms 1c and 2c): the same
  * estimators with h_j = ln(1/u) + sum_k g_j^T Re[R (I - R/u)^k] g_j / k and

@@ -38,6 +38,7 @@ RADEMACHER, GAUSSIAN = 0, 1
 FLAG_SKIP_TRACE_CHECK = 1
 FLAG_AUTOTUNE = 2
 FLAG_COMPLEX_POWER = 4
+FLAG_CLENSHAW = 8
 
 _METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ, "auto": AUTO}
 _PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}

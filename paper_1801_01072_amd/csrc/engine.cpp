@@ -359,7 +359,9 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   const int64_t ldv = round_up(s, dense ? bn : 64);
   const int64_t n_pad = round_up(n, 64);
   const int32_t ntile = dense ? (int32_t)(n_pad / 64) : ent::csr_step_blocks(n, sizeof(T) == 8);
-  const int32_t nslot = m + 1;
+  // Clenshaw (Algorithm 5): slots 0..m hold g^T y_k, slot m+1 holds g^T g
+  const bool clenshaw = method == ENT_CHEBYSHEV && (o.flags & ENT_FLAG_CLENSHAW);
+  const int32_t nslot = m + 1 + (clenshaw ? 1 : 0);
   const bool rad = o.probe_dist == ENT_RADEMACHER;
   const bool use_power = !(o.u_fixed > 0);
   const int32_t pblk = (int32_t)power_blocks(R);
@@ -404,6 +406,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   pe.st = st;
   pe.mark();
   HIP_TRY(hipMemsetAsync(scal, 0, sizeof(double) * 64, st));
+  // CSR step launches may use fewer workgroups than the partial stride
+  if (!dense) HIP_TRY(hipMemsetAsync(part, 0, sizeof(double) * (size_t)nslot * ntile * ldv, st));
   // trace check
   const bool check_trace = !(o.flags & ENT_FLAG_SKIP_TRACE_CHECK);
   if (check_trace) {
@@ -450,12 +454,47 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   HIP_TRY(ent::launch_setup_interval(scal, method, m, o.u_factor, o.u_fixed, o.cutoff, st));
 
   // recurrence
-  const int32_t nsteps = (method == ENT_CHEBYSHEV) ? m : m + 1;
+  const int32_t nsteps = clenshaw ? m + 1 : (method == ENT_CHEBYSHEV) ? m : m + 1;
   const T *Vk = dense || !rad ? G : nullptr;  // null: expand the sign block
   const T *Vkm1 = nullptr;
   T *bufs[2] = {VA, VB};
+  if (clenshaw) {
+    // y_{m+1} = y_{m+2} = 0; y_k = alpha_k g + 2X y_{k+1} - y_{k+2}, k = m..0,
+    // each y_k written over y_{k+2} (same element, same thread)
+    HIP_TRY(hipMemsetAsync(VA, 0, sizeof(T) * (size_t)n_pad * ldv, st));
+    HIP_TRY(hipMemsetAsync(VB, 0, sizeof(T) * (size_t)n_pad * ldv, st));
+    Vk = VA;
+    Vkm1 = VB;
+  }
   pe.steps_begin = pe.mark();
   for (int32_t k = 0; k < nsteps; ++k) {
+    if (clenshaw) {
+      const int32_t kk = m - k;  // index of the y computed by this launch
+      T *Vout = (T *)Vkm1;
+      if (dense) {
+        ent::DenseStepArgs a{};
+        a.R = Rt; a.ldr = ldr; a.n = n; a.ldv = ldv;
+        a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = Vout; a.G = G;
+        a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
+        a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.ntile = ntile; a.bn = bn;
+        a.cg = scal + ent::S_ALPHA + kk;
+        HIP_TRY(ent::launch_dense_step<T>(a, st));
+      } else {
+        ent::CsrStepArgs a{};
+        a.row_ptr = R->row_ptr; a.col_idx = R->col_idx; a.values = R->values; a.n = n; a.ldv = ldv;
+        a.Vk = Vk; a.Vkm1 = k == 0 ? nullptr : Vkm1; a.Vkp1 = Vout;
+        a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
+        a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
+        a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.nblk = ntile; a.win = cwin;
+        a.cg = scal + ent::S_ALPHA + kk;
+        HIP_TRY(ent::launch_csr_step<T>(a, st));
+      }
+      Vkm1 = Vk;
+      Vk = Vout;
+      const int e = pe.mark();
+      if (k == nsteps - 1) pe.steps_end = e;
+      continue;
+    }
     T *Vout = bufs[k & 1];
     double c1, c2, cw;
     int32_t dot_y, slot, slot_gg = -1;
@@ -500,7 +539,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     if (k == nsteps - 1) pe.steps_end = e;
   }
   HIP_TRY(ent::launch_reduce_moments(part, nslot, ntile, ldv, s, d, st));
-  HIP_TRY(ent::launch_final(d, scal, method, m, s, h, st));
+  HIP_TRY(ent::launch_final(d, scal, clenshaw ? ent::FINAL_CLENSHAW : method, m, s, h, st));
   if (hook && hook->feat_dev) {
     HIP_TRY(ent::launch_selector_features(scal, d, m, s, n, hook->feat_dev, st));
     HIP_TRY(ent::launch_mlp_forward(hook->params_dev, hook->feat_dev, 1, hook->y_dev, st));
@@ -514,7 +553,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   HIP_TRY(hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, st));
   if (per_probe) HIP_TRY(hipMemcpyAsync(per_probe, h, sizeof(double) * s, hipMemcpyDeviceToHost, st));
   if (moments)
-    HIP_TRY(hipMemcpyAsync(moments, d, sizeof(double) * nslot * s, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(moments, d, sizeof(double) * (m + 1) * s, hipMemcpyDeviceToHost, st));
   pe.mark();
   HIP_TRY(hipStreamSynchronize(st));
   pe.finish();
@@ -566,7 +605,9 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   while (tiles * splits < 256 && splits < 16 && (n_pad / (2 * splits)) % 32 == 0) splits *= 2;
   const int64_t kps = n_pad / splits;
   const int32_t nblk = ent::bf16x3_epilogue_blocks(n_pad);
-  const int32_t nslot = m + 1;
+  // Clenshaw (Algorithm 5): slots 0..m hold g^T y_k, slot m+1 holds g^T g
+  const bool clenshaw = method == ENT_CHEBYSHEV && (o.flags & ENT_FLAG_CLENSHAW);
+  const int32_t nslot = m + 1 + (clenshaw ? 1 : 0);
   const bool use_power = !(o.u_fixed > 0);
   const int32_t pblk = ent::power_blocks_split(n_pad);
 
@@ -631,11 +672,45 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   }
   HIP_TRY(ent::launch_setup_interval(scal, method, m, o.u_factor, o.u_fixed, o.cutoff, st));
 
-  const int32_t nsteps = (method == ENT_CHEBYSHEV) ? m : m + 1;
+  const int32_t nsteps = clenshaw ? m + 1 : (method == ENT_CHEBYSHEV) ? m : m + 1;
   const float *Vk = G, *Vkm1 = nullptr;
   float *bufs[2] = {VA, VB};
+  if (clenshaw) {
+    // y_{m+1} = y_{m+2} = 0 (and the split of y_{m+1}); see run_poly
+    HIP_TRY(hipMemsetAsync(VA, 0, sizeof(float) * (size_t)n_pad * ldv, st));
+    HIP_TRY(hipMemsetAsync(VB, 0, sizeof(float) * (size_t)n_pad * ldv, st));
+    HIP_TRY(hipMemsetAsync(Vhi, 0, sizeof(uint16_t) * (size_t)n_pad * ldv, st));
+    HIP_TRY(hipMemsetAsync(Vlo, 0, sizeof(uint16_t) * (size_t)n_pad * ldv, st));
+    Vk = VA;
+    Vkm1 = VB;
+  }
   pe.steps_begin = pe.mark();
   for (int32_t k = 0; k < nsteps; ++k) {
+    if (clenshaw) {
+      const int32_t kk = m - k;
+      float *Vout = (float *)Vkm1;
+      ent::Bf16GemmArgs ga{};
+      ga.A_hi = Ahi; ga.A_lo = Alo; ga.V_hi = Vhi; ga.V_lo = Vlo; ga.part_y = party;
+      ga.n_pad = n_pad; ga.ldv = ldv; ga.k_per_split = kps; ga.splits = splits; ga.bn = bn;
+      const int e0 = pe.mark();
+      HIP_TRY(ent::launch_bf16x3_gemm(ga, st));
+      const int e1 = pe.mark();
+      ent::Bf16EpiArgs ea{};
+      ea.part_y = party; ea.splits = splits; ea.Vk = Vk; ea.Vkm1 = k == 0 ? nullptr : Vkm1;
+      ea.Vkp1 = Vout; ea.V_hi = Vhi; ea.V_lo = Vlo; ea.G = G; ea.scal = scal;
+      ea.c1 = 2.0; ea.c2 = -2.0; ea.cw = k == 0 ? 0.0 : -1.0; ea.dot_y = 0; ea.slot = kk;
+      ea.slot_gg = k == 0 ? m + 1 : -1; ea.scale_y = 1; ea.cg = scal + ent::S_ALPHA + kk;
+      ea.part = part; ea.nblk = nblk; ea.n_pad = n_pad; ea.ldv = ldv;
+      HIP_TRY(ent::launch_bf16x3_epilogue(ea, st));
+      const int e2 = pe.mark();
+      if (pe.on) {
+        pe.main_spans.push_back({e0, e1});
+        pe.epi_spans.push_back({e1, e2});
+      }
+      Vkm1 = Vk;
+      Vk = Vout;
+      continue;
+    }
     float *Vout = bufs[k & 1];
     double c1, c2, cw;
     int32_t dot_y, slot, slot_gg = -1;
@@ -678,7 +753,7 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   }
   pe.steps_end = pe.mark();
   HIP_TRY(ent::launch_reduce_moments(part, nslot, nblk, ldv, s, d, st));
-  HIP_TRY(ent::launch_final(d, scal, method, m, s, h, st));
+  HIP_TRY(ent::launch_final(d, scal, clenshaw ? ent::FINAL_CLENSHAW : method, m, s, h, st));
   if (hook && hook->alpha_host)
     HIP_TRY(hipMemcpyAsync(hook->alpha_host, scal + ent::S_ALPHA, sizeof(double) * (m + 1),
                            hipMemcpyDeviceToHost, st));
@@ -686,7 +761,7 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   HIP_TRY(hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, st));
   if (per_probe) HIP_TRY(hipMemcpyAsync(per_probe, h, sizeof(double) * s, hipMemcpyDeviceToHost, st));
   if (moments)
-    HIP_TRY(hipMemcpyAsync(moments, d, sizeof(double) * nslot * s, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(moments, d, sizeof(double) * (m + 1) * s, hipMemcpyDeviceToHost, st));
   pe.mark();
   HIP_TRY(hipStreamSynchronize(st));
   pe.finish();
@@ -1389,6 +1464,8 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
   if (rc != ENT_OK) return rc;
   if (method == ENT_TAYLOR && op.o.cutoff > 0)
     return fail(ENT_EINVAL, "cutoff applies to the Chebyshev method only");
+  if (op.o.flags & ENT_FLAG_CLENSHAW)
+    return fail(ENT_EUNSUPPORTED, "batches use the forward recurrence (no Clenshaw schedule)");
   for (int32_t b = 0; b < count; ++b) {
     rc = validate_matrix(&Rs[b]);
     if (rc != ENT_OK) return fail(rc, "matrix %d: %s", b, g_last_error.c_str());
@@ -1711,6 +1788,8 @@ ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int3
   if (probes < 1) return fail(ENT_EINVAL, "probes = %d < 1", probes);
   if (method == ENT_TAYLOR && op.o.cutoff > 0)
     return fail(ENT_EINVAL, "cutoff applies to the Chebyshev method only");
+  if ((op.o.flags & ENT_FLAG_CLENSHAW) && method != ENT_CHEBYSHEV)
+    return fail(ENT_EINVAL, "the Clenshaw schedule applies to the Chebyshev method only");
   ent_result tmp{};
   if (is_complex(R))
     rc = run_hermitian(R, method, degree, probes, seed, op, &tmp, per_probe, moments);

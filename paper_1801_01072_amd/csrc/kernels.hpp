@@ -22,6 +22,9 @@ enum ScalarSlot {
   S_ALPHA = 16  // alpha_0 .. alpha_m (Chebyshev) follow
 };
 
+// launch_final's method code for the Clenshaw schedule (0 Taylor, 1 Chebyshev).
+constexpr int32_t FINAL_CLENSHAW = 2;
+
 struct DenseStepArgs {
   const void *R;      // n x n, row-major, element type T
   int64_t ldr;
@@ -39,6 +42,7 @@ struct DenseStepArgs {
   double *part;       // partials [slot][row tile][ldv]
   int32_t ntile;      // number of row tiles (partial stride)
   int32_t bn;         // column tile width (64, 128 or 256)
+  const double *cg;   // device scalar: z += (*cg) g (Clenshaw's alpha_k term); null: none
 };
 
 struct CsrStepArgs {
@@ -60,6 +64,7 @@ struct CsrStepArgs {
   double *part;
   int32_t nblk;         // persistent grid size (partial stride)
   const int2 *win;      // column window per row chunk (launch_csr_chunk_window)
+  const double *cg;     // device scalar: z += (*cg) g (Clenshaw's alpha_k term); null: none
 };
 
 // Per-matrix descriptor of a batch (device resident).  Offsets are in
@@ -187,6 +192,7 @@ struct Bf16EpiArgs {
   double *part;                 // [slot][nblk][ldv]
   int32_t nblk;
   int64_t n_pad, ldv;
+  const double *cg;             // device scalar: z += (*cg) g (Clenshaw); null: none
 };
 template <typename Tin>
 hipError_t launch_split_matrix(const Tin *R, int64_t ldr, int64_t n, int64_t n_pad,

@@ -646,6 +646,7 @@ __device__ __forceinline__ void bf16x3_epilogue_body(const Bf16EpiArgs &a, int64
   const int64_t i0 = (blk * blockDim.x + threadIdx.x) * 8;
   const float c1 = (float)a.c1, c2b = (float)(a.c2 * a.scal[S_B]), cw = (float)a.cw;
   const float ys = a.scale_y ? (float)a.scal[S_A] : 1.f;
+  const float cg = a.cg ? (float)a.cg[0] : 0.f;
   double ds = 0.0, gs = 0.0;
   if (i0 < npad) {
     const int64_t off = j * npad + i0;
@@ -681,6 +682,7 @@ __device__ __forceinline__ void bf16x3_epilogue_body(const Bf16EpiArgs &a, int64
       const float vme = e < 4 ? vm0[e] : vm1[e - 4];
       const float ge = e < 4 ? g0[e] : g1[e - 4];
       z[e] = c1 * y[e] + c2b * vke + cw * vme;
+      if (a.cg) z[e] += cg * ge;
       const uint16_t h = bf16_rne(z[e]);
       zh[e] = h;
       zl[e] = bf16_rne(z[e] - bf16_to_f32(h));

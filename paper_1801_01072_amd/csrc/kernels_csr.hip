@@ -198,6 +198,8 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
   const T tb = (T)(a.c2 * a.scal[S_B]);
   const T tc1 = (T)a.c1, tcw = (T)a.cw;
   constexpr bool use_m1 = M1 != 0;
+  const bool use_cg = a.cg != nullptr;
+  const T tcg = use_cg ? (T)a.cg[0] : T(0);
 
   // contiguous chunk range per block
   const int64_t nch = (n + CH - 1) / CH;
@@ -338,6 +340,7 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
         const T y = ta * acc[e];
         T z = tc1 * y + tb * xr[e];
         if (use_m1) z += tcw * vm[e];
+        if (use_cg) z += tcg * gv[e];
         zs[e] = z;
         ds[e] += (double)gv[e] * (double)(a.dot_y ? y : z);
         if (GG) gs[GG ? e : 0] += (double)gv[e] * (double)gv[e];
@@ -378,13 +381,15 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
   }
 }
 
-// Workgroups of the step kernels resident at once on the current device:
-// CUs x the smallest per-CU occupancy over the instances a recurrence
-// launches (registers or LDS bound it).  Every workgroup walks an equal
-// share of the chunks, so a grid larger than this would finish in a second,
-// partial round that takes as long as the first.
-template <typename T>
-static int32_t csr_resident_blocks() {
+// Workgroups of one step-kernel instance resident at once on the current
+// device: CUs x its per-CU occupancy (registers or LDS bound it).  Every
+// workgroup walks an equal share of the chunks, so a grid larger than this
+// would finish in a second, partial round that takes as long as the first.
+// Each instance is launched with its own count; the partial-sum stride is
+// the largest count of any instance (csr_step_blocks), and the partials of
+// workgroups an instance does not launch stay zero.
+template <typename T, bool VK_SIGNS, int M1, bool GG>
+static int32_t csr_instance_blocks() {
   static int32_t cache[64] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
@@ -392,22 +397,22 @@ static int32_t csr_resident_blocks() {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
     cus = 256;
-  const void *kern[] = {(const void *)csr_step_kernel<T, true, 0, true>,
-                        (const void *)csr_step_kernel<T, false, 0, true>,
-                        (const void *)csr_step_kernel<T, true, 0, false>,
-                        (const void *)csr_step_kernel<T, false, 0, false>,
-                        (const void *)csr_step_kernel<T, false, 1, false>,
-                        (const void *)csr_step_kernel<T, false, 2, false>};
-  int per_cu = 1 << 30;
-  for (const void *k : kern) {
-    int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, 64 * kCsrWaves, 0) == hipSuccess && b > 0 &&
-        b < per_cu)
-      per_cu = b;
-  }
-  if (per_cu == 1 << 30) per_cu = 1;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)csr_step_kernel<T, VK_SIGNS, M1, GG>,
+                                                   64 * kCsrWaves, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
   const int32_t r = (int32_t)(cus * per_cu);
   if (dev < 64) cache[dev] = r;
+  return r;
+}
+
+template <typename T>
+static int32_t csr_resident_blocks() {
+  const int32_t c[] = {csr_instance_blocks<T, true, 0, true>(), csr_instance_blocks<T, false, 0, true>(),
+                       csr_instance_blocks<T, true, 0, false>(), csr_instance_blocks<T, false, 0, false>(),
+                       csr_instance_blocks<T, false, 1, false>(), csr_instance_blocks<T, false, 2, false>()};
+  int32_t r = 1;
+  for (int32_t v : c) r = v > r ? v : r;
   return r;
 }
 
@@ -419,31 +424,38 @@ int32_t csr_step_blocks(int64_t n, int32_t fp64) {
   return (int32_t)(groups < cap ? groups : cap);
 }
 
+template <typename T, bool VK_SIGNS, int M1, bool GG>
+static void csr_step_launch(const CsrStepArgs &a, hipStream_t st) {
+  const int32_t inst = csr_instance_blocks<T, VK_SIGNS, M1, GG>();
+  dim3 grid((unsigned)(a.nblk < inst ? a.nblk : inst), (unsigned)(a.ldv / 64));
+  csr_step_kernel<T, VK_SIGNS, M1, GG><<<grid, 64 * kCsrWaves, 0, st>>>(a);
+}
+
+// The partial slots written by a launch must be zero beyond its grid (the
+// caller clears the partial buffer once per estimate).
 template <typename T>
 hipError_t launch_csr_step(const CsrStepArgs &a, hipStream_t st) {
-  dim3 grid((unsigned)a.nblk, (unsigned)(a.ldv / 64));
   const bool vk_signs = a.Vk == nullptr;
   const int m1 = a.cw == 0.0 ? 0 : (a.Vkm1 == nullptr ? 2 : 1);
   const bool gg = a.slot_gg >= 0;
   if ((vk_signs || m1 == 2) && !a.signs) return hipErrorInvalidValue;
-  const unsigned nt = 64 * kCsrWaves;
   if (gg) {
     if (m1 != 0) return hipErrorInvalidValue;  // g.g is taken on the first step only
     if (vk_signs)
-      csr_step_kernel<T, true, 0, true><<<grid, nt, 0, st>>>(a);
+      csr_step_launch<T, true, 0, true>(a, st);
     else
-      csr_step_kernel<T, false, 0, true><<<grid, nt, 0, st>>>(a);
+      csr_step_launch<T, false, 0, true>(a, st);
   } else if (m1 == 0) {
     if (vk_signs)
-      csr_step_kernel<T, true, 0, false><<<grid, nt, 0, st>>>(a);
+      csr_step_launch<T, true, 0, false>(a, st);
     else
-      csr_step_kernel<T, false, 0, false><<<grid, nt, 0, st>>>(a);
+      csr_step_launch<T, false, 0, false>(a, st);
   } else {
     if (vk_signs) return hipErrorInvalidValue;  // V_k is stored from the second step on
     if (m1 == 2)
-      csr_step_kernel<T, false, 2, false><<<grid, nt, 0, st>>>(a);
+      csr_step_launch<T, false, 2, false>(a, st);
     else
-      csr_step_kernel<T, false, 1, false><<<grid, nt, 0, st>>>(a);
+      csr_step_launch<T, false, 1, false>(a, st);
   }
   return hipGetLastError();
 }

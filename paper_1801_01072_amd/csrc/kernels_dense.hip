@@ -141,6 +141,8 @@ __device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, 
   const bool use_m1 = (a.cw != 0.0) && Vkm1;
   const bool want_dot = a.slot >= 0;
   const bool want_gg = a.slot_gg >= 0;
+  const bool use_cg = a.cg != nullptr;
+  const T tcg = use_cg ? (T)a.cg[0] : T(0);
 #pragma unroll
   for (int c = 0; c < NSUB; ++c) {
     const int64_t col = col0 + 16 * c + m16;
@@ -153,6 +155,7 @@ __device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, 
       const T y = ta * acc[f][c][r];
       T z = tc1 * y + tb * Vk[off];
       if (use_m1) z += tcw * Vkm1[off];
+      if (use_cg) z += tcg * G[off];
       if (Vkp1) Vkp1[off] = z;
       if (want_dot) {
         const T g = G[off];

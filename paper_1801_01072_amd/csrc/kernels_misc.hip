@@ -581,7 +581,8 @@ hipError_t launch_reduce_moments(const double *part, int32_t nslot, int32_t ntil
   return hipGetLastError();
 }
 
-// h_j and the mean/standard error.  Chebyshev: h_j = -sum_{k=0}^m alpha_k d_kj.
+// h_j and the mean/standard error.  Chebyshev: h_j = -sum_{k=0}^m alpha_k d_kj
+// (Clenshaw schedule: from g^T y_0, g^T y_2 and g^T g, see FINAL_CLENSHAW).
 // Taylor: h_j = ln(1/u) + u sum_{k=1}^m e_kj / k  (e_kj = g^T (R/u) C^k g).
 __device__ __forceinline__ void final_body(const double *__restrict__ d, double *__restrict__ scal,
                                            int32_t method, int32_t m, int32_t s,
@@ -592,7 +593,13 @@ __device__ __forceinline__ void final_body(const double *__restrict__ d, double 
   double acc = 0.0;
   for (int j = threadIdx.x; j < s; j += blockDim.x) {
     double v;
-    if (method == 1) {
+    if (method == FINAL_CLENSHAW) {
+      // Algorithm 5: g^T f_m g = (alpha_0 g^T g + g^T y_0 - g^T y_2) / 2, with
+      // d_k = g^T y_k in slots 0..m (y_2 = 0 for m < 2) and g^T g in slot m+1
+      const double gg = d[(int64_t)(m + 1) * s + j];
+      const double y2 = m >= 2 ? d[(int64_t)2 * s + j] : 0.0;
+      v = -0.5 * (scal[S_ALPHA] * gg + d[j] - y2);
+    } else if (method == 1) {
       v = 0.0;
       for (int k = 0; k <= m; ++k) v -= scal[S_ALPHA + k] * d[(int64_t)k * s + j];
     } else {

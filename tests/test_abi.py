@@ -117,3 +117,13 @@ def test_complex_storage_rules_without_device(ent):
     f = (ctypes.c_float * 16)()
     M = ent.EntMatrix(10, ent.DENSE, ent.STORE_C128, 10, 0, 1, None, None)
     assert lib.ent_selector_features(ctypes.byref(M), 0, None, f, f) == ent.EUNSUPPORTED
+
+
+def test_clenshaw_flag_rules_without_device(ent):
+    lib = ent._lib
+    res = ent.EntResult()
+    M = ent.EntMatrix(10, ent.DENSE, ent.STORE_F64, 10, 0, 1, None, None)
+    o = ent.options(flags=ent.FLAG_CLENSHAW)
+    for method in (ent.TAYLOR, ent.AUTO):
+        assert lib.ent_entropy_estimate(ctypes.byref(M), method, 10, 10, 0, ctypes.byref(o),
+                                        ctypes.byref(res)) == ent.EINVAL
