@@ -59,17 +59,23 @@ __device__ __forceinline__ int64_t frag_off(int64_t r, int64_t k, int64_t nkb) {
 // ---------------------------------------------------------------------------
 // A = a * R -> hi/lo, fragment-major, zero outside n x n; a = scal[S_A], or 1
 // when scal is null (the split is then of R itself and the scale is applied
-// to the product in the epilogue).  Thread = 8 consecutive columns of a row.
+// to the product in the epilogue).  One wave per 1 KB fragment (32 rows x 16
+// columns): lane l reads 8 consecutive columns of row 32 rb + l % 32 and
+// writes its 16 bytes at byte 16 l, so each wave stores one contiguous
+// fragment of hi and of lo.
 // ---------------------------------------------------------------------------
 template <typename Tin>
-__global__ void split_matrix_kernel(const Tin *__restrict__ R, int64_t ldr, int64_t n, int64_t n_pad,
-                                    const double *__restrict__ scal, uint16_t *__restrict__ hi,
-                                    uint16_t *__restrict__ lo) {
-  const int64_t row = blockIdx.y;
+__global__ __launch_bounds__(256) void split_matrix_kernel(const Tin *__restrict__ R, int64_t ldr, int64_t n,
+                                                           int64_t n_pad, const double *__restrict__ scal,
+                                                           uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
   const double a = scal ? scal[S_A] : 1.0;
   const int64_t nkb = n_pad / 16;
-  for (int64_t c0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8; c0 < n_pad;
-       c0 += (int64_t)gridDim.x * blockDim.x * 8) {
+  const int64_t nfrag = (n_pad / 32) * nkb;
+  const int lane = threadIdx.x & 63;
+  for (int64_t f = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; f < nfrag;
+       f += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+    const int64_t row = 32 * (f / nkb) + (lane & 31);
+    const int64_t c0 = 16 * (f % nkb) + 8 * (lane >> 5);
     u16x8 h, l;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -79,7 +85,7 @@ __global__ void split_matrix_kernel(const Tin *__restrict__ R, int64_t ldr, int6
       h[e] = bf16_rne(v);
       l[e] = bf16_rne(v - bf16_to_f32(h[e]));
     }
-    const int64_t off = frag_off(row, c0, nkb);
+    const int64_t off = f * 512 + 8 * lane;
     *(u16x8 *)(hi + off) = h;
     *(u16x8 *)(lo + off) = l;
   }
@@ -88,9 +94,9 @@ __global__ void split_matrix_kernel(const Tin *__restrict__ R, int64_t ldr, int6
 template <typename Tin>
 hipError_t launch_split_matrix(const Tin *R, int64_t ldr, int64_t n, int64_t n_pad,
                                const double *scal, uint16_t *hi, uint16_t *lo, hipStream_t st) {
-  const int64_t groups = n_pad / 8;
-  dim3 grid((unsigned)((groups + 255) / 256 < 16 ? (groups + 255) / 256 : 16), (unsigned)n_pad);
-  split_matrix_kernel<Tin><<<grid, 256, 0, st>>>(R, ldr, n, n_pad, scal, hi, lo);
+  const int64_t nfrag = (n_pad / 32) * (n_pad / 16);
+  const int64_t blocks = (nfrag + 3) / 4 < 65536 ? (nfrag + 3) / 4 : 65536;
+  split_matrix_kernel<Tin><<<(unsigned)blocks, 256, 0, st>>>(R, ldr, n, n_pad, scal, hi, lo);
   return hipGetLastError();
 }
 template hipError_t launch_split_matrix<double>(const double *, int64_t, int64_t, int64_t,
