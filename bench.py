@@ -481,7 +481,7 @@ def main():
     ap.add_argument("--count", type=int, default=0, help="matrices in the learned4096 workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the estimator "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the estimator "
               "would shard over probes with one all-reduce of the moment partials)", file=sys.stderr)
         sys.exit(2)
 

@@ -41,7 +41,7 @@ typedef enum {
   ENT_ENOMEM = -3,       /* device allocation failed or workspace cap reached */
   ENT_EDEVICE = -4,      /* a HIP runtime call failed                          */
   ENT_ENUMERIC = -5,     /* p~1 <= 0, or a non-finite estimate                 */
-  ENT_EUNSUPPORTED = -6  /* valid request this build does not implement       */
+  ENT_EUNSUPPORTED = -6  /* valid request the library does not implement      */
 } ent_status;
 
 /* Estimator (Algorithm 1 = Taylor, Section 2; Algorithm 2 = Chebyshev,
