@@ -220,6 +220,25 @@ def test_csr_wide_windows_fall_back(orc):
         check_fp64(gpu, per, mom, ref, orc, csr + (n,), method, m, s, seed, 0, label=f"csr wide {method}")
 
 
+def test_csr_long_rows(orc):
+    # ~100 entries per row: several rounds of the step's gather loop per row
+    # (it loads 40 entries of a row at a time), with ragged row lengths
+    import scipy.sparse as sp
+
+    n, m, s, seed = 2000, 10, 64, 3
+    rng = np.random.default_rng(12)
+    B = sp.random(n, n, density=10.0 / n, random_state=rng, format="csr") + sp.eye(n, format="csr")
+    Rs = (B @ B.T).tocsr()
+    Rs = Rs / Rs.diagonal().sum()
+    Rs.sort_indices()
+    assert np.diff(Rs.indptr).mean() > 60
+    csr = (Rs.indptr.astype(np.int64), Rs.indices.astype(np.int32), Rs.data.astype(np.float64), n)
+    for method in ("chebyshev", "taylor"):
+        gpu, per, mom = ent.entropy_estimate_detail(csr_to_dev(csr), method, m, s, seed)
+        ref = orc.estimate(csr, 0 if method == "taylor" else 1, m, s, seed)
+        check_fp64(gpu, per, mom, ref, orc, csr, method, m, s, seed, 0, label=f"csr long rows {method}")
+
+
 def test_csr_poisson_closed_form():
     # tridiagonal experiment: exact H from lambda_i = (4/2n) sin^2(i pi/(2n+2))
     n = 100_000
