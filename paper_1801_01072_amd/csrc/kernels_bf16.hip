@@ -68,20 +68,36 @@ template <typename Tin>
 __global__ __launch_bounds__(256) void split_matrix_kernel(const Tin *__restrict__ R, int64_t ldr, int64_t n,
                                                            int64_t n_pad, const double *__restrict__ scal,
                                                            uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
+  constexpr int VW = 16 / (int)sizeof(Tin);  // elements per 16-byte load
+  typedef Tin vec_t __attribute__((ext_vector_type(VW)));
   const double a = scal ? scal[S_A] : 1.0;
   const int64_t nkb = n_pad / 16;
   const int64_t nfrag = (n_pad / 32) * nkb;
   const int lane = threadIdx.x & 63;
+  // 16-byte loads when every row start is 16-byte aligned
+  const bool vec = ((uintptr_t)R % 16) == 0 && ldr % VW == 0;
   for (int64_t f = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; f < nfrag;
        f += ((int64_t)gridDim.x * blockDim.x) >> 6) {
     const int64_t row = 32 * (f / nkb) + (lane & 31);
     const int64_t c0 = 16 * (f % nkb) + 8 * (lane >> 5);
+    Tin x[8];
+    if (vec && 32 * (f / nkb) + 32 <= n && 16 * (f % nkb) + 16 <= n) {
+      // the fragment lies inside R
+      const vec_t *src = (const vec_t *)(R + row * ldr + c0);
+#pragma unroll
+      for (int q = 0; q < 8 / VW; ++q) {
+        const vec_t t = src[q];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) x[q * VW + e] = t[e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = (row < n && c0 + e < n) ? R[row * ldr + c0 + e] : Tin(0);
+    }
     u16x8 h, l;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int64_t c = c0 + e;
-      float v = 0.f;
-      if (row < n && c < n) v = (float)(a * (double)R[row * ldr + c]);
+      const float v = (float)(a * (double)x[e]);
       h[e] = bf16_rne(v);
       l[e] = bf16_rne(v - bf16_to_f32(h[e]));
     }
