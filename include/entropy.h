@@ -13,7 +13,12 @@
  *    the output structures are left untouched.
  *  - Matrices are passed by descriptor (ent_matrix).  Their arrays live in
  *    device memory of the current HIP device; the caller owns them and the
- *    library never retains a pointer past the call.
+ *    library never retains a pointer past the call.  Before any kernel runs,
+ *    each call checks every array it is given (matrix arrays, and the device
+ *    arrays of the MLP calls): memory of another device, or host memory the
+ *    device cannot read, is ENT_EINVAL, and so is a descriptor whose extent
+ *    ((n - 1) ld + n elements dense; n + 1, nnz, nnz CSR) runs past the end
+ *    of the allocation the pointer lies in (where the runtime reports one).
  *  - Scalar results are returned in host structures / host arrays owned by
  *    the caller.
  *  - Work is enqueued on opt->stream (a hipStream_t; NULL = the legacy

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cmath>
 #include <cstdarg>
@@ -111,7 +112,7 @@ struct DeviceWorkspace {
 
 std::mutex g_ws_mu;
 std::map<int, DeviceWorkspace *> g_ws;
-size_t g_ws_limit = 0;
+std::atomic<size_t> g_ws_limit{0};
 
 DeviceWorkspace *workspace_for(int dev) {
   std::lock_guard<std::mutex> lk(g_ws_mu);
@@ -147,7 +148,7 @@ struct Carve {
 ent_status ensure_workspace(DeviceWorkspace *w, size_t need) {
   if (g_ws_limit && need > g_ws_limit)
     return fail(ENT_ENOMEM, "workspace of %zu bytes exceeds the limit of %zu bytes", need,
-                g_ws_limit);
+                g_ws_limit.load());
   if (w->bytes >= need) return ENT_OK;
   if (w->ptr) {
     HIP_TRY(hipDeviceSynchronize());
@@ -219,6 +220,56 @@ ent_status validate_matrix(const ent_matrix *R, bool allow_complex = false) {
     return fail(ENT_EINVAL, "unknown layout %d", R->layout);
   }
   return ENT_OK;
+}
+
+// The caller's arrays must be memory the current device can read: device
+// memory of the current device (or managed / pinned host memory), with the
+// bytes the descriptor implies inside one allocation.  Checked on the host
+// before any kernel sees the pointers, so a host pointer or a descriptor
+// larger than its allocation is an ENT_EINVAL, not a memory fault.
+ent_status check_device_range(const void *p, size_t bytes, const char *what) {
+  if (!p) return fail(ENT_EINVAL, "%s is NULL", what);
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ENT_EINVAL, "%s is not memory the device can access", what);
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged && at.type != hipMemoryTypeHost)
+    return fail(ENT_EINVAL, "%s is not memory the device can access (memory type %d)", what, (int)at.type);
+  if (at.type == hipMemoryTypeDevice) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (at.device != dev)
+      return fail(ENT_EINVAL, "%s is memory of device %d, not of the current device %d", what, at.device, dev);
+    // the extent check needs the allocation's range (not every allocator
+    // reports one; then only the memory type is checked)
+    void *base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) != hipSuccess) {
+      (void)hipGetLastError();
+      return ENT_OK;
+    }
+    const uintptr_t end = (uintptr_t)base + size, at_p = (uintptr_t)p;
+    if (at_p < (uintptr_t)base || bytes > end - at_p)
+      return fail(ENT_EINVAL, "%s: the %zu bytes the descriptor implies exceed its allocation (%zu bytes from it)",
+                  what, bytes, (size_t)(end - at_p));
+  }
+  return ENT_OK;
+}
+
+// Bytes of each array of R (validate_matrix has accepted R).
+ent_status check_matrix_memory(const ent_matrix *R) {
+  const int64_t n = R->n;
+  const size_t esz = R->dtype == ENT_STORE_F64 ? 8 : R->dtype == ENT_STORE_F32 ? 4 : R->dtype == ENT_STORE_C128 ? 16 : 8;
+  if (R->layout == ENT_DENSE) {
+    if (R->ld > (INT64_MAX / (int64_t)esz) / n) return fail(ENT_EINVAL, "ld = %lld too large", (long long)R->ld);
+    return check_device_range(R->values, (size_t)((n - 1) * R->ld + n) * esz, "R->values");
+  }
+  ent_status rc = check_device_range(R->row_ptr, (size_t)(n + 1) * sizeof(int64_t), "R->row_ptr");
+  if (rc != ENT_OK || R->nnz == 0) return rc;
+  rc = check_device_range(R->col_idx, (size_t)R->nnz * sizeof(int32_t), "R->col_idx");
+  if (rc != ENT_OK) return rc;
+  return check_device_range(R->values, (size_t)R->nnz * esz, "R->values");
 }
 
 struct Opts {
@@ -924,6 +975,8 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
   if (o.sketch < ENT_SKETCH_GAUSSIAN || o.sketch > ENT_SKETCH_COUNT)
     return fail(ENT_EINVAL, "unknown sketch %d", o.sketch);
   if (k < 1 || k > s) return fail(ENT_EINVAL, "rank_k = %d out of range [1, sketch_width]", k);
+  ent_status mrc = check_matrix_memory(R);
+  if (mrc != ENT_OK) return mrc;
   const int64_t n = R->n;
   const bool f64 = R->dtype == ENT_STORE_F64;
   const int prec = o.precision;
@@ -1472,6 +1525,10 @@ ent_status batch_create(const ent_matrix *Rs, int32_t count, int32_t method, int
     if (Rs[b].layout != ENT_DENSE) return fail(ENT_EUNSUPPORTED, "matrix %d: batches are dense only", b);
     if (Rs[b].dtype != Rs[0].dtype) return fail(ENT_EINVAL, "matrix %d: mixed storage types", b);
   }
+  for (int32_t b = 0; b < count; ++b) {
+    rc = check_matrix_memory(&Rs[b]);
+    if (rc != ENT_OK) return fail(rc, "matrix %d: %s", b, g_last_error.c_str());
+  }
   auto *g = new ent_graph_s();
   g->count = count;
   g->method = method;
@@ -1699,7 +1756,7 @@ ent_status with_real_form(const ent_matrix *R, hipStream_t st, F body) {
   const size_t bytes = (size_t)n2 * (size_t)ldm * (c128 ? 8 : 4);
   if (g_ws_limit && bytes > g_ws_limit)
     return fail(ENT_ENOMEM, "real form of %zu bytes exceeds the workspace limit of %zu bytes", bytes,
-                g_ws_limit);
+                g_ws_limit.load());
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   RealFormBuffer *b = real_form_for(dev);
@@ -1746,6 +1803,28 @@ ent_status run_hermitian(const ent_matrix *R, int32_t method, int32_t m, int32_t
   });
 }
 
+// Frees the per-device buffers of one map (each after its device is idle);
+// the first failure is reported, the remaining buffers are still freed.
+template <typename Buf>
+ent_status free_buffers(std::mutex &map_mu, std::map<int, Buf *> &bufs) {
+  ent_status rc = ENT_OK;
+  std::lock_guard<std::mutex> lk(map_mu);
+  for (auto &kv : bufs) {
+    std::lock_guard<std::mutex> l2(kv.second->mu);
+    if (!kv.second->ptr) continue;
+    hipError_t e = hipSetDevice(kv.first);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipFree(kv.second->ptr);
+    if (e != hipSuccess) {
+      if (rc == ENT_OK) rc = fail(ENT_EDEVICE, "releasing a buffer on device %d: %s", kv.first, hipGetErrorString(e));
+      continue;
+    }
+    kv.second->ptr = nullptr;
+    kv.second->bytes = 0;
+  }
+  return rc;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1790,6 +1869,8 @@ ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int3
     return fail(ENT_EINVAL, "cutoff applies to the Chebyshev method only");
   if ((op.o.flags & ENT_FLAG_CLENSHAW) && method != ENT_CHEBYSHEV)
     return fail(ENT_EINVAL, "the Clenshaw schedule applies to the Chebyshev method only");
+  rc = check_matrix_memory(R);
+  if (rc != ENT_OK) return rc;
   ent_result tmp{};
   if (is_complex(R))
     rc = run_hermitian(R, method, degree, probes, seed, op, &tmp, per_probe, moments);
@@ -1813,6 +1894,8 @@ ent_status ent_power_method(const ent_matrix *R, int32_t t, int32_t q, uint64_t 
   if (rc != ENT_OK) return rc;
   if (!p1) return fail(ENT_EINVAL, "p1 is NULL");
   if (t < 0 || q < 1) return fail(ENT_EINVAL, "need t >= 0 and q >= 1");
+  rc = check_matrix_memory(R);
+  if (rc != ENT_OK) return rc;
   hipStream_t st = (hipStream_t)stream;
   if (is_complex(R))
     return with_real_form(R, st, [&](const ent_matrix &M) { return ent_power_method(&M, t, q, seed, stream, p1); });
@@ -1984,6 +2067,11 @@ ent_status ent_mlp_forward(const float *params, const float *X, int32_t count, f
   g_last_error.clear();
   if (!params || !X || !Y) return fail(ENT_EINVAL, "NULL argument");
   if (count < 1) return fail(ENT_EINVAL, "count < 1");
+  const size_t np = sizeof(float) * (size_t)ent::mlp_nparams();
+  ent_status rc = check_device_range(params, np, "params");
+  if (rc == ENT_OK) rc = check_device_range(X, sizeof(float) * 16 * (size_t)count, "X");
+  if (rc == ENT_OK) rc = check_device_range(Y, sizeof(float) * 2 * (size_t)count, "Y");
+  if (rc != ENT_OK) return rc;
   HIP_TRY(ent::launch_mlp_forward(params, X, count, Y, (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   return ENT_OK;
@@ -1995,6 +2083,14 @@ ent_status ent_mlp_grad(const float *params, const float *X, const float *T, int
   g_last_error.clear();
   if (!params || !X || !T || !grad || !loss) return fail(ENT_EINVAL, "NULL argument");
   if (count < 1) return fail(ENT_EINVAL, "count < 1");
+  {
+    const size_t np = sizeof(float) * (size_t)ent::mlp_nparams();
+    ent_status rc = check_device_range(params, np, "params");
+    if (rc == ENT_OK) rc = check_device_range(grad, np, "grad");
+    if (rc == ENT_OK) rc = check_device_range(X, sizeof(float) * 16 * (size_t)count, "X");
+    if (rc == ENT_OK) rc = check_device_range(T, sizeof(float) * 2 * (size_t)count, "T");
+    if (rc != ENT_OK) return rc;
+  }
   hipStream_t st = (hipStream_t)stream;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -2024,6 +2120,15 @@ ent_status ent_mlp_train_epoch(float *params, float *adam_m, float *adam_v, int3
   if (!params || !adam_m || !adam_v || !step || !X || !T || !mean_loss)
     return fail(ENT_EINVAL, "NULL argument");
   if (count < 1 || batch < 1) return fail(ENT_EINVAL, "count and batch must be >= 1");
+  {
+    const size_t np = sizeof(float) * (size_t)ent::mlp_nparams();
+    ent_status rc = check_device_range(params, np, "params");
+    if (rc == ENT_OK) rc = check_device_range(adam_m, np, "adam_m");
+    if (rc == ENT_OK) rc = check_device_range(adam_v, np, "adam_v");
+    if (rc == ENT_OK) rc = check_device_range(X, sizeof(float) * 16 * (size_t)count, "X");
+    if (rc == ENT_OK) rc = check_device_range(T, sizeof(float) * 2 * (size_t)count, "T");
+    if (rc != ENT_OK) return rc;
+  }
   hipStream_t st = (hipStream_t)stream;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -2089,6 +2194,8 @@ ent_status ent_selector_features(const ent_matrix *R, uint64_t seed, const ent_o
   Opts op = resolve_options(opt);
   rc = validate_options(op.o);
   if (rc != ENT_OK) return rc;
+  rc = check_matrix_memory(R);
+  if (rc != ENT_OK) return rc;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   SelectorState st;
@@ -2141,35 +2248,19 @@ ent_status ent_set_workspace_limit(size_t bytes) {
   return ENT_OK;
 }
 
+// The two maps are released one after the other, never with both map locks
+// held: a Hermitian estimate holds its real-form buffer while it takes the
+// workspace map lock.
 ent_status ent_release_workspace(void) {
   g_last_error.clear();
-  std::lock_guard<std::mutex> lk(g_ws_mu);
   int cur = 0;
   HIP_TRY(hipGetDevice(&cur));
-  for (auto &kv : g_ws) {
-    std::lock_guard<std::mutex> l2(kv.second->mu);
-    if (kv.second->ptr) {
-      HIP_TRY(hipSetDevice(kv.first));
-      HIP_TRY(hipDeviceSynchronize());
-      HIP_TRY(hipFree(kv.second->ptr));
-      kv.second->ptr = nullptr;
-      kv.second->bytes = 0;
-    }
-  }
-  {
-    std::lock_guard<std::mutex> l3(g_rf_mu);
-    for (auto &kv : g_rf) {
-      std::lock_guard<std::mutex> l4(kv.second->mu);
-      if (kv.second->ptr) {
-        HIP_TRY(hipSetDevice(kv.first));
-        HIP_TRY(hipDeviceSynchronize());
-        HIP_TRY(hipFree(kv.second->ptr));
-        kv.second->ptr = nullptr;
-        kv.second->bytes = 0;
-      }
-    }
-  }
-  HIP_TRY(hipSetDevice(cur));
+  const ent_status r1 = free_buffers(g_ws_mu, g_ws);
+  const ent_status r2 = free_buffers(g_rf_mu, g_rf);
+  const hipError_t e = hipSetDevice(cur);
+  if (r1 != ENT_OK) return r1;
+  if (r2 != ENT_OK) return r2;
+  if (e != hipSuccess) return fail(ENT_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
   return ENT_OK;
 }
 

@@ -126,3 +126,39 @@ def test_sampled_probes_at_n2048_bf16x3(orc):
     err = np.max(np.abs(per[sel] - ref.per_probe)) / np.mean(np.abs(ref.per_probe))
     print(f"[herm n=2048 bf16x3] sampled per-probe rel err {err:.2e}", flush=True)
     assert err <= 1e-3
+
+
+def test_release_while_estimating_from_another_thread():
+    # a Hermitian estimate holds its real-form buffer while it takes the
+    # workspace; releasing both from another thread must neither deadlock
+    # nor disturb the estimates
+    import threading
+
+    n, m, s, seed = 300, 10, 16, 5
+    R, _ = herm(n, 41)
+    Rt = torch.from_numpy(R).to(DEV)
+    ref = ent.entropy_estimate(Rt, "chebyshev", m, s, seed).entropy
+    out, errs = [], []
+
+    def worker():
+        try:
+            for _ in range(6):
+                out.append(ent.entropy_estimate(Rt, "chebyshev", m, s, seed).entropy)
+        except Exception as e:  # pragma: no cover
+            errs.append(e)
+
+    def releaser():
+        try:
+            for _ in range(30):
+                ent.release_workspace()
+        except Exception as e:  # pragma: no cover
+            errs.append(e)
+
+    th = [threading.Thread(target=worker, daemon=True), threading.Thread(target=releaser, daemon=True)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=60)
+    assert not any(t.is_alive() for t in th), "estimate and release did not both finish"
+    assert not errs, errs
+    assert out == [ref] * 6

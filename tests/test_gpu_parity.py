@@ -319,3 +319,59 @@ def test_bf16x3_fp32_storage_and_determinism(orc):
     assert np.array_equal(a[1], b[1])
     ref = orc.estimate(R, 1, m, s, seed)
     assert abs(a[0].entropy - ref.entropy) <= 1e-3 * ref.entropy
+
+
+def _hip_runtime():
+    # the HIP runtime this process already uses (the library's calls go to it)
+    import ctypes
+
+    paths = {l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l}
+    assert len(paths) == 1, paths
+    return ctypes.CDLL(paths.pop())
+
+
+def test_host_pointer_and_oversized_descriptor_rejected():
+    # both are refused on the host, before any kernel runs; each case is
+    # handed to the library only after the same runtime queries confirm that
+    # the library's check will refuse it
+    import ctypes
+
+    hip = _hip_runtime()
+
+    class Attr(ctypes.Structure):
+        _fields_ = [("type", ctypes.c_int), ("device", ctypes.c_int), ("devicePointer", ctypes.c_void_p),
+                    ("hostPointer", ctypes.c_void_p), ("isManaged", ctypes.c_int), ("allocationFlags", ctypes.c_uint)]
+
+    res = ent.EntResult()
+    host = np.eye(64) / 64.0
+    at = Attr()
+    rc = hip.hipPointerGetAttributes(ctypes.byref(at), ctypes.c_void_p(host.ctypes.data))
+    if rc == 0 and at.type != 0:  # pragma: no cover - runtime reports pageable memory as accessible
+        pytest.skip(f"runtime reports host memory as type {at.type}")
+    M = ent.EntMatrix(64, ent.DENSE, ent.STORE_F64, 64, 0, host.ctypes.data, None, None)
+    assert ent._lib.ent_entropy_estimate(ctypes.byref(M), 1, 10, 8, 0, None, ctypes.byref(res)) == ent.EINVAL
+    assert "access" in ent.last_error()
+
+    R = torch.eye(1024, dtype=torch.float64, device=DEV) / 1024.0
+    base, size = ctypes.c_void_p(), ctypes.c_size_t()
+    if hip.hipMemGetAddressRange(ctypes.byref(base), ctypes.byref(size), ctypes.c_void_p(R.data_ptr())) != 0:
+        pytest.skip("the runtime reports no allocation range")  # pragma: no cover
+    avail = base.value + size.value - R.data_ptr()
+    nbig = int(np.sqrt(avail / 8)) + 2
+    assert ((nbig - 1) * nbig + nbig) * 8 > avail
+    M = ent.EntMatrix(nbig, ent.DENSE, ent.STORE_F64, nbig, 0, R.data_ptr(), None, None)
+    assert ent._lib.ent_entropy_estimate(ctypes.byref(M), 1, 10, 8, 0, None, ctypes.byref(res)) == ent.EINVAL
+    assert "exceed its allocation" in ent.last_error()
+    assert ent._lib.ent_power_method(ctypes.byref(M), 5, 1, 0, None, ctypes.byref(ctypes.c_double())) == ent.EINVAL
+    # CSR: col_idx shorter than nnz
+    rp = torch.tensor([0, 1, 2], dtype=torch.int64, device=DEV)
+    ci = torch.tensor([0, 1], dtype=torch.int32, device=DEV)
+    va = torch.tensor([0.5, 0.5], dtype=torch.float64, device=DEV)
+    if hip.hipMemGetAddressRange(ctypes.byref(base), ctypes.byref(size), ctypes.c_void_p(ci.data_ptr())) != 0:
+        pytest.skip("the runtime reports no allocation range")  # pragma: no cover
+    big_nnz = (base.value + size.value - ci.data_ptr()) // 4 + 1
+    M = ent.EntMatrix(2, ent.CSR, ent.STORE_F64, 0, big_nnz, va.data_ptr(), rp.data_ptr(), ci.data_ptr())
+    assert ent._lib.ent_entropy_estimate(ctypes.byref(M), 1, 10, 8, 0, None, ctypes.byref(res)) == ent.EINVAL
+    # the same arrays with their true sizes are accepted
+    M = ent.EntMatrix(2, ent.CSR, ent.STORE_F64, 0, 2, va.data_ptr(), rp.data_ptr(), ci.data_ptr())
+    assert ent._lib.ent_entropy_estimate(ctypes.byref(M), 1, 10, 8, 0, None, ctypes.byref(res)) == ent.OK
