@@ -108,3 +108,43 @@ def test_mlp_gradient_finite_differences(orc):
         Pm[i] -= hstep
         fd = (orc.mlp_loss_grad(Pp, X, T)[0] - orc.mlp_loss_grad(Pm, X, T)[0]) / (2 * hstep)
         assert fd == pytest.approx(g[i], rel=1e-6, abs=2e-8)  # FD rounding ~ eps*loss/h
+
+
+def test_mlp_forward_closed_forms(orc):
+    # special parameter choices whose outputs follow from the network's
+    # definition (16 -> 64 -> 64 -> 2, ReLU after the two hidden layers) with
+    # no matrix product: a transposed weight block, a misplaced bias or a
+    # wrong activation changes them
+    IN, H, OUT = 16, 64, 2
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((9, IN))
+
+    def pack(W1, b1, W2, b2, W3, b3):
+        return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3.ravel(), b3])
+
+    # all weights zero: the output is the last bias for every input
+    b3 = np.array([0.25, -1.5])
+    P = pack(np.zeros((H, IN)), rng.standard_normal(H), np.zeros((H, H)), rng.standard_normal(H),
+             np.zeros((OUT, H)), b3)
+    assert np.array_equal(orc.mlp_forward(P, X), np.tile(b3, (9, 1)))
+
+    # W1 copies input (o mod 16) into hidden unit o with weight w_o; W2 is a
+    # permutation (unit o reads unit perm[o]); W3 weights c; biases zero:
+    # y_r = sum_o c[r, o] * relu(w_perm[o] * x[perm[o] mod 16])
+    w = rng.uniform(0.5, 2.0, H)
+    W1 = np.zeros((H, IN))
+    W1[np.arange(H), np.arange(H) % IN] = w
+    perm = rng.permutation(H)
+    W2 = np.zeros((H, H))
+    W2[np.arange(H), perm] = 1.0
+    C = rng.standard_normal((OUT, H))
+    P = pack(W1, np.zeros(H), W2, np.zeros(H), C, np.zeros(OUT))
+    Y = orc.mlp_forward(P, X)
+    for r in range(X.shape[0]):
+        for k in range(OUT):
+            expect = sum(C[k, o] * max(w[perm[o]] * X[r, perm[o] % IN], 0.0) for o in range(H))
+            assert Y[r, k] == pytest.approx(expect, rel=1e-13, abs=1e-13)
+    # the hidden biases enter before the ReLU: a bias of -inf-like size
+    # switches every unit off
+    P = pack(W1, np.full(H, -1e3), W2, np.zeros(H), C, np.zeros(OUT))
+    assert np.array_equal(orc.mlp_forward(P, X), np.zeros((9, OUT)))
