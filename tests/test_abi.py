@@ -127,3 +127,18 @@ def test_clenshaw_flag_rules_without_device(ent):
     for method in (ent.TAYLOR, ent.AUTO):
         assert lib.ent_entropy_estimate(ctypes.byref(M), method, 10, 10, 0, ctypes.byref(o),
                                         ctypes.byref(res)) == ent.EINVAL
+
+
+def test_host_array_rejected_before_any_kernel(ent):
+    # a descriptor that passes every argument rule but points at host memory
+    # is refused by the pointer check (here: no device at all), never launched
+    import numpy as np
+
+    lib = ent._lib
+    res = ent.EntResult()
+    host = np.eye(8) / 8.0
+    M = ent.EntMatrix(8, ent.DENSE, ent.STORE_F64, 8, 0, host.ctypes.data, None, None)
+    assert lib.ent_entropy_estimate(ctypes.byref(M), 1, 10, 4, 0, None, ctypes.byref(res)) == ent.EINVAL
+    assert "access" in ent.last_error()
+    p1 = ctypes.c_double()
+    assert lib.ent_power_method(ctypes.byref(M), 5, 1, 0, None, ctypes.byref(p1)) == ent.EINVAL
