@@ -963,7 +963,7 @@ ent_status run_auto(const ent_matrix *R, int32_t m_plain, int32_t s, uint64_t se
 
 // ---------------------------------------------------------------------------
 // Random projection (Algorithm 3): R~ = R Pi on the MFMA product kernels,
-// Gram matrix and its Jacobi eigenvalues in FP64, top-k singular values.
+// Gram matrix and its eigenvalues in FP64, top-k singular values.
 // ---------------------------------------------------------------------------
 ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_result *out,
                         double *sigma_out) {

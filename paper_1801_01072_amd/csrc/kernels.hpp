@@ -279,7 +279,7 @@ hipError_t launch_count_sketch(const T *R, int64_t ldr, int64_t n, int32_t s, ui
 template <typename T>
 hipError_t launch_gram(const T *X, int64_t si, int64_t sa, int64_t n, int32_t s, double *scratch,
                        int32_t nsplit, double *G, hipStream_t st);
-// Eigenvalues of G by parallel Jacobi, sigma = sqrt, top k -> sigma[0..k),
+// Eigenvalues of G (tridiagonalization + bisection), sigma = sqrt, top k -> sigma[0..k),
 // scal[S_ENT] = sum sigma ln(1/sigma).  work: N*N doubles, eig: N (N = s
 // rounded up to even, at most 256).
 hipError_t launch_rp_spectrum(const double *G, int32_t s, int32_t k, double *work, double *eig,

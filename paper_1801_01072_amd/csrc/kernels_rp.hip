@@ -1,9 +1,9 @@
 // kernels_rp.hip -- random-projection estimator (Algorithm 3, Section 5):
 // sketch R~ = R Pi (Gaussian and Hadamard sketches: product on the existing
 // MFMA kernels; input-sparsity sketch: one signed pass over R), Gram matrix
-// R~^T R~ in FP64, its eigenvalues by a parallel cyclic Jacobi method in one
-// workgroup, singular values sigma = sqrt(lambda), the k largest kept and
-// H^ = sum sigma ln(1/sigma).
+// R~^T R~ in FP64, its eigenvalues by Householder tridiagonalization and
+// bisection in one workgroup, singular values sigma = sqrt(lambda), the k
+// largest kept and H^ = sum sigma ln(1/sigma).
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -222,121 +222,132 @@ template hipError_t launch_gram<float>(const float *, int64_t, int64_t, int64_t,
                                        int32_t, double *, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Parallel cyclic Jacobi on a symmetric N x N matrix (N even, in place in
-// global memory), one workgroup.  A sweep is N-1 rounds of the round-robin
-// schedule (index 0 fixed, the others rotate), each round rotating N/2
-// disjoint (p, q) planes at once: rotation parameters from the round's
-// starting matrix, then all row updates, then all column updates.  Stops when
-// the off-diagonal Frobenius norm is below tol * ||A||_F, or after
-// max_sweeps sweeps (every thread reads the same shared decision).  For
-// N <= 128 the matrix is moved into LDS (128 KB) for the whole iteration.
+// Eigenvalues of a symmetric N x N matrix (N <= 256, row-major, overwritten),
+// one workgroup of 1024 threads:
+//  1. Householder reduction to tridiagonal form T (d on the diagonal, e next
+//     to it): for k = 0..N-3 the reflector H = I - beta v v^T that maps
+//     column k below the diagonal onto alpha e_1 is applied to the trailing
+//     block as A22 -= v w^T + w v^T with p = beta A22 v, w = p - (beta/2)(v.p) v
+//     (the symmetric rank-2 form of H A22 H; Golub & Van Loan, Section 8.3.1);
+//  2. each eigenvalue of T by bisection on the Sturm count (the number of
+//     negative pivots of T - x I is the number of eigenvalues below x), one
+//     thread per eigenvalue, from the Gershgorin interval.
+// Only eigenvalues are formed.  For N <= 128 the matrix lives in LDS (row
+// stride N + 1) for the whole reduction, else in the global work buffer.
 // ---------------------------------------------------------------------------
 template <bool IN_LDS>
-__global__ __launch_bounds__(1024) void jacobi_eig_kernel(double *__restrict__ Ag, int32_t N,
-                                                          double tol, int32_t max_sweeps,
-                                                          double *__restrict__ eig) {
-  __shared__ double As[IN_LDS ? 128 * 129 : 1];  // row stride N + 1: no bank conflicts down a column
-  __shared__ int sp[128], sq[128];
-  __shared__ double sc[128], ss[128];
+__global__ __launch_bounds__(1024) void tridiag_eig_kernel(double *__restrict__ Ag, int32_t N,
+                                                           double *__restrict__ eig) {
+  constexpr int NMAX = IN_LDS ? 128 : 256;
+  constexpr int TPR = 1024 / NMAX;  // threads per row in the row-parallel phases
+  __shared__ double As[IN_LDS ? 128 * 129 : 1];
+  __shared__ double v[NMAX], w[NMAX], d[NMAX], e[NMAX];
   __shared__ double red[16];
-  __shared__ int done;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int half = N / 2;
+  __shared__ double bounds[3];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double *A = IN_LDS ? As : Ag;
   const int ld = IN_LDS ? N + 1 : N;
-  if (IN_LDS) {
-    for (int e = tid; e < N * N; e += nt) As[(e / N) * ld + e % N] = Ag[e];
+  if (IN_LDS)
+    for (int x = tid; x < N * N; x += 1024) As[(x / N) * ld + x % N] = Ag[x];
+  __syncthreads();
+  // block-wide sum in a fixed order, returned to every thread
+  auto block_sum = [&](double x) -> double {
+    x = wave_sum(x);
+    if (lane == 0) red[wv] = x;
+    __syncthreads();
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += red[q];
+    __syncthreads();
+    return t;
+  };
+  const int rsub = tid / TPR, part = tid % TPR;
+  for (int k = 0; k + 2 < N; ++k) {
+    const int i0 = k + 1;
+    // column k below the diagonal is row k right of it (A is symmetric)
+    double sq = 0.0;
+    for (int j = i0 + 1 + tid; j < N; j += 1024) sq += A[k * ld + j] * A[k * ld + j];
+    const double tail = block_sum(sq);
+    const double x0 = A[k * ld + i0];
+    if (tail == 0.0) {  // already tridiagonal in this column
+      if (tid == 0) {
+        d[k] = A[k * ld + k];
+        e[k] = x0;
+      }
+      continue;
+    }
+    const double alpha = -copysign(sqrt(tail + x0 * x0), x0);
+    const double v0 = x0 - alpha;  // no cancellation: x0 and alpha differ in sign
+    const double beta = 2.0 / (tail + v0 * v0);
+    for (int j = i0 + tid; j < N; j += 1024) v[j] = j == i0 ? v0 : A[k * ld + j];
+    __syncthreads();
+    // p = beta A22 v, kept in w
+    const int i = i0 + rsub;
+    double acc = 0.0;
+    if (i < N)
+      for (int j = i0 + part; j < N; j += TPR) acc += A[i * ld + j] * v[j];
+#pragma unroll
+    for (int off = TPR / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (i < N && part == 0) w[i] = beta * acc;
+    __syncthreads();
+    const double vp = block_sum(tid + i0 < N ? v[tid + i0] * w[tid + i0] : 0.0);
+    const double K = 0.5 * beta * vp;
+    if (tid + i0 < N) w[tid + i0] -= K * v[tid + i0];
+    __syncthreads();
+    if (i < N) {
+      const double vi = v[i], wi = w[i];
+      for (int j = i0 + part; j < N; j += TPR) A[i * ld + j] -= vi * w[j] + wi * v[j];
+    }
+    if (tid == 0) {
+      d[k] = A[k * ld + k];
+      e[k] = alpha;
+    }
     __syncthreads();
   }
-  for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
-    // convergence test
-    double off = 0.0, fro = 0.0;
-    for (int e = tid; e < N * N; e += nt) {
-      const double v = A[(e / N) * ld + e % N];
-      fro += v * v;
-      if (e / N != e % N) off += v * v;
+  if (tid == 0) {
+    d[N - 2] = A[(N - 2) * ld + N - 2];
+    d[N - 1] = A[(N - 1) * ld + N - 1];
+    e[N - 2] = A[(N - 2) * ld + N - 1];
+    // Gershgorin interval of T and the pivot floor of the Sturm recurrence
+    double lo = 0.0, hi = 0.0, emax2 = 0.0;
+    for (int q = 0; q < N; ++q) {
+      const double r = (q > 0 ? fabs(e[q - 1]) : 0.0) + (q + 1 < N ? fabs(e[q]) : 0.0);
+      lo = q == 0 ? d[q] - r : fmin(lo, d[q] - r);
+      hi = q == 0 ? d[q] + r : fmax(hi, d[q] + r);
+      if (q + 1 < N) emax2 = fmax(emax2, e[q] * e[q]);
     }
-    off = wave_sum(off);
-    fro = wave_sum(fro);
-    if ((tid & 63) == 0) {
-      red[tid >> 6] = off;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double o = 0.0;
-      for (int w = 0; w < nt / 64; ++w) o += red[w];
-      red[15] = o;
-    }
-    __syncthreads();
-    const double off_tot = red[15];
-    __syncthreads();
-    if ((tid & 63) == 0) red[tid >> 6] = fro;
-    __syncthreads();
-    if (tid == 0) {
-      double f = 0.0;
-      for (int w = 0; w < nt / 64; ++w) f += red[w];
-      done = (sqrt(off_tot) <= tol * sqrt(f)) || (f == 0.0) || (sweep == max_sweeps);
-    }
-    __syncthreads();
-    if (done) break;
-    for (int r = 0; r < N - 1; ++r) {
-      if (tid < half) {
-        const int i = tid;
-        int p = (i == 0) ? 0 : ((i - 1 + r) % (N - 1)) + 1;
-        int q = ((N - 1 - i - 1 + r) % (N - 1)) + 1;
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        const double apq = A[p * ld + q];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double theta = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
-          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          s = t * c;
-        }
-        sp[i] = p;
-        sq[i] = q;
-        sc[i] = c;
-        ss[i] = s;
-      }
-      __syncthreads();
-      // rows p, q of every pair
-      for (int e = tid; e < half * N; e += nt) {
-        const int i = e / N, k = e % N;
-        const int p = sp[i], q = sq[i];
-        const double c = sc[i], s = ss[i];
-        const double apk = A[p * ld + k], aqk = A[q * ld + k];
-        A[p * ld + k] = c * apk - s * aqk;
-        A[q * ld + k] = s * apk + c * aqk;
-      }
-      __syncthreads();
-      // columns p, q of every pair
-      for (int e = tid; e < half * N; e += nt) {
-        const int i = e / N, k = e % N;
-        const int p = sp[i], q = sq[i];
-        const double c = sc[i], s = ss[i];
-        const double akp = A[k * ld + p], akq = A[k * ld + q];
-        A[k * ld + p] = c * akp - s * akq;
-        A[k * ld + q] = s * akp + c * akq;
-      }
-      __syncthreads();
-      if (tid < half) {
-        A[sp[tid] * ld + sq[tid]] = 0.0;
-        A[sq[tid] * ld + sp[tid]] = 0.0;
-      }
-      __syncthreads();
-    }
+    bounds[0] = lo;
+    bounds[1] = hi;
+    bounds[2] = 2.2250738585072014e-308 * fmax(1.0, emax2);
   }
-  for (int i = tid; i < N; i += nt) eig[i] = A[i * ld + i];
+  __syncthreads();
+  for (int q = tid; q + 1 < N; q += 1024) e[q] = e[q] * e[q];  // the recurrence uses e^2
+  __syncthreads();
+  if (tid < N) {
+    const double pivmin = bounds[2];
+    const double tnorm = fmax(fabs(bounds[0]), fabs(bounds[1]));
+    double a = bounds[0], b = bounds[1];
+    // stop at 2 ulp of the eigenvalue or 1e-22 ||T|| (square roots of
+    // eigenvalues near zero are then exact to about 1e-11 sqrt||T||)
+    for (int it = 0; it < 160; ++it) {
+      if (b - a <= fmax(4.440892098500626e-16 * fmax(fabs(a), fabs(b)), 1e-22 * tnorm)) break;
+      const double x = 0.5 * (a + b);
+      int cnt = 0;
+      double qv = d[0] - x;
+      if (fabs(qv) < pivmin) qv = -pivmin;
+      cnt += qv < 0.0;
+      for (int r = 1; r < N; ++r) {
+        qv = d[r] - x - e[r - 1] / qv;
+        if (fabs(qv) < pivmin) qv = -pivmin;
+        cnt += qv < 0.0;
+      }
+      if (cnt > tid)
+        b = x;
+      else
+        a = x;
+    }
+    eig[tid] = 0.5 * (a + b);
+  }
 }
-
-// Stopping tolerance of the Jacobi sweeps, relative to ||A||_F: rotations in
-// FP64 leave off-diagonal residue of order N eps ||A||_F (about 1.4e-14 at
-// N = 128), so a tolerance below that would never be met.
-constexpr double kJacobiTol = 1e-13;
 
 // Copy the s x s Gram matrix into an N x N (N even) work matrix.
 __global__ void pad_square_kernel(const double *__restrict__ G, int32_t s, double *__restrict__ A,
@@ -384,9 +395,9 @@ hipError_t launch_rp_spectrum(const double *G, int32_t s, int32_t k, double *wor
   if (N > 256) return hipErrorInvalidValue;
   pad_square_kernel<<<64, 256, 0, st>>>(G, s, work, N);
   if (N <= 128)
-    jacobi_eig_kernel<true><<<1, 1024, 0, st>>>(work, N, kJacobiTol, 40, eig);
+    tridiag_eig_kernel<true><<<1, 1024, 0, st>>>(work, N, eig);
   else
-    jacobi_eig_kernel<false><<<1, 1024, 0, st>>>(work, N, kJacobiTol, 40, eig);
+    tridiag_eig_kernel<false><<<1, 1024, 0, st>>>(work, N, eig);
   rp_finish_kernel<<<1, 256, 0, st>>>(eig, N, k, sigma, scal);
   return hipGetLastError();
 }

@@ -22,7 +22,8 @@ def low_rank(n, k, seed, tau=3.0):
     return W.dense_density(p, seed), p
 
 
-@pytest.mark.parametrize("n,k,s", [(600, 10, 64), (257, 7, 33), (1000, 40, 128), (130, 5, 5)])
+@pytest.mark.parametrize("n,k,s", [(600, 10, 64), (257, 7, 33), (1000, 40, 128), (130, 5, 5), (300, 12, 200),
+                                   (400, 30, 256)])
 def test_randproj_fp64_parity(orc, n, k, s):
     R, p = low_rank(n, k, 40 + n)
     seed = 3
