@@ -227,11 +227,15 @@ template hipError_t launch_gram<float>(const float *, int64_t, int64_t, int64_t,
 //  1. Householder reduction to tridiagonal form T (d on the diagonal, e next
 //     to it): for k = 0..N-3 the reflector H = I - beta v v^T that maps
 //     column k below the diagonal onto alpha e_1 is applied to the trailing
-//     block as A22 -= v w^T + w v^T with p = beta A22 v, w = p - (beta/2)(v.p) v
-//     (the symmetric rank-2 form of H A22 H; Golub & Van Loan, Section 8.3.1);
-//  2. each eigenvalue of T by bisection on the Sturm count (the number of
-//     negative pivots of T - x I is the number of eigenvalues below x), one
-//     thread per eigenvalue, from the Gershgorin interval.
+//     block as A22 -= v w^T + w v^T with p = beta A22 v, w = p - K v,
+//     K = (beta/2) v.p (the symmetric rank-2 form of H A22 H; Golub & Van
+//     Loan, Section 8.3.1).  Four barriers per step: the threads that update
+//     row k+1 also sum the squares the next step needs.
+//  2. each eigenvalue of T by multisection on the Sturm count (the number of
+//     negative pivots of T - x I is the number of eigenvalues below x): a
+//     group of 1024/NMAX threads per eigenvalue evaluates that many points of
+//     its interval at once, from the Gershgorin interval down to 2 ulp or
+//     1e-22 ||T||.
 // Only eigenvalues are formed.  For N <= 128 the matrix lives in LDS (row
 // stride N + 1) for the whole reduction, else in the global work buffer.
 // ---------------------------------------------------------------------------
@@ -239,40 +243,46 @@ template <bool IN_LDS>
 __global__ __launch_bounds__(1024) void tridiag_eig_kernel(double *__restrict__ Ag, int32_t N,
                                                            double *__restrict__ eig) {
   constexpr int NMAX = IN_LDS ? 128 : 256;
-  constexpr int TPR = 1024 / NMAX;  // threads per row in the row-parallel phases
+  constexpr int TPR = 1024 / NMAX;  // threads per row, and per eigenvalue
   __shared__ double As[IN_LDS ? 128 * 129 : 1];
   __shared__ double v[NMAX], w[NMAX], d[NMAX], e[NMAX];
   __shared__ double red[16];
-  __shared__ double bounds[3];
+  __shared__ double s_tail, bounds[3];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double *A = IN_LDS ? As : Ag;
   const int ld = IN_LDS ? N + 1 : N;
   if (IN_LDS)
     for (int x = tid; x < N * N; x += 1024) As[(x / N) * ld + x % N] = Ag[x];
   __syncthreads();
-  // block-wide sum in a fixed order, returned to every thread
+  // sum over the block in a fixed order, returned to every thread (one
+  // barrier; red is next written only after at least one more barrier)
   auto block_sum = [&](double x) -> double {
     x = wave_sum(x);
     if (lane == 0) red[wv] = x;
     __syncthreads();
     double t = 0.0;
     for (int q = 0; q < 16; ++q) t += red[q];
-    __syncthreads();
     return t;
   };
+  // sum of squares of row r right of column c0 (all threads)
+  auto row_tail = [&](int r, int c0) -> double {
+    double sq = 0.0;
+    for (int j = c0 + tid; j < N; j += 1024) sq += A[r * ld + j] * A[r * ld + j];
+    return block_sum(sq);
+  };
   const int rsub = tid / TPR, part = tid % TPR;
+  double tail = N > 2 ? row_tail(0, 2) : 0.0;
   for (int k = 0; k + 2 < N; ++k) {
     const int i0 = k + 1;
     // column k below the diagonal is row k right of it (A is symmetric)
-    double sq = 0.0;
-    for (int j = i0 + 1 + tid; j < N; j += 1024) sq += A[k * ld + j] * A[k * ld + j];
-    const double tail = block_sum(sq);
     const double x0 = A[k * ld + i0];
     if (tail == 0.0) {  // already tridiagonal in this column
       if (tid == 0) {
         d[k] = A[k * ld + k];
         e[k] = x0;
       }
+      __syncthreads();  // every thread has read red from the previous sum
+      tail = k + 3 < N ? row_tail(i0, i0 + 2) : 0.0;
       continue;
     }
     const double alpha = -copysign(sqrt(tail + x0 * x0), x0);
@@ -289,19 +299,29 @@ __global__ __launch_bounds__(1024) void tridiag_eig_kernel(double *__restrict__ 
     for (int off = TPR / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (i < N && part == 0) w[i] = beta * acc;
     __syncthreads();
-    const double vp = block_sum(tid + i0 < N ? v[tid + i0] * w[tid + i0] : 0.0);
-    const double K = 0.5 * beta * vp;
-    if (tid + i0 < N) w[tid + i0] -= K * v[tid + i0];
-    __syncthreads();
+    const double K = 0.5 * beta * block_sum(tid + i0 < N ? v[tid + i0] * w[tid + i0] : 0.0);
+    // A22 -= v (p - K v)^T + (p - K v) v^T; row i0's group also sums the
+    // squares of its new entries right of i0 + 1 (the next step's tail)
+    double sq = 0.0;
     if (i < N) {
-      const double vi = v[i], wi = w[i];
-      for (int j = i0 + part; j < N; j += TPR) A[i * ld + j] -= vi * w[j] + wi * v[j];
+      const double vi = v[i], wi = w[i] - K * v[i];
+      for (int j = i0 + part; j < N; j += TPR) {
+        const double a_new = A[i * ld + j] - (vi * (w[j] - K * v[j]) + wi * v[j]);
+        A[i * ld + j] = a_new;
+        if (j >= i0 + 2) sq += a_new * a_new;
+      }
+    }
+    if (rsub == 0) {
+#pragma unroll
+      for (int off = TPR / 2; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, 64);
+      if (part == 0) s_tail = sq;
     }
     if (tid == 0) {
       d[k] = A[k * ld + k];
       e[k] = alpha;
     }
     __syncthreads();
+    tail = s_tail;
   }
   if (tid == 0) {
     d[N - 2] = A[(N - 2) * ld + N - 2];
@@ -322,15 +342,18 @@ __global__ __launch_bounds__(1024) void tridiag_eig_kernel(double *__restrict__ 
   __syncthreads();
   for (int q = tid; q + 1 < N; q += 1024) e[q] = e[q] * e[q];  // the recurrence uses e^2
   __syncthreads();
-  if (tid < N) {
+  // eigenvalue jv (ascending) by the TPR threads of group rsub: each
+  // iteration splits [a, b] at TPR points; the group keeps the subinterval
+  // whose left end has at most jv eigenvalues below it and whose right end
+  // more (a and b stay identical across the group)
+  const int jv = rsub;
+  if (jv < N) {
     const double pivmin = bounds[2];
     const double tnorm = fmax(fabs(bounds[0]), fabs(bounds[1]));
     double a = bounds[0], b = bounds[1];
-    // stop at 2 ulp of the eigenvalue or 1e-22 ||T|| (square roots of
-    // eigenvalues near zero are then exact to about 1e-11 sqrt||T||)
-    for (int it = 0; it < 160; ++it) {
+    for (int it = 0; it < 64; ++it) {
       if (b - a <= fmax(4.440892098500626e-16 * fmax(fabs(a), fabs(b)), 1e-22 * tnorm)) break;
-      const double x = 0.5 * (a + b);
+      const double x = a + (b - a) * (double)(part + 1) / (double)(TPR + 1);
       int cnt = 0;
       double qv = d[0] - x;
       if (fabs(qv) < pivmin) qv = -pivmin;
@@ -340,12 +363,16 @@ __global__ __launch_bounds__(1024) void tridiag_eig_kernel(double *__restrict__ 
         if (fabs(qv) < pivmin) qv = -pivmin;
         cnt += qv < 0.0;
       }
-      if (cnt > tid)
-        b = x;
-      else
-        a = x;
+      double na = cnt > jv ? a : x, nb = cnt > jv ? x : b;
+#pragma unroll
+      for (int off = TPR / 2; off >= 1; off >>= 1) {
+        na = fmax(na, __shfl_xor(na, off, 64));
+        nb = fmin(nb, __shfl_xor(nb, off, 64));
+      }
+      a = na;
+      b = nb;
     }
-    eig[tid] = 0.5 * (a + b);
+    if (part == 0) eig[jv] = 0.5 * (a + b);
   }
 }
 
