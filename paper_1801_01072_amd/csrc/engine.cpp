@@ -410,6 +410,12 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   const int64_t ldv = round_up(s, dense ? bn : 64);
   const int64_t n_pad = round_up(n, 64);
   const int32_t ntile = dense ? (int32_t)(n_pad / 64) : ent::csr_step_blocks(n, sizeof(T) == 8);
+  // dense steps whose tile grid is smaller than the chip split K
+  const int32_t ksplit = dense ? ent::dense_step_splits(n, ntile, ldv, bn) : 1;
+  const int64_t kper = round_up((n + ksplit - 1) / ksplit, 32);
+  // per-probe dot partials: one per row tile (64 rows), or per 16 rows when
+  // the split-K epilogue forms them
+  const int32_t npart = ksplit > 1 ? (int32_t)(n_pad / 16) : ntile;
   // Clenshaw (Algorithm 5): slots 0..m hold g^T y_k, slot m+1 holds g^T g
   const bool clenshaw = method == ENT_CHEBYSHEV && (o.flags & ENT_FLAG_CLENSHAW);
   const int32_t nslot = m + 1 + (clenshaw ? 1 : 0);
@@ -443,7 +449,9 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   if (!dense && rad) cv.add(&signs, (size_t)n_pad * (ldv / 32));
   cv.add(&VA, (size_t)n_pad * ldv);
   cv.add(&VB, (size_t)n_pad * ldv);
-  cv.add(&part, (size_t)nslot * ntile * ldv);
+  T *party = nullptr;
+  if (ksplit > 1) cv.add(&party, (size_t)ksplit * n_pad * ldv);
+  cv.add(&part, (size_t)nslot * npart * ldv);
   cv.add(&d, (size_t)nslot * s);
   cv.add(&h, (size_t)s);
   ent_status rc = ensure_workspace(ws, cv.total());
@@ -529,6 +537,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
         a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.ntile = ntile; a.bn = bn;
         a.cg = scal + ent::S_ALPHA + kk;
+        a.ksplit = ksplit; a.kper = kper; a.party = party; a.nptile = npart;
         HIP_TRY(ent::launch_dense_step<T>(a, st));
       } else {
         ent::CsrStepArgs a{};
@@ -571,6 +580,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
       a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr; a.G = G;
       a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
       a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.ntile = ntile; a.bn = bn;
+      a.ksplit = ksplit; a.kper = kper; a.party = party; a.nptile = npart;
       HIP_TRY(ent::launch_dense_step<T>(a, st));
     } else {
       ent::CsrStepArgs a{};
@@ -589,7 +599,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     const int e = pe.mark();
     if (k == nsteps - 1) pe.steps_end = e;
   }
-  HIP_TRY(ent::launch_reduce_moments(part, nslot, ntile, ldv, s, d, st));
+  HIP_TRY(ent::launch_reduce_moments(part, nslot, npart, ldv, s, d, st));
   HIP_TRY(ent::launch_final(d, scal, clenshaw ? ent::FINAL_CLENSHAW : method, m, s, h, st));
   if (hook && hook->feat_dev) {
     HIP_TRY(ent::launch_selector_features(scal, d, m, s, n, hook->feat_dev, st));

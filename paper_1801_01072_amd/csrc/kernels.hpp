@@ -43,6 +43,13 @@ struct DenseStepArgs {
   int32_t ntile;      // number of row tiles (partial stride)
   int32_t bn;         // column tile width (64, 128 or 256)
   const double *cg;   // device scalar: z += (*cg) g (Clenshaw's alpha_k term); null: none
+  // Split-K (ksplit > 1): the product runs over ksplit ranges of kper
+  // columns into party[ks][row][ldv] (element type T, n_pad rows), and a
+  // second kernel sums them in split order and applies the epilogue.
+  int32_t ksplit;
+  int64_t kper;       // multiple of 32
+  void *party;
+  int32_t nptile;     // split-K: 16-row partial tiles (part is [slot][nptile][ldv])
 };
 
 struct CsrStepArgs {
@@ -157,6 +164,10 @@ hipError_t launch_realify(const Tin *Rc, int64_t ldr, int64_t n, Tout *M, int64_
 // ---- recurrence steps --------------------------------------------------------
 template <typename T>
 hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st);
+// K-splits for a dense step whose tile grid (ntile x ldv/bn) has fewer than
+// 512 workgroups (two per CU): a power of two up to 16 while every split
+// keeps >= 256 columns.
+int32_t dense_step_splits(int64_t n, int32_t ntile, int64_t ldv, int32_t bn);
 template <typename T>
 hipError_t launch_csr_step(const CsrStepArgs &a, hipStream_t st);
 int32_t csr_step_blocks(int64_t n, int32_t fp64);

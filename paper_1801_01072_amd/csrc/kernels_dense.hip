@@ -21,16 +21,24 @@
 // is permuted consistently for A and B).  The V_k chunk (32 x BN) is shared
 // by the 4 waves through LDS.  Row/column padding of the V buffers is zero,
 // so only the loads of R need bounds checks.
+//
+// Split-K: when the tile grid is smaller than the chip (n = 4096 with 64
+// probes has 64 tiles), each workgroup sums one range of columns into a
+// partial block and dense_split_epilogue_kernel adds the partials in split
+// order and applies the epilogue, with dot partials per 16 rows.
 #include "device_common.hpp"
 #include "kernels.hpp"
 
 namespace ent {
 
 // Body of one tile: rows [64*WR*tm, +64*WR) (wave w owns WR 16-row slabs),
-// probe columns [BN*tn, +BN).  Shared by the single-matrix kernel and the
-// grouped (batched) kernel.
+// probe columns [BN*tn, +BN), product columns [kbeg, kend) (kbeg a multiple
+// of 32; kend a multiple of 32 or >= n).  Shared by the single-matrix kernel
+// and the grouped (batched) kernel.  With yout the raw products go to
+// yout[row][ldv] (every row of the tile) instead of the epilogue.
 template <typename T, int BN, int WR>
-__device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, int tn) {
+__device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, int tn, int64_t kbeg,
+                                                int64_t kend, T *yout) {
   using M = Mfma16<T>;
   using v4 = typename M::v4;
   constexpr int BM = 64 * WR, BK = 32, PAD = 2, LDL = BN + PAD;
@@ -104,9 +112,9 @@ __device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, 
     }
   };
 
-  load_v(0);
-  load_a(0);
-  for (int64_t kc = 0; kc < n; kc += BK) {
+  load_v(kbeg);
+  load_a(kbeg);
+  for (int64_t kc = kbeg; kc < kend; kc += BK) {
     store_v();
     T acur[WR][8];
 #pragma unroll
@@ -114,7 +122,7 @@ __device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, 
 #pragma unroll
       for (int t = 0; t < 8; ++t) acur[f][t] = areg[f][t];
     __syncthreads();
-    if (kc + BK < n) {
+    if (kc + BK < kend) {
       load_v(kc + BK);
       load_a(kc + BK);
     }
@@ -131,6 +139,16 @@ __device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, 
     __syncthreads();
   }
 
+  if (yout) {
+#pragma unroll
+    for (int c = 0; c < NSUB; ++c)
+#pragma unroll
+      for (int f = 0; f < WR; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          yout[(wrow0 + 16 * f + M::drow(kq, r)) * ldv + col0 + 16 * c + m16] = acc[f][c][r];
+    return;
+  }
   // ---- epilogue ----
   const T ta = (T)a.scal[S_A];
   const T tb = (T)(a.c2 * a.scal[S_B]);
@@ -188,7 +206,88 @@ template <typename T, int BN, int WR>
 __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
   const int ntn = (int)(a.ldv / BN);
   const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-  dense_step_tile<T, BN, WR>(a, b / ntn, b % ntn);
+  if (a.ksplit > 1) {
+    // tile order: row tile fastest within a K-split, so the tiles of one
+    // split (same V_k rows) are neighbours
+    const int ntl = a.ntile * ntn;
+    const int ks = b / ntl, t = b % ntl;
+    const int64_t kbeg = (int64_t)ks * a.kper;
+    const int64_t kend = kbeg + a.kper < a.n ? kbeg + a.kper : a.n;
+    T *yout = (T *)a.party + (int64_t)ks * (int64_t)a.ntile * 64 * a.ldv;
+    dense_step_tile<T, BN, WR>(a, t / ntn, t % ntn, kbeg, kend, yout);
+  } else {
+    dense_step_tile<T, BN, WR>(a, b / ntn, b % ntn, 0, a.n, nullptr);
+  }
+}
+
+// Split-K epilogue: y = a sum_ks party[ks] (split order), z = c1 y + c2 b V_k
+// + cw V_{k-1} (+ cg g), V_{k+1} = z, and the per-probe dots over each
+// 16-row tile (part is [slot][nptile][ldv]).  Workgroup = (16 rows, 64
+// probes); thread = one probe of 4 rows, its loads of every split issued
+// together.
+template <typename T>
+__global__ __launch_bounds__(256) void dense_split_epilogue_kernel(DenseStepArgs a) {
+  __shared__ double red[2][4][64];
+  const int tp = blockIdx.x, tid = threadIdx.x, pl = tid & 63, rq = tid >> 6;
+  const int64_t ldv = a.ldv, col = (int64_t)blockIdx.y * 64 + pl;
+  const int64_t pstride = (int64_t)a.ntile * 64 * ldv;
+  const T *P = (const T *)a.party;
+  const T *Vk = (const T *)a.Vk, *Vkm1 = (const T *)a.Vkm1, *G = (const T *)a.G;
+  T *Vkp1 = (T *)a.Vkp1;
+  const T ta = (T)a.scal[S_A];
+  const T tb = (T)(a.c2 * a.scal[S_B]);
+  const T tc1 = (T)a.c1, tcw = (T)a.cw;
+  const bool use_m1 = (a.cw != 0.0) && Vkm1;
+  const bool want_dot = a.slot >= 0, want_gg = a.slot_gg >= 0;
+  const bool use_cg = a.cg != nullptr;
+  const T tcg = use_cg ? (T)a.cg[0] : T(0);
+  int64_t off[4];
+  T acc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    off[i] = ((int64_t)tp * 16 + rq * 4 + i) * ldv + col;
+    acc[i] = T(0);
+  }
+  for (int ks = 0; ks < a.ksplit; ++ks) {
+    T pv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pv[i] = P[ks * pstride + off[i]];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += pv[i];
+  }
+  double ds = 0.0, gs = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const T y = ta * acc[i];
+    T z = tc1 * y + tb * Vk[off[i]];
+    if (use_m1) z += tcw * Vkm1[off[i]];
+    if (use_cg) z += tcg * G[off[i]];
+    if (Vkp1) Vkp1[off[i]] = z;
+    if (want_dot) {
+      const T g = G[off[i]];
+      ds += (double)g * (double)(a.dot_y ? y : z);
+      if (want_gg) gs += (double)g * (double)g;
+    }
+  }
+  if (!want_dot) return;
+  red[0][rq][pl] = ds;
+  red[1][rq][pl] = gs;
+  __syncthreads();
+  if (rq == 0) {
+    const double s0 = red[0][0][pl] + red[0][1][pl] + red[0][2][pl] + red[0][3][pl];
+    a.part[((int64_t)a.slot * a.nptile + tp) * ldv + col] = s0;
+    if (want_gg) {
+      const double s1 = red[1][0][pl] + red[1][1][pl] + red[1][2][pl] + red[1][3][pl];
+      a.part[((int64_t)a.slot_gg * a.nptile + tp) * ldv + col] = s1;
+    }
+  }
+}
+
+int32_t dense_step_splits(int64_t n, int32_t ntile, int64_t ldv, int32_t bn) {
+  const int64_t tiles = (int64_t)ntile * (ldv / bn);
+  int32_t ks = 1;
+  while (tiles * ks < 512 && ks < 16 && n / (2 * ks) >= 256) ks *= 2;
+  return ks;
 }
 
 // Grouped step over a batch: block -> (matrix, row tile) from the tile table;
@@ -208,18 +307,26 @@ __global__ __launch_bounds__(256) void batch_dense_step_kernel(BatchStepArgs ba)
   a.part = ba.base.part + M.poff;
   a.ntile = M.ntile;
   a.scal = M.scal;
-  dense_step_tile<T, BN, WR>(a, tl.y, 0);
+  dense_step_tile<T, BN, WR>(a, tl.y, 0, 0, a.n, nullptr);
 }
 
 template <typename T>
 hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st) {
   const int ntn = (int)(a.ldv / a.bn);
-  const unsigned grid = (unsigned)(a.ntile * ntn);
+  if (a.ksplit > 1 && (!a.party || a.kper % 32 != 0 || (int64_t)a.ksplit * a.kper < a.n ||
+                       a.nptile != a.ntile * 4))
+    return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)(a.ntile * ntn * (a.ksplit > 1 ? a.ksplit : 1));
   switch (a.bn) {
     case 64: dense_step_kernel<T, 64, 1><<<grid, 256, 0, st>>>(a); break;
     case 128: dense_step_kernel<T, 128, 1><<<grid, 256, 0, st>>>(a); break;
     case 256: dense_step_kernel<T, 256, 1><<<grid, 256, 0, st>>>(a); break;
     default: return hipErrorInvalidValue;
+  }
+  if (a.ksplit > 1) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dense_split_epilogue_kernel<T><<<dim3((unsigned)a.nptile, (unsigned)(a.ldv / 64)), 256, 0, st>>>(a);
   }
   return hipGetLastError();
 }
