@@ -118,6 +118,24 @@ def test_dense_fp32_compute(orc, method):
     assert rel <= 1e-3
 
 
+@pytest.mark.parametrize("n,s", [(2048, 8), (3000, 20)])
+def test_dense_split_k(orc, n, s):
+    # few row tiles: the product runs over 8 column ranges (the last one of
+    # n = 3000 ends inside a 32-column chunk) and the split epilogue sums
+    # them; FP64 to the oracle, forward (Chebyshev, Taylor) and Clenshaw
+    R = W.dense_density(W.spectrum_exp(n, n / 6.0), 300 + n)
+    m, seed = 6, 4
+    for method, flags in (("chebyshev", 0), ("taylor", 0), ("chebyshev", ent.FLAG_CLENSHAW)):
+        gpu, per, mom = ent.entropy_estimate_detail(to_dev(R), method, m, s, seed, flags=flags)
+        ref = orc.estimate(R, 0 if method == "taylor" else 1, m, s, seed)
+        err = np.max(np.abs(per - ref.per_probe)) / np.mean(np.abs(ref.per_probe))
+        print(f"[split-K n={n} s={s} {method} flags={flags}] per-probe rel {err:.2e}", flush=True)
+        assert err <= 1e-10
+    gpu = ent.entropy_estimate(to_dev(R), "chebyshev", m, s, seed, precision="f32")
+    ref = orc.estimate(R, 1, m, s, seed)
+    assert abs(gpu.entropy - ref.entropy) / abs(ref.entropy) <= 1e-3
+
+
 def test_special_states(orc):
     n = 96
     # pure state: Taylor gives exactly ln(1) + 0 (u = 1)
