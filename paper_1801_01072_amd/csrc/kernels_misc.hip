@@ -568,16 +568,32 @@ __device__ __forceinline__ void reduce_moments_body(const double *__restrict__ p
   d[(int64_t)k * s + j] = acc;
 }
 
-__global__ void reduce_moments_kernel(const double *__restrict__ part, int32_t nslot,
-                                      int32_t ntile, int64_t ldv, int32_t s,
-                                      double *__restrict__ d) {
-  reduce_moments_body(part, nslot, ntile, ldv, s, d, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+// One estimate's moments: workgroup = (slot, 64 probes); wave w sums the
+// tiles of its contiguous quarter in order, then the quarters are added in
+// order (fixed, so repeated runs agree bit for bit).
+__global__ __launch_bounds__(256) void reduce_moments_kernel(const double *__restrict__ part, int32_t nslot,
+                                                             int32_t ntile, int64_t ldv, int32_t s,
+                                                             double *__restrict__ d) {
+  __shared__ double q[4][64];
+  const int k = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.y * 64 + lane;
+  const int32_t per = (ntile + 3) / 4;
+  const int32_t i0 = w * per, i1 = i0 + per < ntile ? i0 + per : ntile;
+  double acc = 0.0;
+  if (j < s) {
+    const double *p = part + (int64_t)k * ntile * ldv + j;
+    for (int32_t i = i0; i < i1; ++i) acc += p[(int64_t)i * ldv];
+  }
+  q[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && j < s) d[(int64_t)k * s + j] = ((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane];
 }
 
 hipError_t launch_reduce_moments(const double *part, int32_t nslot, int32_t ntile, int64_t ldv,
                                  int32_t s, double *d, hipStream_t st) {
-  const int64_t tot = (int64_t)nslot * s;
-  reduce_moments_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(part, nslot, ntile, ldv, s, d);
+  if (nslot < 1 || s < 1) return hipSuccess;
+  reduce_moments_kernel<<<dim3((unsigned)nslot, (unsigned)((s + 63) / 64)), 256, 0, st>>>(part, nslot, ntile, ldv,
+                                                                                         s, d);
   return hipGetLastError();
 }
 
