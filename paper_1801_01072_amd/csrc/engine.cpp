@@ -477,10 +477,10 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         HIP_TRY(ent::launch_trace_dense<float>((const float *)R->values, R->ld, n, scal, st));
     } else {
       if (R->dtype == ENT_STORE_F64)
-        HIP_TRY(ent::launch_trace_csr<double>(R->row_ptr, R->col_idx, (const double *)R->values, n,
+        HIP_TRY(ent::launch_trace_csr<double>(R->row_ptr, R->col_idx, (const double *)R->values, n, R->nnz,
                                               scal, st));
       else
-        HIP_TRY(ent::launch_trace_csr<float>(R->row_ptr, R->col_idx, (const float *)R->values, n,
+        HIP_TRY(ent::launch_trace_csr<float>(R->row_ptr, R->col_idx, (const float *)R->values, n, R->nnz,
                                              scal, st));
     }
   }

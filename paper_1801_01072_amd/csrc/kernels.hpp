@@ -142,7 +142,7 @@ hipError_t launch_setup_interval(double *scal, int32_t method, int32_t m, double
 template <typename T>
 hipError_t launch_trace_dense(const T *R, int64_t ldr, int64_t n, double *scal, hipStream_t st);
 template <typename T>
-hipError_t launch_trace_csr(const int64_t *rp, const int32_t *ci, const T *val, int64_t n,
+hipError_t launch_trace_csr(const int64_t *rp, const int32_t *ci, const T *val, int64_t n, int64_t nnz,
                             double *scal, hipStream_t st);
 
 // CSR structure check; flag[0] |= 1 on any violation (flag must start at 0).

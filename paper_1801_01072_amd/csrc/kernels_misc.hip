@@ -409,18 +409,26 @@ hipError_t launch_trace_dense(const T *R, int64_t ldr, int64_t n, double *scal, 
 template hipError_t launch_trace_dense<double>(const double *, int64_t, int64_t, double *, hipStream_t);
 template hipError_t launch_trace_dense<float>(const float *, int64_t, int64_t, double *, hipStream_t);
 
-// CSR: diagonal entries found by a scan of each row; per-block partials are
-// combined by the last pass in block order.
-template <typename T>
-__global__ void trace_csr_partial_kernel(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                         const T *__restrict__ val, int64_t n,
-                                         double *__restrict__ tmp) {
+// CSR: diagonal entries found by a scan of each row, L lanes per row (L by
+// the mean row length, as in the power-method product) so that a row's
+// column indices are read together; per-block partials are combined by the
+// last pass in block order.
+template <typename T, int L>
+__global__ __launch_bounds__(256) void trace_csr_partial_kernel(const int64_t *__restrict__ rp,
+                                                                const int32_t *__restrict__ ci,
+                                                                const T *__restrict__ val, int64_t n,
+                                                                double *__restrict__ tmp) {
+  constexpr int RPB = 256 / L;
   __shared__ double red[4];
+  const int sub = threadIdx.x % L;
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
-      if (ci[e] == i) acc += (double)val[e];
+  for (int64_t base = (int64_t)blockIdx.x * RPB; base < n; base += (int64_t)gridDim.x * RPB) {
+    const int64_t row = base + threadIdx.x / L;
+    if (row < n) {
+      const int64_t e1 = rp[row + 1];
+      for (int64_t e = rp[row] + sub; e < e1; e += L)
+        if (ci[e] == row) acc += (double)val[e];
+    }
   }
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -437,18 +445,26 @@ __global__ void sum_to_slot_kernel(const double *__restrict__ tmp, int32_t cnt, 
 
 template <typename T>
 hipError_t launch_trace_csr(const int64_t *rp, const int32_t *ci, const T *val, int64_t n,
-                            double *scal, hipStream_t st) {
+                            int64_t nnz, double *scal, hipStream_t st) {
   // scal has room after the coefficient area: use a scratch tail of 1024 doubles
   double *tmp = scal + 4096;
   const int blocks = 1024;
-  trace_csr_partial_kernel<T><<<blocks, 256, 0, st>>>(rp, ci, val, n, tmp);
+  const double avg = n > 0 ? (double)nnz / (double)n : 0.0;
+  if (avg <= 1.5)
+    trace_csr_partial_kernel<T, 1><<<blocks, 256, 0, st>>>(rp, ci, val, n, tmp);
+  else if (avg <= 3.0)
+    trace_csr_partial_kernel<T, 2><<<blocks, 256, 0, st>>>(rp, ci, val, n, tmp);
+  else if (avg <= 6.0)
+    trace_csr_partial_kernel<T, 4><<<blocks, 256, 0, st>>>(rp, ci, val, n, tmp);
+  else
+    trace_csr_partial_kernel<T, 8><<<blocks, 256, 0, st>>>(rp, ci, val, n, tmp);
   sum_to_slot_kernel<<<1, 64, 0, st>>>(tmp, blocks, scal + S_TRACE);
   return hipGetLastError();
 }
 template hipError_t launch_trace_csr<double>(const int64_t *, const int32_t *, const double *,
-                                             int64_t, double *, hipStream_t);
+                                             int64_t, int64_t, double *, hipStream_t);
 template hipError_t launch_trace_csr<float>(const int64_t *, const int32_t *, const float *, int64_t,
-                                            double *, hipStream_t);
+                                            int64_t, double *, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // CSR structure check: row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz, and
@@ -465,7 +481,21 @@ __global__ void validate_csr_kernel(const int64_t *__restrict__ rp, const int32_
     if (i == n && v != nnz) bad = true;
     if (i < n && rp[i + 1] < v) bad = true;
   }
-  for (int64_t e = t0; e < nnz; e += stride) {
+  // column indices, 16 bytes per load when the array allows it (a negative
+  // index is a large unsigned one)
+  int64_t done = 0;
+  if (((uintptr_t)ci & 15) == 0) {
+    const int4 *c4 = (const int4 *)ci;
+    const int64_t n4 = nnz / 4;
+    for (int64_t q = t0; q < n4; q += stride) {
+      const int4 v = c4[q];
+      if ((int64_t)(uint32_t)v.x >= n || (int64_t)(uint32_t)v.y >= n || (int64_t)(uint32_t)v.z >= n ||
+          (int64_t)(uint32_t)v.w >= n)
+        bad = true;
+    }
+    done = n4 * 4;
+  }
+  for (int64_t e = done + t0; e < nnz; e += stride) {
     const int32_t c = ci[e];
     if (c < 0 || (int64_t)c >= n) bad = true;
   }

@@ -393,3 +393,37 @@ def test_host_pointer_and_oversized_descriptor_rejected():
     # the same arrays with their true sizes are accepted
     M = ent.EntMatrix(2, ent.CSR, ent.STORE_F64, 0, 2, va.data_ptr(), rp.data_ptr(), ci.data_ptr())
     assert ent._lib.ent_entropy_estimate(ctypes.byref(M), 1, 10, 8, 0, None, ctypes.byref(res)) == ent.OK
+
+
+def test_csr_structure_rejected(orc):
+    # malformed CSR input is refused by the device-side structure check
+    # before any step reads it (n is not a multiple of 64, so even a column
+    # index of n would stay inside the padded buffers)
+    n = 100
+    rp, ci, val, _ = W.banded_density_csr(n, 3, seed=5)
+    ci = ci.astype(np.int32)
+
+    def run(rp_, ci_, val_, nnz=None):
+        M = ent.csr_matrix(torch.from_numpy(rp_).to(DEV), torch.from_numpy(ci_).to(DEV),
+                           torch.from_numpy(val_).to(DEV), n)
+        if nnz is not None:
+            M.nnz = nnz
+        return ent.entropy_estimate(M, "chebyshev", 8, 8, 1)
+
+    good = run(rp, ci, val)
+    bad = []
+    c = ci.copy(); c[len(c) // 2] = n; bad.append((rp, c, val, None))
+    c = ci.copy(); c[7] = -1; bad.append((rp, c, val, None))
+    r = rp.copy(); r[10], r[11] = r[11], r[10]; bad.append((r, ci, val, None))
+    r = rp.copy(); r[0] = 1; bad.append((r, ci, val, None))
+    bad.append((rp, ci, val, len(ci) - 1))
+    for k, (r_, c_, v_, nnz) in enumerate(bad):
+        with pytest.raises(ent.EntropyError) as e:
+            run(r_, c_, v_, nnz)
+        assert e.value.status == ent.EINVAL, k
+        assert "CSR structure" in str(e.value), k
+    # column indices not 16-byte aligned (scalar path of the check): same result
+    ci_off = torch.zeros(len(ci) + 1, dtype=torch.int32, device=DEV)
+    ci_off[1:] = torch.from_numpy(ci).to(DEV)
+    M = ent.csr_matrix(torch.from_numpy(rp).to(DEV), ci_off[1:], torch.from_numpy(val).to(DEV), n)
+    assert ent.entropy_estimate(M, "chebyshev", 8, 8, 1).entropy == good.entropy
