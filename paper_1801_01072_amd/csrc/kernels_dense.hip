@@ -206,18 +206,22 @@ template <typename T, int BN, int WR>
 __global__ __launch_bounds__(256) void dense_step_kernel(DenseStepArgs a) {
   const int ntn = (int)(a.ldv / BN);
   const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-  if (a.ksplit > 1) {
-    // tile order: row tile fastest within a K-split, so the tiles of one
-    // split (same V_k rows) are neighbours
-    const int ntl = a.ntile * ntn;
-    const int ks = b / ntl, t = b % ntl;
-    const int64_t kbeg = (int64_t)ks * a.kper;
-    const int64_t kend = kbeg + a.kper < a.n ? kbeg + a.kper : a.n;
-    T *yout = (T *)a.party + (int64_t)ks * (int64_t)a.ntile * 64 * a.ldv;
-    dense_step_tile<T, BN, WR>(a, t / ntn, t % ntn, kbeg, kend, yout);
-  } else {
-    dense_step_tile<T, BN, WR>(a, b / ntn, b % ntn, 0, a.n, nullptr);
-  }
+  dense_step_tile<T, BN, WR>(a, b / ntn, b % ntn, 0, a.n, nullptr);
+}
+
+// Split-K product (a kernel of its own, so the fused kernel's code is not
+// shaped by this path): tile order row tile fastest within a K-split, so the
+// tiles of one split (same V_k rows) are neighbours.
+template <typename T, int BN, int WR>
+__global__ __launch_bounds__(256) void dense_step_split_kernel(DenseStepArgs a) {
+  const int ntn = (int)(a.ldv / BN);
+  const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int ntl = a.ntile * ntn;
+  const int ks = b / ntl, t = b % ntl;
+  const int64_t kbeg = (int64_t)ks * a.kper;
+  const int64_t kend = kbeg + a.kper < a.n ? kbeg + a.kper : a.n;
+  T *yout = (T *)a.party + (int64_t)ks * (int64_t)a.ntile * 64 * a.ldv;
+  dense_step_tile<T, BN, WR>(a, t / ntn, t % ntn, kbeg, kend, yout);
 }
 
 // Split-K epilogue: y = a sum_ks party[ks] (split order), z = c1 y + c2 b V_k
@@ -317,11 +321,20 @@ hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st) {
                        a.nptile != a.ntile * 4))
     return hipErrorInvalidValue;
   const unsigned grid = (unsigned)(a.ntile * ntn * (a.ksplit > 1 ? a.ksplit : 1));
-  switch (a.bn) {
-    case 64: dense_step_kernel<T, 64, 1><<<grid, 256, 0, st>>>(a); break;
-    case 128: dense_step_kernel<T, 128, 1><<<grid, 256, 0, st>>>(a); break;
-    case 256: dense_step_kernel<T, 256, 1><<<grid, 256, 0, st>>>(a); break;
-    default: return hipErrorInvalidValue;
+  if (a.ksplit > 1) {
+    switch (a.bn) {
+      case 64: dense_step_split_kernel<T, 64, 1><<<grid, 256, 0, st>>>(a); break;
+      case 128: dense_step_split_kernel<T, 128, 1><<<grid, 256, 0, st>>>(a); break;
+      case 256: dense_step_split_kernel<T, 256, 1><<<grid, 256, 0, st>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (a.bn) {
+      case 64: dense_step_kernel<T, 64, 1><<<grid, 256, 0, st>>>(a); break;
+      case 128: dense_step_kernel<T, 128, 1><<<grid, 256, 0, st>>>(a); break;
+      case 256: dense_step_kernel<T, 256, 1><<<grid, 256, 0, st>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   if (a.ksplit > 1) {
     const hipError_t e = hipGetLastError();
