@@ -337,7 +337,7 @@ ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t 
 // The same power method on the bf16 hi/lo split of a dense R.
 ent_status enqueue_power_split(const uint16_t *hi, const uint16_t *lo, int64_t n, int64_t n_pad,
                                int32_t t, int32_t q, uint64_t seed, double *x0, double *x1,
-                               double *part3, double *norm, double *scal, hipStream_t st) {
+                               double *part3, double *norm, double *scal, double *ypart, hipStream_t st) {
   // the split is zero beyond n, and so must be the vectors it multiplies
   HIP_TRY(ent::launch_fill(x0, n_pad, 0.0, st));
   HIP_TRY(ent::launch_fill(x1, n_pad, 0.0, st));
@@ -347,7 +347,7 @@ ent_status enqueue_power_split(const uint16_t *hi, const uint16_t *lo, int64_t n
     const double *in_norm = nullptr;
     for (int32_t it = 0; it <= t; ++it) {
       int32_t nblk = 0;
-      HIP_TRY(ent::launch_power_gemv_split(hi, lo, n_pad, n, xin, in_norm, xout, part3, &nblk, st));
+      HIP_TRY(ent::launch_power_gemv_split(hi, lo, n_pad, n, xin, in_norm, xout, part3, ypart, &nblk, st));
       HIP_TRY(ent::launch_power_reduce(part3, nblk, norm, st));
       std::swap(xin, xout);
       in_norm = norm;
@@ -676,7 +676,7 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   HIP_TRY(hipGetDevice(&dev));
   DeviceWorkspace *ws = workspace_for(dev);
   std::lock_guard<std::mutex> lk(ws->mu);
-  double *scal = nullptr, *x0 = nullptr, *x1 = nullptr, *p0 = nullptr, *p1 = nullptr;
+  double *scal = nullptr, *x0 = nullptr, *x1 = nullptr, *p0 = nullptr, *p1 = nullptr, *ypart = nullptr;
   double *part = nullptr, *d = nullptr, *h = nullptr;
   uint16_t *Ahi = nullptr, *Alo = nullptr, *Vhi = nullptr, *Vlo = nullptr;
   float *G = nullptr, *VA = nullptr, *VB = nullptr, *party = nullptr;
@@ -687,6 +687,8 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
     cv.add(&x1, n_pad);
     cv.add(&p0, 3 * (size_t)pblk);
     cv.add(&p1, 4);
+    const int32_t pparts = ent::power_split_parts(n_pad);
+    if (pparts > 1) cv.add(&ypart, (size_t)pparts * n_pad);
   }
   cv.add(&Ahi, (size_t)n_pad * n_pad);
   cv.add(&Alo, (size_t)n_pad * n_pad);
@@ -726,7 +728,7 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   if (use_power) {
     pe.power_begin = pe.mark();
     rc = enqueue_power_split(Ahi, Alo, n, n_pad, o.power_iters, o.power_trials, seed, x0, x1, p0, p1,
-                             scal, st);
+                             scal, ypart, st);
     if (rc != ENT_OK) return rc;
     pe.power_end = pe.mark();
     pe.power_launches = o.power_trials * (o.power_iters + 1);

@@ -217,11 +217,14 @@ hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, i
 int32_t bf16x3_tile_rows(int64_t n_pad);
 hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st);
 // Power-method product on the fragment-major bf16 hi/lo split of R; x must
-// be zero in [n, n_pad).  power_blocks_split: its grid (= partial count).
+// be zero in [n, n_pad).  power_blocks_split: the most partials it writes.
+// power_split_parts: column parts per band (> 1: ypart holds parts x n_pad
+// doubles).
 int32_t power_blocks_split(int64_t n_pad);
+int32_t power_split_parts(int64_t n_pad);
 hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64_t n_pad, int64_t n,
                                    const double *x, const double *in_norm, double *y, double *part3,
-                                   int32_t *nblk, hipStream_t st);
+                                   double *ypart, int32_t *nblk, hipStream_t st);
 hipError_t launch_bf16x3_epilogue(const Bf16EpiArgs &a, hipStream_t st);
 int32_t bf16x3_epilogue_blocks(int64_t n_pad);
 // ---- BF16x3 batches (descriptor-driven; tables of (matrix, tile) pairs) ----

@@ -624,9 +624,96 @@ hipError_t launch_batch_power_split(const BatchMat *mats, const int2 *ptiles, in
 
 int32_t power_blocks_split(int64_t n_pad) { return (int32_t)(n_pad / 32); }
 
+// One workgroup per band leaves some CUs with two bands when the band count
+// is not a multiple of 256 (n_pad = 10240: 320 bands, 3.9 TB/s against 6.2
+// at 8192).  Then each band's columns are split into S parts of whole
+// 16-column blocks (about 1024 workgroups in all): part p of band b goes to
+// ypart[p][row], and a second pass adds the parts in order, scales, and
+// forms the norm partials per 256 rows.
+int32_t power_split_parts(int64_t n_pad) {
+  const int64_t nb = n_pad / 32, nkb = n_pad / 16;
+  if (nb % 256 == 0) return 1;
+  int64_t p = 1;
+  while (nb * p < 1024 && 2 * p * 16 <= nkb) p *= 2;
+  return (int32_t)p;
+}
+
+__global__ __launch_bounds__(256) void power_split_part_kernel(const uint16_t *__restrict__ hi,
+                                                               const uint16_t *__restrict__ lo,
+                                                               int64_t n_pad, const double *__restrict__ x,
+                                                               double *__restrict__ ypart, int32_t nparts) {
+  constexpr int W = 4;
+  __shared__ double red[W][32];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t band = blockIdx.x, part = blockIdx.y;
+  const int64_t nkb = n_pad / 16;
+  const int64_t kb0 = part * nkb / nparts, kb1 = (part + 1) * nkb / nparts;
+  const uint16_t *H = hi + band * nkb * 512 + 8 * lane;
+  const uint16_t *Lo = lo + band * nkb * 512 + 8 * lane;
+  const int64_t kofs = 8 * (lane >> 5);
+  double acc = 0.0, acc2 = 0.0;
+  int64_t kb = kb0 + w;
+  for (; kb + W < kb1; kb += 2 * W) {
+    const u16x8 h0 = *(const u16x8 *)(H + kb * 512), l0 = *(const u16x8 *)(Lo + kb * 512);
+    const u16x8 h1 = *(const u16x8 *)(H + (kb + W) * 512), l1 = *(const u16x8 *)(Lo + (kb + W) * 512);
+    const double *x0 = x + kb * 16 + kofs, *x1 = x + (kb + W) * 16 + kofs;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      acc += (double)(bf16_to_f32(h0[e]) + bf16_to_f32(l0[e])) * x0[e];
+      acc2 += (double)(bf16_to_f32(h1[e]) + bf16_to_f32(l1[e])) * x1[e];
+    }
+  }
+  for (; kb < kb1; kb += W) {
+    const u16x8 h0 = *(const u16x8 *)(H + kb * 512), l0 = *(const u16x8 *)(Lo + kb * 512);
+    const double *x0 = x + kb * 16 + kofs;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc += (double)(bf16_to_f32(h0[e]) + bf16_to_f32(l0[e])) * x0[e];
+  }
+  acc += acc2;
+  acc += __shfl_xor(acc, 32, 64);  // the two 8-column halves of a row
+  if (lane < 32) red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && lane < 32) {
+    double sum = 0.0;
+    for (int q = 0; q < W; ++q) sum += red[q][lane];
+    ypart[part * n_pad + band * 32 + lane] = sum;
+  }
+}
+
+__global__ __launch_bounds__(256) void power_split_combine_kernel(const double *__restrict__ ypart,
+                                                                  int32_t nparts, int64_t n_pad, int64_t n,
+                                                                  const double *__restrict__ x,
+                                                                  const double *__restrict__ in_norm,
+                                                                  double *__restrict__ y,
+                                                                  double *__restrict__ part3) {
+  const double sc = in_norm ? 1.0 / sqrt(in_norm[0]) : 1.0;
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double yy = 0.0, xy = 0.0, xx = 0.0;
+  if (r < n) {
+    double sum = 0.0;
+    for (int32_t p = 0; p < nparts; ++p) sum += ypart[p * n_pad + r];
+    const double yv = sc * sum, xs = sc * x[r];
+    y[r] = yv;
+    yy = yv * yv;
+    xy = xs * yv;
+    xx = xs * xs;
+  }
+  block_power_partials(yy, xy, xx, part3, blockIdx.x);
+}
+
 hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64_t n_pad, int64_t n,
                                    const double *x, const double *in_norm, double *y, double *part3,
-                                   int32_t *nblk, hipStream_t st) {
+                                   double *ypart, int32_t *nblk, hipStream_t st) {
+  const int32_t parts = power_split_parts(n_pad);
+  if (parts > 1) {
+    if (!ypart) return hipErrorInvalidValue;
+    power_split_part_kernel<<<dim3((unsigned)(n_pad / 32), (unsigned)parts), 256, 0, st>>>(hi, lo, n_pad, x, ypart,
+                                                                                          parts);
+    const int32_t blocks = (int32_t)((n_pad + 255) / 256);
+    *nblk = blocks;
+    power_split_combine_kernel<<<(unsigned)blocks, 256, 0, st>>>(ypart, parts, n_pad, n, x, in_norm, y, part3);
+    return hipGetLastError();
+  }
   const int32_t blocks = power_blocks_split(n_pad);
   *nblk = blocks;
   power_gemv_split_kernel<<<(unsigned)blocks, 1024, 0, st>>>(hi, lo, n_pad, n, x, in_norm, y, part3);
