@@ -662,8 +662,7 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   const int bn = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
   const int64_t ldv = round_up(s, bn);
   const int64_t tiles = (n_pad / ent::bf16x3_tile_rows(n_pad)) * (ldv / bn);
-  int32_t splits = 1;
-  while (tiles * splits < 256 && splits < 16 && (n_pad / (2 * splits)) % 32 == 0) splits *= 2;
+  const int32_t splits = ent::bf16x3_splits(n_pad, tiles);
   const int64_t kps = n_pad / splits;
   const int32_t nblk = ent::bf16x3_epilogue_blocks(n_pad);
   // Clenshaw (Algorithm 5): slots 0..m hold g^T y_k, slot m+1 holds g^T g
@@ -1052,8 +1051,7 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
     const int bn = s <= 64 ? 64 : (s <= 128 ? 128 : 256);
     const int64_t ldv = round_up(s, bn);
     const int64_t tiles = (n_pad / ent::bf16x3_tile_rows(n_pad)) * (ldv / bn);
-    int32_t splits = 1;
-    while (tiles * splits < 256 && splits < 16 && (n_pad / (2 * splits)) % 32 == 0) splits *= 2;
+    const int32_t splits = ent::bf16x3_splits(n_pad, tiles);
     uint16_t *Ahi = nullptr, *Alo = nullptr, *Phi = nullptr, *Plo = nullptr;
     float *P = nullptr, *X = nullptr, *party = nullptr;
     cv.add(&Ahi, (size_t)n_pad * n_pad);

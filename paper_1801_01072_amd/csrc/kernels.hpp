@@ -215,6 +215,9 @@ hipError_t launch_probe_gen_t(float *G, uint16_t *hi, uint16_t *lo, int64_t n, i
                               uint32_t stream = 0, double scale = 1.0);
 // Rows of the GEMM's workgroup tile for a padded size (256 when it divides).
 int32_t bf16x3_tile_rows(int64_t n_pad);
+// K-splits of the GEMM for a grid of `tiles` output tiles (n_pad / splits is
+// a multiple of 32).
+int32_t bf16x3_splits(int64_t n_pad, int64_t tiles);
 hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st);
 // Power-method product on the fragment-major bf16 hi/lo split of R; x must
 // be zero in [n, n_pad).  power_blocks_split: the most partials it writes.

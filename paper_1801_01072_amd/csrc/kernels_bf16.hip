@@ -722,6 +722,28 @@ hipError_t launch_power_gemv_split(const uint16_t *hi, const uint16_t *lo, int64
 
 int32_t bf16x3_tile_rows(int64_t n_pad) { return n_pad % 256 == 0 ? 256 : 128; }
 
+// K-splits of the GEMM for `tiles` output tiles.  A workgroup fills a CU (its
+// LDS ring), so the grid runs in rounds of 256 workgroups and a split count
+// costs rounds(tiles * s) / s of a full-K tile's time; each split also adds
+// a partial block for the epilogue to read (weighted 1/64 per split).  Any s
+// up to 16 whose column range is a multiple of 32: n_pad = 8192 (32 tiles)
+// keeps 8 splits, 10240 (40 tiles) takes 5 (one round of 200) instead of 8
+// (320: a second round with 64 workgroups).
+int32_t bf16x3_splits(int64_t n_pad, int64_t tiles) {
+  int32_t best = 1;
+  double best_cost = 1e300;
+  for (int32_t sp = 1; sp <= 16; ++sp) {
+    if (n_pad % (32 * (int64_t)sp) != 0) continue;
+    const double rounds = (double)((tiles * sp + 255) / 256);
+    const double cost = rounds / sp + sp / 64.0;
+    if (cost < best_cost - 1e-12) {
+      best_cost = cost;
+      best = sp;
+    }
+  }
+  return best;
+}
+
 hipError_t launch_bf16x3_gemm(const Bf16GemmArgs &a, hipStream_t st) {
   const int bm = bf16x3_tile_rows(a.n_pad);
   const int nrt = (int)(a.n_pad / bm), nct = (int)(a.ldv / a.bn);
