@@ -41,7 +41,9 @@ extern "C" {
 
 typedef enum {
   ENT_OK = 0,
-  ENT_EINVAL = -1,       /* null pointer, size < 1, unknown enum, bad layout  */
+  ENT_EINVAL = -1,       /* null or inaccessible pointer, descriptor past its
+                            allocation, malformed CSR structure, size < 1,
+                            unknown enum, bad layout                         */
   ENT_ENOTDENSITY = -2,  /* |tr R - 1| above tolerance (see ent_options)      */
   ENT_ENOMEM = -3,       /* device allocation failed or workspace cap reached */
   ENT_EDEVICE = -4,      /* a HIP runtime call failed                          */
