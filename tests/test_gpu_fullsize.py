@@ -61,3 +61,30 @@ def test_csr_n1e7_f32(orc):
     assert err <= 1e-3
     assert res.p1_est == pytest.approx(ref.p1_est, rel=1e-10)
     assert res.std_err > 0 and np.all(np.isfinite(per))
+
+
+def test_batch_1024_matrices_f32(orc):
+    # 1024 dense density matrices, n ~ U[64, 2048], rank k ~ U[n/8, n],
+    # Dirichlet spectra, Chebyshev m = 40, s = 64 Rademacher probes, t = 20,
+    # FP32, one captured graph with the tile autotuner: four matrices spread
+    # over the sizes against the oracle (all probes), replays bit-identical
+    count, m, s, t = 1024, 40, 64, 20
+    mseed, pseed = W.MATRIX_SEED + 4, W.PROBE_SEED + 4
+    ns, ks = W.batch_shapes(count, mseed, 64, 2048)
+    spectra = W.batch_spectra(ns, ks, mseed)
+    mats = [W.dense_density_torch(p, mseed * 7 + i, device=DEV, dtype=torch.float32) for i, p in enumerate(spectra)]
+    torch.cuda.synchronize()
+    g = ent.Graph(mats, "chebyshev", m, s, pseed, precision="f32", probe_dist="rademacher", power_iters=t,
+                  flags=ent.FLAG_AUTOTUNE)
+    res = g.launch()
+    per = g.per_probe()
+    res2 = g.launch()
+    assert [r.entropy for r in res] == [r.entropy for r in res2]
+    assert np.all(np.isfinite(per))
+    idx = [int(i) for i in np.argsort(ns)[np.linspace(0, count - 1, 4).astype(int)]]
+    for b in idx:
+        Rh = mats[b].double().cpu().numpy()
+        ref = orc.estimate(Rh, 1, m, s, pseed + b, t=t, dist=0)
+        err = float(np.max(np.abs(per[b] - ref.per_probe)) / np.mean(np.abs(ref.per_probe)))
+        print(f"[batch 1024] matrix {b} (n = {ns[b]}): per-probe rel {err:.2e}", flush=True)
+        assert err <= 1e-3
