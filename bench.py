@@ -69,6 +69,7 @@ KERNEL_SOURCES = {
     "dense_step_kernel": "kernels_dense.hip",
     "batch_dense_step_kernel": "kernels_dense.hip",
     "csr_step_kernel": "kernels_csr.hip",
+    "band_step_kernel": "kernels_band.hip",
 }
 
 
@@ -130,6 +131,23 @@ def csr_step_bytes(n, nnz, s, m, vbytes, method):
         reads_vm1 = method == "chebyshev" and k > 1        # V_{k-1} for k = 1 is the sign block
         writes = method == "chebyshev" or k < steps - 1
         tot += csr + signs + blk * (reads_vk + reads_vm1 + writes)
+    return tot, steps
+
+
+def band_step_bytes(n, hp, s, m, vbytes, method):
+    """Algorithmic HBM bytes of the m product steps of the banded kernel: the
+    16-row slabs (16 + 2 hp values per row, zeros of the band included), the
+    probe sign bits and the V blocks each step must read and write once."""
+    slabs = ((n + 15) // 16) * 16 * (16 + 2 * hp) * vbytes
+    signs = n * s / 8
+    blk = n * s * vbytes
+    tot = 0.0
+    steps = m if method == "chebyshev" else m + 1
+    for k in range(steps):
+        reads_vk = k > 0
+        reads_vm1 = method == "chebyshev" and k > 1
+        writes = method == "chebyshev" or k < steps - 1
+        tot += slabs + signs + blk * (reads_vk + reads_vm1 + writes)
     return tot, steps
 
 
@@ -478,6 +496,8 @@ def main():
     ap.add_argument("--store", default=None, choices=["f64", "f32"])
     ap.add_argument("--cpu-probes", type=int, default=0, help="oracle sample size (0 = host threads)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--csr-general", action="store_true",
+                    help="CSR workloads: the general CSR step kernel even for banded R")
     ap.add_argument("--count", type=int, default=0, help="matrices in the learned4096 workload")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -544,6 +564,8 @@ def main():
     kw = dict(probe_dist=cfg["dist"], precision=precision, power_iters=t, u_factor=cfg.get("c", 6.0))
     if herm:
         kw["flags"] = ent.FLAG_COMPLEX_POWER
+    if getattr(args, "csr_general", False):
+        kw["flags"] = kw.get("flags", 0) | ent.FLAG_CSR_GENERAL
 
     for _ in range(args.warmup):
         ent.entropy_estimate(Rd, cfg["method"], m, s, pseed, **kw)
@@ -584,15 +606,22 @@ def main():
     else:
         nnz = int(Rd[0][-1]) if host_R is None else int(host_R[0][-1])
         vb = 8 if precision == "f64" else 4
-        tot_bytes, steps = csr_step_bytes(n, nnz, s, m, vb, cfg["method"])
+        hp = int(tms[-1]["csr_band"])
+        if hp > 0:
+            # banded input: the step ran on the 16-row slabs
+            kernel = "band_step_kernel"
+            tot_bytes, steps = band_step_bytes(n, hp, s, m, vb, cfg["method"])
+        else:
+            kernel = "csr_step_kernel"
+            tot_bytes, steps = csr_step_bytes(n, nnz, s, m, vb, cfg["method"])
         per_launch = tot_bytes / steps
         achieved = per_launch / (avg_step_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic("csr_step_kernel", args.workload + ("" if precision == "f32" else "_" + precision)),
-                "kernel": "csr_step_kernel",
+                "traffic": measured_traffic(kernel, args.workload + ("" if precision == "f32" else "_" + precision)),
+                "kernel": kernel, "band_half_width": hp,
                 "avg_launch_ms": avg_step_ms, "algorithmic_bytes_per_launch": per_launch}
-        log(f"csr_step_kernel: {avg_step_ms:.4f} ms/launch -> {achieved:.1f} GB/s")
+        log(f"{kernel}: {avg_step_ms:.4f} ms/launch -> {achieved:.1f} GB/s")
     log(f"phases (ms): {phases}")
 
     # accuracy of sampled probes and the CPU oracle baseline on the same estimate

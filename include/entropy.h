@@ -108,10 +108,15 @@ enum {
                                     the batch if no cached choice exists      */
   ENT_FLAG_COMPLEX_POWER = 4,    /* Hermitian R: u = min{1, c p~1} from the
                                     power method instead of the paper's u = 1 */
-  ENT_FLAG_CLENSHAW = 8          /* Chebyshev: evaluate g^T f_m(R) g by the
+  ENT_FLAG_CLENSHAW = 8,         /* Chebyshev: evaluate g^T f_m(R) g by the
                                     backward Clenshaw recurrence (Algorithm 5,
                                     Appendix B) instead of the forward three-
                                     term recurrence; see ent_entropy_estimate */
+  ENT_FLAG_CSR_GENERAL = 16      /* CSR R: run the general CSR step kernel even
+                                    when every entry lies within 16 of the
+                                    diagonal (such R otherwise runs the banded
+                                    step kernel on a per-estimate copy of R in
+                                    16-row slabs; same results within rounding) */
 };
 
 /*
@@ -305,7 +310,9 @@ typedef struct {
   int32_t step_launches;
   int32_t power_launches;
   int32_t epilogue_launches;
-  int32_t reserved;
+  int32_t csr_band;      /* CSR R: padded half-bandwidth (4, 8 or 16) of the
+                            banded step kernel that ran; 0: the general CSR
+                            kernel or a dense path                            */
 } ent_timing;
 
 ent_status ent_timing_enable(int32_t on);

@@ -39,6 +39,7 @@ FLAG_SKIP_TRACE_CHECK = 1
 FLAG_AUTOTUNE = 2
 FLAG_COMPLEX_POWER = 4
 FLAG_CLENSHAW = 8
+FLAG_CSR_GENERAL = 16
 
 _METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ, "auto": AUTO}
 _PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
@@ -76,7 +77,7 @@ class EntTiming(ctypes.Structure):
                 ("steps_ms", ctypes.c_double), ("step_max_ms", ctypes.c_double),
                 ("epilogue_ms", ctypes.c_double), ("other_ms", ctypes.c_double),
                 ("step_launches", ctypes.c_int32), ("power_launches", ctypes.c_int32),
-                ("epilogue_launches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("epilogue_launches", ctypes.c_int32), ("csr_band", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p

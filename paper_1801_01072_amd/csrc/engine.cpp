@@ -32,6 +32,7 @@ struct PhaseEvents {
   std::vector<hipEvent_t> ev;
   int power_begin = -1, power_end = -1, steps_begin = -1, steps_end = -1;
   int32_t power_launches = 0;
+  int32_t csr_band = 0;  // padded half-bandwidth of the banded CSR step (0: none)
   // split steps (product kernel + separate epilogue kernel): event index
   // pairs of the product launches and of the epilogue launches
   std::vector<std::pair<int, int>> main_spans, epi_spans;
@@ -79,6 +80,7 @@ struct PhaseEvents {
     }
     t.other_ms = t.total_ms - t.power_ms - t.steps_ms - t.epilogue_ms;
     t.power_launches = power_launches;
+    t.csr_band = csr_band;
     g_last_timing = t;
   }
 };
@@ -359,16 +361,24 @@ ent_status enqueue_power_split(const uint16_t *hi, const uint16_t *lo, int64_t n
 
 // Validate a CSR structure on the device before any kernel dereferences its
 // indices (one synchronisation).  Uses the first 256 bytes of the workspace.
-ent_status check_csr(const ent_matrix *R, void *scratch, hipStream_t st) {
+// With hbw non-null, also measures the half-bandwidth max |col - row| (after
+// the structure check, in the same synchronisation).
+ent_status check_csr(const ent_matrix *R, void *scratch, hipStream_t st, int32_t *hbw = nullptr) {
   if (R->layout != ENT_CSR) return ENT_OK;
   int32_t *flag = (int32_t *)scratch;
-  int32_t h = 0;
-  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+  int32_t h[2] = {0, 0};
+  HIP_TRY(hipMemsetAsync(flag, 0, 2 * sizeof(int32_t), st));
   HIP_TRY(ent::launch_validate_csr(R->row_ptr, R->col_idx, R->n, R->nnz, flag, st));
-  HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&h[0], flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (h) return fail(ENT_EINVAL, "invalid CSR structure (row_ptr must start at 0, be non-decreasing "
-                                 "and end at nnz; column indices must lie in [0, n))");
+  if (h[0]) return fail(ENT_EINVAL, "invalid CSR structure (row_ptr must start at 0, be non-decreasing "
+                                    "and end at nnz; column indices must lie in [0, n))");
+  if (hbw) {
+    HIP_TRY(ent::launch_csr_half_bandwidth(R->row_ptr, R->col_idx, R->n, flag + 1, st));
+    HIP_TRY(hipMemcpyAsync(&h[1], flag + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *hbw = h[1];
+  }
   return ENT_OK;
 }
 
@@ -409,7 +419,27 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   const int bn = dense ? (s <= 64 ? 64 : (s <= 128 ? 128 : 64)) : 64;
   const int64_t ldv = round_up(s, dense ? bn : 64);
   const int64_t n_pad = round_up(n, 64);
-  const int32_t ntile = dense ? (int32_t)(n_pad / 64) : ent::csr_step_blocks(n, sizeof(T) == 8);
+
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DeviceWorkspace *ws = workspace_for(dev);
+  std::lock_guard<std::mutex> lk(ws->mu);
+
+  // CSR: validate the structure, and serve a matrix whose entries all lie
+  // within 16 of the diagonal with the banded step kernel
+  int32_t hp = 0;
+  if (!dense) {
+    ent_status rc0 = ensure_workspace(ws, 256);
+    if (rc0 != ENT_OK) return rc0;
+    int32_t hbw = 0;
+    rc0 = check_csr(R, ws->ptr, st, (o.flags & ENT_FLAG_CSR_GENERAL) ? nullptr : &hbw);
+    if (rc0 != ENT_OK) return rc0;
+    if (!(o.flags & ENT_FLAG_CSR_GENERAL)) hp = ent::band_half_width_padded(hbw);
+  }
+  const bool banded = hp > 0;
+  const int32_t ntile = dense ? (int32_t)(n_pad / 64)
+                              : (banded ? ent::band_step_waves(n, hp, sizeof(T) == 8)
+                                        : ent::csr_step_blocks(n, sizeof(T) == 8));
   // dense steps whose tile grid is smaller than the chip split K
   const int32_t ksplit = dense ? ent::dense_step_splits(n, ntile, ldv, bn) : 1;
   const int64_t kper = round_up((n + ksplit - 1) / ksplit, 32);
@@ -423,20 +453,16 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   const bool use_power = !(o.u_fixed > 0);
   const int32_t pblk = (int32_t)power_blocks(R);
 
-  int dev = 0;
-  HIP_TRY(hipGetDevice(&dev));
-  DeviceWorkspace *ws = workspace_for(dev);
-  std::lock_guard<std::mutex> lk(ws->mu);
-
   double *scal = nullptr, *x0 = nullptr, *x1 = nullptr, *p0 = nullptr, *p1 = nullptr;
   double *part = nullptr, *d = nullptr, *h = nullptr;
-  T *Rc = nullptr, *G = nullptr, *VA = nullptr, *VB = nullptr;
+  T *Rc = nullptr, *G = nullptr, *VA = nullptr, *VB = nullptr, *band = nullptr;
   uint32_t *signs = nullptr;
   int2 *cwin = nullptr;
   const int32_t ch = ent::csr_chunk_rows(sizeof(T) == 8);
   Carve cv;
   cv.add(&scal, kScalarDoubles);
-  if (!dense) cv.add(&cwin, (size_t)((n + ch - 1) / ch));
+  if (!dense && !banded) cv.add(&cwin, (size_t)((n + ch - 1) / ch));
+  if (banded) cv.add(&band, ent::band_pack_elems(n, hp));
   if (use_power) {
     cv.add(&x0, n_pad);
     cv.add(&x1, n_pad);
@@ -457,12 +483,11 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   ent_status rc = ensure_workspace(ws, cv.total());
   if (rc != ENT_OK) return rc;
   cv.assign(ws->ptr);
-  rc = check_csr(R, scal, st);
-  if (rc != ENT_OK) return rc;
 
   PhaseEvents pe;
   pe.on = g_timing_on;
   pe.st = st;
+  pe.csr_band = hp;
   pe.mark();
   HIP_TRY(hipMemsetAsync(scal, 0, sizeof(double) * 64, st));
   // CSR step launches may use fewer workgroups than the partial stride
@@ -495,7 +520,10 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     Rt = Rc;
     ldr = ldc;
   }
-  if (!dense) HIP_TRY(ent::launch_csr_chunk_window(R->row_ptr, R->col_idx, n, ch, cwin, st));
+  if (banded)
+    HIP_TRY(ent::launch_band_pack<T>(R->row_ptr, R->col_idx, (const T *)R->values, n, hp, band, st));
+  else if (!dense)
+    HIP_TRY(ent::launch_csr_chunk_window(R->row_ptr, R->col_idx, n, ch, cwin, st));
   // probes
   if (dense || !rad)
     HIP_TRY(ent::launch_probe_gen<T>(G, nullptr, op.probe_rows > 0 ? op.probe_rows : n, n_pad, s, ldv,
@@ -539,6 +567,15 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         a.cg = scal + ent::S_ALPHA + kk;
         a.ksplit = ksplit; a.kper = kper; a.party = party; a.nptile = npart;
         HIP_TRY(ent::launch_dense_step<T>(a, st));
+      } else if (banded) {
+        ent::BandStepArgs a{};
+        a.band = band; a.n = n; a.ldv = ldv;
+        a.Vk = Vk; a.Vkm1 = k == 0 ? nullptr : Vkm1; a.Vkp1 = Vout;
+        a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
+        a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
+        a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.nwave = ntile;
+        a.cg = scal + ent::S_ALPHA + kk;
+        HIP_TRY(ent::launch_band_step<T>(a, hp, st));
       } else {
         ent::CsrStepArgs a{};
         a.row_ptr = R->row_ptr; a.col_idx = R->col_idx; a.values = R->values; a.n = n; a.ldv = ldv;
@@ -582,6 +619,14 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
       a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.ntile = ntile; a.bn = bn;
       a.ksplit = ksplit; a.kper = kper; a.party = party; a.nptile = npart;
       HIP_TRY(ent::launch_dense_step<T>(a, st));
+    } else if (banded) {
+      ent::BandStepArgs a{};
+      a.band = band; a.n = n; a.ldv = ldv;
+      a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr;
+      a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
+      a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
+      a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nwave = ntile;
+      HIP_TRY(ent::launch_band_step<T>(a, hp, st));
     } else {
       ent::CsrStepArgs a{};
       a.row_ptr = R->row_ptr; a.col_idx = R->col_idx; a.values = R->values; a.n = n; a.ldv = ldv;

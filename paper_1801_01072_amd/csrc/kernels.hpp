@@ -178,6 +178,40 @@ hipError_t launch_csr_chunk_window(const int64_t *rp, const int32_t *ci, int64_t
                                    int2 *win, hipStream_t st);
 
 
+// ---- banded CSR (every entry within HP of the diagonal) -----------------------
+// Half-bandwidth max |col - row| of a validated CSR matrix into out[0] (which
+// must start at 0); the padded half-bandwidth (4, 8 or 16) the banded step
+// serves it with, or 0 if it is wider.
+hipError_t launch_csr_half_bandwidth(const int64_t *rp, const int32_t *ci, int64_t n, int32_t *out,
+                                     hipStream_t st);
+int32_t band_half_width_padded(int32_t hbw);
+// Elements of the 16-row slab storage, and the slabs from the CSR arrays.
+size_t band_pack_elems(int64_t n, int32_t hp);
+template <typename T>
+hipError_t launch_band_pack(const int64_t *rp, const int32_t *ci, const T *val, int64_t n, int32_t hp,
+                            T *band, hipStream_t st);
+struct BandStepArgs {
+  const void *band;    // slabs (launch_band_pack), element type T
+  int64_t n;
+  int64_t ldv;         // padded probe count (multiple of 64)
+  const void *Vk;      // null: V_k is the sign block (first step)
+  const void *Vkm1;    // null: V_{k-1} is the sign block (if cw != 0)
+  void *Vkp1;          // null: no write (last Taylor step)
+  const uint32_t *signs;  // Rademacher sign bits [n_pad][ldv/32] (null: Gaussian)
+  const void *G;          // Gaussian probe block (null: Rademacher)
+  const double *scal;
+  double c1, c2, cw;
+  int32_t dot_y;
+  int32_t slot;
+  int32_t slot_gg;
+  double *part;        // partials [slot][wave][ldv]
+  int32_t nwave;       // waves of the grid (partial stride), from band_step_waves
+  const double *cg;    // device scalar: z += (*cg) g (Clenshaw's alpha_k term); null: none
+};
+int32_t band_step_waves(int64_t n, int32_t hp, int32_t fp64);
+template <typename T>
+hipError_t launch_band_step(const BandStepArgs &a, int32_t hp, hipStream_t st);
+
 // ---- BF16x3 dense path (probe-major blocks, leading dimension n_pad) ----------
 struct Bf16GemmArgs {
   const uint16_t *A_hi, *A_lo;  // n_pad x n_pad, row-major, bf16 bits

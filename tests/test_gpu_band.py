@@ -1,0 +1,154 @@
+"""GPU parity of the banded CSR step (a CSR R whose entries all lie within 16
+of the diagonal runs as 16-row MFMA slabs): which kernel ran, per-probe
+values against the FP64 oracle for every padded band width, precision,
+schedule and probe distribution, ragged sizes, duplicate entries, and
+agreement with the general CSR kernel on the same input."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1801_01072_amd as ent  # noqa: E402
+
+DEV = "cuda:0"
+TOL64 = 1e-10
+TOL32 = 1e-3
+
+
+def csr_to_dev(csr):
+    rp, ci, val, n = csr
+    return (torch.from_numpy(rp).to(DEV), torch.from_numpy(ci).to(DEV), torch.from_numpy(val).to(DEV), n)
+
+
+def run(csr, method, m, s, seed, **kw):
+    ent.timing_enable(True)
+    try:
+        res, per, mom = ent.entropy_estimate_detail(csr_to_dev(csr), method, m, s, seed, **kw)
+        band = ent.last_timing()["csr_band"]
+    finally:
+        ent.timing_enable(False)
+    return res, per, mom, band
+
+
+def per_probe_rel(per, ref):
+    return float(np.max(np.abs(per - ref.per_probe)) / max(np.mean(np.abs(ref.per_probe)), 1e-2))
+
+
+# half-bandwidth of B -> of R = B B^T (2 hb), and the padded width served
+@pytest.mark.parametrize("hb,hp", [(1, 4), (2, 4), (3, 8), (4, 8), (5, 16), (8, 16)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_band_widths(orc, hb, hp, dtype):
+    n, m, s, seed = 5003, 20, 64, 41 + hb
+    csr = W.banded_density_csr(n, hb, seed=100 + hb, dtype=dtype)
+    prec = "f64" if dtype == np.float64 else "f32"
+    res, per, _, band = run(csr, "chebyshev", m, s, seed, precision=prec)
+    ref = orc.estimate(csr, 1, m, s, seed)
+    err = per_probe_rel(per, ref)
+    print(f"[band hb={hb} {prec}] kernel band {band}; H gpu={res.entropy:.12f} oracle={ref.entropy:.12f} "
+          f"per-probe rel {err:.2e}", flush=True)
+    assert band == hp
+    assert err <= (TOL64 if dtype == np.float64 else TOL32)
+    if dtype == np.float64:
+        assert abs(res.entropy - ref.entropy) <= TOL64 * abs(ref.entropy)
+
+
+@pytest.mark.parametrize("method,flags", [("chebyshev", 0), ("taylor", 0), ("chebyshev", ent.FLAG_CLENSHAW)])
+@pytest.mark.parametrize("dist", ["rademacher", "gaussian"])
+def test_band_schedules_and_probes(orc, method, flags, dist):
+    n, m, s, seed = 20_000, 30, 96, 17
+    csr = W.banded_density_csr(n, 8, seed=7)
+    d = 0 if dist == "rademacher" else 1
+    res, per, mom, band = run(csr, method, m, s, seed, probe_dist=dist, flags=flags)
+    ref = orc.estimate(csr, 0 if method == "taylor" else 1, m, s, seed, dist=d)
+    err = per_probe_rel(per, ref)
+    print(f"[band {method} flags={flags} {dist}] H gpu={res.entropy:.14f} oracle={ref.entropy:.14f} "
+          f"per-probe rel {err:.2e}", flush=True)
+    assert band == 16
+    assert err <= TOL64
+    assert res.std_err == pytest.approx(ref.std_err, rel=1e-8)
+    if method == "chebyshev" and not flags:
+        for j in (0, s // 2, s - 1):
+            g = orc.probe_vector(seed, d, 0, n, j)
+            dref = orc.cheb_moments_forward(csr, 0.0, ref.u, m, g)
+            assert np.max(np.abs(mom[:, j] - dref)) <= TOL64 * float(g @ g)
+
+
+@pytest.mark.parametrize("n,s", [(1, 1), (5, 3), (16, 64), (17, 65), (1000, 50), (4111, 130)])
+def test_band_ragged(orc, n, s):
+    # n below one 16-row block, exactly one, one plus a row; probe counts
+    # below, at and above one 64-probe chunk
+    csr = W.banded_density_csr(n, 4, seed=n + 3)
+    m, seed = 11, 5
+    res, per, _, band = run(csr, "chebyshev", m, s, seed)
+    ref = orc.estimate(csr, 1, m, s, seed)
+    err = per_probe_rel(per, ref)
+    print(f"[band ragged n={n} s={s}] kernel band {band}; per-probe rel {err:.2e}", flush=True)
+    assert band == (4 if n <= 5 else 8)
+    assert err <= TOL64
+
+
+def test_band_duplicates_and_empty_rows(orc):
+    # duplicate (row, col) entries are summed; a zero row contributes nothing
+    n, m, s, seed = 3000, 15, 64, 9
+    rp, ci, val, _ = W.banded_density_csr(n, 2, seed=11)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    # split every diagonal entry into two halves stored twice
+    diag = ci == rows
+    val2 = np.concatenate([np.where(diag, val / 2, val), val[diag] / 2])
+    ci2 = np.concatenate([ci, ci[diag]])
+    rows2 = np.concatenate([rows, rows[diag]])
+    order = np.argsort(rows2, kind="stable")
+    ci2, val2, rows2 = ci2[order], val2[order], rows2[order]
+    rp2 = np.zeros(n + 1, np.int64)
+    np.add.at(rp2, rows2 + 1, 1)
+    rp2 = np.cumsum(rp2)
+    dup = (rp2, ci2.astype(np.int32), val2, n)
+    res, per, _, band = run(dup, "chebyshev", m, s, seed)
+    ref = orc.estimate((rp, ci, val, n), 1, m, s, seed)
+    assert band == 4
+    assert per_probe_rel(per, ref) <= TOL64
+    # a matrix with empty rows (rank deficient, still unit trace)
+    keep = (rows % 7) != 3
+    ce = ((ci % 7) != 3) & keep
+    rp3 = np.zeros(n + 1, np.int64)
+    np.add.at(rp3, rows[ce] + 1, 1)
+    rp3 = np.cumsum(rp3)
+    v3 = val[ce] / val[ce][ci[ce] == rows[ce]].sum()
+    z = (rp3, ci[ce].astype(np.int32), v3, n)
+    res, per, _, band = run(z, "chebyshev", m, s, seed)
+    ref = orc.estimate(z, 1, m, s, seed)
+    assert band == 4
+    assert per_probe_rel(per, ref) <= TOL64
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_band_matches_general_kernel(orc, dtype):
+    n, m, s, seed = 30_000, 25, 64, 23
+    csr = W.banded_density_csr(n, 8, seed=29, dtype=dtype)
+    prec = "f64" if dtype == np.float64 else "f32"
+    a = run(csr, "chebyshev", m, s, seed, precision=prec)
+    b = run(csr, "chebyshev", m, s, seed, precision=prec, flags=ent.FLAG_CSR_GENERAL)
+    assert a[3] == 16 and b[3] == 0
+    tol = TOL64 if dtype == np.float64 else 1e-4
+    rel = float(np.max(np.abs(a[1] - b[1])) / np.mean(np.abs(b[1])))
+    print(f"[band vs general {prec}] per-probe rel {rel:.2e}", flush=True)
+    assert rel <= tol
+    # repeated runs are bit-identical
+    c = run(csr, "chebyshev", m, s, seed, precision=prec)
+    assert np.array_equal(a[1], c[1])
+
+
+def test_wider_band_runs_general_kernel(orc):
+    # half-bandwidth 18 (> 16): the general CSR kernel
+    n, m, s, seed = 4000, 12, 64, 3
+    csr = W.banded_density_csr(n, 9, seed=31)
+    res, per, _, band = run(csr, "chebyshev", m, s, seed)
+    ref = orc.estimate(csr, 1, m, s, seed)
+    assert band == 0
+    assert per_probe_rel(per, ref) <= TOL64
