@@ -314,7 +314,7 @@ ent_status validate_options(const ent_options &o) {
 template <typename T>
 ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t t, int32_t q,
                          uint64_t seed, double *x0, double *x1, double *part3, double *norm,
-                         double *scal, hipStream_t st) {
+                         double *scal, hipStream_t st, const T *band = nullptr, int32_t hp = 0) {
   const int64_t n = R->n;
   for (int32_t trial = 0; trial < q; ++trial) {
     HIP_TRY(ent::launch_power_start(x0, n, seed, trial, st));
@@ -322,9 +322,13 @@ ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t 
     const double *in_norm = nullptr;
     for (int32_t it = 0; it <= t; ++it) {  // t iterations + the Rayleigh product
       int32_t nblk = 0;
-      if (R->layout == ENT_DENSE)
+      if (R->layout == ENT_DENSE) {
         HIP_TRY(ent::launch_power_gemv<T>(Rc, ldr, n, xin, in_norm, xout, part3, &nblk, st));
-      else
+      } else if (band) {
+        // banded CSR: the same product on the slabs of the step kernel
+        nblk = ent::power_blocks_csr(n);
+        HIP_TRY(ent::launch_power_band<T>(band, hp, n, xin, in_norm, xout, part3, nblk, st));
+      } else
         HIP_TRY(ent::launch_power_spmv<T>(R->row_ptr, R->col_idx, (const T *)R->values, n, R->nnz,
                                           xin, in_norm, xout, part3, &nblk, st));
       HIP_TRY(ent::launch_power_reduce(part3, nblk, norm, st));
@@ -533,7 +537,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   // power method and interval
   if (use_power) {
     pe.power_begin = pe.mark();
-    rc = enqueue_power<T>(R, Rt, ldr, o.power_iters, o.power_trials, seed, x0, x1, p0, p1, scal, st);
+    rc = enqueue_power<T>(R, Rt, ldr, o.power_iters, o.power_trials, seed, x0, x1, p0, p1, scal, st, band, hp);
     if (rc != ENT_OK) return rc;
     pe.power_end = pe.mark();
     pe.power_launches = o.power_trials * (o.power_iters + 1);

@@ -209,6 +209,11 @@ struct BandStepArgs {
   const double *cg;    // device scalar: z += (*cg) g (Clenshaw's alpha_k term); null: none
 };
 int32_t band_step_waves(int64_t n, int32_t hp, int32_t fp64);
+// Power-method product on the slabs: the contract of launch_power_spmv, with
+// nblk workgroups (nblk triples written; power_blocks_csr(n) of them).
+template <typename T>
+hipError_t launch_power_band(const T *band, int32_t hp, int64_t n, const double *x, const double *in_norm,
+                             double *y, double *part3, int32_t nblk, hipStream_t st);
 template <typename T>
 hipError_t launch_band_step(const BandStepArgs &a, int32_t hp, hipStream_t st);
 

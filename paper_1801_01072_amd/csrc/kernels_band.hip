@@ -16,14 +16,15 @@
 //
 // Step: a wave owns a contiguous range of blocks and one 64-probe chunk.  The
 // V_k rows a block needs (K rows) sit in registers as K/4 B-operand fragments
-// of four rows each, a ring of KS + 4 fragments: while block b multiplies,
-// the four fragments that block b+1 adds (and its slab values) are already
-// in flight, so each V_k row is read from HBM once per wave range (plus a
-// halo of HP rows at each end).  Probe p of the chunk is column p/4 of
+// of four rows each, a window of KS + 4 fragments slid by one block after
+// each product: while block b multiplies, the four fragments that block b+1
+// adds (and its slab values) are already in flight, so each V_k row is read
+// from HBM once per wave range (plus a halo of HP rows at each end).  Probe p of the chunk is column p/4 of
 // 16-probe tile p%4, so a lane's four tiles are four consecutive probes of
-// one row: every V access (ring fragments, epilogue operands, results) is a
-// 16-byte (FP32) or 32-byte (FP64) piece per lane, four whole 256 B rows per
-// instruction.  There is no LDS and no barrier; per-probe dot partials stay
+// one row: every V access (window fragments, epilogue operands, results) is
+// a 16-byte (FP32) or 32-byte (FP64) piece per lane, four whole 256 B rows per
+// instruction.  The epilogue's V_k rows are taken from the window, not read
+// again.  There is no LDS and no barrier; per-probe dot partials stay
 // in FP64 registers until the end (one partial per wave per probe, summed in
 // fixed order).
 #include "device_common.hpp"
@@ -61,41 +62,74 @@ size_t band_pack_elems(int64_t n, int32_t hp) {
 }
 
 // ---------------------------------------------------------------------------
+// Row of entry e among the 16 rows r0 .. r0+15 whose row pointers are bnd[0..16]
+// (wave-uniform): the number of row starts after r0 at or before e.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int row_in_block(int64_t e, const int64_t *bnd) {
+  int i = 0;
+#pragma unroll
+  for (int k = 1; k < 16; ++k) i += e >= bnd[k] ? 1 : 0;
+  return i;
+}
+
+// The row pointers rp[r0 .. r0+16] (clamped at n) of one 16-row block, as
+// wave-uniform values.
+__device__ __forceinline__ void block_bounds(const int64_t *__restrict__ rp, int64_t r0, int64_t n, int lane,
+                                             int64_t *bnd) {
+  const int64_t r = r0 + (lane < 16 ? lane : 16);
+  const int64_t v = rp[r < n ? r : n];
+#pragma unroll
+  for (int k = 0; k <= 16; ++k) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v & 0xffffffffu), k);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), k);
+    bnd[k] = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Half-bandwidth of a (validated) CSR matrix: out[0] = max |col - row|
-// (out[0] must start at 0).  One thread per row.
+// (out[0] must start at 0).  One wave per 16-row block, grid-stride: the
+// block's entries are read contiguously, and an entry's row is found from
+// the block's row pointers.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void csr_half_bandwidth_kernel(const int64_t *__restrict__ rp,
                                                                  const int32_t *__restrict__ ci,
                                                                  int64_t n, int32_t *__restrict__ out) {
-  int32_t m = 0;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e1 = rp[r + 1];
-    for (int64_t e = rp[r]; e < e1; ++e) {
-      const int64_t d = (int64_t)ci[e] - r;
+  const int lane = threadIdx.x & 63;
+  const int64_t nb = (n + 15) / 16;
+  int64_t m = 0;
+  for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nb; b += (int64_t)gridDim.x * 4) {
+    int64_t bnd[17];
+    block_bounds(rp, 16 * b, n, lane, bnd);
+    for (int64_t e = bnd[0] + lane; e < bnd[16]; e += 64) {
+      const int64_t d = (int64_t)ci[e] - (16 * b + row_in_block(e, bnd));
       const int64_t ad = d < 0 ? -d : d;
-      const int32_t a32 = ad > 0x7fffffff ? 0x7fffffff : (int32_t)ad;
-      m = a32 > m ? a32 : m;
+      m = ad > m ? ad : m;
     }
   }
+  int32_t m32 = m > 0x7fffffff ? 0x7fffffff : (int32_t)m;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
-    const int32_t o = __shfl_xor(m, off, 64);
-    m = o > m ? o : m;
+    const int32_t o = __shfl_xor(m32, off, 64);
+    m32 = o > m32 ? o : m32;
   }
-  if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(out, m);
+  if (lane == 0 && m32 > 0) atomicMax(out, m32);
 }
 
 hipError_t launch_csr_half_bandwidth(const int64_t *rp, const int32_t *ci, int64_t n, int32_t *out,
                                      hipStream_t st) {
-  const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  const int64_t nb = (n + 15) / 16;
+  const int64_t blocks = (nb + 3) / 4 < 4096 ? (nb + 3) / 4 : 4096;
   csr_half_bandwidth_kernel<<<(unsigned)(blocks > 0 ? blocks : 1), 256, 0, st>>>(rp, ci, n, out);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Packing: one thread per (block b, lane l) writes that lane's KS slab values.
-// Requires |col - row| <= HP for every entry; duplicate entries are summed
-// in entry order.
+// Packing: one wave per 16-row block.  The block's entries are copied into
+// LDS with contiguous loads (when they fit), then lane l gathers the KS slab
+// values of row l%16 and k-slot l/16 by walking that row's entries in order
+// (duplicate entries are summed in entry order).  Requires |col - row| <= HP
+// for every entry.
 // ---------------------------------------------------------------------------
 template <typename T, int KS>
 __global__ __launch_bounds__(256) void band_pack_kernel(const int64_t *__restrict__ rp,
@@ -103,13 +137,29 @@ __global__ __launch_bounds__(256) void band_pack_kernel(const int64_t *__restric
                                                         const T *__restrict__ val, int64_t n,
                                                         T *__restrict__ band) {
   constexpr int HP = BandShape<KS>::HP;
+  constexpr int CAP = 1024;  // entries of a block staged in LDS
+  __shared__ int32_t scol[4][CAP];
+  __shared__ T sval[4][CAP];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, q = l >> 4;
   const int64_t nb = (n + 15) / 16;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t b = idx >> 6;
-  if (b >= nb) return;
-  const int l = (int)(idx & 63);
-  const int q = l >> 4;
-  const int64_t row = 16 * b + (l & 15);
+  const int64_t b = (int64_t)blockIdx.x * 4 + w;
+  const bool live = b < nb;
+  int64_t bnd[17];
+  bool staged = false;
+  if (live) {
+    block_bounds(rp, 16 * b, n, l, bnd);
+    staged = bnd[16] - bnd[0] <= CAP;
+    if (staged) {
+      for (int64_t e = bnd[0] + l; e < bnd[16]; e += 64) {
+        scol[w][e - bnd[0]] = ci[e];
+        sval[w][e - bnd[0]] = val[e];
+      }
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+  const int i = l & 15;
+  const int64_t row = 16 * b + i;
   const int64_t base = 16 * b - HP;
   T out[KS];
 #pragma unroll
@@ -117,16 +167,17 @@ __global__ __launch_bounds__(256) void band_pack_kernel(const int64_t *__restric
   if (row < n) {
     const int64_t e1 = rp[row + 1];
     for (int64_t e = rp[row]; e < e1; ++e) {
-      const int64_t j = (int64_t)ci[e] - base - q;  // slab column minus this lane's k-slot
+      const int32_t col = staged ? scol[w][e - bnd[0]] : ci[e];
+      const int64_t j = (int64_t)col - base - q;  // slab column minus this lane's k-slot
       if (j < 0 || (j & 3) != 0) continue;
       const int64_t kk = j >> 2;
-      const T v = val[e];
+      const T v = staged ? sval[w][e - bnd[0]] : val[e];
 #pragma unroll
       for (int k = 0; k < KS; ++k)
         if (k == kk) out[k] += v;
     }
   }
-  T *dst = band + idx * KS;
+  T *dst = band + (64 * b + l) * KS;
 #pragma unroll
   for (int k = 0; k < KS; ++k) dst[k] = out[k];
 }
@@ -134,8 +185,8 @@ __global__ __launch_bounds__(256) void band_pack_kernel(const int64_t *__restric
 template <typename T>
 hipError_t launch_band_pack(const int64_t *rp, const int32_t *ci, const T *val, int64_t n, int32_t hp,
                             T *band, hipStream_t st) {
-  const int64_t threads = ((n + 15) / 16) * 64;
-  const unsigned blocks = (unsigned)((threads + 255) / 256);
+  const int64_t nb = (n + 15) / 16;
+  const unsigned blocks = (unsigned)((nb + 3) / 4);
   switch (hp) {
     case 4: band_pack_kernel<T, 6><<<blocks, 256, 0, st>>>(rp, ci, val, n, band); break;
     case 8: band_pack_kernel<T, 8><<<blocks, 256, 0, st>>>(rp, ci, val, n, band); break;
@@ -197,6 +248,44 @@ __device__ __forceinline__ void vk_piece(const T *__restrict__ Vk, const uint32_
   for (int t = 0; t < 4; ++t) x[t] = in ? x[t] : T(0);
 }
 
+// The block's own V_k rows 16b .. 16b+15 in the MFMA result order, from the
+// four window fragments that hold them (fragment j: row 16b + 4j + q at lane
+// group q).  FP64 results hold row q + 4r in register r at lane group q: the
+// fragments themselves.  FP32 results hold row 4q + r: a transpose of
+// (fragment, lane group), done in registers by two rounds of lane-group
+// swaps (32-lane halves between fragments j and j+2, then 16-lane rows
+// between fragments 2i and 2i+1).
+template <typename T>
+__device__ __forceinline__ void own_rows(const T *f0, const T *f1, const T *f2, const T *f3, T (*x)[4]) {
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      x[0][t] = f0[t];
+      x[1][t] = f1[t];
+      x[2][t] = f2[t];
+      x[3][t] = f3[t];
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      uint32_t m0 = __float_as_uint(f0[t]), m1 = __float_as_uint(f1[t]);
+      uint32_t m2 = __float_as_uint(f2[t]), m3 = __float_as_uint(f3[t]);
+      const auto a02 = __builtin_amdgcn_permlane32_swap(m0, m2, false, false);
+      const auto a13 = __builtin_amdgcn_permlane32_swap(m1, m3, false, false);
+      m0 = a02[0];
+      m2 = a02[1];
+      m1 = a13[0];
+      m3 = a13[1];
+      const auto b01 = __builtin_amdgcn_permlane16_swap(m0, m1, false, false);
+      const auto b23 = __builtin_amdgcn_permlane16_swap(m2, m3, false, false);
+      x[0][t] = __uint_as_float(b01[0]);
+      x[1][t] = __uint_as_float(b01[1]);
+      x[2][t] = __uint_as_float(b23[0]);
+      x[3][t] = __uint_as_float(b23[1]);
+    }
+  }
+}
+
 // The lane's KS slab values of block b.
 template <typename T, int KS>
 __device__ __forceinline__ void load_slab(const T *__restrict__ band, int64_t b, int lane, T *a) {
@@ -209,6 +298,66 @@ __device__ __forceinline__ void load_slab(const T *__restrict__ band, int64_t b,
     a[k + 1] = v[1];
   }
 }
+
+// ---------------------------------------------------------------------------
+// Power-method product on the slabs (Algorithm 4): y = (R x) / ||x_prev||
+// in FP64, and the block triples (sums of y^2, xs.y, xs^2 with
+// xs = x / ||x_prev||) of the CSR product.  A workgroup takes four slab
+// blocks (64 rows) per pass, grid-stride; lane l of a block's wave forms
+// the partial sum of its k-slot over the KS k-steps of row l%16, and the
+// four k-slots are added in fixed order.
+// ---------------------------------------------------------------------------
+template <typename T, int KS>
+__global__ __launch_bounds__(256) void power_band_kernel(const T *__restrict__ band, int64_t n,
+                                                         const double *__restrict__ x,
+                                                         const double *__restrict__ in_norm,
+                                                         double *__restrict__ y, double *__restrict__ part3) {
+  constexpr int HP = BandShape<KS>::HP;
+  const double sc = in_norm ? 1.0 / sqrt(in_norm[0]) : 1.0;
+  const int lane = threadIdx.x & 63, q = lane >> 4;
+  const int64_t nb = (n + 15) / 16;
+  double yy = 0.0, xy = 0.0, xx = 0.0;
+  for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nb; b += (int64_t)gridDim.x * 4) {
+    T a[KS];
+    load_slab<T, KS>(band, b, lane, a);
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int64_t col = 16 * b - HP + 4 * k + q;
+      const double xv = (col >= 0 && col < n) ? x[col] : 0.0;
+      acc += (double)a[k] * xv;
+    }
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    const int64_t row = 16 * b + (lane & 15);
+    if (q == 0 && row < n) {
+      const double yv = sc * acc;
+      const double xs = sc * x[row];
+      y[row] = yv;
+      yy += yv * yv;
+      xy += xs * yv;
+      xx += xs * xs;
+    }
+  }
+  block_power_partials(yy, xy, xx, part3, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_power_band(const T *band, int32_t hp, int64_t n, const double *x, const double *in_norm,
+                             double *y, double *part3, int32_t nblk, hipStream_t st) {
+  if (nblk < 1) return hipErrorInvalidValue;
+  switch (hp) {
+    case 4: power_band_kernel<T, 6><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, in_norm, y, part3); break;
+    case 8: power_band_kernel<T, 8><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, in_norm, y, part3); break;
+    case 16: power_band_kernel<T, 12><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, in_norm, y, part3); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_power_band<float>(const float *, int32_t, int64_t, const double *, const double *,
+                                             double *, double *, int32_t, hipStream_t);
+template hipError_t launch_power_band<double>(const double *, int32_t, int64_t, const double *, const double *,
+                                              double *, double *, int32_t, hipStream_t);
 
 template <typename T, int KS>
 __global__ __launch_bounds__(64 * kBandWaves) void band_step_kernel(BandStepArgs a) {
@@ -267,12 +416,13 @@ __global__ __launch_bounds__(64 * kBandWaves) void band_step_kernel(BandStepArgs
           vk_piece<T>(Vk, signs, vk_signs, 4 * (fn + j) + q, n, ldv, nw, chunk0, c, win[KS + j]);
         load_slab<T, KS>(band, b + 1, lane, an);
       }
-      // epilogue operands of this block's rows (register r holds row drow(q, r))
+      // epilogue operands of this block's rows (register r holds row drow(q, r));
+      // the V_k rows come from the window (fragments HP/4 .. HP/4+3)
       T xr[4][4], vm[4][4], gv[4][4];
+      own_rows<T>(win[HP / 4], win[HP / 4 + 1], win[HP / 4 + 2], win[HP / 4 + 3], xr);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = 16 * b + M::drow(q, r);
-        vk_piece<T>(Vk, signs, vk_signs, row, n, ldv, nw, chunk0, c, xr[r]);
         if (m1 == 1)
           load4<T>(Vkm1, row, ldv, chunk0, c, vm[r]);
         else if (m1 == 2)
