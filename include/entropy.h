@@ -112,11 +112,17 @@ enum {
                                     backward Clenshaw recurrence (Algorithm 5,
                                     Appendix B) instead of the forward three-
                                     term recurrence; see ent_entropy_estimate */
-  ENT_FLAG_CSR_GENERAL = 16      /* CSR R: run the general CSR step kernel even
-                                    when every entry lies within 16 of the
-                                    diagonal (such R otherwise runs the banded
-                                    step kernel on a per-estimate copy of R in
-                                    16-row slabs; same results within rounding) */
+  ENT_FLAG_CSR_GENERAL = 16,     /* CSR R: always the general CSR kernels.  By
+                                    default an R whose entries all lie within
+                                    16 of the diagonal runs the banded kernels
+                                    (steps and power method) on a per-estimate
+                                    copy of R in 16-row slabs of 16 + 2 hp
+                                    values per row (hp = 4, 8 or 16, the half-
+                                    bandwidth rounded up) when that copy has no
+                                    more bytes per row than the CSR arrays;
+                                    same results within rounding             */
+  ENT_FLAG_CSR_BANDED = 32       /* CSR R within 16 of the diagonal: the banded
+                                    kernels whatever the byte counts          */
 };
 
 /*

@@ -40,6 +40,7 @@ FLAG_AUTOTUNE = 2
 FLAG_COMPLEX_POWER = 4
 FLAG_CLENSHAW = 8
 FLAG_CSR_GENERAL = 16
+FLAG_CSR_BANDED = 32
 
 _METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ, "auto": AUTO}
 _PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}

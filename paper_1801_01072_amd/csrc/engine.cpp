@@ -435,10 +435,17 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   if (!dense) {
     ent_status rc0 = ensure_workspace(ws, 256);
     if (rc0 != ENT_OK) return rc0;
+    // the step streams the matrix once per product: take the slabs (16 + 2 hp
+    // values per row) only if they are no larger than the CSR arrays (values,
+    // column indices, row pointers), unless the caller asks for them
+    const double csr_row = ((double)(sizeof(T) + 4) * (double)R->nnz + 8.0 * (double)(n + 1)) / (double)n;
+    const bool forced = (o.flags & ENT_FLAG_CSR_BANDED) != 0;
+    const bool want = !(o.flags & ENT_FLAG_CSR_GENERAL) && (forced || 24.0 * sizeof(T) <= csr_row);
     int32_t hbw = 0;
-    rc0 = check_csr(R, ws->ptr, st, (o.flags & ENT_FLAG_CSR_GENERAL) ? nullptr : &hbw);
+    rc0 = check_csr(R, ws->ptr, st, want ? &hbw : nullptr);
     if (rc0 != ENT_OK) return rc0;
-    if (!(o.flags & ENT_FLAG_CSR_GENERAL)) hp = ent::band_half_width_padded(hbw);
+    if (want) hp = ent::band_half_width_padded(hbw);
+    if (hp > 0 && (double)(16 + 2 * hp) * sizeof(T) > csr_row && !forced) hp = 0;
   }
   const bool banded = hp > 0;
   const int32_t ntile = dense ? (int32_t)(n_pad / 64)

@@ -1,5 +1,6 @@
-"""GPU parity of the banded CSR step (a CSR R whose entries all lie within 16
-of the diagonal runs as 16-row MFMA slabs): which kernel ran, per-probe
+"""GPU parity of the banded CSR kernels (a CSR R whose entries all lie within
+16 of the diagonal runs as 16-row MFMA slabs when they are no larger than the
+CSR arrays, or always with FLAG_CSR_BANDED): which kernel ran, per-probe
 values against the FP64 oracle for every padded band width, precision,
 schedule and probe distribution, ragged sizes, duplicate entries, and
 agreement with the general CSR kernel on the same input."""
@@ -47,7 +48,7 @@ def test_band_widths(orc, hb, hp, dtype):
     n, m, s, seed = 5003, 20, 64, 41 + hb
     csr = W.banded_density_csr(n, hb, seed=100 + hb, dtype=dtype)
     prec = "f64" if dtype == np.float64 else "f32"
-    res, per, _, band = run(csr, "chebyshev", m, s, seed, precision=prec)
+    res, per, _, band = run(csr, "chebyshev", m, s, seed, precision=prec, flags=ent.FLAG_CSR_BANDED)
     ref = orc.estimate(csr, 1, m, s, seed)
     err = per_probe_rel(per, ref)
     print(f"[band hb={hb} {prec}] kernel band {band}; H gpu={res.entropy:.12f} oracle={ref.entropy:.12f} "
@@ -64,7 +65,7 @@ def test_band_schedules_and_probes(orc, method, flags, dist):
     n, m, s, seed = 20_000, 30, 96, 17
     csr = W.banded_density_csr(n, 8, seed=7)
     d = 0 if dist == "rademacher" else 1
-    res, per, mom, band = run(csr, method, m, s, seed, probe_dist=dist, flags=flags)
+    res, per, mom, band = run(csr, method, m, s, seed, probe_dist=dist, flags=flags | ent.FLAG_CSR_BANDED)
     ref = orc.estimate(csr, 0 if method == "taylor" else 1, m, s, seed, dist=d)
     err = per_probe_rel(per, ref)
     print(f"[band {method} flags={flags} {dist}] H gpu={res.entropy:.14f} oracle={ref.entropy:.14f} "
@@ -85,7 +86,7 @@ def test_band_ragged(orc, n, s):
     # below, at and above one 64-probe chunk
     csr = W.banded_density_csr(n, 4, seed=n + 3)
     m, seed = 11, 5
-    res, per, _, band = run(csr, "chebyshev", m, s, seed)
+    res, per, _, band = run(csr, "chebyshev", m, s, seed, flags=ent.FLAG_CSR_BANDED)
     ref = orc.estimate(csr, 1, m, s, seed)
     err = per_probe_rel(per, ref)
     print(f"[band ragged n={n} s={s}] kernel band {band}; per-probe rel {err:.2e}", flush=True)
@@ -109,7 +110,7 @@ def test_band_duplicates_and_empty_rows(orc):
     np.add.at(rp2, rows2 + 1, 1)
     rp2 = np.cumsum(rp2)
     dup = (rp2, ci2.astype(np.int32), val2, n)
-    res, per, _, band = run(dup, "chebyshev", m, s, seed)
+    res, per, _, band = run(dup, "chebyshev", m, s, seed, flags=ent.FLAG_CSR_BANDED)
     ref = orc.estimate((rp, ci, val, n), 1, m, s, seed)
     assert band == 4
     assert per_probe_rel(per, ref) <= TOL64
@@ -121,7 +122,7 @@ def test_band_duplicates_and_empty_rows(orc):
     rp3 = np.cumsum(rp3)
     v3 = val[ce] / val[ce][ci[ce] == rows[ce]].sum()
     z = (rp3, ci[ce].astype(np.int32), v3, n)
-    res, per, _, band = run(z, "chebyshev", m, s, seed)
+    res, per, _, band = run(z, "chebyshev", m, s, seed, flags=ent.FLAG_CSR_BANDED)
     ref = orc.estimate(z, 1, m, s, seed)
     assert band == 4
     assert per_probe_rel(per, ref) <= TOL64
@@ -152,3 +153,20 @@ def test_wider_band_runs_general_kernel(orc):
     ref = orc.estimate(csr, 1, m, s, seed)
     assert band == 0
     assert per_probe_rel(per, ref) <= TOL64
+
+
+def test_default_kernel_choice_by_bytes(orc):
+    # half-bandwidth 16 with 33 entries per row: slabs of 48 values per row
+    # are smaller than the CSR arrays (FP32: 192 against 272 bytes), so the
+    # banded kernels run by default; a tridiagonal R (3 entries per row, slabs
+    # of 24 values) stays on the general kernels unless forced
+    n, m, s, seed = 20_000, 12, 64, 4
+    csr = W.banded_density_csr(n, 8, seed=5, dtype=np.float32)
+    assert run(csr, "chebyshev", m, s, seed, precision="f32")[3] == 16
+    tri = W.poisson_csr_fast(n)
+    res, per, _, band = run(tri, "chebyshev", m, s, seed)
+    assert band == 0
+    res2, per2, _, band2 = run(tri, "chebyshev", m, s, seed, flags=ent.FLAG_CSR_BANDED)
+    assert band2 == 4
+    ref = orc.estimate(tri, 1, m, s, seed)
+    assert per_probe_rel(per, ref) <= TOL64 and per_probe_rel(per2, ref) <= TOL64
