@@ -38,7 +38,7 @@ template <int KS>
 struct BandShape {
   static constexpr int HP = 2 * KS - 8;          // padded half-bandwidth
   static constexpr int K = 4 * KS;               // slab width (= 16 + 2 HP)
-  static constexpr int WF = KS + 4;              // ring: the block's fragments and the next four
+  static constexpr int WF = KS + 4;              // window: the block's fragments and the next four
 };
 
 constexpr int kBandWaves = 4;  // waves per workgroup (independent)
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(64 * kBandWaves) void band_step_kernel(BandStepArgs
   const T tcg = use_cg ? (T)a.cg[0] : T(0);
 
   double ds[4] = {0.0, 0.0, 0.0, 0.0}, gs[4] = {0.0, 0.0, 0.0, 0.0};
-  T win[WF][4];  // fragments: V_k rows 4f + q, probes 4c .. 4c+3; the block's are 0 .. KS-1
+  T win[WF][4];  // window fragments: V_k rows 4f + q, probes 4c .. 4c+3; the block's are 0 .. KS-1
   T an[KS];      // slab values of the next block
   if (b_beg < b_end) {
     const int64_t f0 = 4 * b_beg - HP / 4;
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(64 * kBandWaves) void band_step_kernel(BandStepArgs
         else
           load4<T>(G, row, ldv, chunk0, c, gv[r]);
       }
-      // Y_b = slab_b x ring, one 16-probe tile per probe of the lane's four
+      // Y_b = slab_b x window, one 16-probe tile per probe of the lane's four
       v4 acc[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc[t] = v4{T(0), T(0), T(0), T(0)};
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(64 * kBandWaves) void band_step_kernel(BandStepArgs
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = M::mma(ac[k], win[k][t], acc[t]);
       }
-      // slide the ring by one block
+      // slide the window by one block
 #pragma unroll
       for (int j = 0; j < KS; ++j) {
 #pragma unroll
