@@ -170,3 +170,22 @@ def test_default_kernel_choice_by_bytes(orc):
     assert band2 == 4
     ref = orc.estimate(tri, 1, m, s, seed)
     assert per_probe_rel(per, ref) <= TOL64 and per_probe_rel(per2, ref) <= TOL64
+
+
+@pytest.mark.parametrize("method,flags", [("chebyshev", 0), ("taylor", 0), ("chebyshev", ent.FLAG_CLENSHAW)])
+@pytest.mark.parametrize("dist", ["rademacher", "gaussian"])
+def test_band_fp32_schedules_and_probes(orc, method, flags, dist):
+    # FP32 values and products: stored Gaussian probe block or sign bits, every
+    # schedule, three 64-probe chunks with a ragged last one
+    n, m, s, seed = 12_345, 25, 150, 31
+    csr = W.banded_density_csr(n, 8, seed=13, dtype=np.float32)
+    d = 0 if dist == "rademacher" else 1
+    res, per, _, band = run(csr, method, m, s, seed, precision="f32", probe_dist=dist,
+                            flags=flags | ent.FLAG_CSR_BANDED)
+    ref = orc.estimate(csr, 0 if method == "taylor" else 1, m, s, seed, dist=d)
+    err = per_probe_rel(per, ref)
+    rel = abs(res.entropy - ref.entropy) / abs(ref.entropy)
+    print(f"[band f32 {method} flags={flags} {dist}] H gpu={res.entropy:.10f} oracle={ref.entropy:.10f} "
+          f"rel {rel:.2e} per-probe rel {err:.2e}", flush=True)
+    assert band == 16
+    assert err <= TOL32 and rel <= TOL32
