@@ -156,3 +156,18 @@ def test_builder_loads_without_the_package():
             "assert 'paper_1801_01072_amd' not in sys.modules, 'package imported'")
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_flag_constants_mirror_the_header(ent):
+    """The binding's ENT_FLAG_* values and the timing struct's fields are the
+    header's."""
+    text = open(HEADER).read()
+    flags = dict((k, int(v)) for k, v in re.findall(r"\bENT_FLAG_([A-Z0-9_]+)\s*=\s*(\d+)", text))
+    assert flags, "no flags parsed"
+    for name, value in flags.items():
+        assert getattr(ent, "FLAG_" + name) == value, name
+    end = text.index("} ent_timing;")
+    body = text[text.rindex("typedef struct {", 0, end):end]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b(?:double|int32_t)\s+([a-z_]+)\s*;", body)
+    assert [f for f, _ in ent.EntTiming._fields_] == fields

@@ -153,6 +153,10 @@ def test_wider_band_runs_general_kernel(orc):
     ref = orc.estimate(csr, 1, m, s, seed)
     assert band == 0
     assert per_probe_rel(per, ref) <= TOL64
+    # asking for the banded kernels does not change that
+    res2, per2, _, band2 = run(csr, "chebyshev", m, s, seed, flags=ent.FLAG_CSR_BANDED)
+    assert band2 == 0
+    assert np.array_equal(per, per2)
 
 
 def test_default_kernel_choice_by_bytes(orc):
