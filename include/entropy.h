@@ -27,7 +27,10 @@
  *  - Workspace (probe blocks, recurrence buffers, partial sums) is owned by
  *    the library, cached per device between calls and released by
  *    ent_release_workspace().  ent_set_workspace_limit() caps it; a call
- *    that would exceed the cap returns ENT_ENOMEM.
+ *    that would exceed the cap returns ENT_ENOMEM.  A CSR R served by the
+ *    banded kernels (ENT_FLAG_CSR_GENERAL, ENT_FLAG_CSR_BANDED) adds its slab
+ *    copy to the workspace: 16 + 2 hp values of the compute type per row,
+ *    rounded up to 16 rows, rebuilt by every call and never kept past it.
  */
 #ifndef ENTROPY_H
 #define ENTROPY_H
