@@ -12,13 +12,21 @@
  *    on failure the status is negative, ent_last_error() describes it, and
  *    the output structures are left untouched.
  *  - Matrices are passed by descriptor (ent_matrix).  Their arrays live in
- *    device memory of the current HIP device; the caller owns them and the
- *    library never retains a pointer past the call.  Before any kernel runs,
- *    each call checks every array it is given (matrix arrays, and the device
- *    arrays of the MLP calls): memory of another device, or host memory the
- *    device cannot read, is ENT_EINVAL, and so is a descriptor whose extent
- *    ((n - 1) ld + n elements dense; n + 1, nnz, nnz CSR) runs past the end
- *    of the allocation the pointer lies in (where the runtime reports one).
+ *    device memory of the current HIP device, or in host memory: the single-
+ *    matrix calls (ent_entropy_estimate(_detail), ent_power_method,
+ *    ent_selector_features) first copy every array that lies in host memory
+ *    (pageable or pinned) to a library-owned device buffer, the extent the
+ *    descriptor states ((n - 1) ld + n elements dense; n + 1, nnz, nnz CSR),
+ *    on the call's stream.  That buffer is kept per device for later calls
+ *    (released by ent_release_workspace(), counted against the workspace
+ *    limit); host extents cannot be checked and are the caller's contract.
+ *    The caller owns R and the library never retains a pointer past the call.
+ *    Before any kernel runs, each call checks every device array it is given
+ *    (matrix arrays, and the device arrays of the MLP calls): memory of
+ *    another device is ENT_EINVAL, and so is a descriptor whose extent runs
+ *    past the end of the allocation the pointer lies in (where the runtime
+ *    reports one).  The batched calls take device (or pinned, device-
+ *    readable) arrays only.
  *  - Scalar results are returned in host structures / host arrays owned by
  *    the caller.
  *  - Work is enqueued on opt->stream (a hipStream_t; NULL = the legacy
@@ -47,7 +55,8 @@ typedef enum {
   ENT_EINVAL = -1,       /* null or inaccessible pointer, descriptor past its
                             allocation, malformed CSR structure, size < 1,
                             unknown enum, bad layout                         */
-  ENT_ENOTDENSITY = -2,  /* |tr R - 1| above tolerance (see ent_options)      */
+  ENT_ENOTDENSITY = -2,  /* |tr R - 1| above tolerance (see ent_options), or
+                            tr R <= 0 with ENT_FLAG_NORMALIZE              */
   ENT_ENOMEM = -3,       /* device allocation failed or workspace cap reached */
   ENT_EDEVICE = -4,      /* a HIP runtime call failed                          */
   ENT_ENUMERIC = -5,     /* p~1 <= 0, or a non-finite estimate                 */
@@ -124,8 +133,18 @@ enum {
                                     bandwidth rounded up) when that copy has no
                                     more bytes per row than the CSR arrays;
                                     same results within rounding             */
-  ENT_FLAG_CSR_BANDED = 32       /* CSR R within 16 of the diagonal: the banded
+  ENT_FLAG_CSR_BANDED = 32,      /* CSR R within 16 of the diagonal: the banded
                                     kernels whatever the byte counts          */
+  ENT_FLAG_NORMALIZE = 64        /* estimate H(R / tr R) instead of requiring
+                                    tr R = 1 (Section 1.1: a density matrix
+                                    has unit trace).  tr R is computed on the
+                                    device (Re tr R for Hermitian storage) and
+                                    folded into the product scale, p~1 and the
+                                    singular values; R itself is not modified
+                                    or copied.  p1_est and u are those of
+                                    R / tr R.  tr R <= 0 or non-finite is
+                                    ENT_ENOTDENSITY.  Overrides
+                                    ENT_FLAG_SKIP_TRACE_CHECK and trace_tol.  */
 };
 
 /*

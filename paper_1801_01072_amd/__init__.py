@@ -41,6 +41,7 @@ FLAG_COMPLEX_POWER = 4
 FLAG_CLENSHAW = 8
 FLAG_CSR_GENERAL = 16
 FLAG_CSR_BANDED = 32
+FLAG_NORMALIZE = 64
 
 _METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ, "auto": AUTO}
 _PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
@@ -187,7 +188,8 @@ def _store_dtype(t) -> int:
 
 
 def dense_matrix(R) -> EntMatrix:
-    """Descriptor of a dense 2-D device tensor with unit column stride."""
+    """Descriptor of a dense 2-D tensor with unit column stride (device memory,
+    or host memory that the library copies to the device)."""
     if R.dim() != 2 or R.shape[0] != R.shape[1]:
         raise ValueError("R must be a square 2-D tensor")
     if R.stride(1) != 1:
@@ -196,7 +198,8 @@ def dense_matrix(R) -> EntMatrix:
 
 
 def csr_matrix(row_ptr, col_idx, values, n: int) -> EntMatrix:
-    """Descriptor of a CSR matrix held in device tensors (int64, int32, values)."""
+    """Descriptor of a CSR matrix held in tensors (int64, int32, values), on the
+    device or in host memory (copied in by the library)."""
     import torch
 
     if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32:

@@ -188,6 +188,25 @@ RealFormBuffer *real_form_for(int dev) {
   return b;
 }
 
+// Device copies of matrices the caller passes in host memory: one grow-only
+// buffer per device, held for the duration of the call that filled it.
+struct StagingBuffer {
+  std::mutex mu;
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_stage_mu;
+std::map<int, StagingBuffer *> g_stage;
+
+StagingBuffer *staging_for(int dev) {
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  auto it = g_stage.find(dev);
+  if (it != g_stage.end()) return it->second;
+  auto *b = new StagingBuffer();
+  g_stage[dev] = b;
+  return b;
+}
+
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 constexpr int kScalarDoubles = 8192;
@@ -274,6 +293,82 @@ ent_status check_matrix_memory(const ent_matrix *R) {
   return check_device_range(R->values, (size_t)R->nnz * esz, "R->values");
 }
 
+// Host memory (pageable, or pinned by the HIP runtime): the estimate entry
+// points copy such arrays to the device before anything else reads them.
+bool is_host_memory(const void *p) {
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;  // memory the runtime does not know: pageable host memory
+  }
+  return at.type == hipMemoryTypeUnregistered || at.type == hipMemoryTypeHost;
+}
+
+// Runs body(R') with R' = R, or, when any array of R lies in host memory, a
+// descriptor of device copies of those arrays in the device's staging buffer
+// (extents as the descriptor states them: (n - 1) ld + n entries dense; n + 1,
+// nnz, nnz CSR).  The copies are enqueued on st, so every later use on st
+// sees them; the buffer is held until body returns.
+template <typename F>
+ent_status with_device_copy(const ent_matrix *R, hipStream_t st, F body) {
+  const int64_t n = R->n;
+  const size_t esz = R->dtype == ENT_STORE_F64 ? 8 : R->dtype == ENT_STORE_F32 ? 4 : R->dtype == ENT_STORE_C128 ? 16 : 8;
+  struct Piece {
+    const void *src;
+    size_t bytes;
+    const void **dst;
+  };
+  ent_matrix M = *R;
+  std::vector<Piece> pieces;
+  if (R->layout == ENT_DENSE) {
+    if (R->ld > (INT64_MAX / (int64_t)esz) / n) return fail(ENT_EINVAL, "ld = %lld too large", (long long)R->ld);
+    if (is_host_memory(R->values)) pieces.push_back({R->values, (size_t)((n - 1) * R->ld + n) * esz, &M.values});
+  } else {
+    if (is_host_memory(R->row_ptr))
+      pieces.push_back({R->row_ptr, (size_t)(n + 1) * sizeof(int64_t), (const void **)&M.row_ptr});
+    if (R->nnz > 0 && is_host_memory(R->col_idx))
+      pieces.push_back({R->col_idx, (size_t)R->nnz * sizeof(int32_t), (const void **)&M.col_idx});
+    if (R->nnz > 0 && is_host_memory(R->values))
+      pieces.push_back({R->values, (size_t)R->nnz * esz, &M.values});
+  }
+  if (pieces.empty()) return body(R);
+  size_t total = 0;
+  for (auto &pc : pieces) total += (pc.bytes + 255) & ~size_t(255);
+  if (g_ws_limit && total > g_ws_limit)
+    return fail(ENT_ENOMEM, "device copy of the host matrix (%zu bytes) exceeds the workspace limit of %zu bytes",
+                total, g_ws_limit.load());
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  StagingBuffer *b = staging_for(dev);
+  std::lock_guard<std::mutex> lk(b->mu);
+  if (b->bytes < total) {
+    if (b->ptr) {
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(b->ptr));
+      b->ptr = nullptr;
+      b->bytes = 0;
+    }
+    if (hipMalloc(&b->ptr, total) != hipSuccess) {
+      (void)hipGetLastError();
+      b->ptr = nullptr;
+      return fail(ENT_ENOMEM, "could not allocate %zu bytes for the device copy of the host matrix", total);
+    }
+    b->bytes = total;
+  }
+  size_t off = 0;
+  for (auto &pc : pieces) {
+    void *d = (char *)b->ptr + off;
+    HIP_TRY(hipMemcpyAsync(d, pc.src, pc.bytes, hipMemcpyHostToDevice, st));
+    *pc.dst = d;
+    off += (pc.bytes + 255) & ~size_t(255);
+  }
+  const ent_status rc = body(&M);
+  // the body synchronises st on success; on failure make sure no copy is
+  // still reading the caller's host arrays or writing the buffer
+  (void)hipStreamSynchronize(st);
+  return rc;
+}
+
 struct Opts {
   ent_options o;
   hipStream_t st;
@@ -282,6 +377,22 @@ struct Opts {
   int64_t probe_rows = -1;
   // The matrix's trace is this multiple of tr R (2 for the real form).
   double trace_div = 1.0;
+  bool no_alloc = false;
+};
+
+// The memory one estimate carves its buffers from, held (locked) for the
+// whole estimate: the device's cached workspace, grown with hipMalloc on
+// demand.
+struct WsLease {
+  DeviceWorkspace *ws = nullptr;
+  std::unique_lock<std::mutex> lk;
+  ent_status acquire(int dev, bool) {
+    ws = workspace_for(dev);
+    lk = std::unique_lock<std::mutex>(ws->mu);
+    return ENT_OK;
+  }
+  void *ptr() const { return ws->ptr; }
+  ent_status ensure(size_t need) { return ensure_workspace(ws, need); }
 };
 
 Opts resolve_options(const ent_options *opt) {
@@ -371,7 +482,7 @@ ent_status check_csr(const ent_matrix *R, void *scratch, hipStream_t st, int32_t
   if (R->layout != ENT_CSR) return ENT_OK;
   int32_t *flag = (int32_t *)scratch;
   int32_t h[2] = {0, 0};
-  HIP_TRY(hipMemsetAsync(flag, 0, 2 * sizeof(int32_t), st));
+  HIP_TRY(ent::launch_zero(flag, 2 * sizeof(int32_t), st));
   HIP_TRY(ent::launch_validate_csr(R->row_ptr, R->col_idx, R->n, R->nnz, flag, st));
   HIP_TRY(hipMemcpyAsync(&h[0], flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -426,14 +537,17 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
 
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
-  DeviceWorkspace *ws = workspace_for(dev);
-  std::lock_guard<std::mutex> lk(ws->mu);
+  WsLease ws;
+  {
+    const ent_status r0 = ws.acquire(dev, op.no_alloc);
+    if (r0 != ENT_OK) return r0;
+  }
 
   // CSR: validate the structure, and serve a matrix whose entries all lie
   // within 16 of the diagonal with the banded step kernel
   int32_t hp = 0;
   if (!dense) {
-    ent_status rc0 = ensure_workspace(ws, 256);
+    ent_status rc0 = ws.ensure(256);
     if (rc0 != ENT_OK) return rc0;
     // the step streams the matrix once per product: take the slabs (16 + 2 hp
     // values per row) only if they are no larger than the CSR arrays (values,
@@ -442,7 +556,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     const bool forced = (o.flags & ENT_FLAG_CSR_BANDED) != 0;
     const bool want = !(o.flags & ENT_FLAG_CSR_GENERAL) && (forced || 24.0 * sizeof(T) <= csr_row);
     int32_t hbw = 0;
-    rc0 = check_csr(R, ws->ptr, st, want ? &hbw : nullptr);
+    rc0 = check_csr(R, ws.ptr(), st, want ? &hbw : nullptr);
     if (rc0 != ENT_OK) return rc0;
     if (want) hp = ent::band_half_width_padded(hbw);
     if (hp > 0 && (double)(16 + 2 * hp) * sizeof(T) > csr_row && !forced) hp = 0;
@@ -491,21 +605,22 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   cv.add(&part, (size_t)nslot * npart * ldv);
   cv.add(&d, (size_t)nslot * s);
   cv.add(&h, (size_t)s);
-  ent_status rc = ensure_workspace(ws, cv.total());
+  ent_status rc = ws.ensure(cv.total());
   if (rc != ENT_OK) return rc;
-  cv.assign(ws->ptr);
+  cv.assign(ws.ptr());
 
   PhaseEvents pe;
-  pe.on = g_timing_on;
+  pe.on = g_timing_on && !op.no_alloc;
   pe.st = st;
   pe.csr_band = hp;
   pe.mark();
-  HIP_TRY(hipMemsetAsync(scal, 0, sizeof(double) * 64, st));
+  HIP_TRY(ent::launch_zero(scal, sizeof(double) * 64, st));
   // CSR step launches may use fewer workgroups than the partial stride
-  if (!dense) HIP_TRY(hipMemsetAsync(part, 0, sizeof(double) * (size_t)nslot * ntile * ldv, st));
-  // trace check
-  const bool check_trace = !(o.flags & ENT_FLAG_SKIP_TRACE_CHECK);
-  if (check_trace) {
+  if (!dense) HIP_TRY(ent::launch_zero(part, sizeof(double) * (size_t)nslot * ntile * ldv, st));
+  // trace check (or the trace that normalises R)
+  const bool normalize = (o.flags & ENT_FLAG_NORMALIZE) != 0;
+  const bool check_trace = !(o.flags & ENT_FLAG_SKIP_TRACE_CHECK) && !normalize;
+  if (check_trace || normalize) {
     if (dense) {
       if (R->dtype == ENT_STORE_F64)
         HIP_TRY(ent::launch_trace_dense<double>((const double *)R->values, R->ld, n, scal, st));
@@ -549,7 +664,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     pe.power_end = pe.mark();
     pe.power_launches = o.power_trials * (o.power_iters + 1);
   }
-  HIP_TRY(ent::launch_setup_interval(scal, method, m, o.u_factor, o.u_fixed, o.cutoff, st));
+  HIP_TRY(ent::launch_setup_interval(scal, method, m, o.u_factor, o.u_fixed, o.cutoff, st,
+                                     normalize ? op.trace_div : 0.0));
 
   // recurrence
   const int32_t nsteps = clenshaw ? m + 1 : (method == ENT_CHEBYSHEV) ? m : m + 1;
@@ -559,8 +675,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   if (clenshaw) {
     // y_{m+1} = y_{m+2} = 0; y_k = alpha_k g + 2X y_{k+1} - y_{k+2}, k = m..0,
     // each y_k written over y_{k+2} (same element, same thread)
-    HIP_TRY(hipMemsetAsync(VA, 0, sizeof(T) * (size_t)n_pad * ldv, st));
-    HIP_TRY(hipMemsetAsync(VB, 0, sizeof(T) * (size_t)n_pad * ldv, st));
+    HIP_TRY(ent::launch_zero(VA, sizeof(T) * (size_t)n_pad * ldv, st));
+    HIP_TRY(ent::launch_zero(VB, sizeof(T) * (size_t)n_pad * ldv, st));
     Vk = VA;
     Vkm1 = VB;
   }
@@ -681,6 +797,11 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
       return fail(ENT_ENOTDENSITY, "trace of R is %.17g, not 1 within %.3g",
                   hs[ent::S_TRACE] / op.trace_div, tol);
   }
+  if (normalize) {
+    const double tr = hs[ent::S_TRACE] / op.trace_div;
+    if (!(tr > 0) || !std::isfinite(1.0 / tr))
+      return fail(ENT_ENOTDENSITY, "trace of R is %.17g: R cannot be normalised to unit trace", tr);
+  }
   if (hs[ent::S_FLAG] != 0.0)
     return fail(ENT_ENUMERIC, "numeric failure: p1~ = %.17g, u = %.17g, estimate = %.17g",
                 hs[ent::S_P1], hs[ent::S_U], hs[ent::S_ENT]);
@@ -729,8 +850,11 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
 
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
-  DeviceWorkspace *ws = workspace_for(dev);
-  std::lock_guard<std::mutex> lk(ws->mu);
+  WsLease ws;
+  {
+    const ent_status r0 = ws.acquire(dev, op.no_alloc);
+    if (r0 != ENT_OK) return r0;
+  }
   double *scal = nullptr, *x0 = nullptr, *x1 = nullptr, *p0 = nullptr, *p1 = nullptr, *ypart = nullptr;
   double *part = nullptr, *d = nullptr, *h = nullptr;
   uint16_t *Ahi = nullptr, *Alo = nullptr, *Vhi = nullptr, *Vlo = nullptr;
@@ -756,17 +880,18 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
   cv.add(&part, (size_t)nslot * nblk * ldv);
   cv.add(&d, (size_t)nslot * s);
   cv.add(&h, (size_t)s);
-  ent_status rc = ensure_workspace(ws, cv.total());
+  ent_status rc = ws.ensure(cv.total());
   if (rc != ENT_OK) return rc;
-  cv.assign(ws->ptr);
+  cv.assign(ws.ptr());
 
   PhaseEvents pe;
-  pe.on = g_timing_on;
+  pe.on = g_timing_on && !op.no_alloc;
   pe.st = st;
   pe.mark();
-  HIP_TRY(hipMemsetAsync(scal, 0, sizeof(double) * 64, st));
-  const bool check_trace = !(o.flags & ENT_FLAG_SKIP_TRACE_CHECK);
-  if (check_trace) {
+  HIP_TRY(ent::launch_zero(scal, sizeof(double) * 64, st));
+  const bool normalize = (o.flags & ENT_FLAG_NORMALIZE) != 0;
+  const bool check_trace = !(o.flags & ENT_FLAG_SKIP_TRACE_CHECK) && !normalize;
+  if (check_trace || normalize) {
     if (f64)
       HIP_TRY(ent::launch_trace_dense<double>((const double *)R->values, R->ld, n, scal, st));
     else
@@ -788,17 +913,18 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
     pe.power_end = pe.mark();
     pe.power_launches = o.power_trials * (o.power_iters + 1);
   }
-  HIP_TRY(ent::launch_setup_interval(scal, method, m, o.u_factor, o.u_fixed, o.cutoff, st));
+  HIP_TRY(ent::launch_setup_interval(scal, method, m, o.u_factor, o.u_fixed, o.cutoff, st,
+                                     normalize ? op.trace_div : 0.0));
 
   const int32_t nsteps = clenshaw ? m + 1 : (method == ENT_CHEBYSHEV) ? m : m + 1;
   const float *Vk = G, *Vkm1 = nullptr;
   float *bufs[2] = {VA, VB};
   if (clenshaw) {
     // y_{m+1} = y_{m+2} = 0 (and the split of y_{m+1}); see run_poly
-    HIP_TRY(hipMemsetAsync(VA, 0, sizeof(float) * (size_t)n_pad * ldv, st));
-    HIP_TRY(hipMemsetAsync(VB, 0, sizeof(float) * (size_t)n_pad * ldv, st));
-    HIP_TRY(hipMemsetAsync(Vhi, 0, sizeof(uint16_t) * (size_t)n_pad * ldv, st));
-    HIP_TRY(hipMemsetAsync(Vlo, 0, sizeof(uint16_t) * (size_t)n_pad * ldv, st));
+    HIP_TRY(ent::launch_zero(VA, sizeof(float) * (size_t)n_pad * ldv, st));
+    HIP_TRY(ent::launch_zero(VB, sizeof(float) * (size_t)n_pad * ldv, st));
+    HIP_TRY(ent::launch_zero(Vhi, sizeof(uint16_t) * (size_t)n_pad * ldv, st));
+    HIP_TRY(ent::launch_zero(Vlo, sizeof(uint16_t) * (size_t)n_pad * ldv, st));
     Vk = VA;
     Vkm1 = VB;
   }
@@ -889,6 +1015,11 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
       return fail(ENT_ENOTDENSITY, "trace of R is %.17g, not 1 within %.3g",
                   hs[ent::S_TRACE] / op.trace_div, tol);
   }
+  if (normalize) {
+    const double tr = hs[ent::S_TRACE] / op.trace_div;
+    if (!(tr > 0) || !std::isfinite(1.0 / tr))
+      return fail(ENT_ENOTDENSITY, "trace of R is %.17g: R cannot be normalised to unit trace", tr);
+  }
   if (hs[ent::S_FLAG] != 0.0)
     return fail(ENT_ENUMERIC, "numeric failure: p1~ = %.17g, u = %.17g, estimate = %.17g",
                 hs[ent::S_P1], hs[ent::S_U], hs[ent::S_ENT]);
@@ -962,6 +1093,30 @@ bool selector_check(const std::vector<double> &mom, const std::vector<double> &a
   return std::isfinite(hm) && std::fabs(hm - h4) <= 2.5e-4 * std::fabs(hm);
 }
 
+// The selector's sketch pass: power method and a degree-12 Chebyshev moment
+// pass with 16 Rademacher probes on [0, u], FP32 -- or FP64 for a CSR R
+// stored in FP64 (CSR values are read in their stored precision) -- then the
+// features and the network on the device; y receives the network's outputs.
+ent_status feature_pass(const ent_matrix *R, uint64_t seed, const Opts &op, const SelectorState &st,
+                        float y[2], ent_result *fr) {
+  const bool csr64 = R->layout == ENT_CSR && R->dtype == ENT_STORE_F64;
+  Opts fo = op;
+  fo.o.precision = csr64 ? ENT_F64 : ENT_F32;
+  fo.o.u_fixed = 0.0;
+  fo.o.cutoff = 0.0;
+  fo.o.probe_dist = ENT_RADEMACHER;
+  fo.o.flags &= ~ENT_FLAG_CLENSHAW;
+  SelHook fh;
+  fh.feat_dev = st.feat;
+  fh.params_dev = st.params;
+  fh.y_dev = st.y;
+  fh.y_host = y;
+  const uint64_t fseed = seed ^ 0x5E1EC7ull;
+  if (csr64)
+    return run_poly<double>(R, ENT_CHEBYSHEV, kFeatDegree, kFeatProbes, fseed, fo, fr, nullptr, nullptr, &fh);
+  return run_poly<float>(R, ENT_CHEBYSHEV, kFeatDegree, kFeatProbes, fseed, fo, fr, nullptr, nullptr, &fh);
+}
+
 ent_status run_auto(const ent_matrix *R, int32_t m_plain, int32_t s, uint64_t seed, const Opts &op,
                     ent_result *out, double *per_probe, double *moments) {
   int dev = 0;
@@ -974,21 +1129,10 @@ ent_status run_auto(const ent_matrix *R, int32_t m_plain, int32_t s, uint64_t se
       return fail(ENT_EINVAL, "ENT_AUTO needs a selector: call ent_selector_load first");
     st = it->second;
   }
-  // 1. sketch pass: power method + degree-12 Chebyshev moments with 16 probes, FP32
-  Opts fo = op;
-  fo.o.precision = ENT_F32;
-  fo.o.u_fixed = 0.0;
-  fo.o.cutoff = 0.0;
-  fo.o.probe_dist = ENT_RADEMACHER;
+  // 1. sketch pass: power method + degree-12 Chebyshev moments with 16 probes
   float y[2] = {0.f, 0.f};
-  SelHook fh;
-  fh.feat_dev = st.feat;
-  fh.params_dev = st.params;
-  fh.y_dev = st.y;
-  fh.y_host = y;
   ent_result fr{};
-  ent_status rc = run_poly<float>(R, ENT_CHEBYSHEV, kFeatDegree, kFeatProbes, seed ^ 0x5E1EC7ull,
-                                  fo, &fr, nullptr, nullptr, &fh);
+  ent_status rc = feature_pass(R, seed, op, st, y, &fr);
   if (rc != ENT_OK) return rc;
   int32_t m_hat = 0;
   double lo = 0.0;
@@ -1061,7 +1205,8 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
   cv.add(&work, (size_t)N * N);
   cv.add(&eig, (size_t)N);
   cv.add(&sig, (size_t)k);
-  const bool check_trace = !(o.flags & ENT_FLAG_SKIP_TRACE_CHECK);
+  const bool normalize = (o.flags & ENT_FLAG_NORMALIZE) != 0;
+  const bool check_trace = !(o.flags & ENT_FLAG_SKIP_TRACE_CHECK) && !normalize;
   PhaseEvents pe;
   pe.on = g_timing_on;
   pe.st = st;
@@ -1081,12 +1226,13 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
     cv.assign(ws->ptr);
     pe.mark();
     HIP_TRY(ent::launch_fill(scal, 64, 0.0, st));
-    if (check_trace) {
+    if (check_trace || normalize) {
       if (f64)
         HIP_TRY(ent::launch_trace_dense<double>((const double *)R->values, R->ld, n, scal, st));
       else
         HIP_TRY(ent::launch_trace_dense<float>((const float *)R->values, R->ld, n, scal, st));
     }
+    if (normalize) HIP_TRY(ent::launch_set_norm(scal, op.trace_div, st));
     if (f64)
       HIP_TRY(ent::launch_count_sketch<double>((const double *)R->values, R->ld, n, s, seed, cnt, off, rows,
                                                Y, ldy, st, 0));
@@ -1123,12 +1269,13 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
     pe.mark();
     HIP_TRY(ent::launch_fill(scal, 64, 0.0, st));
     HIP_TRY(ent::launch_fill(scal + ent::S_A, 1, 1.0, st));
-    if (check_trace) {
+    if (check_trace || normalize) {
       if (f64)
         HIP_TRY(ent::launch_trace_dense<double>((const double *)R->values, R->ld, n, scal, st));
       else
         HIP_TRY(ent::launch_trace_dense<float>((const float *)R->values, R->ld, n, scal, st));
     }
+    if (normalize) HIP_TRY(ent::launch_set_norm(scal, op.trace_div, st));
     HIP_TRY(ent::launch_probe_gen_t(P, Phi, Plo, n, n_pad, s, ldv, seed,
                                     o.sketch == ENT_SKETCH_SRHT ? 2 : ENT_GAUSSIAN, st, 2u,
                                     1.0 / std::sqrt((double)s)));
@@ -1174,12 +1321,13 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
     pe.mark();
     HIP_TRY(ent::launch_fill(scal, 64, 0.0, st));
     HIP_TRY(ent::launch_fill(scal + ent::S_A, 1, 1.0, st));
-    if (check_trace) {
+    if (check_trace || normalize) {
       if (f64)
         HIP_TRY(ent::launch_trace_dense<double>((const double *)R->values, R->ld, n, scal, st));
       else
         HIP_TRY(ent::launch_trace_dense<float>((const float *)R->values, R->ld, n, scal, st));
     }
+    if (normalize) HIP_TRY(ent::launch_set_norm(scal, op.trace_div, st));
     const void *Rt = R->values;
     int64_t ldr = R->ld;
     if (copy) {
@@ -1221,6 +1369,11 @@ ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_
     if (!(std::fabs(hs[ent::S_TRACE] / op.trace_div - 1.0) <= tol))
       return fail(ENT_ENOTDENSITY, "trace of R is %.17g, not 1 within %.3g",
                   hs[ent::S_TRACE] / op.trace_div, tol);
+  }
+  if (normalize) {
+    const double tr = hs[ent::S_TRACE] / op.trace_div;
+    if (!(tr > 0) || !std::isfinite(1.0 / tr))
+      return fail(ENT_ENOTDENSITY, "trace of R is %.17g: R cannot be normalised to unit trace", tr);
   }
   if (hs[ent::S_FLAG] != 0.0) return fail(ENT_ENUMERIC, "non-finite random-projection estimate");
   out->entropy = hs[ent::S_ENT];
@@ -1320,7 +1473,8 @@ ent_status enqueue_batch(ent_graph_s *g, hipStream_t st, PhaseEvents *pe) {
     HIP_TRY((ent::launch_batch_convert<double, T>(g->mats_d, count, g->max_elems, st)));
   else
     HIP_TRY((ent::launch_batch_convert<float, T>(g->mats_d, count, g->max_elems, st)));
-  if (!(o.flags & ENT_FLAG_SKIP_TRACE_CHECK)) HIP_TRY(ent::launch_batch_trace<T>(g->mats_d, count, st));
+  if (!(o.flags & ENT_FLAG_SKIP_TRACE_CHECK) || (o.flags & ENT_FLAG_NORMALIZE))
+    HIP_TRY(ent::launch_batch_trace<T>(g->mats_d, count, st));
   HIP_TRY(ent::launch_batch_probes<T>(g->mats_d, count, g->max_npad, (T *)g->G, g->s, g->ldv,
                                       o.probe_dist, st));
   if (!(o.u_fixed > 0)) {
@@ -1344,7 +1498,7 @@ ent_status enqueue_batch(ent_graph_s *g, hipStream_t st, PhaseEvents *pe) {
     }
   }
   HIP_TRY(ent::launch_batch_setup(g->mats_d, count, g->method, g->m, o.u_factor, o.u_fixed,
-                                  o.cutoff, st));
+                                  o.cutoff, st, (o.flags & ENT_FLAG_NORMALIZE) ? 1.0 : 0.0));
   const int32_t nsteps = (g->method == ENT_CHEBYSHEV) ? g->m : g->m + 1;
   const T *Vk = (const T *)g->G, *Vkm1 = nullptr;
   T *bufs[2] = {(T *)g->VA, (T *)g->VB};
@@ -1399,7 +1553,7 @@ ent_status enqueue_batch_bf16(ent_graph_s *g, hipStream_t st, PhaseEvents *pe) {
   const ent_options &o = g->o;
   const int32_t count = g->count;
   HIP_TRY(ent::launch_fill(g->scal, (int64_t)count * g->sb, 0.0, st));
-  if (!(o.flags & ENT_FLAG_SKIP_TRACE_CHECK)) {
+  if (!(o.flags & ENT_FLAG_SKIP_TRACE_CHECK) || (o.flags & ENT_FLAG_NORMALIZE)) {
     if (g->src_f64)
       HIP_TRY(ent::launch_batch_trace<double>(g->mats_d, count, st));
     else
@@ -1435,7 +1589,7 @@ ent_status enqueue_batch_bf16(ent_graph_s *g, hipStream_t st, PhaseEvents *pe) {
     }
   }
   HIP_TRY(ent::launch_batch_setup(g->mats_d, count, g->method, g->m, o.u_factor, o.u_fixed,
-                                  o.cutoff, st));
+                                  o.cutoff, st, (o.flags & ENT_FLAG_NORMALIZE) ? 1.0 : 0.0));
   const int32_t nsteps = (g->method == ENT_CHEBYSHEV) ? g->m : g->m + 1;
   const float *Vk = (const float *)g->G, *Vkm1 = nullptr;
   float *bufs[2] = {(float *)g->VA, (float *)g->VB};
@@ -1778,12 +1932,15 @@ ent_status batch_collect(ent_graph_s *g, ent_result *outs) {
                          hipMemcpyDeviceToHost, g->stream));
   HIP_TRY(hipStreamSynchronize(g->stream));
   g->launched = true;
-  const bool check = !(g->o.flags & ENT_FLAG_SKIP_TRACE_CHECK);
+  const bool normalize = (g->o.flags & ENT_FLAG_NORMALIZE) != 0;
+  const bool check = !(g->o.flags & ENT_FLAG_SKIP_TRACE_CHECK) && !normalize;
   const double tol = g->o.trace_tol > 0 ? g->o.trace_tol : ((g->src_f64 && g->comp_f64) ? 1e-10 : 1e-4);
   for (int32_t b = 0; b < g->count; ++b) {
     const double *hs = g->host_scal + (int64_t)b * g->sb;
     if (check && !(std::fabs(hs[ent::S_TRACE] - 1.0) <= tol))
       return fail(ENT_ENOTDENSITY, "matrix %d: trace %.17g is not 1 within %.3g", b, hs[ent::S_TRACE], tol);
+    if (normalize && (!(hs[ent::S_TRACE] > 0) || !std::isfinite(1.0 / hs[ent::S_TRACE])))
+      return fail(ENT_ENOTDENSITY, "matrix %d: trace %.17g cannot be normalised to 1", b, hs[ent::S_TRACE]);
     if (hs[ent::S_FLAG] != 0.0)
       return fail(ENT_ENUMERIC, "matrix %d: numeric failure (p1~ = %.17g)", b, hs[ent::S_P1]);
   }
@@ -1891,80 +2048,13 @@ ent_status free_buffers(std::mutex &map_mu, std::map<int, Buf *> &bufs) {
   return rc;
 }
 
-}  // namespace
-
-// ===========================================================================
-// C ABI
-// ===========================================================================
-extern "C" {
-
-void ent_options_default(ent_options *opt) {
-  if (!opt) return;
-  std::memset(opt, 0, sizeof(*opt));
-  opt->power_iters = 20;
-  opt->power_trials = 1;
-  opt->u_factor = 6.0;
-  opt->precision = ENT_F64;
-  opt->probe_dist = ENT_RADEMACHER;
-}
-
-ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int32_t degree,
-                                       int32_t probes, uint64_t seed, const ent_options *opt,
-                                       ent_result *out, double *per_probe, double *moments) {
-  g_last_error.clear();
-  ent_status rc = validate_matrix(R, true);
-  if (rc != ENT_OK) return rc;
-  if (!out) return fail(ENT_EINVAL, "out is NULL");
-  Opts op = resolve_options(opt);
-  rc = validate_options(op.o);
-  if (rc != ENT_OK) return rc;
-  if (is_complex(R) && (method == ENT_RANDPROJ || method == ENT_AUTO))
-    return fail(ENT_EUNSUPPORTED, "Hermitian R: Taylor and Chebyshev estimators only");
-  if (method == ENT_RANDPROJ) {
-    ent_result tmp{};
-    rc = run_randproj(R, seed, op, &tmp, per_probe);
-    if (rc == ENT_OK) *out = tmp;
-    return rc;
-  }
-  if (method != ENT_TAYLOR && method != ENT_CHEBYSHEV && method != ENT_AUTO)
-    return fail(ENT_EINVAL, "unknown method %d", method);
-  if (degree < 1) return fail(ENT_EINVAL, "degree = %d < 1", degree);
-  if (degree > 4000) return fail(ENT_EINVAL, "degree = %d > 4000", degree);
-  if (probes < 1) return fail(ENT_EINVAL, "probes = %d < 1", probes);
-  if (method == ENT_TAYLOR && op.o.cutoff > 0)
-    return fail(ENT_EINVAL, "cutoff applies to the Chebyshev method only");
-  if ((op.o.flags & ENT_FLAG_CLENSHAW) && method != ENT_CHEBYSHEV)
-    return fail(ENT_EINVAL, "the Clenshaw schedule applies to the Chebyshev method only");
-  rc = check_matrix_memory(R);
-  if (rc != ENT_OK) return rc;
-  ent_result tmp{};
-  if (is_complex(R))
-    rc = run_hermitian(R, method, degree, probes, seed, op, &tmp, per_probe, moments);
-  else if (method == ENT_AUTO)
-    rc = run_auto(R, degree, probes, seed, op, &tmp, per_probe, moments);
-  else
-    rc = poly_dispatch(R, method, degree, probes, seed, op, &tmp, per_probe, moments, nullptr);
-  if (rc == ENT_OK) *out = tmp;
-  return rc;
-}
-
-ent_status ent_entropy_estimate(const ent_matrix *R, int32_t method, int32_t degree, int32_t probes,
-                                uint64_t seed, const ent_options *opt, ent_result *out) {
-  return ent_entropy_estimate_detail(R, method, degree, probes, seed, opt, out, nullptr, nullptr);
-}
-
-ent_status ent_power_method(const ent_matrix *R, int32_t t, int32_t q, uint64_t seed, void *stream,
-                            double *p1) {
-  g_last_error.clear();
-  ent_status rc = validate_matrix(R, true);
-  if (rc != ENT_OK) return rc;
-  if (!p1) return fail(ENT_EINVAL, "p1 is NULL");
-  if (t < 0 || q < 1) return fail(ENT_EINVAL, "need t >= 0 and q >= 1");
-  rc = check_matrix_memory(R);
-  if (rc != ENT_OK) return rc;
+// Algorithm 4 on a device-resident R (validated, arrays checked).
+ent_status power_method_device(const ent_matrix *R, int32_t t, int32_t q, uint64_t seed, void *stream,
+                               double *p1) {
+  ent_status rc = ENT_OK;
   hipStream_t st = (hipStream_t)stream;
   if (is_complex(R))
-    return with_real_form(R, st, [&](const ent_matrix &M) { return ent_power_method(&M, t, q, seed, stream, p1); });
+    return with_real_form(R, st, [&](const ent_matrix &M) { return power_method_device(&M, t, q, seed, stream, p1); });
   const int64_t n = R->n, n_pad = round_up(n, 64);
   const int32_t pblk = (int32_t)power_blocks(R);
   const bool f64 = R->dtype == ENT_STORE_F64;
@@ -2014,6 +2104,88 @@ ent_status ent_power_method(const ent_matrix *R, int32_t t, int32_t q, uint64_t 
   HIP_TRY(hipStreamSynchronize(st));
   *p1 = v;
   return ENT_OK;
+}
+
+// Argument rules shared by the polynomial estimate entry points.
+ent_status check_poly_args(int32_t method, int32_t degree, int32_t probes, const Opts &op) {
+  if (degree < 1) return fail(ENT_EINVAL, "degree = %d < 1", degree);
+  if (degree > 4000) return fail(ENT_EINVAL, "degree = %d > 4000", degree);
+  if (probes < 1) return fail(ENT_EINVAL, "probes = %d < 1", probes);
+  if (method == ENT_TAYLOR && op.o.cutoff > 0)
+    return fail(ENT_EINVAL, "cutoff applies to the Chebyshev method only");
+  if ((op.o.flags & ENT_FLAG_CLENSHAW) && method != ENT_CHEBYSHEV)
+    return fail(ENT_EINVAL, "the Clenshaw schedule applies to the Chebyshev method only");
+  return ENT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void ent_options_default(ent_options *opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->power_iters = 20;
+  opt->power_trials = 1;
+  opt->u_factor = 6.0;
+  opt->precision = ENT_F64;
+  opt->probe_dist = ENT_RADEMACHER;
+}
+
+ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int32_t degree,
+                                       int32_t probes, uint64_t seed, const ent_options *opt,
+                                       ent_result *out, double *per_probe, double *moments) {
+  g_last_error.clear();
+  ent_status rc = validate_matrix(R, true);
+  if (rc != ENT_OK) return rc;
+  if (!out) return fail(ENT_EINVAL, "out is NULL");
+  Opts op = resolve_options(opt);
+  rc = validate_options(op.o);
+  if (rc != ENT_OK) return rc;
+  if (is_complex(R) && (method == ENT_RANDPROJ || method == ENT_AUTO))
+    return fail(ENT_EUNSUPPORTED, "Hermitian R: Taylor and Chebyshev estimators only");
+  if (method == ENT_RANDPROJ) {
+    ent_result tmp{};
+    rc = with_device_copy(R, op.st, [&](const ent_matrix *D) { return run_randproj(D, seed, op, &tmp, per_probe); });
+    if (rc == ENT_OK) *out = tmp;
+    return rc;
+  }
+  if (method != ENT_TAYLOR && method != ENT_CHEBYSHEV && method != ENT_AUTO)
+    return fail(ENT_EINVAL, "unknown method %d", method);
+  rc = check_poly_args(method, degree, probes, op);
+  if (rc != ENT_OK) return rc;
+  ent_result tmp{};
+  rc = with_device_copy(R, op.st, [&](const ent_matrix *D) {
+    ent_status r2 = check_matrix_memory(D);
+    if (r2 != ENT_OK) return r2;
+    if (is_complex(D)) return run_hermitian(D, method, degree, probes, seed, op, &tmp, per_probe, moments);
+    if (method == ENT_AUTO) return run_auto(D, degree, probes, seed, op, &tmp, per_probe, moments);
+    return poly_dispatch(D, method, degree, probes, seed, op, &tmp, per_probe, moments, nullptr);
+  });
+  if (rc == ENT_OK) *out = tmp;
+  return rc;
+}
+
+ent_status ent_entropy_estimate(const ent_matrix *R, int32_t method, int32_t degree, int32_t probes,
+                                uint64_t seed, const ent_options *opt, ent_result *out) {
+  return ent_entropy_estimate_detail(R, method, degree, probes, seed, opt, out, nullptr, nullptr);
+}
+
+ent_status ent_power_method(const ent_matrix *R, int32_t t, int32_t q, uint64_t seed, void *stream,
+                            double *p1) {
+  g_last_error.clear();
+  ent_status rc = validate_matrix(R, true);
+  if (rc != ENT_OK) return rc;
+  if (!p1) return fail(ENT_EINVAL, "p1 is NULL");
+  if (t < 0 || q < 1) return fail(ENT_EINVAL, "need t >= 0 and q >= 1");
+  return with_device_copy(R, (hipStream_t)stream, [&](const ent_matrix *D) {
+    ent_status r2 = check_matrix_memory(D);
+    if (r2 != ENT_OK) return r2;
+    return power_method_device(D, t, q, seed, stream, p1);
+  });
 }
 
 ent_status ent_chebyshev_coeffs(double lo, double u, int32_t m, double *alpha) {
@@ -2260,8 +2432,6 @@ ent_status ent_selector_features(const ent_matrix *R, uint64_t seed, const ent_o
   Opts op = resolve_options(opt);
   rc = validate_options(op.o);
   if (rc != ENT_OK) return rc;
-  rc = check_matrix_memory(R);
-  if (rc != ENT_OK) return rc;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   SelectorState st;
@@ -2272,20 +2442,13 @@ ent_status ent_selector_features(const ent_matrix *R, uint64_t seed, const ent_o
       return fail(ENT_EINVAL, "call ent_selector_load first (the features pass also runs the network)");
     st = it->second;
   }
-  Opts fo = op;
-  fo.o.precision = ENT_F32;
-  fo.o.u_fixed = 0.0;
-  fo.o.cutoff = 0.0;
-  fo.o.probe_dist = ENT_RADEMACHER;
   float y[2];
-  SelHook fh;
-  fh.feat_dev = st.feat;
-  fh.params_dev = st.params;
-  fh.y_dev = st.y;
-  fh.y_host = y;
   ent_result fr{};
-  rc = run_poly<float>(R, ENT_CHEBYSHEV, kFeatDegree, kFeatProbes, seed ^ 0x5E1EC7ull, fo, &fr,
-                       nullptr, nullptr, &fh);
+  rc = with_device_copy(R, op.st, [&](const ent_matrix *D) {
+    ent_status r2 = check_matrix_memory(D);
+    if (r2 != ENT_OK) return r2;
+    return feature_pass(D, seed, op, st, y, &fr);
+  });
   if (rc != ENT_OK) return rc;
   HIP_TRY(hipMemcpy(features, st.feat, sizeof(float) * 16, hipMemcpyDeviceToHost));
   if (outputs) {
@@ -2323,9 +2486,11 @@ ent_status ent_release_workspace(void) {
   HIP_TRY(hipGetDevice(&cur));
   const ent_status r1 = free_buffers(g_ws_mu, g_ws);
   const ent_status r2 = free_buffers(g_rf_mu, g_rf);
+  const ent_status r3 = free_buffers(g_stage_mu, g_stage);
   const hipError_t e = hipSetDevice(cur);
   if (r1 != ENT_OK) return r1;
   if (r2 != ENT_OK) return r2;
+  if (r3 != ENT_OK) return r3;
   if (e != hipSuccess) return fail(ENT_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
   return ENT_OK;
 }

@@ -17,6 +17,8 @@ enum ScalarSlot {
   S_B = 4,      // shift: Chebyshev (u+lo)/(u-lo), Taylor 1
   S_FLAG = 5,   // nonzero: numeric failure (p~1 <= 0 or non-finite)
   S_TRACE = 6,  // tr R
+  S_NORM = 7,   // > 0: the estimate is of R / tr R, products scaled by this
+                // factor (div / tr R); 0: R as given
   S_ENT = 8,    // estimate
   S_SE = 9,     // standard error
   S_ALPHA = 16  // alpha_0 .. alpha_m (Chebyshev) follow
@@ -135,8 +137,13 @@ hipError_t launch_power_rq(double *scal, const double *norm3, int32_t trial, hip
 // u = u_fixed > 0 ? u_fixed : min(1, c p~1); interval scalars and, for
 // Chebyshev, alpha_0..alpha_m (closed form of Lemma 3 when lo = 0,
 // interpolant at m+1 Chebyshev points otherwise).
+// norm_div > 0: the estimate is of R / tr R; S_NORM = norm_div / scal[S_TRACE]
+// (norm_div = the multiple of tr R that the trace kernel measured), p~1 and
+// the product scale are multiplied by it.
 hipError_t launch_setup_interval(double *scal, int32_t method, int32_t m, double c,
-                                 double u_fixed, double lo, hipStream_t st);
+                                 double u_fixed, double lo, hipStream_t st, double norm_div = 0.0);
+// S_NORM alone (random projection: singular values scaled by it).
+hipError_t launch_set_norm(double *scal, double norm_div, hipStream_t st);
 
 // ---- trace check -----------------------------------------------------------
 template <typename T>
@@ -292,6 +299,8 @@ template <typename T>
 hipError_t launch_batch_dense_step(const BatchStepArgs &ba, int32_t ntiles, int32_t wr,
                                    hipStream_t st);
 hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t st);
+// Zero `bytes` bytes at p (kernel stores, no memset node).
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 // R (compute copy, ld = ldr, zero columns n..ldr) <- src for every matrix.
 template <typename Tin, typename Tout>
 hipError_t launch_batch_convert(const BatchMat *mats, int32_t count, int64_t max_elems,
@@ -313,7 +322,8 @@ hipError_t launch_batch_power_reduce(const BatchMat *mats, int32_t count, const 
 hipError_t launch_batch_power_rq(const BatchMat *mats, int32_t count, const double *norm,
                                  int32_t trial, hipStream_t st);
 hipError_t launch_batch_setup(const BatchMat *mats, int32_t count, int32_t method, int32_t m,
-                              double c, double u_fixed, double lo, hipStream_t st);
+                              double c, double u_fixed, double lo, hipStream_t st,
+                              double norm_div = 0.0);
 hipError_t launch_batch_reduce(const BatchMat *mats, int32_t count, const double *part,
                                int32_t nslot, int64_t ldv, int32_t s, double *d, hipStream_t st);
 hipError_t launch_batch_final(const BatchMat *mats, int32_t count, const double *d, int32_t method,

@@ -310,9 +310,23 @@ hipError_t launch_power_rq(double *scal, const double *norm3, int32_t trial, hip
 // Interval [lo, u] and Chebyshev coefficients
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void setup_interval_body(double *__restrict__ scal, int32_t method,
-                                                    int32_t m, double c, double u_fixed, double lo) {
+                                                    int32_t m, double c, double u_fixed, double lo,
+                                                    double norm_div) {
   __shared__ double su;
   if (threadIdx.x == 0) {
+    // R / tr R (problem statement, unit trace): every eigenvalue, hence p~1,
+    // and every product R v are scaled by 1 / tr R
+    double nm = 1.0;
+    if (norm_div > 0.0) {
+      const double tr = scal[S_TRACE] / norm_div;
+      nm = 1.0 / tr;
+      if (!(tr > 0.0) || !isfinite(nm)) {
+        scal[S_FLAG] = 1.0;
+        nm = 1.0;
+      }
+      scal[S_NORM] = nm;
+      if (!(u_fixed > 0.0)) scal[S_P1] *= nm;
+    }
     double u;
     if (u_fixed > 0.0) {
       u = u_fixed;
@@ -325,10 +339,10 @@ __device__ __forceinline__ void setup_interval_body(double *__restrict__ scal, i
     scal[S_U] = u;
     scal[S_LO] = lo;
     if (method == 0) {  // Taylor: A = R/u, C = I - A
-      scal[S_A] = 1.0 / u;
+      scal[S_A] = nm / u;
       scal[S_B] = 1.0;
     } else {  // Chebyshev: X = a R - b I maps [lo, u] onto [-1, 1]
-      scal[S_A] = 2.0 / (u - lo);
+      scal[S_A] = nm * 2.0 / (u - lo);
       scal[S_B] = (u + lo) / (u - lo);
     }
     su = u;
@@ -370,13 +384,30 @@ __device__ __forceinline__ void setup_interval_body(double *__restrict__ scal, i
 }
 
 __global__ void setup_interval_kernel(double *__restrict__ scal, int32_t method, int32_t m,
-                                      double c, double u_fixed, double lo) {
-  setup_interval_body(scal, method, m, c, u_fixed, lo);
+                                      double c, double u_fixed, double lo, double norm_div) {
+  setup_interval_body(scal, method, m, c, u_fixed, lo, norm_div);
 }
 
 hipError_t launch_setup_interval(double *scal, int32_t method, int32_t m, double c, double u_fixed,
-                                 double lo, hipStream_t st) {
-  setup_interval_kernel<<<1, 256, 0, st>>>(scal, method, m, c, u_fixed, lo);
+                                 double lo, hipStream_t st, double norm_div) {
+  setup_interval_kernel<<<1, 256, 0, st>>>(scal, method, m, c, u_fixed, lo, norm_div);
+  return hipGetLastError();
+}
+
+__global__ void set_norm_kernel(double *__restrict__ scal, double norm_div) {
+  if (threadIdx.x != 0) return;
+  const double tr = scal[S_TRACE] / norm_div;
+  const double nm = 1.0 / tr;
+  if (!(tr > 0.0) || !isfinite(nm)) {
+    scal[S_FLAG] = 1.0;
+    scal[S_NORM] = 1.0;
+  } else {
+    scal[S_NORM] = nm;
+  }
+}
+
+hipError_t launch_set_norm(double *scal, double norm_div, hipStream_t st) {
+  set_norm_kernel<<<1, 64, 0, st>>>(scal, norm_div);
   return hipGetLastError();
 }
 
@@ -703,6 +734,32 @@ hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Zero bytes [p, p + bytes): 16-byte stores over the aligned bulk, byte
+// stores for the head and tail.  Used instead of a memset node so that a
+// captured sequence clears its buffers with kernels only.
+__global__ void zero_kernel(unsigned char *__restrict__ p, int64_t head, int64_t nvec, int64_t bytes) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint4 *v = (uint4 *)(p + head);
+  for (int64_t i = tid; i < nvec; i += stride) v[i] = make_uint4(0u, 0u, 0u, 0u);
+  const int64_t tail0 = head + 16 * nvec;
+  for (int64_t i = tid; i < head; i += stride) p[i] = 0;
+  for (int64_t i = tail0 + tid; i < bytes; i += stride) p[i] = 0;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  const uintptr_t a = (uintptr_t)p;
+  int64_t head = (int64_t)((16 - (a & 15)) & 15);
+  if ((size_t)head > bytes) head = (int64_t)bytes;
+  const int64_t nvec = ((int64_t)bytes - head) / 16;
+  const int64_t work = nvec > 0 ? nvec : (int64_t)bytes;
+  const int64_t blocks = (work + 255) / 256 < 2048 ? (work + 255) / 256 : 2048;
+  zero_kernel<<<(unsigned)(blocks > 0 ? blocks : 1), 256, 0, st>>>((unsigned char *)p, head, nvec,
+                                                                   (int64_t)bytes);
+  return hipGetLastError();
+}
+
 template <typename Tin, typename Tout>
 __global__ void batch_convert_kernel(const BatchMat *__restrict__ mats) {
   const BatchMat &M = mats[blockIdx.y];
@@ -839,13 +896,13 @@ hipError_t launch_batch_power_rq(const BatchMat *mats, int32_t count, const doub
 }
 
 __global__ void batch_setup_kernel(const BatchMat *__restrict__ mats, int32_t method, int32_t m,
-                                   double c, double u_fixed, double lo) {
-  setup_interval_body(mats[blockIdx.x].scal, method, m, c, u_fixed, lo);
+                                   double c, double u_fixed, double lo, double norm_div) {
+  setup_interval_body(mats[blockIdx.x].scal, method, m, c, u_fixed, lo, norm_div);
 }
 
 hipError_t launch_batch_setup(const BatchMat *mats, int32_t count, int32_t method, int32_t m,
-                              double c, double u_fixed, double lo, hipStream_t st) {
-  batch_setup_kernel<<<(unsigned)count, 256, 0, st>>>(mats, method, m, c, u_fixed, lo);
+                              double c, double u_fixed, double lo, hipStream_t st, double norm_div) {
+  batch_setup_kernel<<<(unsigned)count, 256, 0, st>>>(mats, method, m, c, u_fixed, lo, norm_div);
   return hipGetLastError();
 }
 

@@ -404,9 +404,11 @@ __global__ void rp_finish_kernel(const double *__restrict__ eig, int32_t N, int3
   }
   __syncthreads();
   if (tid == 0) {
+    // S_NORM > 0: singular values of (R / tr R) Pi = those of R Pi / tr R
+    const double nm = scal[S_NORM] > 0.0 ? scal[S_NORM] : 1.0;
     double h = 0.0;
     for (int i = 0; i < k && i < N; ++i) {
-      const double sg = sv[i];
+      const double sg = sv[i] * nm;
       sigma[i] = sg;
       if (sg > 0.0) h += sg * log(1.0 / sg);
     }

@@ -129,19 +129,22 @@ def test_clenshaw_flag_rules_without_device(ent):
                                         ctypes.byref(res)) == ent.EINVAL
 
 
-def test_host_array_rejected_before_any_kernel(ent):
-    # a descriptor that passes every argument rule but points at host memory
-    # is refused by the pointer check (here: no device at all), never launched
+def test_host_array_without_device_fails_cleanly(ent):
+    # a descriptor in host memory is copied to the device before anything
+    # reads it; with no device here, that copy-in is a device error, the
+    # result is left untouched and nothing is launched
     import numpy as np
 
     lib = ent._lib
     res = ent.EntResult()
+    res.entropy = 123.0
     host = np.eye(8) / 8.0
     M = ent.EntMatrix(8, ent.DENSE, ent.STORE_F64, 8, 0, host.ctypes.data, None, None)
-    assert lib.ent_entropy_estimate(ctypes.byref(M), 1, 10, 4, 0, None, ctypes.byref(res)) == ent.EINVAL
-    assert "access" in ent.last_error()
-    p1 = ctypes.c_double()
-    assert lib.ent_power_method(ctypes.byref(M), 5, 1, 0, None, ctypes.byref(p1)) == ent.EINVAL
+    assert lib.ent_entropy_estimate(ctypes.byref(M), 1, 10, 4, 0, None, ctypes.byref(res)) == ent.EDEVICE
+    assert res.entropy == 123.0
+    p1 = ctypes.c_double(7.0)
+    assert lib.ent_power_method(ctypes.byref(M), 5, 1, 0, None, ctypes.byref(p1)) == ent.EDEVICE
+    assert p1.value == 7.0
 
 
 def test_builder_loads_without_the_package():

@@ -1,0 +1,198 @@
+"""Boundary rules of the C ABI on the GPU: R / tr R on request
+(ENT_FLAG_NORMALIZE), matrices passed in host memory (copied in), the
+workspace cap (ENT_ENOMEM, output untouched), and the learned selector on a
+CSR R stored in FP64.
+
+The problem statement (Section 1.1) takes R with unit trace; the normalising
+flag estimates H(R / tr R), checked against the oracle on R / tr R.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1801_01072_amd as ent  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def rel_per_probe(per, ref):
+    return float(np.max(np.abs(per - ref.per_probe)) / max(np.mean(np.abs(ref.per_probe)), 1e-2))
+
+
+# ------------------------------------------------------------- normalise ----
+@pytest.mark.parametrize("method", ["chebyshev", "taylor"])
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 2e-5), ("bf16x3", 2e-5)])
+def test_normalize_dense_matches_oracle_on_unit_trace(orc, method, precision, tol):
+    n, m, s, seed, tau = 150, 14, 24, 31, 3.7
+    R = W.dense_density(W.spectrum_exp(n, 25.0), 41)
+    Rd = torch.from_numpy(R * tau).to(DEV)
+    with pytest.raises(ent.EntropyError) as ei:
+        ent.entropy_estimate(Rd, method, m, s, seed, precision=precision)
+    assert ei.value.status == ent.ENOTDENSITY
+    gpu, per, _ = ent.entropy_estimate_detail(Rd, method, m, s, seed, precision=precision,
+                                              flags=ent.FLAG_NORMALIZE, probe_dist="gaussian")
+    # the oracle on the stored values divided by their trace
+    Rs = R * tau
+    ref = orc.estimate(Rs / np.trace(Rs), 0 if method == "taylor" else 1, m, s, seed, dist=1)
+    err = rel_per_probe(per, ref)
+    print(f"[normalize {method} {precision}] H gpu={gpu.entropy:.12f} oracle={ref.entropy:.12f} "
+          f"per-probe err={err:.2e}", flush=True)
+    assert err <= tol
+    # FP32 and BF16x3 run the power method on a rounded copy (FP32) or the
+    # bf16 split of the FP64-stored R
+    p1_tol = 1e-12 if precision == "f64" else 1e-6
+    assert gpu.p1_est == pytest.approx(ref.p1_est, rel=p1_tol)
+    assert gpu.u == pytest.approx(ref.u, rel=p1_tol)
+
+
+def test_normalize_csr_hermitian_and_randproj(orc):
+    # CSR (banded kernels), FP64
+    n, m, s, seed, tau = 3000, 12, 16, 5, 0.25
+    rp, ci, val, _ = W.banded_density_csr(n, 8, seed=7)
+    Rc = (torch.from_numpy(rp).to(DEV), torch.from_numpy(ci).to(DEV), torch.from_numpy(val * tau).to(DEV), n)
+    gpu, per, _ = ent.entropy_estimate_detail(Rc, "chebyshev", m, s, seed, flags=ent.FLAG_NORMALIZE)
+    vs = val * tau
+    ref = orc.estimate((rp, ci, vs / vs[np.repeat(np.arange(n), np.diff(rp)) == ci].sum(), n), 1, m, s, seed)
+    assert rel_per_probe(per, ref) <= 1e-10
+    # Hermitian: trace of the real part
+    nh = 60
+    Rh = W.hermitian_density(W.spectrum_exp(nh, 9.0), 3) * 2.5
+    gpu, per, _ = ent.entropy_estimate_detail(torch.from_numpy(Rh).to(DEV), "chebyshev", 10, 8, 4,
+                                              flags=ent.FLAG_NORMALIZE, probe_dist="gaussian")
+    refh = orc.zestimate(Rh / np.trace(Rh).real, 1, 10, 8, 4, dist=1, u_override=1.0)
+    assert rel_per_probe(per, refh) <= 1e-10
+    # random projection: singular values scale with 1 / tr R
+    nr, k, sw = 200, 6, 20
+    Rr = W.dense_density(W.spectrum_linear_topk(nr, k), 17) * 4.0
+    gpu, sig, _ = ent.entropy_estimate_detail(torch.from_numpy(Rr).to(DEV), "randproj", 1, 1, 9,
+                                              rank_k=k, sketch_width=sw, flags=ent.FLAG_NORMALIZE)
+    h, sig_ref = orc.rp_entropy(Rr / np.trace(Rr), sw, k, 9)
+    assert np.max(np.abs(sig - sig_ref)) <= 1e-10 * np.max(sig_ref)
+    assert gpu.entropy == pytest.approx(h, rel=1e-10)
+
+
+def test_normalize_batch(orc):
+    rng = np.random.default_rng(4)
+    host, mats = [], []
+    for i, n in enumerate((40, 97, 130)):
+        R = W.dense_density(W.spectrum_dirichlet(n, n, 0.5, rng), 70 + i) * (1.0 + i)
+        host.append(R)
+        mats.append(torch.from_numpy(R).to(DEV))
+    res = ent.entropy_estimate_batched(mats, "chebyshev", 10, 12, 50, precision="f64",
+                                       flags=ent.FLAG_NORMALIZE)
+    for b, R in enumerate(host):
+        ref = orc.estimate(R / np.trace(R), 1, 10, 12, 50 + b)
+        assert res[b].entropy == pytest.approx(ref.entropy, rel=1e-10)
+
+
+def test_normalize_rejects_nonpositive_trace():
+    n = 32
+    R = W.dense_density(W.spectrum_inverse(n), 2)
+    for bad in (-R, np.zeros_like(R)):
+        with pytest.raises(ent.EntropyError) as ei:
+            ent.entropy_estimate(torch.from_numpy(bad).to(DEV), "chebyshev", 8, 4, 1, flags=ent.FLAG_NORMALIZE)
+        assert ei.value.status == ent.ENOTDENSITY
+
+
+# -------------------------------------------------------- host matrices ----
+def test_host_dense_and_csr_are_copied_in():
+    n, m, s, seed = 300, 12, 20, 8
+    R = W.dense_density(W.spectrum_exp(n, 40.0), 9)
+    dev = ent.entropy_estimate_detail(torch.from_numpy(R).to(DEV), "chebyshev", m, s, seed)
+    for host in (torch.from_numpy(R), torch.from_numpy(R).pin_memory()):
+        got = ent.entropy_estimate_detail(host, "chebyshev", m, s, seed)
+        assert got[0].entropy == dev[0].entropy and np.array_equal(got[1], dev[1])
+    # a host view with ld > n
+    big = np.zeros((n, n + 7))
+    big[:, :n] = R
+    got = ent.entropy_estimate(torch.from_numpy(big)[:, :n], "chebyshev", m, s, seed)
+    assert got.entropy == dev[0].entropy
+    assert ent.power_method(torch.from_numpy(R), 20, 2, seed) == ent.power_method(
+        torch.from_numpy(R).to(DEV), 20, 2, seed)
+    # CSR arrays on the host (all, or only some of them)
+    csr = W.banded_density_csr(2000, 8, seed=3)
+    rp, ci, val, nn = csr
+    d_all = (torch.from_numpy(rp).to(DEV), torch.from_numpy(ci).to(DEV), torch.from_numpy(val).to(DEV), nn)
+    ref = ent.entropy_estimate(d_all, "chebyshev", 10, 8, 2)
+    h_all = (torch.from_numpy(rp), torch.from_numpy(ci), torch.from_numpy(val), nn)
+    mixed = (torch.from_numpy(rp), d_all[1], torch.from_numpy(val), nn)
+    for Rx in (h_all, mixed):
+        assert ent.entropy_estimate(Rx, "chebyshev", 10, 8, 2).entropy == ref.entropy
+    # Hermitian host storage
+    Rh = W.hermitian_density(W.spectrum_exp(40, 7.0), 2)
+    a = ent.entropy_estimate(torch.from_numpy(Rh), "chebyshev", 8, 6, 3)
+    b = ent.entropy_estimate(torch.from_numpy(Rh).to(DEV), "chebyshev", 8, 6, 3)
+    assert a.entropy == b.entropy
+
+
+def test_host_matrix_errors_still_checked():
+    # a host matrix that is not a density matrix: copied in, then refused by the trace check
+    R = W.dense_density(W.spectrum_inverse(20), 2) * 2.0
+    with pytest.raises(ent.EntropyError) as ei:
+        ent.entropy_estimate(torch.from_numpy(R), "chebyshev", 8, 4, 1)
+    assert ei.value.status == ent.ENOTDENSITY
+    # a malformed host CSR structure: copied in, then refused by the device check
+    rp = np.array([0, 2, 1, 3], dtype=np.int64)
+    ci = np.array([0, 1, 2], dtype=np.int32)
+    val = np.array([0.5, 0.25, 0.25])
+    with pytest.raises(ent.EntropyError) as ei:
+        ent.entropy_estimate((torch.from_numpy(rp), torch.from_numpy(ci), torch.from_numpy(val), 3),
+                             "chebyshev", 4, 4, 1)
+    assert ei.value.status == ent.EINVAL
+
+
+# ------------------------------------------------------ workspace limit ----
+def test_workspace_limit_forces_enomem_and_leaves_output():
+    n, m, s = 512, 10, 64
+    R = torch.from_numpy(W.dense_density(W.spectrum_inverse(n), 1)).to(DEV)
+    M = ent.as_matrix(R)
+    o = ent.options()
+    try:
+        ent.set_workspace_limit(1 << 20)       # 1 MiB: below what n = 512, s = 64 needs
+        res = ent.EntResult()
+        res.entropy = 42.0
+        st = ent._lib.ent_entropy_estimate(ctypes.byref(M), ent.CHEBYSHEV, m, s, 1, ctypes.byref(o),
+                                           ctypes.byref(res))
+        assert st == ent.ENOMEM
+        assert "limit" in ent.last_error()
+        assert res.entropy == 42.0
+        # a host matrix whose device copy alone exceeds the cap
+        Rh = torch.from_numpy(W.dense_density(W.spectrum_inverse(n), 1))
+        Mh = ent.as_matrix(Rh)
+        st = ent._lib.ent_entropy_estimate(ctypes.byref(Mh), ent.CHEBYSHEV, m, s, 1, ctypes.byref(o),
+                                           ctypes.byref(res))
+        assert st == ent.ENOMEM and res.entropy == 42.0
+        # batches and the power method obey the same cap
+        with pytest.raises(ent.EntropyError) as ei:
+            ent.entropy_estimate_batched([R, R], "chebyshev", m, s, 1)
+        assert ei.value.status == ent.ENOMEM
+    finally:
+        ent.set_workspace_limit(0)
+    assert np.isfinite(ent.entropy_estimate(R, "chebyshev", m, s, 1).entropy)
+
+
+# ------------------------------------------- selector on FP64-stored CSR ----
+def test_auto_on_fp64_csr(orc):
+    from paper_1801_01072_amd import learned as L
+
+    ent.selector_load(L.load())
+    n, s, seed = 4000, 32, 6
+    csr = W.banded_density_csr(n, 8, seed=12)
+    rp, ci, val, _ = csr
+    Rc = (torch.from_numpy(rp).to(DEV), torch.from_numpy(ci).to(DEV), torch.from_numpy(val).to(DEV), n)
+    f, y = ent.selector_features(Rc, seed)
+    assert np.all(np.isfinite(f)) and np.all(np.isfinite(y))
+    r, per, _ = ent.entropy_estimate_detail(Rc, "auto", 40, s, seed, precision="f64")
+    ref = orc.estimate(csr, 1, r.degree, s, seed, lo=r.lo, u_override=r.u)
+    err = rel_per_probe(per, ref)
+    print(f"[auto csr f64] m={r.degree} lo={r.lo:.3e} fell_back={r.fell_back} err={err:.2e}", flush=True)
+    assert err <= 1e-9
