@@ -263,6 +263,34 @@ ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int3
                                        ent_result *out, double *per_probe, double *moments);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * Taylor / Chebyshev estimate as ent_entropy_estimate_detail (same kernels,
+ * same results), with every workspace buffer carved from a fixed device
+ * array of ENT_NOALLOC_SCRATCH_BYTES compiled into the library -- one copy
+ * per GPU, held from the library's load until the process ends -- instead of
+ * the cached workspace.  No hipMalloc, hipFree or allocating library routine
+ * is called, and no phase events are recorded (ent_timing is not updated).
+ *  - R must be real (ENT_STORE_F64 / ENT_STORE_F32), dense or CSR, with
+ *    every array in device memory of the current device (host arrays would
+ *    need a device copy): ENT_EINVAL otherwise.  Hermitian storage,
+ *    ENT_RANDPROJ and ENT_AUTO: ENT_EUNSUPPORTED.
+ *  - An estimate whose workspace exceeds ENT_NOALLOC_SCRATCH_BYTES returns
+ *    ENT_ENOMEM (the message states both sizes) before any kernel runs.
+ *    Dense FP64 at n = 8192 with 256 probes and degree 50 needs about 64 MB.
+ *  - Every call on one GPU uses that GPU's one array, and the next call
+ *    overwrites what the last one left there; the library runs such calls
+ *    one at a time (a per-device lock held until the call has synchronised
+ *    its stream).  Work enqueued on the same memory by other means would
+ *    race with it.
+ * Arguments, outputs and errors otherwise as ent_entropy_estimate_detail.
+ */
+#define ENT_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+ent_status ent_entropy_estimate_noalloc(const ent_matrix *R, int32_t method, int32_t degree,
+                                        int32_t probes, uint64_t seed, const ent_options *opt,
+                                        ent_result *out, double *per_probe, double *moments);
+
+/*
  * Algorithm 4 (Appendix A): q trials of t power iterations from random sign
  * vectors, each iterate divided by its 2-norm, Rayleigh quotient of the last
  * iterate, maximum over trials.  *p1 (host) receives p~1.  Hermitian R: the

@@ -92,6 +92,10 @@ _SIGNATURES = {
                                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                                    ctypes.POINTER(EntOptions),
                                                    ctypes.POINTER(EntResult), _P, _P]),
+    "ent_entropy_estimate_noalloc": (ctypes.c_int, [ctypes.POINTER(EntMatrix), ctypes.c_int32,
+                                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                                    ctypes.POINTER(EntOptions),
+                                                    ctypes.POINTER(EntResult), _P, _P]),
     "ent_power_method": (ctypes.c_int, [ctypes.POINTER(EntMatrix), ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_uint64, _P, ctypes.POINTER(ctypes.c_double)]),
     "ent_chebyshev_coeffs": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P]),
@@ -276,6 +280,24 @@ def entropy_estimate_detail(R, method="chebyshev", degree=30, probes=50, seed=0,
                                             per.ctypes.data_as(_P), mom.ctypes.data_as(_P)))
     if meth == RANDPROJ:
         return _result(res), per[:nper], None
+    return _result(res), per, mom.reshape(degree + 1, probes)
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def entropy_estimate_noalloc(R, method="chebyshev", degree=30, probes=50, seed=0, **opts):
+    """entropy_estimate_detail through the entry point that allocates no
+    device memory (fixed per-device scratch; Taylor / Chebyshev only)."""
+    M = as_matrix(R)
+    o = options(**opts)
+    res = EntResult()
+    meth = _METHODS.get(method, method)
+    per = np.zeros(probes, dtype=np.float64)
+    mom = np.zeros((degree + 1) * probes, dtype=np.float64)
+    _check(_lib.ent_entropy_estimate_noalloc(ctypes.byref(M), meth, degree, probes, seed,
+                                             ctypes.byref(o), ctypes.byref(res),
+                                             per.ctypes.data_as(_P), mom.ctypes.data_as(_P)))
     return _result(res), per, mom.reshape(degree + 1, probes)
 
 

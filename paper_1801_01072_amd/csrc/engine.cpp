@@ -377,22 +377,42 @@ struct Opts {
   int64_t probe_rows = -1;
   // The matrix's trace is this multiple of tr R (2 for the real form).
   double trace_div = 1.0;
+  // The no-allocation entry point: workspace from the fixed scratch array,
+  // no phase events.
   bool no_alloc = false;
 };
 
 // The memory one estimate carves its buffers from, held (locked) for the
 // whole estimate: the device's cached workspace, grown with hipMalloc on
-// demand.
+// demand, or -- for the no-allocation entry point -- the device's fixed
+// scratch array, whose size is then a hard limit.
 struct WsLease {
   DeviceWorkspace *ws = nullptr;
+  void *fixed = nullptr;
   std::unique_lock<std::mutex> lk;
-  ent_status acquire(int dev, bool) {
+  ent_status acquire(int dev, bool no_alloc) {
+    if (no_alloc) {
+      std::mutex *mu = nullptr;
+      const hipError_t e = ent::noalloc_scratch(dev, &fixed, &mu);
+      if (e != hipSuccess)
+        return fail(ENT_EDEVICE, "address of the fixed scratch array on device %d: %s", dev, hipGetErrorString(e));
+      lk = std::unique_lock<std::mutex>(*mu);
+      return ENT_OK;
+    }
     ws = workspace_for(dev);
     lk = std::unique_lock<std::mutex>(ws->mu);
     return ENT_OK;
   }
-  void *ptr() const { return ws->ptr; }
-  ent_status ensure(size_t need) { return ensure_workspace(ws, need); }
+  void *ptr() const { return fixed ? fixed : ws->ptr; }
+  ent_status ensure(size_t need) {
+    if (fixed) {
+      if (need > ent::kNoAllocScratchBytes)
+        return fail(ENT_ENOMEM, "the estimate needs %zu bytes of workspace; the fixed scratch of the "
+                                "no-allocation entry point holds %zu bytes", need, ent::kNoAllocScratchBytes);
+      return ENT_OK;
+    }
+    return ensure_workspace(ws, need);
+  }
 };
 
 Opts resolve_options(const ent_options *opt) {
@@ -2106,6 +2126,9 @@ ent_status power_method_device(const ent_matrix *R, int32_t t, int32_t q, uint64
   return ENT_OK;
 }
 
+static_assert(ENT_NOALLOC_SCRATCH_BYTES == ent::kNoAllocScratchBytes,
+              "the header's scratch size is the library's");
+
 // Argument rules shared by the polynomial estimate entry points.
 ent_status check_poly_args(int32_t method, int32_t degree, int32_t probes, const Opts &op) {
   if (degree < 1) return fail(ENT_EINVAL, "degree = %d < 1", degree);
@@ -2172,6 +2195,37 @@ ent_status ent_entropy_estimate_detail(const ent_matrix *R, int32_t method, int3
 ent_status ent_entropy_estimate(const ent_matrix *R, int32_t method, int32_t degree, int32_t probes,
                                 uint64_t seed, const ent_options *opt, ent_result *out) {
   return ent_entropy_estimate_detail(R, method, degree, probes, seed, opt, out, nullptr, nullptr);
+}
+
+ent_status ent_entropy_estimate_noalloc(const ent_matrix *R, int32_t method, int32_t degree,
+                                        int32_t probes, uint64_t seed, const ent_options *opt,
+                                        ent_result *out, double *per_probe, double *moments) {
+  g_last_error.clear();
+  ent_status rc = validate_matrix(R, false);
+  if (rc != ENT_OK) return rc;
+  if (!out) return fail(ENT_EINVAL, "out is NULL");
+  Opts op = resolve_options(opt);
+  rc = validate_options(op.o);
+  if (rc != ENT_OK) return rc;
+  if (method != ENT_TAYLOR && method != ENT_CHEBYSHEV)
+    return fail(method == ENT_RANDPROJ || method == ENT_AUTO ? ENT_EUNSUPPORTED : ENT_EINVAL,
+                "the no-allocation entry point runs the Taylor and Chebyshev estimators only (method %d)",
+                method);
+  rc = check_poly_args(method, degree, probes, op);
+  if (rc != ENT_OK) return rc;
+  // a host array would need a device copy, i.e. an allocation
+  const void *arrays[3] = {R->values, R->layout == ENT_CSR ? (const void *)R->row_ptr : nullptr,
+                           R->layout == ENT_CSR && R->nnz > 0 ? (const void *)R->col_idx : nullptr};
+  for (const void *a : arrays)
+    if (a && is_host_memory(a))
+      return fail(ENT_EINVAL, "the no-allocation entry point takes device arrays only");
+  rc = check_matrix_memory(R);
+  if (rc != ENT_OK) return rc;
+  op.no_alloc = true;
+  ent_result tmp{};
+  rc = poly_dispatch(R, method, degree, probes, seed, op, &tmp, per_probe, moments, nullptr);
+  if (rc == ENT_OK) *out = tmp;
+  return rc;
 }
 
 ent_status ent_power_method(const ent_matrix *R, int32_t t, int32_t q, uint64_t seed, void *stream,

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 namespace ent {
 
 // Device scalar block (FP64).  The power method, the interval and the
@@ -371,5 +373,12 @@ hipError_t launch_reduce_moments(const double *part, int32_t nslot, int32_t ntil
 // Per-probe values and the estimate (Algorithms 1-2 output line).
 hipError_t launch_final(const double *d, double *scal, int32_t method, int32_t m, int32_t s,
                         double *h, hipStream_t st);
+
+// ---- fixed scratch of the no-allocation entry point ---------------------------
+// Size of the per-device scratch array (ENT_NOALLOC_SCRATCH_BYTES).
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+// This device's copy of the scratch array (looked up once per device, with
+// that device current) and the lock that serialises the calls using it.
+hipError_t noalloc_scratch(int dev, void **ptr, std::mutex **use);
 
 }  // namespace ent
