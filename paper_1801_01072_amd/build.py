@@ -27,13 +27,22 @@ COMMON = [
 ]
 
 
+# Per-file code generation options.  The dense step keeps its MFMA
+# accumulators in ordinary VGPRs (the VGPR form of the MFMA instructions), so
+# they are not copied between accumulation and ordinary registers around
+# every iteration of its K loop.
+EXTRA = {
+    "kernels_dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -31,41 +31,129 @@
 
 namespace ent {
 
+// s_waitcnt vmcnt(N) in the gfx9 encoding, expcnt and lgkmcnt left free.
+template <int N>
+__device__ __forceinline__ void dense_wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt immediate");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+
+// Chunk geometry of the dense step: BK columns of R per chunk (32, 16 or 8),
+// KPL = BK/4 of them per lane; one stage holds the chunk's V_k rows (BK x BN,
+// shared by the 4 waves) and each wave's A values (WR 16-row slabs x BK); the
+// NST stages take at most 60 KB, so two workgroups fit on a CU.
+template <typename T, int BN, int WR>
+struct DenseChunk {
+  static constexpr int NST = 3;                      // stages (prefetch distance NST - 1)
+  static constexpr int BUDGET = 61440;
+  static_assert(NST >= 3 && NST <= 4, "the waits cover three or four stages");
+  static constexpr int ES = (int)sizeof(T);
+  static constexpr int VEC = 16 / ES;                // elements per 16-byte piece
+  static constexpr int RB = BN * ES;                 // bytes per V row
+  static constexpr int stage_bytes(int bk) { return bk * RB + 64 * WR * bk * ES; }
+  static constexpr int BK = (NST * stage_bytes(32) <= BUDGET) ? 32
+                          : (NST * stage_bytes(16) <= BUDGET || 2 * ES < 16) ? 16 : 8;
+  static constexpr int KPL = BK / 4;                 // k values per lane per chunk
+  static constexpr int G = RB / 16;                  // 16-byte groups per V row
+  static constexpr int VBYTES = BK * RB;
+  static constexpr int NVL = BK * G / 256;           // V pieces per wave (direct loads)
+  static constexpr int APL = KPL / VEC;              // A pieces per lane and slab
+  static constexpr int NAL = WR * APL;               // A direct loads per wave
+  static constexpr int ABYTES = 4 * NAL * 1024;      // A of the 4 waves
+  static_assert(KPL % VEC == 0, "a lane's A values must be whole 16-byte pieces");
+  static_assert((BK * G) % 256 == 0, "V pieces must split over the 4 waves");
+  static_assert(4 * ES <= G, "V rows too short for the swizzle");
+  // V row r sits at r * RB bytes, its 16-byte groups XOR-swizzled so that
+  // the four 16-lane groups of an MFMA B-operand read (rows t, KPL+t, 2KPL+t,
+  // 3KPL+t, 16 consecutive probes each) fall on disjoint banks
+  __device__ static constexpr int swz(int r) { return ((r / KPL) & 3) * ES; }
+  __device__ static int voff(int r, int col) {
+    return r * RB + (((col / VEC) ^ swz(r)) << 4) + (col % VEC) * ES;
+  }
+};
+
 // Body of one tile: rows [64*WR*tm, +64*WR) (wave w owns WR 16-row slabs),
 // probe columns [BN*tn, +BN), product columns [kbeg, kend) (kbeg a multiple
 // of 32; kend a multiple of 32 or >= n).  Shared by the single-matrix kernel
 // and the grouped (batched) kernel.  With yout the raw products go to
 // yout[row][ldv] (every row of the tile) instead of the epilogue.
+//
+// Pipeline over chunks of BK columns, three stages deep: the chunk's V_k rows
+// and each wave's A values go from global memory straight into LDS (direct
+// loads, no registers), two chunks ahead of the MFMAs that read them; every
+// wait on them is explicit (vmcnt), one barrier per chunk.  Lane (m, q) of a
+// wave loads R[row m][k0 + KPL q .. + KPL) of each of its slabs, which it
+// reads back from its own 16-byte slots: MFMA k-slot q of call t is column
+// KPL q + t (the k order inside a chunk is permuted consistently for A and
+// B).  A ragged last chunk (n not a multiple of BK) reads A into registers,
+// column min(k, n - 1) element by element: V_k is zero in rows k >= n, so
+// those products vanish.
 template <typename T, int BN, int WR>
 __device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, int tn, int64_t kbeg,
                                                 int64_t kend, T *yout) {
   using M = Mfma16<T>;
   using v4 = typename M::v4;
-  constexpr int BM = 64 * WR, BK = 32, PAD = 2, LDL = BN + PAD;
+  using C = DenseChunk<T, BN, WR>;
+  constexpr int BM = 64 * WR, BK = C::BK, KPL = C::KPL, VEC = C::VEC;
   constexpr int NSUB = BN / 16;
-  constexpr int VEC = 16 / (int)sizeof(T);
-  constexpr int VPR = BN / VEC;
-  constexpr int NV = BK * VPR / 256;
+  constexpr int NVL = C::NVL, NAL = C::NAL, APL = C::APL;
   typedef T vec_t __attribute__((ext_vector_type(VEC)));
 
-  __shared__ __attribute__((aligned(16))) T Vs[BK * LDL];
-  __shared__ double red[2][4][BN];
+  // stage s at lds + s * STAGE: the V_k chunk (VBYTES), then the A values of
+  // the 4 waves (ABYTES)
+  constexpr int STAGE = C::VBYTES + C::ABYTES, NST = C::NST;
+  // one LDS array (the epilogue's per-wave dot sums reuse it after the
+  // products): with a single LDS object the compiler adds no waits of its own
+  // between the direct loads into one stage and the reads of another
+  static_assert(NST * STAGE >= 2 * 4 * BN * 8, "the dot sums fit in the stages");
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[NST * STAGE];
+  double(*red)[4][BN] = (double(*)[4][BN])lds;
 
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t n = a.n, ldv = a.ldv;
   const T *__restrict__ R = (const T *)a.R;
   const T *__restrict__ Vk = (const T *)a.Vk;
   const int64_t col0 = (int64_t)tn * BN;
   const int m16 = lane & 15, kq = lane >> 4;
   const int64_t wrow0 = (int64_t)tm * BM + 16 * WR * w;  // first row of this wave
-  bool arow_ok[WR];
+  // rows beyond n read row n - 1: their products are discarded (zeroed in the
+  // epilogue and in yout)
   const T *Arow[WR];
 #pragma unroll
   for (int f = 0; f < WR; ++f) {
     const int64_t arow = wrow0 + 16 * f + m16;
-    arow_ok[f] = arow < n;
-    Arow[f] = R + (arow_ok[f] ? arow : 0) * a.ldr;
+    Arow[f] = R + (arow < n ? arow : n - 1) * a.ldr + KPL * kq;
   }
+  // V piece q = (i*4 + w)*64 + lane of a chunk: row q / G, swizzled group q % G
+  int64_t vsrc[NVL];
+#pragma unroll
+  for (int i = 0; i < NVL; ++i) {
+    const int q = (i * 4 + w) * 64 + lane;
+    const int r = q / C::G, gs = q % C::G;
+    vsrc[i] = (int64_t)r * ldv + col0 + (int64_t)(gs ^ C::swz(r)) * VEC;
+  }
+
+  const int nfull = (int)((kend - kbeg) / BK);
+  const bool ragged = kbeg + (int64_t)nfull * BK < kend;
+
+  using LdsPtr = __attribute__((address_space(3))) void *;
+  auto issue_v = [&](int c, unsigned char *st) {
+    const T *vb = Vk + (kbeg + (int64_t)c * BK) * ldv;
+#pragma unroll
+    for (int i = 0; i < NVL; ++i)
+      __builtin_amdgcn_global_load_lds((const void *)(vb + vsrc[i]), (LdsPtr)(st + (i * 4 + w) * 1024), 16, 0, 0);
+  };
+  auto issue = [&](int c, unsigned char *st) {
+    issue_v(c, st);
+    const int64_t kc = kbeg + (int64_t)c * BK;
+#pragma unroll
+    for (int f = 0; f < WR; ++f)
+#pragma unroll
+      for (int h = 0; h < APL; ++h)
+        __builtin_amdgcn_global_load_lds((const void *)(Arow[f] + kc + h * VEC),
+                                         (LdsPtr)(st + C::VBYTES + ((w * WR + f) * APL + h) * 1024), 16, 0, 0);
+  };
 
   v4 acc[WR][NSUB];
 #pragma unroll
@@ -73,71 +161,107 @@ __device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, 
 #pragma unroll
     for (int c = 0; c < NSUB; ++c) acc[f][c] = v4{0, 0, 0, 0};
 
-  vec_t vreg[NV];
-  T areg[WR][8];
-
-  auto load_v = [&](int64_t kc) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int idx = tid + i * 256;
-      const int r = idx / VPR, cv = idx % VPR;
-      vreg[i] = *(const vec_t *)(Vk + (kc + r) * ldv + col0 + cv * VEC);
-    }
+  // operands of one chunk in registers: this lane's A values (APL 16-byte
+  // pieces per slab) and B values (KPL x NSUB)
+  struct Frag {
+    vec_t a[WR][APL];
+    T b[KPL][NSUB];
   };
-  auto load_a = [&](int64_t kc) {
-    const int64_t k0 = kc + 8 * kq;
-#pragma unroll
-    for (int f = 0; f < WR; ++f) {
-      if (arow_ok[f] && k0 + 8 <= n) {
-#pragma unroll
-        for (int h = 0; h < 8 / VEC; ++h) {
-          const vec_t v = *(const vec_t *)(Arow[f] + k0 + h * VEC);
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) areg[f][h * VEC + e] = v[e];
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) areg[f][t] = (arow_ok[f] && k0 + t < n) ? Arow[f][k0 + t] : T(0);
-      }
-    }
-  };
-  auto store_v = [&]() {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int idx = tid + i * 256;
-      const int r = idx / VPR, cv = idx % VPR;
-      T *dst = Vs + r * LDL + cv * VEC;
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) dst[e] = vreg[i][e];
-    }
-  };
-
-  load_v(kbeg);
-  load_a(kbeg);
-  for (int64_t kc = kbeg; kc < kend; kc += BK) {
-    store_v();
-    T acur[WR][8];
+  auto read_frag = [&](Frag &fr, const unsigned char *st) {
 #pragma unroll
     for (int f = 0; f < WR; ++f)
 #pragma unroll
-      for (int t = 0; t < 8; ++t) acur[f][t] = areg[f][t];
-    __syncthreads();
-    if (kc + BK < kend) {
-      load_v(kc + BK);
-      load_a(kc + BK);
-    }
+      for (int h = 0; h < APL; ++h)
+        fr.a[f][h] = *(const vec_t *)(st + C::VBYTES + ((w * WR + f) * APL + h) * 1024 + 16 * lane);
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const T *brow = Vs + (8 * kq + t) * LDL + m16;
+    for (int t = 0; t < KPL; ++t)
 #pragma unroll
-      for (int c = 0; c < NSUB; ++c) {
-        const T bv = brow[16 * c];
+      for (int c2 = 0; c2 < NSUB; ++c2) fr.b[t][c2] = *(const T *)(st + C::voff(KPL * kq + t, 16 * c2 + m16));
+  };
+  auto mfma_frag = [&](const Frag &fr) {
 #pragma unroll
-        for (int f = 0; f < WR; ++f) acc[f][c] = M::mma(acur[f][t], bv, acc[f][c]);
-      }
-    }
-    __syncthreads();
+    for (int t = 0; t < KPL; ++t)
+#pragma unroll
+      for (int c2 = 0; c2 < NSUB; ++c2)
+#pragma unroll
+        for (int f = 0; f < WR; ++f) acc[f][c2] = M::mma(fr.a[f][t / VEC][t % VEC], fr.b[t][c2], acc[f][c2]);
+  };
+
+  // Chunk j is loaded into stage j % NST at step j - NST (direct loads) and
+  // read into registers at step j - 1, after that step's barrier; step j
+  // multiplies it.  Step c: wait until this wave's loads of chunk c + 1 have
+  // landed and its reads of chunk c have returned, barrier (every wave's part
+  // of chunk c + 1 landed; every wave done reading chunk c, whose stage chunk
+  // c + NST now takes), issue chunk c + NST, read chunk c + 1, multiply chunk c.
+  constexpr int PER = NVL + NAL;  // direct loads per wave per chunk
+  for (int c = 0; c < NST; ++c)
+    if (c < nfull) issue(c, lds + c * STAGE);
+  Frag fx, fy;
+  // wait until at most k chunks' loads of this wave are in flight (k < NST)
+  auto wait_chunks = [&](int k) {
+    if (NST >= 4 && k >= 3)
+      dense_wait_vm<(NST >= 4 ? 3 : 0) * PER>();
+    else if (k >= 2)
+      dense_wait_vm<2 * PER>();
+    else if (k >= 1)
+      dense_wait_vm<PER>();
+    else
+      dense_wait_vm<0>();
+  };
+  auto step = [&](int c, int s0, Frag &cur, Frag &nxt) {
+    // chunks issued after chunk c + 1: c + 2 .. min(c + NST - 1, nfull - 1)
+    const int ahead = nfull - 2 - c < NST - 2 ? nfull - 2 - c : NST - 2;
+    wait_chunks(ahead);
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's reads of chunk c returned
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    if (c + NST < nfull) issue(c + NST, lds + s0 * STAGE);
+    if (c + 1 < nfull) read_frag(nxt, lds + (s0 == NST - 1 ? 0 : s0 + 1) * STAGE);
+    mfma_frag(cur);
+  };
+  if (nfull > 0) {
+    wait_chunks(nfull - 1 < NST - 1 ? nfull - 1 : NST - 1);  // chunk 0 landed
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    read_frag(fx, lds);
   }
+  int c = 0, s0 = 0;
+  for (; c + 1 < nfull; c += 2) {
+    step(c, s0, fx, fy);
+    s0 = s0 == NST - 1 ? 0 : s0 + 1;
+    step(c + 1, s0, fy, fx);
+    s0 = s0 == NST - 1 ? 0 : s0 + 1;
+  }
+  if (c < nfull) {
+    step(c, s0, fx, fy);
+    s0 = s0 == NST - 1 ? 0 : s0 + 1;
+  }
+  if (ragged) {
+    // the stage this chunk takes (s0) was last read at step nfull - NST - 1,
+    // before barriers every wave has passed; its A values come into
+    // registers element by element, column min(k, n - 1)
+    unsigned char *st = lds + s0 * STAGE;
+    dense_wait_vm<0>();
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    issue_v(nfull, st);
+    const int64_t k0 = kbeg + (int64_t)nfull * BK + KPL * kq;
+    Frag fr;
+#pragma unroll
+    for (int f = 0; f < WR; ++f)
+#pragma unroll
+      for (int t = 0; t < KPL; ++t) fr.a[f][t / VEC][t % VEC] = (Arow[f] - KPL * kq)[k0 + t < n ? k0 + t : n - 1];
+    dense_wait_vm<0>();
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < KPL; ++t)
+#pragma unroll
+      for (int c2 = 0; c2 < NSUB; ++c2) fr.b[t][c2] = *(const T *)(st + C::voff(KPL * kq + t, 16 * c2 + m16));
+    mfma_frag(fr);
+  }
+  __syncthreads();
 
   if (yout) {
 #pragma unroll
@@ -145,8 +269,10 @@ __device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, 
 #pragma unroll
       for (int f = 0; f < WR; ++f)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          yout[(wrow0 + 16 * f + M::drow(kq, r)) * ldv + col0 + 16 * c + m16] = acc[f][c][r];
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = wrow0 + 16 * f + M::drow(kq, r);
+          yout[row * ldv + col0 + 16 * c + m16] = row < n ? acc[f][c][r] : T(0);
+        }
     return;
   }
   // ---- epilogue ----
@@ -169,8 +295,9 @@ __device__ __forceinline__ void dense_step_tile(const DenseStepArgs &a, int tm, 
     for (int f = 0; f < WR; ++f)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t off = (wrow0 + 16 * f + M::drow(kq, r)) * ldv + col;
-      const T y = ta * acc[f][c][r];
+      const int64_t row = wrow0 + 16 * f + M::drow(kq, r);
+      const int64_t off = row * ldv + col;
+      const T y = row < n ? ta * acc[f][c][r] : T(0);
       T z = tc1 * y + tb * Vk[off];
       if (use_m1) z += tcw * Vkm1[off];
       if (use_cg) z += tcg * G[off];
