@@ -13,14 +13,11 @@
 // (c1,c2,cw) = (-1,1,0) so Z = (I - R/u) V_k, dots with Y give
 // e_{k,j} = g_j^T (R/u)(I - R/u)^k g_j.
 //
-// Tiling: a workgroup of 4 waves owns 64*WR rows x BN probe columns.  Each
-// wave owns WR slabs of 16 rows and streams them straight from HBM into
-// registers: lane (m = l%16, q = l/16) loads 8 consecutive elements
-// R[row m][kc + 8q .. kc + 8q + 7] and feeds them to 8 successive MFMAs, so
-// MFMA k-slot q of call t is column kc + 8q + t (the k order inside a chunk
-// is permuted consistently for A and B).  The V_k chunk (32 x BN) is shared
-// by the 4 waves through LDS.  Row/column padding of the V buffers is zero,
-// so only the loads of R need bounds checks.
+// Tiling: a workgroup of 4 waves owns 64*WR rows x BN probe columns; each
+// wave owns WR slabs of 16 rows.  K is walked in chunks whose V_k rows and A
+// values are loaded straight into LDS three chunks ahead (see
+// dense_step_tile).  Row/column padding of the V buffers is zero, so a
+// ragged end of K needs no masking of V.
 //
 // Split-K: when the tile grid is smaller than the chip (n = 4096 with 64
 // probes has 64 tiles), each workgroup sums one range of columns into a
