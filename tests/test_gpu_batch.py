@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from tolerances import TOL_BF16X3, TOL_F32
 
 pytestmark = pytest.mark.gpu
 
@@ -70,12 +71,16 @@ def test_batch_graph_replays_and_eager_agree():
 def test_batch_fp32_against_oracle(orc):
     mats, host = make_batch(NS, 7, dtype=np.float32)
     m, s, seed = 20, 64, 11
-    res = ent.entropy_estimate_batched(mats, "chebyshev", m, s, seed, precision="f32")
+    g = ent.Graph(mats, "chebyshev", m, s, seed, precision="f32")
+    res = g.launch()
+    per = g.per_probe()
     for b, R in enumerate(host):
         ref = orc.estimate(R, 1, m, s, seed + b)
         rel = abs(res[b].entropy - ref.entropy) / abs(ref.entropy)
-        print(f"[batch f32] b={b} n={R.shape[0]} rel={rel:.2e}", flush=True)
-        assert rel <= 1e-3
+        err = np.max(np.abs(per[b] - ref.per_probe)) / max(np.mean(np.abs(ref.per_probe)), 1e-2)
+        print(f"[batch f32] b={b} n={R.shape[0]} rel={rel:.2e} per-probe={err:.2e}", flush=True)
+        assert rel <= TOL_F32 and err <= TOL_F32
+    g.destroy()
 
 
 def test_batch_autotune_choice(tmp_path, monkeypatch):
@@ -119,7 +124,7 @@ def test_batch_bf16x3_against_oracle(orc, method, dtype):
         err = np.max(np.abs(per[b] - ref.per_probe)) / scale
         rel = abs(res[b].entropy - ref.entropy) / max(abs(ref.entropy), 1e-2)
         print(f"[batch bf16x3 {method}] b={b} n={R.shape[0]} rel={rel:.2e} per-probe={err:.2e}", flush=True)
-        assert err <= 1e-3 and rel <= 1e-3
+        assert err <= TOL_BF16X3 and rel <= TOL_BF16X3
         assert res[b].p1_est == pytest.approx(ref.p1_est, rel=1e-6)
     # replays are bitwise identical and equal to the eager sequence
     again = [r.entropy for r in g.launch()]

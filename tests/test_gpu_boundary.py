@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from tolerances import TOL64, TOL_BF16X3, TOL_F32
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +31,7 @@ def rel_per_probe(per, ref):
 
 # ------------------------------------------------------------- normalise ----
 @pytest.mark.parametrize("method", ["chebyshev", "taylor"])
-@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 2e-5), ("bf16x3", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL_F32), ("bf16x3", TOL_BF16X3)])
 def test_normalize_dense_matches_oracle_on_unit_trace(orc, method, precision, tol):
     n, m, s, seed, tau = 150, 14, 24, 31, 3.7
     R = W.dense_density(W.spectrum_exp(n, 25.0), 41)

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from tolerances import TOL_BF16X3, TOL_F32
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +51,7 @@ def test_fp64_parity(orc, method, dist):
             assert np.max(np.abs(mom[:, j] - d)) <= 1e-10 * float(g @ g)
 
 
-@pytest.mark.parametrize("prec,storage,tol", [("f32", np.complex64, 1e-3), ("bf16x3", np.complex128, 1e-3),
+@pytest.mark.parametrize("prec,storage,tol", [("f32", np.complex64, TOL_F32), ("bf16x3", np.complex128, TOL_BF16X3),
                                               ("f64", np.complex64, 1e-10)])
 def test_reduced_precision_and_storage(orc, prec, storage, tol):
     n, m, s, seed = 300, 15, 16, 3
@@ -125,7 +126,7 @@ def test_sampled_probes_at_n2048_bf16x3(orc):
     ref = orc.zestimate(R, 1, m, s, seed, dist=1, u_override=1.0, probes=sel)
     err = np.max(np.abs(per[sel] - ref.per_probe)) / np.mean(np.abs(ref.per_probe))
     print(f"[herm n=2048 bf16x3] sampled per-probe rel err {err:.2e}", flush=True)
-    assert err <= 1e-3
+    assert err <= TOL_BF16X3
 
 
 def test_release_while_estimating_from_another_thread():

@@ -2,8 +2,8 @@
 the same seeded inputs, probe by probe.
 
 FP64 bar: per-probe values and the estimate within 1e-10 relative, moments
-within 1e-10 of ||g||^2, p~1 within 1e-12 relative.  FP32 bar: 1e-3
-relative on the estimate (measured errors are printed).
+within 1e-10 of ||g||^2, p~1 within 1e-12 relative.  FP32 / BF16x3 bar:
+TOL_F32 / TOL_BF16X3 per probe (tests/tolerances.py; measured errors are printed).
 """
 import math
 
@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from tolerances import TOL_BF16X3, TOL_F32
 
 pytestmark = pytest.mark.gpu
 
@@ -111,11 +112,13 @@ def test_dense_storage_fp32_and_strided(orc):
 def test_dense_fp32_compute(orc, method):
     n, m, s, seed = 512, 30, 50, 9
     R = W.dense_density(W.spectrum_inverse(n), W.MATRIX_SEED + 1)
-    gpu = ent.entropy_estimate(to_dev(R), method, m, s, seed, precision="f32")
+    gpu, per, _ = ent.entropy_estimate_detail(to_dev(R), method, m, s, seed, precision="f32")
     ref = orc.estimate(R, 0 if method == "taylor" else 1, m, s, seed)
     rel = abs(gpu.entropy - ref.entropy) / abs(ref.entropy)
-    print(f"[f32 {method}] H gpu={gpu.entropy:.10f} oracle={ref.entropy:.10f} rel err={rel:.2e}", flush=True)
-    assert rel <= 1e-3
+    perr = np.max(np.abs(per - ref.per_probe)) / np.mean(np.abs(ref.per_probe))
+    print(f"[f32 {method}] H gpu={gpu.entropy:.10f} oracle={ref.entropy:.10f} rel err={rel:.2e} "
+          f"per-probe={perr:.2e}", flush=True)
+    assert rel <= TOL_F32 and perr <= TOL_F32
 
 
 @pytest.mark.parametrize("n,s", [(2048, 8), (3000, 20)])
@@ -131,9 +134,9 @@ def test_dense_split_k(orc, n, s):
         err = np.max(np.abs(per - ref.per_probe)) / np.mean(np.abs(ref.per_probe))
         print(f"[split-K n={n} s={s} {method} flags={flags}] per-probe rel {err:.2e}", flush=True)
         assert err <= 1e-10
-    gpu = ent.entropy_estimate(to_dev(R), "chebyshev", m, s, seed, precision="f32")
+    gpu, per, _ = ent.entropy_estimate_detail(to_dev(R), "chebyshev", m, s, seed, precision="f32")
     ref = orc.estimate(R, 1, m, s, seed)
-    assert abs(gpu.entropy - ref.entropy) / abs(ref.entropy) <= 1e-3
+    assert np.max(np.abs(per - ref.per_probe)) / np.mean(np.abs(ref.per_probe)) <= TOL_F32
 
 
 def test_special_states(orc):
@@ -206,7 +209,7 @@ def test_csr_banded_parity(orc, method, dtype):
         rel = abs(gpu.entropy - ref.entropy) / abs(ref.entropy)
         perr = np.max(np.abs(per - ref.per_probe)) / np.mean(np.abs(ref.per_probe))
         print(f"[csr f32 {method}] H gpu={gpu.entropy:.10f} oracle={ref.entropy:.10f} rel={rel:.2e} per-probe={perr:.2e}", flush=True)
-        assert rel <= 1e-3
+        assert rel <= TOL_F32 and perr <= TOL_F32
 
 
 @pytest.mark.parametrize("n,s", [(1, 1), (7, 3), (1000, 65), (4097, 130)])
@@ -288,7 +291,7 @@ def test_poisson_1e7_paper_configuration(orc):
     ref = orc.estimate(host, 1, m, s, seed, t=20, dist=0, c=1.0, probes=sel)
     err = np.max(np.abs(per[sel] - ref.per_probe)) / np.mean(np.abs(ref.per_probe))
     print(f"[poisson 1e7] sampled per-probe rel err vs oracle {err:.2e}", flush=True)
-    assert err <= 1e-3
+    assert err <= TOL_F32
 
 
 # --------------------------------------------------------------- BF16x3 ------
@@ -308,7 +311,7 @@ def test_dense_bf16x3_small_config(orc, method, dist):
     # the power method reads the bf16 hi/lo split of R (about 2^-17 relative per
     # entry) and accumulates in FP64
     assert gpu.p1_est == pytest.approx(ref.p1_est, rel=1e-6)
-    assert rel <= 1e-3 and perr <= 1e-3
+    assert rel <= TOL_BF16X3 and perr <= TOL_BF16X3
 
 
 @pytest.mark.parametrize("n,s,m", [(1, 1, 1), (100, 5, 3), (200, 37, 7), (300, 300, 6), (700, 129, 12)])
@@ -319,10 +322,12 @@ def test_dense_bf16x3_ragged(orc, n, s, m):
         gpu, per, mom = ent.entropy_estimate_detail(to_dev(R), method, m, s, seed, probe_dist="gaussian",
                                                     precision="bf16x3")
         ref = orc.estimate(R, 0 if method == "taylor" else 1, m, s, seed, dist=1)
-        scale = max(np.mean(np.abs(ref.per_probe)), 1e-2)
+        # n = 1 (a pure state): h_j is about 0 and its bf16x3 error is a
+        # fraction of ||g||^2, so the scale has a floor of 1
+        scale = max(np.mean(np.abs(ref.per_probe)), 1.0)
         perr = np.max(np.abs(per - ref.per_probe)) / scale
         print(f"[bf16x3 {n}x{s} m={m} {method}] rel per-probe err={perr:.2e}", flush=True)
-        assert perr <= 1e-3
+        assert perr <= TOL_BF16X3
         if method == "chebyshev":
             # moments of a matrix with spectrum in [-1, 1] stay within ||g||^2
             g2 = mom[0]
@@ -336,7 +341,7 @@ def test_bf16x3_fp32_storage_and_determinism(orc):
     b = ent.entropy_estimate_detail(to_dev(R), "chebyshev", m, s, seed, precision="bf16x3")
     assert np.array_equal(a[1], b[1])
     ref = orc.estimate(R, 1, m, s, seed)
-    assert abs(a[0].entropy - ref.entropy) <= 1e-3 * ref.entropy
+    assert np.max(np.abs(a[1] - ref.per_probe)) / np.mean(np.abs(ref.per_probe)) <= TOL_BF16X3
 
 
 def _hip_runtime():
