@@ -176,7 +176,8 @@ def bench_batch(args, cfg):
     log(f"generated {count} matrices (sum n^2 = {sum_n2:.3e}) in {time.time() - t0:.1f}s")
     g = ent.Graph(mats, cfg["method"], m, s, pseed, precision=precision, probe_dist=cfg["dist"],
                   power_iters=t, flags=ent.FLAG_AUTOTUNE)
-    log(f"graph ready: tile rows {g.tile_rows}, workspace {g.workspace_bytes / 1e9:.2f} GB")
+    log(f"graph ready: tile rows {g.tile_rows}, step schedule window {g.window_bytes >> 20} MB "
+        f"(0: one launch per step), workspace {g.workspace_bytes / 1e9:.2f} GB")
     for _ in range(args.warmup):
         g.launch()
     torch.cuda.synchronize()
@@ -234,7 +235,8 @@ def bench_batch(args, cfg):
                                f"rank ~ U[n/8,n], Dirichlet(0.5) spectra; {cfg['method']} m={m}, s={s} "
                                f"{cfg['dist']} probes, t={t}; one hipGraph launch per batch",
                    "count": count, "sum_n2": sum_n2, "precision": precision,
-                   "tile_rows": g.tile_rows, "parallelism": "single GPU"},
+                   "tile_rows": g.tile_rows, "schedule_window_bytes": g.window_bytes,
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": measured_traffic(kernel, args.workload + ("" if precision == "f32" else "_" + precision)),

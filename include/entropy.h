@@ -135,7 +135,7 @@ enum {
                                     same results within rounding             */
   ENT_FLAG_CSR_BANDED = 32,      /* CSR R within 16 of the diagonal: the banded
                                     kernels whatever the byte counts          */
-  ENT_FLAG_NORMALIZE = 64        /* estimate H(R / tr R) instead of requiring
+  ENT_FLAG_NORMALIZE = 64,       /* estimate H(R / tr R) instead of requiring
                                     tr R = 1 (Section 1.1: a density matrix
                                     has unit trace).  tr R is computed on the
                                     device (Re tr R for Hermitian storage) and
@@ -145,6 +145,9 @@ enum {
                                     R / tr R.  tr R <= 0 or non-finite is
                                     ENT_ENOTDENSITY.  Overrides
                                     ENT_FLAG_SKIP_TRACE_CHECK and trace_tol.  */
+  ENT_FLAG_BATCH_STEPWISE = 128  /* batches: one grouped launch per recurrence
+                                    step instead of the persistent schedule
+                                    (see ent_graph_create)                   */
 };
 
 /*
@@ -385,10 +388,22 @@ ent_status ent_last_timing(ent_timing *out);
  *
  * ent_entropy_estimate_batched: one synchronous run; outs[count].
  * ent_graph_create: plans the batch (workspace, descriptor and tile tables,
- *   tile shape -- from the autotune cache, or timed on the batch when
- *   ENT_FLAG_AUTOTUNE is set; the cache persists as JSON in the file named by
- *   the environment variable ENT_AUTOTUNE_CACHE), then captures the whole
- *   launch sequence into a hipGraph on a private stream.
+ *   tile shape and step schedule -- from the autotune cache, or timed on the
+ *   batch when ENT_FLAG_AUTOTUNE is set; the cache persists as JSON in the
+ *   file named by the environment variable ENT_AUTOTUNE_CACHE), then captures
+ *   the whole launch sequence into a hipGraph on a private stream.
+ *   The m recurrence steps of every matrix run by default as ONE persistent
+ *   launch: its workgroups (as many as are resident at once) take (matrix,
+ *   row tile, step) items from a device schedule.  Each matrix belongs to one
+ *   XCD and only workgroups on that XCD take its items; per XCD, matrices of
+ *   decreasing n enter a window of bounded bytes (1 GB over all XCDs by
+ *   default) and advance one step per round.  An item waits until every tile
+ *   of its matrix's previous step is done (per-matrix counters); each wait is
+ *   bounded (environment variable ENT_SCHED_SPIN_LIMIT polls, default 2^20)
+ *   and an expired wait, or an XCD's items left untaken, makes
+ *   ent_graph_launch return ENT_EDEVICE.  With ENT_FLAG_BATCH_STEPWISE, or
+ *   when the autotuner finds it faster, each step is one grouped launch over
+ *   every tile instead.  Both give bit-identical results.
  * ent_graph_launch: replays the graph, synchronises, fills outs[count].
  * ent_graph_per_probe: h_j of the last launch, per_probe[count * probes].
  * ent_graph_time_eager: runs the same sequence without the graph, recording
@@ -405,6 +420,8 @@ ent_status ent_graph_launch(ent_graph graph, ent_result *outs);
 ent_status ent_graph_per_probe(ent_graph graph, double *per_probe);
 ent_status ent_graph_time_eager(ent_graph graph, ent_result *outs, ent_timing *timing);
 int32_t ent_graph_tile_rows(ent_graph graph);       /* 64 or 128 (chosen tile shape; BF16x3: 128) */
+size_t ent_graph_window_bytes(ent_graph graph);     /* window of the persistent schedule; 0: one
+                                                       grouped launch per step */
 size_t ent_graph_workspace_bytes(ent_graph graph);
 ent_status ent_graph_destroy(ent_graph graph);
 

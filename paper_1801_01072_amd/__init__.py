@@ -42,6 +42,7 @@ FLAG_CLENSHAW = 8
 FLAG_CSR_GENERAL = 16
 FLAG_CSR_BANDED = 32
 FLAG_NORMALIZE = 64
+FLAG_BATCH_STEPWISE = 128
 
 _METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ, "auto": AUTO}
 _PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
@@ -115,6 +116,7 @@ _SIGNATURES = {
     "ent_graph_per_probe": (ctypes.c_int, [_P, _P]),
     "ent_graph_time_eager": (ctypes.c_int, [_P, ctypes.POINTER(EntResult), ctypes.POINTER(EntTiming)]),
     "ent_graph_tile_rows": (ctypes.c_int32, [_P]),
+    "ent_graph_window_bytes": (ctypes.c_size_t, [_P]),
     "ent_graph_workspace_bytes": (ctypes.c_size_t, [_P]),
     "ent_graph_destroy": (ctypes.c_int, [_P]),
     "ent_mlp_nparams": (ctypes.c_int32, []),
@@ -464,6 +466,11 @@ class Graph:
     @property
     def workspace_bytes(self) -> int:
         return _lib.ent_graph_workspace_bytes(self._h)
+
+    @property
+    def window_bytes(self) -> int:
+        """Window of the persistent step schedule (0: one launch per step)."""
+        return _lib.ent_graph_window_bytes(self._h)
 
     def destroy(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kernels.hpp"
+
 namespace ent {
 
 // ---------------------------------------------------------------------------
@@ -174,6 +176,102 @@ __device__ __forceinline__ void block_power_partials(double yy, double xy, doubl
     part3[3 * blk + 1] = b;
     part3[3 * blk + 2] = c;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batch steps: taking items, waiting for a matrix's previous step,
+// publishing a finished tile.  Items are taken from the segment of the XCD
+// the workgroup runs on, and every item of a matrix runs on the same XCD, so
+// a tile's stores reach the only L2 its consumers read through: publishing
+// waits until this workgroup's stores are performed (vmcnt), then one thread
+// moves the counter; waiting polls the counter, then invalidates at device
+// scope, which drops this CU's L1 (lines that another CU of the XCD has since
+// rewritten in L2) and never loses a dirty L2 line.  No L2 write-back is
+// needed.  Counters are vector atomics.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcc_id() {
+  return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kMaxXcc - 1));  // HW_REG_XCC_ID[3:0]
+}
+
+// Next item index of this workgroup, or -1 when its XCD's segment is
+// exhausted or a wait has failed.  sh: a __shared__ int of the calling kernel.
+__device__ __forceinline__ int sched_next(const SchedArgs &s, int *sh) {
+  __syncthreads();  // every wave is done with the previous item (and with sh)
+  if (threadIdx.x == 0) {
+    int i = -1;
+    const int seg = s.seg_of_xcc[xcc_id()];
+    if (seg >= 0) {
+      const int q = __hip_atomic_fetch_add(s.head + seg, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (q < s.seg_off[seg + 1] - s.seg_off[seg] &&
+          __hip_atomic_fetch_add(s.err, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        i = s.seg_off[seg] + q;
+    }
+    *sh = i;
+  }
+  __syncthreads();
+  return *sh;
+}
+
+// Waits until done[b] >= need; false (and *err set) after spin_limit polls.
+__device__ __forceinline__ bool sched_wait(const SchedArgs &s, int b, int need, int *sh) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    int polls = 0;
+    while (__hip_atomic_fetch_add(s.done + b, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      if (__hip_atomic_fetch_add(s.err, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          polls++ >= s.spin_limit) {
+        __hip_atomic_fetch_or(s.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    *sh = ok;
+  }
+  __syncthreads();
+  asm volatile("buffer_inv sc1" ::: "memory");  // L1 of this CU (device scope: a group-scope invalidate may keep it)
+  return *sh != 0;
+}
+
+// Publishes one finished tile of matrix b.
+__device__ __forceinline__ void sched_release(const SchedArgs &s, int b) {
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores of the tile are performed in L2
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(s.done + b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Recurrence of step k (the host's per-step launches use the same rule):
+// Chebyshev forward: V_1 = Y_0 - V_0 (dot slot 1, g.g in slot 0), then
+// V_{k+1} = 2 Y_k - 2 V_k - V_{k-1} written over V_{k-1}; Taylor: W_{k+1} =
+// W_k - Y_k into alternating buffers, dots with Y_k in slot k, the last step
+// writes nothing.  V_0 is the probe block.
+struct StepRule {
+  double c1, c2, cw;
+  int32_t dot_y, slot, slot_gg;
+  int vk, vkm1, vout;  // buffer ids: 0 = probe block, 1 = VA, 2 = VB, -1 = none
+};
+__device__ __forceinline__ StepRule step_rule(int32_t method, int32_t k, int32_t nsteps) {
+  StepRule r;
+  const int out = 1 + (k & 1), prev = 1 + ((k - 1) & 1);
+  if (method == 1) {  // Chebyshev
+    r.dot_y = 0;
+    r.slot = k + 1;
+    if (k == 0) {
+      r.c1 = 1.0; r.c2 = -1.0; r.cw = 0.0; r.slot_gg = 0;
+      r.vk = 0; r.vkm1 = -1;
+    } else {
+      r.c1 = 2.0; r.c2 = -2.0; r.cw = -1.0; r.slot_gg = -1;
+      r.vk = prev; r.vkm1 = k == 1 ? 0 : out;
+    }
+    r.vout = out;
+  } else {  // Taylor
+    r.c1 = -1.0; r.c2 = 1.0; r.cw = 0.0;
+    r.dot_y = 1; r.slot = k; r.slot_gg = -1;
+    r.vk = k == 0 ? 0 : prev;
+    r.vkm1 = -1;
+    r.vout = k < nsteps - 1 ? out : -1;
+  }
+  return r;
 }
 
 }  // namespace ent

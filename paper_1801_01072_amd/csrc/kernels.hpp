@@ -292,6 +292,55 @@ hipError_t launch_batch_probe_t(const BatchMat *mats, const int2 *tiles, int32_t
 hipError_t launch_batch_power_split(const BatchMat *mats, const int2 *ptiles, int32_t nptiles,
                                     const uint16_t *Ahi, const uint16_t *Alo, const double *x,
                                     const double *norm, double *y, double *pout, hipStream_t st);
+// ---- persistent batch steps: one launch walks a schedule of work items ------
+// Item (matrix b, row tile t, step k, 0).  Every matrix belongs to one XCD and
+// its items form part of that XCD's segment of the schedule, which only the
+// workgroups running on that XCD take; so a tile's inputs were written by the
+// same XCD and the XCD's L2 is their point of coherence.  A segment lists
+// every tile of step k - 1 of a matrix before any tile of its step k; an item
+// waits until done[b] >= k * ntile_b (all tiles of step k - 1 finished), runs
+// the tile, then adds one to done[b].  Waits are bounded: after spin_limit
+// polls the item sets *err and every workgroup stops taking items.
+constexpr int kMaxXcc = 16;
+struct SchedArgs {
+  const int4 *items;
+  int32_t nitems;
+  int32_t spin_limit;
+  int32_t nseg;                  // segments (XCDs that hold workgroups)
+  int32_t seg_off[kMaxXcc + 1];  // segment s: items [seg_off[s], seg_off[s + 1])
+  int32_t seg_of_xcc[kMaxXcc];   // hardware XCC id -> segment (-1: none)
+  int32_t *head;   // [nseg] next item of each segment (zeroed before the launch)
+  int32_t *done;   // per-matrix finished tiles (zeroed before the launch)
+  int32_t *err;    // nonzero: a wait timed out (zeroed before the launch)
+};
+// XCC id of the workgroups of a grid: ids[blockIdx.x] (one-time probe).
+hipError_t launch_xcc_probe(int32_t *ids, int32_t grid, hipStream_t st);
+// After a persistent launch: sets bit 1 of *err when a segment's items were
+// not all taken (no workgroup of the launch ran on its XCD).
+hipError_t launch_sched_check(const SchedArgs &s, hipStream_t st);
+// Buffers and recurrence of the batched steps, common to every item.
+struct BatchPersistArgs {
+  SchedArgs sched;
+  const BatchMat *mats;
+  int32_t method;    // ENT_TAYLOR / ENT_CHEBYSHEV
+  int32_t nsteps;    // m (Chebyshev) or m + 1 (Taylor)
+  int64_t ldv;
+  const void *G;     // probe block (batch base; FP32 probe-major for BF16x3)
+  void *VA, *VB;     // recurrence buffers (batch base)
+  double *part;      // step partials (batch base)
+  // BF16x3: fragment-major split of every R and the two bf16 hi/lo sets of V
+  const uint16_t *Ahi, *Alo;
+  uint16_t *Vhi[2], *Vlo[2];
+};
+// Grid of the persistent step kernels (workgroups resident at once); 0 if the
+// runtime cannot tell.
+int32_t batch_persistent_grid(int32_t precision, int32_t wr, int64_t ldv);
+int32_t bf16x3_persistent_grid(int64_t ldv);
+template <typename T>
+hipError_t launch_batch_dense_persistent(const BatchPersistArgs &pa, int32_t wr, int32_t grid,
+                                         hipStream_t st);
+hipError_t launch_batch_bf16x3_persistent(const BatchPersistArgs &pa, int32_t grid, hipStream_t st);
+
 hipError_t launch_batch_bf16x3_step(const Bf16EpiArgs &base, const BatchMat *mats, const int2 *tiles,
                                     int32_t ntiles, const uint16_t *Ahi, const uint16_t *Alo,
                                     const uint16_t *vin_hi, const uint16_t *vin_lo, hipStream_t st);

@@ -521,6 +521,74 @@ __global__ __launch_bounds__(256) void batch_bf16x3_step_kernel(Bf16EpiArgs base
                                 M.n_pad, 0, (int)(M.n_pad / kBK), (int64_t)t.y * 128, 0, &e, t.y);
 }
 
+// Persistent batch steps (BF16x3): each workgroup takes (matrix, 128-row
+// tile, step) items in schedule order, waits for the matrix's previous step,
+// runs the fused GEMM + epilogue tile of the grouped kernel with that step's
+// recurrence (bf16 V sets by step parity), publishes it.
+template <int BN>
+__global__ __launch_bounds__(256) void batch_bf16x3_persistent_kernel(BatchPersistArgs pa) {
+  __shared__ int sh;
+  for (;;) {
+    const int i = sched_next(pa.sched, &sh);
+    if (i < 0) return;
+    const int4 it = pa.sched.items[i];
+    const BatchMat &M = pa.mats[it.x];
+    if (!sched_wait(pa.sched, it.x, it.z * M.ntile, &sh)) return;
+    const StepRule r = step_rule(pa.method, it.z, pa.nsteps);
+    const float *bufs[3] = {(const float *)pa.G + M.voff, (const float *)pa.VA + M.voff,
+                            (const float *)pa.VB + M.voff};
+    Bf16EpiArgs e{};
+    e.part_y = nullptr;
+    e.splits = 1;
+    e.Vk = bufs[r.vk];
+    e.Vkm1 = r.vkm1 >= 0 ? bufs[r.vkm1] : nullptr;
+    e.Vkp1 = r.vout >= 0 ? (float *)bufs[r.vout] : nullptr;
+    const int pin = it.z & 1, pout = (it.z + 1) & 1;
+    e.V_hi = pa.Vhi[pout] + M.voff;
+    e.V_lo = pa.Vlo[pout] + M.voff;
+    e.G = bufs[0];
+    e.scal = M.scal;
+    e.c1 = r.c1; e.c2 = r.c2; e.cw = r.cw;
+    e.dot_y = r.dot_y; e.slot = r.slot; e.slot_gg = r.slot_gg;
+    e.scale_y = 1;
+    e.part = pa.part + M.poff;
+    e.nblk = M.ntile;
+    e.n_pad = M.n_pad;
+    e.ldv = pa.ldv;
+    e.cg = nullptr;
+    bf16x3_gemm_tile<BN, 2, true>(pa.Ahi + M.aoff, pa.Alo + M.aoff, pa.Vhi[pin] + M.voff,
+                                  pa.Vlo[pin] + M.voff, nullptr, M.n_pad, 0, (int)(M.n_pad / kBK),
+                                  (int64_t)it.y * 128, 0, &e, it.y);
+    sched_release(pa.sched, it.x);
+  }
+}
+
+hipError_t launch_batch_bf16x3_persistent(const BatchPersistArgs &pa, int32_t grid, hipStream_t st) {
+  if (grid < 1) return hipErrorInvalidValue;
+  switch (pa.ldv) {
+    case 64: batch_bf16x3_persistent_kernel<64><<<(unsigned)grid, 256, 0, st>>>(pa); break;
+    case 128: batch_bf16x3_persistent_kernel<128><<<(unsigned)grid, 256, 0, st>>>(pa); break;
+    case 256: batch_bf16x3_persistent_kernel<256><<<(unsigned)grid, 256, 0, st>>>(pa); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int32_t bf16x3_persistent_grid(int64_t ldv) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  hipError_t e;
+  switch (ldv) {
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_bf16x3_persistent_kernel<64>, 256, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_bf16x3_persistent_kernel<128>, 256, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_bf16x3_persistent_kernel<256>, 256, 0); break;
+    default: return 0;
+  }
+  if (e != hipSuccess) return 0;
+  return cus * (per > 0 ? per : 1);
+}
+
 hipError_t launch_batch_bf16x3_step(const Bf16EpiArgs &base, const BatchMat *mats, const int2 *tiles,
                                     int32_t ntiles, const uint16_t *Ahi, const uint16_t *Alo,
                                     const uint16_t *vin_hi, const uint16_t *vin_lo, hipStream_t st) {

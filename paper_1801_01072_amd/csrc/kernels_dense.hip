@@ -438,6 +438,73 @@ __global__ __launch_bounds__(256) void batch_dense_step_kernel(BatchStepArgs ba)
   dense_step_tile<T, BN, WR>(a, tl.y, 0, 0, a.n, nullptr);
 }
 
+// Persistent batch steps: each workgroup takes (matrix, row tile, step)
+// items in schedule order, waits for the matrix's previous step, runs the
+// tile body of the grouped kernel with that step's recurrence, publishes it.
+template <typename T, int WR>
+__global__ __launch_bounds__(256) void batch_dense_persistent_kernel(BatchPersistArgs pa) {
+  __shared__ int sh;
+  for (;;) {
+    const int i = sched_next(pa.sched, &sh);
+    if (i < 0) return;
+    const int4 it = pa.sched.items[i];
+    const BatchMat &M = pa.mats[it.x];
+    if (!sched_wait(pa.sched, it.x, it.z * M.ntile, &sh)) return;
+    const StepRule r = step_rule(pa.method, it.z, pa.nsteps);
+    const T *bufs[3] = {(const T *)pa.G + M.voff, (const T *)pa.VA + M.voff, (const T *)pa.VB + M.voff};
+    DenseStepArgs a{};
+    a.R = M.R;
+    a.ldr = M.ldr;
+    a.n = M.n;
+    a.ldv = pa.ldv;
+    a.Vk = bufs[r.vk];
+    a.Vkm1 = r.vkm1 >= 0 ? bufs[r.vkm1] : nullptr;
+    a.Vkp1 = r.vout >= 0 ? (void *)bufs[r.vout] : nullptr;
+    a.G = bufs[0];
+    a.scal = M.scal;
+    a.c1 = r.c1; a.c2 = r.c2; a.cw = r.cw;
+    a.dot_y = r.dot_y; a.slot = r.slot; a.slot_gg = r.slot_gg;
+    a.part = pa.part + M.poff;
+    a.ntile = M.ntile;
+    a.bn = 64;
+    dense_step_tile<T, 64, WR>(a, it.y, 0, 0, a.n, nullptr);
+    sched_release(pa.sched, it.x);
+  }
+}
+
+template <typename T>
+hipError_t launch_batch_dense_persistent(const BatchPersistArgs &pa, int32_t wr, int32_t grid,
+                                         hipStream_t st) {
+  if (pa.ldv != 64 || grid < 1) return hipErrorInvalidValue;
+  if (wr == 1)
+    batch_dense_persistent_kernel<T, 1><<<(unsigned)grid, 256, 0, st>>>(pa);
+  else if (wr == 2)
+    batch_dense_persistent_kernel<T, 2><<<(unsigned)grid, 256, 0, st>>>(pa);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+template hipError_t launch_batch_dense_persistent<double>(const BatchPersistArgs &, int32_t, int32_t, hipStream_t);
+template hipError_t launch_batch_dense_persistent<float>(const BatchPersistArgs &, int32_t, int32_t, hipStream_t);
+
+// Resident workgroups of the persistent step kernels (CUs x occupancy).
+int32_t batch_persistent_grid(int32_t precision, int32_t wr, int64_t ldv) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (precision == 0)
+    e = wr == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_dense_persistent_kernel<double, 2>, 256, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_dense_persistent_kernel<double, 1>, 256, 0);
+  else if (precision == 1)
+    e = wr == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_dense_persistent_kernel<float, 2>, 256, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_dense_persistent_kernel<float, 1>, 256, 0);
+  else
+    return bf16x3_persistent_grid(ldv);
+  if (e != hipSuccess) return 0;
+  return cus * (per > 0 ? per : 1);
+}
+
 template <typename T>
 hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st) {
   const int ntn = (int)(a.ldv / a.bn);

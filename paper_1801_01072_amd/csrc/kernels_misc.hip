@@ -747,6 +747,29 @@ __global__ void zero_kernel(unsigned char *__restrict__ p, int64_t head, int64_t
   for (int64_t i = tail0 + tid; i < bytes; i += stride) p[i] = 0;
 }
 
+__global__ void xcc_probe_kernel(int32_t *ids) {
+  if (threadIdx.x == 0) ids[blockIdx.x] = xcc_id();
+}
+
+hipError_t launch_xcc_probe(int32_t *ids, int32_t grid, hipStream_t st) {
+  xcc_probe_kernel<<<(unsigned)grid, 64, 0, st>>>(ids);
+  return hipGetLastError();
+}
+
+__global__ void sched_check_kernel(SchedArgs s) {
+  const int q = (int)threadIdx.x;
+  if (q < s.nseg) {
+    const int len = s.seg_off[q + 1] - s.seg_off[q];
+    if (len > 0 && __hip_atomic_load(s.head + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < len)
+      __hip_atomic_fetch_or(s.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+hipError_t launch_sched_check(const SchedArgs &s, hipStream_t st) {
+  sched_check_kernel<<<1, 64, 0, st>>>(s);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
   if (bytes == 0) return hipSuccess;
   const uintptr_t a = (uintptr_t)p;

@@ -133,3 +133,49 @@ def test_batch_bf16x3_against_oracle(orc, method, dtype):
     assert [r.entropy for r in eager] == again
     assert tm["step_launches"] == (m if method == "chebyshev" else m + 1)
     g.destroy()
+
+
+def test_persistent_schedule_matches_stepwise(orc):
+    # the persistent step schedule (default) and one grouped launch per step
+    # give bit-identical results (same tile bodies, same reduction order)
+    mats, host = make_batch(NS, 19, dtype=np.float32)
+    for prec in ("f32", "bf16x3", "f64"):
+        gp = ent.Graph(mats, "chebyshev", 14, 64, 5, precision=prec)
+        gs = ent.Graph(mats, "chebyshev", 14, 64, 5, precision=prec, flags=ent.FLAG_BATCH_STEPWISE)
+        assert gp.window_bytes > 0 and gs.window_bytes == 0
+        rp, rs = gp.launch(), gs.launch()
+        assert [r.entropy for r in rp] == [r.entropy for r in rs]
+        assert np.array_equal(gp.per_probe(), gs.per_probe())
+        # replays of the persistent graph stay identical
+        _ = torch.ones(1000, device=DEV).sum().item()
+        assert [r.entropy for r in gp.launch()] == [r.entropy for r in rp]
+        gp.destroy()
+        gs.destroy()
+    # Taylor through the persistent schedule against the oracle
+    g = ent.Graph(mats, "taylor", 9, 32, 3, precision="f64", probe_dist="gaussian")
+    res = g.launch()
+    per = g.per_probe()
+    for b, R in enumerate(host):
+        ref = orc.estimate(R.astype(np.float64), 0, 9, 32, 3 + b, dist=1)
+        assert np.max(np.abs(per[b] - ref.per_probe)) / max(np.mean(np.abs(ref.per_probe)), 1e-2) <= 1e-10
+    g.destroy()
+
+
+def test_persistent_wait_bound_reports_failure(monkeypatch):
+    # a bound of zero polls: a step of a matrix whose previous step is still
+    # running gives up at once; the kernel exits normally and the launch
+    # reports ENT_EDEVICE (one matrix of 16 row tiles: its step-1 items are
+    # taken right after its step-0 items, before those can have finished)
+    monkeypatch.setenv("ENT_SCHED_SPIN_LIMIT", "0")
+    R = torch.from_numpy(W.dense_density(W.spectrum_exp(2048, 200.0), 3)).to(DEV)
+    g = ent.Graph([R], "chebyshev", 12, 64, 1, precision="f32")
+    assert g.window_bytes > 0
+    with pytest.raises(ent.EntropyError) as ei:
+        for _ in range(3):
+            g.launch()
+    assert ei.value.status == ent.EDEVICE and "bound" in ei.value.message
+    g.destroy()
+    monkeypatch.delenv("ENT_SCHED_SPIN_LIMIT")
+    g = ent.Graph([R], "chebyshev", 12, 64, 1, precision="f32")
+    assert np.isfinite(g.launch()[0].entropy)
+    g.destroy()
