@@ -696,6 +696,7 @@ def bench_single(args, cfg):
                        "rel_err_vs_exact": abs(r_p.entropy - H_exact) / H_exact if H_exact else None,
                        "kernel": k_p, "avg_launch_ms": st_ms, "achieved_tflops": ach,
                        "frac": ach / MFMA_PEAK_TFLOPS[prec],
+                       "traffic": measured_traffic(k_p, args.workload + ("" if prec == "bf16x3" else "_" + prec)),
                        "epilogue_avg_launch_ms": epi_ms if prec == "bf16x3" else None,
                        "phases_ms": ph, "_per_probe": per_p}
         log(f"{prec}: {ms_p:.3f} ms/estimate ({1e3 / ms_p:.2f} est/s, {ms_per_step / ms_p:.2f}x the "
