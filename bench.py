@@ -255,6 +255,60 @@ def bench_batch(args, cfg):
         sys.exit(3)
 
 
+def truncation_report(spectra, auto, plain, m_plain, L, m_max=400):
+    """Truncation error of the polynomial each run used, from the known
+    spectrum: |sum_i p(lambda_i) - H| / H with p the Chebyshev expansion of
+    x ln x on the run's [lo, u] at its degree (the probe-free part of the
+    estimate).  Reports how often the selector's runs and the plain runs meet
+    the selector's training target, and the smallest fixed plain degree on
+    [0, u] that meets it on as many matrices (the plain schedule at matched
+    accuracy)."""
+    import torch
+
+    bar = L.TARGET_ERR
+    e_auto, e_plain, curves = [], [], []
+    for p, ra, rp in zip(spectra, auto, plain):
+        p = np.asarray(p, dtype=np.float64)
+        H = float(-np.sum(p[p > 0] * np.log(p[p > 0])))
+
+        def moments(lo, u, deg):
+            t = (2.0 * p - (u + lo)) / (u - lo)
+            out = np.empty(deg + 1)
+            tkm1, tk = np.ones_like(t), t.copy()
+            out[0] = p.size
+            if deg >= 1:
+                out[1] = tk.sum()
+            for k in range(2, deg + 1):
+                tkm1, tk = tk, 2.0 * t * tk - tkm1
+                out[k] = tk.sum()
+            return out
+
+        def coeffs(lo, u, deg):
+            uu = torch.tensor([u], dtype=torch.float64)
+            if lo > 0:
+                return L.cutoff_coeffs(lo / u, uu, deg)[0].numpy()
+            return L.lemma3_coeffs(uu, deg)[0].numpy()
+
+        if ra.method == 2:  # Algorithm 3: no polynomial
+            e_auto.append(abs(ra.entropy - H) / H)
+        else:
+            e_auto.append(abs(-coeffs(ra.lo, ra.u, ra.degree) @ moments(ra.lo, ra.u, ra.degree) - H) / H)
+        c = coeffs(0.0, rp.u, m_max)
+        curve = np.abs(-np.cumsum(c * moments(0.0, rp.u, m_max)) - H) / H
+        e_plain.append(curve[m_plain])
+        curves.append(curve)
+    e_auto, e_plain, curves = np.array(e_auto), np.array(e_plain), np.array(curves)
+    need = int(np.sum(e_auto <= bar))
+    meets = (curves <= bar).sum(axis=0)
+    ok = np.nonzero(meets >= need)[0]
+    m_eq = int(ok[0]) if ok.size else None
+    return {"bar": bar, "auto_meets_bar": float(np.mean(e_auto <= bar)),
+            "plain_meets_bar": float(np.mean(e_plain <= bar)),
+            "median_auto": float(np.median(e_auto)), "median_plain": float(np.median(e_plain)),
+            "plain_degree_matching_auto": m_eq,
+            "plain_products_matching_auto": (m_eq * len(spectra)) if m_eq is not None else None}
+
+
 def bench_learned(args, cfg):
     """The learned selector (method "auto") on held-out dense n = 4096 density
     matrices of the training families, against the plain schedule (Chebyshev
@@ -287,8 +341,8 @@ def bench_learned(args, cfg):
     H = np.array([float(-np.sum(p[p > 0] * np.log(p[p > 0]))) for p in spectra])
     kw = dict(probe_dist=cfg["dist"], precision=precision, power_iters=t)
 
-    def one_pass(method):
-        return [ent.entropy_estimate(R, method, m, s, pseed + i, **kw) for i, R in enumerate(mats)]
+    def one_pass(method, degree=m):
+        return [ent.entropy_estimate(R, method, degree, s, pseed + i, **kw) for i, R in enumerate(mats)]
 
     for _ in range(args.warmup):
         one_pass("auto")
@@ -311,6 +365,21 @@ def bench_learned(args, cfg):
     log(f"auto {ms_auto:.1f} ms/pass ({prod_auto} products, fallback {100 * fb:.1f}%), plain "
         f"{ms_plain:.1f} ms/pass ({prod_plain} products); median rel err vs exact: auto "
         f"{np.median(err_auto):.2e}, plain {np.median(err_plain):.2e}")
+    trunc = truncation_report(spectra, auto, plain, m, L)
+    log(f"truncation (polynomial trace vs exact, bar {L.TARGET_ERR:g}): auto meets it on "
+        f"{trunc['auto_meets_bar']:.3f}, plain m={m} on {trunc['plain_meets_bar']:.3f}; plain needs "
+        f"m={trunc['plain_degree_matching_auto']} to meet it as often ({trunc['plain_products_matching_auto']} "
+        f"products vs {prod_auto})")
+    m_eq = trunc["plain_degree_matching_auto"]
+    if m_eq is not None:
+        one_pass("chebyshev", m_eq)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one_pass("chebyshev", m_eq)
+        torch.cuda.synchronize()
+        trunc["plain_matching_estimates_per_s"] = count / (time.perf_counter() - t0)
+        log(f"plain at m={m_eq}: {trunc['plain_matching_estimates_per_s']:.1f} estimates/s "
+            f"(auto {count * 1e3 / ms_auto:.1f})")
 
     # dominant kernel: the recurrence product of the main pass
     ent.timing_enable(True)
@@ -366,6 +435,8 @@ def bench_learned(args, cfg):
             "plain_estimates_per_s": count * 1e3 / ms_plain,
             "products_auto": prod_auto, "products_plain": prod_plain,
             "fallback_rate": fb,
+            "routed_to_randproj": int(sum(r.method == ent.RANDPROJ for r in auto)),
+            "truncation": trunc,
             "median_rel_err_vs_exact_auto": float(np.median(err_auto)),
             "median_rel_err_vs_exact_plain": float(np.median(err_plain)),
             "mean_rel_err_vs_exact_auto": float(np.mean(err_auto)),

@@ -145,9 +145,11 @@ enum {
                                     R / tr R.  tr R <= 0 or non-finite is
                                     ENT_ENOTDENSITY.  Overrides
                                     ENT_FLAG_SKIP_TRACE_CHECK and trace_tol.  */
-  ENT_FLAG_BATCH_STEPWISE = 128  /* batches: one grouped launch per recurrence
+  ENT_FLAG_BATCH_STEPWISE = 128, /* batches: one grouped launch per recurrence
                                     step instead of the persistent schedule
                                     (see ent_graph_create)                   */
+  ENT_FLAG_AUTO_RANDPROJ = 256   /* ENT_AUTO: route an R whose sketch looks
+                                    numerically low-rank to Algorithm 3      */
 };
 
 /*
@@ -321,8 +323,16 @@ ent_status ent_chebyshev_coeffs(double lo, double u, int32_t m, double *alpha);
  * ent_selector_load: copies the parameters (host, ent_mlp_nparams() floats,
  *   layout W1[64][16], b1[64], W2[64][64], b2[64], W3[2][64], b3[2]) to the
  *   current device.
- * ent_entropy_estimate with method ENT_AUTO: runs the sketch pass, the
- *   network, then Chebyshev on [lo, u] with the predicted degree.  The
+ * ent_entropy_estimate with method ENT_AUTO: runs the sketch pass.  With
+ *   ENT_FLAG_AUTO_RANDPROJ and a dense R whose sketch rank n (1 - mean h(X)),
+ *   h(X) = ((1 - X)/2)^12 from the normalised moments, is at most
+ *   sketch_width / 8 (sketch_width 0: 128), Algorithm 3 (Section 5) runs
+ *   with that width, k = rank_k (0: width / 2) and a Gaussian sketch, and its
+ *   result is kept (result.method = ENT_RANDPROJ) if its k singular values
+ *   sum to 1 (the unit trace) within 5%; else 1 more product is counted.  The sketch cannot tell zero eigenvalues from
+ *   tiny ones (a spectrum p_i ~ i^-2 looks rank 6 to it), whose entropy
+ *   Algorithm 3 misses, hence the flag.  Otherwise the network, then
+ *   Chebyshev on [lo, u] with the predicted degree.  The
  *   a-posteriori check requires every moment |d_kj| <= ||g_j||^2 and
  *   |H(m) - H(m-4)| <= 2.5e-4 |H(m)|; if it fails, the plain schedule on
  *   [0, u] with the caller's degree is run instead (result.fell_back = 1).

@@ -43,6 +43,7 @@ FLAG_CSR_GENERAL = 16
 FLAG_CSR_BANDED = 32
 FLAG_NORMALIZE = 64
 FLAG_BATCH_STEPWISE = 128
+FLAG_AUTO_RANDPROJ = 256
 
 _METHODS = {"taylor": TAYLOR, "chebyshev": CHEBYSHEV, "randproj": RANDPROJ, "auto": AUTO}
 _PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}

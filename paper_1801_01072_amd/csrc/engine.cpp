@@ -531,6 +531,7 @@ struct SelHook {
   const float *params_dev = nullptr;
   float *y_dev = nullptr;         // 2 outputs
   float *y_host = nullptr;
+  float *feat_host = nullptr;     // 16 features (optional)
   double *alpha_host = nullptr;   // m + 1 coefficients
 };
 
@@ -799,6 +800,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     HIP_TRY(ent::launch_selector_features(scal, d, m, s, n, hook->feat_dev, st));
     HIP_TRY(ent::launch_mlp_forward(hook->params_dev, hook->feat_dev, 1, hook->y_dev, st));
     HIP_TRY(hipMemcpyAsync(hook->y_host, hook->y_dev, 2 * sizeof(float), hipMemcpyDeviceToHost, st));
+    if (hook->feat_host)
+      HIP_TRY(hipMemcpyAsync(hook->feat_host, hook->feat_dev, 16 * sizeof(float), hipMemcpyDeviceToHost, st));
   }
   if (hook && hook->alpha_host)
     HIP_TRY(hipMemcpyAsync(hook->alpha_host, scal + ent::S_ALPHA, sizeof(double) * (m + 1),
@@ -1064,6 +1067,7 @@ ent_status run_bf16x3(const ent_matrix *R, int32_t method, int32_t m, int32_t s,
 // Learned degree / cutoff selector (ENT_AUTO)
 // ---------------------------------------------------------------------------
 constexpr int32_t kFeatDegree = 12, kFeatProbes = 16;
+constexpr int32_t kRouteSketch = 128;  // random-projection width of the low-rank route
 
 struct SelectorState {
   float *params = nullptr;  // device copy of the MLP parameters
@@ -1083,16 +1087,39 @@ ent_status poly_dispatch(const ent_matrix *R, int32_t method, int32_t m, int32_t
   }
 }
 
-// Maps the network outputs to (m, lo): y0 = ln m*, y1 = log10(lo*/u) with
-// values below -11 meaning lo = 0.  A 25% degree margin and half a decade of
-// cutoff margin are applied.
+// Maps the network outputs to (m, lo): y0 = ln m*, y1 = log10(lo*/u), where
+// lo = 0 is trained as -6 (useful cutoffs lie in [10^-4.75, 10^-1.25] u) and
+// decoded below -5.25.  A 25% degree margin and half a decade of cutoff
+// margin are applied.
 void selector_decode(const float y[2], double u, int32_t *m, double *lo) {
   double md = std::exp((double)y[0]) * 1.25;
   if (!(md > 4.0)) md = 4.0;
   if (md > 400.0) md = 400.0;
   *m = (int32_t)std::ceil(md - 1e-3);  // tolerate FP32 rounding of the output
   const double z = (double)y[1];
-  *lo = (z < -11.0) ? 0.0 : u * std::pow(10.0, std::min(z, 0.0) - 0.5);
+  *lo = (z < -5.25) ? 0.0 : u * std::pow(10.0, std::min(z, 0.0) - 0.5);
+}
+
+// Numerical rank from the sketch's normalised moments mu_k = feat[2 + k]
+// (k = 1..12; mu_0 = 1): the share of the spectrum near 0 is the mean of
+// h(X) = ((1 - X) / 2)^12 over the eigenvalues, X = 2R/u - 1 (h = 1 at
+// x = 0, (1 - x/u)^12 elsewhere), expanded in Chebyshev polynomials of
+// degree <= 12 by repeated products with 0.5 T_0 - 0.5 T_1
+// (T_1 T_k = (T_{k+1} + T_{|k-1|}) / 2).  Returns n (1 - that share).
+double selector_rank(const float feat[16], int64_t n) {
+  double c[kFeatDegree + 2] = {1.0};
+  for (int q = 0; q < kFeatDegree; ++q) {
+    double nc[kFeatDegree + 2] = {0.0};
+    for (int k = 0; k <= q; ++k) {
+      nc[k] += 0.5 * c[k];
+      nc[k + 1] -= 0.25 * c[k];
+      nc[k == 0 ? 1 : k - 1] -= 0.25 * c[k];
+    }
+    std::memcpy(c, nc, sizeof(c));
+  }
+  double zero = c[0];
+  for (int k = 1; k <= kFeatDegree; ++k) zero += c[k] * (double)feat[2 + k];
+  return (double)n * (1.0 - zero);
 }
 
 // A-posteriori check: every moment bounded by ||g||^2 (the spectrum stayed in
@@ -1120,7 +1147,7 @@ bool selector_check(const std::vector<double> &mom, const std::vector<double> &a
 // stored in FP64 (CSR values are read in their stored precision) -- then the
 // features and the network on the device; y receives the network's outputs.
 ent_status feature_pass(const ent_matrix *R, uint64_t seed, const Opts &op, const SelectorState &st,
-                        float y[2], ent_result *fr) {
+                        float y[2], ent_result *fr, float *feat = nullptr) {
   const bool csr64 = R->layout == ENT_CSR && R->dtype == ENT_STORE_F64;
   Opts fo = op;
   fo.o.precision = csr64 ? ENT_F64 : ENT_F32;
@@ -1133,11 +1160,15 @@ ent_status feature_pass(const ent_matrix *R, uint64_t seed, const Opts &op, cons
   fh.params_dev = st.params;
   fh.y_dev = st.y;
   fh.y_host = y;
+  fh.feat_host = feat;
   const uint64_t fseed = seed ^ 0x5E1EC7ull;
   if (csr64)
     return run_poly<double>(R, ENT_CHEBYSHEV, kFeatDegree, kFeatProbes, fseed, fo, fr, nullptr, nullptr, &fh);
   return run_poly<float>(R, ENT_CHEBYSHEV, kFeatDegree, kFeatProbes, fseed, fo, fr, nullptr, nullptr, &fh);
 }
+
+ent_status run_randproj(const ent_matrix *R, uint64_t seed, const Opts &op, ent_result *out,
+                        double *sigma_out);
 
 ent_status run_auto(const ent_matrix *R, int32_t m_plain, int32_t s, uint64_t seed, const Opts &op,
                     ent_result *out, double *per_probe, double *moments) {
@@ -1152,10 +1183,40 @@ ent_status run_auto(const ent_matrix *R, int32_t m_plain, int32_t s, uint64_t se
     st = it->second;
   }
   // 1. sketch pass: power method + degree-12 Chebyshev moments with 16 probes
-  float y[2] = {0.f, 0.f};
+  float y[2] = {0.f, 0.f}, feat[16] = {};
   ent_result fr{};
-  ent_status rc = feature_pass(R, seed, op, st, y, &fr);
+  ent_status rc = feature_pass(R, seed, op, st, y, &fr, feat);
   if (rc != ENT_OK) return rc;
+  // 1b. on request, a numerically low-rank R (sketch rank at most 1/8 of the
+  // random projection's width) goes to Algorithm 3 (Section 5): one product;
+  // kept if the k singular values hold the unit trace (within 5%)
+  int32_t products = kFeatDegree;
+  const int32_t s_rp = op.o.sketch_width > 0 ? op.o.sketch_width : kRouteSketch;
+  if ((op.o.flags & ENT_FLAG_AUTO_RANDPROJ) && R->layout == ENT_DENSE &&
+      selector_rank(feat, R->n) <= s_rp / 8.0) {
+    Opts ro = op;
+    ro.o.sketch_width = s_rp;
+    ro.o.rank_k = op.o.rank_k > 0 ? std::min(op.o.rank_k, s_rp) : s_rp / 2;
+    ro.o.sketch = ENT_SKETCH_GAUSSIAN;
+    std::vector<double> sig(ro.o.rank_k);
+    ent_result r{};
+    rc = run_randproj(R, seed, ro, &r, sig.data());
+    if (rc != ENT_OK) return rc;
+    ++products;
+    double held = 0.0;
+    for (double v : sig) held += v;
+    if (std::fabs(held - 1.0) <= 0.05) {  // tr R = 1 (checked, or normalised)
+      r.p1_est = fr.p1_est;
+      r.u = fr.u;
+      r.method = ENT_RANDPROJ;
+      r.fell_back = 0;
+      r.products = products;
+      if (per_probe) std::fill(per_probe, per_probe + s, r.entropy);
+      if (moments) std::fill(moments, moments + (size_t)(m_plain + 1) * s, 0.0);
+      *out = r;
+      return ENT_OK;
+    }
+  }
   int32_t m_hat = 0;
   double lo = 0.0;
   selector_decode(y, fr.u, &m_hat, &lo);
@@ -1169,7 +1230,7 @@ ent_status run_auto(const ent_matrix *R, int32_t m_plain, int32_t s, uint64_t se
   ent_result r{};
   rc = poly_dispatch(R, ENT_CHEBYSHEV, m_hat, s, seed, mo, &r, per_probe, mom.data(), &mh);
   bool ok = rc == ENT_OK && selector_check(mom, alpha, m_hat, s);
-  int32_t products = kFeatDegree + m_hat;
+  products += m_hat;
   if (ok) {
     // the caller's table has (m_plain + 1) rows: copy the rows that fit
     if (moments) {

@@ -29,7 +29,7 @@ POWER_ITERS = 20
 U_FACTOR = 6.0
 TARGET_ERR = 5e-4
 M_MAX = 300
-ZERO_CODE = -12.5                                     # log10(lo/u) label meaning lo = 0
+ZERO_CODE = -6.0                                      # log10(lo/u) label meaning lo = 0 (decoded below -5.25)
 RHO_GRID = 10.0 ** (-np.arange(1, 49) / 4.0)          # lo/u candidates 10^-0.25 .. 10^-12
 CUTOFF_NODES = 1024
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.npz")

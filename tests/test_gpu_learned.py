@@ -150,3 +150,76 @@ def test_auto_moments_fit_the_callers_table():
 def test_selector_rejects_bad_params():
     with pytest.raises(ent.EntropyError):
         ent.selector_load(np.zeros(10, dtype=np.float32))
+
+
+def test_simulated_features_match_library_features():
+    """The training features are simulated from the spectrum alone (Gaussian
+    directions in the eigenbasis stand for the sketch's probes under a Haar
+    U).  On explicit R = U diag(p) U^T with random orthogonal U, the library's
+    own sketch features must follow the same law: per feature, the means of
+    48 library samples (6 matrices x 8 sketch seeds) and 2048 simulated ones
+    agree within 5 standard errors, and the spreads within a factor of 2."""
+    n = 512
+    ent.selector_load(np.zeros(ent.mlp_nparams(), dtype=np.float32))
+    rng = np.random.default_rng(17)
+    cases = (("exp", W.spectrum_exp(n, 60.0)), ("power", W.spectrum_power(n, 1.0)),
+             ("dirichlet", W.spectrum_dirichlet(n, 256, 0.5, rng)))
+    for name, p in cases:
+        lib = []
+        for u_seed in range(6):
+            R = torch.from_numpy(W.dense_density(p, 1000 + u_seed)).to(DEV)
+            for s_seed in range(8):
+                f, _ = ent.selector_features(R, 77 + 13 * s_seed)
+                lib.append(f.astype(np.float64))
+        lib = np.array(lib)
+        P = np.tile(p, (2048, 1))
+        sim, _, _, _ = L.batch_features_labels(P, np.ones_like(P), seed=5, device=DEV)
+        sim = sim.cpu().numpy().astype(np.float64)
+        for k in range(16):
+            a, b = lib[:, k], sim[:, k]
+            se = math.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
+            diff = abs(a.mean() - b.mean())
+            print(f"[features {name}] f{k:2d} library {a.mean():+.5f} +- {a.std():.5f}  "
+                  f"simulated {b.mean():+.5f} +- {b.std():.5f}  z={diff / max(se, 1e-12):.2f}", flush=True)
+            assert diff <= 5.0 * se + 2e-5, (name, k)
+            if b.std() > 1e-3:
+                assert 0.5 <= a.std() / b.std() <= 2.0, (name, k)
+
+
+def test_auto_routes_low_rank_to_randproj():
+    """With ENT_FLAG_AUTO_RANDPROJ, a numerically low-rank R (sketch rank <=
+    128 / 8) goes to Algorithm 3: the result is the random projection's own
+    (bit-identical to calling it with width 128, k = 64), with 12 + 1
+    products; its error is Algorithm 3's (the singular values of R Pi deviate
+    from the eigenvalues by O(sqrt(rank / width)); at most 4.7% in 200
+    simulated draws of each case below).  Without the flag nothing is
+    routed; a full-rank spectrum is not routed, and a power law whose sketch
+    looks low-rank (p_i ~ 1/i) is tried and rejected by the trace the
+    singular values hold, costing one product."""
+    ent.selector_load(np.zeros(ent.mlp_nparams(), dtype=np.float32))
+    n = 1024
+    F = ent.FLAG_AUTO_RANDPROJ
+    for k, kind in ((8, "flat"), (12, "exp")):
+        pk = np.ones(k) / k if kind == "flat" else np.exp(-np.arange(k) / 3.0)
+        pk = pk / pk.sum()
+        H = float(-np.sum(pk * np.log(pk)))
+        R = W.low_rank_density_torch(pk, n, 40 + k, device=DEV)
+        auto = ent.entropy_estimate(R, "auto", 40, 64, 5, flags=F)
+        rp = ent.entropy_estimate(R, "randproj", 40, 64, 5, sketch_width=128, rank_k=64)
+        plain = ent.entropy_estimate(R, "chebyshev", 40, 64, 5)
+        print(f"[route rank {k} {kind}] H={H:.6f} auto={auto.entropy:.6f} (method {auto.method}, "
+              f"products {auto.products}) plain m=40: {plain.entropy:.6f}", flush=True)
+        assert auto.method == ent.RANDPROJ and auto.products == 13 and auto.fell_back == 0
+        assert auto.entropy == rp.entropy
+        assert abs(auto.entropy - H) / H < 0.06
+        off = ent.entropy_estimate(R, "auto", 40, 64, 5)
+        assert off.method == ent.AUTO
+    full = ent.entropy_estimate(torch.from_numpy(W.dense_density(W.spectrum_exp(n, 60.0), 3)).to(DEV),
+                                "auto", 40, 64, 5, flags=F)
+    assert full.method == ent.AUTO
+    assert full.products == 12 + full.degree if not full.fell_back else full.products > 12 + 40
+    power = ent.entropy_estimate(torch.from_numpy(W.dense_density(W.spectrum_power(384, 1.0), 4)).to(DEV),
+                                 "auto", 40, 64, 5, flags=F)
+    print(f"[route power] method {power.method} products {power.products} degree {power.degree}", flush=True)
+    assert power.method == ent.AUTO
+    assert power.products == 13 + power.degree if not power.fell_back else power.products > 13 + 40
