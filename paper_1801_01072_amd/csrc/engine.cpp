@@ -734,6 +734,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
         a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.nblk = ntile; a.win = cwin;
         a.cg = scal + ent::S_ALPHA + kk;
+        a.s = s;
         HIP_TRY(ent::launch_csr_step<T>(a, st));
       }
       Vkm1 = Vk;
@@ -784,6 +785,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
       a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
       a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
       a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nblk = ntile; a.win = cwin;
+      a.s = s;
       HIP_TRY(ent::launch_csr_step<T>(a, st));
     }
     // Chebyshev: V_{k+1} is written over V_{k-1} (same element, same thread),

@@ -76,6 +76,8 @@ struct CsrStepArgs {
   int32_t nblk;         // persistent grid size (partial stride)
   const int2 *win;      // column window per row chunk (launch_csr_chunk_window)
   const double *cg;     // device scalar: z += (*cg) g (Clenshaw's alpha_k term); null: none
+  int32_t s;            // probes in use (<= ldv): columns past s are neither read
+                        // nor written, and their dot partials are zero; 0: ldv
 };
 
 // Per-matrix descriptor of a batch (device resident).  Offsets are in

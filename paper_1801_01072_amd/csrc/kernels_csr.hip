@@ -92,11 +92,12 @@ __device__ __forceinline__ int probe_of(int o, int e) {
 }
 
 // Lane o's P probes of row r in the chunk starting at probe chunk0 (a
-// multiple of 64): from V, or expanded from the sign bits.
+// multiple of 64): from V, or expanded from the sign bits.  A piece whose
+// probes all lie past the probes in use (pv[h] false) is not read: zeros.
 template <typename T, bool SIGNS>
 __device__ __forceinline__ void load_row(const T *__restrict__ V, const uint32_t *__restrict__ signs,
                                          int64_t r, int64_t ldv, int32_t nw, int32_t chunk0, int o,
-                                         T *x) {
+                                         T *x, const bool *pv) {
   constexpr int VE = CsrLanes<T>::VE;
   if (SIGNS) {
 #pragma unroll
@@ -110,7 +111,8 @@ __device__ __forceinline__ void load_row(const T *__restrict__ V, const uint32_t
     const T *src = V + r * ldv + chunk0 + VE * o;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const v16 q = *(const v16 *)(src + 32 * h);
+      v16 q = {};
+      if (pv[h]) q = *(const v16 *)(src + 32 * h);
 #pragma unroll
       for (int e = 0; e < VE; ++e) x[h * VE + e] = q[e];
     }
@@ -130,9 +132,10 @@ __device__ __forceinline__ void lds_row(const uint8_t *row, T *x) {
   }
 }
 
-// Lane o's P values z into row r of V (global memory).
+// Lane o's P values z into row r of V (global memory), pieces in use only.
 template <typename T>
-__device__ __forceinline__ void store_row(T *V, int64_t r, int64_t ldv, int32_t chunk0, int o, const T *z) {
+__device__ __forceinline__ void store_row(T *V, int64_t r, int64_t ldv, int32_t chunk0, int o, const T *z,
+                                          const bool *pv) {
   constexpr int VE = CsrLanes<T>::VE;
   typedef T v16 __attribute__((ext_vector_type(VE)));
   T *dst = V + r * ldv + chunk0 + VE * o;
@@ -141,7 +144,7 @@ __device__ __forceinline__ void store_row(T *V, int64_t r, int64_t ldv, int32_t 
     v16 q;
 #pragma unroll
     for (int e = 0; e < VE; ++e) q[e] = z[h * VE + e];
-    *(v16 *)(dst + 32 * h) = q;
+    if (pv[h]) *(v16 *)(dst + 32 * h) = q;
   }
 }
 
@@ -183,6 +186,12 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
   const int64_t n = a.n, ldv = a.ldv;
   const int32_t nw = (int32_t)(ldv >> 5);
   const int32_t chunk0 = (int32_t)blockIdx.y * 64;
+  // pieces of this lane holding probes in use (the last chunk of a probe
+  // count that is not a multiple of 64 skips the rest: no padding traffic)
+  const int32_t s_use = a.s > 0 ? a.s : (int32_t)ldv;
+  constexpr int VEC = C::VE;
+  const bool pv[2] = {chunk0 + VEC * o < s_use, chunk0 + 32 + VEC * o < s_use};
+  const int32_t chunk_bytes = (s_use - chunk0 < 64 ? s_use - chunk0 : 64) * (int32_t)sizeof(T);
   const int64_t *__restrict__ rp = a.row_ptr;
   const int32_t *__restrict__ ci = a.col_idx;
   const T *__restrict__ val = (const T *)a.values;
@@ -219,9 +228,11 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
       int64_t row = mw.x + byte / ROWB;
       row = row < mw.y ? row : mw.y;
       const uint8_t *src = (const uint8_t *)(Vk + row * ldv + chunk0) + byte % ROWB;
-      __builtin_amdgcn_global_load_lds((const void *)src,
-                                       (__attribute__((address_space(3))) void *)(&wbuf[b][0] + i * 1024),
-                                       16, 0, 0);
+      // 16-byte pieces past the probes in use are not copied (never used)
+      if ((byte % ROWB) < chunk_bytes)
+        __builtin_amdgcn_global_load_lds((const void *)src,
+                                         (__attribute__((address_space(3))) void *)(&wbuf[b][0] + i * 1024),
+                                         16, 0, 0);
     }
   };
 
@@ -246,7 +257,7 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
   __syncthreads();
   for (int64_t c = c_beg; c < c_end; ++c) {
     const int buf = (int)((c - c_beg) & 1);
-    if (zrow >= 0 && Vkp1) store_row<T>(Vkp1, zrow, ldv, chunk0, o, zs);
+    if (zrow >= 0 && Vkp1) store_row<T>(Vkp1, zrow, ldv, chunk0, o, zs, pv);
     zrow = -1;
     if (use_win && c + 1 < c_end) stage(c + 1, buf ^ 1);
     int2 mw = make_int2(0, 0);
@@ -272,20 +283,20 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
     if (inlds)
       lds_row<T>(wb + (rr - mw.x) * ROWB, xr);
     else
-      load_row<T, VK_SIGNS>(Vk, signs, rr, ldv, nw, chunk0, o, xr);
+      load_row<T, VK_SIGNS>(Vk, signs, rr, ldv, nw, chunk0, o, xr, pv);
     if (use_m1) {
       if (M1 == 2)
-        load_row<T, true>(nullptr, signs, rr, ldv, nw, chunk0, o, vm);
+        load_row<T, true>(nullptr, signs, rr, ldv, nw, chunk0, o, vm, pv);
       else
-        load_row<T, false>(Vkm1, nullptr, rr, ldv, nw, chunk0, o, vm);
+        load_row<T, false>(Vkm1, nullptr, rr, ldv, nw, chunk0, o, vm, pv);
     } else {
 #pragma unroll
       for (int e = 0; e < P; ++e) vm[e] = T(0);
     }
     if (signs)
-      load_row<T, true>(nullptr, signs, rr, ldv, nw, chunk0, o, gv);
+      load_row<T, true>(nullptr, signs, rr, ldv, nw, chunk0, o, gv, pv);
     else
-      load_row<T, false>(G, nullptr, rr, ldv, nw, chunk0, o, gv);
+      load_row<T, false>(G, nullptr, rr, ldv, nw, chunk0, o, gv, pv);
     // longest row of the wave: the number of gather rounds
     int mlen = len;
 #pragma unroll
@@ -323,7 +334,7 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
 #pragma unroll
           for (int q = 0; q < U; ++q) {
             const int32_t col = __shfl(mc[t], gl + q, 64);
-            load_row<T, VK_SIGNS>(Vk, signs, col, ldv, nw, chunk0, o, x[q]);
+            load_row<T, VK_SIGNS>(Vk, signs, col, ldv, nw, chunk0, o, x[q], pv);
           }
         }
 #pragma unroll
@@ -350,7 +361,14 @@ __global__ __launch_bounds__(64 * kCsrWaves) void csr_step_kernel(CsrStepArgs a)
     // the next window has landed, and every wave is done with this one
     __syncthreads();
   }
-  if (zrow >= 0 && Vkp1) store_row<T>(Vkp1, zrow, ldv, chunk0, o, zs);
+  if (zrow >= 0 && Vkp1) store_row<T>(Vkp1, zrow, ldv, chunk0, o, zs, pv);
+  // probes past the ones in use: their window bytes were never copied
+#pragma unroll
+  for (int e = 0; e < P; ++e)
+    if (!pv[e / VEC]) {
+      ds[e] = 0.0;
+      if (GG) gs[GG ? e : 0] = 0.0;
+    }
   // per probe: sum over the wave's rows (lanes o, o+L, ...), then over waves
 #pragma unroll
   for (int e = 0; e < P; ++e) {
