@@ -74,6 +74,7 @@ KERNEL_SOURCES = {
     "batch_dense_step_kernel": "kernels_dense.hip",
     "csr_step_kernel": "kernels_csr.hip",
     "band_step_kernel": "kernels_band.hip",
+    "tri_step_kernel": "kernels_tri.hip",
 }
 
 
@@ -135,6 +136,23 @@ def csr_step_bytes(n, nnz, s, m, vbytes, method):
         reads_vm1 = method == "chebyshev" and k > 1        # V_{k-1} for k = 1 is the sign block
         writes = method == "chebyshev" or k < steps - 1
         tot += csr + signs + blk * (reads_vk + reads_vm1 + writes)
+    return tot, steps
+
+
+def tri_step_bytes(n, s, m, vbytes, method):
+    """Algorithmic HBM bytes of the m product steps of the tridiagonal kernel:
+    three values (stored as four) per row, the probe sign bits and the V
+    blocks each step must read and write once."""
+    diag = 4 * vbytes * n
+    signs = n * s / 8
+    blk = n * s * vbytes
+    tot = 0.0
+    steps = m if method == "chebyshev" else m + 1
+    for k in range(steps):
+        reads_vk = k > 0
+        reads_vm1 = method == "chebyshev" and k > 1
+        writes = method == "chebyshev" or k < steps - 1
+        tot += diag + signs + blk * (reads_vk + reads_vm1 + writes)
     return tot, steps
 
 
@@ -733,7 +751,11 @@ def bench_single(args, cfg):
         nnz = int(Rd[0][-1]) if host_R is None else int(host_R[0][-1])
         vb = 8 if precision == "f64" else 4
         hp = int(last_t["csr_band"])
-        if hp > 0:
+        if hp == 1:
+            # tridiagonal input: the three-row stencil kernel
+            kernel = "tri_step_kernel"
+            tot_bytes, steps = tri_step_bytes(n, s, m, vb, cfg["method"])
+        elif hp > 0:
             # banded input: the step ran on the 16-row slabs
             kernel = "band_step_kernel"
             tot_bytes, steps = band_step_bytes(n, hp, s, m, vb, cfg["method"])

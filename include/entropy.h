@@ -38,7 +38,8 @@
  *    that would exceed the cap returns ENT_ENOMEM.  A CSR R served by the
  *    banded kernels (ENT_FLAG_CSR_GENERAL, ENT_FLAG_CSR_BANDED) adds its slab
  *    copy to the workspace: 16 + 2 hp values of the compute type per row,
- *    rounded up to 16 rows, rebuilt by every call and never kept past it.
+ *    rounded up to 16 rows, rebuilt by every call and never kept past it;
+ *    a tridiagonal CSR R its three diagonals (4 values per row, likewise).
  */
 #ifndef ENTROPY_H
 #define ENTROPY_H
@@ -126,7 +127,12 @@ enum {
                                     term recurrence; see ent_entropy_estimate */
   ENT_FLAG_CSR_GENERAL = 16,     /* CSR R: always the general CSR kernels.  By
                                     default an R whose entries all lie within
-                                    16 of the diagonal runs the banded kernels
+                                    one of the diagonal (tridiagonal, at most
+                                    3n entries) runs the tridiagonal step
+                                    kernel on a per-estimate copy of its three
+                                    diagonals (power method on the CSR
+                                    arrays), and one whose entries all lie
+                                    within 16 of the diagonal the banded kernels
                                     (steps and power method) on a per-estimate
                                     copy of R in 16-row slabs of 16 + 2 hp
                                     values per row (hp = 4, 8 or 16, the half-
@@ -134,7 +140,8 @@ enum {
                                     more bytes per row than the CSR arrays;
                                     same results within rounding             */
   ENT_FLAG_CSR_BANDED = 32,      /* CSR R within 16 of the diagonal: the banded
-                                    kernels whatever the byte counts          */
+                                    kernels whatever the byte counts (also for
+                                    a tridiagonal R)                          */
   ENT_FLAG_NORMALIZE = 64,       /* estimate H(R / tr R) instead of requiring
                                     tr R = 1 (Section 1.1: a density matrix
                                     has unit trace).  tr R is computed on the
@@ -380,7 +387,8 @@ typedef struct {
   int32_t power_launches;
   int32_t epilogue_launches;
   int32_t csr_band;      /* CSR R: padded half-bandwidth (4, 8 or 16) of the
-                            banded step kernel that ran; 0: the general CSR
+                            banded step kernel that ran, 1 for the
+                            tridiagonal step kernel; 0: the general CSR
                             kernel or a dense path                            */
 } ent_timing;
 

@@ -567,8 +567,10 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   }
 
   // CSR: validate the structure, and serve a matrix whose entries all lie
-  // within 16 of the diagonal with the banded step kernel
+  // within one of the diagonal with the tridiagonal step kernel, within 16
+  // with the banded step kernel
   int32_t hp = 0;
+  bool tri = false;
   if (!dense) {
     ent_status rc0 = ws.ensure(256);
     if (rc0 != ENT_OK) return rc0;
@@ -578,16 +580,20 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     const double csr_row = ((double)(sizeof(T) + 4) * (double)R->nnz + 8.0 * (double)(n + 1)) / (double)n;
     const bool forced = (o.flags & ENT_FLAG_CSR_BANDED) != 0;
     const bool want = !(o.flags & ENT_FLAG_CSR_GENERAL) && (forced || 24.0 * sizeof(T) <= csr_row);
+    // at most three entries per row (duplicates aside) may be tridiagonal
+    const bool maybe_tri = !(o.flags & (ENT_FLAG_CSR_GENERAL | ENT_FLAG_CSR_BANDED)) && R->nnz <= 3 * n;
     int32_t hbw = 0;
-    rc0 = check_csr(R, ws.ptr(), st, want ? &hbw : nullptr);
+    rc0 = check_csr(R, ws.ptr(), st, (want || maybe_tri) ? &hbw : nullptr);
     if (rc0 != ENT_OK) return rc0;
-    if (want) hp = ent::band_half_width_padded(hbw);
+    tri = maybe_tri && hbw <= 1;
+    if (want && !tri) hp = ent::band_half_width_padded(hbw);
     if (hp > 0 && (double)(16 + 2 * hp) * sizeof(T) > csr_row && !forced) hp = 0;
   }
   const bool banded = hp > 0;
   const int32_t ntile = dense ? (int32_t)(n_pad / 64)
-                              : (banded ? ent::band_step_waves(n, hp, sizeof(T) == 8)
-                                        : ent::csr_step_blocks(n, sizeof(T) == 8));
+                              : (tri ? ent::tri_step_blocks(n, sizeof(T) == 8)
+                                     : (banded ? ent::band_step_waves(n, hp, sizeof(T) == 8)
+                                               : ent::csr_step_blocks(n, sizeof(T) == 8)));
   // dense steps whose tile grid is smaller than the chip split K
   const int32_t ksplit = dense ? ent::dense_step_splits(n, ntile, ldv, bn) : 1;
   const int64_t kper = round_up((n + ksplit - 1) / ksplit, 32);
@@ -603,14 +609,15 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
 
   double *scal = nullptr, *x0 = nullptr, *x1 = nullptr, *p0 = nullptr, *p1 = nullptr;
   double *part = nullptr, *d = nullptr, *h = nullptr;
-  T *Rc = nullptr, *G = nullptr, *VA = nullptr, *VB = nullptr, *band = nullptr;
+  T *Rc = nullptr, *G = nullptr, *VA = nullptr, *VB = nullptr, *band = nullptr, *trid = nullptr;
   uint32_t *signs = nullptr;
   int2 *cwin = nullptr;
   const int32_t ch = ent::csr_chunk_rows(sizeof(T) == 8);
   Carve cv;
   cv.add(&scal, kScalarDoubles);
-  if (!dense && !banded) cv.add(&cwin, (size_t)((n + ch - 1) / ch));
+  if (!dense && !banded && !tri) cv.add(&cwin, (size_t)((n + ch - 1) / ch));
   if (banded) cv.add(&band, ent::band_pack_elems(n, hp));
+  if (tri) cv.add(&trid, 4 * (size_t)n);
   if (use_power) {
     cv.add(&x0, n_pad);
     cv.add(&x1, n_pad);
@@ -635,7 +642,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   PhaseEvents pe;
   pe.on = g_timing_on && !op.no_alloc;
   pe.st = st;
-  pe.csr_band = hp;
+  pe.csr_band = tri ? 1 : hp;
   pe.mark();
   HIP_TRY(ent::launch_zero(scal, sizeof(double) * 64, st));
   // CSR step launches may use fewer workgroups than the partial stride
@@ -671,6 +678,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   }
   if (banded)
     HIP_TRY(ent::launch_band_pack<T>(R->row_ptr, R->col_idx, (const T *)R->values, n, hp, band, st));
+  else if (tri)
+    HIP_TRY(ent::launch_tri_pack<T>(R->row_ptr, R->col_idx, (const T *)R->values, n, trid, st));
   else if (!dense)
     HIP_TRY(ent::launch_csr_chunk_window(R->row_ptr, R->col_idx, n, ch, cwin, st));
   // probes
@@ -726,6 +735,15 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.nwave = ntile;
         a.cg = scal + ent::S_ALPHA + kk;
         HIP_TRY(ent::launch_band_step<T>(a, hp, st));
+      } else if (tri) {
+        ent::TriStepArgs a{};
+        a.diag = trid; a.n = n; a.ldv = ldv; a.s = s;
+        a.Vk = Vk; a.Vkm1 = k == 0 ? nullptr : Vkm1; a.Vkp1 = Vout;
+        a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
+        a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
+        a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.nblk = ntile;
+        a.cg = scal + ent::S_ALPHA + kk;
+        HIP_TRY(ent::launch_tri_step<T>(a, st));
       } else {
         ent::CsrStepArgs a{};
         a.row_ptr = R->row_ptr; a.col_idx = R->col_idx; a.values = R->values; a.n = n; a.ldv = ldv;
@@ -778,6 +796,14 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
       a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
       a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nwave = ntile;
       HIP_TRY(ent::launch_band_step<T>(a, hp, st));
+    } else if (tri) {
+      ent::TriStepArgs a{};
+      a.diag = trid; a.n = n; a.ldv = ldv; a.s = s;
+      a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr;
+      a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
+      a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
+      a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nblk = ntile;
+      HIP_TRY(ent::launch_tri_step<T>(a, st));
     } else {
       ent::CsrStepArgs a{};
       a.row_ptr = R->row_ptr; a.col_idx = R->col_idx; a.values = R->values; a.n = n; a.ldv = ldv;

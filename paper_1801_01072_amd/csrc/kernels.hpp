@@ -189,6 +189,34 @@ hipError_t launch_csr_chunk_window(const int64_t *rp, const int32_t *ci, int64_t
                                    int2 *win, hipStream_t st);
 
 
+// ---- tridiagonal CSR (every entry within one of the diagonal) ---------------
+// Row r's values as {l_r, d_r, u_r, 0} (4 n elements of type T), duplicate
+// entries summed in entry order.
+template <typename T>
+hipError_t launch_tri_pack(const int64_t *rp, const int32_t *ci, const T *val, int64_t n, T *D, hipStream_t st);
+struct TriStepArgs {
+  const void *diag;    // launch_tri_pack output, element type T
+  int64_t n;
+  int64_t ldv;         // padded probe count (multiple of 64)
+  int32_t s;           // probes in use (<= ldv; 0: ldv): later columns are not touched
+  const void *Vk;      // null: V_k is the sign block (first step)
+  const void *Vkm1;    // null: V_{k-1} is the sign block (if cw != 0)
+  void *Vkp1;          // null: no write (last Taylor step)
+  const uint32_t *signs;  // Rademacher sign bits [n_pad][ldv/32] (null: Gaussian)
+  const void *G;          // Gaussian probe block (null: Rademacher)
+  const double *scal;
+  double c1, c2, cw;
+  int32_t dot_y;
+  int32_t slot;
+  int32_t slot_gg;
+  double *part;        // partials [slot][block][ldv]
+  int32_t nblk;        // workgroups of the grid (partial stride), from tri_step_blocks
+  const double *cg;    // device scalar: z += (*cg) g (Clenshaw's alpha_k term); null: none
+};
+int32_t tri_step_blocks(int64_t n, int32_t fp64);
+template <typename T>
+hipError_t launch_tri_step(const TriStepArgs &a, hipStream_t st);
+
 // ---- banded CSR (every entry within HP of the diagonal) -----------------------
 // Half-bandwidth max |col - row| of a validated CSR matrix into out[0] (which
 // must start at 0); the padded half-bandwidth (4, 8 or 16) the banded step

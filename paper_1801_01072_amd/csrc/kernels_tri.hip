@@ -1,0 +1,246 @@
+// kernels_tri.hip -- one step of the polynomial recurrence for a tridiagonal
+// R (every entry within one of the diagonal: the paper's Poisson experiment
+// of Section 6 and any R of that pattern), HBM-bound: the product
+// (R V)_r = l_r V_{r-1} + d_r V_r + u_r V_{r+1} is a three-row stencil, so
+// the step streams V_k, V_{k-1}, the probes and three values per row once and
+// writes V_{k+1} once, with no index arrays and no gathers.
+//
+// Mapping: a wave runs four independent streams (lanes 16 q .. 16 q + 15),
+// each over its own contiguous range of rows; lane p of a stream owns probes
+// 4 p .. 4 p + 3 of the workgroup's 64-probe chunk, so each row access is one
+// contiguous 256-byte (FP32) or 512-byte (FP64) piece per stream.  A stream
+// keeps V_{r-1} and V_r in registers and loads two new rows per iteration, so
+// every V_k row is read once; latency is hidden by occupancy (loading the
+// next iteration's rows ahead, or four rows per iteration, measured no
+// faster: 30.1 and 31.2 ms against 29.0 ms per step at n = 10^8, s = 100,
+// which moves about 126 GB, near what a device copy reaches here with this
+// share of writes).  Per-probe dot partials stay in
+// FP64 registers (fixed-order sums: rows in order within a stream, streams
+// and waves combined in a fixed order).  Rademacher probes are read as packed
+// sign bits, also where V_k or V_{k-1} is the probe block itself.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace ent {
+
+namespace {
+constexpr int kTriWaves = 4;                 // waves per workgroup
+constexpr int kTriStreams = 4 * kTriWaves;   // row streams per workgroup
+constexpr int kTriRows = 2;                  // rows per stream iteration
+}  // namespace
+
+// Tridiagonal values of row r as {l_r, d_r, u_r, 0}; duplicate entries are
+// summed in entry order.  One thread per row.
+template <typename T>
+__global__ __launch_bounds__(256) void tri_pack_kernel(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                       const T *__restrict__ val, int64_t n, T *__restrict__ D) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  T l = T(0), d = T(0), u = T(0);
+  for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+    const int64_t off = (int64_t)ci[e] - r;
+    if (off < 0)
+      l += val[e];
+    else if (off == 0)
+      d += val[e];
+    else
+      u += val[e];
+  }
+  D[4 * r] = l;
+  D[4 * r + 1] = d;
+  D[4 * r + 2] = u;
+  D[4 * r + 3] = T(0);
+}
+
+template <typename T>
+hipError_t launch_tri_pack(const int64_t *rp, const int32_t *ci, const T *val, int64_t n, T *D, hipStream_t st) {
+  const int64_t blocks = (n + 255) / 256;
+  tri_pack_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(rp, ci, val, n, D);
+  return hipGetLastError();
+}
+template hipError_t launch_tri_pack<double>(const int64_t *, const int32_t *, const double *, int64_t, double *,
+                                            hipStream_t);
+template hipError_t launch_tri_pack<float>(const int64_t *, const int32_t *, const float *, int64_t, float *,
+                                           hipStream_t);
+
+// VK_SIGNS: V_k is the sign block.  M1: no V_{k-1} term (0), V_{k-1} stored
+// (1) or the sign block (2).  GG: also accumulate g.g (first Chebyshev step).
+template <typename T, bool VK_SIGNS, int M1, bool GG>
+__global__ __launch_bounds__(64 * kTriWaves) void tri_step_kernel(TriStepArgs a) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  __shared__ double red[2][kTriWaves][64];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = tid >> 6, q = lane >> 4, p = lane & 15;
+  const int64_t n = a.n, ldv = a.ldv;
+  const int32_t chunk0 = (int32_t)blockIdx.y * 64;
+  const int32_t s_use = a.s > 0 ? a.s : (int32_t)ldv;
+  const int32_t col = chunk0 + 4 * p;
+  // a lane whose probes all lie past the ones in use reads and writes nothing
+  const bool pv = col < s_use;
+  const int64_t nw = ldv >> 5;
+  const int32_t wsel = col >> 5, bsh = col & 31;
+  const T *__restrict__ D = (const T *)a.diag;
+  const T *__restrict__ Vk = (const T *)a.Vk;
+  const T *__restrict__ G = (const T *)a.G;
+  const uint32_t *__restrict__ signs = a.signs;
+  // V_{k+1} is written over V_{k-1} element by element by the lane that
+  // read it, so these two may alias each other (and nothing else)
+  const T *Vkm1 = (const T *)a.Vkm1;
+  T *Vkp1 = (T *)a.Vkp1;
+  const T ta = (T)a.scal[S_A];
+  const T tb = (T)(a.c2 * a.scal[S_B]);
+  const T tc1 = (T)a.c1, tcw = (T)a.cw;
+  const bool use_cg = a.cg != nullptr;
+  const T tcg = use_cg ? (T)a.cg[0] : T(0);
+
+  // this stream's rows [r_beg, r_end): equal shares, a multiple of kTriRows
+  const int64_t nstream = (int64_t)gridDim.x * kTriStreams;
+  const int64_t sid = (int64_t)blockIdx.x * kTriStreams + w * 4 + q;
+  int64_t share = (n + nstream - 1) / nstream;
+  share = (share + kTriRows - 1) / kTriRows * kTriRows;
+  const int64_t r_beg = sid * share < n ? sid * share : n;
+  const int64_t r_end = r_beg + share < n ? r_beg + share : n;
+
+  // row r of the sign block as this lane's four probes; zero outside [0, n)
+  auto signs_row = [&](int64_t r) -> v4 {
+    v4 x = {T(0), T(0), T(0), T(0)};
+    if (pv && r >= 0 && r < n) {
+      const uint32_t bits = signs[r * nw + wsel] >> bsh;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = ((bits >> e) & 1u) ? T(-1) : T(1);
+    }
+    return x;
+  };
+  auto v_row = [&](const T *V, int64_t r) -> v4 {
+    v4 x = {T(0), T(0), T(0), T(0)};
+    if (pv && r >= 0 && r < n) x = *(const v4 *)(V + r * ldv + col);
+    return x;
+  };
+  auto vk_row = [&](int64_t r) -> v4 { return VK_SIGNS ? signs_row(r) : v_row(Vk, r); };
+  auto vm_row = [&](int64_t r) -> v4 {
+    if (M1 == 2) return signs_row(r);
+    if (M1 == 1) return v_row(Vkm1, r);
+    return v4{T(0), T(0), T(0), T(0)};
+  };
+  auto g_row = [&](int64_t r) -> v4 { return signs ? signs_row(r) : v_row(G, r); };
+  auto d_row = [&](int64_t r) -> v4 {
+    v4 x = {T(0), T(0), T(0), T(0)};
+    if (r < n) x = *(const v4 *)(D + 4 * r);
+    return x;
+  };
+
+  double ds[4] = {0.0, 0.0, 0.0, 0.0}, gs[4] = {0.0, 0.0, 0.0, 0.0};
+  auto row = [&](int64_t r, const v4 &vp, const v4 &vc, const v4 &vn, const v4 &vm, const v4 &gv, const v4 &dd) {
+    v4 z;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const T y = ta * ((dd[0] * vp[e] + dd[1] * vc[e]) + dd[2] * vn[e]);
+      T ze = tc1 * y + tb * vc[e];
+      if (M1 != 0) ze += tcw * vm[e];
+      if (use_cg) ze += tcg * gv[e];
+      z[e] = ze;
+      ds[e] += (double)gv[e] * (double)(a.dot_y ? y : ze);
+      if (GG) gs[e] += (double)gv[e] * (double)gv[e];
+    }
+    if (Vkp1 && pv) *(v4 *)(Vkp1 + r * ldv + col) = z;
+  };
+
+  if (r_beg < r_end) {
+    v4 vp = vk_row(r_beg - 1), vc = vk_row(r_beg);
+    for (int64_t r = r_beg; r < r_end; r += kTriRows) {
+      const v4 n1 = vk_row(r + 1), n2 = vk_row(r + 2);
+      const v4 m0 = vm_row(r), m1 = vm_row(r + 1);
+      const v4 g0 = g_row(r), g1 = g_row(r + 1);
+      const v4 d0 = d_row(r), d1 = d_row(r + 1);
+      row(r, vp, vc, n1, m0, g0, d0);
+      if (r + 1 < r_end) row(r + 1, vc, n1, n2, m1, g1, d1);
+      vp = n1;
+      vc = n2;
+    }
+  }
+  // per probe: the four streams of the wave (lanes p, p + 16, p + 32, p + 48),
+  // then the waves of the workgroup, in a fixed order
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    ds[e] += __shfl_xor(ds[e], 16, 64);
+    ds[e] += __shfl_xor(ds[e], 32, 64);
+    if (GG) {
+      gs[e] += __shfl_xor(gs[e], 16, 64);
+      gs[e] += __shfl_xor(gs[e], 32, 64);
+    }
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      red[0][w][4 * p + e] = ds[e];
+      red[1][w][4 * p + e] = GG ? gs[e] : 0.0;
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kTriWaves; ++k) {
+      t0 += red[0][k][lane];
+      t1 += red[1][k][lane];
+    }
+    const int64_t bidx = (int64_t)blockIdx.x * ldv + chunk0 + lane;
+    a.part[(int64_t)a.slot * a.nblk * ldv + bidx] = t0;
+    if (GG) a.part[(int64_t)a.slot_gg * a.nblk * ldv + bidx] = t1;
+  }
+}
+
+// Workgroups resident at once (CUs x per-CU occupancy of the widest
+// instance), fewer when the rows give each stream less than 64 rows.
+int32_t tri_step_blocks(int64_t n, int32_t fp64) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  const hipError_t e =
+      fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)tri_step_kernel<double, false, 1, false>,
+                                                          64 * kTriWaves, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)tri_step_kernel<float, false, 1, false>,
+                                                          64 * kTriWaves, 0);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  const int64_t cap = (int64_t)cus * per_cu;
+  const int64_t want = (n + 64 * kTriStreams - 1) / (64 * kTriStreams);
+  return (int32_t)(want < 1 ? 1 : (want < cap ? want : cap));
+}
+
+template <typename T, bool VK_SIGNS, int M1, bool GG>
+static void tri_step_launch(const TriStepArgs &a, hipStream_t st) {
+  dim3 grid((unsigned)a.nblk, (unsigned)(a.ldv / 64));
+  tri_step_kernel<T, VK_SIGNS, M1, GG><<<grid, 64 * kTriWaves, 0, st>>>(a);
+}
+
+template <typename T>
+hipError_t launch_tri_step(const TriStepArgs &a, hipStream_t st) {
+  const bool vk_signs = a.Vk == nullptr;
+  const int m1 = a.cw == 0.0 ? 0 : (a.Vkm1 == nullptr ? 2 : 1);
+  const bool gg = a.slot_gg >= 0;
+  if ((vk_signs || m1 == 2) && !a.signs) return hipErrorInvalidValue;
+  if (a.nblk < 1 || a.ldv % 64 != 0) return hipErrorInvalidValue;
+  if (gg) {
+    if (m1 != 0) return hipErrorInvalidValue;  // g.g is taken on the first step only
+    if (vk_signs)
+      tri_step_launch<T, true, 0, true>(a, st);
+    else
+      tri_step_launch<T, false, 0, true>(a, st);
+  } else if (m1 == 0) {
+    if (vk_signs)
+      tri_step_launch<T, true, 0, false>(a, st);
+    else
+      tri_step_launch<T, false, 0, false>(a, st);
+  } else {
+    if (vk_signs) return hipErrorInvalidValue;  // V_k is stored from the second step on
+    if (m1 == 2)
+      tri_step_launch<T, false, 2, false>(a, st);
+    else
+      tri_step_launch<T, false, 1, false>(a, st);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_tri_step<double>(const TriStepArgs &, hipStream_t);
+template hipError_t launch_tri_step<float>(const TriStepArgs &, hipStream_t);
+
+}  // namespace ent

@@ -181,18 +181,21 @@ def test_wider_band_runs_general_kernel(orc):
 def test_default_kernel_choice_by_bytes(orc):
     # half-bandwidth 16 with 33 entries per row: slabs of 48 values per row
     # are smaller than the CSR arrays (FP32: 192 against 272 bytes), so the
-    # banded kernels run by default; a tridiagonal R (3 entries per row, slabs
-    # of 24 values) stays on the general kernels unless forced
+    # banded kernels run by default; a tridiagonal R (3 entries per row) runs
+    # the tridiagonal kernel, the general kernels or the slabs when asked
     n, m, s, seed = 20_000, 12, 64, 4
     csr = W.banded_density_csr(n, 8, seed=5, dtype=np.float32)
     assert run(csr, "chebyshev", m, s, seed, precision="f32")[3] == 16
     tri = W.poisson_csr_fast(n)
     res, per, _, band = run(tri, "chebyshev", m, s, seed)
-    assert band == 0
+    assert band == 1
+    res1, per1, _, band1 = run(tri, "chebyshev", m, s, seed, flags=ent.FLAG_CSR_GENERAL)
+    assert band1 == 0
     res2, per2, _, band2 = run(tri, "chebyshev", m, s, seed, flags=ent.FLAG_CSR_BANDED)
     assert band2 == 4
     ref = orc.estimate(tri, 1, m, s, seed)
-    assert per_probe_rel(per, ref) <= TOL64 and per_probe_rel(per2, ref) <= TOL64
+    for p in (per, per1, per2):
+        assert per_probe_rel(p, ref) <= TOL64
 
 
 @pytest.mark.parametrize("method,flags", [("chebyshev", 0), ("taylor", 0), ("chebyshev", ent.FLAG_CLENSHAW)])

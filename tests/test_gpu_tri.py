@@ -1,0 +1,136 @@
+"""GPU parity of the tridiagonal step kernel (a CSR R whose entries all lie
+within one of the diagonal, such as the Poisson matrix of Section 6): which
+kernel ran, per-probe values against the FP64 oracle for both precisions,
+every schedule and probe distribution, ragged sizes and probe counts,
+duplicate and missing entries, and agreement with the general CSR kernel on
+the same input."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tolerances import TOL64, TOL_F32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1801_01072_amd as ent  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def csr_to_dev(csr):
+    rp, ci, val, n = csr
+    return (torch.from_numpy(rp).to(DEV), torch.from_numpy(ci).to(DEV), torch.from_numpy(val).to(DEV), n)
+
+
+def run(csr, method, m, s, seed, **kw):
+    ent.timing_enable(True)
+    try:
+        res, per, mom = ent.entropy_estimate_detail(csr_to_dev(csr), method, m, s, seed, **kw)
+        kern = ent.last_timing()["csr_band"]
+    finally:
+        ent.timing_enable(False)
+    return res, per, mom, kern
+
+
+def rel(per, ref):
+    return float(np.max(np.abs(per - ref.per_probe)) / max(np.mean(np.abs(ref.per_probe)), 1e-2))
+
+
+def random_tridiagonal(n, seed, dtype=np.float64):
+    """R = B B^T / tr with B lower bidiagonal is pentadiagonal; a symmetric
+    positive tridiagonal R instead: diagonally dominant, random off-diagonal."""
+    rng = np.random.default_rng(seed)
+    off = rng.uniform(-1.0, 1.0, size=max(n - 1, 0))
+    diag = np.abs(np.concatenate([[0.0], off])) + np.abs(np.concatenate([off, [0.0]])) + rng.uniform(0.1, 1.0, n)
+    tr = diag.sum()
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        for j, v in ((i - 1, off[i - 1] if i > 0 else 0.0), (i, diag[i]), (i + 1, off[i] if i < n - 1 else 0.0)):
+            if 0 <= j < n:
+                rows.append(i)
+                cols.append(j)
+                vals.append(v / tr)
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, np.array(rows) + 1, 1)
+    return np.cumsum(rp), np.array(cols, np.int32), np.array(vals, dtype), n
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("method,flags", [("chebyshev", 0), ("taylor", 0), ("chebyshev", ent.FLAG_CLENSHAW)])
+@pytest.mark.parametrize("dist", ["rademacher", "gaussian"])
+def test_tri_schedules_probes_precisions(orc, dtype, method, flags, dist):
+    n, m, s, seed = 30_001, 25, 96, 13
+    csr = random_tridiagonal(n, 3, dtype)
+    prec = "f64" if dtype == np.float64 else "f32"
+    d = 0 if dist == "rademacher" else 1
+    res, per, mom, kern = run(csr, method, m, s, seed, probe_dist=dist, precision=prec, flags=flags)
+    ref = orc.estimate(csr, 0 if method == "taylor" else 1, m, s, seed, dist=d)
+    err = rel(per, ref)
+    print(f"[tri {prec} {method} flags={flags} {dist}] kernel {kern}; H gpu={res.entropy:.12f} "
+          f"oracle={ref.entropy:.12f} per-probe rel {err:.2e}", flush=True)
+    assert kern == 1
+    assert err <= (TOL64 if dtype == np.float64 else TOL_F32)
+    if dtype == np.float64:
+        assert abs(res.entropy - ref.entropy) <= TOL64 * abs(ref.entropy)
+        if method == "chebyshev" and not flags:
+            for j in (0, s - 1):
+                g = orc.probe_vector(seed, d, 0, n, j)
+                dref = orc.cheb_moments_forward(csr, 0.0, ref.u, m, g)
+                assert np.max(np.abs(mom[:, j] - dref)) <= TOL64 * float(g @ g)
+
+
+@pytest.mark.parametrize("n,s", [(1, 1), (2, 3), (3, 64), (5, 65), (33, 100), (1000, 130), (4097, 50)])
+def test_tri_ragged(orc, n, s):
+    # n of one, two or a few rows (streams with no rows, with one row, with
+    # an odd count); probe counts below, at and past one 64-probe chunk
+    csr = W.poisson_csr(n) if n > 1 else (np.array([0, 1], np.int64), np.array([0], np.int32), np.ones(1), 1)
+    m, seed = 9, 7
+    for dist in ("rademacher", "gaussian"):
+        d = 0 if dist == "rademacher" else 1
+        res, per, _, kern = run(csr, "chebyshev", m, s, seed, probe_dist=dist)
+        ref = orc.estimate(csr, 1, m, s, seed, dist=d)
+        err = rel(per, ref)
+        print(f"[tri ragged n={n} s={s} {dist}] kernel {kern}; per-probe rel {err:.2e}", flush=True)
+        assert kern == 1
+        assert err <= TOL64
+
+
+def test_tri_duplicates_missing_entries_and_general_agreement(orc):
+    # rows with no coupling to their neighbours (a block-diagonal tridiagonal
+    # R), duplicate diagonal entries (summed; within the 3n entries that make
+    # a tridiagonal candidate) and an all-diagonal R run the tridiagonal
+    # kernel; the general CSR kernel agrees on each
+    n, m, s, seed = 5000, 15, 64, 21
+    rp, ci, val, _ = random_tridiagonal(n, 9)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    # cut the coupling between rows 99 and 100, 199 and 200, ...
+    keep = ~((np.abs(ci - rows) == 1) & ((np.minimum(ci, rows) % 100) == 99))
+    ci, val, rows = ci[keep], val[keep], rows[keep]
+
+    def build(r, c, v):
+        order = np.argsort(r, kind="stable")
+        ptr = np.zeros(n + 1, np.int64)
+        np.add.at(ptr, r[order] + 1, 1)
+        return np.cumsum(ptr), c[order].astype(np.int32), v[order], n
+
+    cut = build(rows, ci, val)
+    # the diagonal entry of every 100th row stored as two halves
+    twice = (ci == rows) & (rows % 100 == 0)
+    dup = build(np.concatenate([rows, rows[twice]]), np.concatenate([ci, ci[twice]]),
+                np.concatenate([np.where(twice, val / 2, val), val[twice] / 2]))
+    assert dup[0][-1] <= 3 * n
+    p = np.random.default_rng(2).uniform(0.5, 1.5, n)
+    p /= p.sum()
+    dg = (np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32), p, n)
+    for name, csr, base in (("cut", cut, cut), ("duplicates", dup, cut), ("diagonal", dg, dg)):
+        res, per, _, kern = run(csr, "chebyshev", m, s, seed)
+        res_g, per_g, _, kern_g = run(csr, "chebyshev", m, s, seed, flags=ent.FLAG_CSR_GENERAL)
+        ref = orc.estimate(base, 1, m, s, seed)
+        print(f"[tri {name}] kernel {kern} / {kern_g}; per-probe rel {rel(per, ref):.2e} "
+              f"(general {rel(per_g, ref):.2e})", flush=True)
+        assert kern == 1 and kern_g == 0
+        assert rel(per, ref) <= TOL64 and rel(per_g, ref) <= TOL64
