@@ -69,9 +69,11 @@ WORKLOADS = {
 
 KERNEL_SOURCES = {
     "bf16x3_gemm_kernel": "kernels_bf16.hip",
-    "batch_bf16x3_gemm_kernel": "kernels_bf16.hip",
+    "batch_bf16x3_step_kernel": "kernels_bf16.hip",
+    "batch_bf16x3_persistent_kernel": "kernels_bf16.hip",
     "dense_step_kernel": "kernels_dense.hip",
     "batch_dense_step_kernel": "kernels_dense.hip",
+    "batch_dense_persistent_kernel": "kernels_dense.hip",
     "csr_step_kernel": "kernels_csr.hip",
     "band_step_kernel": "kernels_band.hip",
     "tri_step_kernel": "kernels_tri.hip",
@@ -189,11 +191,15 @@ def bench_batch(args, cfg):
     mats = []
     for i, p in enumerate(spectra):
         mats.append(W.dense_density_torch(p, mseed * 7 + i, device="cuda:0", dtype=torch.float32))
+        if (i + 1) % 128 == 0:
+            torch.cuda.synchronize()
+            log(f"generated {i + 1}/{count} matrices ({time.time() - t0:.1f} s)")
     torch.cuda.synchronize()
     sum_n2 = float(np.sum(ns.astype(np.float64) ** 2))
     log(f"generated {count} matrices (sum n^2 = {sum_n2:.3e}) in {time.time() - t0:.1f}s")
+    flags = ent.FLAG_AUTOTUNE | (ent.FLAG_BATCH_STEPWISE if getattr(args, "batch_stepwise", False) else 0)
     g = ent.Graph(mats, cfg["method"], m, s, pseed, precision=precision, probe_dist=cfg["dist"],
-                  power_iters=t, flags=ent.FLAG_AUTOTUNE)
+                  power_iters=t, flags=flags)
     log(f"graph ready: tile rows {g.tile_rows}, step schedule window {g.window_bytes >> 20} MB "
         f"(0: one launch per step), workspace {g.workspace_bytes / 1e9:.2f} GB")
     for _ in range(args.warmup):
@@ -211,8 +217,18 @@ def bench_batch(args, cfg):
     flop = 2.0 * sum_n2 * s
     achieved = flop / (avg_step_ms * 1e-3) / 1e12
     peak = MFMA_PEAK_TFLOPS[precision]
-    kernel = "batch_bf16x3_gemm_kernel" if precision == "bf16x3" else "batch_dense_step_kernel"
-    log(f"{kernel}: {avg_step_ms:.3f} ms/launch -> {achieved:.1f} TFLOP/s; phases {phases}")
+    nsteps = m if cfg["method"] == "chebyshev" else m + 1
+    persistent = g.window_bytes > 0
+    bf = precision == "bf16x3"
+    if persistent:
+        # one launch runs every recurrence step of every matrix
+        kernel = "batch_bf16x3_persistent_kernel" if bf else "batch_dense_persistent_kernel"
+        launch_ms, flop_launch = avg_step_ms * nsteps, flop * nsteps
+    else:
+        kernel = "batch_bf16x3_step_kernel" if bf else "batch_dense_step_kernel"
+        launch_ms, flop_launch = avg_step_ms, flop
+    log(f"{kernel}: {launch_ms:.3f} ms/launch, {avg_step_ms:.3f} ms per recurrence step -> "
+        f"{achieved:.1f} TFLOP/s; phases {phases}")
     cpu = None
     H_exact = [float(-np.sum(p[p > 0] * np.log(p[p > 0]))) for p in spectra]
     import oracle
@@ -259,7 +275,8 @@ def bench_batch(args, cfg):
                      "frac": achieved / peak,
                      "traffic": measured_traffic(kernel, args.workload + ("" if precision == "f32" else "_" + precision)),
                      "kernel": kernel,
-                     "avg_launch_ms": avg_step_ms, "algorithmic_flop_per_launch": flop},
+                     "avg_launch_ms": launch_ms, "algorithmic_flop_per_launch": flop_launch,
+                     "ms_per_recurrence_step": avg_step_ms, "launches_per_batch": 1 if persistent else nsteps},
         "cpu_baseline": cpu,
         "phases_ms": phases,
         "accuracy": {"sampled_matrices": len(idx),
@@ -611,6 +628,9 @@ def main():
     ap.add_argument("--csr-general", action="store_true",
                     help="CSR workloads: the general CSR step kernel even for banded R")
     ap.add_argument("--count", type=int, default=0, help="matrices in the learned4096 workload")
+    ap.add_argument("--batch-stepwise", action="store_true",
+                    help="batch workloads: one grouped launch per recurrence step instead of the "
+                         "persistent schedule")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the estimator "
