@@ -590,8 +590,12 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     if (hp > 0 && (double)(16 + 2 * hp) * sizeof(T) > csr_row && !forced) hp = 0;
   }
   const bool banded = hp > 0;
+  // rows of the V blocks (and of G): the tridiagonal kernel reads each row
+  // of up to 256 probes in one pass, so they are s values rounded up to 4;
+  // everything else, and the partial sums and sign words, use ldv
+  const int64_t ldb = (tri && s <= 256) ? round_up(s, 4) : ldv;
   const int32_t ntile = dense ? (int32_t)(n_pad / 64)
-                              : (tri ? ent::tri_step_blocks(n, sizeof(T) == 8)
+                              : (tri ? ent::tri_step_blocks(n, s, sizeof(T) == 8)
                                      : (banded ? ent::band_step_waves(n, hp, sizeof(T) == 8)
                                                : ent::csr_step_blocks(n, sizeof(T) == 8)));
   // dense steps whose tile grid is smaller than the chip split K
@@ -626,10 +630,10 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   }
   const int64_t ldc = round_up(n, vec_elems);
   if (need_copy) cv.add(&Rc, (size_t)n * ldc);
-  if (dense || !rad) cv.add(&G, (size_t)n_pad * ldv);
+  if (dense || !rad) cv.add(&G, (size_t)n_pad * ldb);
   if (!dense && rad) cv.add(&signs, (size_t)n_pad * (ldv / 32));
-  cv.add(&VA, (size_t)n_pad * ldv);
-  cv.add(&VB, (size_t)n_pad * ldv);
+  cv.add(&VA, (size_t)n_pad * ldb);
+  cv.add(&VB, (size_t)n_pad * ldb);
   T *party = nullptr;
   if (ksplit > 1) cv.add(&party, (size_t)ksplit * n_pad * ldv);
   cv.add(&part, (size_t)nslot * npart * ldv);
@@ -684,7 +688,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     HIP_TRY(ent::launch_csr_chunk_window(R->row_ptr, R->col_idx, n, ch, cwin, st));
   // probes
   if (dense || !rad)
-    HIP_TRY(ent::launch_probe_gen<T>(G, nullptr, op.probe_rows > 0 ? op.probe_rows : n, n_pad, s, ldv,
+    HIP_TRY(ent::launch_probe_gen<T>(G, nullptr, op.probe_rows > 0 ? op.probe_rows : n, n_pad, s, ldb,
                                      seed, o.probe_dist, st));
   else
     HIP_TRY(ent::launch_sign_gen(signs, n, s, ldv, seed, st));
@@ -707,8 +711,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   if (clenshaw) {
     // y_{m+1} = y_{m+2} = 0; y_k = alpha_k g + 2X y_{k+1} - y_{k+2}, k = m..0,
     // each y_k written over y_{k+2} (same element, same thread)
-    HIP_TRY(ent::launch_zero(VA, sizeof(T) * (size_t)n_pad * ldv, st));
-    HIP_TRY(ent::launch_zero(VB, sizeof(T) * (size_t)n_pad * ldv, st));
+    HIP_TRY(ent::launch_zero(VA, sizeof(T) * (size_t)n_pad * ldb, st));
+    HIP_TRY(ent::launch_zero(VB, sizeof(T) * (size_t)n_pad * ldb, st));
     Vk = VA;
     Vkm1 = VB;
   }
@@ -737,7 +741,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         HIP_TRY(ent::launch_band_step<T>(a, hp, st));
       } else if (tri) {
         ent::TriStepArgs a{};
-        a.diag = trid; a.n = n; a.ldv = ldv; a.s = s;
+        a.diag = trid; a.n = n; a.ldv = ldv; a.ldb = ldb; a.s = s;
         a.Vk = Vk; a.Vkm1 = k == 0 ? nullptr : Vkm1; a.Vkp1 = Vout;
         a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
         a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
@@ -798,7 +802,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
       HIP_TRY(ent::launch_band_step<T>(a, hp, st));
     } else if (tri) {
       ent::TriStepArgs a{};
-      a.diag = trid; a.n = n; a.ldv = ldv; a.s = s;
+      a.diag = trid; a.n = n; a.ldv = ldv; a.ldb = ldb; a.s = s;
       a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr;
       a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
       a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;

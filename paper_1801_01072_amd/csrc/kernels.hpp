@@ -197,8 +197,9 @@ hipError_t launch_tri_pack(const int64_t *rp, const int32_t *ci, const T *val, i
 struct TriStepArgs {
   const void *diag;    // launch_tri_pack output, element type T
   int64_t n;
-  int64_t ldv;         // padded probe count (multiple of 64)
-  int32_t s;           // probes in use (<= ldv; 0: ldv): later columns are not touched
+  int64_t ldv;         // partial-sum and sign-word row stride: probes rounded up to 64
+  int64_t ldb;         // row stride of V_k, V_{k-1}, V_{k+1} and G: >= s, a multiple of 4, <= ldv
+  int32_t s;           // probes in use (<= ldb; 0: ldv): later columns are not touched
   const void *Vk;      // null: V_k is the sign block (first step)
   const void *Vkm1;    // null: V_{k-1} is the sign block (if cw != 0)
   void *Vkp1;          // null: no write (last Taylor step)
@@ -213,7 +214,7 @@ struct TriStepArgs {
   int32_t nblk;        // workgroups of the grid (partial stride), from tri_step_blocks
   const double *cg;    // device scalar: z += (*cg) g (Clenshaw's alpha_k term); null: none
 };
-int32_t tri_step_blocks(int64_t n, int32_t fp64);
+int32_t tri_step_blocks(int64_t n, int32_t s, int32_t fp64);
 template <typename T>
 hipError_t launch_tri_step(const TriStepArgs &a, hipStream_t st);
 

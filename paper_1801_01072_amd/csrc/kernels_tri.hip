@@ -5,16 +5,16 @@
 // the step streams V_k, V_{k-1}, the probes and three values per row once and
 // writes V_{k+1} once, with no index arrays and no gathers.
 //
-// Mapping: a wave runs four independent streams (lanes 16 q .. 16 q + 15),
+// Mapping: a wave runs 64 / LS independent streams of LS lanes (LS = 16, 32
+// or 64: the narrowest whose 4-probe pieces cover the probes in one pass),
 // each over its own contiguous range of rows; lane p of a stream owns probes
-// 4 p .. 4 p + 3 of the workgroup's 64-probe chunk, so each row access is one
-// contiguous 256-byte (FP32) or 512-byte (FP64) piece per stream.  A stream
+// 4 p .. 4 p + 3, and the V blocks are stored with rows of s values rounded
+// up to 4 (not to 64), so each row access is one contiguous run of the
+// probes in use and consecutive rows follow each other in memory.  A stream
 // keeps V_{r-1} and V_r in registers and loads two new rows per iteration, so
 // every V_k row is read once; latency is hidden by occupancy (loading the
 // next iteration's rows ahead, or four rows per iteration, measured no
-// faster: 30.1 and 31.2 ms against 29.0 ms per step at n = 10^8, s = 100,
-// which moves about 126 GB, near what a device copy reaches here with this
-// share of writes).  Per-probe dot partials stay in
+// faster).  Per-probe dot partials stay in
 // FP64 registers (fixed-order sums: rows in order within a stream, streams
 // and waves combined in a fixed order).  Rademacher probes are read as packed
 // sign bits, also where V_k or V_{k-1} is the probe block itself.
@@ -63,16 +63,25 @@ template hipError_t launch_tri_pack<double>(const int64_t *, const int32_t *, co
 template hipError_t launch_tri_pack<float>(const int64_t *, const int32_t *, const float *, int64_t, float *,
                                            hipStream_t);
 
+// Lanes per row stream for s probes: the narrowest of 16, 32, 64 whose
+// 4-probe pieces cover s in one pass (so a row is read as one contiguous run
+// of s values), 16 (64-probe chunks) beyond 256 probes.
+__host__ __device__ inline int tri_stream_lanes(int32_t s) { return s <= 64 ? 16 : (s <= 128 ? 32 : (s <= 256 ? 64 : 16)); }
+
 // VK_SIGNS: V_k is the sign block.  M1: no V_{k-1} term (0), V_{k-1} stored
 // (1) or the sign block (2).  GG: also accumulate g.g (first Chebyshev step).
-template <typename T, bool VK_SIGNS, int M1, bool GG>
+// LS: lanes per row stream (64 / LS streams per wave, 4 LS probes per pass).
+template <typename T, int LS, bool VK_SIGNS, int M1, bool GG>
 __global__ __launch_bounds__(64 * kTriWaves) void tri_step_kernel(TriStepArgs a) {
   typedef T v4 __attribute__((ext_vector_type(4)));
-  __shared__ double red[2][kTriWaves][64];
+  constexpr int NSW = 64 / LS;          // streams per wave
+  constexpr int SPB = NSW * kTriWaves;  // streams per workgroup
+  constexpr int PP = 4 * LS;            // probes per pass
+  __shared__ double red[2][kTriWaves][PP];
   const int tid = threadIdx.x, lane = tid & 63;
-  const int w = tid >> 6, q = lane >> 4, p = lane & 15;
-  const int64_t n = a.n, ldv = a.ldv;
-  const int32_t chunk0 = (int32_t)blockIdx.y * 64;
+  const int w = tid >> 6, q = lane / LS, p = lane % LS;
+  const int64_t n = a.n, ldb = a.ldb, ldv = a.ldv;
+  const int32_t chunk0 = (int32_t)blockIdx.y * PP;
   const int32_t s_use = a.s > 0 ? a.s : (int32_t)ldv;
   const int32_t col = chunk0 + 4 * p;
   // a lane whose probes all lie past the ones in use reads and writes nothing
@@ -94,8 +103,8 @@ __global__ __launch_bounds__(64 * kTriWaves) void tri_step_kernel(TriStepArgs a)
   const T tcg = use_cg ? (T)a.cg[0] : T(0);
 
   // this stream's rows [r_beg, r_end): equal shares, a multiple of kTriRows
-  const int64_t nstream = (int64_t)gridDim.x * kTriStreams;
-  const int64_t sid = (int64_t)blockIdx.x * kTriStreams + w * 4 + q;
+  const int64_t nstream = (int64_t)gridDim.x * SPB;
+  const int64_t sid = (int64_t)blockIdx.x * SPB + w * NSW + q;
   int64_t share = (n + nstream - 1) / nstream;
   share = (share + kTriRows - 1) / kTriRows * kTriRows;
   const int64_t r_beg = sid * share < n ? sid * share : n;
@@ -113,7 +122,7 @@ __global__ __launch_bounds__(64 * kTriWaves) void tri_step_kernel(TriStepArgs a)
   };
   auto v_row = [&](const T *V, int64_t r) -> v4 {
     v4 x = {T(0), T(0), T(0), T(0)};
-    if (pv && r >= 0 && r < n) x = *(const v4 *)(V + r * ldv + col);
+    if (pv && r >= 0 && r < n) x = *(const v4 *)(V + r * ldb + col);
     return x;
   };
   auto vk_row = [&](int64_t r) -> v4 { return VK_SIGNS ? signs_row(r) : v_row(Vk, r); };
@@ -142,7 +151,7 @@ __global__ __launch_bounds__(64 * kTriWaves) void tri_step_kernel(TriStepArgs a)
       ds[e] += (double)gv[e] * (double)(a.dot_y ? y : ze);
       if (GG) gs[e] += (double)gv[e] * (double)gv[e];
     }
-    if (Vkp1 && pv) *(v4 *)(Vkp1 + r * ldv + col) = z;
+    if (Vkp1 && pv) *(v4 *)(Vkp1 + r * ldb + col) = z;
   };
 
   if (r_beg < r_end) {
@@ -158,18 +167,17 @@ __global__ __launch_bounds__(64 * kTriWaves) void tri_step_kernel(TriStepArgs a)
       vc = n2;
     }
   }
-  // per probe: the four streams of the wave (lanes p, p + 16, p + 32, p + 48),
-  // then the waves of the workgroup, in a fixed order
+  // per probe: the streams of the wave (lanes p, p + LS, ...), then the
+  // waves of the workgroup, in a fixed order
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    ds[e] += __shfl_xor(ds[e], 16, 64);
-    ds[e] += __shfl_xor(ds[e], 32, 64);
-    if (GG) {
-      gs[e] += __shfl_xor(gs[e], 16, 64);
-      gs[e] += __shfl_xor(gs[e], 32, 64);
+#pragma unroll
+    for (int off = LS; off < 64; off <<= 1) {
+      ds[e] += __shfl_xor(ds[e], off, 64);
+      if (GG) gs[e] += __shfl_xor(gs[e], off, 64);
     }
   }
-  if (lane < 16) {
+  if (lane < LS) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       red[0][w][4 * p + e] = ds[e];
@@ -177,68 +185,88 @@ __global__ __launch_bounds__(64 * kTriWaves) void tri_step_kernel(TriStepArgs a)
     }
   }
   __syncthreads();
-  if (w == 0) {
+  for (int t = tid; t < PP; t += 64 * kTriWaves) {
     double t0 = 0.0, t1 = 0.0;
 #pragma unroll
     for (int k = 0; k < kTriWaves; ++k) {
-      t0 += red[0][k][lane];
-      t1 += red[1][k][lane];
+      t0 += red[0][k][t];
+      t1 += red[1][k][t];
     }
-    const int64_t bidx = (int64_t)blockIdx.x * ldv + chunk0 + lane;
-    a.part[(int64_t)a.slot * a.nblk * ldv + bidx] = t0;
-    if (GG) a.part[(int64_t)a.slot_gg * a.nblk * ldv + bidx] = t1;
+    if (chunk0 + t < ldv) {
+      const int64_t bidx = (int64_t)blockIdx.x * ldv + chunk0 + t;
+      a.part[(int64_t)a.slot * a.nblk * ldv + bidx] = t0;
+      if (GG) a.part[(int64_t)a.slot_gg * a.nblk * ldv + bidx] = t1;
+    }
   }
 }
 
-// Workgroups resident at once (CUs x per-CU occupancy of the widest
-// instance), fewer when the rows give each stream less than 64 rows.
-int32_t tri_step_blocks(int64_t n, int32_t fp64) {
+// Workgroups resident at once (CUs x per-CU occupancy of one instance),
+// fewer when the rows give each stream less than 64 rows.
+int32_t tri_step_blocks(int64_t n, int32_t s, int32_t fp64) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
   const hipError_t e =
-      fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)tri_step_kernel<double, false, 1, false>,
+      fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)tri_step_kernel<double, 32, false, 1, false>,
                                                           64 * kTriWaves, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)tri_step_kernel<float, false, 1, false>,
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)tri_step_kernel<float, 32, false, 1, false>,
                                                           64 * kTriWaves, 0);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   const int64_t cap = (int64_t)cus * per_cu;
-  const int64_t want = (n + 64 * kTriStreams - 1) / (64 * kTriStreams);
+  const int64_t spb = (64 / tri_stream_lanes(s)) * kTriWaves;
+  const int64_t want = (n + 64 * spb - 1) / (64 * spb);
   return (int32_t)(want < 1 ? 1 : (want < cap ? want : cap));
 }
 
-template <typename T, bool VK_SIGNS, int M1, bool GG>
+template <typename T, int LS, bool VK_SIGNS, int M1, bool GG>
 static void tri_step_launch(const TriStepArgs &a, hipStream_t st) {
-  dim3 grid((unsigned)a.nblk, (unsigned)(a.ldv / 64));
-  tri_step_kernel<T, VK_SIGNS, M1, GG><<<grid, 64 * kTriWaves, 0, st>>>(a);
+  const int32_t s_use = a.s > 0 ? a.s : (int32_t)a.ldv;
+  dim3 grid((unsigned)a.nblk, (unsigned)((s_use + 4 * LS - 1) / (4 * LS)));
+  tri_step_kernel<T, LS, VK_SIGNS, M1, GG><<<grid, 64 * kTriWaves, 0, st>>>(a);
+}
+
+template <typename T, int LS>
+static hipError_t tri_step_dispatch(const TriStepArgs &a, hipStream_t st) {
+  const bool vk_signs = a.Vk == nullptr;
+  const int m1 = a.cw == 0.0 ? 0 : (a.Vkm1 == nullptr ? 2 : 1);
+  const bool gg = a.slot_gg >= 0;
+  if (gg) {
+    if (m1 != 0) return hipErrorInvalidValue;  // g.g is taken on the first step only
+    if (vk_signs)
+      tri_step_launch<T, LS, true, 0, true>(a, st);
+    else
+      tri_step_launch<T, LS, false, 0, true>(a, st);
+  } else if (m1 == 0) {
+    if (vk_signs)
+      tri_step_launch<T, LS, true, 0, false>(a, st);
+    else
+      tri_step_launch<T, LS, false, 0, false>(a, st);
+  } else {
+    if (vk_signs) return hipErrorInvalidValue;  // V_k is stored from the second step on
+    if (m1 == 2)
+      tri_step_launch<T, LS, false, 2, false>(a, st);
+    else
+      tri_step_launch<T, LS, false, 1, false>(a, st);
+  }
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_tri_step(const TriStepArgs &a, hipStream_t st) {
   const bool vk_signs = a.Vk == nullptr;
   const int m1 = a.cw == 0.0 ? 0 : (a.Vkm1 == nullptr ? 2 : 1);
-  const bool gg = a.slot_gg >= 0;
   if ((vk_signs || m1 == 2) && !a.signs) return hipErrorInvalidValue;
-  if (a.nblk < 1 || a.ldv % 64 != 0) return hipErrorInvalidValue;
-  if (gg) {
-    if (m1 != 0) return hipErrorInvalidValue;  // g.g is taken on the first step only
-    if (vk_signs)
-      tri_step_launch<T, true, 0, true>(a, st);
-    else
-      tri_step_launch<T, false, 0, true>(a, st);
-  } else if (m1 == 0) {
-    if (vk_signs)
-      tri_step_launch<T, true, 0, false>(a, st);
-    else
-      tri_step_launch<T, false, 0, false>(a, st);
-  } else {
-    if (vk_signs) return hipErrorInvalidValue;  // V_k is stored from the second step on
-    if (m1 == 2)
-      tri_step_launch<T, false, 2, false>(a, st);
-    else
-      tri_step_launch<T, false, 1, false>(a, st);
+  const int32_t s_use = a.s > 0 ? a.s : (int32_t)a.ldv;
+  // V rows of ldb >= s values (a multiple of 4: 16- or 32-byte pieces stay
+  // aligned); partials and sign words in rows of ldv, a multiple of 64
+  if (a.nblk < 1 || a.ldv % 64 != 0 || a.ldb % 4 != 0 || a.ldb < s_use || a.ldv < s_use ||
+      a.ldb > a.ldv)
+    return hipErrorInvalidValue;
+  switch (tri_stream_lanes(s_use)) {
+    case 64: return tri_step_dispatch<T, 64>(a, st);
+    case 32: return tri_step_dispatch<T, 32>(a, st);
+    default: return tri_step_dispatch<T, 16>(a, st);
   }
-  return hipGetLastError();
 }
 template hipError_t launch_tri_step<double>(const TriStepArgs &, hipStream_t);
 template hipError_t launch_tri_step<float>(const TriStepArgs &, hipStream_t);

@@ -83,10 +83,12 @@ def test_tri_schedules_probes_precisions(orc, dtype, method, flags, dist):
                 assert np.max(np.abs(mom[:, j] - dref)) <= TOL64 * float(g @ g)
 
 
-@pytest.mark.parametrize("n,s", [(1, 1), (2, 3), (3, 64), (5, 65), (33, 100), (1000, 130), (4097, 50)])
+@pytest.mark.parametrize("n,s", [(1, 1), (2, 3), (3, 64), (5, 65), (33, 100), (1000, 130), (4097, 50), (999, 256), (1000, 300)])
 def test_tri_ragged(orc, n, s):
     # n of one, two or a few rows (streams with no rows, with one row, with
-    # an odd count); probe counts below, at and past one 64-probe chunk
+    # an odd count); probe counts for each stream width (16 lanes up to 64
+    # probes, 32 up to 128, 64 up to 256, then 64-probe passes over rows of
+    # 64-multiple length), at and past each width's edge
     csr = W.poisson_csr(n) if n > 1 else (np.array([0, 1], np.int64), np.array([0], np.int32), np.ones(1), 1)
     m, seed = 9, 7
     for dist in ("rademacher", "gaussian"):
