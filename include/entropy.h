@@ -128,10 +128,10 @@ enum {
   ENT_FLAG_CSR_GENERAL = 16,     /* CSR R: always the general CSR kernels.  By
                                     default an R whose entries all lie within
                                     one of the diagonal (tridiagonal, at most
-                                    3n entries) runs the tridiagonal step
-                                    kernel on a per-estimate copy of its three
-                                    diagonals (power method on the CSR
-                                    arrays), and one whose entries all lie
+                                    3n entries) runs the tridiagonal kernels
+                                    (steps and power method) on a
+                                    per-estimate copy of its three diagonals,
+                                    and one whose entries all lie
                                     within 16 of the diagonal the banded kernels
                                     (steps and power method) on a per-estimate
                                     copy of R in 16-row slabs of 16 + 2 hp

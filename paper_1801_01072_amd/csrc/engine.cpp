@@ -447,7 +447,8 @@ ent_status validate_options(const ent_options &o) {
 template <typename T>
 ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t t, int32_t q,
                          uint64_t seed, double *x0, double *x1, double *part3, double *norm,
-                         double *scal, hipStream_t st, const T *band = nullptr, int32_t hp = 0) {
+                         double *scal, hipStream_t st, const T *band = nullptr, int32_t hp = 0,
+                         const T *trid = nullptr) {
   const int64_t n = R->n;
   for (int32_t trial = 0; trial < q; ++trial) {
     HIP_TRY(ent::launch_power_start(x0, n, seed, trial, st));
@@ -461,6 +462,10 @@ ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t 
         // banded CSR: the same product on the slabs of the step kernel
         nblk = ent::power_blocks_csr(n);
         HIP_TRY(ent::launch_power_band<T>(band, hp, n, xin, in_norm, xout, part3, nblk, st));
+      } else if (trid) {
+        // tridiagonal CSR: the same product on the packed diagonals
+        nblk = ent::power_blocks_csr(n);
+        HIP_TRY(ent::launch_power_tri<T>(trid, n, xin, in_norm, xout, part3, nblk, st));
       } else
         HIP_TRY(ent::launch_power_spmv<T>(R->row_ptr, R->col_idx, (const T *)R->values, n, R->nnz,
                                           xin, in_norm, xout, part3, &nblk, st));
@@ -695,7 +700,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   // power method and interval
   if (use_power) {
     pe.power_begin = pe.mark();
-    rc = enqueue_power<T>(R, Rt, ldr, o.power_iters, o.power_trials, seed, x0, x1, p0, p1, scal, st, band, hp);
+    rc = enqueue_power<T>(R, Rt, ldr, o.power_iters, o.power_trials, seed, x0, x1, p0, p1, scal, st, band, hp,
+                          trid);
     if (rc != ENT_OK) return rc;
     pe.power_end = pe.mark();
     pe.power_launches = o.power_trials * (o.power_iters + 1);

@@ -215,6 +215,11 @@ struct TriStepArgs {
   const double *cg;    // device scalar: z += (*cg) g (Clenshaw's alpha_k term); null: none
 };
 int32_t tri_step_blocks(int64_t n, int32_t s, int32_t fp64);
+// Power-method product on the packed diagonals: the contract of
+// launch_power_spmv, with nblk workgroups (nblk triples written).
+template <typename T>
+hipError_t launch_power_tri(const T *D, int64_t n, const double *x, const double *in_norm, double *y,
+                            double *part3, int32_t nblk, hipStream_t st);
 template <typename T>
 hipError_t launch_tri_step(const TriStepArgs &a, hipStream_t st);
 

@@ -63,6 +63,42 @@ template hipError_t launch_tri_pack<double>(const int64_t *, const int32_t *, co
 template hipError_t launch_tri_pack<float>(const int64_t *, const int32_t *, const float *, int64_t, float *,
                                            hipStream_t);
 
+// Power-method product on the packed diagonals: the contract of
+// launch_power_spmv (y = (R x) / ||x_prev||, one partial triple per block),
+// one row per thread, grid-stride over the rows.
+template <typename T>
+__global__ __launch_bounds__(256) void power_tri_kernel(const T *__restrict__ D, int64_t n, const double *__restrict__ x,
+                                                        const double *__restrict__ in_norm, double *__restrict__ y,
+                                                        double *__restrict__ part3) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  const double sc = in_norm ? 1.0 / sqrt(in_norm[0]) : 1.0;
+  double yy = 0.0, xy = 0.0, xx = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const v4 d = *(const v4 *)(D + 4 * r);
+    const double xr = x[r];
+    const double xl = r > 0 ? x[r - 1] : 0.0;
+    const double xu = r + 1 < n ? x[r + 1] : 0.0;
+    const double yv = sc * (((double)d[0] * xl + (double)d[1] * xr) + (double)d[2] * xu);
+    const double xs = sc * xr;
+    y[r] = yv;
+    yy += yv * yv;
+    xy += xs * yv;
+    xx += xs * xs;
+  }
+  block_power_partials(yy, xy, xx, part3, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_power_tri(const T *D, int64_t n, const double *x, const double *in_norm, double *y,
+                            double *part3, int32_t nblk, hipStream_t st) {
+  power_tri_kernel<T><<<(unsigned)nblk, 256, 0, st>>>(D, n, x, in_norm, y, part3);
+  return hipGetLastError();
+}
+template hipError_t launch_power_tri<double>(const double *, int64_t, const double *, const double *, double *,
+                                             double *, int32_t, hipStream_t);
+template hipError_t launch_power_tri<float>(const float *, int64_t, const double *, const double *, double *,
+                                            double *, int32_t, hipStream_t);
+
 // Lanes per row stream for s probes: the narrowest of 16, 32, 64 whose
 // 4-probe pieces cover s in one pass (so a row is read as one contiguous run
 // of s values), 16 (64-probe chunks) beyond 256 probes.
