@@ -72,6 +72,7 @@ KERNEL_SOURCES = {
     "batch_bf16x3_step_kernel": "kernels_bf16.hip",
     "batch_bf16x3_persistent_kernel": "kernels_bf16.hip",
     "dense_step_kernel": "kernels_dense.hip",
+    "dense_step_split_kernel": "kernels_dense.hip",
     "batch_dense_step_kernel": "kernels_dense.hip",
     "batch_dense_persistent_kernel": "kernels_dense.hip",
     "csr_step_kernel": "kernels_csr.hip",
@@ -424,6 +425,9 @@ def bench_learned(args, cfg):
         tms.append(ent.last_timing())
     ent.timing_enable(False)
     avg_step_ms = float(np.mean([x["steps_ms"] / x["step_launches"] for x in tms]))
+    split = int(tms[-1]["epilogue_launches"]) > 0
+    avg_epi_ms = float(np.mean([x["epilogue_ms"] / max(x["epilogue_launches"], 1) for x in tms]))
+    step_kernel = "dense_step_split_kernel" if split else "dense_step_kernel"
     flop = 2.0 * n * n * s
     achieved = flop / (avg_step_ms * 1e-3) / 1e12
     peak = MFMA_PEAK_TFLOPS[precision]
@@ -463,8 +467,9 @@ def bench_learned(args, cfg):
                                f"s={s} {cfg['dist']} probes, fallback Chebyshev m={m} on [0,u]",
                    "count": count, "n": n, "precision": precision, "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": "dense_step_kernel",
-                     "avg_launch_ms": avg_step_ms, "algorithmic_flop_per_launch": flop},
+                     "frac": achieved / peak, "traffic": None, "kernel": step_kernel,
+                     "avg_launch_ms": avg_step_ms, "algorithmic_flop_per_launch": flop,
+                     "epilogue_avg_launch_ms": avg_epi_ms if split else None},
         "cpu_baseline": cpu,
         "learned_vs_plain": {
             "plain_estimates_per_s": count * 1e3 / ms_plain,
@@ -755,7 +760,11 @@ def bench_single(args, cfg):
     avg_step_ms, avg_epi_ms, phases, last_t = kernel_timing(ent, Rd, cfg, pseed, kw, max(3, min(args.steps, 10)))
     launches = last_t["step_launches"]
     if dense:
-        kernel = "bf16x3_gemm_kernel" if precision == "bf16x3" else "dense_step_kernel"
+        # FP32/FP64: the split-K form runs when the tile grid is small (its
+        # product kernel, with the split reduction in a separate epilogue)
+        split = precision != "bf16x3" and int(last_t["epilogue_launches"]) > 0
+        kernel = ("bf16x3_gemm_kernel" if precision == "bf16x3" else
+                  ("dense_step_split_kernel" if split else "dense_step_kernel"))
         # a complex n x n by n x s product is 8 n^2 s real flops (the real 2n x 2n form)
         flop = (8.0 if herm else 2.0) * n * n * s
         achieved = flop / (avg_step_ms * 1e-3) / 1e12
@@ -765,6 +774,7 @@ def bench_single(args, cfg):
                 "kernel": kernel, "avg_launch_ms": avg_step_ms, "algorithmic_flop_per_launch": flop}
         if precision == "bf16x3":
             roof["executed_tflops"] = 3 * achieved
+        if precision == "bf16x3" or split:
             roof["epilogue_avg_launch_ms"] = avg_epi_ms
         log(f"{kernel}: {avg_step_ms:.4f} ms/launch over {launches} launches -> {achieved:.2f} TFLOP/s")
     else:
@@ -800,7 +810,8 @@ def bench_single(args, cfg):
         ms_p, _ = time_estimates(ent, Rd, cfg, pseed, kwp, args.steps, args.warmup)
         st_ms, epi_ms, ph, _ = kernel_timing(ent, Rd, cfg, pseed, kwp, 3)
         r_p, per_p, _ = ent.entropy_estimate_detail(Rd, cfg["method"], m, s, pseed, **kwp)
-        k_p = "bf16x3_gemm_kernel" if prec == "bf16x3" else "dense_step_kernel"
+        k_p = ("bf16x3_gemm_kernel" if prec == "bf16x3" else
+               ("dense_step_split_kernel" if epi_ms > 0 else "dense_step_kernel"))
         flop = (8.0 if herm else 2.0) * n * n * s
         ach = flop / (st_ms * 1e-3) / 1e12
         forms[prec] = {"value": 1e3 / ms_p, "unit": "estimates/s", "ms_per_step": ms_p,
@@ -810,7 +821,7 @@ def bench_single(args, cfg):
                        "kernel": k_p, "avg_launch_ms": st_ms, "achieved_tflops": ach,
                        "frac": ach / MFMA_PEAK_TFLOPS[prec],
                        "traffic": measured_traffic(k_p, args.workload + ("" if prec == "bf16x3" else "_" + prec)),
-                       "epilogue_avg_launch_ms": epi_ms if prec == "bf16x3" else None,
+                       "epilogue_avg_launch_ms": epi_ms if epi_ms > 0 else None,
                        "phases_ms": ph, "_per_probe": per_p}
         log(f"{prec}: {ms_p:.3f} ms/estimate ({1e3 / ms_p:.2f} est/s, {ms_per_step / ms_p:.2f}x the "
             f"{precision} path); {k_p} {st_ms:.4f} ms/launch -> {ach:.1f} TFLOP/s")

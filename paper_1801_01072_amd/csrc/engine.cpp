@@ -559,7 +559,10 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   } else if (!stored_T) {
     return fail(ENT_EUNSUPPORTED, "CSR values must be stored in the compute precision");
   }
-  const int bn = dense ? (s <= 64 ? 64 : (s <= 128 ? 128 : 64)) : 64;
+  // dense probe tile: 128 wide when that adds no padding over 64 (at
+  // n = 8192, s = 256, with the K split its narrower grid brings in: 2.3%
+  // less time per estimate in FP64, 3.5% in FP32)
+  const int bn = dense ? (s <= 64 ? 64 : (round_up(s, 128) == round_up(s, 64) ? 128 : 64)) : 64;
   const int64_t ldv = round_up(s, dense ? bn : 64);
   const int64_t n_pad = round_up(n, 64);
 
@@ -723,6 +726,23 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     Vkm1 = VB;
   }
   pe.steps_begin = pe.mark();
+  // a K-split dense step is timed as its product kernel and its epilogue
+  int prev_mark = pe.steps_begin, split_mark = -1;
+  auto dense_step = [&](const ent::DenseStepArgs &a) -> hipError_t {
+    if (a.ksplit < 2 || !pe.on) return ent::launch_dense_step<T>(a, st);
+    const hipError_t e = ent::launch_dense_step<T>(a, st, false);
+    if (e != hipSuccess) return e;
+    split_mark = pe.mark();
+    return ent::launch_dense_split_epilogue<T>(a, st);
+  };
+  auto end_step = [&](int e) {
+    if (split_mark >= 0) {
+      pe.main_spans.push_back({prev_mark, split_mark});
+      pe.epi_spans.push_back({split_mark, e});
+      split_mark = -1;
+    }
+    prev_mark = e;
+  };
   for (int32_t k = 0; k < nsteps; ++k) {
     if (clenshaw) {
       const int32_t kk = m - k;  // index of the y computed by this launch
@@ -735,7 +755,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.ntile = ntile; a.bn = bn;
         a.cg = scal + ent::S_ALPHA + kk;
         a.ksplit = ksplit; a.kper = kper; a.party = party; a.nptile = npart;
-        HIP_TRY(ent::launch_dense_step<T>(a, st));
+        HIP_TRY(dense_step(a));
       } else if (banded) {
         ent::BandStepArgs a{};
         a.band = band; a.n = n; a.ldv = ldv;
@@ -769,6 +789,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
       Vk = Vout;
       const int e = pe.mark();
       if (k == nsteps - 1) pe.steps_end = e;
+      end_step(e);
       continue;
     }
     T *Vout = bufs[k & 1];
@@ -797,7 +818,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
       a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
       a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.ntile = ntile; a.bn = bn;
       a.ksplit = ksplit; a.kper = kper; a.party = party; a.nptile = npart;
-      HIP_TRY(ent::launch_dense_step<T>(a, st));
+      HIP_TRY(dense_step(a));
     } else if (banded) {
       ent::BandStepArgs a{};
       a.band = band; a.n = n; a.ldv = ldv;
@@ -831,6 +852,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     Vk = Vout;
     const int e = pe.mark();
     if (k == nsteps - 1) pe.steps_end = e;
+    end_step(e);
   }
   HIP_TRY(ent::launch_reduce_moments(part, nslot, npart, ldv, s, d, st));
   HIP_TRY(ent::launch_final(d, scal, clenshaw ? ent::FINAL_CLENSHAW : method, m, s, h, st));

@@ -173,8 +173,12 @@ hipError_t launch_realify(const Tin *Rc, int64_t ldr, int64_t n, Tout *M, int64_
                           hipStream_t st);
 
 // ---- recurrence steps --------------------------------------------------------
+// One dense step; with a K split (ksplit > 1) the product kernel and then,
+// unless epilogue is false, the split epilogue (launch_dense_split_epilogue).
 template <typename T>
-hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st);
+hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st, bool epilogue = true);
+template <typename T>
+hipError_t launch_dense_split_epilogue(const DenseStepArgs &a, hipStream_t st);
 // K-splits for a dense step whose tile grid (ntile x ldv/bn) has fewer than
 // 512 workgroups (two per CU): a power of two up to 16 while every split
 // keeps >= 256 columns.

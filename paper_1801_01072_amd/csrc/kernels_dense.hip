@@ -506,7 +506,16 @@ int32_t batch_persistent_grid(int32_t precision, int32_t wr, int64_t ldv) {
 }
 
 template <typename T>
-hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st) {
+hipError_t launch_dense_split_epilogue(const DenseStepArgs &a, hipStream_t st) {
+  if (a.ksplit < 2 || !a.party || a.nptile != a.ntile * 4) return hipErrorInvalidValue;
+  dense_split_epilogue_kernel<T><<<dim3((unsigned)a.nptile, (unsigned)(a.ldv / 64)), 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+template hipError_t launch_dense_split_epilogue<double>(const DenseStepArgs &, hipStream_t);
+template hipError_t launch_dense_split_epilogue<float>(const DenseStepArgs &, hipStream_t);
+
+template <typename T>
+hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st, bool epilogue) {
   const int ntn = (int)(a.ldv / a.bn);
   if (a.ksplit > 1 && (!a.party || a.kper % 32 != 0 || (int64_t)a.ksplit * a.kper < a.n ||
                        a.nptile != a.ntile * 4))
@@ -527,10 +536,10 @@ hipError_t launch_dense_step(const DenseStepArgs &a, hipStream_t st) {
       default: return hipErrorInvalidValue;
     }
   }
-  if (a.ksplit > 1) {
+  if (a.ksplit > 1 && epilogue) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dense_split_epilogue_kernel<T><<<dim3((unsigned)a.nptile, (unsigned)(a.ldv / 64)), 256, 0, st>>>(a);
+    return launch_dense_split_epilogue<T>(a, st);
   }
   return hipGetLastError();
 }
@@ -549,7 +558,7 @@ hipError_t launch_batch_dense_step(const BatchStepArgs &ba, int32_t ntiles, int3
 }
 template hipError_t launch_batch_dense_step<double>(const BatchStepArgs &, int32_t, int32_t, hipStream_t);
 template hipError_t launch_batch_dense_step<float>(const BatchStepArgs &, int32_t, int32_t, hipStream_t);
-template hipError_t launch_dense_step<double>(const DenseStepArgs &, hipStream_t);
-template hipError_t launch_dense_step<float>(const DenseStepArgs &, hipStream_t);
+template hipError_t launch_dense_step<double>(const DenseStepArgs &, hipStream_t, bool);
+template hipError_t launch_dense_step<float>(const DenseStepArgs &, hipStream_t, bool);
 
 }  // namespace ent
