@@ -77,6 +77,7 @@ KERNEL_SOURCES = {
     "batch_dense_persistent_kernel": "kernels_dense.hip",
     "csr_step_kernel": "kernels_csr.hip",
     "band_step_kernel": "kernels_band.hip",
+    "band_pair_kernel": "kernels_band.hip",
     "tri_step_kernel": "kernels_tri.hip",
 }
 
@@ -157,6 +158,25 @@ def tri_step_bytes(n, s, m, vbytes, method):
         writes = method == "chebyshev" or k < steps - 1
         tot += diag + signs + blk * (reads_vk + reads_vm1 + writes)
     return tot, steps
+
+
+def band_pair_bytes(n, hp, s, m, vbytes, method):
+    """Algorithmic HBM bytes of the two-step banded launches (steps k, k + 1
+    in one pass): the slabs and sign bits once per pass, V_k and V_{k-1}
+    read once, V_{k+1} and V_{k+2} written once.  Returns (bytes of the pair
+    launches, number of pair launches); an odd last step runs alone and is
+    not included."""
+    slabs = ((n + 15) // 16) * 16 * (16 + 2 * hp) * vbytes
+    signs = n * s / 8
+    blk = n * s * vbytes
+    steps = m if method == "chebyshev" else m + 1
+    tot, pairs = 0.0, 0
+    for k in range(0, steps - 1, 2):
+        reads = (k > 0) + (method == "chebyshev" and k > 1)
+        writes = 1 + (method == "chebyshev" or k + 1 < steps - 1)
+        tot += slabs + signs + blk * (reads + writes)
+        pairs += 1
+    return tot, pairs
 
 
 def band_step_bytes(n, hp, s, m, vbytes, method):
@@ -785,6 +805,10 @@ def bench_single(args, cfg):
             # tridiagonal input: the three-row stencil kernel
             kernel = "tri_step_kernel"
             tot_bytes, steps = tri_step_bytes(n, s, m, vb, cfg["method"])
+        elif hp > 0 and int(last_t["steps_fused"]) == 2:
+            # banded input, two steps per launch
+            kernel = "band_pair_kernel"
+            tot_bytes, steps = band_pair_bytes(n, hp, s, m, vb, cfg["method"])
         elif hp > 0:
             # banded input: the step ran on the 16-row slabs
             kernel = "band_step_kernel"

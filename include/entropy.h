@@ -390,6 +390,11 @@ typedef struct {
                             banded step kernel that ran, 1 for the
                             tridiagonal step kernel; 0: the general CSR
                             kernel or a dense path                            */
+  int32_t steps_fused;   /* recurrence steps per product launch: 2 for the
+                            banded FP32 two-step kernel (steps_ms and
+                            step_launches then cover its launches; the last
+                            step of an odd count runs alone, in other_ms),
+                            1 otherwise                                       */
 } ent_timing;
 
 ent_status ent_timing_enable(int32_t on);

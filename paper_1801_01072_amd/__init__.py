@@ -81,7 +81,8 @@ class EntTiming(ctypes.Structure):
                 ("steps_ms", ctypes.c_double), ("step_max_ms", ctypes.c_double),
                 ("epilogue_ms", ctypes.c_double), ("other_ms", ctypes.c_double),
                 ("step_launches", ctypes.c_int32), ("power_launches", ctypes.c_int32),
-                ("epilogue_launches", ctypes.c_int32), ("csr_band", ctypes.c_int32)]
+                ("epilogue_launches", ctypes.c_int32), ("csr_band", ctypes.c_int32),
+                ("steps_fused", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p

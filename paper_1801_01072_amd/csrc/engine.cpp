@@ -34,6 +34,7 @@ struct PhaseEvents {
   int32_t power_launches = 0;
   int32_t csr_band = 0;  // padded half-bandwidth of the banded CSR step (0: none)
   int32_t logical_steps = 0;  // > 0: the steps span holds this many steps in one launch
+  int32_t steps_fused = 1;    // recurrence steps per product launch
   // split steps (product kernel + separate epilogue kernel): event index
   // pairs of the product launches and of the epilogue launches
   std::vector<std::pair<int, int>> main_spans, epi_spans;
@@ -83,9 +84,17 @@ struct PhaseEvents {
     t.other_ms = t.total_ms - t.power_ms - t.steps_ms - t.epilogue_ms;
     t.power_launches = power_launches;
     t.csr_band = csr_band;
+    t.steps_fused = steps_fused;
     g_last_timing = t;
   }
 };
+
+// The banded two-step launch is on unless the environment variable
+// ENT_BAND_PAIRS is 0 (for timing comparisons).
+bool band_pairs_enabled() {
+  const char *e = std::getenv("ENT_BAND_PAIRS");
+  return !(e && e[0] == '0');
+}
 
 ent_status fail(ent_status st, const char *fmt, ...) {
   char buf[512];
@@ -622,6 +631,11 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   double *scal = nullptr, *x0 = nullptr, *x1 = nullptr, *p0 = nullptr, *p1 = nullptr;
   double *part = nullptr, *d = nullptr, *h = nullptr;
   T *Rc = nullptr, *G = nullptr, *VA = nullptr, *VB = nullptr, *band = nullptr, *trid = nullptr;
+  // banded FP32 R: two recurrence steps per launch (two more V blocks: a
+  // pair's outputs may not overwrite its inputs)
+  const int32_t nsteps_all = clenshaw ? m + 1 : (method == ENT_CHEBYSHEV) ? m : m + 1;
+  const bool band_pairs = banded && sizeof(T) == 4 && nsteps_all >= 2 && band_pairs_enabled();
+  T *VC = nullptr, *VD = nullptr;
   uint32_t *signs = nullptr;
   int2 *cwin = nullptr;
   const int32_t ch = ent::csr_chunk_rows(sizeof(T) == 8);
@@ -642,6 +656,10 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   if (!dense && rad) cv.add(&signs, (size_t)n_pad * (ldv / 32));
   cv.add(&VA, (size_t)n_pad * ldb);
   cv.add(&VB, (size_t)n_pad * ldb);
+  if (band_pairs) {
+    cv.add(&VC, (size_t)n_pad * ldb);
+    cv.add(&VD, (size_t)n_pad * ldb);
+  }
   T *party = nullptr;
   if (ksplit > 1) cv.add(&party, (size_t)ksplit * n_pad * ldv);
   cv.add(&part, (size_t)nslot * npart * ldv);
@@ -743,7 +761,85 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     }
     prev_mark = e;
   };
-  for (int32_t k = 0; k < nsteps; ++k) {
+  if (band_pairs) {
+    // steps k, k + 1 in one launch; the last step of an odd count alone
+    pe.steps_fused = 2;
+    T *pool[4] = {VA, VB, VC, VD};
+    auto free_buf = [&](const void *x, const void *y, const void *z) -> T * {
+      for (T *b : pool)
+        if (b != x && b != y && b != z) return b;
+      return nullptr;
+    };
+    auto params = [&](int32_t k, double *c1, double *c2, double *cw, int32_t *dot_y, int32_t *slot,
+                      int32_t *slot_gg, const double **cg, bool *write) {
+      *cg = nullptr;
+      *slot_gg = -1;
+      *write = true;
+      if (clenshaw) {
+        const int32_t kk = m - k;
+        *c1 = 2.0; *c2 = -2.0; *cw = k == 0 ? 0.0 : -1.0; *dot_y = 0; *slot = kk;
+        *slot_gg = k == 0 ? m + 1 : -1;
+        *cg = scal + ent::S_ALPHA + kk;
+      } else if (method == ENT_CHEBYSHEV) {
+        if (k == 0) {
+          *c1 = 1.0; *c2 = -1.0; *cw = 0.0; *slot_gg = 0;
+        } else {
+          *c1 = 2.0; *c2 = -2.0; *cw = -1.0;
+        }
+        *dot_y = 0;
+        *slot = k + 1;
+      } else {
+        *c1 = -1.0; *c2 = 1.0; *cw = 0.0; *dot_y = 1; *slot = k;
+        *write = k < nsteps - 1;
+      }
+    };
+    int32_t k = 0;
+    while (k < nsteps) {
+      double c1, c2, cw;
+      int32_t dot_y, slot, slot_gg;
+      const double *cg;
+      bool write;
+      params(k, &c1, &c2, &cw, &dot_y, &slot, &slot_gg, &cg, &write);
+      if (k + 1 < nsteps) {
+        ent::BandPairArgs pa{};
+        pa.band = band; pa.n = n; pa.ldv = ldv;
+        pa.Vk = Vk; pa.Vkm1 = cw != 0.0 ? Vkm1 : nullptr;
+        pa.signs = rad ? signs : nullptr; pa.G = rad ? nullptr : G;
+        pa.scal = scal; pa.part = part; pa.nwave = ntile;
+        pa.c1[0] = c1; pa.c2[0] = c2; pa.cw[0] = cw; pa.dot_y[0] = dot_y; pa.slot[0] = slot;
+        pa.slot_gg = slot_gg; pa.cg[0] = cg;
+        double c1b, c2b, cwb;
+        int32_t dyb, slotb, ggb;
+        const double *cgb;
+        bool writeb;
+        params(k + 1, &c1b, &c2b, &cwb, &dyb, &slotb, &ggb, &cgb, &writeb);
+        pa.c1[1] = c1b; pa.c2[1] = c2b; pa.cw[1] = cwb; pa.dot_y[1] = dyb; pa.slot[1] = slotb; pa.cg[1] = cgb;
+        T *outA = free_buf(Vk, Vkm1, nullptr);
+        T *outB = free_buf(Vk, Vkm1, outA);
+        pa.VoutA = outA;
+        pa.VoutB = writeb ? outB : nullptr;
+        const int e0 = pe.mark();
+        HIP_TRY(ent::launch_band_pair(pa, hp, st));
+        const int e1 = pe.mark();
+        if (pe.on) pe.main_spans.push_back({e0, e1});
+        Vkm1 = outA;
+        Vk = outB;
+        k += 2;
+      } else {
+        ent::BandStepArgs a{};
+        a.band = band; a.n = n; a.ldv = ldv;
+        a.Vk = Vk; a.Vkm1 = cw != 0.0 ? Vkm1 : nullptr;
+        a.Vkp1 = write ? free_buf(Vk, Vkm1, nullptr) : nullptr;
+        a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
+        a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
+        a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nwave = ntile; a.cg = cg;
+        HIP_TRY(ent::launch_band_step<T>(a, hp, st));
+        k += 1;
+      }
+    }
+    pe.steps_end = pe.mark();
+  }
+  for (int32_t k = band_pairs ? nsteps : 0; k < nsteps; ++k) {
     if (clenshaw) {
       const int32_t kk = m - k;  // index of the y computed by this launch
       T *Vout = (T *)Vkm1;

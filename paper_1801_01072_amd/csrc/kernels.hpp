@@ -258,6 +258,34 @@ struct BandStepArgs {
   const double *cg;    // device scalar: z += (*cg) g (Clenshaw's alpha_k term); null: none
 };
 int32_t band_step_waves(int64_t n, int32_t hp, int32_t fp64);
+// Two consecutive recurrence steps in one pass (FP32): step A reads V_k
+// (null: the sign block) and V_{k-1} (null with cw[0] != 0: the sign block)
+// and writes V_{k+1} to VoutA; step B reads V_{k+1} and V_k and writes V_{k+2}
+// to VoutB (null: no write).  Neither output may alias an input: a wave
+// recomputes step A on the block before and after its range (whose V_k and
+// V_{k-1} rows other waves read at the same time).  Per-step scalars as in
+// BandStepArgs, index 0 for step A and 1 for step B; slot_gg applies to
+// step A.
+struct BandPairArgs {
+  const void *band;
+  int64_t n;
+  int64_t ldv;
+  const void *Vk;
+  const void *Vkm1;
+  void *VoutA;
+  void *VoutB;
+  const uint32_t *signs;
+  const void *G;
+  const double *scal;
+  double c1[2], c2[2], cw[2];
+  int32_t dot_y[2];
+  int32_t slot[2];
+  int32_t slot_gg;
+  const double *cg[2];
+  double *part;        // partials [slot][wave][ldv]
+  int32_t nwave;       // waves of the grid (partial stride), from band_step_waves
+};
+hipError_t launch_band_pair(const BandPairArgs &a, int32_t hp, hipStream_t st);
 // Power-method product on the slabs: the contract of launch_power_spmv, with
 // nblk workgroups (nblk triples written; power_blocks_csr(n) of them).
 template <typename T>

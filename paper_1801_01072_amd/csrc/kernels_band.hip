@@ -42,6 +42,7 @@ struct BandShape {
 };
 
 constexpr int kBandWaves = 4;  // waves per workgroup (independent)
+constexpr int kBandPairProbes = 2;  // probes per lane of the two-step kernel (32-probe chunks)
 
 // KS of the instance serving padded half-bandwidth hp
 inline int ks_of(int32_t hp) { return (hp + 8) / 2; }
@@ -487,6 +488,340 @@ __global__ __launch_bounds__(64 * kBandWaves) void band_step_kernel(BandStepArgs
       a.part[(int64_t)a.slot * a.nwave * ldv + bidx + t] = ds[t];
       if (gg) a.part[(int64_t)a.slot_gg * a.nwave * ldv + bidx + t] = gs[t];
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per pass (FP32).  A wave walks step A over the blocks of its range
+// plus one block on each side (V_{k+1} of a neighbouring block is needed by
+// step B at the range's edges; those two are computed but neither stored nor
+// counted), and step B one block behind: after step A of block b, the V_{k+1}
+// fragments of blocks b-2 .. b are in a second register window and step B
+// of block b-1 multiplies the slab of b-1 (kept from step A) with them.
+// Step B's V_k term is V_{k+1} of its block (step A's result, kept), its
+// V_{k-1} term is V_k of its block (step A's window rows, kept), and its
+// probe rows are step A's.  So a pair reads each slab, V_k, V_{k-1} and probe
+// row once and writes V_{k+1} and V_{k+2}: 4 V row passes per two steps
+// instead of 6.  Step A's result rows go from the MFMA result order to the
+// B-operand fragment order by the same transpose own_rows does (its own
+// inverse).
+// ---------------------------------------------------------------------------
+template <int NP>
+__device__ __forceinline__ void pair_load(const float *__restrict__ V, int64_t row, int64_t ldv, int32_t col0, float *x) {
+  typedef float vN __attribute__((ext_vector_type(NP)));
+  const vN v = *(const vN *)(V + row * ldv + col0);
+#pragma unroll
+  for (int t = 0; t < NP; ++t) x[t] = v[t];
+}
+template <int NP>
+__device__ __forceinline__ void pair_signs(const uint32_t *__restrict__ signs, int64_t row, int32_t nw, int32_t col0,
+                                           float *x) {
+  const uint32_t wd = signs[row * nw + (col0 >> 5)] >> (col0 & 31);
+#pragma unroll
+  for (int t = 0; t < NP; ++t) x[t] = ((wd >> t) & 1u) ? -1.f : 1.f;
+}
+template <int NP>
+__device__ __forceinline__ void pair_store(float *V, int64_t row, int64_t ldv, int32_t col0, const float *z) {
+  typedef float vN __attribute__((ext_vector_type(NP)));
+  vN v;
+#pragma unroll
+  for (int t = 0; t < NP; ++t) v[t] = z[t];
+  *(vN *)(V + row * ldv + col0) = v;
+}
+// V_k (or the sign block) at `row`, zero outside [0, n).
+template <int NP>
+__device__ __forceinline__ void pair_vk(const float *__restrict__ Vk, const uint32_t *__restrict__ signs, bool from_signs,
+                                        int64_t row, int64_t n, int64_t ldv, int32_t nw, int32_t col0, float *x) {
+  const bool in = row >= 0 && row < n;
+  const int64_t rr = in ? row : 0;
+  if (from_signs)
+    pair_signs<NP>(signs, rr, nw, col0, x);
+  else
+    pair_load<NP>(Vk, rr, ldv, col0, x);
+#pragma unroll
+  for (int t = 0; t < NP; ++t) x[t] = in ? x[t] : 0.f;
+}
+// The block's own rows in the MFMA result order from four fragments (and
+// back: the transpose is its own inverse), NP probes per lane.
+template <int NP>
+__device__ __forceinline__ void pair_own(const float *f0, const float *f1, const float *f2, const float *f3,
+                                         float (*x)[NP]) {
+#pragma unroll
+  for (int t = 0; t < NP; ++t) {
+    uint32_t m0 = __float_as_uint(f0[t]), m1 = __float_as_uint(f1[t]);
+    uint32_t m2 = __float_as_uint(f2[t]), m3 = __float_as_uint(f3[t]);
+    const auto a02 = __builtin_amdgcn_permlane32_swap(m0, m2, false, false);
+    const auto a13 = __builtin_amdgcn_permlane32_swap(m1, m3, false, false);
+    m0 = a02[0];
+    m2 = a02[1];
+    m1 = a13[0];
+    m3 = a13[1];
+    const auto b01 = __builtin_amdgcn_permlane16_swap(m0, m1, false, false);
+    const auto b23 = __builtin_amdgcn_permlane16_swap(m2, m3, false, false);
+    x[0][t] = __uint_as_float(b01[0]);
+    x[1][t] = __uint_as_float(b01[1]);
+    x[2][t] = __uint_as_float(b23[0]);
+    x[3][t] = __uint_as_float(b23[1]);
+  }
+}
+
+// NP: probes per lane (4: 64-probe chunks; 2: 32-probe chunks, half the
+// per-lane state, the slabs read once per chunk).
+template <int KS, int NP, bool VK_SIGNS, int M1A, bool GG>
+__global__ __launch_bounds__(64 * kBandWaves) void band_pair_kernel(BandPairArgs a) {
+  typedef float T;
+  typedef Mfma16<T> M;
+  typedef typename M::v4 v4;
+  constexpr int HP = BandShape<KS>::HP, WF = BandShape<KS>::WF;
+  constexpr int W2 = 4 - HP / 4;  // first fragment of step B's window in the 12-fragment ring
+  const int lane = threadIdx.x & 63;
+  const int q = lane >> 4, c = lane & 15;
+  const int64_t wv = (int64_t)blockIdx.x * kBandWaves + (threadIdx.x >> 6);
+  const int64_t nwv = (int64_t)gridDim.x * kBandWaves;
+  const int64_t n = a.n, ldv = a.ldv;
+  const int32_t nw = (int32_t)(ldv >> 5);
+  const int32_t chunk0 = (int32_t)blockIdx.y * (16 * NP);
+  const int32_t col0 = chunk0 + NP * c;
+  const int64_t nb = (n + 15) >> 4;
+  const int64_t per = (nb + nwv - 1) / nwv;
+  const int64_t b_beg = wv * per < nb ? wv * per : nb;
+  const int64_t b_end = b_beg + per < nb ? b_beg + per : nb;
+  const T *__restrict__ band = (const T *)a.band;
+  const T *__restrict__ Vk = (const T *)a.Vk;
+  const T *__restrict__ Vkm1 = (const T *)a.Vkm1;
+  const T *__restrict__ G = (const T *)a.G;
+  const uint32_t *__restrict__ signs = a.signs;
+  T *__restrict__ VoutA = (T *)a.VoutA;
+  T *__restrict__ VoutB = (T *)a.VoutB;
+  const bool g_signs = signs != nullptr && G == nullptr;
+  const T ta = (T)a.scal[S_A];
+  const T tbA = (T)(a.c2[0] * a.scal[S_B]), tbB = (T)(a.c2[1] * a.scal[S_B]);
+  const T c1A = (T)a.c1[0], c1B = (T)a.c1[1], cwA = (T)a.cw[0], cwB = (T)a.cw[1];
+  const T cgA = a.cg[0] ? (T)a.cg[0][0] : T(0), cgB = a.cg[1] ? (T)a.cg[1][0] : T(0);
+  const bool dyA = a.dot_y[0] != 0, dyB = a.dot_y[1] != 0;
+
+  double dA[NP], dB[NP], gs[NP];
+#pragma unroll
+  for (int t = 0; t < NP; ++t) dA[t] = dB[t] = gs[t] = 0.0;
+  if (b_beg < b_end) {
+    const int64_t a_beg = b_beg - 1, a_end = b_end + 1;  // step A blocks [a_beg, a_end)
+    T win[WF][NP];   // V_k fragments of step A's current block
+    T an[KS];       // slab of the next step-A block
+    T w2[12][NP];    // V_{k+1} fragments of blocks b-2, b-1, b after step A of block b
+    T acp[KS];      // slab of the previous block (step B's)
+    T zp[4][NP], xp[4][NP], gp[4][NP];  // previous block: V_{k+1}, V_k, probe rows (result order)
+#pragma unroll
+    for (int j = 0; j < 12; ++j)
+#pragma unroll
+      for (int t = 0; t < NP; ++t) w2[j][t] = T(0);
+    {
+      const int64_t f0 = 4 * a_beg - HP / 4;
+#pragma unroll
+      for (int j = 0; j < KS; ++j)
+        pair_vk<NP>(Vk, signs, VK_SIGNS, 4 * (f0 + j) + q, n, ldv, nw, col0, win[j]);
+      if (a_beg >= 0)
+        load_slab<T, KS>(band, a_beg, lane, an);
+      else {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) an[k] = T(0);
+      }
+    }
+    for (int64_t b = a_beg; b < a_end; ++b) {
+      T ac[KS];
+#pragma unroll
+      for (int k = 0; k < KS; ++k) ac[k] = an[k];
+      if (b + 1 < a_end) {
+        const int64_t fn = 4 * b - HP / 4 + KS;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          pair_vk<NP>(Vk, signs, VK_SIGNS, 4 * (fn + j) + q, n, ldv, nw, col0, win[KS + j]);
+        if (b + 1 < nb) {
+          load_slab<T, KS>(band, b + 1, lane, an);
+        } else {
+#pragma unroll
+          for (int k = 0; k < KS; ++k) an[k] = T(0);
+        }
+      }
+      // step A on block b
+      T xr[4][NP], vm[4][NP], gv[4][NP];
+      pair_own<NP>(win[HP / 4], win[HP / 4 + 1], win[HP / 4 + 2], win[HP / 4 + 3], xr);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = 16 * b + M::drow(q, r);
+        const bool in = row >= 0 && row < n;
+        const int64_t rr = in ? row : 0;
+        if (M1A == 1)
+          pair_load<NP>(Vkm1, rr, ldv, col0, vm[r]);
+        else if (M1A == 2)
+          pair_signs<NP>(signs, rr, nw, col0, vm[r]);
+        if (g_signs)
+          pair_signs<NP>(signs, rr, nw, col0, gv[r]);
+        else
+          pair_load<NP>(G, rr, ldv, col0, gv[r]);
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+          vm[r][t] = (M1A != 0 && in) ? vm[r][t] : T(0);
+          gv[r][t] = in ? gv[r][t] : T(0);
+        }
+      }
+      v4 acc[NP];
+#pragma unroll
+      for (int t = 0; t < NP; ++t) acc[t] = v4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+#pragma unroll
+        for (int t = 0; t < NP; ++t) acc[t] = M::mma(ac[k], win[k][t], acc[t]);
+      }
+#pragma unroll
+      for (int j = 0; j < KS; ++j) {
+#pragma unroll
+        for (int t = 0; t < NP; ++t) win[j][t] = win[j + 4][t];
+      }
+      const bool own = b >= b_beg && b < b_end;
+      T za[4][NP];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = 16 * b + M::drow(q, r);
+        const bool in = row >= 0 && row < n;
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+          const T y = ta * acc[t][r];
+          T z = c1A * y + tbA * xr[r][t];
+          if (M1A != 0) z += cwA * vm[r][t];
+          z += cgA * gv[r][t];
+          za[r][t] = in ? z : T(0);
+          if (own && in) {
+            dA[t] += (double)gv[r][t] * (double)(dyA ? y : z);
+            if (GG) gs[t] += (double)gv[r][t] * (double)gv[r][t];
+          }
+        }
+        if (own && in) pair_store<NP>(VoutA, row, ldv, col0, za[r]);
+      }
+      // V_{k+1} of block b into the step-B window (fragment order)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+#pragma unroll
+        for (int t = 0; t < NP; ++t) w2[j][t] = w2[j + 4][t];
+      }
+      {
+        T fr[4][NP];
+        pair_own<NP>(za[0], za[1], za[2], za[3], fr);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int t = 0; t < NP; ++t) w2[8 + j][t] = fr[j][t];
+      }
+      // step B on block b - 1
+      const int64_t cb = b - 1;
+      if (cb >= b_beg && cb < b_end) {
+        v4 bcc[NP];
+#pragma unroll
+        for (int t = 0; t < NP; ++t) bcc[t] = v4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+#pragma unroll
+          for (int t = 0; t < NP; ++t) bcc[t] = M::mma(acp[k], w2[W2 + k][t], bcc[t]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = 16 * cb + M::drow(q, r);
+          const bool in = row < n;
+          T z4[NP];
+#pragma unroll
+          for (int t = 0; t < NP; ++t) {
+            const T y = ta * bcc[t][r];
+            T z = c1B * y + tbB * zp[r][t];
+            z += cwB * xp[r][t];
+            z += cgB * gp[r][t];
+            z4[t] = z;
+            if (in) dB[t] += (double)gp[r][t] * (double)(dyB ? y : z);
+          }
+          if (in && VoutB) pair_store<NP>(VoutB, row, ldv, col0, z4);
+        }
+      }
+      // this block's values for step B at the next block
+#pragma unroll
+      for (int k = 0; k < KS; ++k) acp[k] = ac[k];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int t = 0; t < NP; ++t) {
+          zp[r][t] = za[r][t];
+          xp[r][t] = xr[r][t];
+          gp[r][t] = gv[r][t];
+        }
+    }
+  }
+  // per probe: the four row groups (lanes c, c+16, c+32, c+48), fixed order
+#pragma unroll
+  for (int t = 0; t < NP; ++t) {
+    dA[t] += __shfl_xor(dA[t], 16, 64);
+    dA[t] += __shfl_xor(dA[t], 32, 64);
+    dB[t] += __shfl_xor(dB[t], 16, 64);
+    dB[t] += __shfl_xor(dB[t], 32, 64);
+    if (GG) {
+      gs[t] += __shfl_xor(gs[t], 16, 64);
+      gs[t] += __shfl_xor(gs[t], 32, 64);
+    }
+  }
+  if (q == 0) {
+    const int64_t bidx = wv * ldv + col0;
+#pragma unroll
+    for (int t = 0; t < NP; ++t) {
+      a.part[(int64_t)a.slot[0] * a.nwave * ldv + bidx + t] = dA[t];
+      a.part[(int64_t)a.slot[1] * a.nwave * ldv + bidx + t] = dB[t];
+      if (GG) a.part[(int64_t)a.slot_gg * a.nwave * ldv + bidx + t] = gs[t];
+    }
+  }
+}
+
+template <int KS, bool VK_SIGNS, int M1A, bool GG>
+static void band_pair_launch(const BandPairArgs &a, hipStream_t st) {
+  constexpr int NP = kBandPairProbes;
+  dim3 grid((unsigned)(a.nwave / kBandWaves), (unsigned)(a.ldv / (16 * NP)));
+  band_pair_kernel<KS, NP, VK_SIGNS, M1A, GG><<<grid, 64 * kBandWaves, 0, st>>>(a);
+}
+
+template <int KS>
+static hipError_t band_pair_dispatch(const BandPairArgs &a, hipStream_t st) {
+  const bool vk_signs = a.Vk == nullptr;
+  const int m1 = a.cw[0] == 0.0 ? 0 : (a.Vkm1 == nullptr ? 2 : 1);
+  const bool gg = a.slot_gg >= 0;
+  if (gg) {
+    if (m1 != 0) return hipErrorInvalidValue;  // g.g is taken on the first step only
+    if (vk_signs)
+      band_pair_launch<KS, true, 0, true>(a, st);
+    else
+      band_pair_launch<KS, false, 0, true>(a, st);
+  } else if (m1 == 0) {
+    if (vk_signs)
+      band_pair_launch<KS, true, 0, false>(a, st);
+    else
+      band_pair_launch<KS, false, 0, false>(a, st);
+  } else {
+    if (vk_signs) return hipErrorInvalidValue;  // V_k is stored from the second step on
+    if (m1 == 2)
+      band_pair_launch<KS, false, 2, false>(a, st);
+    else
+      band_pair_launch<KS, false, 1, false>(a, st);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_band_pair(const BandPairArgs &a, int32_t hp, hipStream_t st) {
+  if (a.nwave <= 0 || a.nwave % kBandWaves != 0 || a.ldv % 64 != 0 || !a.VoutA) return hipErrorInvalidValue;
+  if ((a.Vk == nullptr || (a.cw[0] != 0.0 && a.Vkm1 == nullptr)) && !a.signs) return hipErrorInvalidValue;
+  if (a.G == nullptr && a.signs == nullptr) return hipErrorInvalidValue;
+  // outputs must not alias the inputs (other waves read the input rows next
+  // to their ranges during the launch)
+  const void *outs[2] = {a.VoutA, a.VoutB};
+  for (const void *o : outs)
+    if (o && (o == a.Vk || o == a.Vkm1 || o == a.G)) return hipErrorInvalidValue;
+  switch (hp) {
+    case 4: return band_pair_dispatch<6>(a, st);
+    case 8: return band_pair_dispatch<8>(a, st);
+    case 16: return band_pair_dispatch<12>(a, st);
+    default: return hipErrorInvalidValue;
   }
 }
 

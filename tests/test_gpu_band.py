@@ -215,3 +215,35 @@ def test_band_fp32_schedules_and_probes(orc, method, flags, dist):
           f"rel {rel:.2e} per-probe rel {err:.2e}", flush=True)
     assert band == 16
     assert err <= TOL32 and rel <= TOL32
+
+
+@pytest.mark.parametrize("n,s,m", [(1, 1, 3), (5, 3, 4), (16, 64, 5), (17, 65, 6), (1000, 50, 7), (4111, 130, 8)])
+def test_band_two_step_launches(orc, monkeypatch, n, s, m):
+    """FP32 banded R runs two recurrence steps per launch (the last step of
+    an odd count alone): per-probe values against the FP64 oracle and against
+    one launch per step (ENT_BAND_PAIRS=0), for every schedule, with sizes
+    below, at and past one 16-row block and one 64-probe chunk, and odd and
+    even step counts."""
+    csr = W.banded_density_csr(n, 4, seed=n + 5, dtype=np.float32)
+    seed = 3
+    for method, flags in (("chebyshev", 0), ("taylor", 0), ("chebyshev", ent.FLAG_CLENSHAW)):
+        for dist in ("rademacher", "gaussian"):
+            kw = dict(precision="f32", probe_dist=dist, flags=flags | ent.FLAG_CSR_BANDED)
+            ent.timing_enable(True)
+            try:
+                res, per, mom = ent.entropy_estimate_detail(csr_to_dev(csr), method, m, s, seed, **kw)
+                t = ent.last_timing()
+                monkeypatch.setenv("ENT_BAND_PAIRS", "0")
+                res1, per1, mom1 = ent.entropy_estimate_detail(csr_to_dev(csr), method, m, s, seed, **kw)
+                t1 = ent.last_timing()
+                monkeypatch.delenv("ENT_BAND_PAIRS")
+            finally:
+                ent.timing_enable(False)
+            ref = orc.estimate(csr, 0 if method == "taylor" else 1, m, s, seed, dist=0 if dist == "rademacher" else 1)
+            e2, e1 = per_probe_rel(per, ref), per_probe_rel(per1, ref)
+            print(f"[band pairs n={n} s={s} m={m} {method} flags={flags} {dist}] fused {t['steps_fused']} "
+                  f"launches {t['step_launches']}; per-probe rel {e2:.2e} (one step per launch {e1:.2e})",
+                  flush=True)
+            assert t["csr_band"] == (4 if n <= 5 else 8) and t["steps_fused"] == 2 and t1["steps_fused"] == 1
+            assert e2 <= TOL32 and e1 <= TOL32
+            assert np.max(np.abs(mom - mom1)) <= TOL32 * max(1.0, float(np.max(np.abs(mom1))))
