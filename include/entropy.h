@@ -393,8 +393,9 @@ typedef struct {
   int32_t steps_fused;   /* recurrence steps per product launch: 2 for the
                             banded FP32 two-step kernel (steps_ms and
                             step_launches then cover its launches; the last
-                            step of an odd count runs alone, in other_ms),
-                            1 otherwise                                       */
+                            step of an odd count runs alone, in other_ms;
+                            environment variable ENT_BAND_PAIRS=0 runs one
+                            step per launch), 1 otherwise                     */
 } ent_timing;
 
 ent_status ent_timing_enable(int32_t on);
