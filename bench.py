@@ -79,6 +79,7 @@ KERNEL_SOURCES = {
     "band_step_kernel": "kernels_band.hip",
     "band_pair_kernel": "kernels_band.hip",
     "tri_step_kernel": "kernels_tri.hip",
+    "tri_pair_kernel": "kernels_tri.hip",
 }
 
 
@@ -158,6 +159,24 @@ def tri_step_bytes(n, s, m, vbytes, method):
         writes = method == "chebyshev" or k < steps - 1
         tot += diag + signs + blk * (reads_vk + reads_vm1 + writes)
     return tot, steps
+
+
+def tri_pair_bytes(n, s, m, vbytes, method):
+    """Algorithmic HBM bytes of the two-step tridiagonal launches: the
+    diagonals and sign bits once per pass, V_k and V_{k-1} read once, V_{k+1}
+    and V_{k+2} written once (odd last step excluded, as for the banded
+    pairs)."""
+    diag = 4 * vbytes * n
+    signs = n * s / 8
+    blk = n * s * vbytes
+    steps = m if method == "chebyshev" else m + 1
+    tot, pairs = 0.0, 0
+    for k in range(0, steps - 1, 2):
+        reads = (k > 0) + (method == "chebyshev" and k > 1)
+        writes = 1 + (method == "chebyshev" or k + 1 < steps - 1)
+        tot += diag + signs + blk * (reads + writes)
+        pairs += 1
+    return tot, pairs
 
 
 def band_pair_bytes(n, hp, s, m, vbytes, method):
@@ -801,7 +820,11 @@ def bench_single(args, cfg):
         nnz = int(Rd[0][-1]) if host_R is None else int(host_R[0][-1])
         vb = 8 if precision == "f64" else 4
         hp = int(last_t["csr_band"])
-        if hp == 1:
+        if hp == 1 and int(last_t["steps_fused"]) == 2:
+            # tridiagonal input, two steps per launch
+            kernel = "tri_pair_kernel"
+            tot_bytes, steps = tri_pair_bytes(n, s, m, vb, cfg["method"])
+        elif hp == 1:
             # tridiagonal input: the three-row stencil kernel
             kernel = "tri_step_kernel"
             tot_bytes, steps = tri_step_bytes(n, s, m, vb, cfg["method"])

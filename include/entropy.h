@@ -391,11 +391,12 @@ typedef struct {
                             tridiagonal step kernel; 0: the general CSR
                             kernel or a dense path                            */
   int32_t steps_fused;   /* recurrence steps per product launch: 2 for the
-                            banded FP32 two-step kernel (steps_ms and
-                            step_launches then cover its launches; the last
-                            step of an odd count runs alone, in other_ms;
-                            environment variable ENT_BAND_PAIRS=0 runs one
-                            step per launch), 1 otherwise                     */
+                            banded FP32 and the tridiagonal two-step
+                            kernels (steps_ms and step_launches then cover
+                            their launches; the last step of an odd count
+                            runs alone, in other_ms; environment variables
+                            ENT_BAND_PAIRS=0 / ENT_TRI_PAIRS=0 run one step
+                            per launch), 1 otherwise                          */
 } ent_timing;
 
 ent_status ent_timing_enable(int32_t on);

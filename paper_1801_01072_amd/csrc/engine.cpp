@@ -89,10 +89,11 @@ struct PhaseEvents {
   }
 };
 
-// The banded two-step launch is on unless the environment variable
-// ENT_BAND_PAIRS is 0 (for timing comparisons).
-bool band_pairs_enabled() {
-  const char *e = std::getenv("ENT_BAND_PAIRS");
+// The two-step launches (banded FP32, tridiagonal) are on unless the
+// environment variable named (ENT_BAND_PAIRS, ENT_TRI_PAIRS) is 0 (for
+// timing comparisons).
+bool step_pairs_enabled(const char *name) {
+  const char *e = std::getenv(name);
   return !(e && e[0] == '0');
 }
 
@@ -634,7 +635,9 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   // banded FP32 R: two recurrence steps per launch (two more V blocks: a
   // pair's outputs may not overwrite its inputs)
   const int32_t nsteps_all = clenshaw ? m + 1 : (method == ENT_CHEBYSHEV) ? m : m + 1;
-  const bool band_pairs = banded && sizeof(T) == 4 && nsteps_all >= 2 && band_pairs_enabled();
+  const bool band_pairs = banded && sizeof(T) == 4 && nsteps_all >= 2 && step_pairs_enabled("ENT_BAND_PAIRS");
+  // tridiagonal R: likewise (both precisions)
+  const bool tri_pairs = tri && nsteps_all >= 2 && step_pairs_enabled("ENT_TRI_PAIRS");
   T *VC = nullptr, *VD = nullptr;
   uint32_t *signs = nullptr;
   int2 *cwin = nullptr;
@@ -656,7 +659,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   if (!dense && rad) cv.add(&signs, (size_t)n_pad * (ldv / 32));
   cv.add(&VA, (size_t)n_pad * ldb);
   cv.add(&VB, (size_t)n_pad * ldb);
-  if (band_pairs) {
+  if (band_pairs || tri_pairs) {
     cv.add(&VC, (size_t)n_pad * ldb);
     cv.add(&VD, (size_t)n_pad * ldb);
   }
@@ -761,7 +764,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     }
     prev_mark = e;
   };
-  if (band_pairs) {
+  if (band_pairs || tri_pairs) {
     // steps k, k + 1 in one launch; the last step of an odd count alone
     pe.steps_fused = 2;
     T *pool[4] = {VA, VB, VC, VD};
@@ -819,12 +822,35 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         pa.VoutA = outA;
         pa.VoutB = writeb ? outB : nullptr;
         const int e0 = pe.mark();
-        HIP_TRY(ent::launch_band_pair(pa, hp, st));
+        if (tri_pairs) {
+          ent::TriPairArgs ta{};
+          ta.diag = trid; ta.n = n; ta.ldv = ldv; ta.ldb = ldb; ta.s = s;
+          ta.Vk = pa.Vk; ta.Vkm1 = pa.Vkm1; ta.VoutA = pa.VoutA; ta.VoutB = pa.VoutB;
+          ta.signs = pa.signs; ta.G = pa.G; ta.scal = scal; ta.part = part; ta.nblk = ntile;
+          for (int i = 0; i < 2; ++i) {
+            ta.c1[i] = pa.c1[i]; ta.c2[i] = pa.c2[i]; ta.cw[i] = pa.cw[i];
+            ta.dot_y[i] = pa.dot_y[i]; ta.slot[i] = pa.slot[i]; ta.cg[i] = pa.cg[i];
+          }
+          ta.slot_gg = pa.slot_gg;
+          HIP_TRY(ent::launch_tri_pair<T>(ta, st));
+        } else {
+          HIP_TRY(ent::launch_band_pair(pa, hp, st));
+        }
         const int e1 = pe.mark();
         if (pe.on) pe.main_spans.push_back({e0, e1});
         Vkm1 = outA;
         Vk = outB;
         k += 2;
+      } else if (tri_pairs) {
+        ent::TriStepArgs a{};
+        a.diag = trid; a.n = n; a.ldv = ldv; a.ldb = ldb; a.s = s;
+        a.Vk = Vk; a.Vkm1 = cw != 0.0 ? Vkm1 : nullptr;
+        a.Vkp1 = write ? free_buf(Vk, Vkm1, nullptr) : nullptr;
+        a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
+        a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
+        a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nblk = ntile; a.cg = cg;
+        HIP_TRY(ent::launch_tri_step<T>(a, st));
+        k += 1;
       } else {
         ent::BandStepArgs a{};
         a.band = band; a.n = n; a.ldv = ldv;
@@ -839,7 +865,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     }
     pe.steps_end = pe.mark();
   }
-  for (int32_t k = band_pairs ? nsteps : 0; k < nsteps; ++k) {
+  for (int32_t k = (band_pairs || tri_pairs) ? nsteps : 0; k < nsteps; ++k) {
     if (clenshaw) {
       const int32_t kk = m - k;  // index of the y computed by this launch
       T *Vout = (T *)Vkm1;
