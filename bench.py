@@ -79,7 +79,7 @@ KERNEL_SOURCES = {
     "band_step_kernel": "kernels_band.hip",
     "band_pair_kernel": "kernels_band.hip",
     "tri_step_kernel": "kernels_tri.hip",
-    "tri_pair_kernel": "kernels_tri.hip",
+    "tri_fused_kernel": "tri_fused_impl.hpp",
 }
 
 
@@ -161,22 +161,31 @@ def tri_step_bytes(n, s, m, vbytes, method):
     return tot, steps
 
 
-def tri_pair_bytes(n, s, m, vbytes, method):
-    """Algorithmic HBM bytes of the two-step tridiagonal launches: the
-    diagonals and sign bits once per pass, V_k and V_{k-1} read once, V_{k+1}
-    and V_{k+2} written once (odd last step excluded, as for the banded
-    pairs)."""
+def fuse_split(steps, nf):
+    """The engine's split of the recurrence steps into launches of at most nf
+    steps, as even as possible, longer launches first."""
+    nl = -(-steps // nf)
+    return [steps // nl + (1 if i < steps % nl else 0) for i in range(nl)]
+
+
+def tri_fused_bytes(n, s, m, vbytes, method, nf):
+    """Algorithmic HBM bytes of the multi-step tridiagonal launches (up to nf
+    steps per pass): the diagonals and sign bits once per pass, V_k and
+    V_{k-1} read once, the last two steps' blocks written once (a one-step
+    launch excluded).  Returns (bytes, launches)."""
     diag = 4 * vbytes * n
     signs = n * s / 8
     blk = n * s * vbytes
     steps = m if method == "chebyshev" else m + 1
-    tot, pairs = 0.0, 0
-    for k in range(0, steps - 1, 2):
-        reads = (k > 0) + (method == "chebyshev" and k > 1)
-        writes = 1 + (method == "chebyshev" or k + 1 < steps - 1)
-        tot += diag + signs + blk * (reads + writes)
-        pairs += 1
-    return tot, pairs
+    tot, launches, k = 0.0, 0, 0
+    for ln in fuse_split(steps, nf):
+        if ln >= 2:
+            reads = (k > 0) + (method == "chebyshev" and k > 1)
+            writes = 1 + (method == "chebyshev" or k + ln - 1 < steps - 1)
+            tot += diag + signs + blk * (reads + writes)
+            launches += 1
+        k += ln
+    return tot, launches
 
 
 def band_pair_bytes(n, hp, s, m, vbytes, method):
@@ -820,10 +829,10 @@ def bench_single(args, cfg):
         nnz = int(Rd[0][-1]) if host_R is None else int(host_R[0][-1])
         vb = 8 if precision == "f64" else 4
         hp = int(last_t["csr_band"])
-        if hp == 1 and int(last_t["steps_fused"]) == 2:
-            # tridiagonal input, two steps per launch
-            kernel = "tri_pair_kernel"
-            tot_bytes, steps = tri_pair_bytes(n, s, m, vb, cfg["method"])
+        if hp == 1 and int(last_t["steps_fused"]) >= 2:
+            # tridiagonal input, several steps per launch
+            kernel = "tri_fused_kernel"
+            tot_bytes, steps = tri_fused_bytes(n, s, m, vb, cfg["method"], int(last_t["steps_fused"]))
         elif hp == 1:
             # tridiagonal input: the three-row stencil kernel
             kernel = "tri_step_kernel"

@@ -391,12 +391,17 @@ typedef struct {
                             tridiagonal step kernel; 0: the general CSR
                             kernel or a dense path                            */
   int32_t steps_fused;   /* recurrence steps per product launch: 2 for the
-                            banded FP32 and the tridiagonal two-step
-                            kernels (steps_ms and step_launches then cover
-                            their launches; the last step of an odd count
-                            runs alone, in other_ms; environment variables
-                            ENT_BAND_PAIRS=0 / ENT_TRI_PAIRS=0 run one step
-                            per launch), 1 otherwise                          */
+                            banded FP32 two-step kernel (the last step of
+                            an odd count runs alone, in other_ms;
+                            ENT_BAND_PAIRS=0 runs one step per launch); for
+                            the tridiagonal kernel the steps of the first
+                            launch, the m steps split into launches of at
+                            most ENT_TRI_FUSE steps (1..10, default 10) as
+                            evenly as possible, longer first (a one-step
+                            launch in other_ms); steps_ms and step_launches
+                            then cover the multi-step launches; 1
+                            otherwise, also where the two more V blocks
+                            the multi-step launches need do not fit       */
 } ent_timing;
 
 ent_status ent_timing_enable(int32_t on);

@@ -89,12 +89,32 @@ struct PhaseEvents {
   }
 };
 
-// The two-step launches (banded FP32, tridiagonal) are on unless the
-// environment variable named (ENT_BAND_PAIRS, ENT_TRI_PAIRS) is 0 (for
-// timing comparisons).
+// The banded FP32 two-step launches are on unless the environment variable
+// named (ENT_BAND_PAIRS) is 0 (for timing comparisons).
 bool step_pairs_enabled(const char *name) {
   const char *e = std::getenv(name);
   return !(e && e[0] == '0');
+}
+
+// Recurrence steps per tridiagonal launch: ENT_TRI_FUSE (1 = one step per
+// launch, at most kTriMaxFuse), else the most.
+constexpr int32_t kTriFuseDefault = ent::kTriMaxFuse;
+int32_t tri_fuse_steps() {
+  const char *e = std::getenv("ENT_TRI_FUSE");
+  if (!e || !*e) return kTriFuseDefault;
+  const int v = std::atoi(e);
+  return v < 1 ? 1 : (v > ent::kTriMaxFuse ? ent::kTriMaxFuse : v);
+}
+
+// Split nsteps recurrence steps into launches of at most nf steps, as even
+// as possible, longer launches first (a launch of one step runs the
+// single-step kernel).
+std::vector<int32_t> fuse_split(int32_t nsteps, int32_t nf) {
+  std::vector<int32_t> sizes;
+  if (nsteps <= 0) return sizes;
+  const int32_t nl = (nsteps + nf - 1) / nf;
+  for (int32_t i = 0; i < nl; ++i) sizes.push_back(nsteps / nl + (i < nsteps % nl ? 1 : 0));
+  return sizes;
 }
 
 ent_status fail(ent_status st, const char *fmt, ...) {
@@ -635,40 +655,52 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   // banded FP32 R: two recurrence steps per launch (two more V blocks: a
   // pair's outputs may not overwrite its inputs)
   const int32_t nsteps_all = clenshaw ? m + 1 : (method == ENT_CHEBYSHEV) ? m : m + 1;
-  const bool band_pairs = banded && sizeof(T) == 4 && nsteps_all >= 2 && step_pairs_enabled("ENT_BAND_PAIRS");
-  // tridiagonal R: likewise (both precisions)
-  const bool tri_pairs = tri && nsteps_all >= 2 && step_pairs_enabled("ENT_TRI_PAIRS");
+  bool band_pairs = banded && sizeof(T) == 4 && nsteps_all >= 2 && step_pairs_enabled("ENT_BAND_PAIRS");
+  // tridiagonal R: up to kTriMaxFuse steps per launch (both precisions)
+  const int32_t tri_nf = tri ? tri_fuse_steps() : 1;
+  bool tri_pairs = tri && nsteps_all >= 2 && tri_nf >= 2;
   T *VC = nullptr, *VD = nullptr;
   uint32_t *signs = nullptr;
   int2 *cwin = nullptr;
   const int32_t ch = ent::csr_chunk_rows(sizeof(T) == 8);
-  Carve cv;
-  cv.add(&scal, kScalarDoubles);
-  if (!dense && !banded && !tri) cv.add(&cwin, (size_t)((n + ch - 1) / ch));
-  if (banded) cv.add(&band, ent::band_pack_elems(n, hp));
-  if (tri) cv.add(&trid, 4 * (size_t)n);
-  if (use_power) {
-    cv.add(&x0, n_pad);
-    cv.add(&x1, n_pad);
-    cv.add(&p0, 3 * (size_t)pblk);
-    cv.add(&p1, 4);
-  }
-  const int64_t ldc = round_up(n, vec_elems);
-  if (need_copy) cv.add(&Rc, (size_t)n * ldc);
-  if (dense || !rad) cv.add(&G, (size_t)n_pad * ldb);
-  if (!dense && rad) cv.add(&signs, (size_t)n_pad * (ldv / 32));
-  cv.add(&VA, (size_t)n_pad * ldb);
-  cv.add(&VB, (size_t)n_pad * ldb);
-  if (band_pairs || tri_pairs) {
-    cv.add(&VC, (size_t)n_pad * ldb);
-    cv.add(&VD, (size_t)n_pad * ldb);
-  }
   T *party = nullptr;
-  if (ksplit > 1) cv.add(&party, (size_t)ksplit * n_pad * ldv);
-  cv.add(&part, (size_t)nslot * npart * ldv);
-  cv.add(&d, (size_t)nslot * s);
-  cv.add(&h, (size_t)s);
+  const int64_t ldc = round_up(n, vec_elems);
+  auto plan = [&](Carve &cv) {
+    cv.add(&scal, kScalarDoubles);
+    if (!dense && !banded && !tri) cv.add(&cwin, (size_t)((n + ch - 1) / ch));
+    if (banded) cv.add(&band, ent::band_pack_elems(n, hp));
+    if (tri) cv.add(&trid, 4 * (size_t)n);
+    if (use_power) {
+      cv.add(&x0, n_pad);
+      cv.add(&x1, n_pad);
+      cv.add(&p0, 3 * (size_t)pblk);
+      cv.add(&p1, 4);
+    }
+    if (need_copy) cv.add(&Rc, (size_t)n * ldc);
+    if (dense || !rad) cv.add(&G, (size_t)n_pad * ldb);
+    if (!dense && rad) cv.add(&signs, (size_t)n_pad * (ldv / 32));
+    cv.add(&VA, (size_t)n_pad * ldb);
+    cv.add(&VB, (size_t)n_pad * ldb);
+    if (band_pairs || tri_pairs) {
+      cv.add(&VC, (size_t)n_pad * ldb);
+      cv.add(&VD, (size_t)n_pad * ldb);
+    }
+    if (ksplit > 1) cv.add(&party, (size_t)ksplit * n_pad * ldv);
+    cv.add(&part, (size_t)nslot * npart * ldv);
+    cv.add(&d, (size_t)nslot * s);
+    cv.add(&h, (size_t)s);
+  };
+  Carve cv;
+  plan(cv);
   ent_status rc = ws.ensure(cv.total());
+  if (rc == ENT_ENOMEM && (band_pairs || tri_pairs)) {
+    // the multi-step launches need two more V blocks: without room for
+    // them, one step per launch
+    band_pairs = tri_pairs = false;
+    cv = Carve();
+    plan(cv);
+    rc = ws.ensure(cv.total());
+  }
   if (rc != ENT_OK) return rc;
   cv.assign(ws.ptr());
 
@@ -765,8 +797,15 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     prev_mark = e;
   };
   if (band_pairs || tri_pairs) {
-    // steps k, k + 1 in one launch; the last step of an odd count alone
-    pe.steps_fused = 2;
+    // banded: steps k, k + 1 in one launch, the last step of an odd count
+    // alone; tridiagonal: launches of up to tri_nf steps
+    std::vector<int32_t> sizes;
+    if (tri_pairs) {
+      sizes = fuse_split(nsteps, tri_nf);
+    } else {
+      for (int32_t k = 0; k < nsteps; k += 2) sizes.push_back(k + 1 < nsteps ? 2 : 1);
+    }
+    pe.steps_fused = sizes[0];
     T *pool[4] = {VA, VB, VC, VD};
     auto free_buf = [&](const void *x, const void *y, const void *z) -> T * {
       for (T *b : pool)
@@ -797,50 +836,56 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
       }
     };
     int32_t k = 0;
-    while (k < nsteps) {
+    for (const int32_t len : sizes) {
       double c1, c2, cw;
       int32_t dot_y, slot, slot_gg;
       const double *cg;
       bool write;
       params(k, &c1, &c2, &cw, &dot_y, &slot, &slot_gg, &cg, &write);
-      if (k + 1 < nsteps) {
-        ent::BandPairArgs pa{};
-        pa.band = band; pa.n = n; pa.ldv = ldv;
-        pa.Vk = Vk; pa.Vkm1 = cw != 0.0 ? Vkm1 : nullptr;
-        pa.signs = rad ? signs : nullptr; pa.G = rad ? nullptr : G;
-        pa.scal = scal; pa.part = part; pa.nwave = ntile;
-        pa.c1[0] = c1; pa.c2[0] = c2; pa.cw[0] = cw; pa.dot_y[0] = dot_y; pa.slot[0] = slot;
-        pa.slot_gg = slot_gg; pa.cg[0] = cg;
-        double c1b, c2b, cwb;
-        int32_t dyb, slotb, ggb;
-        const double *cgb;
-        bool writeb;
-        params(k + 1, &c1b, &c2b, &cwb, &dyb, &slotb, &ggb, &cgb, &writeb);
-        pa.c1[1] = c1b; pa.c2[1] = c2b; pa.cw[1] = cwb; pa.dot_y[1] = dyb; pa.slot[1] = slotb; pa.cg[1] = cgb;
+      if (len >= 2) {
+        // per-step scalars of steps k .. k + len - 1
+        double c1s[ent::kTriMaxFuse], c2s[ent::kTriMaxFuse], cws[ent::kTriMaxFuse];
+        int32_t dys[ent::kTriMaxFuse], slots[ent::kTriMaxFuse];
+        const double *cgs[ent::kTriMaxFuse];
+        bool last_write = write;
+        for (int32_t j = 0; j < len; ++j) {
+          int32_t gg;
+          params(k + j, &c1s[j], &c2s[j], &cws[j], &dys[j], &slots[j], &gg, &cgs[j], &last_write);
+        }
         T *outA = free_buf(Vk, Vkm1, nullptr);
         T *outB = free_buf(Vk, Vkm1, outA);
-        pa.VoutA = outA;
-        pa.VoutB = writeb ? outB : nullptr;
         const int e0 = pe.mark();
         if (tri_pairs) {
-          ent::TriPairArgs ta{};
+          ent::TriFusedArgs ta{};
           ta.diag = trid; ta.n = n; ta.ldv = ldv; ta.ldb = ldb; ta.s = s;
-          ta.Vk = pa.Vk; ta.Vkm1 = pa.Vkm1; ta.VoutA = pa.VoutA; ta.VoutB = pa.VoutB;
-          ta.signs = pa.signs; ta.G = pa.G; ta.scal = scal; ta.part = part; ta.nblk = ntile;
-          for (int i = 0; i < 2; ++i) {
-            ta.c1[i] = pa.c1[i]; ta.c2[i] = pa.c2[i]; ta.cw[i] = pa.cw[i];
-            ta.dot_y[i] = pa.dot_y[i]; ta.slot[i] = pa.slot[i]; ta.cg[i] = pa.cg[i];
+          ta.Vk = Vk; ta.Vkm1 = cw != 0.0 ? Vkm1 : nullptr;
+          ta.VoutA = outA; ta.VoutB = last_write ? outB : nullptr;
+          ta.signs = rad ? signs : nullptr; ta.G = rad ? nullptr : G;
+          ta.scal = scal; ta.part = part; ta.nblk = ntile; ta.slot_gg = slot_gg;
+          for (int32_t j = 0; j < len; ++j) {
+            ta.c1[j] = c1s[j]; ta.c2[j] = c2s[j]; ta.cw[j] = cws[j];
+            ta.dot_y[j] = dys[j]; ta.slot[j] = slots[j]; ta.cg[j] = cgs[j];
           }
-          ta.slot_gg = pa.slot_gg;
-          HIP_TRY(ent::launch_tri_pair<T>(ta, st));
+          HIP_TRY(ent::launch_tri_fused<T>(ta, len, st));
         } else {
+          ent::BandPairArgs pa{};
+          pa.band = band; pa.n = n; pa.ldv = ldv;
+          pa.Vk = Vk; pa.Vkm1 = cw != 0.0 ? Vkm1 : nullptr;
+          pa.signs = rad ? signs : nullptr; pa.G = rad ? nullptr : G;
+          pa.scal = scal; pa.part = part; pa.nwave = ntile; pa.slot_gg = slot_gg;
+          for (int32_t j = 0; j < 2; ++j) {
+            pa.c1[j] = c1s[j]; pa.c2[j] = c2s[j]; pa.cw[j] = cws[j];
+            pa.dot_y[j] = dys[j]; pa.slot[j] = slots[j]; pa.cg[j] = cgs[j];
+          }
+          pa.VoutA = outA;
+          pa.VoutB = last_write ? outB : nullptr;
           HIP_TRY(ent::launch_band_pair(pa, hp, st));
         }
         const int e1 = pe.mark();
         if (pe.on) pe.main_spans.push_back({e0, e1});
         Vkm1 = outA;
         Vk = outB;
-        k += 2;
+        k += len;
       } else if (tri_pairs) {
         ent::TriStepArgs a{};
         a.diag = trid; a.n = n; a.ldv = ldv; a.ldb = ldb; a.s = s;

@@ -219,12 +219,14 @@ struct TriStepArgs {
   const double *cg;    // device scalar: z += (*cg) g (Clenshaw's alpha_k term); null: none
 };
 int32_t tri_step_blocks(int64_t n, int32_t s, int32_t fp64);
-// Two consecutive recurrence steps in one pass (the contract of
-// BandPairArgs: step A reads V_k (null: sign block) and V_{k-1} (null with
-// cw[0] != 0: sign block) and writes V_{k+1} to VoutA; step B writes V_{k+2}
-// to VoutB (null: no write); outputs may not alias inputs; row strides as in
-// TriStepArgs).
-struct TriPairArgs {
+// nf consecutive recurrence steps in one pass (2 <= nf <= kTriMaxFuse).
+// Step 0 reads V_k (null: sign block) and V_{k-1} (null with cw[0] != 0:
+// sign block); only the results of steps nf - 2 (VoutA) and nf - 1 (VoutB;
+// null: no write) are stored; the outputs may not alias the inputs; row
+// strides as in TriStepArgs; per-step scalars indexed by step, slot_gg for
+// step 0.
+constexpr int kTriMaxFuse = 10;
+struct TriFusedArgs {
   const void *diag;
   int64_t n, ldv, ldb;
   int32_t s;
@@ -235,16 +237,16 @@ struct TriPairArgs {
   const uint32_t *signs;
   const void *G;
   const double *scal;
-  double c1[2], c2[2], cw[2];
-  int32_t dot_y[2];
-  int32_t slot[2];
+  double c1[kTriMaxFuse], c2[kTriMaxFuse], cw[kTriMaxFuse];
+  int32_t dot_y[kTriMaxFuse];
+  int32_t slot[kTriMaxFuse];
   int32_t slot_gg;
-  const double *cg[2];
+  const double *cg[kTriMaxFuse];
   double *part;
   int32_t nblk;
 };
 template <typename T>
-hipError_t launch_tri_pair(const TriPairArgs &a, hipStream_t st);
+hipError_t launch_tri_fused(const TriFusedArgs &a, int32_t nf, hipStream_t st);
 // Power-method product on the packed diagonals: the contract of
 // launch_power_spmv, with nblk workgroups (nblk triples written).
 template <typename T>

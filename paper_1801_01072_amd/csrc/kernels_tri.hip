@@ -236,210 +236,6 @@ __global__ __launch_bounds__(64 * kTriWaves) void tri_step_kernel(TriStepArgs a)
   }
 }
 
-// Two steps per pass: a stream computes step A (V_{k+1}) on its rows plus
-// one row on each side, and step B (V_{k+2}) one row behind, from the last
-// three step-A rows held in registers; step B's V_{k-1} term is V_k of its
-// row, still in the V_k window.  A pair reads V_k, V_{k-1}, the probes and
-// the diagonals once and writes V_{k+1} and V_{k+2}: four V row passes per
-// two steps instead of six.
-template <typename T, int LS, bool VK_SIGNS, int M1A, bool GG>
-__global__ __launch_bounds__(64 * kTriWaves) void tri_pair_kernel(TriPairArgs a) {
-  typedef T v4 __attribute__((ext_vector_type(4)));
-  constexpr int NSW = 64 / LS;
-  constexpr int SPB = NSW * kTriWaves;
-  constexpr int PP = 4 * LS;
-  __shared__ double red[3][kTriWaves][PP];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int w = tid >> 6, q = lane / LS, p = lane % LS;
-  const int64_t n = a.n, ldb = a.ldb, ldv = a.ldv;
-  const int32_t chunk0 = (int32_t)blockIdx.y * PP;
-  const int32_t s_use = a.s > 0 ? a.s : (int32_t)ldv;
-  const int32_t col = chunk0 + 4 * p;
-  const bool pv = col < s_use;
-  const int64_t nw = ldv >> 5;
-  const int32_t wsel = col >> 5, bsh = col & 31;
-  const T *__restrict__ D = (const T *)a.diag;
-  const T *__restrict__ Vk = (const T *)a.Vk;
-  const T *__restrict__ Vkm1 = (const T *)a.Vkm1;
-  const T *__restrict__ G = (const T *)a.G;
-  const uint32_t *__restrict__ signs = a.signs;
-  T *__restrict__ VoutA = (T *)a.VoutA;
-  T *__restrict__ VoutB = (T *)a.VoutB;
-  const T ta = (T)a.scal[S_A];
-  const T tbA = (T)(a.c2[0] * a.scal[S_B]), tbB = (T)(a.c2[1] * a.scal[S_B]);
-  const T c1A = (T)a.c1[0], c1B = (T)a.c1[1], cwA = (T)a.cw[0], cwB = (T)a.cw[1];
-  const T cgA = a.cg[0] ? (T)a.cg[0][0] : T(0), cgB = a.cg[1] ? (T)a.cg[1][0] : T(0);
-  const bool dyA = a.dot_y[0] != 0, dyB = a.dot_y[1] != 0;
-
-  const int64_t nstream = (int64_t)gridDim.x * SPB;
-  const int64_t sid = (int64_t)blockIdx.x * SPB + w * NSW + q;
-  const int64_t share = (n + nstream - 1) / nstream;
-  const int64_t r_beg = sid * share < n ? sid * share : n;
-  const int64_t r_end = r_beg + share < n ? r_beg + share : n;
-
-  auto signs_row = [&](int64_t r) -> v4 {
-    v4 x = {T(0), T(0), T(0), T(0)};
-    if (pv && r >= 0 && r < n) {
-      const uint32_t bits = signs[r * nw + wsel] >> bsh;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) x[e] = ((bits >> e) & 1u) ? T(-1) : T(1);
-    }
-    return x;
-  };
-  auto v_row = [&](const T *V, int64_t r) -> v4 {
-    v4 x = {T(0), T(0), T(0), T(0)};
-    if (pv && r >= 0 && r < n) x = *(const v4 *)(V + r * ldb + col);
-    return x;
-  };
-  auto vk_row = [&](int64_t r) -> v4 { return VK_SIGNS ? signs_row(r) : v_row(Vk, r); };
-  auto vm_row = [&](int64_t r) -> v4 {
-    if (M1A == 2) return signs_row(r);
-    if (M1A == 1) return v_row(Vkm1, r);
-    return v4{T(0), T(0), T(0), T(0)};
-  };
-  auto g_row = [&](int64_t r) -> v4 { return signs ? signs_row(r) : v_row(G, r); };
-  auto d_row = [&](int64_t r) -> v4 {
-    v4 x = {T(0), T(0), T(0), T(0)};
-    if (r >= 0 && r < n) x = *(const v4 *)(D + 4 * r);
-    return x;
-  };
-
-  double dA[4] = {0.0, 0.0, 0.0, 0.0}, dB[4] = {0.0, 0.0, 0.0, 0.0}, gs[4] = {0.0, 0.0, 0.0, 0.0};
-  if (r_beg < r_end) {
-    v4 pk = vk_row(r_beg - 2), ck = vk_row(r_beg - 1);   // V_k[r-1], V_k[r]
-    v4 pa = {T(0), T(0), T(0), T(0)}, ca = pa;           // V_{k+1}[r-2], V_{k+1}[r-1]
-    v4 gq = pa, dq = pa;                                   // probe and diagonals of row r-1
-    for (int64_t r = r_beg - 1; r <= r_end; ++r) {
-      const v4 nk = vk_row(r + 1);
-      const v4 m = vm_row(r), g = g_row(r), d = d_row(r);
-      const bool in = r >= 0 && r < n;
-      const bool ownA = r >= r_beg && r < r_end;
-      v4 za;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const T y = ta * ((d[0] * pk[e] + d[1] * ck[e]) + d[2] * nk[e]);
-        T z = c1A * y + tbA * ck[e];
-        if (M1A != 0) z += cwA * m[e];
-        z += cgA * g[e];
-        za[e] = in ? z : T(0);
-        if (ownA) {
-          dA[e] += (double)g[e] * (double)(dyA ? y : z);
-          if (GG) gs[e] += (double)g[e] * (double)g[e];
-        }
-      }
-      if (ownA && pv) *(v4 *)(VoutA + r * ldb + col) = za;
-      // step B on row r - 1
-      const int64_t rb = r - 1;
-      if (rb >= r_beg && rb < r_end) {
-        v4 zb;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const T y = ta * ((dq[0] * pa[e] + dq[1] * ca[e]) + dq[2] * za[e]);
-          T z = c1B * y + tbB * ca[e];
-          z += cwB * pk[e];
-          z += cgB * gq[e];
-          zb[e] = z;
-          dB[e] += (double)gq[e] * (double)(dyB ? y : z);
-        }
-        if (VoutB && pv) *(v4 *)(VoutB + rb * ldb + col) = zb;
-      }
-      pa = ca;
-      ca = za;
-      pk = ck;
-      ck = nk;
-      gq = g;
-      dq = d;
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-#pragma unroll
-    for (int off = LS; off < 64; off <<= 1) {
-      dA[e] += __shfl_xor(dA[e], off, 64);
-      dB[e] += __shfl_xor(dB[e], off, 64);
-      if (GG) gs[e] += __shfl_xor(gs[e], off, 64);
-    }
-  }
-  if (lane < LS) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      red[0][w][4 * p + e] = dA[e];
-      red[1][w][4 * p + e] = dB[e];
-      red[2][w][4 * p + e] = GG ? gs[e] : 0.0;
-    }
-  }
-  __syncthreads();
-  for (int t = tid; t < PP; t += 64 * kTriWaves) {
-    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < kTriWaves; ++k) {
-      t0 += red[0][k][t];
-      t1 += red[1][k][t];
-      t2 += red[2][k][t];
-    }
-    if (chunk0 + t < ldv) {
-      const int64_t bidx = (int64_t)blockIdx.x * ldv + chunk0 + t;
-      a.part[(int64_t)a.slot[0] * a.nblk * ldv + bidx] = t0;
-      a.part[(int64_t)a.slot[1] * a.nblk * ldv + bidx] = t1;
-      if (GG) a.part[(int64_t)a.slot_gg * a.nblk * ldv + bidx] = t2;
-    }
-  }
-}
-
-template <typename T, int LS, bool VK_SIGNS, int M1A, bool GG>
-static void tri_pair_launch(const TriPairArgs &a, hipStream_t st) {
-  const int32_t s_use = a.s > 0 ? a.s : (int32_t)a.ldv;
-  dim3 grid((unsigned)a.nblk, (unsigned)((s_use + 4 * LS - 1) / (4 * LS)));
-  tri_pair_kernel<T, LS, VK_SIGNS, M1A, GG><<<grid, 64 * kTriWaves, 0, st>>>(a);
-}
-
-template <typename T, int LS>
-static hipError_t tri_pair_dispatch(const TriPairArgs &a, hipStream_t st) {
-  const bool vk_signs = a.Vk == nullptr;
-  const int m1 = a.cw[0] == 0.0 ? 0 : (a.Vkm1 == nullptr ? 2 : 1);
-  const bool gg = a.slot_gg >= 0;
-  if (gg) {
-    if (m1 != 0) return hipErrorInvalidValue;
-    if (vk_signs)
-      tri_pair_launch<T, LS, true, 0, true>(a, st);
-    else
-      tri_pair_launch<T, LS, false, 0, true>(a, st);
-  } else if (m1 == 0) {
-    if (vk_signs)
-      tri_pair_launch<T, LS, true, 0, false>(a, st);
-    else
-      tri_pair_launch<T, LS, false, 0, false>(a, st);
-  } else {
-    if (vk_signs) return hipErrorInvalidValue;
-    if (m1 == 2)
-      tri_pair_launch<T, LS, false, 2, false>(a, st);
-    else
-      tri_pair_launch<T, LS, false, 1, false>(a, st);
-  }
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_tri_pair(const TriPairArgs &a, hipStream_t st) {
-  const bool vk_signs = a.Vk == nullptr;
-  const int m1 = a.cw[0] == 0.0 ? 0 : (a.Vkm1 == nullptr ? 2 : 1);
-  if ((vk_signs || m1 == 2) && !a.signs) return hipErrorInvalidValue;
-  const int32_t s_use = a.s > 0 ? a.s : (int32_t)a.ldv;
-  if (a.nblk < 1 || a.ldv % 64 != 0 || a.ldb % 4 != 0 || a.ldb < s_use || a.ldv < s_use || a.ldb > a.ldv ||
-      !a.VoutA)
-    return hipErrorInvalidValue;
-  const void *outs[2] = {a.VoutA, a.VoutB};
-  for (const void *o : outs)
-    if (o && (o == a.Vk || o == a.Vkm1 || o == a.G)) return hipErrorInvalidValue;
-  switch (tri_stream_lanes(s_use)) {
-    case 64: return tri_pair_dispatch<T, 64>(a, st);
-    case 32: return tri_pair_dispatch<T, 32>(a, st);
-    default: return tri_pair_dispatch<T, 16>(a, st);
-  }
-}
-template hipError_t launch_tri_pair<double>(const TriPairArgs &, hipStream_t);
-template hipError_t launch_tri_pair<float>(const TriPairArgs &, hipStream_t);
-
 // Workgroups resident at once (CUs x per-CU occupancy of one instance),
 // fewer when the rows give each stream less than 64 rows.
 int32_t tri_step_blocks(int64_t n, int32_t s, int32_t fp64) {

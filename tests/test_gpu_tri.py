@@ -139,34 +139,47 @@ def test_tri_duplicates_missing_entries_and_general_agreement(orc):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("n,s,m", [(1, 1, 3), (2, 3, 4), (7, 64, 5), (33, 100, 6), (4097, 130, 7)])
-def test_tri_two_step_launches(orc, monkeypatch, dtype, n, s, m):
-    """A tridiagonal R runs two recurrence steps per launch (the last step of
-    an odd count alone): per-probe values against the FP64 oracle and
-    against one launch per step (ENT_TRI_PAIRS=0), for every schedule and
+@pytest.mark.parametrize("n,s,m", [(1, 1, 3), (2, 3, 4), (7, 64, 5), (33, 100, 6), (4097, 130, 7),
+                                   (1000, 100, 10)])
+def test_tri_fused_launches(orc, monkeypatch, dtype, n, s, m):
+    """A tridiagonal R runs several recurrence steps per launch
+    (ENT_TRI_FUSE = 1..10, the steps split as evenly as possible, a launch of
+    one step on the single-step kernel): per-probe values against the FP64
+    oracle and moments against one launch per step, for every schedule and
     probe kind, streams with no rows, one row and a few."""
     csr = W.poisson_csr(n, dtype) if n > 1 else (np.array([0, 1], np.int64), np.array([0], np.int32),
                                                  np.ones(1, dtype), 1)
     prec = "f64" if dtype == np.float64 else "f32"
     tol = TOL64 if dtype == np.float64 else TOL_F32
     seed = 5
+
+    def first_launch(nsteps, nf):
+        nl = -(-nsteps // nf)
+        return nsteps // nl + (1 if nsteps % nl else 0)
+
     for method, flags in (("chebyshev", 0), ("taylor", 0), ("chebyshev", ent.FLAG_CLENSHAW)):
+        nsteps = m if (method == "chebyshev" and not flags) else m + 1
+        ref = orc.estimate(csr, 0 if method == "taylor" else 1, m, s, seed, dist=0)
         for dist in ("rademacher", "gaussian"):
             kw = dict(precision=prec, probe_dist=dist, flags=flags)
+            if dist == "gaussian":
+                ref = orc.estimate(csr, 0 if method == "taylor" else 1, m, s, seed, dist=1)
+            out = {}
             ent.timing_enable(True)
             try:
-                res, per, mom = ent.entropy_estimate_detail(csr_to_dev(csr), method, m, s, seed, **kw)
-                t = ent.last_timing()
-                monkeypatch.setenv("ENT_TRI_PAIRS", "0")
-                res1, per1, mom1 = ent.entropy_estimate_detail(csr_to_dev(csr), method, m, s, seed, **kw)
-                t1 = ent.last_timing()
-                monkeypatch.delenv("ENT_TRI_PAIRS")
+                for nf in (1, 2, 3, 5, 10):
+                    monkeypatch.setenv("ENT_TRI_FUSE", str(nf))
+                    res, per, mom = ent.entropy_estimate_detail(csr_to_dev(csr), method, m, s, seed, **kw)
+                    out[nf] = (per, mom, ent.last_timing())
             finally:
+                monkeypatch.delenv("ENT_TRI_FUSE")
                 ent.timing_enable(False)
-            ref = orc.estimate(csr, 0 if method == "taylor" else 1, m, s, seed, dist=0 if dist == "rademacher" else 1)
-            e2, e1 = rel(per, ref), rel(per1, ref)
-            print(f"[tri pairs {prec} n={n} s={s} m={m} {method} flags={flags} {dist}] fused {t['steps_fused']} "
-                  f"launches {t['step_launches']}; per-probe rel {e2:.2e} (one step per launch {e1:.2e})", flush=True)
-            assert t["csr_band"] == 1 and t["steps_fused"] == 2 and t1["steps_fused"] == 1
-            assert e2 <= tol and e1 <= tol
-            assert np.max(np.abs(mom - mom1)) <= tol * max(1.0, float(np.max(np.abs(mom1))))
+            mom1 = out[1][1]
+            for nf, (per, mom, t) in out.items():
+                e = rel(per, ref)
+                print(f"[tri fused {prec} n={n} s={s} m={m} {method} flags={flags} {dist} nf={nf}] "
+                      f"fused {t['steps_fused']} launches {t['step_launches']}; per-probe rel {e:.2e}", flush=True)
+                want = 1 if nf == 1 else first_launch(nsteps, nf)
+                assert t["csr_band"] == 1 and t["steps_fused"] == want
+                assert e <= tol
+                assert np.max(np.abs(mom - mom1)) <= tol * max(1.0, float(np.max(np.abs(mom1))))
