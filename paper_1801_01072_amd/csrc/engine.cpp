@@ -478,14 +478,38 @@ template <typename T>
 ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t t, int32_t q,
                          uint64_t seed, double *x0, double *x1, double *part3, double *norm,
                          double *scal, hipStream_t st, const T *band = nullptr, int32_t hp = 0,
-                         const T *trid = nullptr) {
+                         const T *trid = nullptr, int32_t *launches = nullptr) {
   const int64_t n = R->n;
+  // tridiagonal R: after the first product, the products of a trial in
+  // launches of up to pf (ENT_TRI_POWER_FUSE, 1 = one per launch)
+  int32_t pf = 1;
+  if (trid) {
+    const char *e = std::getenv("ENT_TRI_POWER_FUSE");
+    pf = e && *e ? std::atoi(e) : ent::kPowerMaxFuse;
+    pf = pf < 1 ? 1 : (pf > ent::kPowerMaxFuse ? ent::kPowerMaxFuse : pf);
+  }
+  int32_t nl = 0;
   for (int32_t trial = 0; trial < q; ++trial) {
     HIP_TRY(ent::launch_power_start(x0, n, seed, trial, st));
     double *xin = x0, *xout = x1;
     const double *in_norm = nullptr;
-    for (int32_t it = 0; it <= t; ++it) {  // t iterations + the Rayleigh product
+    for (int32_t it = 0; it <= t;) {  // t iterations + the Rayleigh product
       int32_t nblk = 0;
+      const int32_t rem = t + 1 - it;
+      ++nl;
+      if (trid && it >= 1 && pf >= 2 && rem >= 2) {
+        // the remaining products split as evenly as possible, longer first
+        const int32_t nlaunch = (rem + pf - 1) / pf;
+        const int32_t k = rem / nlaunch + (rem % nlaunch ? 1 : 0);
+        nblk = ent::power_blocks_csr(n);
+        HIP_TRY(ent::launch_power_tri_fused<T>(trid, n, xin, in_norm, xout, part3, nblk, k, st));
+        HIP_TRY(ent::launch_power_reduce(part3, nblk, norm, st));
+        std::swap(xin, xout);
+        in_norm = norm;
+        it += k;
+        continue;
+      }
+      ++it;
       if (R->layout == ENT_DENSE) {
         HIP_TRY(ent::launch_power_gemv<T>(Rc, ldr, n, xin, in_norm, xout, part3, &nblk, st));
       } else if (band) {
@@ -505,6 +529,7 @@ ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t 
     }
     HIP_TRY(ent::launch_power_rq(scal, norm, trial, st));
   }
+  if (launches) *launches = nl;
   return ENT_OK;
 }
 
@@ -756,11 +781,12 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   // power method and interval
   if (use_power) {
     pe.power_begin = pe.mark();
+    int32_t pl = 0;
     rc = enqueue_power<T>(R, Rt, ldr, o.power_iters, o.power_trials, seed, x0, x1, p0, p1, scal, st, band, hp,
-                          trid);
+                          trid, &pl);
     if (rc != ENT_OK) return rc;
     pe.power_end = pe.mark();
-    pe.power_launches = o.power_trials * (o.power_iters + 1);
+    pe.power_launches = pl;
   }
   HIP_TRY(ent::launch_setup_interval(scal, method, m, o.u_factor, o.u_fixed, o.cutoff, st,
                                      normalize ? op.trace_div : 0.0));

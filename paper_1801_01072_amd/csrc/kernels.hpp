@@ -252,6 +252,16 @@ hipError_t launch_tri_fused(const TriFusedArgs &a, int32_t nf, hipStream_t st);
 template <typename T>
 hipError_t launch_power_tri(const T *D, int64_t n, const double *x, const double *in_norm, double *y,
                             double *part3, int32_t nblk, hipStream_t st);
+// k (2..kPowerMaxFuse) consecutive power-method products in one pass: the
+// first divides by sqrt(prev3[0]) (the previous product's ||y||^2), the
+// middle ones by the previous Rayleigh quotient prev3[1] / prev3[2], the last
+// by nothing; y = the last product (may not alias x); nblk triples as
+// launch_power_tri, over the last product and its input.  prev3 null: no
+// scaling.
+constexpr int kPowerMaxFuse = 10;
+template <typename T>
+hipError_t launch_power_tri_fused(const T *D, int64_t n, const double *x, const double *prev3, double *y,
+                                  double *part3, int32_t nblk, int32_t k, hipStream_t st);
 template <typename T>
 hipError_t launch_tri_step(const TriStepArgs &a, hipStream_t st);
 

@@ -99,6 +99,129 @@ template hipError_t launch_power_tri<double>(const double *, int64_t, const doub
 template hipError_t launch_power_tri<float>(const float *, int64_t, const double *, const double *, double *,
                                             double *, int32_t, hipStream_t);
 
+// K consecutive power-method products on the packed diagonals in one pass
+// (temporal blocking of the stencil on one vector).  A wave owns a
+// contiguous range of rows and slides a 64-row tile along it: at tile base b
+// product j covers rows b - j + lane, one row behind product j - 1, whose
+// rows b - j + lane - 1 and b - j + lane are its own values one and two
+// lanes down (wave-wide DPP shifts), the first lanes taking lanes 62 and 63
+// of its previous tile.  The first product divides by ||x|| (in_norm, as
+// launch_power_tri), the products after it by the previous launch's
+// Rayleigh quotient x.y / x.x (prev3, if positive: it keeps the values near
+// unit size without a norm per product), and the last one by nothing, so the
+// triple written (||y||^2, x.y, x.x over the last product and its input) is
+// the one launch_power_tri would give for it up to scale: the Rayleigh
+// quotient and the next normalization are unchanged.  Only the last
+// product is stored.
+namespace {
+__device__ __forceinline__ double dpp_shr1(double v, double lane0) {
+  // lane i takes v of lane i - 1; lane 0 takes lane0
+  const int2 a = *(const int2 *)&v, o = *(const int2 *)&lane0;
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(o.x, a.x, 0x138, 0xf, 0xf, false);
+  r.y = __builtin_amdgcn_update_dpp(o.y, a.y, 0x138, 0xf, 0xf, false);
+  return *(const double *)&r;
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const int2 a = *(const int2 *)&v;
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(a.x, l);
+  r.y = __builtin_amdgcn_readlane(a.y, l);
+  return *(const double *)&r;
+}
+}  // namespace
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void power_tri_fused_kernel(const T *__restrict__ D, int64_t n,
+                                                              const double *__restrict__ x,
+                                                              const double *__restrict__ prev3,
+                                                              double *__restrict__ y, double *__restrict__ part3) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nwave = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t wid = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
+  const int64_t share = (n + nwave - 1) / nwave;
+  const int64_t r_beg = wid * share < n ? wid * share : n;
+  const int64_t r_end = r_beg + share < n ? r_beg + share : n;
+  const double sc0 = prev3 ? 1.0 / sqrt(prev3[0]) : 1.0;
+  double rinv = 1.0;
+  if (prev3) {
+    const double rho = prev3[1] / prev3[2];
+    if (rho > 0.0 && isfinite(1.0 / rho)) rinv = 1.0 / rho;
+  }
+  double yy = 0.0, xy = 0.0, xx = 0.0;
+  if (r_beg < r_end) {
+    double cur[K], p62[K], p63[K];  // product j: this tile's value, lanes 62, 63 of the previous tile
+#pragma unroll
+    for (int j = 0; j < K; ++j) cur[j] = p62[j] = p63[j] = 0.0;
+    // loads clamped into [0, n), values outside zeroed: no branches in the loop
+    auto clampr = [&](int64_t r) -> int64_t { return r < 0 ? 0 : (r >= n ? n - 1 : r); };
+    auto x_at = [&](int64_t r) -> double {
+      const double v = x[clampr(r)];
+      return r >= 0 && r < n ? v : 0.0;
+    };
+    for (int64_t b = r_beg - (K - 1); b - (K - 1) < r_end; b += 64) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int64_t xr = b - j + lane;
+        double lo, mid, hi;
+        if (j == 0) {
+          lo = x_at(xr - 1);
+          mid = x_at(xr);
+          hi = x_at(xr + 1);
+        } else {
+          hi = cur[j - 1];
+          mid = dpp_shr1(cur[j - 1], p63[j - 1]);
+          lo = dpp_shr1(mid, p62[j - 1]);
+        }
+        const bool in = xr >= 0 && xr < n;
+        const v4 d = *(const v4 *)(D + 4 * clampr(xr));
+        double v = ((double)d[0] * lo + (double)d[1] * mid) + (double)d[2] * hi;
+        if (j == 0) v *= sc0;
+        if (j < K - 1) v *= rinv;
+        v = in ? v : 0.0;
+        cur[j] = v;
+        if (j == K - 1 && xr >= r_beg && xr < r_end) {
+          y[xr] = v;
+          yy += v * v;
+          xy += mid * v;
+          xx += mid * mid;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        p62[j] = read_lane(cur[j], 62);
+        p63[j] = read_lane(cur[j], 63);
+      }
+    }
+  }
+  block_power_partials(yy, xy, xx, part3, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_power_tri_fused(const T *D, int64_t n, const double *x, const double *prev3, double *y,
+                                  double *part3, int32_t nblk, int32_t k, hipStream_t st) {
+  if (n < 1 || nblk < 1 || !D || !x || !y || !part3 || y == x) return hipErrorInvalidValue;
+  switch (k) {
+    case 2: power_tri_fused_kernel<T, 2><<<(unsigned)nblk, 256, 0, st>>>(D, n, x, prev3, y, part3); break;
+    case 3: power_tri_fused_kernel<T, 3><<<(unsigned)nblk, 256, 0, st>>>(D, n, x, prev3, y, part3); break;
+    case 4: power_tri_fused_kernel<T, 4><<<(unsigned)nblk, 256, 0, st>>>(D, n, x, prev3, y, part3); break;
+    case 5: power_tri_fused_kernel<T, 5><<<(unsigned)nblk, 256, 0, st>>>(D, n, x, prev3, y, part3); break;
+    case 6: power_tri_fused_kernel<T, 6><<<(unsigned)nblk, 256, 0, st>>>(D, n, x, prev3, y, part3); break;
+    case 7: power_tri_fused_kernel<T, 7><<<(unsigned)nblk, 256, 0, st>>>(D, n, x, prev3, y, part3); break;
+    case 8: power_tri_fused_kernel<T, 8><<<(unsigned)nblk, 256, 0, st>>>(D, n, x, prev3, y, part3); break;
+    case 9: power_tri_fused_kernel<T, 9><<<(unsigned)nblk, 256, 0, st>>>(D, n, x, prev3, y, part3); break;
+    case 10: power_tri_fused_kernel<T, 10><<<(unsigned)nblk, 256, 0, st>>>(D, n, x, prev3, y, part3); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_power_tri_fused<double>(const double *, int64_t, const double *, const double *,
+                                                   double *, double *, int32_t, int32_t, hipStream_t);
+template hipError_t launch_power_tri_fused<float>(const float *, int64_t, const double *, const double *,
+                                                  double *, double *, int32_t, int32_t, hipStream_t);
+
 // Lanes per row stream for s probes: the narrowest of 16, 32, 64 whose
 // 4-probe pieces cover s in one pass (so a row is read as one contiguous run
 // of s values), 16 (64-probe chunks) beyond 256 probes.

@@ -183,3 +183,38 @@ def test_tri_fused_launches(orc, monkeypatch, dtype, n, s, m):
                 assert t["csr_band"] == 1 and t["steps_fused"] == want
                 assert e <= tol
                 assert np.max(np.abs(mom - mom1)) <= tol * max(1.0, float(np.max(np.abs(mom1))))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("n", [1, 2, 7, 63, 64, 65, 130, 4097])
+def test_tri_power_fused(orc, monkeypatch, dtype, n):
+    """After the first product, the power method's products on a tridiagonal
+    R run up to ten per launch (ENT_TRI_POWER_FUSE; the middle products
+    scaled by the previous Rayleigh quotient, not normalised): p~1 against
+    the oracle's power method and against one product per launch, for
+    iteration counts that split evenly and unevenly, one and two trials,
+    tiles that the rows fill, overrun and leave nearly empty."""
+    csr = random_tridiagonal(n, 11, dtype)
+    prec = "f64" if dtype == np.float64 else "f32"
+    seed = 3
+    for t, q in ((1, 1), (2, 1), (5, 2), (20, 1), (23, 2)):
+        kw = dict(precision=prec, power_iters=t, power_trials=q)
+        ref = orc.estimate(csr, 1, 4, 8, seed, t=t, q=q)
+        ent.timing_enable(True)
+        try:
+            res, _, _ = ent.entropy_estimate_detail(csr_to_dev(csr), "chebyshev", 4, 8, seed, **kw)
+            tl = ent.last_timing()
+            monkeypatch.setenv("ENT_TRI_POWER_FUSE", "1")
+            res1, _, _ = ent.entropy_estimate_detail(csr_to_dev(csr), "chebyshev", 4, 8, seed, **kw)
+            tl1 = ent.last_timing()
+        finally:
+            monkeypatch.delenv("ENT_TRI_POWER_FUSE", raising=False)
+            ent.timing_enable(False)
+        nl = -(-t // 10) if t >= 2 else t
+        print(f"[tri power {prec} n={n} t={t} q={q}] p1 {res.p1_est:.15e} oracle {ref.p1_est:.15e} "
+              f"one per launch {res1.p1_est:.15e}; launches {tl['power_launches']} / {tl1['power_launches']}",
+              flush=True)
+        assert tl["csr_band"] == 1
+        assert tl["power_launches"] == q * (1 + nl) and tl1["power_launches"] == q * (t + 1)
+        assert abs(res.p1_est - ref.p1_est) <= 1e-12 * ref.p1_est
+        assert abs(res.p1_est - res1.p1_est) <= 1e-12 * res1.p1_est
