@@ -683,7 +683,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   bool band_pairs = banded && sizeof(T) == 4 && nsteps_all >= 2 && step_pairs_enabled("ENT_BAND_PAIRS");
   // tridiagonal R: up to kTriMaxFuse steps per launch (both precisions)
   const int32_t tri_nf = tri ? tri_fuse_steps() : 1;
-  bool tri_pairs = tri && nsteps_all >= 2 && tri_nf >= 2;
+  bool tri_fused = tri && nsteps_all >= 2 && tri_nf >= 2;
   T *VC = nullptr, *VD = nullptr;
   uint32_t *signs = nullptr;
   int2 *cwin = nullptr;
@@ -706,7 +706,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     if (!dense && rad) cv.add(&signs, (size_t)n_pad * (ldv / 32));
     cv.add(&VA, (size_t)n_pad * ldb);
     cv.add(&VB, (size_t)n_pad * ldb);
-    if (band_pairs || tri_pairs) {
+    if (band_pairs || tri_fused) {
       cv.add(&VC, (size_t)n_pad * ldb);
       cv.add(&VD, (size_t)n_pad * ldb);
     }
@@ -718,10 +718,10 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   Carve cv;
   plan(cv);
   ent_status rc = ws.ensure(cv.total());
-  if (rc == ENT_ENOMEM && (band_pairs || tri_pairs)) {
+  if (rc == ENT_ENOMEM && (band_pairs || tri_fused)) {
     // the multi-step launches need two more V blocks: without room for
     // them, one step per launch
-    band_pairs = tri_pairs = false;
+    band_pairs = tri_fused = false;
     cv = Carve();
     plan(cv);
     rc = ws.ensure(cv.total());
@@ -822,11 +822,11 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     }
     prev_mark = e;
   };
-  if (band_pairs || tri_pairs) {
+  if (band_pairs || tri_fused) {
     // banded: steps k, k + 1 in one launch, the last step of an odd count
     // alone; tridiagonal: launches of up to tri_nf steps
     std::vector<int32_t> sizes;
-    if (tri_pairs) {
+    if (tri_fused) {
       sizes = fuse_split(nsteps, tri_nf);
     } else {
       for (int32_t k = 0; k < nsteps; k += 2) sizes.push_back(k + 1 < nsteps ? 2 : 1);
@@ -881,7 +881,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         T *outA = free_buf(Vk, Vkm1, nullptr);
         T *outB = free_buf(Vk, Vkm1, outA);
         const int e0 = pe.mark();
-        if (tri_pairs) {
+        if (tri_fused) {
           ent::TriFusedArgs ta{};
           ta.diag = trid; ta.n = n; ta.ldv = ldv; ta.ldb = ldb; ta.s = s;
           ta.Vk = Vk; ta.Vkm1 = cw != 0.0 ? Vkm1 : nullptr;
@@ -912,7 +912,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         Vkm1 = outA;
         Vk = outB;
         k += len;
-      } else if (tri_pairs) {
+      } else if (tri_fused) {
         ent::TriStepArgs a{};
         a.diag = trid; a.n = n; a.ldv = ldv; a.ldb = ldb; a.s = s;
         a.Vk = Vk; a.Vkm1 = cw != 0.0 ? Vkm1 : nullptr;
@@ -936,7 +936,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     }
     pe.steps_end = pe.mark();
   }
-  for (int32_t k = (band_pairs || tri_pairs) ? nsteps : 0; k < nsteps; ++k) {
+  for (int32_t k = (band_pairs || tri_fused) ? nsteps : 0; k < nsteps; ++k) {
     if (clenshaw) {
       const int32_t kk = m - k;  // index of the y computed by this launch
       T *Vout = (T *)Vkm1;
