@@ -339,9 +339,14 @@ ent_status ent_chebyshev_coeffs(double lo, double u, int32_t m, double *alpha);
  *   sum to 1 (the unit trace) within 5%; else 1 more product is counted.  The sketch cannot tell zero eigenvalues from
  *   tiny ones (a spectrum p_i ~ i^-2 looks rank 6 to it), whose entropy
  *   Algorithm 3 misses, hence the flag.  Otherwise the network, then
- *   Chebyshev on [lo, u] with the predicted degree.  The
- *   a-posteriori check requires every moment |d_kj| <= ||g_j||^2 and
- *   |H(m) - H(m-4)| <= 2.5e-4 |H(m)|; if it fails, the plain schedule on
+ *   Chebyshev on [lo, u] with the predicted degree m.  The a-posteriori
+ *   check requires every moment |d_kj| <= ||g_j||^2 (the spectrum inside
+ *   the interval) and |H(m) - H(m-4)| <= 2.5e-4 |H(m)| (converged).  If
+ *   only the second part fails, the same recurrence continues to
+ *   ceil(1.5 m) and then ceil(2.25 m) (at most 511; ENT_F64 and ENT_F32 --
+ *   the moments and the coefficients do not depend on the final degree, so
+ *   only the new products are run) and is checked again; result.degree is
+ *   the degree reached.  If the check still fails, the plain schedule on
  *   [0, u] with the caller's degree is run instead (result.fell_back = 1).
  *   result.products counts every product of every pass.
  * ent_selector_features: the sketch pass alone; features[16] (host) and, if

@@ -586,6 +586,22 @@ int64_t power_blocks(const ent_matrix *R) {
 // Optional work appended to an estimate: selector features and MLP inference
 // on the device (feature pass of the learned selector), and a copy of the
 // polynomial coefficients for the host-side a-posteriori check.
+// Degree stages of one forward Chebyshev estimate (FP64 / FP32 paths): the
+// recurrence runs to deg[0]; while check rejects the moments and stages
+// remain, the same recurrence continues to the next degree on the same
+// interval and probes.  The moments g^T T_k(X) g do not depend on the final
+// degree, nor do the coefficients (Lemma 3 on [0, u]; the fixed 1024-node
+// projection on [lo, u] up to degree 511), so a stage adds only its new
+// products.  The estimate is the one at the degree reached.
+struct DegreeStages {
+  int32_t count = 0;
+  int32_t deg[4] = {};
+  // 1: accept, 0: continue to the next stage, -1: reject (no further stage)
+  int (*check)(const std::vector<double> &mom, const std::vector<double> &alpha, int32_t m, int32_t s) = nullptr;
+  int32_t used = 0;    // out: the degree of the estimate returned
+  int32_t passed = 0;  // out: check accepted it
+};
+
 struct SelHook {
   float *feat_dev = nullptr;      // 16 features
   const float *params_dev = nullptr;
@@ -593,6 +609,7 @@ struct SelHook {
   float *y_host = nullptr;
   float *feat_host = nullptr;     // 16 features (optional)
   double *alpha_host = nullptr;   // m + 1 coefficients
+  DegreeStages *stages = nullptr; // run_poly only; m is then the last stage's degree
 };
 
 // ---------------------------------------------------------------------------
@@ -680,10 +697,14 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   // banded FP32 R: two recurrence steps per launch (two more V blocks: a
   // pair's outputs may not overwrite its inputs)
   const int32_t nsteps_all = clenshaw ? m + 1 : (method == ENT_CHEBYSHEV) ? m : m + 1;
-  bool band_pairs = banded && sizeof(T) == 4 && nsteps_all >= 2 && step_pairs_enabled("ENT_BAND_PAIRS");
+  // degree stages (forward Chebyshev): one step per launch, so a stage can
+  // end after any step
+  DegreeStages *stg = (hook && hook->stages && hook->stages->count > 0 && method == ENT_CHEBYSHEV && !clenshaw)
+                          ? hook->stages : nullptr;
+  bool band_pairs = banded && sizeof(T) == 4 && nsteps_all >= 2 && !stg && step_pairs_enabled("ENT_BAND_PAIRS");
   // tridiagonal R: up to kTriMaxFuse steps per launch (both precisions)
   const int32_t tri_nf = tri ? tri_fuse_steps() : 1;
-  bool tri_fused = tri && nsteps_all >= 2 && tri_nf >= 2;
+  bool tri_fused = tri && nsteps_all >= 2 && tri_nf >= 2 && !stg;
   T *VC = nullptr, *VD = nullptr;
   uint32_t *signs = nullptr;
   int2 *cwin = nullptr;
@@ -936,119 +957,138 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     }
     pe.steps_end = pe.mark();
   }
-  for (int32_t k = (band_pairs || tri_fused) ? nsteps : 0; k < nsteps; ++k) {
-    if (clenshaw) {
-      const int32_t kk = m - k;  // index of the y computed by this launch
-      T *Vout = (T *)Vkm1;
+  int32_t k_begin = (band_pairs || tri_fused) ? nsteps : 0;
+  int32_t m_run = stg ? stg->deg[0] : m;  // degree of the estimate
+  int32_t stage = 0;
+  for (;;) {
+    const int32_t k_end = stg ? m_run : nsteps;
+    for (int32_t k = k_begin; k < k_end; ++k) {
+      if (clenshaw) {
+        const int32_t kk = m - k;  // index of the y computed by this launch
+        T *Vout = (T *)Vkm1;
+        if (dense) {
+          ent::DenseStepArgs a{};
+          a.R = Rt; a.ldr = ldr; a.n = n; a.ldv = ldv;
+          a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = Vout; a.G = G;
+          a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
+          a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.ntile = ntile; a.bn = bn;
+          a.cg = scal + ent::S_ALPHA + kk;
+          a.ksplit = ksplit; a.kper = kper; a.party = party; a.nptile = npart;
+          HIP_TRY(dense_step(a));
+        } else if (banded) {
+          ent::BandStepArgs a{};
+          a.band = band; a.n = n; a.ldv = ldv;
+          a.Vk = Vk; a.Vkm1 = k == 0 ? nullptr : Vkm1; a.Vkp1 = Vout;
+          a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
+          a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
+          a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.nwave = ntile;
+          a.cg = scal + ent::S_ALPHA + kk;
+          HIP_TRY(ent::launch_band_step<T>(a, hp, st));
+        } else if (tri) {
+          ent::TriStepArgs a{};
+          a.diag = trid; a.n = n; a.ldv = ldv; a.ldb = ldb; a.s = s;
+          a.Vk = Vk; a.Vkm1 = k == 0 ? nullptr : Vkm1; a.Vkp1 = Vout;
+          a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
+          a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
+          a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.nblk = ntile;
+          a.cg = scal + ent::S_ALPHA + kk;
+          HIP_TRY(ent::launch_tri_step<T>(a, st));
+        } else {
+          ent::CsrStepArgs a{};
+          a.row_ptr = R->row_ptr; a.col_idx = R->col_idx; a.values = R->values; a.n = n; a.ldv = ldv;
+          a.Vk = Vk; a.Vkm1 = k == 0 ? nullptr : Vkm1; a.Vkp1 = Vout;
+          a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
+          a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
+          a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.nblk = ntile; a.win = cwin;
+          a.cg = scal + ent::S_ALPHA + kk;
+          a.s = s;
+          HIP_TRY(ent::launch_csr_step<T>(a, st));
+        }
+        Vkm1 = Vk;
+        Vk = Vout;
+        const int e = pe.mark();
+        if (k == nsteps - 1) pe.steps_end = e;
+        end_step(e);
+        continue;
+      }
+      T *Vout = bufs[k & 1];
+      double c1, c2, cw;
+      int32_t dot_y, slot, slot_gg = -1;
+      bool write = true;
+      if (method == ENT_CHEBYSHEV) {
+        if (k == 0) {
+          c1 = 1.0; c2 = -1.0; cw = 0.0;
+          slot_gg = 0;
+        } else {
+          c1 = 2.0; c2 = -2.0; cw = -1.0;
+        }
+        dot_y = 0;
+        slot = k + 1;
+      } else {
+        c1 = -1.0; c2 = 1.0; cw = 0.0;
+        dot_y = 1;
+        slot = k;
+        write = k < nsteps - 1;
+      }
       if (dense) {
         ent::DenseStepArgs a{};
         a.R = Rt; a.ldr = ldr; a.n = n; a.ldv = ldv;
-        a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = Vout; a.G = G;
-        a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
-        a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.ntile = ntile; a.bn = bn;
-        a.cg = scal + ent::S_ALPHA + kk;
+        a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr; a.G = G;
+        a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
+        a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.ntile = ntile; a.bn = bn;
         a.ksplit = ksplit; a.kper = kper; a.party = party; a.nptile = npart;
         HIP_TRY(dense_step(a));
       } else if (banded) {
         ent::BandStepArgs a{};
         a.band = band; a.n = n; a.ldv = ldv;
-        a.Vk = Vk; a.Vkm1 = k == 0 ? nullptr : Vkm1; a.Vkp1 = Vout;
+        a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr;
         a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
-        a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
-        a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.nwave = ntile;
-        a.cg = scal + ent::S_ALPHA + kk;
+        a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
+        a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nwave = ntile;
         HIP_TRY(ent::launch_band_step<T>(a, hp, st));
       } else if (tri) {
         ent::TriStepArgs a{};
         a.diag = trid; a.n = n; a.ldv = ldv; a.ldb = ldb; a.s = s;
-        a.Vk = Vk; a.Vkm1 = k == 0 ? nullptr : Vkm1; a.Vkp1 = Vout;
+        a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr;
         a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
-        a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
-        a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.nblk = ntile;
-        a.cg = scal + ent::S_ALPHA + kk;
+        a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
+        a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nblk = ntile;
         HIP_TRY(ent::launch_tri_step<T>(a, st));
       } else {
         ent::CsrStepArgs a{};
         a.row_ptr = R->row_ptr; a.col_idx = R->col_idx; a.values = R->values; a.n = n; a.ldv = ldv;
-        a.Vk = Vk; a.Vkm1 = k == 0 ? nullptr : Vkm1; a.Vkp1 = Vout;
+        a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr;
         a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
-        a.scal = scal; a.c1 = 2.0; a.c2 = -2.0; a.cw = k == 0 ? 0.0 : -1.0; a.dot_y = 0;
-        a.slot = kk; a.slot_gg = k == 0 ? m + 1 : -1; a.part = part; a.nblk = ntile; a.win = cwin;
-        a.cg = scal + ent::S_ALPHA + kk;
+        a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
+        a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nblk = ntile; a.win = cwin;
         a.s = s;
         HIP_TRY(ent::launch_csr_step<T>(a, st));
       }
-      Vkm1 = Vk;
+      // Chebyshev: V_{k+1} is written over V_{k-1} (same element, same thread),
+      // so two buffers plus the probe block suffice.  Taylor: W_{k+1} may not
+      // overwrite W_k (read by every tile), so outputs alternate.
+      if (method == ENT_CHEBYSHEV) Vkm1 = Vk;
       Vk = Vout;
       const int e = pe.mark();
-      if (k == nsteps - 1) pe.steps_end = e;
+      if (k == k_end - 1) pe.steps_end = e;
       end_step(e);
-      continue;
     }
-    T *Vout = bufs[k & 1];
-    double c1, c2, cw;
-    int32_t dot_y, slot, slot_gg = -1;
-    bool write = true;
-    if (method == ENT_CHEBYSHEV) {
-      if (k == 0) {
-        c1 = 1.0; c2 = -1.0; cw = 0.0;
-        slot_gg = 0;
-      } else {
-        c1 = 2.0; c2 = -2.0; cw = -1.0;
-      }
-      dot_y = 0;
-      slot = k + 1;
-    } else {
-      c1 = -1.0; c2 = 1.0; cw = 0.0;
-      dot_y = 1;
-      slot = k;
-      write = k < nsteps - 1;
-    }
-    if (dense) {
-      ent::DenseStepArgs a{};
-      a.R = Rt; a.ldr = ldr; a.n = n; a.ldv = ldv;
-      a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr; a.G = G;
-      a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
-      a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.ntile = ntile; a.bn = bn;
-      a.ksplit = ksplit; a.kper = kper; a.party = party; a.nptile = npart;
-      HIP_TRY(dense_step(a));
-    } else if (banded) {
-      ent::BandStepArgs a{};
-      a.band = band; a.n = n; a.ldv = ldv;
-      a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr;
-      a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
-      a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
-      a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nwave = ntile;
-      HIP_TRY(ent::launch_band_step<T>(a, hp, st));
-    } else if (tri) {
-      ent::TriStepArgs a{};
-      a.diag = trid; a.n = n; a.ldv = ldv; a.ldb = ldb; a.s = s;
-      a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr;
-      a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
-      a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
-      a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nblk = ntile;
-      HIP_TRY(ent::launch_tri_step<T>(a, st));
-    } else {
-      ent::CsrStepArgs a{};
-      a.row_ptr = R->row_ptr; a.col_idx = R->col_idx; a.values = R->values; a.n = n; a.ldv = ldv;
-      a.Vk = Vk; a.Vkm1 = Vkm1; a.Vkp1 = write ? Vout : nullptr;
-      a.signs = rad ? signs : nullptr; a.G = rad ? nullptr : G;
-      a.scal = scal; a.c1 = c1; a.c2 = c2; a.cw = cw; a.dot_y = dot_y;
-      a.slot = slot; a.slot_gg = slot_gg; a.part = part; a.nblk = ntile; a.win = cwin;
-      a.s = s;
-      HIP_TRY(ent::launch_csr_step<T>(a, st));
-    }
-    // Chebyshev: V_{k+1} is written over V_{k-1} (same element, same thread),
-    // so two buffers plus the probe block suffice.  Taylor: W_{k+1} may not
-    // overwrite W_k (read by every tile), so outputs alternate.
-    if (method == ENT_CHEBYSHEV) Vkm1 = Vk;
-    Vk = Vout;
-    const int e = pe.mark();
-    if (k == nsteps - 1) pe.steps_end = e;
-    end_step(e);
+    HIP_TRY(ent::launch_reduce_moments(part, stg ? m_run + 1 : nslot, npart, ldv, s, d, st));
+    HIP_TRY(ent::launch_final(d, scal, clenshaw ? ent::FINAL_CLENSHAW : method, m_run, s, h, st));
+    if (!stg) break;
+    // the check on the host; on rejection the recurrence continues from V_k, V_{k-1}
+    std::vector<double> smom((size_t)(m_run + 1) * s), salpha(m_run + 1);
+    HIP_TRY(hipMemcpyAsync(smom.data(), d, sizeof(double) * smom.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(salpha.data(), scal + ent::S_ALPHA, sizeof(double) * salpha.size(),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int verdict = stg->check(smom, salpha, m_run, s);
+    stg->passed = verdict == 1 ? 1 : 0;
+    stg->used = m_run;
+    if (verdict != 0 || stage + 1 >= stg->count) break;
+    k_begin = k_end;
+    m_run = stg->deg[++stage];
   }
-  HIP_TRY(ent::launch_reduce_moments(part, nslot, npart, ldv, s, d, st));
-  HIP_TRY(ent::launch_final(d, scal, clenshaw ? ent::FINAL_CLENSHAW : method, m, s, h, st));
   if (hook && hook->feat_dev) {
     HIP_TRY(ent::launch_selector_features(scal, d, m, s, n, hook->feat_dev, st));
     HIP_TRY(ent::launch_mlp_forward(hook->params_dev, hook->feat_dev, 1, hook->y_dev, st));
@@ -1057,14 +1097,14 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
       HIP_TRY(hipMemcpyAsync(hook->feat_host, hook->feat_dev, 16 * sizeof(float), hipMemcpyDeviceToHost, st));
   }
   if (hook && hook->alpha_host)
-    HIP_TRY(hipMemcpyAsync(hook->alpha_host, scal + ent::S_ALPHA, sizeof(double) * (m + 1),
+    HIP_TRY(hipMemcpyAsync(hook->alpha_host, scal + ent::S_ALPHA, sizeof(double) * (m_run + 1),
                            hipMemcpyDeviceToHost, st));
 
   double hs[16];
   HIP_TRY(hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, st));
   if (per_probe) HIP_TRY(hipMemcpyAsync(per_probe, h, sizeof(double) * s, hipMemcpyDeviceToHost, st));
   if (moments)
-    HIP_TRY(hipMemcpyAsync(moments, d, sizeof(double) * (m + 1) * s, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(moments, d, sizeof(double) * (m_run + 1) * s, hipMemcpyDeviceToHost, st));
   pe.mark();
   HIP_TRY(hipStreamSynchronize(st));
   pe.finish();
@@ -1088,12 +1128,12 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   out->p1_est = use_power ? hs[ent::S_P1] : 0.0;
   out->u = hs[ent::S_U];
   out->lo = hs[ent::S_LO];
-  out->degree = m;
+  out->degree = m_run;
   out->probes = s;
   out->method = method;
   out->precision = o.precision;
   out->fell_back = 0;
-  out->products = (method == ENT_CHEBYSHEV) ? m : m + 1;
+  out->products = (method == ENT_CHEBYSHEV) ? m_run : m_run + 1;
   return ENT_OK;
 }
 
@@ -1340,6 +1380,10 @@ ent_status poly_dispatch(const ent_matrix *R, int32_t method, int32_t m, int32_t
   }
 }
 
+// Highest degree a selector stage reaches (the projection coefficients on
+// [lo, u] are independent of the degree up to 511).
+constexpr int32_t kStageMaxDegree = 511;
+
 // Maps the network outputs to (m, lo): y0 = ln m*, y1 = log10(lo*/u), where
 // lo = 0 is trained as -6 (useful cutoffs lie in [10^-4.75, 10^-1.25] u) and
 // decoded below -5.25.  A 25% degree margin and half a decade of cutoff
@@ -1377,11 +1421,15 @@ double selector_rank(const float feat[16], int64_t n) {
 
 // A-posteriori check: every moment bounded by ||g||^2 (the spectrum stayed in
 // [lo, u]) and the partial sums converged: |H(m) - H(m-4)| <= 2.5e-4 |H(m)|.
-bool selector_check(const std::vector<double> &mom, const std::vector<double> &alpha, int32_t m,
-                    int32_t s) {
+// The a-posteriori check in two parts: -1 if some |d_kj| exceeds ||g_j||^2
+// (an eigenvalue outside the interval: T_k grows there, and a higher degree
+// does not help), 0 if the partial sums at degrees m and m - 4 differ by more
+// than 2.5e-4 relative (not converged yet), 1 if both pass.
+int selector_stage_check(const std::vector<double> &mom, const std::vector<double> &alpha, int32_t m,
+                         int32_t s) {
   for (int32_t k = 0; k <= m; ++k)
     for (int32_t j = 0; j < s; ++j)
-      if (!(std::fabs(mom[(size_t)k * s + j]) <= (1.0 + 1e-6) * mom[j])) return false;
+      if (!(std::fabs(mom[(size_t)k * s + j]) <= (1.0 + 1e-6) * mom[j])) return -1;
   auto partial = [&](int32_t mm) {
     double acc = 0.0;
     for (int32_t j = 0; j < s; ++j) {
@@ -1392,7 +1440,13 @@ bool selector_check(const std::vector<double> &mom, const std::vector<double> &a
     return acc / s;
   };
   const double hm = partial(m), h4 = partial(std::max(m - 4, 0));
-  return std::isfinite(hm) && std::fabs(hm - h4) <= 2.5e-4 * std::fabs(hm);
+  if (!std::isfinite(hm)) return -1;
+  return std::fabs(hm - h4) <= 2.5e-4 * std::fabs(hm) ? 1 : 0;
+}
+
+bool selector_check(const std::vector<double> &mom, const std::vector<double> &alpha, int32_t m,
+                    int32_t s) {
+  return selector_stage_check(mom, alpha, m, s) == 1;
 }
 
 // The selector's sketch pass: power method and a degree-12 Chebyshev moment
@@ -1473,21 +1527,37 @@ ent_status run_auto(const ent_matrix *R, int32_t m_plain, int32_t s, uint64_t se
   int32_t m_hat = 0;
   double lo = 0.0;
   selector_decode(y, fr.u, &m_hat, &lo);
-  // 2. main pass on [lo, u] with the predicted degree (power method reused)
+  // 2. main pass on [lo, u] with the predicted degree (power method reused).
+  // Where the check finds the spectrum inside the interval but the partial
+  // sums not converged, the same recurrence continues to 1.5x and then 2.25x
+  // the degree (at most kStageMaxDegree, where the coefficients on [lo, u]
+  // are still nested) before the fallback; the BF16x3 form has no stages.
   Opts mo = op;
   mo.o.u_fixed = fr.u;
   mo.o.cutoff = lo;
-  std::vector<double> mom((size_t)(m_hat + 1) * s), alpha(m_hat + 1);
+  DegreeStages ds;
+  ds.check = selector_stage_check;
+  ds.deg[ds.count++] = m_hat;
+  if (op.o.precision != ENT_BF16X3) {
+    for (double f : {1.5, 2.25}) {
+      const int32_t mm = std::min(kStageMaxDegree, (int32_t)std::ceil(f * m_hat));
+      if (mm > ds.deg[ds.count - 1]) ds.deg[ds.count++] = mm;
+    }
+  }
+  const int32_t m_top = ds.deg[ds.count - 1];
+  std::vector<double> mom((size_t)(m_top + 1) * s), alpha(m_top + 1);
   SelHook mh;
   mh.alpha_host = alpha.data();
+  if (op.o.precision != ENT_BF16X3) mh.stages = &ds;
   ent_result r{};
-  rc = poly_dispatch(R, ENT_CHEBYSHEV, m_hat, s, seed, mo, &r, per_probe, mom.data(), &mh);
-  bool ok = rc == ENT_OK && selector_check(mom, alpha, m_hat, s);
-  products += m_hat;
+  rc = poly_dispatch(R, ENT_CHEBYSHEV, mh.stages ? m_top : m_hat, s, seed, mo, &r, per_probe, mom.data(), &mh);
+  const int32_t m_used = mh.stages ? ds.used : m_hat;
+  bool ok = rc == ENT_OK && (mh.stages ? ds.passed != 0 : selector_check(mom, alpha, m_hat, s));
+  products += m_used;
   if (ok) {
     // the caller's table has (m_plain + 1) rows: copy the rows that fit
     if (moments) {
-      const int32_t rows = std::min(m_hat, m_plain) + 1;
+      const int32_t rows = std::min(m_used, m_plain) + 1;
       std::memcpy(moments, mom.data(), sizeof(double) * (size_t)rows * s);
       std::fill(moments + (size_t)rows * s, moments + (size_t)(m_plain + 1) * s, 0.0);
     }
