@@ -705,7 +705,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   // tridiagonal R: up to kTriMaxFuse steps per launch (both precisions)
   const int32_t tri_nf = tri ? tri_fuse_steps() : 1;
   bool tri_fused = tri && nsteps_all >= 2 && tri_nf >= 2 && !stg;
-  T *VC = nullptr, *VD = nullptr;
+  T *VC = nullptr, *VD = nullptr, *tprep = nullptr;
   uint32_t *signs = nullptr;
   int2 *cwin = nullptr;
   const int32_t ch = ent::csr_chunk_rows(sizeof(T) == 8);
@@ -716,6 +716,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     if (!dense && !banded && !tri) cv.add(&cwin, (size_t)((n + ch - 1) / ch));
     if (banded) cv.add(&band, ent::band_pack_elems(n, hp));
     if (tri) cv.add(&trid, 4 * (size_t)n);
+    if (tri_fused && method == ENT_CHEBYSHEV) cv.add(&tprep, 4 * (size_t)n);
     if (use_power) {
       cv.add(&x0, n_pad);
       cv.add(&x1, n_pad);
@@ -811,6 +812,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   }
   HIP_TRY(ent::launch_setup_interval(scal, method, m, o.u_factor, o.u_fixed, o.cutoff, st,
                                      normalize ? op.trace_div : 0.0));
+  // tridiagonal Chebyshev steps run on the prepared 2X = 2(aR - bI)
+  if (tprep) HIP_TRY(ent::launch_tri_prepare<T>(trid, scal, n, tprep, st));
 
   // recurrence
   const int32_t nsteps = clenshaw ? m + 1 : (method == ENT_CHEBYSHEV) ? m : m + 1;
@@ -904,7 +907,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         const int e0 = pe.mark();
         if (tri_fused) {
           ent::TriFusedArgs ta{};
-          ta.diag = trid; ta.n = n; ta.ldv = ldv; ta.ldb = ldb; ta.s = s;
+          ta.diag = trid; ta.prep = tprep; ta.n = n; ta.ldv = ldv; ta.ldb = ldb; ta.s = s;
           ta.Vk = Vk; ta.Vkm1 = cw != 0.0 ? Vkm1 : nullptr;
           ta.VoutA = outA; ta.VoutB = last_write ? outB : nullptr;
           ta.signs = rad ? signs : nullptr; ta.G = rad ? nullptr : G;

@@ -228,6 +228,7 @@ int32_t tri_step_blocks(int64_t n, int32_t s, int32_t fp64);
 constexpr int kTriMaxFuse = 10;
 struct TriFusedArgs {
   const void *diag;
+  const void *prep;    // Chebyshev and Clenshaw steps: launch_tri_prepare output (2X), required
   int64_t n, ldv, ldb;
   int32_t s;
   const void *Vk;
@@ -247,6 +248,10 @@ struct TriFusedArgs {
 };
 template <typename T>
 hipError_t launch_tri_fused(const TriFusedArgs &a, int32_t nf, hipStream_t st);
+// P = 2X = 2(aR - bI) on the packed diagonals (rows {2a l, 2(a d - b), 2a u, 0}),
+// a and b read from scal on the device; P may not alias D.
+template <typename T>
+hipError_t launch_tri_prepare(const T *D, const double *scal, int64_t n, T *P, hipStream_t st);
 // Power-method product on the packed diagonals: the contract of
 // launch_power_spmv, with nblk workgroups (nblk triples written).
 template <typename T>

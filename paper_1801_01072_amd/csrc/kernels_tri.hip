@@ -99,6 +99,35 @@ template hipError_t launch_power_tri<double>(const double *, int64_t, const doub
 template hipError_t launch_power_tri<float>(const float *, int64_t, const double *, const double *, double *,
                                             double *, int32_t, hipStream_t);
 
+// The Chebyshev step operator 2X = 2(aR - bI) on the packed diagonals
+// (a = scal[S_A], b = scal[S_B], set once the interval is known): row r of P
+// is {2a l_r, 2(a d_r - b), 2a u_r, 0}, so a Chebyshev step is
+// z = P v - V_{k-1} (plus Clenshaw's alpha_k g).  One thread per row.
+template <typename T>
+__global__ __launch_bounds__(256) void tri_prepare_kernel(const T *__restrict__ D, const double *__restrict__ scal,
+                                                          int64_t n, T *__restrict__ P) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  const double a = scal[S_A], b = scal[S_B];
+  const v4 d = *(const v4 *)(D + 4 * r);
+  v4 o;
+  o[0] = (T)(2.0 * a * (double)d[0]);
+  o[1] = (T)(2.0 * (a * (double)d[1] - b));
+  o[2] = (T)(2.0 * a * (double)d[2]);
+  o[3] = T(0);
+  *(v4 *)(P + 4 * r) = o;
+}
+
+template <typename T>
+hipError_t launch_tri_prepare(const T *D, const double *scal, int64_t n, T *P, hipStream_t st) {
+  if (n < 1 || !D || !scal || !P || P == D) return hipErrorInvalidValue;
+  tri_prepare_kernel<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(D, scal, n, P);
+  return hipGetLastError();
+}
+template hipError_t launch_tri_prepare<double>(const double *, const double *, int64_t, double *, hipStream_t);
+template hipError_t launch_tri_prepare<float>(const float *, const double *, int64_t, float *, hipStream_t);
+
 // K consecutive power-method products on the packed diagonals in one pass
 // (temporal blocking of the stencil on one vector).  A wave owns a
 // contiguous range of rows and slides a 64-row tile along it: at tile base b

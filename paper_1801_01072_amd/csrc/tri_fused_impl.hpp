@@ -16,9 +16,11 @@
 // needs V_{k+NF-1} and V_{k+NF}): a launch reads V_k, V_{k-1}, the probes and
 // the diagonals once and writes two V blocks, four V row passes for NF steps
 // instead of 3 NF.  Two probes per lane keep about a dozen registers per
-// step, so ten steps fit.  The product scale is folded into the step's
-// coefficient (z = (c1 a) (R~ v) + ...), and a dot product of the product
-// itself (Taylor) is scaled once at the end.  Dot partials are FP64, summed
+// step, so ten steps fit.  Chebyshev and Clenshaw steps read the prepared
+// operator 2X = 2(aR - bI) instead of R's diagonals, so a step is
+// z = (2X) v - V_{k-1} (+ alpha_k g); Taylor steps fold the scale into the
+// coefficient (z = (c1 a)(R v) + c2 b v) and scale the dot products of the
+// product itself once at the end.  Dot partials are FP64, summed
 // in a fixed order (rows in order, streams and waves in a fixed order).
 #pragma once
 #include <type_traits>
@@ -61,7 +63,8 @@ __global__ __launch_bounds__(64 * kFusedWaves) void tri_fused_kernel(TriFusedArg
   const int32_t cl = pv ? col : 0;  // loads of lanes past the probes read column 0 (never stored)
   const int64_t nw = ldv >> 5;
   const int32_t wsel = cl >> 5, bsh = cl & 31;
-  const T *__restrict__ D = (const T *)a.diag;
+  // Chebyshev / Clenshaw (no dot of the product itself): the prepared 2X
+  const T *__restrict__ D = (const T *)(DY ? a.diag : a.prep);
   const T *__restrict__ Vk = (const T *)a.Vk;
   const T *__restrict__ Vkm1 = (const T *)a.Vkm1;
   const T *__restrict__ G = (const T *)a.G;
@@ -172,7 +175,11 @@ __global__ __launch_bounds__(64 * kFusedWaves) void tri_fused_kernel(TriFusedArg
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const T yt = (dx[j][0] * lo[e] + dx[j][1] * mid[e]) + dx[j][2] * hi[e];
-          T ze = c1t[j] * yt + tb[j] * mid[e];
+          T ze;
+          if constexpr (DY)
+            ze = c1t[j] * yt + tb[j] * mid[e];
+          else  // yt = 2X v; the first forward Chebyshev step is X g
+            ze = (j == 0 && GG && !CG) ? T(0.5) * yt : yt;
           if (j > 0 || M1) ze += cw[j] * old[e];
           if (CG) ze += cg[j] * g_of(gh[j])[e];
           z[e] = in ? ze : T(0);
@@ -321,13 +328,22 @@ hipError_t launch_tri_fused(const TriFusedArgs &a, int32_t nf, hipStream_t st) {
   for (int32_t j = 1; j < nf; ++j)
     if ((a.dot_y[j] != 0) != dy || (a.cg[j] != nullptr) != cg) return hipErrorInvalidValue;
   if ((vks && !rad) || (!rad && !a.G) || (m1 && !a.Vkm1) || (gg && m1)) return hipErrorInvalidValue;
+  // Chebyshev / Clenshaw on the prepared 2X: every step is 2X v (c1 = 2,
+  // c2 = -2), except the first forward Chebyshev step, X g (c1 = 1, c2 = -1)
+  if (!dy) {
+    if (!a.prep || a.prep == a.diag) return hipErrorInvalidValue;
+    for (int32_t j = 0; j < nf; ++j) {
+      const bool half = j == 0 && gg && !cg;
+      if (a.c1[j] != (half ? 1.0 : 2.0) || a.c2[j] != -a.c1[j]) return hipErrorInvalidValue;
+    }
+  }
   const int32_t s_use = a.s > 0 ? a.s : (int32_t)a.ldv;
   if (a.n < 1 || a.nblk < 1 || a.ldv % 64 != 0 || a.ldb % 4 != 0 || a.ldb < s_use || a.ldv < s_use ||
       a.ldb > a.ldv || !a.VoutA || !a.scal || !a.part || !a.diag || (!vks && !a.Vk))
     return hipErrorInvalidValue;
   const void *outs[2] = {a.VoutA, a.VoutB};
   for (const void *o : outs)
-    if (o && (o == a.Vk || o == a.Vkm1 || o == a.G || o == a.diag)) return hipErrorInvalidValue;
+    if (o && (o == a.Vk || o == a.Vkm1 || o == a.G || o == a.diag || o == a.prep)) return hipErrorInvalidValue;
   switch (nf) {
     case 2: return tri_fused_width<T, 2>(a, s_use, st, rad, vks, m1, gg, dy, cg);
     case 3: return tri_fused_width<T, 3>(a, s_use, st, rad, vks, m1, gg, dy, cg);
