@@ -560,11 +560,22 @@ ent_status enqueue_power_split(const uint16_t *hi, const uint16_t *lo, int64_t n
 // indices (one synchronisation).  Uses the first 256 bytes of the workspace.
 // With hbw non-null, also measures the half-bandwidth max |col - row| (after
 // the structure check, in the same synchronisation).
-ent_status check_csr(const ent_matrix *R, void *scratch, hipStream_t st, int32_t *hbw = nullptr) {
+ent_status check_csr(const ent_matrix *R, void *scratch, hipStream_t st, int32_t *hbw = nullptr,
+                     bool short_rows = false) {
   if (R->layout != ENT_CSR) return ENT_OK;
   int32_t *flag = (int32_t *)scratch;
   int32_t h[2] = {0, 0};
   HIP_TRY(ent::launch_zero(flag, 2 * sizeof(int32_t), st));
+  if (hbw && short_rows) {
+    // a few entries per row: the check and the half-bandwidth in one pass
+    HIP_TRY(ent::launch_validate_csr_rows(R->row_ptr, R->col_idx, R->n, R->nnz, flag, st));
+    HIP_TRY(hipMemcpyAsync(h, flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h[0]) return fail(ENT_EINVAL, "invalid CSR structure (row_ptr must start at 0, be non-decreasing "
+                                      "and end at nnz; column indices must lie in [0, n))");
+    *hbw = h[1];
+    return ENT_OK;
+  }
   HIP_TRY(ent::launch_validate_csr(R->row_ptr, R->col_idx, R->n, R->nnz, flag, st));
   HIP_TRY(hipMemcpyAsync(&h[0], flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -663,7 +674,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     // at most three entries per row (duplicates aside) may be tridiagonal
     const bool maybe_tri = !(o.flags & (ENT_FLAG_CSR_GENERAL | ENT_FLAG_CSR_BANDED)) && R->nnz <= 3 * n;
     int32_t hbw = 0;
-    rc0 = check_csr(R, ws.ptr(), st, (want || maybe_tri) ? &hbw : nullptr);
+    rc0 = check_csr(R, ws.ptr(), st, (want || maybe_tri) ? &hbw : nullptr, maybe_tri);
     if (rc0 != ENT_OK) return rc0;
     tri = maybe_tri && hbw <= 1;
     if (want && !tri) hp = ent::band_half_width_padded(hbw);
@@ -706,6 +717,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   const int32_t tri_nf = tri ? tri_fuse_steps() : 1;
   bool tri_fused = tri && nsteps_all >= 2 && tri_nf >= 2 && !stg;
   T *VC = nullptr, *VD = nullptr, *tprep = nullptr;
+  double *ttmp = nullptr;
   uint32_t *signs = nullptr;
   int2 *cwin = nullptr;
   const int32_t ch = ent::csr_chunk_rows(sizeof(T) == 8);
@@ -715,7 +727,10 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     cv.add(&scal, kScalarDoubles);
     if (!dense && !banded && !tri) cv.add(&cwin, (size_t)((n + ch - 1) / ch));
     if (banded) cv.add(&band, ent::band_pack_elems(n, hp));
-    if (tri) cv.add(&trid, 4 * (size_t)n);
+    if (tri) {
+      cv.add(&trid, 4 * (size_t)n);
+      cv.add(&ttmp, (size_t)ent::kTriTraceBlocks);
+    }
     if (tri_fused && method == ENT_CHEBYSHEV) cv.add(&tprep, 4 * (size_t)n);
     if (use_power) {
       cv.add(&x0, n_pad);
@@ -768,7 +783,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
         HIP_TRY(ent::launch_trace_dense<double>((const double *)R->values, R->ld, n, scal, st));
       else
         HIP_TRY(ent::launch_trace_dense<float>((const float *)R->values, R->ld, n, scal, st));
-    } else {
+    } else if (!tri) {  // the tridiagonal pack below sums the diagonal itself
       if (R->dtype == ENT_STORE_F64)
         HIP_TRY(ent::launch_trace_csr<double>(R->row_ptr, R->col_idx, (const double *)R->values, n, R->nnz,
                                               scal, st));
@@ -791,7 +806,8 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   if (banded)
     HIP_TRY(ent::launch_band_pack<T>(R->row_ptr, R->col_idx, (const T *)R->values, n, hp, band, st));
   else if (tri)
-    HIP_TRY(ent::launch_tri_pack<T>(R->row_ptr, R->col_idx, (const T *)R->values, n, trid, st));
+    HIP_TRY(ent::launch_tri_pack<T>(R->row_ptr, R->col_idx, (const T *)R->values, n, trid, ttmp,
+                                    (check_trace || normalize) ? scal + ent::S_TRACE : nullptr, st));
   else if (!dense)
     HIP_TRY(ent::launch_csr_chunk_window(R->row_ptr, R->col_idx, n, ch, cwin, st));
   // probes

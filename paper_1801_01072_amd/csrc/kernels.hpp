@@ -159,6 +159,11 @@ hipError_t launch_trace_csr(const int64_t *rp, const int32_t *ci, const T *val, 
 // CSR structure check; flag[0] |= 1 on any violation (flag must start at 0).
 hipError_t launch_validate_csr(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nnz,
                                int32_t *flag, hipStream_t st);
+// The same check and the half-bandwidth max |col - row| (into flag[1], which
+// must start at 0; meaningful only if flag[0] stays 0) in one pass, one row
+// per thread: for short rows (at most a few entries each on average).
+hipError_t launch_validate_csr_rows(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nnz,
+                                    int32_t *flag, hipStream_t st);
 
 // ---- conversion --------------------------------------------------------------
 template <typename Tin, typename Tout>
@@ -195,9 +200,13 @@ hipError_t launch_csr_chunk_window(const int64_t *rp, const int32_t *ci, int64_t
 
 // ---- tridiagonal CSR (every entry within one of the diagonal) ---------------
 // Row r's values as {l_r, d_r, u_r, 0} (4 n elements of type T), duplicate
-// entries summed in entry order.
+// entries summed in entry order.  With trace non-null, also the trace (the
+// diagonal entries summed in FP64, in a fixed order) into *trace, through
+// kTriTraceBlocks partial sums in tmp.
+constexpr int32_t kTriTraceBlocks = 2048;
 template <typename T>
-hipError_t launch_tri_pack(const int64_t *rp, const int32_t *ci, const T *val, int64_t n, T *D, hipStream_t st);
+hipError_t launch_tri_pack(const int64_t *rp, const int32_t *ci, const T *val, int64_t n, T *D, double *tmp,
+                           double *trace, hipStream_t st);
 struct TriStepArgs {
   const void *diag;    // launch_tri_pack output, element type T
   int64_t n;

@@ -539,6 +539,49 @@ hipError_t launch_validate_csr(const int64_t *rp, const int32_t *ci, int64_t n, 
   return hipGetLastError();
 }
 
+// One row per thread: row_ptr's local conditions (rp[0] = 0, rp[n] = nnz,
+// 0 <= rp[r] <= rp[r+1] <= nnz) hold for every row exactly when row_ptr is
+// valid, and a row's column indices are read only if its range lies in
+// [0, nnz), so the entries of a valid structure are each checked once.
+__global__ __launch_bounds__(256) void validate_csr_rows_kernel(const int64_t *__restrict__ rp,
+                                                                const int32_t *__restrict__ ci, int64_t n,
+                                                                int64_t nnz, int32_t *__restrict__ flag) {
+  bool bad = false;
+  int64_t hb = 0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = rp[r], b = rp[r + 1];
+    if ((r == 0 && a != 0) || (r == n - 1 && b != nnz) || a < 0 || b < a || b > nnz) {
+      bad = true;
+      continue;
+    }
+    for (int64_t e = a; e < b; ++e) {
+      const int64_t c = ci[e];
+      if (c < 0 || c >= n) {
+        bad = true;
+      } else {
+        const int64_t d = c > r ? c - r : r - c;
+        hb = d > hb ? d : hb;
+      }
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+  // n < 2^31 (int32 column indices), so the half-bandwidth fits
+  int32_t h = (int32_t)hb;
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t o = __shfl_xor(h, off, 64);
+    h = o > h ? o : h;
+  }
+  if ((threadIdx.x & 63) == 0 && h > 0) atomicMax(flag + 1, h);
+}
+
+hipError_t launch_validate_csr_rows(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nnz,
+                                    int32_t *flag, hipStream_t st) {
+  if (n < 1) return hipErrorInvalidValue;
+  const int64_t b = (n + 255) / 256;
+  validate_csr_rows_kernel<<<(unsigned)(b < 4096 ? b : 4096), 256, 0, st>>>(rp, ci, n, nnz, flag);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Conversion copies
 // ---------------------------------------------------------------------------

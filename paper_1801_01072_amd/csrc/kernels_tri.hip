@@ -30,38 +30,67 @@ constexpr int kTriRows = 2;                  // rows per stream iteration
 }  // namespace
 
 // Tridiagonal values of row r as {l_r, d_r, u_r, 0}; duplicate entries are
-// summed in entry order.  One thread per row.
-template <typename T>
+// summed in entry order.  One thread per row, grid-stride; with TRACE, each
+// workgroup also sums the diagonal entries (FP64) of its rows into tmp.
+template <typename T, bool TRACE>
 __global__ __launch_bounds__(256) void tri_pack_kernel(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                       const T *__restrict__ val, int64_t n, T *__restrict__ D) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  T l = T(0), d = T(0), u = T(0);
-  for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
-    const int64_t off = (int64_t)ci[e] - r;
-    if (off < 0)
-      l += val[e];
-    else if (off == 0)
-      d += val[e];
-    else
-      u += val[e];
+                                                       const T *__restrict__ val, int64_t n, T *__restrict__ D,
+                                                       double *__restrict__ tmp) {
+  double tr = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    T l = T(0), d = T(0), u = T(0);
+    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+      const int64_t off = (int64_t)ci[e] - r;
+      if (off < 0) {
+        l += val[e];
+      } else if (off == 0) {
+        d += val[e];
+        if (TRACE) tr += (double)val[e];
+      } else {
+        u += val[e];
+      }
+    }
+    D[4 * r] = l;
+    D[4 * r + 1] = d;
+    D[4 * r + 2] = u;
+    D[4 * r + 3] = T(0);
   }
-  D[4 * r] = l;
-  D[4 * r + 1] = d;
-  D[4 * r + 2] = u;
-  D[4 * r + 3] = T(0);
+  if (TRACE) {
+    __shared__ double red[4];
+    tr = wave_sum(tr);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tr;
+    __syncthreads();
+    if (threadIdx.x == 0) tmp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+// The workgroups' partial traces summed in order by one wave.
+__global__ void tri_trace_sum_kernel(const double *__restrict__ tmp, int32_t cnt, double *__restrict__ trace) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += 64) acc += tmp[i];
+  acc = wave_sum(acc);
+  if (threadIdx.x == 0) *trace = acc;
 }
 
 template <typename T>
-hipError_t launch_tri_pack(const int64_t *rp, const int32_t *ci, const T *val, int64_t n, T *D, hipStream_t st) {
-  const int64_t blocks = (n + 255) / 256;
-  tri_pack_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(rp, ci, val, n, D);
+hipError_t launch_tri_pack(const int64_t *rp, const int32_t *ci, const T *val, int64_t n, T *D, double *tmp,
+                           double *trace, hipStream_t st) {
+  if (n < 1) return hipErrorInvalidValue;
+  const int64_t want = (n + 255) / 256;
+  const int32_t blocks = (int32_t)(want < kTriTraceBlocks ? want : kTriTraceBlocks);
+  if (trace) {
+    if (!tmp) return hipErrorInvalidValue;
+    tri_pack_kernel<T, true><<<(unsigned)blocks, 256, 0, st>>>(rp, ci, val, n, D, tmp);
+    tri_trace_sum_kernel<<<1, 64, 0, st>>>(tmp, blocks, trace);
+  } else {
+    tri_pack_kernel<T, false><<<(unsigned)blocks, 256, 0, st>>>(rp, ci, val, n, D, nullptr);
+  }
   return hipGetLastError();
 }
 template hipError_t launch_tri_pack<double>(const int64_t *, const int32_t *, const double *, int64_t, double *,
-                                            hipStream_t);
+                                            double *, double *, hipStream_t);
 template hipError_t launch_tri_pack<float>(const int64_t *, const int32_t *, const float *, int64_t, float *,
-                                           hipStream_t);
+                                           double *, double *, hipStream_t);
 
 // Power-method product on the packed diagonals: the contract of
 // launch_power_spmv (y = (R x) / ||x_prev||, one partial triple per block),

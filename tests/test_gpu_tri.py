@@ -218,3 +218,36 @@ def test_tri_power_fused(orc, monkeypatch, dtype, n):
         assert tl["power_launches"] == q * (1 + nl) and tl1["power_launches"] == q * (t + 1)
         assert abs(res.p1_est - ref.p1_est) <= 1e-12 * ref.p1_est
         assert abs(res.p1_est - res1.p1_est) <= 1e-12 * res1.p1_est
+
+
+def test_tri_csr_structure_rejected():
+    """Malformed short-row CSR input (at most three entries per row: the
+    one-pass row check that also measures the half-bandwidth) is refused
+    before any kernel reads it: a column index of n or -1, row pointers out of
+    order, a first row pointer of 1, an nnz that row_ptr does not end at.  The
+    well-formed matrix goes through the tridiagonal kernel."""
+    n = 100
+    rp, ci, val, _ = W.poisson_csr(n, np.float64)
+    ci = ci.astype(np.int32)
+
+    def attempt(rp_, ci_, val_, nnz=None):
+        M = ent.csr_matrix(torch.from_numpy(rp_).to(DEV), torch.from_numpy(ci_).to(DEV),
+                           torch.from_numpy(val_).to(DEV), n)
+        if nnz is not None:
+            M.nnz = nnz
+        return ent.entropy_estimate(M, "chebyshev", 8, 8, 1)
+
+    _, _, _, kern = run((rp, ci, val, n), "chebyshev", 8, 8, 1)
+    assert kern == 1
+    bad = []
+    c = ci.copy(); c[len(c) // 2] = n; bad.append((rp, c, val, None))
+    c = ci.copy(); c[7] = -1; bad.append((rp, c, val, None))
+    r = rp.copy(); r[10], r[11] = r[11], r[10]; bad.append((r, ci, val, None))
+    r = rp.copy(); r[0] = 1; bad.append((r, ci, val, None))
+    bad.append((rp, ci, val, len(ci) - 1))
+    for k, (r_, c_, v_, nnz) in enumerate(bad):
+        with pytest.raises(ent.EntropyError) as e:
+            attempt(r_, c_, v_, nnz)
+        print(f"[tri structure {k}] {e.value}", flush=True)
+        assert e.value.status == ent.EINVAL, k
+        assert "CSR structure" in str(e.value), k
