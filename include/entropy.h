@@ -39,7 +39,12 @@
  *    banded kernels (ENT_FLAG_CSR_GENERAL, ENT_FLAG_CSR_BANDED) adds its slab
  *    copy to the workspace: 16 + 2 hp values of the compute type per row,
  *    rounded up to 16 rows, rebuilt by every call and never kept past it;
- *    a tridiagonal CSR R its three diagonals (4 values per row, likewise).
+ *    a tridiagonal CSR R its three diagonals (4 values per row, likewise;
+ *    Chebyshev: a second copy, the prepared 2X).  The multi-step kernels
+ *    (banded FP32 pairs; tridiagonal launches of several steps) add two V
+ *    blocks, except a tridiagonal forward estimate whose steps all fit in
+ *    one launch; where the additional blocks do not fit, the call runs one
+ *    step per launch instead of returning ENT_ENOMEM.
  */
 #ifndef ENTROPY_H
 #define ENTROPY_H

@@ -716,6 +716,9 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
   // tridiagonal R: up to kTriMaxFuse steps per launch (both precisions)
   const int32_t tri_nf = tri ? tri_fuse_steps() : 1;
   bool tri_fused = tri && nsteps_all >= 2 && tri_nf >= 2 && !stg;
+  // all steps in one launch from the probe block: its two outputs are the
+  // only V blocks (Clenshaw starts from two zero blocks)
+  const bool tri_one_launch = tri_fused && !clenshaw && nsteps_all <= tri_nf;
   T *VC = nullptr, *VD = nullptr, *tprep = nullptr;
   double *ttmp = nullptr;
   uint32_t *signs = nullptr;
@@ -743,7 +746,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     if (!dense && rad) cv.add(&signs, (size_t)n_pad * (ldv / 32));
     cv.add(&VA, (size_t)n_pad * ldb);
     cv.add(&VB, (size_t)n_pad * ldb);
-    if (band_pairs || tri_fused) {
+    if (band_pairs || (tri_fused && !tri_one_launch)) {
       cv.add(&VC, (size_t)n_pad * ldb);
       cv.add(&VD, (size_t)n_pad * ldb);
     }
@@ -875,7 +878,7 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     T *pool[4] = {VA, VB, VC, VD};
     auto free_buf = [&](const void *x, const void *y, const void *z) -> T * {
       for (T *b : pool)
-        if (b != x && b != y && b != z) return b;
+        if (b && b != x && b != y && b != z) return b;
       return nullptr;
     };
     auto params = [&](int32_t k, double *c1, double *c2, double *cw, int32_t *dot_y, int32_t *slot,
