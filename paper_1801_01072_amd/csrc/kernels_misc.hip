@@ -36,6 +36,29 @@ __global__ void probe_rademacher_kernel(T *__restrict__ G, uint32_t *__restrict_
   }
 }
 
+// Sign bits only: one thread per row (grid-stride), each Philox block
+// giving four consecutive words of the row, the same bits as
+// probe_rademacher_kernel.
+__global__ __launch_bounds__(256) void sign_words_kernel(uint32_t *__restrict__ signs, int64_t n, int32_t s,
+                                                         int32_t nw, uint64_t seed) {
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t *dst = signs + row * nw;
+    for (int32_t blk = 0; 4 * blk < nw; ++blk) {
+      const U4 o = philox_block(seed, 0u, row, (uint32_t)blk);
+      const uint32_t w4[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int32_t word = 4 * blk + k;
+        if (word >= nw) break;
+        const int32_t lo = word * 32;
+        const uint32_t valid = (s - lo >= 32) ? 0xffffffffu : (s > lo ? ((1u << (s - lo)) - 1u) : 0u);
+        dst[word] = w4[k] & valid;
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ void probe_gaussian_kernel(T *__restrict__ G, int64_t n, int64_t n_pad, int32_t s,
                                       int64_t ldv, uint64_t seed) {
@@ -66,7 +89,10 @@ template hipError_t launch_probe_gen<float>(float *, uint32_t *, int64_t, int64_
 
 hipError_t launch_sign_gen(uint32_t *signs, int64_t n, int32_t s, int64_t ldv, uint64_t seed,
                            hipStream_t st) {
-  return launch_probe_gen<float>(nullptr, signs, n, n, s, ldv, seed, 0, st);
+  if (n < 1 || !signs || ldv % 32 != 0) return hipErrorInvalidValue;
+  const int64_t b = (n + 255) / 256;
+  sign_words_kernel<<<(unsigned)(b < 8192 ? b : 8192), 256, 0, st>>>(signs, n, s, (int32_t)(ldv >> 5), seed);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
