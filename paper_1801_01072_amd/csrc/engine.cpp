@@ -480,11 +480,11 @@ ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t 
                          double *scal, hipStream_t st, const T *band = nullptr, int32_t hp = 0,
                          const T *trid = nullptr, int32_t *launches = nullptr) {
   const int64_t n = R->n;
-  // tridiagonal R: after the first product, the products of a trial in
-  // launches of up to pf (ENT_TRI_POWER_FUSE, 1 = one per launch)
+  // tridiagonal and banded R: after the first product, the products of a
+  // trial in launches of up to pf (ENT_POWER_FUSE, 1 = one per launch)
   int32_t pf = 1;
-  if (trid) {
-    const char *e = std::getenv("ENT_TRI_POWER_FUSE");
+  if (trid || band) {
+    const char *e = std::getenv("ENT_POWER_FUSE");
     pf = e && *e ? std::atoi(e) : ent::kPowerMaxFuse;
     pf = pf < 1 ? 1 : (pf > ent::kPowerMaxFuse ? ent::kPowerMaxFuse : pf);
   }
@@ -497,12 +497,17 @@ ent_status enqueue_power(const ent_matrix *R, const T *Rc, int64_t ldr, int32_t 
       int32_t nblk = 0;
       const int32_t rem = t + 1 - it;
       ++nl;
-      if (trid && it >= 1 && pf >= 2 && rem >= 2) {
+      if ((trid || band) && it >= 1 && pf >= 2 && rem >= 2) {
         // the remaining products split as evenly as possible, longer first
         const int32_t nlaunch = (rem + pf - 1) / pf;
         const int32_t k = rem / nlaunch + (rem % nlaunch ? 1 : 0);
-        nblk = ent::power_blocks_csr(n);
-        HIP_TRY(ent::launch_power_tri_fused<T>(trid, n, xin, in_norm, xout, part3, nblk, k, st));
+        if (trid) {
+          nblk = ent::power_blocks_csr(n);
+          HIP_TRY(ent::launch_power_tri_fused<T>(trid, n, xin, in_norm, xout, part3, nblk, k, st));
+        } else {
+          nblk = ent::power_band_fused_blocks(n);
+          HIP_TRY(ent::launch_power_band_fused<T>(band, hp, n, xin, in_norm, xout, part3, nblk, k, st));
+        }
         HIP_TRY(ent::launch_power_reduce(part3, nblk, norm, st));
         std::swap(xin, xout);
         in_norm = norm;

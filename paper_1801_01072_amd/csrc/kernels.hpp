@@ -343,6 +343,13 @@ hipError_t launch_band_pair(const BandPairArgs &a, int32_t hp, hipStream_t st);
 template <typename T>
 hipError_t launch_power_band(const T *band, int32_t hp, int64_t n, const double *x, const double *in_norm,
                              double *y, double *part3, int32_t nblk, hipStream_t st);
+// k (2..kPowerMaxFuse) consecutive power-method products on the slabs in one
+// pass: the contract of launch_power_tri_fused, with nblk workgroups from
+// power_band_fused_blocks(n) (nblk triples written).
+template <typename T>
+hipError_t launch_power_band_fused(const T *band, int32_t hp, int64_t n, const double *x, const double *prev3,
+                                   double *y, double *part3, int32_t nblk, int32_t k, hipStream_t st);
+int32_t power_band_fused_blocks(int64_t n);
 template <typename T>
 hipError_t launch_band_step(const BandStepArgs &a, int32_t hp, hipStream_t st);
 

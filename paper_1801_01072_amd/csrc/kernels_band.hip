@@ -360,6 +360,125 @@ template hipError_t launch_power_band<float>(const float *, int32_t, int64_t, co
 template hipError_t launch_power_band<double>(const double *, int32_t, int64_t, const double *, const double *,
                                               double *, double *, int32_t, hipStream_t);
 
+// K consecutive power-method products on the slabs in one pass (temporal
+// blocking, as launch_power_tri_fused): a wave owns a contiguous range of
+// 16-row blocks; product j runs one block behind product j - 1 (a block's
+// stencil reaches at most 16 rows, one block, to each side) and reads product
+// j - 1's values of the three blocks around its own from a four-block ring in
+// LDS, private to the wave.  Each product reads its block's slab: from HBM for
+// product 0, from the caches for the products a few blocks behind.  Scaling
+// and the triple as launch_power_tri_fused.
+template <typename T, int KS, int K>
+__global__ __launch_bounds__(256) void power_band_fused_kernel(const T *__restrict__ band, int64_t n,
+                                                               const double *__restrict__ x,
+                                                               const double *__restrict__ prev3,
+                                                               double *__restrict__ y, double *__restrict__ part3) {
+  constexpr int HP = BandShape<KS>::HP;
+  __shared__ double ring[4][K][4][16];  // [wave][product][block & 3][row in block]
+  const int lane = threadIdx.x & 63, q = lane >> 4, c = lane & 15;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nb = (n + 15) / 16;
+  const int64_t nwave = (int64_t)gridDim.x * 4;
+  const int64_t wid = (int64_t)blockIdx.x * 4 + w;
+  const int64_t per = (nb + nwave - 1) / nwave;
+  const int64_t b_beg = wid * per < nb ? wid * per : nb;
+  const int64_t b_end = b_beg + per < nb ? b_beg + per : nb;
+  const double sc0 = prev3 ? 1.0 / sqrt(prev3[0]) : 1.0;
+  double rinv = 1.0;
+  if (prev3) {
+    const double rho = prev3[1] / prev3[2];
+    if (rho > 0.0 && isfinite(1.0 / rho)) rinv = 1.0 / rho;
+  }
+  double yy = 0.0, xy = 0.0, xx = 0.0;
+  if (b_beg < b_end) {
+    for (int i = lane; i < K * 64; i += 64) (&ring[w][0][0][0])[i] = 0.0;
+    for (int64_t beta = b_beg - (K - 1); beta - (K - 1) < b_end; ++beta) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int64_t bb = beta - j;
+        const bool blk_in = bb >= 0 && bb < nb;
+        T a[KS];
+        if (blk_in) {
+          load_slab<T, KS>(band, bb, lane, a);
+        } else {
+#pragma unroll
+          for (int k = 0; k < KS; ++k) a[k] = T(0);
+        }
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+          const int64_t col = 16 * bb - HP + 4 * k + q;
+          double xv;
+          if (j == 0)
+            xv = (col >= 0 && col < n) ? x[col] : 0.0;
+          else
+            xv = ring[w][j - 1][(col >> 4) & 3][col & 15];
+          acc += (double)a[k] * xv;
+        }
+        acc += __shfl_xor(acc, 16, 64);
+        acc += __shfl_xor(acc, 32, 64);
+        const int64_t row = 16 * bb + c;
+        double v = acc;
+        if (j == 0) v *= sc0;
+        if (j < K - 1) v *= rinv;
+        v = (blk_in && row < n) ? v : 0.0;
+        if (j == K - 1 && q == 0 && bb >= b_beg && bb < b_end && row < n) {
+          const double xin = ring[w][K - 2][bb & 3][c];  // the last product's input row
+          y[row] = v;
+          yy += v * v;
+          xy += xin * v;
+          xx += xin * xin;
+        }
+        if (q == 0) ring[w][j][bb & 3][c] = v;
+      }
+    }
+  }
+  block_power_partials(yy, xy, xx, part3, blockIdx.x);
+}
+
+template <typename T, int KS>
+static void power_band_fused_k(const T *band, int64_t n, const double *x, const double *prev3, double *y,
+                               double *part3, int32_t nblk, int32_t k, hipStream_t st) {
+  switch (k) {
+    case 2: power_band_fused_kernel<T, KS, 2><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, prev3, y, part3); break;
+    case 3: power_band_fused_kernel<T, KS, 3><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, prev3, y, part3); break;
+    case 4: power_band_fused_kernel<T, KS, 4><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, prev3, y, part3); break;
+    case 5: power_band_fused_kernel<T, KS, 5><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, prev3, y, part3); break;
+    case 6: power_band_fused_kernel<T, KS, 6><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, prev3, y, part3); break;
+    case 7: power_band_fused_kernel<T, KS, 7><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, prev3, y, part3); break;
+    case 8: power_band_fused_kernel<T, KS, 8><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, prev3, y, part3); break;
+    case 9: power_band_fused_kernel<T, KS, 9><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, prev3, y, part3); break;
+    default: power_band_fused_kernel<T, KS, 10><<<(unsigned)nblk, 256, 0, st>>>(band, n, x, prev3, y, part3); break;
+  }
+}
+
+// Workgroups of the fused banded power launch: at most 512 (2048 waves), so
+// that a wave's range is long against the K - 1 blocks of lead-in.
+int32_t power_band_fused_blocks(int64_t n) {
+  const int64_t nb = (n + 15) / 16;
+  const int64_t b = (nb + 63) / 64;
+  return (int32_t)(b < 1 ? 1 : (b < 512 ? b : 512));
+}
+
+template <typename T>
+hipError_t launch_power_band_fused(const T *band, int32_t hp, int64_t n, const double *x, const double *prev3,
+                                   double *y, double *part3, int32_t nblk, int32_t k, hipStream_t st) {
+  if (n < 1 || nblk < 1 || k < 2 || k > kPowerMaxFuse || !band || !x || !y || !part3 || y == x)
+    return hipErrorInvalidValue;
+  switch (hp) {
+    case 4: power_band_fused_k<T, 6>(band, n, x, prev3, y, part3, nblk, k, st); break;
+    case 8: power_band_fused_k<T, 8>(band, n, x, prev3, y, part3, nblk, k, st); break;
+    case 16: power_band_fused_k<T, 12>(band, n, x, prev3, y, part3, nblk, k, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_power_band_fused<float>(const float *, int32_t, int64_t, const double *, const double *,
+                                                   double *, double *, int32_t, int32_t, hipStream_t);
+template hipError_t launch_power_band_fused<double>(const double *, int32_t, int64_t, const double *,
+                                                    const double *, double *, double *, int32_t, int32_t,
+                                                    hipStream_t);
+
 template <typename T, int KS>
 __global__ __launch_bounds__(64 * kBandWaves) void band_step_kernel(BandStepArgs a) {
   typedef Mfma16<T> M;

@@ -247,3 +247,39 @@ def test_band_two_step_launches(orc, monkeypatch, n, s, m):
             assert t["csr_band"] == (4 if n <= 5 else 8) and t["steps_fused"] == 2 and t1["steps_fused"] == 1
             assert e2 <= TOL32 and e1 <= TOL32
             assert np.max(np.abs(mom - mom1)) <= TOL32 * max(1.0, float(np.max(np.abs(mom1))))
+
+
+@pytest.mark.parametrize("hb,hp", [(1, 4), (3, 8), (8, 16)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("n", [7, 33, 1000, 5003])
+def test_band_power_fused(orc, monkeypatch, hb, hp, dtype, n):
+    """After the first product, the power method's products on a banded R
+    run up to ten per launch (ENT_POWER_FUSE; each product one 16-row block
+    behind the one before, the middle products scaled by the previous Rayleigh
+    quotient): p~1 against the oracle's power method and against one product
+    per launch, for iteration counts that split evenly and unevenly, one and
+    two trials, every padded band width, ranges of one block and of many."""
+    csr = W.banded_density_csr(n, hb, seed=300 + hb, dtype=dtype)
+    prec = "f64" if dtype == np.float64 else "f32"
+    seed = 7
+    for t, q in ((2, 1), (5, 2), (20, 1), (23, 2)):
+        kw = dict(precision=prec, power_iters=t, power_trials=q, flags=ent.FLAG_CSR_BANDED)
+        ref = orc.estimate(csr, 1, 4, 8, seed, t=t, q=q)
+        ent.timing_enable(True)
+        try:
+            res, _, _ = ent.entropy_estimate_detail(csr_to_dev(csr), "chebyshev", 4, 8, seed, **kw)
+            tl = ent.last_timing()
+            monkeypatch.setenv("ENT_POWER_FUSE", "1")
+            res1, _, _ = ent.entropy_estimate_detail(csr_to_dev(csr), "chebyshev", 4, 8, seed, **kw)
+            tl1 = ent.last_timing()
+        finally:
+            monkeypatch.delenv("ENT_POWER_FUSE", raising=False)
+            ent.timing_enable(False)
+        print(f"[band power {prec} hb={hb} n={n} t={t} q={q}] p1 {res.p1_est:.15e} oracle {ref.p1_est:.15e} "
+              f"one per launch {res1.p1_est:.15e}; launches {tl['power_launches']} / {tl1['power_launches']}",
+              flush=True)
+        h = min(2 * hb, n - 1)  # the half-bandwidth R = B B^T reaches at this n
+        assert tl["csr_band"] == (4 if h <= 4 else (8 if h <= 8 else 16)) and (n < 17 or tl["csr_band"] == hp)
+        assert tl["power_launches"] == q * (1 + -(-t // 10)) and tl1["power_launches"] == q * (t + 1)
+        assert abs(res.p1_est - ref.p1_est) <= 1e-12 * ref.p1_est
+        assert abs(res.p1_est - res1.p1_est) <= 1e-12 * res1.p1_est

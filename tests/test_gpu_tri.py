@@ -189,7 +189,7 @@ def test_tri_fused_launches(orc, monkeypatch, dtype, n, s, m):
 @pytest.mark.parametrize("n", [1, 2, 7, 63, 64, 65, 130, 4097])
 def test_tri_power_fused(orc, monkeypatch, dtype, n):
     """After the first product, the power method's products on a tridiagonal
-    R run up to ten per launch (ENT_TRI_POWER_FUSE; the middle products
+    R run up to ten per launch (ENT_POWER_FUSE; the middle products
     scaled by the previous Rayleigh quotient, not normalised): p~1 against
     the oracle's power method and against one product per launch, for
     iteration counts that split evenly and unevenly, one and two trials,
@@ -204,11 +204,11 @@ def test_tri_power_fused(orc, monkeypatch, dtype, n):
         try:
             res, _, _ = ent.entropy_estimate_detail(csr_to_dev(csr), "chebyshev", 4, 8, seed, **kw)
             tl = ent.last_timing()
-            monkeypatch.setenv("ENT_TRI_POWER_FUSE", "1")
+            monkeypatch.setenv("ENT_POWER_FUSE", "1")
             res1, _, _ = ent.entropy_estimate_detail(csr_to_dev(csr), "chebyshev", 4, 8, seed, **kw)
             tl1 = ent.last_timing()
         finally:
-            monkeypatch.delenv("ENT_TRI_POWER_FUSE", raising=False)
+            monkeypatch.delenv("ENT_POWER_FUSE", raising=False)
             ent.timing_enable(False)
         nl = -(-t // 10) if t >= 2 else t
         print(f"[tri power {prec} n={n} t={t} q={q}] p1 {res.p1_est:.15e} oracle {ref.p1_est:.15e} "
