@@ -394,7 +394,10 @@ typedef struct {
   double epilogue_ms;    /* separate epilogue kernels (BF16x3 path), summed   */
   double other_ms;       /* probes, trace check, setup and reductions         */
   int32_t step_launches;
-  int32_t power_launches;
+  int32_t power_launches; /* product launches of the power method: t + 1 per
+                            trial, fewer for a banded or tridiagonal CSR R,
+                            whose products after a trial's first run up to
+                            ENT_POWER_FUSE (1..10, default 10) per launch  */
   int32_t epilogue_launches;
   int32_t csr_band;      /* CSR R: padded half-bandwidth (4, 8 or 16) of the
                             banded step kernel that ran, 1 for the
