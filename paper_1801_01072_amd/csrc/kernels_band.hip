@@ -479,7 +479,11 @@ template hipError_t launch_power_band_fused<double>(const double *, int32_t, int
                                                     const double *, double *, double *, int32_t, int32_t,
                                                     hipStream_t);
 
-template <typename T, int KS>
+// VKS: V_k is the sign block.  M1: no V_{k-1} term (0), V_{k-1} stored (1)
+// or the sign block (2).  GS: the probe rows come from the sign bits.  All
+// three are compile-time choices, so a block's row loads issue together
+// rather than one branch and wait each.
+template <typename T, int KS, bool VKS, int M1, bool GS>
 __global__ __launch_bounds__(64 * kBandWaves) void band_step_kernel(BandStepArgs a) {
   typedef Mfma16<T> M;
   typedef typename M::v4 v4;
@@ -503,10 +507,10 @@ __global__ __launch_bounds__(64 * kBandWaves) void band_step_kernel(BandStepArgs
   // it, so these two may alias each other (and nothing else)
   const T *Vkm1 = (const T *)a.Vkm1;
   T *Vkp1 = (T *)a.Vkp1;
-  const bool vk_signs = Vk == nullptr;
-  const int m1 = a.cw == 0.0 ? 0 : (Vkm1 == nullptr ? 2 : 1);
+  constexpr bool vk_signs = VKS;
+  constexpr int m1 = M1;
   const bool gg = a.slot_gg >= 0;
-  const bool g_signs = signs != nullptr && G == nullptr;
+  constexpr bool g_signs = GS;
   const bool dot_y = a.dot_y != 0;
   const T ta = (T)a.scal[S_A];
   const T tb = (T)(a.c2 * a.scal[S_B]);
@@ -529,11 +533,20 @@ __global__ __launch_bounds__(64 * kBandWaves) void band_step_kernel(BandStepArgs
 #pragma unroll
       for (int k = 0; k < KS; ++k) ac[k] = an[k];
       if (b + 1 < b_end) {
-        // the four fragments block b+1 adds, and its slab
+        // the four fragments block b+1 adds, and its slab.  Loaded from
+        // clamped rows and not zeroed, so the loads stay in flight across
+        // this block's products: a row outside [0, n) meets zero slab
+        // coefficients (the slabs hold no entry outside the matrix)
         const int64_t fn = 4 * b - HP / 4 + KS;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          vk_piece<T>(Vk, signs, vk_signs, 4 * (fn + j) + q, n, ldv, nw, chunk0, c, win[KS + j]);
+        for (int j = 0; j < 4; ++j) {
+          const int64_t row = 4 * (fn + j) + q;
+          const int64_t rr = row < 0 ? 0 : (row >= n ? n - 1 : row);
+          if (vk_signs)
+            sign4<T>(signs, rr, nw, chunk0, c, win[KS + j]);
+          else
+            load4<T>(Vk, rr, ldv, chunk0, c, win[KS + j]);
+        }
         load_slab<T, KS>(band, b + 1, lane, an);
       }
       // epilogue operands of this block's rows (register r holds row drow(q, r));
@@ -543,15 +556,15 @@ __global__ __launch_bounds__(64 * kBandWaves) void band_step_kernel(BandStepArgs
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = 16 * b + M::drow(q, r);
-        if (m1 == 1)
+        if constexpr (m1 == 1)
           load4<T>(Vkm1, row, ldv, chunk0, c, vm[r]);
-        else if (m1 == 2)
+        else if constexpr (m1 == 2)
           sign4<T>(signs, row, nw, chunk0, c, vm[r]);
         else {
 #pragma unroll
           for (int t = 0; t < 4; ++t) vm[r][t] = T(0);
         }
-        if (g_signs)
+        if constexpr (g_signs)
           sign4<T>(signs, row, nw, chunk0, c, gv[r]);
         else
           load4<T>(G, row, ldv, chunk0, c, gv[r]);
@@ -685,8 +698,10 @@ __device__ __forceinline__ void pair_own(const float *f0, const float *f1, const
 }
 
 // NP: probes per lane (4: 64-probe chunks; 2: 32-probe chunks, half the
-// per-lane state, the slabs read once per chunk).
-template <int KS, int NP, bool VK_SIGNS, int M1A, bool GG>
+// per-lane state, the slabs read once per chunk).  GS: the probe rows come
+// from the sign bits (Rademacher), else from G; a compile-time choice, so the
+// four rows' loads of a block issue together instead of one branch each.
+template <int KS, int NP, bool VK_SIGNS, int M1A, bool GG, bool GS>
 __global__ __launch_bounds__(64 * kBandWaves) void band_pair_kernel(BandPairArgs a) {
   typedef float T;
   typedef Mfma16<T> M;
@@ -712,7 +727,7 @@ __global__ __launch_bounds__(64 * kBandWaves) void band_pair_kernel(BandPairArgs
   const uint32_t *__restrict__ signs = a.signs;
   T *__restrict__ VoutA = (T *)a.VoutA;
   T *__restrict__ VoutB = (T *)a.VoutB;
-  const bool g_signs = signs != nullptr && G == nullptr;
+  constexpr bool g_signs = GS;
   const T ta = (T)a.scal[S_A];
   const T tbA = (T)(a.c2[0] * a.scal[S_B]), tbB = (T)(a.c2[1] * a.scal[S_B]);
   const T c1A = (T)a.c1[0], c1B = (T)a.c1[1], cwA = (T)a.cw[0], cwB = (T)a.cw[1];
@@ -750,10 +765,22 @@ __global__ __launch_bounds__(64 * kBandWaves) void band_pair_kernel(BandPairArgs
 #pragma unroll
       for (int k = 0; k < KS; ++k) ac[k] = an[k];
       if (b + 1 < a_end) {
+        // the next block's four window fragments, rows 4 fn .. 4 fn + 15,
+        // loaded from clamped rows and not zeroed, so the loads stay in
+        // flight across this block's products: a row outside [0, n) meets
+        // zero slab coefficients (the slabs hold no entry outside the
+        // matrix), and rows past n give results that are zeroed before
+        // any store or dot product
         const int64_t fn = 4 * b - HP / 4 + KS;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          pair_vk<NP>(Vk, signs, VK_SIGNS, 4 * (fn + j) + q, n, ldv, nw, col0, win[KS + j]);
+        for (int j = 0; j < 4; ++j) {
+          const int64_t row = 4 * (fn + j) + q;
+          const int64_t rr = row < 0 ? 0 : (row >= n ? n - 1 : row);
+          if (VK_SIGNS)
+            pair_signs<NP>(signs, rr, nw, col0, win[KS + j]);
+          else
+            pair_load<NP>(Vk, rr, ldv, col0, win[KS + j]);
+        }
         if (b + 1 < nb) {
           load_slab<T, KS>(band, b + 1, lane, an);
         } else {
@@ -773,14 +800,15 @@ __global__ __launch_bounds__(64 * kBandWaves) void band_pair_kernel(BandPairArgs
           pair_load<NP>(Vkm1, rr, ldv, col0, vm[r]);
         else if (M1A == 2)
           pair_signs<NP>(signs, rr, nw, col0, vm[r]);
-        if (g_signs)
+        if constexpr (g_signs)
           pair_signs<NP>(signs, rr, nw, col0, gv[r]);
         else
           pair_load<NP>(G, rr, ldv, col0, gv[r]);
+        // a row outside [0, n) keeps the (finite) values of row rr: its
+        // results are zeroed below and it adds to no dot product
+        if (M1A == 0) {
 #pragma unroll
-        for (int t = 0; t < NP; ++t) {
-          vm[r][t] = (M1A != 0 && in) ? vm[r][t] : T(0);
-          gv[r][t] = in ? gv[r][t] : T(0);
+          for (int t = 0; t < NP; ++t) vm[r][t] = T(0);
         }
       }
       v4 acc[NP];
@@ -898,7 +926,10 @@ template <int KS, bool VK_SIGNS, int M1A, bool GG>
 static void band_pair_launch(const BandPairArgs &a, hipStream_t st) {
   constexpr int NP = kBandPairProbes;
   dim3 grid((unsigned)(a.nwave / kBandWaves), (unsigned)(a.ldv / (16 * NP)));
-  band_pair_kernel<KS, NP, VK_SIGNS, M1A, GG><<<grid, 64 * kBandWaves, 0, st>>>(a);
+  if (a.signs != nullptr && a.G == nullptr)
+    band_pair_kernel<KS, NP, VK_SIGNS, M1A, GG, true><<<grid, 64 * kBandWaves, 0, st>>>(a);
+  else
+    band_pair_kernel<KS, NP, VK_SIGNS, M1A, GG, false><<<grid, 64 * kBandWaves, 0, st>>>(a);
 }
 
 template <int KS>
@@ -955,7 +986,7 @@ static int32_t band_resident_blocks() {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
     cus = 256;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)band_step_kernel<T, KS>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)band_step_kernel<T, KS, false, 1, true>,
                                                    64 * kBandWaves, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;
   const int32_t r = (int32_t)(cus * per_cu);
@@ -980,6 +1011,28 @@ int32_t band_step_waves(int64_t n, int32_t hp, int32_t fp64) {
   return (int32_t)(blocks * kBandWaves);
 }
 
+template <typename T, int KS, bool VKS, int M1>
+static hipError_t band_step_launch(const BandStepArgs &a, dim3 grid, hipStream_t st) {
+  if (a.signs != nullptr && a.G == nullptr)
+    band_step_kernel<T, KS, VKS, M1, true><<<grid, 64 * kBandWaves, 0, st>>>(a);
+  else
+    band_step_kernel<T, KS, VKS, M1, false><<<grid, 64 * kBandWaves, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+// V_k is the sign block only on the first step, which has no V_{k-1} term.
+template <typename T, int KS>
+static hipError_t band_step_dispatch(const BandStepArgs &a, dim3 grid, hipStream_t st) {
+  const bool vks = a.Vk == nullptr;
+  const int m1 = a.cw == 0.0 ? 0 : (a.Vkm1 == nullptr ? 2 : 1);
+  if (vks) return m1 == 0 ? band_step_launch<T, KS, true, 0>(a, grid, st) : hipErrorInvalidValue;
+  switch (m1) {
+    case 0: return band_step_launch<T, KS, false, 0>(a, grid, st);
+    case 1: return band_step_launch<T, KS, false, 1>(a, grid, st);
+    default: return band_step_launch<T, KS, false, 2>(a, grid, st);
+  }
+}
+
 template <typename T>
 hipError_t launch_band_step(const BandStepArgs &a, int32_t hp, hipStream_t st) {
   if (a.nwave <= 0 || a.nwave % kBandWaves != 0 || a.ldv % 64 != 0) return hipErrorInvalidValue;
@@ -987,9 +1040,9 @@ hipError_t launch_band_step(const BandStepArgs &a, int32_t hp, hipStream_t st) {
   if (a.G == nullptr && a.signs == nullptr) return hipErrorInvalidValue;
   dim3 grid((unsigned)(a.nwave / kBandWaves), (unsigned)(a.ldv / 64));
   switch (hp) {
-    case 4: band_step_kernel<T, 6><<<grid, 64 * kBandWaves, 0, st>>>(a); break;
-    case 8: band_step_kernel<T, 8><<<grid, 64 * kBandWaves, 0, st>>>(a); break;
-    case 16: band_step_kernel<T, 12><<<grid, 64 * kBandWaves, 0, st>>>(a); break;
+    case 4: return band_step_dispatch<T, 6>(a, grid, st);
+    case 8: return band_step_dispatch<T, 8>(a, grid, st);
+    case 16: return band_step_dispatch<T, 12>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
