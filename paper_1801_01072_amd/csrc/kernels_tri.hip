@@ -25,7 +25,6 @@ namespace ent {
 
 namespace {
 constexpr int kTriWaves = 4;                 // waves per workgroup
-constexpr int kTriStreams = 4 * kTriWaves;   // row streams per workgroup
 constexpr int kTriRows = 2;                  // rows per stream iteration
 }  // namespace
 
