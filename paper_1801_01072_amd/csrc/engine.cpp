@@ -1109,10 +1109,10 @@ ent_status run_poly(const ent_matrix *R, int32_t method, int32_t m, int32_t s, u
     HIP_TRY(hipMemcpyAsync(salpha.data(), scal + ent::S_ALPHA, sizeof(double) * salpha.size(),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    const int verdict = stg->check(smom, salpha, m_run, s);
-    stg->passed = verdict == 1 ? 1 : 0;
+    const int outcome = stg->check(smom, salpha, m_run, s);
+    stg->passed = outcome == 1 ? 1 : 0;
     stg->used = m_run;
-    if (verdict != 0 || stage + 1 >= stg->count) break;
+    if (outcome != 0 || stage + 1 >= stg->count) break;
     k_begin = k_end;
     m_run = stg->deg[++stage];
   }
